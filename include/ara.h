@@ -1,0 +1,279 @@
+/*
+ * ara.h -- C-ABI of the MI355X aggregate risk analysis engine (libara.so).
+ *
+ * The engine computes the analysis stage of aggregate risk analysis as defined
+ * in Bahl, Baltzer, Rau-Chaplin, Varghese, "Parallel Simulations for Analysing
+ * Portfolios of Catastrophic Event Risk":
+ *   inputs  (Section II-A): a Year Event Table (YET) of trials, each a sequence
+ *           of event occurrences ordered by time; Event Loss Tables (ELTs) of
+ *           (event, loss) records with per-ELT financial terms; a layer = a list
+ *           of ELTs plus the layer terms of Table I;
+ *   method  (Section II-B, basic algorithm, steps 1-4): per trial, look up each
+ *           occurrence in the layer's ELTs (direct access tables, Section III-B),
+ *           apply financial terms and sum across ELTs, apply occurrence terms,
+ *           take the cumulative sum in time order under the aggregate terms;
+ *   outputs (Section II-C): the Year Loss Table (one loss per trial) and the
+ *           PML / TVaR filters named in Section I.
+ *
+ * Conventions for every entry point:
+ *   - Returns an ara_status: ARA_OK (0) or a negative error.  No C++ exception
+ *     and no abort crosses this boundary.  After an error on a context,
+ *     ara_last_error(ctx) gives a human-readable message.
+ *   - Pointers are plain host or device pointers as stated by an ara_mem
+ *     argument.  ARA_MEM_DEVICE buffers are borrowed: the caller keeps them
+ *     alive and unchanged for as long as the handle that uses them lives.
+ *     ARA_MEM_HOST inputs are copied to device memory owned by the handle.
+ *   - Work is enqueued on the context's HIP stream.  Calls documented as
+ *     "blocking" synchronise that stream before returning; the others are
+ *     asynchronous, and errors that kernels detect (an event ID outside the
+ *     catalog, bad trial offsets) are reported by the next blocking call or by
+ *     ara_sync().
+ *   - A context and its handles are used by one host thread at a time.
+ *   - Event IDs are 0-based: valid IDs are 0 .. catalog_size-1, with
+ *     1 <= catalog_size <= 2^28 (larger catalogs: ARA_E_INVALID_ARG).
+ *   - Arithmetic is binary64 throughout.  ARA_F32 only selects binary32
+ *     storage of the loss tables.
+ */
+#ifndef ARA_H
+#define ARA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ara_status {
+    ARA_OK = 0,
+    ARA_E_INVALID_ARG = -1,    /* NULL handle/pointer, negative size, bad range or option        */
+    ARA_E_EVENT_ID_RANGE = -2, /* an event ID outside [0, catalog_size)                          */
+    ARA_E_BAD_OFFSETS = -3,    /* trial offsets not CSR: offsets[0]=0, non-decreasing, end=n_events */
+    ARA_E_BAD_LOSS = -4,       /* a loss that is negative, NaN or infinite                        */
+    ARA_E_DUP_EVENT = -5,      /* an ELT lists the same event twice                               */
+    ARA_E_BAD_TERMS = -6,      /* retention NaN/negative/infinite, limit NaN/negative, fx invalid  */
+    ARA_E_EMPTY = -7,          /* risk measures of an empty YLT                                   */
+    ARA_E_OOM = -8,            /* device allocation failed                                        */
+    ARA_E_DEVICE = -9,         /* no usable gfx950 device, or a HIP runtime error                 */
+    ARA_E_BUSY = -10,          /* releasing an ELT still used by a live layer                     */
+    ARA_E_UNSUPPORTED = -11    /* a requested table placement cannot hold this catalog            */
+} ara_status;
+
+typedef enum ara_precision {
+    ARA_F64 = 0, /* loss tables stored in binary64                                                    */
+    ARA_F32 = 1  /* loss tables stored rounded to binary32 (arithmetic stays binary64)                */
+} ara_precision;
+
+typedef enum ara_mem { ARA_MEM_HOST = 0, ARA_MEM_DEVICE = 1 } ara_mem;
+
+/* Layer terms of Table I.  Retentions finite and >= 0; limits >= 0, +INFINITY = no limit. */
+typedef struct ara_layer_terms {
+    double occ_retention; /* T_OccR: deductible per event occurrence                 */
+    double occ_limit;     /* T_OccL: cover per occurrence in excess of the retention */
+    double agg_retention; /* T_AggR: deductible on the trial's cumulative loss        */
+    double agg_limit;     /* T_AggL: cover on the cumulative loss above the retention */
+} ara_layer_terms;
+
+/* Financial terms I of one ELT (Section II-A names them but does not define them).
+ * Applied to each looked-up event loss l as min(max(fx*l - retention, 0), limit).
+ * fx finite >= 0, retention finite >= 0, limit >= 0 or +INFINITY.
+ * A NULL ara_elt_terms pointer means the identity (1, 0, +INFINITY). */
+typedef struct ara_elt_terms {
+    double fx;
+    double retention;
+    double limit;
+} ara_elt_terms;
+
+/* Where a layer's combined loss table lives while trials are analysed. */
+typedef enum ara_placement {
+    ARA_PLACE_AUTO = 0,         /* pick from the catalog size (default)                              */
+    ARA_PLACE_LDS_BITMAP = 1,   /* LDS: 1 bit/event "occurrence loss nonzero" + ranks; values in L2  */
+    ARA_PLACE_LDS_DENSE = 2,    /* LDS: the whole combined table (small catalogs)                    */
+    ARA_PLACE_GLOBAL_DENSE = 3  /* HBM/L2: the whole combined table, gathered per occurrence         */
+} ara_placement;
+
+/* Context options (ara_set_option). */
+typedef enum ara_option {
+    ARA_OPT_PLACEMENT = 1,      /* an ara_placement value                                            */
+    ARA_OPT_BLOCK_THREADS = 2,  /* threads per workgroup of the trial kernel: 256, 512 or 1024       */
+    ARA_OPT_GRID_PER_CU = 3     /* workgroups per compute unit of the trial kernel (1..64; 0 = auto)  */
+} ara_option;
+
+typedef struct ara_ctx ara_ctx;
+typedef struct ara_yet ara_yet;
+typedef struct ara_elt ara_elt;
+typedef struct ara_layer ara_layer;
+
+/* Static string for a status code (never NULL). */
+const char *ara_status_str(int status);
+
+/* Last error message of a context ("" if none), valid until the next call on ctx.
+ * With ctx == NULL: the message of the calling thread's last failure that had no
+ * context (ara_ctx_create). */
+const char *ara_last_error(const ara_ctx *ctx);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int ara_version(void);
+
+/* Rank k (1..n) of the order statistic that return period rp selects from n year
+ * losses sorted in descending order: k = ceil(n / rp) clamped to [1, n], taking
+ * the nearest integer when n / rp is within 4 ulps of it.  PML(rp) is the k-th
+ * largest loss and TVaR(rp) the mean of the k largest (a tail level alpha is
+ * rp = 1 / alpha).  The paper names PML and TVaR (Section I) without defining
+ * them; this is the engine's definition.  Host only; needs no device.
+ * Errors: ARA_E_INVALID_ARG if n < 1, rp < 1, rp is NaN or k is NULL. */
+ara_status ara_return_period_rank(int64_t n, double rp, int64_t *k);
+
+/* Validates layer terms as documented at ara_layer_terms (host only). */
+ara_status ara_check_layer_terms(const ara_layer_terms *terms);
+
+/* Creates a context on HIP device `device` (must be gfx950).  hip_stream is a
+ * hipStream_t to enqueue on (borrowed), or NULL for the device's null stream.
+ * Errors: ARA_E_DEVICE (no such device / not gfx950), ARA_E_OOM, ARA_E_INVALID_ARG. */
+ara_status ara_ctx_create(int device, void *hip_stream, ara_ctx **out);
+
+/* Synchronises and destroys the context.  Handles created on it must be released first. */
+ara_status ara_ctx_destroy(ara_ctx *ctx);
+
+/* Changes the stream later work is enqueued on (borrowed hipStream_t, NULL = null stream). */
+ara_status ara_ctx_set_stream(ara_ctx *ctx, void *hip_stream);
+
+/* Sets a tuning option (ara_option) of the context.  ARA_E_INVALID_ARG for unknown options/values. */
+ara_status ara_set_option(ara_ctx *ctx, int option, int64_t value);
+
+/* Blocking.  Waits for all work enqueued on the context and reports (then clears)
+ * the first device-detected input error: ARA_E_EVENT_ID_RANGE, ARA_E_BAD_OFFSETS,
+ * ARA_E_BAD_LOSS or ARA_E_DUP_EVENT.  ARA_E_DEVICE on a HIP runtime error. */
+ara_status ara_sync(ara_ctx *ctx);
+
+/* ---------------------------------------------------------------- Year Event Table
+ * Creates a YET handle (Section II-A item 1; in memory as the paper's event-ID and
+ * trial-boundary vectors, Section III-B).
+ *   event_ids      int32[n_events]: the event of every occurrence, all trials
+ *                  concatenated, each trial in ascending time order.
+ *   trial_offsets  int64[n_trials + 1]: trial t is event_ids[off[t] .. off[t+1]);
+ *                  off[0] = 0, non-decreasing, off[n_trials] = n_events.
+ *   catalog_size   number of events in the catalog (>= 1).
+ *   mem            ARA_MEM_DEVICE: both arrays are borrowed device pointers;
+ *                  ARA_MEM_HOST: both are copied to the device.
+ * Blocking: every ID and offset is checked on the device before returning.
+ * Errors: ARA_E_INVALID_ARG, ARA_E_EVENT_ID_RANGE, ARA_E_BAD_OFFSETS, ARA_E_OOM, ARA_E_DEVICE. */
+ara_status ara_yet_create(ara_ctx *ctx, const int32_t *event_ids, int64_t n_events,
+                          const int64_t *trial_offsets, int64_t n_trials, int32_t catalog_size,
+                          ara_mem mem, ara_yet **out);
+ara_status ara_yet_release(ara_yet *yet);
+
+/* ---------------------------------------------------------------- Event Loss Table
+ * Creates an ELT handle (Section II-A item 2) and builds its direct access table
+ * over the whole catalog (Section III-B): entry e holds the loss of event e, or 0
+ * if the ELT does not list e.
+ *   event_ids, losses  n_pairs records (int32 event, binary64 loss >= 0, finite);
+ *                      every event at most once; any order.
+ *   terms              financial terms I of this ELT, or NULL for the identity.
+ *   precision          storage of the direct access table (ARA_F32 rounds each loss
+ *                      to nearest binary32).
+ *   mem                as for ara_yet_create (DEVICE records are borrowed and re-read
+ *                      by ara_layer_build with ARA_BUILD_TABLES).
+ * Blocking.  Errors: ARA_E_INVALID_ARG, ARA_E_EVENT_ID_RANGE, ARA_E_BAD_LOSS,
+ * ARA_E_DUP_EVENT, ARA_E_BAD_TERMS, ARA_E_OOM, ARA_E_DEVICE. */
+ara_status ara_elt_create(ara_ctx *ctx, const int32_t *event_ids, const double *losses, int64_t n_pairs,
+                          int32_t catalog_size, const ara_elt_terms *terms, ara_precision precision,
+                          ara_mem mem, ara_elt **out);
+/* ARA_E_BUSY while a live layer uses the ELT. */
+ara_status ara_elt_release(ara_elt *elt);
+
+/* ---------------------------------------------------------------- Layer
+ * Creates a layer (Section II-A item 3): the listed ELTs, in this order, under the
+ * layer terms, over a catalog of catalog_size events (every ELT must have been
+ * created with that catalog size).  0 <= n_elts <= 65535; with n_elts = 0 every
+ * trial loses 0.  The layer holds a reference to each ELT.  It builds, on the
+ * device, the layer's combined table: for every catalog event e, the sum over the
+ * layer's ELTs (in listed order, binary64, from +0.0) of the ELT's financial terms
+ * applied to its loss for e -- the per-occurrence work of steps 1 and 2 of the
+ * basic algorithm, which depends only on the event -- stored in binary32 when every
+ * ELT is ARA_F32, else binary64; and the occurrence filter: which events have a
+ * nonzero loss after the occurrence terms, with the compacted values of those.
+ * Asynchronous (the build is enqueued).  Errors: ARA_E_INVALID_ARG (catalog
+ * mismatch, NULL), ARA_E_BAD_TERMS, ARA_E_OOM, ARA_E_DEVICE. */
+ara_status ara_layer_create(ara_ctx *ctx, ara_elt *const *elts, int32_t n_elts, int32_t catalog_size,
+                            const ara_layer_terms *terms, ara_layer **out);
+
+/* New layer terms (an underwriter re-pricing the layer).  Re-enqueues the occurrence
+ * filter build; the combined table is unchanged.  Asynchronous.  ARA_E_BAD_TERMS. */
+ara_status ara_layer_set_terms(ara_ctx *ctx, ara_layer *layer, const ara_layer_terms *terms);
+
+#define ARA_BUILD_TABLES 1 /* also rebuild each member ELT's direct access table from its records */
+
+/* Re-enqueues the layer's table builds: with ARA_BUILD_TABLES, each member ELT's
+ * direct access table from its (resident) records, then the combined table and
+ * the occurrence filter.  Asynchronous; record errors surface at the next
+ * blocking call.  Errors: ARA_E_INVALID_ARG, ARA_E_DEVICE. */
+ara_status ara_layer_build(ara_ctx *ctx, ara_layer *layer, int flags);
+
+/* Blocking.  Number of catalog events whose occurrence-net loss is nonzero under
+ * the current terms, the table placement ara_analyze would use, and the bytes of
+ * LDS it would take per workgroup.  Any output pointer may be NULL. */
+ara_status ara_layer_stats(ara_ctx *ctx, const ara_layer *layer, int64_t *n_occ_nonzero,
+                           int32_t *placement, int64_t *lds_bytes);
+ara_status ara_layer_release(ara_layer *layer);
+
+/* ---------------------------------------------------------------- Analysis
+ * Year Loss Table of trials [trial_begin, trial_end) of the YET under the layer
+ * (Section II-B steps 1-4, Section II-C output):
+ *   ylt[t - trial_begin] = min(max(P_t - AggR, 0), AggL),  P_t = sum over the trial's
+ *   occurrences d of min(max(x_d - OccR, 0), OccL), x_d = combined table[event_d].
+ * This equals the basic algorithm's sum of per-occurrence ceded losses: the
+ * cumulative sum is non-decreasing and the aggregate clamp is non-decreasing with
+ * value 0 at 0, so the differences telescope.  ylt has trial_end - trial_begin
+ * doubles in memory `ylt_mem`.  The YET and the layer must share a catalog size.
+ * Asynchronous for ARA_MEM_DEVICE output; blocking for ARA_MEM_HOST.  Trials with
+ * no events get 0.  Kernel-detected errors: ARA_E_EVENT_ID_RANGE, ARA_E_BAD_OFFSETS.
+ * Errors: ARA_E_INVALID_ARG, ARA_E_UNSUPPORTED (forced placement too small), ARA_E_DEVICE. */
+ara_status ara_analyze(ara_ctx *ctx, const ara_yet *yet, const ara_layer *layer,
+                       int64_t trial_begin, int64_t trial_end, double *ylt, ara_mem ylt_mem);
+
+/* Per-occurrence form of the analysis, the steps exactly as the basic algorithm
+ * orders them: x_d (loss summed over the layer's ELTs after financial terms),
+ * occ_d (after occurrence terms), cum_d (inclusive cumulative sum in time order),
+ * ceded_d = f(cum_d) - f(cum_{d-1}) with f the aggregate clamp and f(cum_0) = 0,
+ * and ylt = the sum of ceded_d per trial.  Per-occurrence arrays have
+ * off[trial_end] - off[trial_begin] doubles, indexed from off[trial_begin]; any of
+ * them (and ylt) may be NULL.  All pointers in memory `mem`.  Asynchronous for
+ * ARA_MEM_DEVICE, blocking for ARA_MEM_HOST.  Errors as ara_analyze. */
+ara_status ara_analyze_events(ara_ctx *ctx, const ara_yet *yet, const ara_layer *layer,
+                              int64_t trial_begin, int64_t trial_end, double *ylt,
+                              double *ev_gross, double *ev_occ, double *ev_cum, double *ev_ceded,
+                              ara_mem mem);
+
+/* Looks events up through the same table placement the trial kernel uses:
+ * gross[i] = combined table[event_ids[i]] and occ[i] = its occurrence-net loss.
+ * For checking lookups bit for bit.  n >= 0; out pointers may be NULL; all in `mem`.
+ * Asynchronous for ARA_MEM_DEVICE, blocking for ARA_MEM_HOST. */
+ara_status ara_lookup(ara_ctx *ctx, const ara_layer *layer, const int32_t *event_ids, int64_t n,
+                      double *gross, double *occ, ara_mem mem);
+
+/* ---------------------------------------------------------------- Order statistics
+ * Device workspace (bytes) that ara_sort_desc and ara_risk_measures need for n losses. */
+ara_status ara_sort_workspace_size(int64_t n, size_t *bytes);
+
+/* Sorts n binary64 values into descending order (-0.0 becomes +0.0; NaN sorts
+ * first).  in/out: device pointers (may alias); workspace: device,
+ * >= ara_sort_workspace_size(n) bytes, or NULL to let the library allocate.
+ * Asynchronous when a workspace is given.  Errors: ARA_E_INVALID_ARG, ARA_E_OOM. */
+ara_status ara_sort_desc(ara_ctx *ctx, const double *in, int64_t n, double *out,
+                         void *workspace, size_t workspace_bytes);
+
+/* Risk measures from a YLT of n >= 1 losses in memory ylt_mem: for each of the n_rp
+ * return periods, pml[i] = the k-th largest loss and tvar[i] = the mean of the k
+ * largest, k = ara_return_period_rank(n, return_periods[i]).  return_periods, pml
+ * and tvar are host arrays of n_rp.  workspace as for ara_sort_desc.  Blocking.
+ * Errors: ARA_E_EMPTY (n == 0), ARA_E_INVALID_ARG, ARA_E_OOM, ARA_E_DEVICE, and any
+ * pending kernel-detected input error. */
+ara_status ara_risk_measures(ara_ctx *ctx, const double *ylt, int64_t n, ara_mem ylt_mem,
+                             const double *return_periods, int32_t n_rp, double *pml, double *tvar,
+                             void *workspace, size_t workspace_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ARA_H */

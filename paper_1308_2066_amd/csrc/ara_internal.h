@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP sources of libara (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ara.h"
+
+namespace ara {
+
+// Error bits a kernel may set in the context's device error word.
+enum : uint32_t { ERR_ID_RANGE = 1u, ERR_OFFSETS = 2u, ERR_LOSS = 4u, ERR_DUP = 8u };
+
+// Device-side description of one ELT: its sparse records, its direct access
+// table over the catalog, and its financial terms.
+struct EltDesc {
+    const int32_t *pair_ids;
+    const double *pair_losses;
+    int64_t n_pairs;
+    void *dat;          // catalog entries, binary64 or binary32 (f32 != 0)
+    uint32_t *seen;     // one bit per catalog event, for duplicate detection
+    int32_t f32;
+    int32_t identity;   // financial terms are (1, 0, +inf)
+    double fx, retention, limit;
+};
+
+// Combined table of a layer and its occurrence filter.
+//   comb    catalog values: the loss per event summed over the layer's ELTs
+//   bitmap  one bit per event: occurrence-net loss of comb[e] is nonzero;
+//           grouped in blocks of 128 events = 4 words
+//   rank    per 128-event block: number of flagged events in earlier blocks
+//   occ     catalog binary64 values: occurrence-net loss min(max(comb[e]-OccR,0),OccL)
+//   vals    occ values of the flagged events, in event order (binary64)
+struct LayerTables {
+    void *comb = nullptr;
+    double *occ = nullptr;
+    uint32_t *bitmap = nullptr;
+    uint32_t *rank = nullptr;
+    double *vals = nullptr;
+    uint32_t *n_flagged = nullptr;
+    int32_t nblk = 0;
+};
+
+constexpr int kEventsPerBlock = 128;        // events per bitmap block
+constexpr int kLdsMaxBytes = 160 * 1024;    // LDS per workgroup on gfx950
+
+inline int32_t bitmap_blocks(int32_t catalog) { return (catalog + kEventsPerBlock - 1) / kEventsPerBlock; }
+inline int64_t bitmap_lds_bytes(int32_t catalog) { return int64_t(bitmap_blocks(catalog)) * (16 + 4); }
+
+// Arguments of the trial kernels.
+struct TrialArgs {
+    const int32_t *ids;
+    int64_t n_events;
+    const int64_t *offs;
+    int64_t t_begin, t_end;
+    int32_t catalog;
+    int32_t nblk;
+    const void *comb;        // combined table (binary64, or binary32 when f32)
+    const double *occ;       // occurrence-net table over the catalog
+    const uint32_t *bitmap;  // occurrence filter (see LayerTables)
+    const uint32_t *rank;
+    const double *vals;
+    double occ_r, occ_l, agg_r, agg_l;
+    double *ylt;
+    double *ev_gross, *ev_occ, *ev_cum, *ev_ceded;
+    uint32_t *err;
+};
+
+// ---- launchers (each enqueues on `s` and returns the launch status)
+hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
+hipError_t launch_validate_yet(const int32_t *ids, int64_t n_events, const int64_t *offs, int64_t n_trials,
+                               int32_t catalog, uint32_t *err, hipStream_t s);
+hipError_t launch_elt_clear(const EltDesc *d, int n_elts, int32_t catalog, hipStream_t s);
+hipError_t launch_elt_scatter(const EltDesc *d, int n_elts, int64_t max_pairs, int32_t catalog, uint32_t *err,
+                              hipStream_t s);
+hipError_t launch_layer_combine(const EltDesc *d, int n_elts, int32_t catalog, bool f32, double occ_r, double occ_l,
+                                const LayerTables &t, hipStream_t s);
+hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double occ_l, const LayerTables &t,
+                               hipStream_t s);
+
+struct TrialLaunch {
+    int placement;      // ara_placement (resolved)
+    bool f32;
+    int block;          // threads per workgroup
+    int grid;           // workgroups
+    size_t lds_bytes;
+};
+hipError_t launch_trial_ylt(const TrialArgs &a, const TrialLaunch &l, hipStream_t s);
+hipError_t launch_trial_events(const TrialArgs &a, bool f32, int grid, hipStream_t s);
+hipError_t launch_lookup(const TrialArgs &a, const TrialLaunch &l, const int32_t *ids, int64_t n, double *gross,
+                         double *occ, hipStream_t s);
+hipError_t prepare_trial_kernels();
+
+// ---- order statistics
+size_t sort_workspace_bytes(int64_t n);
+hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStream_t s);   // sorted keys -> ws
+hipError_t launch_sort_decode(const void *ws, int64_t n, double *out, hipStream_t s);
+hipError_t launch_risk(const void *ws, int64_t n, const int64_t *ks, int n_k, double *out_pml_tvar,
+                       hipStream_t s);
+
+}  // namespace ara

@@ -1,0 +1,139 @@
+// Per-layer tables.
+//
+// Combined table: steps 1 and 2 of the basic algorithm (Section II-B) look each
+// occurrence up in every ELT of the layer, apply that ELT's financial terms and
+// accumulate across ELTs.  The result for an occurrence depends only on its event,
+// so it is computed once per catalog event here, in the same order and rounding
+// (ELTs in listed order, binary64, starting from +0.0); a trial's lookup of event e
+// then reads comb[e].
+//
+// Occurrence filter: step 3 applies the occurrence terms (Table I) to each
+// occurrence independently of the others, so the occurrence-net loss
+// min(max(comb[e] - OccR, 0), OccL) is again a function of the event alone; it is
+// computed once per catalog event (binary64, same operations as per occurrence).
+// Events whose occurrence-net loss is zero contribute nothing to a trial, so the
+// filter also records one bit per event ("nonzero"), per-128-event prefix counts of
+// set bits, and the nonzero values compacted in event order.  A trial kernel can
+// keep the bits and counts in LDS and read only the flagged values from L2.
+#include "ara_internal.h"
+
+namespace ara {
+
+__device__ __forceinline__ double excess(double x, double retention, double limit) {
+    double v = x - retention;
+    v = v < 0.0 ? 0.0 : v;
+    return v > limit ? limit : v;
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_layer_combine(const EltDesc *__restrict__ d, int n_elts, int32_t catalog,
+                                                       V *__restrict__ comb) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= catalog) return;
+    double s = 0.0;
+    for (int j = 0; j < n_elts; ++j) {
+        const EltDesc &t = d[j];
+        double x = t.f32 ? double(reinterpret_cast<const float *>(t.dat)[e]) : reinterpret_cast<const double *>(t.dat)[e];
+        if (!t.identity) x = excess(t.fx * x, t.retention, t.limit);
+        s = s + x;
+    }
+    comb[e] = V(s);
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_layer_bitmap(const V *__restrict__ comb, int32_t catalog, double occ_r,
+                                                      double occ_l, double *__restrict__ occ,
+                                                      uint32_t *__restrict__ bitmap, int64_t n_words) {
+    // one thread per event slot of the bitmap; each wave covers 64 events = 2 words
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool flag = false;
+    if (e < catalog) {
+        const double o = excess(double(comb[e]), occ_r, occ_l);
+        occ[e] = o;
+        flag = o > 0.0;
+    }
+    const uint64_t m = __ballot(flag);
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = (e - lane) >> 5;   // even; n_words is a multiple of 4
+    if (w0 >= n_words) return;
+    if (lane == 0) bitmap[w0] = uint32_t(m);
+    if (lane == 1) bitmap[w0 + 1] = uint32_t(m >> 32);
+}
+
+// Exclusive prefix of per-block set-bit counts.  Single workgroup of 1024.
+__global__ __launch_bounds__(1024) void k_layer_rank(const uint32_t *__restrict__ bitmap, int32_t nblk,
+                                                     uint32_t *__restrict__ rank, uint32_t *__restrict__ n_flagged) {
+    __shared__ uint32_t wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t carry = 0;
+    for (int32_t base = 0; base < nblk; base += 1024) {
+        const int32_t b = base + tid;
+        uint32_t c = 0;
+        if (b < nblk) {
+            const uint4 q = reinterpret_cast<const uint4 *>(bitmap)[b];
+            c = __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
+        }
+        uint32_t inc = c;   // inclusive wave scan
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < w) before += wsum[k];
+            total += wsum[k];
+        }
+        if (b < nblk) rank[b] = carry + before + inc - c;
+        carry += total;
+        __syncthreads();
+    }
+    if (tid == 0) *n_flagged = carry;
+}
+
+__global__ __launch_bounds__(256) void k_layer_compact(const double *__restrict__ occ, int32_t catalog,
+                                                       const uint32_t *__restrict__ bitmap,
+                                                       const uint32_t *__restrict__ rank, double *__restrict__ vals) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= catalog) return;
+    const uint32_t word = bitmap[e >> 5];
+    const uint32_t bit = uint32_t(e) & 31u;
+    if (!((word >> bit) & 1u)) return;
+    const int64_t blk = e >> 7;
+    const uint32_t k = (uint32_t(e) >> 5) & 3u;
+    uint32_t idx = rank[blk] + __popc(word & ((1u << bit) - 1u));
+    for (uint32_t q = 0; q < k; ++q) idx += __popc(bitmap[blk * 4 + q]);
+    vals[idx] = occ[e];
+}
+
+hipError_t launch_layer_combine(const EltDesc *d, int n_elts, int32_t catalog, bool f32, double, double,
+                                const LayerTables &t, hipStream_t s) {
+    const unsigned blocks = unsigned((int64_t(catalog) + 255) / 256);
+    if (f32) hipLaunchKernelGGL(k_layer_combine<float>, dim3(blocks), dim3(256), 0, s, d, n_elts, catalog, (float *)t.comb);
+    else hipLaunchKernelGGL(k_layer_combine<double>, dim3(blocks), dim3(256), 0, s, d, n_elts, catalog, (double *)t.comb);
+    return hipGetLastError();
+}
+
+hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double occ_l, const LayerTables &t,
+                               hipStream_t s) {
+    const unsigned ev_blocks = unsigned((int64_t(catalog) + 255) / 256);
+    // bitmap covers nblk*128 event slots = nblk*2 waves; launch whole waves only
+    const unsigned bm_threads_blocks = unsigned((int64_t(t.nblk) * kEventsPerBlock + 255) / 256);
+    if (f32) {
+        hipLaunchKernelGGL(k_layer_bitmap<float>, dim3(bm_threads_blocks), dim3(256), 0, s, (const float *)t.comb,
+                           catalog, occ_r, occ_l, t.occ, t.bitmap, int64_t(t.nblk) * 4);
+    } else {
+        hipLaunchKernelGGL(k_layer_bitmap<double>, dim3(bm_threads_blocks), dim3(256), 0, s, (const double *)t.comb,
+                           catalog, occ_r, occ_l, t.occ, t.bitmap, int64_t(t.nblk) * 4);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_layer_rank, dim3(1), dim3(1024), 0, s, t.bitmap, t.nblk, t.rank, t.n_flagged);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_layer_compact, dim3(ev_blocks), dim3(256), 0, s, t.occ, catalog, t.bitmap, t.rank, t.vals);
+    return hipGetLastError();
+}
+
+}  // namespace ara

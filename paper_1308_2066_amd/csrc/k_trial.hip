@@ -1,0 +1,469 @@
+// Trial kernels: the analysis stage of Section II-B for every trial of the YET.
+//
+// Per trial (steps 1-4 of the basic algorithm):
+//   x_d   = combined table[event_d]            (steps 1-2, the lookup, hoisted per event)
+//   occ_d = min(max(x_d - OccR, 0), OccL)        (step 3, Table I occurrence terms)
+//   P_d   = occ_1 + ... + occ_d                 (step 4, cumulative in time order)
+//   ceded_d = f(P_d) - f(P_{d-1}),  f(P) = min(max(P - AggR, 0), AggL), f(P_0) = 0
+//   lr    = sum_d ceded_d                       (the trial's year loss, Section II-C)
+// Because occ_d >= 0, P is non-decreasing; f is non-decreasing with f(0) = 0, so the
+// ceded losses telescope and lr = f(P_k).  k_trial_ylt computes lr that way (one
+// reduction per trial).  k_trial_events runs the cumulative sum as a wave-wide
+// inclusive scan and emits every per-occurrence quantity.
+//
+// Design for gfx950 (the paper's "chunking" of a trial into fixed-size blocks of
+// events, Section III-B, taken to wave granularity):
+//   * one wave64 walks one trial at a time in segments of 1024 events: four
+//     16-byte non-temporal buffer loads per lane (64 lanes x 4 IDs x 4 loads), the
+//     buffer's record count clipping the trial's end so no byte past it is fetched;
+//   * segment i+2 is loaded while segment i is looked up (two register buffers);
+//   * the occurrence-net value of an event comes from LDS when the layer's table
+//     fits (dense), else from an LDS bitmap of the events whose occurrence-net loss
+//     is nonzero plus per-128-event counts, with only the flagged events' values
+//     read from L2 (the ID stream is the only large HBM stream);
+//   * persistent grid: one workgroup per LDS-sized slot of each compute unit, so the
+//     table is staged into LDS once per workgroup; consecutive trials go to the waves
+//     of one workgroup (same XCD), which shares their boundary cache lines.
+#include "ara_internal.h"
+
+namespace ara {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kChunk = 256;               // events per wave-wide 16-byte load
+constexpr int kNch = 4;                   // loads per segment
+constexpr int kSeg = kChunk * kNch;       // events per segment
+constexpr int kSlots = kNch * 4;          // events per lane per segment
+constexpr int kBufWord3 = 0x00020000;     // raw buffer descriptor word 3 (32-bit data format)
+constexpr int kNonTemporal = 2;           // cache policy of the ID stream loads
+
+__device__ __forceinline__ double excess(double x, double retention, double limit) {
+    double v = x - retention;
+    v = v < 0.0 ? 0.0 : v;
+    return v > limit ? limit : v;
+}
+
+// Sum over the wave (xor butterfly: every lane ends with the same value, since
+// a + b == b + a exactly in IEEE arithmetic).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Values every lane of the wave agrees on, kept in scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+// Wave-uniform position in a wave's sequence of (trial, segment).
+struct Cursor {
+    int64_t t;       // trial; >= t_end when the wave is done
+    int64_t o0, o1;  // trial's events [o0, o1)
+    int64_t sbase;   // first event of the segment, a multiple of 4
+};
+
+__device__ __forceinline__ void open_trial(const TrialArgs &a, int64_t t, Cursor &c, uint32_t &bad) {
+    c.t = t;
+    c.o0 = c.o1 = c.sbase = 0;
+    if (t < a.t_end) {
+        int64_t o0 = uniform64(a.offs[t]), o1 = uniform64(a.offs[t + 1]);
+        if (!(o0 >= 0 && o0 <= o1 && o1 <= a.n_events)) {
+            bad |= ERR_OFFSETS;
+            o0 = o1 = 0;
+        }
+        c.o0 = o0;
+        c.o1 = o1;
+        c.sbase = o0 & ~int64_t(3);
+    }
+}
+
+__device__ __forceinline__ bool seg_last(const Cursor &c) { return c.sbase + kSeg >= c.o1; }
+
+__device__ __forceinline__ Cursor seg_next(const TrialArgs &a, const Cursor &c, int64_t stride, uint32_t &bad) {
+    Cursor n = c;
+    if (c.t >= a.t_end) return n;
+    if (!seg_last(c)) {
+        n.sbase = c.sbase + kSeg;
+        return n;
+    }
+    open_trial(a, c.t + stride, n, bad);
+    return n;
+}
+
+// Issue the four ID loads of a segment.  Bytes past min(round4(o1), n_events) are
+// outside the buffer record and read as 0 without a memory access; a finished
+// cursor reads nothing.  The loads are always issued so the number of outstanding
+// vector-memory operations is the same on every path.
+__device__ __forceinline__ void load_seg(const TrialArgs &a, const Cursor &c, int lane, u32x4 (&r)[kNch]) {
+    int64_t avail = 0;
+    if (c.t < a.t_end) {
+        int64_t end = (c.o1 + 3) & ~int64_t(3);
+        if (end > a.n_events) end = a.n_events;
+        avail = end - c.sbase;
+        avail = avail < 0 ? 0 : (avail > kSeg ? kSeg : avail);
+    }
+    const int32_t *base = a.ids + (c.t < a.t_end ? c.sbase : 0);
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, int(avail * 4), kBufWord3);
+#pragma unroll
+    for (int k = 0; k < kNch; ++k)
+        r[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, k * kChunk * 4 + lane * 16, 0, kNonTemporal);
+    if (avail & 3) {
+        // The YET ends inside this lane's 16-byte group: fetch its remaining IDs one
+        // dword at a time so a partially covered 16-byte load cannot drop them.
+#pragma unroll
+        for (int k = 0; k < kNch; ++k) {
+            const int g = k * kChunk + lane * 4;
+            if (g < avail && g + 4 > avail) {
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t v = 0;
+                    if (g + j < avail) v = __builtin_amdgcn_raw_buffer_load_b32(rs, (g + j) * 4, 0, 0);
+                    r[k][j] = v;
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// Occurrence-net lookups.  `e` is a valid catalog event.
+//   bitmap placement: bits[e>>5] bit (e&31) set <=> the event's occurrence-net loss
+//   is nonzero; its value is vals[rank of e among set bits].
+__device__ __forceinline__ uint32_t bitmap_rank(const uint32_t *lbits, const uint32_t *lrank, uint32_t e,
+                                                uint32_t word) {
+    const uint32_t blk = e >> 7, q = (e >> 5) & 3u, bit = e & 31u;
+    const u32x4 W = reinterpret_cast<const u32x4 *>(lbits)[blk];
+    uint32_t idx = lrank[blk] + __popc(word & ((1u << bit) - 1u));
+    idx += q > 0 ? __popc(W.x) : 0u;
+    idx += q > 1 ? __popc(W.y) : 0u;
+    idx += q > 2 ? __popc(W.z) : 0u;
+    return idx;
+}
+
+// Stage the layer's table into LDS (whole workgroup; ends with a barrier).
+template <int PL>
+__device__ __forceinline__ void stage_lds(const TrialArgs &a, uint32_t *lds) {
+    if (PL == ARA_PLACE_LDS_BITMAP) {
+        u32x4 *l4 = reinterpret_cast<u32x4 *>(lds);
+        const u32x4 *g4 = reinterpret_cast<const u32x4 *>(a.bitmap);
+        for (int i = threadIdx.x; i < a.nblk; i += blockDim.x) l4[i] = g4[i];
+        uint32_t *lr = lds + size_t(a.nblk) * 4;
+        for (int i = threadIdx.x; i < a.nblk; i += blockDim.x) lr[i] = a.rank[i];
+    } else if (PL == ARA_PLACE_LDS_DENSE) {
+        // occurrence-net table, catalog doubles = 2*catalog words
+        const uint32_t *g = reinterpret_cast<const uint32_t *>(a.occ);
+        const int n = 2 * a.catalog, n4 = n >> 2;
+        u32x4 *l4 = reinterpret_cast<u32x4 *>(lds);
+        const u32x4 *g4 = reinterpret_cast<const u32x4 *>(g);
+        for (int i = threadIdx.x; i < n4; i += blockDim.x) l4[i] = g4[i];
+        for (int i = (n4 << 2) + threadIdx.x; i < n; i += blockDim.x) lds[i] = g[i];
+    }
+    __syncthreads();
+}
+
+// ---------------------------------------------------------------------------------
+// Look up the 16 IDs a lane holds for one segment: v[s] = occurrence-net loss of
+// the event in slot s, 0 for slots outside the trial.  For the bitmap placement the
+// L2 reads are issued here and consumed later (after the next prefetch is issued).
+template <int PL>
+__device__ __forceinline__ void seg_lookup(const TrialArgs &a, const uint32_t *lds, const u32x4 (&r)[kNch],
+                                           int lane, int lo, int hi, double (&v)[kSlots], uint32_t &bad) {
+    const uint32_t C = uint32_t(a.catalog);
+    if (PL == ARA_PLACE_LDS_BITMAP) {
+        const uint32_t *lrank = lds + size_t(a.nblk) * 4;
+        // flagged values are gathered with 32-bit offsets from one buffer descriptor
+        const __amdgpu_buffer_rsrc_t vr =
+            __builtin_amdgcn_make_buffer_rsrc((void *)a.vals, 0, int(C < 0x1FFFFFFFu ? C * 8u : 0xFFFFFFF8u), kBufWord3);
+        uint32_t off[kSlots];
+        uint32_t fl = 0;
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            const int rel = (s >> 2) * kChunk + lane * 4 + (s & 3);
+            const uint32_t id = r[s >> 2][s & 3];
+            const bool valid = rel >= lo && rel < hi;
+            const bool inr = id < C;
+            if (valid && !inr) bad |= ERR_ID_RANGE;
+            const uint32_t e = (valid && inr) ? id : 0u;
+            const uint32_t w = lds[e >> 5];
+            const bool f = valid && inr && ((w >> (e & 31u)) & 1u);
+            fl |= uint32_t(f) << s;
+            off[s] = 0;
+            if (f) off[s] = bitmap_rank(lds, lrank, e, w) * 8u;
+        }
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            v[s] = 0.0;
+            if (fl & (1u << s)) {
+                const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(vr, off[s], 0, 0));
+                v[s] = __builtin_bit_cast(double, q);
+            }
+        }
+    } else if (PL == ARA_PLACE_LDS_DENSE) {
+        const double *tab = reinterpret_cast<const double *>(lds);
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            const int rel = (s >> 2) * kChunk + lane * 4 + (s & 3);
+            const uint32_t id = r[s >> 2][s & 3];
+            const bool valid = rel >= lo && rel < hi;
+            const bool inr = id < C;
+            if (valid && !inr) bad |= ERR_ID_RANGE;
+            v[s] = 0.0;
+            if (valid && inr) v[s] = tab[id];
+        }
+    } else {
+        const __amdgpu_buffer_rsrc_t vr =
+            __builtin_amdgcn_make_buffer_rsrc((void *)a.occ, 0, int(C < 0x1FFFFFFFu ? C * 8u : 0xFFFFFFF8u), kBufWord3);
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            const int rel = (s >> 2) * kChunk + lane * 4 + (s & 3);
+            const uint32_t id = r[s >> 2][s & 3];
+            const bool valid = rel >= lo && rel < hi;
+            const bool inr = id < C;
+            if (valid && !inr) bad |= ERR_ID_RANGE;
+            v[s] = 0.0;
+            if (valid && inr) {
+                const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(vr, id * 8u, 0, 0));
+                v[s] = __builtin_bit_cast(double, q);
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void seg_bounds(const Cursor &c, int &lo, int &hi) {
+    const int64_t l = c.o0 - c.sbase, h = c.o1 - c.sbase;
+    lo = int(l < 0 ? 0 : l);
+    hi = int(h > kSeg ? kSeg : h);
+}
+
+__device__ __forceinline__ void finish_trial(const TrialArgs &a, int64_t t, double acc, int lane) {
+    const double P = wave_sum(acc);
+    if (lane == 0) a.ylt[t - a.t_begin] = excess(P, a.agg_r, a.agg_l);
+}
+
+template <int PL>
+__global__ __launch_bounds__(1024) void k_trial_ylt(TrialArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    stage_lds<PL>(a, lds);
+
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
+    const int64_t stride = int64_t(__builtin_amdgcn_readfirstlane(gridDim.x)) * wpb;
+    uint32_t bad = 0;
+
+    Cursor c0, c1;
+    open_trial(a, a.t_begin + int64_t(blockIdx.x) * wpb + wave, c0, bad);
+    u32x4 A[kNch], B[kNch];
+    load_seg(a, c0, lane, A);
+    c1 = seg_next(a, c0, stride, bad);
+    load_seg(a, c1, lane, B);
+
+    double acc = 0.0;
+    double v[kSlots];
+    int lo, hi;
+    while (c0.t < a.t_end) {
+        // ---- segment c0 (in A); segment c1 (in B) is in flight
+        seg_bounds(c0, lo, hi);
+        seg_lookup<PL>(a, lds, A, lane, lo, hi, v, bad);
+        const Cursor c2 = seg_next(a, c1, stride, bad);
+        __builtin_amdgcn_sched_barrier(0);
+        load_seg(a, c2, lane, A);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) acc += v[s];
+        if (seg_last(c0)) {
+            finish_trial(a, c0.t, acc, lane);
+            acc = 0.0;
+        }
+        if (c1.t >= a.t_end) break;
+        // ---- segment c1 (in B); c2 (in A) is in flight
+        seg_bounds(c1, lo, hi);
+        seg_lookup<PL>(a, lds, B, lane, lo, hi, v, bad);
+        const Cursor c3 = seg_next(a, c2, stride, bad);
+        __builtin_amdgcn_sched_barrier(0);
+        load_seg(a, c3, lane, B);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) acc += v[s];
+        if (seg_last(c1)) {
+            finish_trial(a, c1.t, acc, lane);
+            acc = 0.0;
+        }
+        c0 = c2;
+        c1 = c3;
+    }
+    if (bad) atomicOr(a.err, bad);
+}
+
+// ---------------------------------------------------------------------------------
+// Per-occurrence form: every quantity of the basic algorithm, with the cumulative
+// sum as a wave-wide inclusive scan (lane-local over 4 consecutive events, then a
+// 64-lane scan, plus the carry from the previous 256 events).
+template <typename V>
+__global__ __launch_bounds__(256) void k_trial_events(TrialArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int wpb = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
+    const int64_t stride = int64_t(__builtin_amdgcn_readfirstlane(gridDim.x)) * wpb;
+    const V *comb = reinterpret_cast<const V *>(a.comb);
+    const uint32_t C = uint32_t(a.catalog);
+    const int64_t ev0 = uniform64(a.offs[a.t_begin]);
+    uint32_t bad = 0;
+    for (int64_t t = a.t_begin + int64_t(blockIdx.x) * wpb + wave; t < a.t_end; t += stride) {
+        Cursor c;
+        open_trial(a, t, c, bad);
+        double carryP = 0.0, carryF = 0.0, lr = 0.0;
+        while (true) {
+            u32x4 r[kNch];
+            load_seg(a, c, lane, r);
+            int lo, hi;
+            seg_bounds(c, lo, hi);
+            for (int k = 0; k < kNch && k * kChunk < hi; ++k) {
+                double x[4], o[4], p[4], F[4];
+                bool ok[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int rel = k * kChunk + lane * 4 + j;
+                    const uint32_t id = r[k][j];
+                    const bool valid = rel >= lo && rel < hi;
+                    const bool inr = id < C;
+                    if (valid && !inr) bad |= ERR_ID_RANGE;
+                    ok[j] = valid && inr;
+                    x[j] = ok[j] ? double(comb[id]) : 0.0;
+                    o[j] = ok[j] ? excess(x[j], a.occ_r, a.occ_l) : 0.0;
+                }
+                p[0] = o[0];
+                p[1] = p[0] + o[1];
+                p[2] = p[1] + o[2];
+                p[3] = p[2] + o[3];
+                double inc = p[3];
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const double y = __shfl_up(inc, d, 64);
+                    if (lane >= d) inc += y;
+                }
+                double ex = __shfl_up(inc, 1, 64);
+                if (lane == 0) ex = 0.0;
+                const double base = carryP + ex;
+                double P[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    P[j] = base + p[j];
+                    F[j] = excess(P[j], a.agg_r, a.agg_l);
+                }
+                double Fprev = __shfl_up(F[3], 1, 64);
+                if (lane == 0) Fprev = carryF;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const double ced = F[j] - (j == 0 ? Fprev : F[j - 1]);
+                    if (ok[j]) {
+                        lr += ced;
+                        const int64_t pos = c.sbase + k * kChunk + lane * 4 + j - ev0;
+                        if (a.ev_gross) a.ev_gross[pos] = x[j];
+                        if (a.ev_occ) a.ev_occ[pos] = o[j];
+                        if (a.ev_cum) a.ev_cum[pos] = P[j];
+                        if (a.ev_ceded) a.ev_ceded[pos] = ced;
+                    }
+                }
+                carryP = __shfl(P[3], 63, 64);
+                carryF = __shfl(F[3], 63, 64);
+            }
+            if (seg_last(c)) break;
+            c.sbase += kSeg;
+        }
+        const double tot = wave_sum(lr);
+        if (lane == 0 && a.ylt) a.ylt[t - a.t_begin] = tot;
+    }
+    if (bad) atomicOr(a.err, bad);
+}
+
+// ---------------------------------------------------------------------------------
+// Lookups through a placement, for bit-exact checks of the trial kernel's tables.
+template <int PL, typename V>
+__global__ __launch_bounds__(1024) void k_lookup(TrialArgs a, const int32_t *__restrict__ ids, int64_t n,
+                                                 double *gross, double *occ) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    stage_lds<PL>(a, lds);
+    const uint32_t C = uint32_t(a.catalog);
+    uint32_t bad = 0;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const uint32_t id = uint32_t(ids[i]);
+        if (id >= C) {
+            bad |= ERR_ID_RANGE;
+            if (gross) gross[i] = __builtin_nan("");
+            if (occ) occ[i] = __builtin_nan("");
+            continue;
+        }
+        if (gross) gross[i] = double(reinterpret_cast<const V *>(a.comb)[id]);
+        double o;
+        if (PL == ARA_PLACE_LDS_BITMAP) {
+            const uint32_t w = lds[id >> 5];
+            o = 0.0;
+            if ((w >> (id & 31u)) & 1u)
+                o = a.vals[bitmap_rank(lds, lds + size_t(a.nblk) * 4, id, w)];
+        } else if (PL == ARA_PLACE_LDS_DENSE) {
+            o = reinterpret_cast<const double *>(lds)[id];
+        } else {
+            o = a.occ[id];
+        }
+        if (occ) occ[i] = o;
+    }
+    if (bad) atomicOr(a.err, bad);
+}
+
+// ---------------------------------------------------------------------------------
+hipError_t prepare_trial_kernels() {
+    hipError_t e;
+#define ARA_SET_LDS(fn)                                                                                  \
+    e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            kLdsMaxBytes);                                                               \
+    if (e != hipSuccess) return e;
+    ARA_SET_LDS(k_trial_ylt<ARA_PLACE_LDS_BITMAP>)
+    ARA_SET_LDS(k_trial_ylt<ARA_PLACE_LDS_DENSE>)
+    ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_BITMAP, double>))
+    ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_DENSE, double>))
+    ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_BITMAP, float>))
+    ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_DENSE, float>))
+#undef ARA_SET_LDS
+    return hipSuccess;
+}
+
+hipError_t launch_trial_ylt(const TrialArgs &a, const TrialLaunch &l, hipStream_t s) {
+    switch (l.placement) {
+    case ARA_PLACE_LDS_BITMAP:
+        hipLaunchKernelGGL(k_trial_ylt<ARA_PLACE_LDS_BITMAP>, dim3(l.grid), dim3(l.block), l.lds_bytes, s, a);
+        break;
+    case ARA_PLACE_LDS_DENSE:
+        hipLaunchKernelGGL(k_trial_ylt<ARA_PLACE_LDS_DENSE>, dim3(l.grid), dim3(l.block), l.lds_bytes, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL(k_trial_ylt<ARA_PLACE_GLOBAL_DENSE>, dim3(l.grid), dim3(l.block), 0, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trial_events(const TrialArgs &a, bool f32, int grid, hipStream_t s) {
+    if (f32) hipLaunchKernelGGL(k_trial_events<float>, dim3(grid), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_trial_events<double>, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_lookup(const TrialArgs &a, const TrialLaunch &l, const int32_t *ids, int64_t n, double *gross,
+                         double *occ, hipStream_t s) {
+    const int grid = 256;
+#define ARA_LK(PL)                                                                                             \
+    if (l.f32) hipLaunchKernelGGL((k_lookup<PL, float>), dim3(grid), dim3(1024), l.lds_bytes, s, a, ids, n, gross, occ); \
+    else hipLaunchKernelGGL((k_lookup<PL, double>), dim3(grid), dim3(1024), l.lds_bytes, s, a, ids, n, gross, occ);
+    switch (l.placement) {
+    case ARA_PLACE_LDS_BITMAP: ARA_LK(ARA_PLACE_LDS_BITMAP) break;
+    case ARA_PLACE_LDS_DENSE: ARA_LK(ARA_PLACE_LDS_DENSE) break;
+    default: ARA_LK(ARA_PLACE_GLOBAL_DENSE) break;
+    }
+#undef ARA_LK
+    return hipGetLastError();
+}
+
+}  // namespace ara

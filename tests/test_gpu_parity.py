@@ -1,0 +1,463 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+Bars:
+  * event lookups (combined and occurrence-net loss per event): bit-exact;
+  * integer-valued inputs (every intermediate exact in binary64): bit-exact;
+  * binary64 YLT: |gpu - oracle| <= 1e-12 * max(|oracle|, P_k), P_k the trial's
+    total of occurrence-net losses (both sides sum the same non-negative terms in
+    different orders, each within (k-1)u P_k of the exact value, and the aggregate
+    clamp is 1-Lipschitz; the max() keeps the bound meaningful where the clamp
+    cancels, P_k close to AggR);
+  * PML/TVaR: identical ranks; values within the YLT bound (order statistics are
+    1-Lipschitz in the sup norm) plus the TVaR summation bound;
+  * binary32 tables: |gpu - oracle64| <= 2^-23 * 1.0001 * G_t + 1e-12 * P_k, G_t the
+    trial's gross loss (two binary32 roundings per looked-up loss, each <= 2^-24
+    relative, propagated through 1-Lipschitz clamps).
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from exact_ara import rank_exact
+
+pytestmark = pytest.mark.gpu
+
+INF = math.inf
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "hand_worked_small.json")
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A(ara_lib):
+    return ara_lib
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1308_2066_amd import session
+    return session
+
+
+def analyze(A, S, ctx, w, placement=0, precision=0, t0=0, t1=None, terms=None, block=0, grid_per_cu=0):
+    import torch
+    A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, placement)
+    A.ara_set_option(ctx, A.ARA_OPT_BLOCK_THREADS, block)
+    A.ara_set_option(ctx, A.ARA_OPT_GRID_PER_CU, grid_per_cu)
+    an = S.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts,
+                         terms if terms is not None else w.layer_terms, w.elt_terms, precision)
+    try:
+        t1 = w.n_trials if t1 is None else t1
+        ylt = torch.empty(max(t1 - t0, 1), dtype=torch.float64, device="cuda")
+        A.ara_analyze(ctx, an.yet, an.layer, t0, t1, ylt)
+        A.ara_sync(ctx)
+        return ylt[: t1 - t0].cpu().numpy()
+    finally:
+        an.release()
+        A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, 0)
+        A.ara_set_option(ctx, A.ARA_OPT_BLOCK_THREADS, 0)
+        A.ara_set_option(ctx, A.ARA_OPT_GRID_PER_CU, 0)
+
+
+def analyze_events(A, S, ctx, w, placement=0, precision=0):
+    import torch
+    A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, placement)
+    an = S.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms, w.elt_terms,
+                         precision)
+    try:
+        n, ne = w.n_trials, max(w.n_events, 1)
+        out = {k: torch.full((n if k == "ylt" else ne,), math.nan, dtype=torch.float64, device="cuda")
+               for k in ("ylt", "gross", "occ", "cum", "ceded")}
+        A.ara_analyze_events(ctx, an.yet, an.layer, 0, n, out["ylt"], out["gross"], out["occ"], out["cum"],
+                             out["ceded"])
+        A.ara_sync(ctx)
+        res = {k: v.cpu().numpy() for k, v in out.items()}
+        for k in ("gross", "occ", "cum", "ceded"):
+            res[k] = res[k][: w.n_events]
+        return res
+    finally:
+        an.release()
+        A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, 0)
+
+
+def assert_ylt_close(got, ref, rel=1e-12, what=""):
+    y, P = ref["ylt"], ref["occ_total"]
+    tol = rel * np.maximum(np.abs(y), P)
+    err = np.abs(got - y)
+    bad = np.nonzero(~(err <= tol))[0]
+    assert bad.size == 0, (f"{what}: {bad.size} trials off; first {bad[:5]} got {got[bad[:5]]} "
+                           f"want {y[bad[:5]]} tol {tol[bad[:5]]}")
+
+
+PLACEMENTS = [1, 2, 3]   # LDS bitmap, LDS dense, global dense
+
+
+def _gold_workload(terms=None):
+    g = json.load(open(GOLD))
+    elts = [(np.array(e["ids"], np.int32), np.array(e["losses"], np.float64)) for e in g["elts"]]
+    trials = g["trials"]
+    offs = np.zeros(len(trials) + 1, np.int64)
+    offs[1:] = np.cumsum([len(t) for t in trials])
+    ids = np.array([e for t in trials for e in t], np.int32)
+    lt = tuple(INF if v == "inf" else float(v) for v in (terms or g["layer_terms"]))
+    return g, synth.Workload("hand", ids, offs, g["catalog_size"], elts, lt, None, (1, 2, 3, 4, 6, 250), 0)
+
+
+# ----------------------------------------------------------------------------- hand-worked example
+@pytest.mark.parametrize("placement", PLACEMENTS)
+def test_hand_worked_example(A, S, gpu_ctx, placement):
+    _say(f"hand-worked example placement={placement}")
+    g, w = _gold_workload()
+    ex = g["expected"]
+    ylt = analyze(A, S, gpu_ctx, w, placement)
+    assert ylt.tolist() == [float(v) for v in ex["ylt"]]
+    ev = analyze_events(A, S, gpu_ctx, w, placement)
+    flat = lambda k: [float(v) for t in ex[k] for v in t]
+    assert ev["gross"].tolist() == flat("gross")
+    assert ev["occ"].tolist() == flat("occ")
+    assert ev["cum"].tolist() == flat("cum")
+    assert ev["ceded"].tolist() == flat("ceded")
+    assert ev["ylt"].tolist() == [float(v) for v in ex["ylt"]]
+    import torch
+    pml, tvar = A.ara_risk_measures(gpu_ctx, torch.tensor(ex["ylt"], dtype=torch.float64, device="cuda"),
+                                    ex["return_periods"])
+    from fractions import Fraction as Fr
+    assert pml.tolist() == [float(v) for v in ex["pml"]]
+    assert tvar.tolist() == [float(Fr(v)) for v in ex["tvar"]]
+    for key in ("pass_through_terms", "uncapped_aggregate"):
+        _, w2 = _gold_workload(g["variants"][key]["layer_terms"])
+        y2 = analyze(A, S, gpu_ctx, w2, placement)
+        if key == "pass_through_terms":
+            assert y2.tolist() == [float(v) for v in g["variants"][key]["ylt"]]
+        else:
+            assert y2[0] == g["variants"][key]["ylt_T0"]
+
+
+# ----------------------------------------------------------------------------- exact tiny cases
+@pytest.mark.parametrize("placement", PLACEMENTS)
+def test_random_tiny_integer_bit_exact(A, S, gpu_ctx, placement):
+    rng = np.random.default_rng(100 + placement)
+    for i in range(60):
+        w = synth.random_tiny(rng, integer_losses=True, financial_terms=(i % 2 == 1), events_max=40)
+        _say(f"tiny integer case {i} placement={placement} C={w.catalog_size} elts={len(w.elts)} trials={w.n_trials}")
+        ref = oracle.analyze_workload(w, per_event=True)
+        got = analyze(A, S, gpu_ctx, w, placement)
+        assert got.tolist() == ref["ylt"].tolist(), i
+        if w.n_events:
+            ev = analyze_events(A, S, gpu_ctx, w, placement)
+            assert ev["gross"].tolist() == ref["gross"].tolist()
+            assert ev["occ"].tolist() == ref["occ"].tolist()
+            assert ev["cum"].tolist() == ref["cum"].tolist()
+            assert ev["ceded"].tolist() == ref["ceded"].tolist()
+            assert ev["ylt"].tolist() == ref["ylt"].tolist()
+
+
+def test_random_tiny_real_losses(A, S, gpu_ctx):
+    rng = np.random.default_rng(7)
+    for i in range(40):
+        w = synth.random_tiny(rng, integer_losses=False, financial_terms=(i % 3 == 0), events_max=60)
+        _say(f"tiny real case {i}")
+        ref = oracle.analyze_workload(w)
+        for pl in PLACEMENTS:
+            got = analyze(A, S, gpu_ctx, w, pl)
+            assert_ylt_close(got, ref, what=f"case {i} placement {pl}")
+
+
+# ----------------------------------------------------------------------------- plain 10k-trial configuration
+@pytest.fixture(scope="module")
+def small():
+    return synth.workload_plain_small()
+
+
+@pytest.mark.parametrize("placement", [0] + PLACEMENTS)
+def test_plain_small_ylt(A, S, gpu_ctx, small, placement):
+    _say(f"plain 10k trials placement={placement}")
+    ref = oracle.analyze_workload(small, threads=oracle.max_threads())
+    got = analyze(A, S, gpu_ctx, small, placement)
+    assert_ylt_close(got, ref, what="plain small")
+
+
+def _catalog_lookup_reference(w, precision_f32=False):
+    ids = np.arange(w.catalog_size, dtype=np.int32)
+    offs = np.array([0, w.catalog_size], np.int64)
+    r = oracle.analyze(ids, offs, w.catalog_size, w.elts, w.layer_terms, elt_terms=w.elt_terms,
+                       per_event=True, dat_f32=precision_f32)
+    return r["gross"], r["occ"]
+
+
+@pytest.mark.parametrize("placement", PLACEMENTS)
+def test_lookups_bit_exact_small(A, S, gpu_ctx, small, placement):
+    import torch
+    _say(f"lookups plain small placement={placement}")
+    gross, occ = _catalog_lookup_reference(small)
+    A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, placement)
+    an = S.open_analysis(gpu_ctx, small.event_ids, small.trial_offsets, small.catalog_size, small.elts,
+                         small.layer_terms)
+    try:
+        ids = torch.arange(small.catalog_size, dtype=torch.int32, device="cuda")
+        g = torch.empty(small.catalog_size, dtype=torch.float64, device="cuda")
+        o = torch.empty_like(g)
+        A.ara_lookup(gpu_ctx, an.layer, ids, g, o)
+        A.ara_sync(gpu_ctx)
+        assert np.array_equal(g.cpu().numpy(), gross)
+        assert np.array_equal(o.cpu().numpy(), occ)
+        nz, pl, lds = A.ara_layer_stats(gpu_ctx, an.layer)
+        assert nz == int(np.count_nonzero(occ))
+        assert pl == placement
+    finally:
+        an.release()
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, 0)
+
+
+def test_plain_small_events_mode(A, S, gpu_ctx, small):
+    _say("events mode plain small")
+    ref = oracle.analyze_workload(small, per_event=True, threads=oracle.max_threads())
+    ev = analyze_events(A, S, gpu_ctx, small)
+    assert np.array_equal(ev["gross"], ref["gross"])
+    assert np.array_equal(ev["occ"], ref["occ"])
+    Pk = np.repeat(ref["occ_total"], np.diff(small.trial_offsets))
+    assert np.all(np.abs(ev["cum"] - ref["cum"]) <= 1e-12 * Pk)
+    assert np.all(np.abs(ev["ceded"] - ref["ceded"]) <= 2e-12 * Pk)
+    assert_ylt_close(ev["ylt"], ref, what="events-mode ylt")
+
+
+@pytest.mark.parametrize("terms", [(5e4, 1e6, 2e5, 5e6), (5e4, 1e6, 2e5, INF), (5e4, 1e6, 3e6, INF)])
+def test_plain_small_risk_measures(A, S, gpu_ctx, small, terms):
+    import torch
+    _say(f"risk measures plain small terms={terms}")
+    w = small.with_terms(terms)
+    ref = oracle.analyze_workload(w, threads=oracle.max_threads())
+    got = analyze(A, S, gpu_ctx, w)
+    assert_ylt_close(got, ref)
+    rps = [1.0, 2.0, 10.0, 100.0, 250.0, 1000.0, 10_000.0]
+    pml_o, tvar_o, ranks_o, _ = oracle.risk(ref["ylt"], rps)
+    pml, tvar = A.ara_risk_measures(gpu_ctx, torch.from_numpy(got).cuda(), rps)
+    ranks = [A.ara_return_period_rank(len(got), rp) for rp in rps]
+    assert ranks == ranks_o.tolist()
+    # the GPU's PML is exactly its own k-th order statistic
+    srt = np.sort(got)[::-1]
+    assert pml.tolist() == [srt[k - 1] for k in ranks]
+    ytol = float(np.max(1e-12 * np.maximum(np.abs(ref["ylt"]), ref["occ_total"])))
+    assert np.all(np.abs(pml - pml_o) <= ytol)
+    k = np.array(ranks, dtype=np.float64)
+    assert np.all(np.abs(tvar - tvar_o) <= ytol + 2 * k * 2.0 ** -53 * np.abs(tvar_o))
+
+
+# ----------------------------------------------------------------------------- edge cases
+def _edge_workload(rng, lengths, catalog=5000, n_elts=3, lead=0):
+    lengths = np.asarray(lengths, np.int64)
+    offs = np.zeros(len(lengths) + 1, np.int64)
+    offs[1:] = np.cumsum(lengths)
+    ids = rng.integers(0, catalog, size=int(offs[-1])).astype(np.int32)
+    elts = [synth.elt_sparse(rng, catalog // 3, catalog, 10.0, 2.0) for _ in range(n_elts)]
+    return synth.Workload("edge", ids, offs, catalog, elts, (5e4, 1e6, 2e5, INF), None, (10.0,), 0)
+
+
+@pytest.mark.parametrize("placement", PLACEMENTS)
+def test_edge_trial_lengths(A, S, gpu_ctx, placement):
+    rng = np.random.default_rng(55)
+    lengths = [0, 1, 3, 4, 5, 255, 256, 257, 1023, 1024, 1025, 2047, 2049, 3000, 0, 0, 7, 4099, 1, 2]
+    w = _edge_workload(rng, lengths)
+    assert w.n_events % 4 != 0
+    _say(f"edge lengths placement={placement} n_events={w.n_events}")
+    ref = oracle.analyze_workload(w, per_event=True)
+    got = analyze(A, S, gpu_ctx, w, placement)
+    assert_ylt_close(got, ref)
+    ev = analyze_events(A, S, gpu_ctx, w, placement)
+    assert np.array_equal(ev["gross"], ref["gross"]) and np.array_equal(ev["occ"], ref["occ"])
+    # sub-ranges of trials
+    for t0, t1 in [(0, 1), (3, 11), (13, 20), (5, 5), (19, 20)]:
+        sub = analyze(A, S, gpu_ctx, w, placement, t0=t0, t1=t1)
+        assert np.array_equal(sub, got[t0:t1])
+
+
+def test_single_trial_and_last_partial_group(A, S, gpu_ctx):
+    rng = np.random.default_rng(9)
+    for n in [1, 2, 3, 5, 6, 7, 1021, 1022, 1023, 4097]:
+        w = _edge_workload(rng, [n])
+        _say(f"single trial n={n}")
+        ref = oracle.analyze_workload(w)
+        for pl in PLACEMENTS:
+            assert_ylt_close(analyze(A, S, gpu_ctx, w, pl), ref, what=f"n={n} pl={pl}")
+
+
+def test_many_short_trials_and_empty_layer(A, S, gpu_ctx):
+    rng = np.random.default_rng(21)
+    w = _edge_workload(rng, rng.integers(0, 9, size=5000))
+    _say("many short trials")
+    ref = oracle.analyze_workload(w)
+    for pl in PLACEMENTS:
+        assert_ylt_close(analyze(A, S, gpu_ctx, w, pl), ref)
+    w0 = synth.Workload("empty-layer", w.event_ids, w.trial_offsets, w.catalog_size, [], w.layer_terms)
+    for pl in PLACEMENTS:
+        assert not np.any(analyze(A, S, gpu_ctx, w0, pl))
+
+
+def test_schedule_independence_and_determinism(A, S, gpu_ctx, small):
+    _say("schedule independence")
+    base = analyze(A, S, gpu_ctx, small)
+    for block, gpc in [(256, 1), (512, 2), (1024, 1), (256, 8), (1024, 0)]:
+        again = analyze(A, S, gpu_ctx, small, block=block, grid_per_cu=gpc)
+        assert again.tobytes() == base.tobytes(), (block, gpc)
+
+
+# ----------------------------------------------------------------------------- sort
+@pytest.mark.parametrize("n", [1, 2, 63, 4095, 4096, 4097, 100_003, 1_000_000])
+def test_sort_bit_exact(A, gpu_ctx, n):
+    import torch
+    _say(f"sort n={n}")
+    rng = np.random.default_rng(n)
+    x = rng.lognormal(10, 3, size=n)
+    x[rng.random(n) < 0.2] = 0.0
+    x[rng.random(n) < 0.05] = -0.0
+    x[rng.random(n) < 0.1] = 5e6          # ties
+    x[rng.random(n) < 0.01] = 1e-300
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    A.ara_sort_desc(gpu_ctx, torch.from_numpy(x).cuda(), out)
+    A.ara_sync(gpu_ctx)
+    got = out.cpu().numpy()
+    want = np.sort(x + 0.0)[::-1]
+    assert got.tobytes() == want.tobytes()
+
+
+# ----------------------------------------------------------------------------- errors
+def test_input_errors(A, S, gpu_ctx):
+    import torch
+    _say("input errors")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    with pytest.raises(A.AraError) as e:
+        A.ara_yet_create(gpu_ctx, dev(np.array([0, 5, 9], np.int32)), dev(np.array([0, 3], np.int64)), 9)
+    assert e.value.status == A.ARA_E_EVENT_ID_RANGE
+    with pytest.raises(A.AraError) as e:
+        A.ara_yet_create(gpu_ctx, dev(np.array([0, 5, 8], np.int32)), dev(np.array([0, 2, 1, 3], np.int64)), 9)
+    assert e.value.status == A.ARA_E_BAD_OFFSETS
+    with pytest.raises(A.AraError) as e:
+        A.ara_yet_create(gpu_ctx, dev(np.array([0, 5, 8], np.int32)), dev(np.array([0, 2], np.int64)), 9)
+    assert e.value.status == A.ARA_E_BAD_OFFSETS
+    for ids, losses, code in [([1, 1], [1.0, 2.0], A.ARA_E_DUP_EVENT), ([9], [1.0], A.ARA_E_EVENT_ID_RANGE),
+                              ([1], [-1.0], A.ARA_E_BAD_LOSS), ([1], [math.nan], A.ARA_E_BAD_LOSS),
+                              ([2], [math.inf], A.ARA_E_BAD_LOSS)]:
+        with pytest.raises(A.AraError) as e:
+            A.ara_elt_create(gpu_ctx, dev(np.array(ids, np.int32)), dev(np.array(losses)), 9)
+        assert e.value.status == code
+    with pytest.raises(A.AraError) as e:
+        A.ara_elt_create(gpu_ctx, dev(np.array([1], np.int32)), dev(np.array([1.0])), 9, terms=(-1.0, 0.0, 1.0))
+    assert e.value.status == A.ARA_E_BAD_TERMS
+    elt = A.ara_elt_create(gpu_ctx, dev(np.array([1], np.int32)), dev(np.array([1.0])), 9)
+    with pytest.raises(A.AraError) as e:
+        A.ara_layer_create(gpu_ctx, [elt], 10, (0, 1, 0, 1))
+    assert e.value.status == A.ARA_E_INVALID_ARG
+    with pytest.raises(A.AraError) as e:
+        A.ara_layer_create(gpu_ctx, [elt], 9, (0, 1, -1, 1))
+    assert e.value.status == A.ARA_E_BAD_TERMS
+    layer = A.ara_layer_create(gpu_ctx, [elt], 9, (0, 1, 0, 1))
+    with pytest.raises(A.AraError) as e:
+        A.ara_elt_release(elt)
+    assert e.value.status == A.ARA_E_BUSY
+    yet = A.ara_yet_create(gpu_ctx, dev(np.array([0, 5, 8], np.int32)), dev(np.array([0, 3], np.int64)), 9)
+    y = torch.empty(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(A.AraError) as e:
+        A.ara_analyze(gpu_ctx, yet, layer, 0, 2, torch.empty(2, dtype=torch.float64, device="cuda"))
+    assert e.value.status == A.ARA_E_INVALID_ARG
+    with pytest.raises(A.AraError) as e:
+        A.ara_risk_measures(gpu_ctx, torch.empty(0, dtype=torch.float64, device="cuda"), [10.0])
+    assert e.value.status == A.ARA_E_EMPTY
+    with pytest.raises(A.AraError) as e:
+        A.ara_risk_measures(gpu_ctx, y, [0.5])
+    assert e.value.status == A.ARA_E_INVALID_ARG
+    with pytest.raises(A.AraError) as e:
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_BLOCK_THREADS, 100)
+    assert e.value.status == A.ARA_E_INVALID_ARG
+    A.ara_analyze(gpu_ctx, yet, layer, 0, 1, y)
+    A.ara_sync(gpu_ctx)
+    A.ara_layer_release(layer)
+    A.ara_elt_release(elt)
+    A.ara_yet_release(yet)
+
+
+# ----------------------------------------------------------------------------- paper-scale shape
+@pytest.fixture(scope="module")
+def paper_reduced():
+    return synth.workload_paper_scale(n_trials=20_000)
+
+
+def _twin_terms(w, ref_occ_total):
+    # aggregate terms that do not saturate: retention near the median occurrence-net total, no limit
+    return (w.layer_terms[0], w.layer_terms[1], float(np.median(ref_occ_total)), INF)
+
+
+def test_paper_shape_reduced_f64(A, S, gpu_ctx, paper_reduced):
+    w = paper_reduced
+    _say("paper shape 20k x 1000 f64")
+    ref = oracle.analyze_workload(w, threads=oracle.max_threads())
+    got = analyze(A, S, gpu_ctx, w)
+    assert_ylt_close(got, ref, what="saturating terms")
+    twin = _twin_terms(w, ref["occ_total"])
+    ref2 = oracle.analyze_workload(w.with_terms(twin), threads=oracle.max_threads())
+    assert np.count_nonzero(ref2["ylt"]) > w.n_trials // 3
+    for pl in [1, 3]:
+        got2 = analyze(A, S, gpu_ctx, w, pl, terms=twin)
+        assert_ylt_close(got2, ref2, what=f"twin placement {pl}")
+    # a 1M-event catalog does not fit LDS as a dense table: forcing it is refused
+    with pytest.raises(A.AraError) as e:
+        analyze(A, S, gpu_ctx, w, 2, terms=twin)
+    assert e.value.status == A.ARA_E_UNSUPPORTED
+
+
+def test_paper_shape_lookups_bit_exact(A, S, gpu_ctx, paper_reduced):
+    import torch
+    w = paper_reduced
+    _say("paper shape lookups")
+    gross, occ = _catalog_lookup_reference(w)
+    for pl in [1, 3]:
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, pl)
+        an = S.open_analysis(gpu_ctx, w.event_ids[:4], np.array([0, 4], np.int64), w.catalog_size, w.elts,
+                             w.layer_terms)
+        try:
+            ids = torch.arange(w.catalog_size, dtype=torch.int32, device="cuda")
+            g = torch.empty(w.catalog_size, dtype=torch.float64, device="cuda")
+            o = torch.empty_like(g)
+            A.ara_lookup(gpu_ctx, an.layer, ids, g, o)
+            A.ara_sync(gpu_ctx)
+            assert np.array_equal(g.cpu().numpy(), gross)
+            assert np.array_equal(o.cpu().numpy(), occ)
+        finally:
+            an.release()
+            A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, 0)
+
+
+def test_paper_shape_reduced_f32_tables(A, S, gpu_ctx, paper_reduced):
+    import torch
+    w = paper_reduced
+    _say("paper shape 20k x 1000 f32 tables")
+    twin = None
+    ref = oracle.analyze_workload(w, threads=oracle.max_threads())
+    twin = _twin_terms(w, ref["occ_total"])
+    for terms in [w.layer_terms, twin]:
+        ref = oracle.analyze_workload(w.with_terms(terms), threads=oracle.max_threads())
+        got = analyze(A, S, gpu_ctx, w, precision=1, terms=terms)
+        bound = 2.0 ** -23 * 1.0001 * ref["gross_total"] + 1e-12 * ref["occ_total"]
+        assert np.all(np.abs(got - ref["ylt"]) <= bound)
+    # the binary32 combined table equals the binary32 rounding of the oracle's sum of binary32 losses
+    gross32, _ = _catalog_lookup_reference(w, precision_f32=True)
+    an = S.open_analysis(gpu_ctx, w.event_ids[:4], np.array([0, 4], np.int64), w.catalog_size, w.elts,
+                         w.layer_terms, None, 1)
+    try:
+        ids = torch.arange(w.catalog_size, dtype=torch.int32, device="cuda")
+        g = torch.empty(w.catalog_size, dtype=torch.float64, device="cuda")
+        A.ara_lookup(gpu_ctx, an.layer, ids, g, None)
+        A.ara_sync(gpu_ctx)
+        assert np.array_equal(g.cpu().numpy(), gross32.astype(np.float32).astype(np.float64))
+    finally:
+        an.release()
