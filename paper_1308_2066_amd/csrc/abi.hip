@@ -136,40 +136,52 @@ static void dev_free(void *p) {
     if (p) (void)hipFree(p);
 }
 
-static int64_t lds_bytes_for(int placement, int32_t catalog) {
-    if (placement == ARA_PLACE_LDS_BITMAP) return bitmap_lds_bytes(catalog);
-    if (placement == ARA_PLACE_LDS_DENSE) return int64_t(catalog) * 8;
-    return 0;
+// The bitmap placement keeps its per-wave event queues in a fixed static LDS array
+// (kQueueWords words, 16 waves x kQueueCapMax), next to the dynamic table.  Returns
+// the queue capacity for a workgroup of wpb waves, or 0 if it cannot run.
+static int bitmap_qcap(int32_t catalog, int wpb, int lds_max) {
+    const int64_t table = int64_t(bitmap_table_bytes(bitmap_blocks(catalog)));
+    if (wpb > 16 || table + int64_t(kQueueWords) * 4 > lds_max) return 0;
+    return kQueueCapMax;
 }
 
-// Chooses where the layer's table lives during the trial kernel.
+// Chooses where the layer's table lives during the trial kernel and the launch shape.
 static ara_status plan_trial(ara_ctx *c, const ara_layer *L, int64_t n_trials, TrialLaunch &tl) {
     int pl = c->placement;
-    const int64_t dense = lds_bytes_for(ARA_PLACE_LDS_DENSE, L->catalog);
-    const int64_t bitmap = lds_bytes_for(ARA_PLACE_LDS_BITMAP, L->catalog);
+    const int64_t dense = int64_t(L->catalog) * 8;
+    const int block_bitmap = c->block_threads ? c->block_threads : 1024;
+    const int qcap = bitmap_qcap(L->catalog, block_bitmap / 64, c->lds_max);
     if (pl == ARA_PLACE_AUTO) {
         if (dense <= c->lds_max) pl = ARA_PLACE_LDS_DENSE;
-        else if (bitmap <= c->lds_max) pl = ARA_PLACE_LDS_BITMAP;
+        else if (qcap > 0) pl = ARA_PLACE_LDS_BITMAP;
         else pl = ARA_PLACE_GLOBAL_DENSE;
     }
-    const int64_t lds = lds_bytes_for(pl, L->catalog);
-    if (lds > c->lds_max)
-        return fail(c, ARA_E_UNSUPPORTED, "placement %d needs %lld bytes of LDS, device allows %d", pl, (long long)lds,
-                    c->lds_max);
+    int64_t lds = 0;
+    if (pl == ARA_PLACE_LDS_DENSE) {
+        lds = dense;
+        if (lds > c->lds_max)
+            return fail(c, ARA_E_UNSUPPORTED, "dense LDS table needs %lld bytes, device allows %d", (long long)lds, c->lds_max);
+    } else if (pl == ARA_PLACE_LDS_BITMAP) {
+        if (qcap == 0)
+            return fail(c, ARA_E_UNSUPPORTED, "LDS bitmap of a %d-event catalog leaves no room for the event queues",
+                        L->catalog);
+        lds = int64_t(bitmap_table_bytes(bitmap_blocks(L->catalog)));   // dynamic part; queues are static
+    }
     tl.placement = pl;
     tl.f32 = L->f32;
     tl.lds_bytes = size_t(lds);
+    tl.qcap = pl == ARA_PLACE_LDS_BITMAP ? qcap : 0;
     tl.block = c->block_threads ? c->block_threads : (pl == ARA_PLACE_GLOBAL_DENSE ? 256 : 1024);
     int per_cu = c->grid_per_cu;
     if (per_cu == 0) {
         const int by_threads = 2048 / tl.block;
-        const int by_lds = lds > 0 ? int(c->lds_max / lds) : by_threads;
+        const int64_t lds_all = lds + (pl == ARA_PLACE_LDS_BITMAP ? int64_t(kQueueWords) * 4 : 0);
+        const int by_lds = lds_all > 0 ? int(c->lds_max / lds_all) : by_threads;
         per_cu = std::max(1, std::min(by_threads, by_lds));
     }
     int64_t grid = int64_t(c->n_cu) * per_cu;
-    const int64_t waves_needed = n_trials;                  // one wave per trial at a time
-    const int64_t wpb = tl.block / 64;
-    grid = std::min<int64_t>(grid, std::max<int64_t>(1, (waves_needed + wpb - 1) / wpb));
+    const int64_t wpb = tl.block / 64;                      // one wave per trial at a time
+    grid = std::min<int64_t>(grid, std::max<int64_t>(1, (n_trials + wpb - 1) / wpb));
     tl.grid = int(grid);
     return ARA_OK;
 }
@@ -500,6 +512,8 @@ static void layer_free(ara_layer *L) {
     dev_free(L->t.occ);
     dev_free(L->t.bitmap);
     dev_free(L->t.rank);
+    dev_free(L->t.rel16);
+    dev_free(L->t.base32);
     dev_free(L->t.vals);
     dev_free(L->t.n_flagged);
     delete L;
@@ -538,6 +552,8 @@ extern "C" ara_status ara_layer_create(ara_ctx *c, ara_elt *const *elts, int32_t
     if (s == ARA_OK) s = dev_alloc(c, &L->t.occ, size_t(catalog) * 8, "layer occurrence table");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.bitmap, size_t(nblk) * 16, "layer bitmap");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.rank, size_t(nblk) * 4, "layer ranks");
+    if (s == ARA_OK) s = dev_alloc(c, &L->t.rel16, align16(size_t(nblk) * 2), "layer relative ranks");
+    if (s == ARA_OK) s = dev_alloc(c, &L->t.base32, align16(size_t(bitmap_supers(nblk)) * 4), "layer rank bases");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.vals, size_t(catalog) * 8, "layer values");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.n_flagged, 16, "layer count");
     if (s == ARA_OK && n_elts > 0) {
@@ -612,7 +628,8 @@ static TrialArgs trial_args(const ara_yet *y, const ara_layer *L, int64_t t0, in
     a.comb = L->t.comb;
     a.occ = L->t.occ;
     a.bitmap = L->t.bitmap;
-    a.rank = L->t.rank;
+    a.rel16 = L->t.rel16;
+    a.base32 = L->t.base32;
     a.vals = L->t.vals;
     a.occ_r = L->terms.occ_retention;
     a.occ_l = L->terms.occ_limit;
@@ -646,7 +663,9 @@ extern "C" ara_status ara_analyze(ara_ctx *c, const ara_yet *y, const ara_layer 
         s = dev_alloc(c, &dst, size_t(t1 - t0) * 8, "ylt staging");
         if (s != ARA_OK) return s;
     }
-    hipError_t e = launch_trial_ylt(trial_args(y, L, t0, t1, dst), tl, c->stream);
+    TrialArgs a = trial_args(y, L, t0, t1, dst);
+    a.qcap = tl.qcap;
+    hipError_t e = launch_trial_ylt(a, tl, c->stream);
     if (e != hipSuccess) s = hip_fail(c, e, "trial kernel");
     if (s == ARA_OK && mem == ARA_MEM_HOST) {
         e = hipMemcpyAsync(ylt, dst, size_t(t1 - t0) * 8, hipMemcpyDeviceToHost, c->stream);

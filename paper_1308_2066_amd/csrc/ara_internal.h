@@ -33,6 +33,8 @@ struct EltDesc {
 //   bitmap  one bit per event: occurrence-net loss of comb[e] is nonzero;
 //           grouped in blocks of 128 events = 4 words
 //   rank    per 128-event block: number of flagged events in earlier blocks
+//   rel16   the same count relative to the first block of its 256-block superblock
+//   base32  per superblock (32768 events): number of flagged events before it
 //   occ     catalog binary64 values: occurrence-net loss min(max(comb[e]-OccR,0),OccL)
 //   vals    occ values of the flagged events, in event order (binary64)
 struct LayerTables {
@@ -40,16 +42,28 @@ struct LayerTables {
     double *occ = nullptr;
     uint32_t *bitmap = nullptr;
     uint32_t *rank = nullptr;
+    uint16_t *rel16 = nullptr;
+    uint32_t *base32 = nullptr;
     double *vals = nullptr;
     uint32_t *n_flagged = nullptr;
     int32_t nblk = 0;
 };
 
 constexpr int kEventsPerBlock = 128;        // events per bitmap block
+constexpr int kBlocksPerSuper = 256;        // bitmap blocks per rank superblock (32768 events)
 constexpr int kLdsMaxBytes = 160 * 1024;    // LDS per workgroup on gfx950
+constexpr int kQueueRow = 64;               // queued events are processed one wave-row at a time
+constexpr int kQueueCapMax = 192;           // per-wave queue capacity (events), a multiple of kQueueRow
+constexpr int kQueueCapMin = 128;
+constexpr int kQueueWords = 16 * kQueueCapMax;  // static LDS of the bitmap trial kernel (16 waves)
 
-inline int32_t bitmap_blocks(int32_t catalog) { return (catalog + kEventsPerBlock - 1) / kEventsPerBlock; }
-inline int64_t bitmap_lds_bytes(int32_t catalog) { return int64_t(bitmap_blocks(catalog)) * (16 + 4); }
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+__host__ __device__ inline int32_t bitmap_blocks(int32_t catalog) { return (catalog + kEventsPerBlock - 1) / kEventsPerBlock; }
+__host__ __device__ inline int32_t bitmap_supers(int32_t nblk) { return (nblk + kBlocksPerSuper - 1) / kBlocksPerSuper; }
+// LDS layout of the bitmap placement: bits | rel16 | base32 | per-wave queues.
+__host__ __device__ inline size_t bitmap_rel_offset(int32_t nblk) { return size_t(nblk) * 16; }
+__host__ __device__ inline size_t bitmap_base_offset(int32_t nblk) { return bitmap_rel_offset(nblk) + align16(size_t(nblk) * 2); }
+__host__ __device__ inline size_t bitmap_table_bytes(int32_t nblk) { return bitmap_base_offset(nblk) + align16(size_t(bitmap_supers(nblk)) * 4); }
 
 // Arguments of the trial kernels.
 struct TrialArgs {
@@ -62,8 +76,11 @@ struct TrialArgs {
     const void *comb;        // combined table (binary64, or binary32 when f32)
     const double *occ;       // occurrence-net table over the catalog
     const uint32_t *bitmap;  // occurrence filter (see LayerTables)
-    const uint32_t *rank;
+    const uint16_t *rel16;
+    const uint32_t *base32;
     const double *vals;
+    int32_t qcap;            // per-wave queue capacity (bitmap placement)
+    int32_t pad_;
     double occ_r, occ_l, agg_r, agg_l;
     double *ylt;
     double *ev_gross, *ev_occ, *ev_cum, *ev_ceded;
@@ -88,6 +105,7 @@ struct TrialLaunch {
     int block;          // threads per workgroup
     int grid;           // workgroups
     size_t lds_bytes;
+    int qcap;           // per-wave queue capacity (bitmap placement)
 };
 hipError_t launch_trial_ylt(const TrialArgs &a, const TrialLaunch &l, hipStream_t s);
 hipError_t launch_trial_events(const TrialArgs &a, bool f32, int grid, hipStream_t s);

@@ -92,6 +92,18 @@ __global__ __launch_bounds__(1024) void k_layer_rank(const uint32_t *__restrict_
     if (tid == 0) *n_flagged = carry;
 }
 
+// rel16/base32: the per-block rank split into a 16-bit offset within its superblock
+// of 256 blocks and a 32-bit base per superblock (a smaller table to keep in LDS).
+__global__ __launch_bounds__(256) void k_layer_rank16(const uint32_t *__restrict__ rank, int32_t nblk,
+                                                      uint16_t *__restrict__ rel16, uint32_t *__restrict__ base32) {
+    const int32_t b = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    const int32_t sb = b / kBlocksPerSuper;
+    const uint32_t base = rank[sb * kBlocksPerSuper];
+    rel16[b] = uint16_t(rank[b] - base);
+    if (b % kBlocksPerSuper == 0) base32[sb] = base;
+}
+
 __global__ __launch_bounds__(256) void k_layer_compact(const double *__restrict__ occ, int32_t catalog,
                                                        const uint32_t *__restrict__ bitmap,
                                                        const uint32_t *__restrict__ rank, double *__restrict__ vals) {
@@ -130,6 +142,10 @@ hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double o
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_layer_rank, dim3(1), dim3(1024), 0, s, t.bitmap, t.nblk, t.rank, t.n_flagged);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_layer_rank16, dim3(unsigned((t.nblk + 255) / 256)), dim3(256), 0, s, t.rank, t.nblk, t.rel16,
+                       t.base32);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_layer_compact, dim3(ev_blocks), dim3(256), 0, s, t.occ, catalog, t.bitmap, t.rank, t.vals);

@@ -6,9 +6,11 @@
 // LSD radix sort of 64-bit keys, 8-bit digits, 8 passes.  A binary64 value maps to
 // an unsigned key whose order is the value order (sign flip for non-negatives,
 // complement for negatives, -0.0 canonicalised to +0.0); descending order sorts the
-// complemented key ascending.  Each pass: per-tile digit counts, one exclusive scan
-// over (digit, tile), and a stable scatter in which every wave ranks its keys by
-// matching digits across lanes with 8 ballots.
+// complemented key ascending.  The encoding pass also counts the digits of all 8
+// passes; a pass in which every key has the same digit is skipped on the device
+// (capped YLTs often hold one value many times).  Each other pass: per-tile digit
+// counts, exclusive offsets per (digit, tile), and a stable scatter in which every
+// wave ranks its keys by matching digits across lanes with 8 ballots.
 #include "ara_internal.h"
 
 namespace ara {
@@ -17,6 +19,7 @@ constexpr int kSortThreads = 256;
 constexpr int kSortPerThread = 16;
 constexpr int kSortTile = kSortThreads * kSortPerThread;   // 4096 keys
 constexpr int kWavesPerTile = kSortThreads / 64;            // 4, each owns 1024 consecutive keys
+constexpr int kPasses = 8;
 
 __device__ __forceinline__ uint64_t desc_key(double d) {
     uint64_t u = __builtin_bit_cast(uint64_t, d + 0.0);   // -0.0 + 0.0 == +0.0
@@ -32,34 +35,78 @@ __device__ __forceinline__ double key_value(uint64_t k) {
 
 static inline int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
-size_t sort_workspace_bytes(int64_t n) {
-    const size_t keys = (size_t(n) * 8 + 255) & ~size_t(255);
-    const size_t counts = (size_t(sort_tiles(n)) * 256 * 4 + 255) & ~size_t(255);
-    return 2 * keys + counts + 256;
-}
-
+// Workspace: two key buffers, per-(digit, tile) counts, the 8 digit histograms of
+// all keys, and the pass plan (which buffer holds the keys before each pass, and
+// which passes leave the order unchanged because every key has the same digit).
 struct SortWs {
     uint64_t *a, *b;
-    uint32_t *counts;
+    uint32_t *counts;   // [256][tiles]
+    uint32_t *hist;     // [8][256]
+    uint32_t *plan;     // plan[p]: keys before pass p are in b (1) or a (0), p = 0..8;
+                        // plan[16 + p]: pass p is skipped
 };
 
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+size_t sort_workspace_bytes(int64_t n) {
+    return 2 * align256(size_t(n) * 8) + align256(size_t(sort_tiles(n)) * 256 * 4) + align256(8 * 256 * 4) + 256;
+}
+
 static SortWs sort_ws(void *ws, int64_t n) {
-    const size_t keys = (size_t(n) * 8 + 255) & ~size_t(255);
     char *p = reinterpret_cast<char *>(ws);
-    return SortWs{reinterpret_cast<uint64_t *>(p), reinterpret_cast<uint64_t *>(p + keys),
-                  reinterpret_cast<uint32_t *>(p + 2 * keys)};
+    const size_t keys = align256(size_t(n) * 8);
+    const size_t counts = align256(size_t(sort_tiles(n)) * 256 * 4);
+    SortWs w;
+    w.a = reinterpret_cast<uint64_t *>(p);
+    w.b = reinterpret_cast<uint64_t *>(p + keys);
+    w.counts = reinterpret_cast<uint32_t *>(p + 2 * keys);
+    w.hist = reinterpret_cast<uint32_t *>(p + 2 * keys + counts);
+    w.plan = reinterpret_cast<uint32_t *>(p + 2 * keys + counts + align256(8 * 256 * 4));
+    return w;
 }
 
+__device__ __forceinline__ const uint64_t *cur_keys(const SortWs &w, int pass) {
+    return w.plan[pass] ? w.b : w.a;
+}
+
+__global__ __launch_bounds__(256) void k_sort_init(uint32_t *hist, uint32_t *plan) {
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) hist[i] = 0;
+    if (threadIdx.x < 32) plan[threadIdx.x] = 0;
+}
+
+// Encode values into descending-order keys and count the digits of all 8 passes.
 __global__ __launch_bounds__(256) void k_sort_encode(const double *__restrict__ in, int64_t n,
-                                                     uint64_t *__restrict__ keys) {
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-        keys[i] = desc_key(in[i]);
+                                                     uint64_t *__restrict__ keys, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[8][256];
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
+    __syncthreads();
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const uint64_t k = desc_key(in[i]);
+        keys[i] = k;
+#pragma unroll
+        for (int p = 0; p < 8; ++p) atomicAdd(&h[p][uint32_t(k >> (8 * p)) & 255u], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) {
+        const uint32_t v = (&h[0][0])[i];
+        if (v) atomicAdd(hist + i, v);
+    }
 }
 
-__global__ __launch_bounds__(256) void k_sort_decode(const uint64_t *__restrict__ keys, int64_t n,
-                                                     double *__restrict__ out) {
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
-        out[i] = key_value(keys[i]);
+// Pass p leaves the order unchanged when one digit value holds all n keys; then
+// its kernels do nothing and the keys stay in the same buffer.
+__global__ void k_sort_plan(const uint32_t *__restrict__ hist, int64_t n, uint32_t *__restrict__ plan) {
+    if (threadIdx.x != 0) return;
+    uint32_t sel = 0;
+    plan[0] = 0;
+    for (int p = 0; p < kPasses; ++p) {
+        uint32_t triv = 0;
+        for (int d = 0; d < 256; ++d)
+            if (int64_t(hist[p * 256 + d]) == n) triv = 1;
+        plan[16 + p] = triv;
+        sel = triv ? sel : 1u - sel;
+        plan[p + 1] = sel;
+    }
 }
 
 // Lanes whose digit equals this lane's digit (among lanes with `valid`).
@@ -76,118 +123,135 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, bool valid) {
 __device__ __forceinline__ uint64_t lanes_below(int lane) { return lane ? (~0ull >> (64 - lane)) : 0ull; }
 
 // counts[d * tiles + tile] = number of keys of the tile with digit d
-__global__ __launch_bounds__(kSortThreads) void k_sort_count(const uint64_t *__restrict__ keys, int64_t n, int shift,
-                                                            uint32_t *__restrict__ counts, int64_t tiles) {
+__global__ __launch_bounds__(kSortThreads) void k_sort_count(SortWs w, int64_t n, int pass, int64_t tiles) {
+    if (w.plan[16 + pass]) return;
     __shared__ uint32_t hist[256];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t *keys = cur_keys(w, pass);
+    const int shift = 8 * pass;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     hist[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = int64_t(blockIdx.x) * kSortTile + w * 1024;
+    const int64_t base = int64_t(blockIdx.x) * kSortTile + wv * 1024;
+    uint32_t d[kSortPerThread];
+#pragma unroll
     for (int r = 0; r < kSortPerThread; ++r) {
         const int64_t i = base + r * 64 + lane;
-        const bool valid = i < n;
-        const uint32_t d = valid ? uint32_t(keys[i] >> shift) & 255u : 0u;
-        const uint64_t m = match_digit(d, valid);
-        if (valid && (m & lanes_below(lane)) == 0) atomicAdd(&hist[d], uint32_t(__popcll(m)));
+        d[r] = i < n ? uint32_t(keys[i] >> shift) & 255u : 0u;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortPerThread; ++r) {
+        const bool valid = base + r * 64 + lane < n;
+        const uint64_t m = match_digit(d[r], valid);
+        if (valid && (m & lanes_below(lane)) == 0) atomicAdd(&hist[d[r]], uint32_t(__popcll(m)));
     }
     __syncthreads();
-    counts[int64_t(threadIdx.x) * tiles + blockIdx.x] = hist[threadIdx.x];
+    w.counts[int64_t(threadIdx.x) * tiles + blockIdx.x] = hist[threadIdx.x];
 }
 
-// In-place exclusive scan of len counters (one workgroup of 1024).
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ c, int64_t len) {
-    __shared__ uint32_t part[1024];
-    const int t = threadIdx.x;
-    const int64_t per = (len + 1023) / 1024;
-    const int64_t b = t * per, e = (b + per < len) ? b + per : len;
+// Exclusive offsets of every (digit, tile): thread d sums row d, the 256 row
+// totals are scanned, and each row is rewritten as its running prefix.
+__global__ __launch_bounds__(256) void k_sort_offsets(SortWs w, int pass, int64_t tiles) {
+    if (w.plan[16 + pass]) return;
+    __shared__ uint32_t tot[256];
+    const int d = threadIdx.x;
+    uint32_t *row = w.counts + int64_t(d) * tiles;
     uint32_t s = 0;
-    for (int64_t i = b; i < e; ++i) s += c[i];
-    part[t] = s;
+    for (int64_t t = 0; t < tiles; ++t) s += row[t];
+    tot[d] = s;
     __syncthreads();
-    for (int o = 1; o < 1024; o <<= 1) {   // inclusive Hillis-Steele scan of the partial sums
-        const uint32_t v = t >= o ? part[t - o] : 0u;
+    for (int o = 1; o < 256; o <<= 1) {
+        const uint32_t v = d >= o ? tot[d - o] : 0u;
         __syncthreads();
-        part[t] += v;
+        tot[d] += v;
         __syncthreads();
     }
-    uint32_t run = part[t] - s;
-    for (int64_t i = b; i < e; ++i) {
-        const uint32_t v = c[i];
-        c[i] = run;
+    uint32_t run = tot[d] - s;
+    for (int64_t t = 0; t < tiles; ++t) {
+        const uint32_t v = row[t];
+        row[t] = run;
         run += v;
     }
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint64_t *__restrict__ in,
-                                                              uint64_t *__restrict__ out, int64_t n, int shift,
-                                                              const uint32_t *__restrict__ offs, int64_t tiles) {
+__global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t n, int pass, int64_t tiles) {
+    if (w.plan[16 + pass]) return;
     __shared__ uint32_t whist[kWavesPerTile][256];
     __shared__ uint32_t woff[kWavesPerTile][256];
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t *in = cur_keys(w, pass);
+    uint64_t *out = w.plan[pass] ? w.a : w.b;
+    const int shift = 8 * pass;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int k = 0; k < kWavesPerTile; ++k) whist[k][threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = int64_t(blockIdx.x) * kSortTile + w * 1024;
+    const int64_t base = int64_t(blockIdx.x) * kSortTile + wv * 1024;
     uint64_t key[kSortPerThread];
     uint32_t rank[kSortPerThread];
+#pragma unroll
     for (int r = 0; r < kSortPerThread; ++r) {
         const int64_t i = base + r * 64 + lane;
-        const bool valid = i < n;
-        key[r] = valid ? in[i] : 0ull;
+        key[r] = i < n ? in[i] : 0ull;
+    }
+#pragma unroll
+    for (int r = 0; r < kSortPerThread; ++r) {
+        const bool valid = base + r * 64 + lane < n;
         const uint32_t d = uint32_t(key[r] >> shift) & 255u;
         const uint64_t m = match_digit(d, valid);
         const uint64_t below = m & lanes_below(lane);
-        rank[r] = whist[w][d] + uint32_t(__popcll(below));   // read before this round's update
-        if (valid && below == 0) whist[w][d] += uint32_t(__popcll(m));
+        rank[r] = whist[wv][d] + uint32_t(__popcll(below));   // read before this round's update
+        if (valid && below == 0) whist[wv][d] += uint32_t(__popcll(m));
     }
     __syncthreads();
     {
         const int d = threadIdx.x;
-        uint32_t run = offs[int64_t(d) * tiles + blockIdx.x];
+        uint32_t run = w.counts[int64_t(d) * tiles + blockIdx.x];
         for (int k = 0; k < kWavesPerTile; ++k) {
             woff[k][d] = run;
             run += whist[k][d];
         }
     }
     __syncthreads();
+#pragma unroll
     for (int r = 0; r < kSortPerThread; ++r) {
         const int64_t i = base + r * 64 + lane;
         if (i < n) {
             const uint32_t d = uint32_t(key[r] >> shift) & 255u;
-            out[woff[w][d] + rank[r]] = key[r];
+            out[woff[wv][d] + rank[r]] = key[r];
         }
     }
 }
 
-// Sorted descending keys of `in` end in the first key buffer of the workspace.
+__global__ __launch_bounds__(256) void k_sort_decode(SortWs w, int64_t n, double *__restrict__ out) {
+    const uint64_t *keys = cur_keys(w, kPasses);
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = key_value(keys[i]);
+}
+
+// Sorted descending keys of `in` end in the workspace key buffer the plan names.
 hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     SortWs w = sort_ws(ws, n);
     const int64_t tiles = sort_tiles(n);
-    const unsigned eb = unsigned(std::min<int64_t>((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_sort_encode, dim3(eb), dim3(256), 0, s, in, n, w.a);
+    const unsigned eb = unsigned(std::min<int64_t>((n + 255) / 256, 256));
+    hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, s, w.hist, w.plan);
+    hipLaunchKernelGGL(k_sort_encode, dim3(eb), dim3(256), 0, s, in, n, w.a, w.hist);
+    hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(64), 0, s, w.hist, n, w.plan);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    uint64_t *src = w.a, *dst = w.b;
-    for (int pass = 0; pass < 8; ++pass) {
-        const int shift = pass * 8;
-        hipLaunchKernelGGL(k_sort_count, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, src, n, shift, w.counts, tiles);
-        hipLaunchKernelGGL(k_sort_scan, dim3(1), dim3(1024), 0, s, w.counts, tiles * 256);
-        hipLaunchKernelGGL(k_sort_scatter, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, src, dst, n, shift, w.counts,
-                           tiles);
+    for (int pass = 0; pass < kPasses; ++pass) {
+        hipLaunchKernelGGL(k_sort_count, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, w, n, pass, tiles);
+        hipLaunchKernelGGL(k_sort_offsets, dim3(1), dim3(256), 0, s, w, pass, tiles);
+        hipLaunchKernelGGL(k_sort_scatter, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, w, n, pass, tiles);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
-        uint64_t *t = src;
-        src = dst;
-        dst = t;
     }
-    return hipSuccess;   // 8 passes: result back in w.a
+    return hipSuccess;
 }
 
 hipError_t launch_sort_decode(const void *ws, int64_t n, double *out, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     SortWs w = sort_ws(const_cast<void *>(ws), n);
     const unsigned eb = unsigned(std::min<int64_t>((n + 255) / 256, 4096));
-    hipLaunchKernelGGL(k_sort_decode, dim3(eb), dim3(256), 0, s, w.a, n, out);
+    hipLaunchKernelGGL(k_sort_decode, dim3(eb), dim3(256), 0, s, w, n, out);
     return hipGetLastError();
 }
 
@@ -197,9 +261,9 @@ struct RiskKs {
     int64_t k[16];
 };
 
-__global__ __launch_bounds__(1024) void k_risk(const uint64_t *__restrict__ keys, RiskKs ks, int n_k,
-                                               double *__restrict__ out) {
+__global__ __launch_bounds__(1024) void k_risk(SortWs w, RiskKs ks, int n_k, double *__restrict__ out) {
     __shared__ double part[1024];
+    const uint64_t *keys = cur_keys(w, kPasses);
     const int64_t k = ks.k[blockIdx.x];
     double s = 0.0;
     for (int64_t i = threadIdx.x; i < k; i += 1024) s += key_value(keys[i]);
@@ -222,7 +286,7 @@ hipError_t launch_risk(const void *ws, int64_t n, const int64_t *ks, int n_k, do
         const int m = std::min(16, n_k - base);
         for (int i = 0; i < m; ++i) r.k[i] = ks[base + i];
         // out layout per group: pml[m], tvar[m]
-        hipLaunchKernelGGL(k_risk, dim3(unsigned(m)), dim3(1024), 0, s, w.a, r, m, out + 2 * base);
+        hipLaunchKernelGGL(k_risk, dim3(unsigned(m)), dim3(1024), 0, s, w, r, m, out + 2 * base);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
