@@ -136,12 +136,12 @@ static void dev_free(void *p) {
     if (p) (void)hipFree(p);
 }
 
-// The bitmap placement keeps its per-wave event queues in a fixed static LDS array
-// (kQueueWords words, 16 waves x kQueueCapMax), next to the dynamic table.  Returns
-// the queue capacity for a workgroup of wpb waves, or 0 if it cannot run.
+// The bitmap trial kernel keeps the filter tables and its per-wave event queues
+// (16 waves x kQueueCapMax events) in static LDS.  Returns the queue capacity for a
+// workgroup of wpb waves, or 0 if the catalog's tables do not fit.
 static int bitmap_qcap(int32_t catalog, int wpb, int lds_max) {
-    const int64_t table = int64_t(bitmap_table_bytes(bitmap_blocks(catalog)));
-    if (wpb > 16 || table + int64_t(kQueueWords) * 4 > lds_max) return 0;
+    const size_t table = bitmap_table_bytes(bitmap_blocks(catalog));
+    if (wpb > 16 || lds_max < kLdsMaxBytes || table > trial_bitmap_table_capacity()) return 0;
     return kQueueCapMax;
 }
 
@@ -165,7 +165,7 @@ static ara_status plan_trial(ara_ctx *c, const ara_layer *L, int64_t n_trials, T
         if (qcap == 0)
             return fail(c, ARA_E_UNSUPPORTED, "LDS bitmap of a %d-event catalog leaves no room for the event queues",
                         L->catalog);
-        lds = int64_t(bitmap_table_bytes(bitmap_blocks(L->catalog)));   // dynamic part; queues are static
+        lds = int64_t(bitmap_table_bytes(bitmap_blocks(L->catalog)));   // lookup kernel: dynamic LDS table
     }
     tl.placement = pl;
     tl.f32 = L->f32;
@@ -175,7 +175,7 @@ static ara_status plan_trial(ara_ctx *c, const ara_layer *L, int64_t n_trials, T
     int per_cu = c->grid_per_cu;
     if (per_cu == 0) {
         const int by_threads = 2048 / tl.block;
-        const int64_t lds_all = lds + (pl == ARA_PLACE_LDS_BITMAP ? int64_t(kQueueWords) * 4 : 0);
+        const int64_t lds_all = pl == ARA_PLACE_LDS_BITMAP ? int64_t(kLdsMaxBytes) : lds;   // static LDS = all of it
         const int by_lds = lds_all > 0 ? int(c->lds_max / lds_all) : by_threads;
         per_cu = std::max(1, std::min(by_threads, by_lds));
     }
@@ -663,9 +663,15 @@ extern "C" ara_status ara_analyze(ara_ctx *c, const ara_yet *y, const ara_layer 
         s = dev_alloc(c, &dst, size_t(t1 - t0) * 8, "ylt staging");
         if (s != ARA_OK) return s;
     }
-    TrialArgs a = trial_args(y, L, t0, t1, dst);
-    a.qcap = tl.qcap;
-    hipError_t e = launch_trial_ylt(a, tl, c->stream);
+    // trial indices inside a launch are 32-bit: split very long ranges
+    constexpr int64_t kMaxTrialsPerLaunch = int64_t(1) << 30;
+    hipError_t e = hipSuccess;
+    for (int64_t tb = t0; tb < t1 && e == hipSuccess; tb += kMaxTrialsPerLaunch) {
+        const int64_t te = std::min(t1, tb + kMaxTrialsPerLaunch);
+        TrialArgs a = trial_args(y, L, tb, te, dst + (tb - t0));
+        a.qcap = tl.qcap;
+        e = launch_trial_ylt(a, tl, c->stream);
+    }
     if (e != hipSuccess) s = hip_fail(c, e, "trial kernel");
     if (s == ARA_OK && mem == ARA_MEM_HOST) {
         e = hipMemcpyAsync(ylt, dst, size_t(t1 - t0) * 8, hipMemcpyDeviceToHost, c->stream);

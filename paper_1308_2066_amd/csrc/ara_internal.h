@@ -112,6 +112,9 @@ hipError_t launch_trial_events(const TrialArgs &a, bool f32, int grid, hipStream
 hipError_t launch_lookup(const TrialArgs &a, const TrialLaunch &l, const int32_t *ids, int64_t n, double *gross,
                          double *occ, hipStream_t s);
 hipError_t prepare_trial_kernels();
+// bitmap placement (static LDS: filter tables up to trial_bitmap_table_capacity() bytes + event queues)
+hipError_t launch_trial_ylt_bitmap(const TrialArgs &a, int grid, int block, hipStream_t s);
+size_t trial_bitmap_table_capacity();
 
 // ---- order statistics
 size_t sort_workspace_bytes(int64_t n);

@@ -18,55 +18,15 @@
 //     buffer's record count clipping the trial's end so no byte past it is fetched;
 //   * segment i+2 is loaded while segment i is looked up (two register buffers);
 //   * the occurrence-net value of an event comes from LDS when the layer's table
-//     fits (dense), else from an LDS bitmap of the events whose occurrence-net loss
-//     is nonzero: the 16 bit tests of a segment are issued back to back, the flagged
-//     events (a small fraction) are compacted into a per-wave LDS queue, and rank
-//     computation plus the L2 read of their values run on full 64-lane rows of that
-//     queue (the ID stream is the only large HBM stream);
+//     fits (this file: dense table), or from an LDS bitmap of the events whose
+//     occurrence-net loss is nonzero (k_trial_bitmap.hip), or, for catalogs too
+//     large for either, from the dense table in HBM/L2 (this file);
 //   * persistent grid: one workgroup per LDS-sized slot of each compute unit, so the
 //     table is staged into LDS once per workgroup; consecutive trials go to the waves
 //     of one workgroup (same XCD), which shares their boundary cache lines.
-#include "ara_internal.h"
+#include "trial_common.h"
 
 namespace ara {
-
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
-constexpr int kChunk = 256;               // events per wave-wide 16-byte load
-constexpr int kNch = 4;                   // loads per segment
-constexpr int kSeg = kChunk * kNch;       // events per segment
-constexpr int kSlots = kNch * 4;          // events per lane per segment
-constexpr int kBufWord3 = 0x00020000;     // raw buffer descriptor word 3 (32-bit data format)
-constexpr int kNonTemporal = 2;           // cache policy of the ID stream loads
-
-__device__ __forceinline__ double excess(double x, double retention, double limit) {
-    double v = x - retention;
-    v = v < 0.0 ? 0.0 : v;
-    return v > limit ? limit : v;
-}
-
-// Sum over the wave (xor butterfly: every lane ends with the same value, since
-// a + b == b + a exactly in IEEE arithmetic).
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
-}
-
-// Values every lane of the wave agrees on, kept in scalar registers.
-__device__ __forceinline__ int64_t uniform64(int64_t x) {
-    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x)));
-    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x) >> 32));
-    return int64_t((uint64_t(hi) << 32) | lo);
-}
-
-// Trial offsets are read through the scalar data path (constant address space):
-// they are wave-uniform and their loads then wait on the scalar counter instead of
-// joining the in-order vector-memory queue behind the event-ID prefetch.
-typedef const __attribute__((address_space(4))) int64_t *const_i64_ptr;
-__device__ __forceinline__ int64_t offset_at(const int64_t *offs, int64_t t) {
-    return ((const_i64_ptr)offs)[t];
-}
 
 // Wave-uniform position in a wave's sequence of (trial, segment).
 struct Cursor {
@@ -114,73 +74,17 @@ __device__ __forceinline__ Cursor seg_next(const TrialArgs &a, const Cursor &c, 
     return n;
 }
 
-// Issue the four ID loads of a segment.  Bytes past min(round4(o1), n_events) are
-// outside the buffer record and read as 0 without a memory access; a finished
-// cursor reads nothing.  The loads are always issued so the number of outstanding
-// vector-memory operations is the same on every path.
 __device__ __forceinline__ void load_seg(const TrialArgs &a, const Cursor &c, int lane, u32x4 (&r)[kNch]) {
-    int64_t avail64 = 0;
-    if (c.t < a.t_end) {
-        int64_t end = (c.o1 + 3) & ~int64_t(3);
-        if (end > a.n_events) end = a.n_events;
-        avail64 = end - c.sbase;
-        avail64 = avail64 < 0 ? 0 : (avail64 > kSeg ? kSeg : avail64);
-    }
-    const int avail = int(avail64);   // events readable from sbase, 0..kSeg
-    const int32_t *base = a.ids + (c.t < a.t_end ? c.sbase : 0);
-    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)base, 0, avail * 4, kBufWord3);
-#pragma unroll
-    for (int k = 0; k < kNch; ++k)
-        r[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, k * kChunk * 4 + lane * 16, 0, kNonTemporal);
-    if (avail & 3) {
-        // The YET ends inside one lane's 16-byte group: fetch that group's IDs one
-        // dword at a time so a partially covered 16-byte load cannot drop them.
-        const int g = (avail & ~3) - lane * 4;   // group start relative to chunk k: k * kChunk
-#pragma unroll
-        for (int k = 0; k < kNch; ++k) {
-            if (g == k * kChunk) {
-                const int e0 = k * kChunk + lane * 4;
-                for (int j = 0; j < 4; ++j) {
-                    uint32_t v = 0;
-                    if (e0 + j < avail) v = __builtin_amdgcn_raw_buffer_load_b32(rs, (e0 + j) * 4, 0, 0);
-                    r[k][j] = v;
-                }
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------------
-// Occurrence-net lookups.  `e` is a valid catalog event.
-//   bitmap placement: bits[e>>5] bit (e&31) set <=> the event's occurrence-net loss
-//   is nonzero; its value is vals[rank of e among set bits].
-__device__ __forceinline__ uint32_t bitmap_rank(const uint32_t *lds, int32_t nblk, uint32_t e) {
-    const uint32_t blk = e >> 7, q = (e >> 5) & 3u, bit = e & 31u;
-    const u32x4 W = reinterpret_cast<const u32x4 *>(lds)[blk];
-    const uint16_t *lrel = reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(lds) + bitmap_rel_offset(nblk));
-    const uint32_t *lbase = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lds) + bitmap_base_offset(nblk));
-    const uint32_t word = q == 0 ? W.x : (q == 1 ? W.y : (q == 2 ? W.z : W.w));
-    uint32_t idx = lbase[e >> 15] + uint32_t(lrel[blk]) + __popc(word & ((1u << bit) - 1u));
-    idx += q > 0 ? __popc(W.x) : 0u;
-    idx += q > 1 ? __popc(W.y) : 0u;
-    idx += q > 2 ? __popc(W.z) : 0u;
-    return idx;
+    const bool live = c.t < a.t_end;
+    load_ids(a.ids, live ? c.sbase : 0, live ? seg_avail(c.sbase, c.o1, a.n_events) : 0, lane, r);
 }
 
 // Stage the layer's table into LDS (whole workgroup; ends with a barrier).
 template <int PL>
 __device__ __forceinline__ void stage_lds(const TrialArgs &a, uint32_t *lds) {
     if (PL == ARA_PLACE_LDS_BITMAP) {
-        const int32_t nblk = a.nblk;
-        u32x4 *l4 = reinterpret_cast<u32x4 *>(lds);
-        const u32x4 *g4 = reinterpret_cast<const u32x4 *>(a.bitmap);
-        for (int i = threadIdx.x; i < nblk; i += blockDim.x) l4[i] = g4[i];
-        // rel16 is allocated with 16-byte padding, so whole words can be copied
-        uint32_t *lr = lds + bitmap_rel_offset(nblk) / 4;
-        const uint32_t *gr = reinterpret_cast<const uint32_t *>(a.rel16);
-        for (int i = threadIdx.x; i < (nblk + 1) / 2; i += blockDim.x) lr[i] = gr[i];
-        uint32_t *lb = lds + bitmap_base_offset(nblk) / 4;
-        for (int i = threadIdx.x; i < bitmap_supers(nblk); i += blockDim.x) lb[i] = a.base32[i];
+        stage_bitmap(a, lds);
+        return;
     } else if (PL == ARA_PLACE_LDS_DENSE) {
         // occurrence-net table, catalog doubles = 2*catalog words
         const uint32_t *g = reinterpret_cast<const uint32_t *>(a.occ);
@@ -234,89 +138,6 @@ __device__ __forceinline__ void seg_lookup(const TrialArgs &a, const uint32_t *l
     }
 }
 
-// ---------------------------------------------------------------------------------
-// Bitmap placement, per segment.
-// Filter: for each of the lane's 16 slots, test the event's bit (one LDS read each,
-// all issued before any is used).  Queue: flagged events are appended, slot by slot,
-// to the wave's LDS queue in lane order; if the next slot could overflow it, the
-// queued events are resolved first (rank, L2 read, accumulate).  Rows: the queued
-// events are resolved 64 at a time, their L2 reads issued before the next prefetch.
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t vals_rsrc(const TrialArgs &a) {
-    const uint32_t C = uint32_t(a.catalog);
-    return __builtin_amdgcn_make_buffer_rsrc((void *)a.vals, 0, int(C * 8u), kBufWord3);
-}
-
-__device__ __forceinline__ double load_val(__amdgpu_buffer_rsrc_t vr, uint32_t idx) {
-    const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(vr, idx * 8u, 0, 0));
-    return __builtin_bit_cast(double, q);
-}
-
-// Resolve queue entries [0, qn) now, in queue order (the rare overflow path).
-__device__ __forceinline__ void drain_queue(const TrialArgs &a, const uint32_t *lds, const uint32_t *q, uint32_t qn,
-                                         int lane, double &acc) {
-    const __amdgpu_buffer_rsrc_t vr = vals_rsrc(a);
-    for (uint32_t r0 = 0; r0 < qn; r0 += kQueueRow) {
-        double v = 0.0;
-        if (r0 + lane < qn) v = load_val(vr, bitmap_rank(lds, a.nblk, q[r0 + lane]));
-        acc += v;
-    }
-}
-
-__device__ __forceinline__ uint32_t seg_bitmap_queue(const TrialArgs &a, const uint32_t *lds, uint32_t *q,
-                                                     const u32x4 (&r)[kNch], int lane, int lo, int hi,
-                                                     uint32_t &bad, double &acc) {
-    const uint32_t C = uint32_t(a.catalog);
-    uint32_t e[kSlots], w[kSlots];
-    uint32_t vm = 0, mx = 0;
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        const int rel = (s >> 2) * kChunk + lane * 4 + (s & 3);
-        const uint32_t id = r[s >> 2][s & 3];
-        const bool valid = rel >= lo && rel < hi;
-        vm |= uint32_t(valid) << s;
-        mx = valid && id > mx ? id : mx;
-        e[s] = min(id, C - 1u);
-        w[s] = lds[e[s] >> 5];
-    }
-    if (mx >= C) bad |= ERR_ID_RANGE;
-    uint32_t qn = 0;
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        const bool f = ((vm >> s) & 1u) && ((w[s] >> (e[s] & 31u)) & 1u);
-        const uint64_t m = __ballot(f);
-        const uint32_t cnt = uint32_t(__popcll(m));
-        if (qn + cnt > uint32_t(a.qcap)) {
-            drain_queue(a, lds, q, qn, lane, acc);
-            qn = 0;
-        }
-        if (f) {
-            const uint32_t pos = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), qn));
-            q[pos] = e[s];
-        }
-        qn += cnt;
-    }
-    return qn;
-}
-
-constexpr int kRowsMax = kQueueCapMax / kQueueRow;
-
-// Issue the L2 reads of the queued values: always kRowsMax 64-lane reads, lanes
-// past the queue reading out of the buffer record (0, no memory access), so the
-// number of outstanding vector-memory operations per segment is fixed.
-__device__ __forceinline__ void seg_bitmap_rows(const TrialArgs &a, const uint32_t *lds, const uint32_t *q,
-                                                uint32_t qn, int lane, double (&v)[kRowsMax]) {
-    const __amdgpu_buffer_rsrc_t vr = vals_rsrc(a);
-#pragma unroll
-    for (int k = 0; k < kRowsMax; ++k) {
-        const uint32_t slot = uint32_t(k) * kQueueRow + uint32_t(lane);
-        const bool act = slot < qn;
-        const uint32_t e = act ? q[slot] : 0u;
-        const uint32_t off = act ? bitmap_rank(lds, a.nblk, e) * 8u : 0xFFFFFFF8u;
-        const uint2 r = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(vr, off, 0, 0));
-        v[k] = __builtin_bit_cast(double, r);
-    }
-}
-
 __device__ __forceinline__ void seg_bounds(const Cursor &c, int &lo, int &hi) {
     const int64_t l = c.o0 - c.sbase, h = c.o1 - c.sbase;
     lo = int(l < 0 ? 0 : l);
@@ -328,106 +149,9 @@ __device__ __forceinline__ void finish_trial(const TrialArgs &a, int64_t t, doub
     if (lane == 0) a.ylt[t - a.t_begin] = excess(P, a.agg_r, a.agg_l);
 }
 
-// Bitmap placement, software-pipelined over segments:
-//   iteration i:  ID loads of segment i are complete  ->  filter + queue (LDS)
-//                 -> issue the value reads of segment i -> issue the ID loads of
-//                 segment i+2 -> add the values of segment i-1 (issued one
-//                 iteration earlier) to its trial.
-// Vector-memory operations complete in issue order, so waiting for the values of
-// segment i-1 never waits for the ID loads of segments i+1 and i+2, issued after
-// them: each ID load has two iterations to arrive.  Unrolled by two so in-flight
-// registers are never copied.
-struct Pending {
-    Cursor c;        // segment whose values are in flight (c.t >= t_end: none)
-    double dacc;     // values already resolved for it (queue overflow path)
-};
-
-__device__ __forceinline__ void bitmap_issue(const TrialArgs &a, uint32_t *lds, uint32_t *q, u32x4 (&r)[kNch],
-                                             const Cursor &cur, const Cursor &nxt, int lane, uint32_t &bad,
-                                             double (&v)[kRowsMax], double &dacc) {
-    int lo, hi;
-    seg_bounds(cur, lo, hi);
-    dacc = 0.0;
-    const uint32_t qn = seg_bitmap_queue(a, lds, q, r, lane, lo, hi, bad, dacc);
-    seg_bitmap_rows(a, lds, q, qn, lane, v);
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-    load_seg(a, nxt, lane, r);
-    asm volatile("" ::: "memory");
-    __builtin_amdgcn_sched_barrier(0);
-}
-
-// Adds a finished segment's values to its trial; writes the trial's YLT entry if
-// it was the trial's last segment.
-__device__ __forceinline__ void bitmap_retire(const TrialArgs &a, const Pending &p, const double (&v)[kRowsMax],
-                                              int lane, double &acc) {
-    if (p.c.t >= a.t_end) return;
-    double s = p.dacc;
-#pragma unroll
-    for (int k = 0; k < kRowsMax; ++k) s += v[k];
-    acc += s;
-    if (seg_last(p.c)) {
-        finish_trial(a, p.c.t, acc, lane);
-        acc = 0.0;
-    }
-}
-
-__global__ __launch_bounds__(1024) void k_trial_ylt_bitmap(TrialArgs a) {
-    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];            // bitmap tables
-    __shared__ __attribute__((aligned(16))) uint32_t queues[kQueueWords];     // per-wave event queues
-    stage_lds<ARA_PLACE_LDS_BITMAP>(a, lds);
-
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int wpb = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
-    const int64_t stride = int64_t(__builtin_amdgcn_readfirstlane(gridDim.x)) * wpb;
-    uint32_t *q = queues + size_t(wave) * a.qcap;
-    uint32_t bad = 0;
-
-    Cursor c0, c1;
-    open_trial(a, a.t_begin + int64_t(blockIdx.x) * wpb + wave, c0, bad);
-    u32x4 A[kNch], B[kNch];
-    load_seg(a, c0, lane, A);
-    c1 = seg_next(a, c0, stride, bad);
-    load_seg(a, c1, lane, B);
-
-    double vA[kRowsMax], vB[kRowsMax];
-#pragma unroll
-    for (int k = 0; k < kRowsMax; ++k) vB[k] = 0.0;
-    Pending pA, pB;
-    pB.c.t = a.t_end;   // nothing in flight yet
-    pB.dacc = 0.0;
-    double acc = 0.0;
-    while (c0.t < a.t_end) {
-        c0 = uniform_cursor(c0);
-        c1 = uniform_cursor(c1);
-        pB.c = uniform_cursor(pB.c);
-        const Cursor c2 = uniform_cursor(seg_next(a, c1, stride, bad));
-        bitmap_issue(a, lds, q, A, c0, c2, lane, bad, vA, pA.dacc);
-        pA.c = c0;
-        bitmap_retire(a, pB, vB, lane, acc);
-        if (c1.t >= a.t_end) {
-            bitmap_retire(a, pA, vA, lane, acc);
-            pB.c.t = a.t_end;
-            break;
-        }
-        const Cursor c3 = uniform_cursor(seg_next(a, c2, stride, bad));
-        bitmap_issue(a, lds, q, B, c1, c3, lane, bad, vB, pB.dacc);
-        pB.c = c1;
-        bitmap_retire(a, pA, vA, lane, acc);
-        if (c2.t >= a.t_end) {
-            bitmap_retire(a, pB, vB, lane, acc);
-            break;
-        }
-        c0 = c2;
-        c1 = c3;
-    }
-    if (bad) atomicOr(a.err, bad);
-}
-
-// One segment: look up its events (bitmap: filter + queue; the L2 reads of the
-// queued values are left in flight in v), then issue the loads of segment `nxt`
-// into the register buffer just consumed, then add the values.
+// One segment: look up its events (the L2 reads of the global placement are left
+// in flight in v), then issue the loads of segment `nxt` into the register buffer
+// just consumed, then add the values.
 template <int PL>
 __device__ __forceinline__ void seg_step(const TrialArgs &a, uint32_t *lds, uint32_t *q, u32x4 (&r)[kNch],
                                          const Cursor &cur, const Cursor &nxt, int lane, uint32_t &bad, double &acc) {
@@ -609,9 +333,6 @@ hipError_t prepare_trial_kernels() {
     e = hipFuncSetAttribute(reinterpret_cast<const void *>(fn), hipFuncAttributeMaxDynamicSharedMemorySize, \
                             kLdsMaxBytes);                                                               \
     if (e != hipSuccess) return e;
-    e = hipFuncSetAttribute(reinterpret_cast<const void *>(k_trial_ylt_bitmap),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kLdsMaxBytes - kQueueWords * 4);
-    if (e != hipSuccess) return e;
     ARA_SET_LDS(k_trial_ylt<ARA_PLACE_LDS_DENSE>)
     ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_BITMAP, double>))
     ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_DENSE, double>))
@@ -624,8 +345,7 @@ hipError_t prepare_trial_kernels() {
 hipError_t launch_trial_ylt(const TrialArgs &a, const TrialLaunch &l, hipStream_t s) {
     switch (l.placement) {
     case ARA_PLACE_LDS_BITMAP:
-        hipLaunchKernelGGL(k_trial_ylt_bitmap, dim3(l.grid), dim3(l.block), l.lds_bytes, s, a);
-        break;
+        return launch_trial_ylt_bitmap(a, l.grid, l.block, s);
     case ARA_PLACE_LDS_DENSE:
         hipLaunchKernelGGL(k_trial_ylt<ARA_PLACE_LDS_DENSE>, dim3(l.grid), dim3(l.block), l.lds_bytes, s, a);
         break;

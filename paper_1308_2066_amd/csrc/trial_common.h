@@ -1,0 +1,110 @@
+// Device helpers shared by the trial kernels (internal).
+#pragma once
+
+#include "ara_internal.h"
+
+namespace ara {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kChunk = 256;               // events per wave-wide 16-byte load (64 lanes x 4)
+constexpr int kNch = 4;                   // loads per segment
+constexpr int kSeg = kChunk * kNch;       // events per segment
+constexpr int kSlots = kNch * 4;          // events per lane per segment
+constexpr int kBufWord3 = 0x00020000;     // raw buffer descriptor word 3 (32-bit data format)
+constexpr int kNonTemporal = 2;           // cache policy of the ID stream loads
+
+// min(max(x - retention, 0), limit): the excess-of-loss clamp of Table I.
+__device__ __forceinline__ double excess(double x, double retention, double limit) {
+    double v = x - retention;
+    v = v < 0.0 ? 0.0 : v;
+    return v > limit ? limit : v;
+}
+
+// Sum over the wave (xor butterfly: every lane ends with the same value, since
+// a + b == b + a exactly in IEEE arithmetic).
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x)));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(uint64_t(x) >> 32));
+    return int64_t((uint64_t(hi) << 32) | lo);
+}
+
+// Trial offsets are read through the scalar data path (constant address space):
+// they are wave-uniform and their loads then wait on the scalar counter instead of
+// joining the in-order vector-memory queue behind the event-ID prefetch.
+typedef const __attribute__((address_space(4))) int64_t *const_i64_ptr;
+__device__ __forceinline__ int64_t offset_at(const int64_t *offs, int64_t t) { return ((const_i64_ptr)offs)[t]; }
+
+// Issue the four 16-byte ID loads of a segment starting at event sbase, `avail`
+// events readable (0..kSeg; bytes past them are outside the buffer record and read
+// as 0 without a memory access).  Always issued, so the number of outstanding
+// vector-memory operations is the same on every path.
+__device__ __forceinline__ void load_ids(const int32_t *ids, int64_t sbase, int avail, int lane, u32x4 (&r)[kNch]) {
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)(ids + sbase), 0, avail * 4, kBufWord3);
+#pragma unroll
+    for (int k = 0; k < kNch; ++k)
+        r[k] = __builtin_amdgcn_raw_buffer_load_b128(rs, k * kChunk * 4 + lane * 16, 0, kNonTemporal);
+    if (avail & 3) {
+        // The YET ends inside one lane's 16-byte group: fetch that group's IDs one
+        // dword at a time so a partially covered 16-byte load cannot drop them.
+        const int g = (avail & ~3) - lane * 4;
+#pragma unroll
+        for (int k = 0; k < kNch; ++k) {
+            if (g == k * kChunk) {
+                const int e0 = k * kChunk + lane * 4;
+                for (int j = 0; j < 4; ++j) {
+                    uint32_t v = 0;
+                    if (e0 + j < avail) v = __builtin_amdgcn_raw_buffer_load_b32(rs, (e0 + j) * 4, 0, 0);
+                    r[k][j] = v;
+                }
+            }
+        }
+    }
+}
+
+// Events readable from sbase for a trial ending at o1: up to the trial's end
+// rounded up to a 16-byte group, never past the YET, at most one segment.
+__device__ __forceinline__ int seg_avail(int64_t sbase, int64_t o1, int64_t n_events) {
+    int64_t end = (o1 + 3) & ~int64_t(3);
+    if (end > n_events) end = n_events;
+    int64_t a = end - sbase;
+    return int(a < 0 ? 0 : (a > kSeg ? kSeg : a));
+}
+
+// Occurrence filter in LDS (layout: bits | rel16 | base32, see bitmap_*_offset):
+// index among flagged events of flagged event e.
+__device__ __forceinline__ uint32_t bitmap_rank(const uint32_t *tab, int32_t nblk, uint32_t e) {
+    const uint32_t blk = e >> 7, q = (e >> 5) & 3u, bit = e & 31u;
+    const u32x4 W = reinterpret_cast<const u32x4 *>(tab)[blk];
+    const uint16_t *lrel = reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(tab) + bitmap_rel_offset(nblk));
+    const uint32_t *lbase = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + bitmap_base_offset(nblk));
+    const uint32_t word = q == 0 ? W.x : (q == 1 ? W.y : (q == 2 ? W.z : W.w));
+    uint32_t idx = lbase[e >> 15] + uint32_t(lrel[blk]) + __popc(word & ((1u << bit) - 1u));
+    idx += q > 0 ? __popc(W.x) : 0u;
+    idx += q > 1 ? __popc(W.y) : 0u;
+    idx += q > 2 ? __popc(W.z) : 0u;
+    return idx;
+}
+
+// Copy the layer's occurrence filter into LDS (whole workgroup; ends with a barrier).
+__device__ __forceinline__ void stage_bitmap(const TrialArgs &a, uint32_t *tab) {
+    const int32_t nblk = a.nblk;
+    u32x4 *l4 = reinterpret_cast<u32x4 *>(tab);
+    const u32x4 *g4 = reinterpret_cast<const u32x4 *>(a.bitmap);
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) l4[i] = g4[i];
+    // rel16 is allocated with 16-byte padding, so whole words can be copied
+    uint32_t *lr = tab + bitmap_rel_offset(nblk) / 4;
+    const uint32_t *gr = reinterpret_cast<const uint32_t *>(a.rel16);
+    for (int i = threadIdx.x; i < (nblk + 1) / 2; i += blockDim.x) lr[i] = gr[i];
+    uint32_t *lb = tab + bitmap_base_offset(nblk) / 4;
+    for (int i = threadIdx.x; i < bitmap_supers(nblk); i += blockDim.x) lb[i] = a.base32[i];
+    __syncthreads();
+}
+
+}  // namespace ara
