@@ -24,6 +24,7 @@ times the CPU oracle on a bounded sample of the same workload.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -38,9 +39,150 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
+TRIAL_KERNEL = "k_trial_ylt_bitmap"
+# Sources that define the headline trial kernel; recorded counter readings stand
+# only while these are unchanged.
+TRIAL_KERNEL_SOURCES = ("paper_1308_2066_amd/csrc/k_trial_bitmap.hip", "paper_1308_2066_amd/csrc/trial_common.h",
+                        "paper_1308_2066_amd/csrc/ara_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trial_ylt_bitmap.paper_1Mx1000_f64.traffic.txt")
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_digest() -> str:
+    h = hashlib.sha256()
+    for rel in TRIAL_KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(rel.encode() + b"\0" + f.read() + b"\0")
+    return h.hexdigest()
+
+
+def read_kv(path: str) -> dict:
+    out = {}
+    with open(path) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#") and ":" in line:
+                k, v = line.split(":", 1)
+                out[k.strip()] = v.strip()
+    return out
+
+
+def recorded_traffic(args):
+    """HBM bytes per launch of the headline trial kernel from the committed counter
+    summary, if it was taken on this workload with the current kernel sources."""
+    if not (args.workload == "paper" and args.trials == 1_000_000 and args.precision == "f64"
+            and args.placement in (0, 1) and not args.block and not args.grid_per_cu):
+        return None, "no counter summary for this configuration"
+    if not os.path.exists(TRAFFIC_FILE):
+        return None, "no counter summary recorded"
+    kv = read_kv(TRAFFIC_FILE)
+    if kv.get("source_sha256") != kernel_source_digest():
+        return None, "kernel changed since the counters were taken"
+    return float(kv["traffic_bytes"]), os.path.relpath(TRAFFIC_FILE, ROOT)
+
+
+def cpu_baseline(w, target_s: float):
+    """The CPU oracle (all host threads, OpenMP over trials) on the first trials of
+    the same workload, the sample sized to take about target_s seconds: a fixed
+    per-call cost (dense tables of every ELT) plus a per-trial cost, fitted from two
+    short calibration runs.  Includes PML/TVaR of the sample's YLT."""
+    import oracle
+    threads = oracle.max_threads()
+
+    def run(n):
+        t = time.perf_counter()
+        r = oracle.analyze(w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
+                           elt_terms=w.elt_terms, t_begin=0, t_end=n, threads=threads)
+        oracle.risk(r["ylt"], w.return_periods)
+        return time.perf_counter() - t
+
+    run(min(w.n_trials, 100))            # first touch of the oracle's code and inputs
+    na = min(w.n_trials, 4000)
+    nb = min(w.n_trials, 4 * na)
+    ta, tb = run(na), run(nb)
+    per = max((tb - ta) / max(nb - na, 1), 1e-9)
+    fixed = max(ta - na * per, 0.0)
+    n = int(min(w.n_trials, max(nb, (target_s - fixed) / per)))
+    dt = run(n)
+    ev = float(w.trial_offsets[n] - w.trial_offsets[0])
+    log(f"cpu oracle: calibration {na} trials {ta:.2f}s, {nb} trials {tb:.2f}s; sample {n} trials {dt:.1f}s")
+    return {"value": ev / dt, "unit": "trial-events·layers/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} of {w.n_trials} trials ({int(ev)} trial-events, 1 layer) of the same workload, "
+                      f"dense tables built per call, YLT then PML/TVaR; {dt:.1f}s wall"}
+
+
+def _counter_rows(path: str):
+    import csv
+    if os.path.isdir(path):
+        found = [os.path.join(d, f) for d, _, fs in os.walk(path) for f in fs if f.endswith("counter_collection.csv")]
+        if len(found) != 1:
+            raise SystemExit(f"expected one counter_collection.csv under {path}, found {found}")
+        path = found[0]
+    with open(path, newline="") as f:
+        return list(csv.DictReader(f))
+
+
+def derive_traffic(fetch_path: str, write_path: str, copy_mib: int, cmd: str):
+    """Write the counter summary of the headline kernel: FETCH_SIZE and WRITE_SIZE
+    per dispatch, each scaled by the same counter's reading for the plain device
+    copy of copy_mib MiB that the profiled run ends with."""
+    copy_bytes = copy_mib << 20
+
+    def per_dispatch(path, counter):
+        rows = [r for r in _counter_rows(path) if r["Counter_Name"] == counter]
+        kern = [float(r["Counter_Value"]) for r in rows if TRIAL_KERNEL in r["Kernel_Name"]]
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        if not kern or not copies:
+            raise SystemExit(f"{path}: no {TRIAL_KERNEL} or copy dispatches with {counter}")
+        big = max(copies, key=lambda r: int(r["Grid_Size"]))
+        return float(np.mean(kern)), len(kern), float(big["Counter_Value"])
+
+    fk, fn, fc = per_dispatch(fetch_path, "FETCH_SIZE")
+    wk, wn, wc = per_dispatch(write_path, "WRITE_SIZE")
+    f_scale = copy_bytes / 1024.0 / fc
+    w_scale = copy_bytes / 1024.0 / wc
+    traffic = (fk * f_scale + wk * w_scale) * 1024.0
+    lines = [
+        f"# HBM traffic of {TRIAL_KERNEL}, 1,000,000 trials x 1000 events, catalog 1,000,000, 16-ELT layer, binary64",
+        f"# FETCH_SIZE pass: {cmd.format(counter='FETCH_SIZE')}",
+        f"# WRITE_SIZE pass: {cmd.format(counter='WRITE_SIZE')}",
+        "# Each counter is scaled by its own reading for a plain device copy of copy_bytes (the profiled run",
+        "# ends with one): fetch_scale = copy KiB / FETCH_SIZE of the copy, likewise write_scale.",
+        f"kernel: {TRIAL_KERNEL}",
+        f"source_sha256: {kernel_source_digest()}",
+        f"fetch_kib_per_dispatch: {fk:.1f}  (mean of {fn} dispatches)",
+        f"write_kib_per_dispatch: {wk:.1f}  (mean of {wn} dispatches)",
+        f"copy_bytes: {copy_bytes}",
+        f"copy_fetch_kib: {fc:.1f}",
+        f"copy_write_kib: {wc:.1f}",
+        f"fetch_scale: {f_scale:.4f}",
+        f"write_scale: {w_scale:.4f}",
+        f"traffic_bytes: {traffic:.6g}",
+    ]
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_stats(stats_csv: str, out_path: str, cmd: str, top: int = 16):
+    """Short text summary of a rocprofv3 --stats kernel table."""
+    import csv
+    with open(stats_csv, newline="") as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {cmd}", "",
+             f"{'kernel':<60} {'calls':>6} {'avg us':>10} {'min us':>10} {'max us':>10} {'total %':>8}"]
+    for r in rows[:top]:
+        name = r["Name"]
+        name = name if len(name) <= 60 else name[:57] + "..."
+        lines.append(f"{name:<60} {int(r['Calls']):>6} {float(r['AverageNs']) / 1e3:>10.1f} "
+                     f"{float(r['MinNs']) / 1e3:>10.1f} {float(r['MaxNs']) / 1e3:>10.1f} {float(r['Percentage']):>8.2f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 def main():
@@ -57,7 +199,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle sample time (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
+    ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH", "WRITE"),
+                    help="write the trial kernel's counter summary from two rocprofv3 --pmc outputs and exit")
+    ap.add_argument("--profile-cmd", default="", help="command recorded in a written summary")
+    ap.add_argument("--summarize-stats", nargs=2, metavar=("STATS_CSV", "OUT"),
+                    help="write a text summary of a rocprofv3 kernel_stats.csv and exit")
     args = ap.parse_args()
+    if args.derive_traffic:
+        derive_traffic(args.derive_traffic[0], args.derive_traffic[1], args.copy_probe_mib or 1024, args.profile_cmd)
+        return
+    if args.summarize_stats:
+        summarize_stats(args.summarize_stats[0], args.summarize_stats[1], args.profile_cmd)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
@@ -141,24 +294,8 @@ def main():
     an.release()
     ara.ara_ctx_destroy(ctx)
 
-    cpu = None
-    if args.cpu_seconds > 0:
-        import oracle
-        threads = oracle.max_threads()
-        ids, offs = w.event_ids, w.trial_offsets
-        n = 200 if args.workload == "paper" else 1000
-        t = time.perf_counter()
-        oracle.analyze(ids, offs, w.catalog_size, w.elts, w.layer_terms, t_begin=0, t_end=n, threads=threads)
-        dt = time.perf_counter() - t
-        n2 = int(min(w.n_trials, max(n, n * args.cpu_seconds / max(dt, 1e-3))))
-        t = time.perf_counter()
-        oracle.analyze(ids, offs, w.catalog_size, w.elts, w.layer_terms, t_begin=0, t_end=n2, threads=threads)
-        dt = time.perf_counter() - t
-        ev = float(offs[n2] - offs[0])
-        cpu = {"value": ev / dt, "unit": "trial-events·layers/s", "cores": threads, "kind": "oracle",
-               "sample": f"first {n2} trials ({int(ev)} events) of the same workload, {dt:.1f}s wall, "
-                         f"OpenMP over trials"}
-        log(f"cpu oracle: {cpu['value']:.3g} trial-events/s on {threads} threads ({dt:.1f}s)")
+    cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
+    traffic, traffic_note = recorded_traffic(args)
 
     out = {
         "metric": "trial-events·layers/s (1M trials x 1000 events, 16-ELT layer, whole path incl. sort + PML/TVaR)",
@@ -177,8 +314,9 @@ def main():
                    "elts": len(w.elts), "catalog": w.catalog_size,
                    "placement": ara.PLACEMENT_NAMES.get(placement, str(placement)), "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_trial_ylt", "kernel_ms": k_avg, "algorithmic_bytes": alg_bytes},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": TRIAL_KERNEL if placement == ara.ARA_PLACE_LDS_BITMAP else "k_trial_ylt",
+                     "kernel_ms": k_avg, "algorithmic_bytes": alg_bytes, "traffic_source": traffic_note},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

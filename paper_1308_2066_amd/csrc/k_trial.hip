@@ -145,7 +145,7 @@ __device__ __forceinline__ void seg_bounds(const Cursor &c, int &lo, int &hi) {
 }
 
 __device__ __forceinline__ void finish_trial(const TrialArgs &a, int64_t t, double acc, int lane) {
-    const double P = wave_sum(acc);
+    const double P = wave_total(acc);
     if (lane == 0) a.ylt[t - a.t_begin] = excess(P, a.agg_r, a.agg_l);
 }
 
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(256) void k_trial_events(TrialArgs a) {
             if (seg_last(c)) break;
             c.sbase += kSeg;
         }
-        const double tot = wave_sum(lr);
+        const double tot = wave_total(lr);
         if (lane == 0 && a.ylt) a.ylt[t - a.t_begin] = tot;
     }
     if (bad) atomicOr(a.err, bad);

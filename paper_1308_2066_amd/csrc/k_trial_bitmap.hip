@@ -105,43 +105,57 @@ __device__ __forceinline__ void drain_queue(const TrialArgs &a, const uint32_t *
     }
 }
 
-// Filter + queue of one segment held in r; returns the queue length.
+// Filter + queue of one segment held in r; returns the queue length.  Slot s of a
+// lane holds the event at position k*256 + 4*lane + j (s = 4k + j) of the segment;
+// it counts if that position lies in [lo, hi) and the event's filter bit is set.
+// lo < 4, so only lane 0 of the first load can hold events before the trial.
 __device__ __forceinline__ uint32_t seg_queue(const TrialArgs &a, const uint32_t *tab, uint32_t *q,
                                               const u32x4 (&r)[kNch], int lane, int lo, int hi, uint32_t &mx,
                                               double &dacc) {
     const uint32_t cmax = uint32_t(a.catalog) - 1u;
     uint32_t e[kSlots], w[kSlots];
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        const uint32_t id = r[s >> 2][s & 3];
-        mx = max(mx, id);
-        e[s] = min(id, cmax);
+    for (int s = 0; s < kSlots; s += 2) {
+        const uint32_t i0 = r[s >> 2][s & 3], i1 = r[s >> 2][(s & 3) + 1];
+        mx = max(mx, max(i0, i1));
+        e[s] = min(i0, cmax);
+        e[s + 1] = min(i1, cmax);
         w[s] = tab[e[s] >> 5];
+        w[s + 1] = tab[e[s + 1] >> 5];
+    }
+    const int l4 = lane * 4;
+    bool f[kSlots];
+    uint32_t total = 0;
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        const int base = (s >> 2) * kChunk + (s & 3);
+        f[s] = (__builtin_amdgcn_ubfe(w[s], e[s], 1) != 0u) & (l4 < hi - base);
+        if (s < 4) f[s] = f[s] & (l4 + base >= lo);
+        total += uint32_t(__popcll(__builtin_amdgcn_ballot_w64(f[s])));
     }
     uint32_t qn = 0;
+    if (total <= uint32_t(a.qcap)) {
+        // common case: the whole segment fits the queue
 #pragma unroll
-    for (int k = 0; k < kNch; ++k) {
-        // a chunk needs per-event bounds only where the trial starts or ends in it
-        const bool partial = (k == 0 && lo > 0) || (k + 1) * kChunk > hi;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int s = k * 4 + j;
-            bool f = __builtin_amdgcn_ubfe(w[s], e[s], 1) != 0u;
-            if (partial) {
-                // event position k*256 + 4*lane + j must lie in [lo, hi)
-                const int base = k * kChunk + j;
-                const int l4 = lane * 4;
-                f = f && l4 >= __builtin_amdgcn_readfirstlane(lo - base) && l4 < __builtin_amdgcn_readfirstlane(hi - base);
-            }
-            const uint64_t m = __ballot(f);
-            const uint32_t cnt = uint32_t(__popcll(m));
-            if (qn + cnt > uint32_t(a.qcap)) {
-                drain_queue(a, tab, q, qn, lane, dacc);
-                qn = 0;
-            }
-            if (f) q[__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), qn))] = e[s];
-            qn += cnt;
+        for (int s = 0; s < kSlots; ++s) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(f[s]);
+            uint32_t *qs = q + qn;
+            if (f[s]) qs[__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u))] = e[s];
+            qn += uint32_t(__popcll(m));
         }
+        return qn;
+    }
+    // many flagged events: resolve the queue whenever the next slot would overflow it
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        const uint64_t m = __builtin_amdgcn_ballot_w64(f[s]);
+        const uint32_t cnt = uint32_t(__popcll(m));
+        if (qn + cnt > uint32_t(a.qcap)) {
+            drain_queue(a, tab, q, qn, lane, dacc);
+            qn = 0;
+        }
+        if (f[s]) q[__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), qn))] = e[s];
+        qn += cnt;
     }
     return qn;
 }
@@ -197,7 +211,7 @@ __device__ __forceinline__ void retire(const TrialArgs &a, const Pending &p, con
     for (int k = 0; k < kRows; ++k) s += v[k];
     acc += s;
     if (p.last) {
-        const double P = wave_sum(acc);
+        const double P = wave_total(acc);
         if (lane == 0) a.ylt[p.t] = excess(P, a.agg_r, a.agg_l);
         acc = 0.0;
     }

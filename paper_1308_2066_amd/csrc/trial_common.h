@@ -21,12 +21,34 @@ __device__ __forceinline__ double excess(double x, double retention, double limi
     return v > limit ? limit : v;
 }
 
-// Sum over the wave (xor butterfly: every lane ends with the same value, since
-// a + b == b + a exactly in IEEE arithmetic).
-__device__ __forceinline__ double wave_sum(double x) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
-    return x;
+// One DPP lane permutation of a binary64 value (both halves moved the same way).
+template <int Ctrl>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const uint2 u = __builtin_bit_cast(uint2, x);
+    uint2 r;
+    r.x = uint32_t(__builtin_amdgcn_update_dpp(0, int(u.x), Ctrl, 0xF, 0xF, false));
+    r.y = uint32_t(__builtin_amdgcn_update_dpp(0, int(u.y), Ctrl, 0xF, 0xF, false));
+    return __builtin_bit_cast(double, r);
+}
+
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+    const uint2 u = __builtin_bit_cast(uint2, x);
+    uint2 r;
+    r.x = uint32_t(__builtin_amdgcn_readlane(int(u.x), l));
+    r.y = uint32_t(__builtin_amdgcn_readlane(int(u.y), l));
+    return __builtin_bit_cast(double, r);
+}
+
+// Sum over a full wave, returned to every lane.  Within each 16-lane row: pair lanes
+// i^1, i^2, then mirror halves of 8 and of 16 (each step adds a value and its partner,
+// so both end equal: a + b == b + a exactly); then the four row sums are combined in
+// a fixed order.  No LDS traffic.
+__device__ __forceinline__ double wave_total(double x) {
+    x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4E>(x);    // quad_perm [2,3,0,1]
+    x += dpp_f64<0x141>(x);   // row_half_mirror
+    x += dpp_f64<0x140>(x);   // row_mirror
+    return (readlane_f64(x, 0) + readlane_f64(x, 16)) + (readlane_f64(x, 32) + readlane_f64(x, 48));
 }
 
 __device__ __forceinline__ int64_t uniform64(int64_t x) {
@@ -78,18 +100,20 @@ __device__ __forceinline__ int seg_avail(int64_t sbase, int64_t o1, int64_t n_ev
 }
 
 // Occurrence filter in LDS (layout: bits | rel16 | base32, see bitmap_*_offset):
-// index among flagged events of flagged event e.
+// index among flagged events of flagged event e = rank of its superblock + rank of
+// its 128-event block within the superblock + set bits before it in the block.
+// Branch-free: the block's four words are read at once and selected arithmetically.
 __device__ __forceinline__ uint32_t bitmap_rank(const uint32_t *tab, int32_t nblk, uint32_t e) {
-    const uint32_t blk = e >> 7, q = (e >> 5) & 3u, bit = e & 31u;
+    const uint32_t blk = e >> 7, q = (e >> 5) & 3u;
     const u32x4 W = reinterpret_cast<const u32x4 *>(tab)[blk];
     const uint16_t *lrel = reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(tab) + bitmap_rel_offset(nblk));
     const uint32_t *lbase = reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + bitmap_base_offset(nblk));
-    const uint32_t word = q == 0 ? W.x : (q == 1 ? W.y : (q == 2 ? W.z : W.w));
-    uint32_t idx = lbase[e >> 15] + uint32_t(lrel[blk]) + __popc(word & ((1u << bit) - 1u));
-    idx += q > 0 ? __popc(W.x) : 0u;
-    idx += q > 1 ? __popc(W.y) : 0u;
-    idx += q > 2 ? __popc(W.z) : 0u;
-    return idx;
+    const bool q1 = (q & 1u) != 0u, q2 = (q & 2u) != 0u;
+    const uint32_t word = q2 ? (q1 ? W.w : W.z) : (q1 ? W.y : W.x);
+    const uint32_t c0 = __popc(W.x), c1 = c0 + __popc(W.y), c2 = c1 + __popc(W.z);
+    const uint32_t before = q2 ? (q1 ? c2 : c1) : (q1 ? c0 : 0u);   // set bits in the block's earlier words
+    const uint32_t below = __popc(word & ((1u << (e & 31u)) - 1u));  // set bits below e in its word
+    return lbase[e >> 15] + uint32_t(lrel[blk]) + before + below;
 }
 
 // Copy the layer's occurrence filter into LDS (whole workgroup; ends with a barrier).
