@@ -44,12 +44,18 @@ struct SortWs {
     uint32_t *hist;     // [8][256]
     uint32_t *plan;     // plan[p]: keys before pass p are in b (1) or a (0), p = 0..8;
                         // plan[16 + p]: pass p is skipped
+    double *part;       // [kRiskGroup][kRiskMaxBlocks] partial sums of the top-k keys
 };
+
+constexpr int kRiskGroup = 16;        // return periods per launch
+constexpr int kRiskMaxBlocks = 1024;  // partial sums per return period
+constexpr int kRiskChunk = 8192;      // keys per partial sum, at least
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 size_t sort_workspace_bytes(int64_t n) {
-    return 2 * align256(size_t(n) * 8) + align256(size_t(sort_tiles(n)) * 256 * 4) + align256(8 * 256 * 4) + 256;
+    return 2 * align256(size_t(n) * 8) + align256(size_t(sort_tiles(n)) * 256 * 4) + align256(8 * 256 * 4) + 256 +
+           size_t(kRiskGroup) * kRiskMaxBlocks * 8;
 }
 
 static SortWs sort_ws(void *ws, int64_t n) {
@@ -62,6 +68,7 @@ static SortWs sort_ws(void *ws, int64_t n) {
     w.counts = reinterpret_cast<uint32_t *>(p + 2 * keys);
     w.hist = reinterpret_cast<uint32_t *>(p + 2 * keys + counts);
     w.plan = reinterpret_cast<uint32_t *>(p + 2 * keys + counts + align256(8 * 256 * 4));
+    w.part = reinterpret_cast<double *>(p + 2 * keys + counts + align256(8 * 256 * 4) + 256);
     return w;
 }
 
@@ -75,16 +82,33 @@ __global__ __launch_bounds__(256) void k_sort_init(uint32_t *hist, uint32_t *pla
 }
 
 // Encode values into descending-order keys and count the digits of all 8 passes.
+// Lanes that share the wave's first lane's digit add their count once (year losses
+// often repeat one value, e.g. an aggregate limit); the others add their own.
 __global__ __launch_bounds__(256) void k_sort_encode(const double *__restrict__ in, int64_t n,
                                                      uint64_t *__restrict__ keys, uint32_t *__restrict__ hist) {
     __shared__ uint32_t h[8][256];
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
     __syncthreads();
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
-        const uint64_t k = desc_key(in[i]);
-        keys[i] = k;
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    // every lane of a wave runs the same number of iterations (ballots need the whole wave)
+    const int64_t start = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63);
+    for (int64_t i0 = start; i0 < n; i0 += stride) {
+        const int64_t i = i0 + lane;
+        const bool valid = i < n;
+        uint64_t k = 0;
+        if (valid) {
+            k = desc_key(in[i]);
+            keys[i] = k;
+        }
 #pragma unroll
-        for (int p = 0; p < 8; ++p) atomicAdd(&h[p][uint32_t(k >> (8 * p)) & 255u], 1u);
+        for (int p = 0; p < 8; ++p) {
+            const uint32_t d = uint32_t(k >> (8 * p)) & 255u;
+            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);   // lane 0 is always valid
+            const uint64_t same = __builtin_amdgcn_ballot_w64(valid && d == d0);
+            if (valid && d != d0) atomicAdd(&h[p][d], 1u);
+            if (lane == 0) atomicAdd(&h[p][d0], uint32_t(__popcll(same)));
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) {
@@ -95,16 +119,19 @@ __global__ __launch_bounds__(256) void k_sort_encode(const double *__restrict__ 
 
 // Pass p leaves the order unchanged when one digit value holds all n keys; then
 // its kernels do nothing and the keys stay in the same buffer.
-__global__ void k_sort_plan(const uint32_t *__restrict__ hist, int64_t n, uint32_t *__restrict__ plan) {
+__global__ __launch_bounds__(256) void k_sort_plan(const uint32_t *__restrict__ hist, int64_t n, uint32_t *__restrict__ plan) {
+    __shared__ uint32_t triv[kPasses];
+    if (threadIdx.x < kPasses) triv[threadIdx.x] = 0;
+    __syncthreads();
+    for (int p = 0; p < kPasses; ++p)
+        if (int64_t(hist[p * 256 + threadIdx.x]) == n) triv[p] = 1;   // at most one digit per pass
+    __syncthreads();
     if (threadIdx.x != 0) return;
     uint32_t sel = 0;
     plan[0] = 0;
     for (int p = 0; p < kPasses; ++p) {
-        uint32_t triv = 0;
-        for (int d = 0; d < 256; ++d)
-            if (int64_t(hist[p * 256 + d]) == n) triv = 1;
-        plan[16 + p] = triv;
-        sel = triv ? sel : 1u - sel;
+        plan[16 + p] = triv[p];
+        sel = triv[p] ? sel : 1u - sel;
         plan[p + 1] = sel;
     }
 }
@@ -234,7 +261,7 @@ hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStrea
     const unsigned eb = unsigned(std::min<int64_t>((n + 255) / 256, 256));
     hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, s, w.hist, w.plan);
     hipLaunchKernelGGL(k_sort_encode, dim3(eb), dim3(256), 0, s, in, n, w.a, w.hist);
-    hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(64), 0, s, w.hist, n, w.plan);
+    hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(256), 0, s, w.hist, n, w.plan);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     for (int pass = 0; pass < kPasses; ++pass) {
@@ -255,38 +282,68 @@ hipError_t launch_sort_decode(const void *ws, int64_t n, double *out, hipStream_
     return hipGetLastError();
 }
 
-// One workgroup per return period: PML = k-th largest, TVaR = mean of the k largest,
-// summed with a fixed per-thread stride and a fixed LDS tree (deterministic).
+// PML = the k-th largest, TVaR = the mean of the k largest.  The top k keys are
+// summed in fixed chunks (one workgroup each, fixed stride and LDS tree), then the
+// chunk sums in chunk order: the result does not depend on scheduling.
 struct RiskKs {
-    int64_t k[16];
+    int64_t k[kRiskGroup];
+    int64_t chunk[kRiskGroup];
 };
 
-__global__ __launch_bounds__(1024) void k_risk(SortWs w, RiskKs ks, int n_k, double *__restrict__ out) {
-    __shared__ double part[1024];
-    const uint64_t *keys = cur_keys(w, kPasses);
-    const int64_t k = ks.k[blockIdx.x];
-    double s = 0.0;
-    for (int64_t i = threadIdx.x; i < k; i += 1024) s += key_value(keys[i]);
+__device__ __forceinline__ double block_sum(double s, double *part) {
     part[threadIdx.x] = s;
     __syncthreads();
-    for (int o = 512; o >= 1; o >>= 1) {
-        if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    for (int o = blockDim.x / 2; o >= 1; o >>= 1) {
+        if (int(threadIdx.x) < o) part[threadIdx.x] += part[threadIdx.x + o];
         __syncthreads();
     }
+    return part[0];
+}
+
+__global__ __launch_bounds__(256) void k_risk_part(SortWs w, RiskKs ks) {
+    __shared__ double part[256];
+    const uint64_t *keys = cur_keys(w, kPasses);
+    const int r = blockIdx.y;
+    const int64_t k = ks.k[r], chunk = ks.chunk[r];
+    const int64_t lo = int64_t(blockIdx.x) * chunk;
+    const int64_t hi = lo + chunk < k ? lo + chunk : k;
+    double s = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += key_value(keys[i]);
+    s = block_sum(s, part);
+    if (threadIdx.x == 0) w.part[r * kRiskMaxBlocks + blockIdx.x] = s;   // 0 past k
+}
+
+__global__ __launch_bounds__(256) void k_risk_final(SortWs w, RiskKs ks, int n_k, int nb, double *__restrict__ out) {
+    __shared__ double part[256];
+    const uint64_t *keys = cur_keys(w, kPasses);
+    const int r = blockIdx.x;
+    const int64_t k = ks.k[r];
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += w.part[r * kRiskMaxBlocks + b];
+    s = block_sum(s, part);
     if (threadIdx.x == 0) {
-        out[blockIdx.x] = key_value(keys[k - 1]);
-        out[n_k + blockIdx.x] = part[0] / double(k);
+        out[r] = key_value(keys[k - 1]);
+        out[n_k + r] = s / double(k);
     }
 }
 
 hipError_t launch_risk(const void *ws, int64_t n, const int64_t *ks, int n_k, double *out, hipStream_t s) {
     SortWs w = sort_ws(const_cast<void *>(ws), n);
-    for (int base = 0; base < n_k; base += 16) {
+    for (int base = 0; base < n_k; base += kRiskGroup) {
         RiskKs r{};
-        const int m = std::min(16, n_k - base);
-        for (int i = 0; i < m; ++i) r.k[i] = ks[base + i];
+        const int m = std::min(kRiskGroup, n_k - base);
+        int64_t nb = 1;
+        for (int i = 0; i < m; ++i) {
+            const int64_t k = ks[base + i];
+            int64_t chunk = (k + kRiskMaxBlocks - 1) / kRiskMaxBlocks;
+            chunk = chunk < kRiskChunk ? kRiskChunk : chunk;
+            r.k[i] = k;
+            r.chunk[i] = chunk;
+            nb = std::max(nb, (k + chunk - 1) / chunk);
+        }
         // out layout per group: pml[m], tvar[m]
-        hipLaunchKernelGGL(k_risk, dim3(unsigned(m)), dim3(1024), 0, s, w, r, m, out + 2 * base);
+        hipLaunchKernelGGL(k_risk_part, dim3(unsigned(nb), unsigned(m)), dim3(256), 0, s, w, r);
+        hipLaunchKernelGGL(k_risk_final, dim3(unsigned(m)), dim3(256), 0, s, w, r, m, int(nb), out + 2 * base);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

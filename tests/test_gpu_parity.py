@@ -331,6 +331,29 @@ def test_sort_bit_exact(A, gpu_ctx, n):
     assert got.tobytes() == want.tobytes()
 
 
+@pytest.mark.parametrize("n,kind", [(300_001, "mixed"), (1_000_000, "constant"), (70_000, "mixed")])
+def test_risk_measures_large_k(A, gpu_ctx, n, kind):
+    """PML/TVaR with k up to n (chunked top-k sums): ranks identical, PML bit-exact,
+    TVaR within the summation bound of a k-term sum of non-negative values."""
+    import torch
+    _say(f"risk large k n={n} kind={kind}")
+    rng = np.random.default_rng(n + 17)
+    if kind == "constant":
+        y = np.full(n, 5e7)
+    else:
+        y = rng.lognormal(12, 2, size=n)
+        y[rng.random(n) < 0.3] = 0.0
+        y[rng.random(n) < 0.05] = 5e7
+    rps = [1.0, 1.5, 2.0, 10.0, 100.0, float(n), 2.0 * n]
+    pml_o, tvar_o, ranks_o, _ = oracle.risk(y, rps)
+    pml, tvar = A.ara_risk_measures(gpu_ctx, torch.from_numpy(y).cuda(), rps)
+    assert [A.ara_return_period_rank(n, rp) for rp in rps] == list(ranks_o)
+    assert np.asarray(pml).tobytes() == np.asarray(pml_o).tobytes()
+    k = np.asarray(ranks_o, dtype=np.float64)
+    bound = 2.0 * k * 2.0 ** -53 * np.asarray(tvar_o) + 1e-300
+    assert np.all(np.abs(np.asarray(tvar) - tvar_o) <= bound), (tvar, tvar_o)
+
+
 # ----------------------------------------------------------------------------- errors
 def test_input_errors(A, S, gpu_ctx):
     import torch
