@@ -74,7 +74,7 @@ def recorded_traffic(args):
     """HBM bytes per launch of the headline trial kernel from the committed counter
     summary, if it was taken on this workload with the current kernel sources."""
     if not (args.workload == "paper" and args.trials == 1_000_000 and args.precision == "f64"
-            and args.placement in (0, 1) and not args.block and not args.grid_per_cu):
+            and args.placement in (0, 1) and not args.block and not args.grid_per_cu and not args.no_packing):
         return None, "no counter summary for this configuration"
     if not os.path.exists(TRAFFIC_FILE):
         return None, "no counter summary recorded"
@@ -196,6 +196,7 @@ def main():
     ap.add_argument("--placement", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid-per-cu", type=int, default=0)
+    ap.add_argument("--no-packing", action="store_true", help="stream int32 IDs instead of the packed YET copy")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle sample time (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
@@ -238,6 +239,7 @@ def main():
     ara.ara_set_option(ctx, ara.ARA_OPT_PLACEMENT, args.placement)
     ara.ara_set_option(ctx, ara.ARA_OPT_BLOCK_THREADS, args.block)
     ara.ara_set_option(ctx, ara.ARA_OPT_GRID_PER_CU, args.grid_per_cu)
+    ara.ara_set_option(ctx, ara.ARA_OPT_YET_PACKING, 0 if args.no_packing else 1)
     prec = ara.ARA_F32 if args.precision == "f32" else ara.ARA_F64
     t = time.time()
     an = session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
@@ -245,6 +247,7 @@ def main():
     torch.cuda.synchronize()
     log(f"uploaded + validated in {time.time() - t:.1f}s")
     n_flagged, placement, lds_bytes = ara.ara_layer_stats(ctx, an.layer)
+    id_bytes = ara.ara_yet_info(an.yet)[2]
     log(f"placement={ara.PLACEMENT_NAMES.get(placement, placement)} lds={lds_bytes} flagged={n_flagged}")
 
     ylt = torch.empty(w.n_trials, dtype=torch.float64, device="cuda")
@@ -279,7 +282,10 @@ def main():
         f"(min {min(kern_ms):.4f}, max {max(kern_ms):.4f}); PML {pml.tolist()} TVaR {tvar.tolist()}")
 
     nblk = (w.catalog_size + 127) // 128
+    # algorithmic bytes are defined on int32 event IDs; the kernel may stream the
+    # YET's packed 3-byte copy, reported beside them as moved_bytes
     alg_bytes = 4 * w.n_events + 8 * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * n_flagged
+    moved_bytes = alg_bytes - (4 - id_bytes) * w.n_events
     achieved = alg_bytes / (k_avg * 1e-3) / 1e9
     te = float(w.n_events)   # trial-events x layers (1 layer)
     value = te / (ms_step * 1e-3)
@@ -316,7 +322,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": TRIAL_KERNEL if placement == ara.ARA_PLACE_LDS_BITMAP else "k_trial_ylt",
-                     "kernel_ms": k_avg, "algorithmic_bytes": alg_bytes, "traffic_source": traffic_note},
+                     "kernel_ms": k_avg, "algorithmic_bytes": alg_bytes, "yet_id_bytes": id_bytes,
+                     "moved_bytes": moved_bytes, "traffic_source": traffic_note},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

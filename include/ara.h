@@ -96,7 +96,9 @@ typedef enum ara_placement {
 typedef enum ara_option {
     ARA_OPT_PLACEMENT = 1,      /* an ara_placement value                                            */
     ARA_OPT_BLOCK_THREADS = 2,  /* threads per workgroup of the trial kernel: 256, 512 or 1024       */
-    ARA_OPT_GRID_PER_CU = 3     /* workgroups per compute unit of the trial kernel (1..64; 0 = auto)  */
+    ARA_OPT_GRID_PER_CU = 3,    /* workgroups per compute unit of the trial kernel (1..64; 0 = auto)  */
+    ARA_OPT_YET_PACKING = 4     /* 1 (default): YETs created later also keep a packed copy of their
+                                   event IDs when catalog_size <= 2^24; 0: never                      */
 } ara_option;
 
 typedef struct ara_ctx ara_ctx;
@@ -157,11 +159,20 @@ ara_status ara_sync(ara_ctx *ctx);
  *   mem            ARA_MEM_DEVICE: both arrays are borrowed device pointers;
  *                  ARA_MEM_HOST: both are copied to the device.
  * Blocking: every ID and offset is checked on the device before returning.
+ * Packed copy: when catalog_size <= 2^24 (and ARA_OPT_YET_PACKING is 1), the library
+ * also stores the checked IDs in 3 bytes each (event i at bytes 3i..3i+2, little
+ * endian, in 12-byte groups of 4 events), owned by the handle; the YLT kernels then
+ * stream that copy (3 instead of 4 bytes per occurrence).  Borrowed arrays must not
+ * change while the handle lives: later analyses may read either form.
  * Errors: ARA_E_INVALID_ARG, ARA_E_EVENT_ID_RANGE, ARA_E_BAD_OFFSETS, ARA_E_OOM, ARA_E_DEVICE. */
 ara_status ara_yet_create(ara_ctx *ctx, const int32_t *event_ids, int64_t n_events,
                           const int64_t *trial_offsets, int64_t n_trials, int32_t catalog_size,
                           ara_mem mem, ara_yet **out);
 ara_status ara_yet_release(ara_yet *yet);
+
+/* Sizes of a YET handle and the bytes per event ID of the form the YLT kernels read
+ * (4, or 3 with a packed copy).  Any output pointer may be NULL. */
+ara_status ara_yet_info(const ara_yet *yet, int64_t *n_events, int64_t *n_trials, int32_t *id_bytes);
 
 /* ---------------------------------------------------------------- Event Loss Table
  * Creates an ELT handle (Section II-A item 2) and builds its direct access table

@@ -56,6 +56,7 @@ ARA_PLACE_GLOBAL_DENSE = 3
 ARA_OPT_PLACEMENT = 1
 ARA_OPT_BLOCK_THREADS = 2
 ARA_OPT_GRID_PER_CU = 3
+ARA_OPT_YET_PACKING = 4
 
 ARA_BUILD_TABLES = 1
 
@@ -91,6 +92,7 @@ _SIGS = {
     "ara_sync": (_ST, [_P]),
     "ara_yet_create": (_ST, [_P, _P, _I64, _P, _I64, _I32, ctypes.c_int, ctypes.POINTER(_P)]),
     "ara_yet_release": (_ST, [_P]),
+    "ara_yet_info": (_ST, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
     "ara_elt_create": (_ST, [_P, _P, _P, _I64, _I32, ctypes.POINTER(ara_elt_terms), ctypes.c_int, ctypes.c_int,
                              ctypes.POINTER(_P)]),
     "ara_elt_release": (_ST, [_P]),
@@ -238,6 +240,14 @@ def ara_yet_create(ctx: Ctx, event_ids, trial_offsets, catalog_size: int) -> Yet
 def ara_yet_release(y: Yet):
     _check(_lib.ara_yet_release(y.ptr), y.ctx, "ara_yet_release")
     y.ptr, y._keep = None, None
+
+
+def ara_yet_info(y: Yet):
+    """(n_events, n_trials, id_bytes): id_bytes is 3 when the YLT kernels read the
+    handle's packed copy of the event IDs, else 4."""
+    ne, nt, b = _I64(), _I64(), _I32()
+    _check(_lib.ara_yet_info(y.ptr, ctypes.byref(ne), ctypes.byref(nt), ctypes.byref(b)), y.ctx, "ara_yet_info")
+    return int(ne.value), int(nt.value), int(b.value)
 
 
 def ara_elt_create(ctx: Ctx, event_ids, losses, catalog_size: int, terms: Optional[Sequence[float]] = None,

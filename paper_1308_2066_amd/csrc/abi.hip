@@ -24,6 +24,7 @@ struct ara_ctx {
     int placement = ARA_PLACE_AUTO;
     int block_threads = 0;           // 0 = automatic
     int grid_per_cu = 0;             // 0 = automatic
+    int yet_packing = 1;             // keep a packed copy of YET IDs where they fit 24 bits
     int live = 0;                    // handles alive on this context
     std::string msg;
 };
@@ -35,6 +36,7 @@ struct ara_yet {
     int64_t n_events, n_trials;
     int32_t catalog;
     bool owns;
+    uint8_t *ids24;    // packed copy (owned), or null
 };
 
 struct ara_elt {
@@ -66,6 +68,7 @@ struct ara_layer {
 static constexpr size_t kStageDoubles = 512;   // 2 x 256 return periods
 static constexpr int32_t kMaxCatalog = 1 << 28; // byte offsets into catalog tables stay below 2^31
 static constexpr int32_t kMaxElts = 65535;      // ELT index is a grid dimension of the table builds
+static constexpr int32_t kMaxPackedCatalog = 1 << 24;   // IDs of a packed YET copy take 3 bytes
 
 // ------------------------------------------------------------------ helpers
 // Message of the last error that had no context to hold it (ara_ctx_create).
@@ -323,6 +326,10 @@ extern "C" ara_status ara_set_option(ara_ctx *c, int option, int64_t v) {
         if (v < 0 || v > 64) return fail(c, ARA_E_INVALID_ARG, "bad workgroups per CU %lld", (long long)v);
         c->grid_per_cu = int(v);
         return ARA_OK;
+    case ARA_OPT_YET_PACKING:
+        if (v != 0 && v != 1) return fail(c, ARA_E_INVALID_ARG, "bad packing flag %lld", (long long)v);
+        c->yet_packing = int(v);
+        return ARA_OK;
     default:
         return fail(c, ARA_E_INVALID_ARG, "unknown option %d", option);
     }
@@ -347,7 +354,7 @@ extern "C" ara_status ara_yet_create(ara_ctx *c, const int32_t *ids, int64_t n_e
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     ara_yet *y = new (std::nothrow) ara_yet();
     if (!y) return ARA_E_OOM;
-    *y = ara_yet{c, ids, offs, n_events, n_trials, catalog, mem == ARA_MEM_HOST};
+    *y = ara_yet{c, ids, offs, n_events, n_trials, catalog, mem == ARA_MEM_HOST, nullptr};
     if (y->owns) {
         int32_t *di = nullptr;
         int64_t *doff = nullptr;
@@ -371,11 +378,19 @@ extern "C" ara_status ara_yet_create(ara_ctx *c, const int32_t *ids, int64_t n_e
     }
     hipError_t e = launch_validate_yet(y->ids, n_events, y->offs, n_trials, catalog, c->d_err, c->stream);
     ara_status s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "validate yet");
+    if (s == ARA_OK && c->yet_packing && n_events > 0 && catalog <= kMaxPackedCatalog) {
+        s = dev_alloc(c, &y->ids24, yet_packed_bytes(n_events), "packed yet ids");
+        if (s == ARA_OK) {
+            e = launch_yet_pack(y->ids, n_events, y->ids24, c->stream);
+            s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "pack yet");
+        }
+    }
     if (s != ARA_OK) {
         if (y->owns) {
             dev_free(const_cast<int32_t *>(y->ids));
             dev_free(const_cast<int64_t *>(y->offs));
         }
+        dev_free(y->ids24);
         delete y;
         return s;
     }
@@ -392,8 +407,17 @@ extern "C" ara_status ara_yet_release(ara_yet *y) {
         dev_free(const_cast<int32_t *>(y->ids));
         dev_free(const_cast<int64_t *>(y->offs));
     }
+    dev_free(y->ids24);
     y->ctx->live--;
     delete y;
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_yet_info(const ara_yet *y, int64_t *n_events, int64_t *n_trials, int32_t *id_bytes) {
+    if (!y) return ARA_E_INVALID_ARG;
+    if (n_events) *n_events = y->n_events;
+    if (n_trials) *n_trials = y->n_trials;
+    if (id_bytes) *id_bytes = y->ids24 ? 3 : 4;
     return ARA_OK;
 }
 
@@ -618,6 +642,7 @@ static TrialArgs trial_args(const ara_yet *y, const ara_layer *L, int64_t t0, in
     TrialArgs a{};
     if (y) {
         a.ids = y->ids;
+        a.ids24 = y->ids24;
         a.n_events = y->n_events;
         a.offs = y->offs;
     }

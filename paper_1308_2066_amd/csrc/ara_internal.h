@@ -68,6 +68,7 @@ __host__ __device__ inline size_t bitmap_table_bytes(int32_t nblk) { return bitm
 // Arguments of the trial kernels.
 struct TrialArgs {
     const int32_t *ids;
+    const uint8_t *ids24;    // packed copy of ids (3 bytes each), or null
     int64_t n_events;
     const int64_t *offs;
     int64_t t_begin, t_end;
@@ -91,6 +92,8 @@ struct TrialArgs {
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_validate_yet(const int32_t *ids, int64_t n_events, const int64_t *offs, int64_t n_trials,
                                int32_t catalog, uint32_t *err, hipStream_t s);
+size_t yet_packed_bytes(int64_t n_events);
+hipError_t launch_yet_pack(const int32_t *ids, int64_t n_events, uint8_t *packed, hipStream_t s);
 hipError_t launch_elt_clear(const EltDesc *d, int n_elts, int32_t catalog, hipStream_t s);
 hipError_t launch_elt_scatter(const EltDesc *d, int n_elts, int64_t max_pairs, int32_t catalog, uint32_t *err,
                               hipStream_t s);

@@ -53,6 +53,32 @@ hipError_t launch_validate_yet(const int32_t *ids, int64_t n_events, const int64
     return hipGetLastError();
 }
 
+// Packed copy of checked event IDs (all < 2^24): 4 IDs per 12-byte group, event i at
+// bytes 3i..3i+2 little endian; the last group is zero-padded.
+size_t yet_packed_bytes(int64_t n_events) { return size_t((n_events + 3) / 4) * 12; }
+
+__global__ void k_yet_pack(const int32_t *__restrict__ ids, int64_t n_events, uint32_t *__restrict__ out) {
+    const int64_t groups = (n_events + 3) / 4;
+    for (int64_t g = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; g < groups; g += int64_t(gridDim.x) * blockDim.x) {
+        uint32_t v[4];
+        if (4 * g + 4 <= n_events) {
+            const i32x4 x = __builtin_nontemporal_load(reinterpret_cast<const i32x4 *>(ids) + g);
+            v[0] = uint32_t(x.x), v[1] = uint32_t(x.y), v[2] = uint32_t(x.z), v[3] = uint32_t(x.w);
+        } else {
+            for (int j = 0; j < 4; ++j) v[j] = 4 * g + j < n_events ? uint32_t(ids[4 * g + j]) : 0u;
+        }
+        out[3 * g + 0] = v[0] | (v[1] << 24);
+        out[3 * g + 1] = (v[1] >> 8) | (v[2] << 16);
+        out[3 * g + 2] = (v[2] >> 16) | (v[3] << 8);
+    }
+}
+
+hipError_t launch_yet_pack(const int32_t *ids, int64_t n_events, uint8_t *packed, hipStream_t s) {
+    if (n_events <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_yet_pack, dim3(4096), dim3(256), 0, s, ids, n_events, reinterpret_cast<uint32_t *>(packed));
+    return hipGetLastError();
+}
+
 // Zero each ELT's direct access table and its duplicate-detection bits.
 // grid.y = ELT index.
 __global__ void k_elt_clear(const EltDesc *__restrict__ d, int32_t catalog) {

@@ -6,8 +6,9 @@
 // cumulative sum is non-decreasing and the aggregate clamp is non-decreasing with
 // value 0 at 0, so the differences telescope.
 //
-// A wave walks its trials in segments of 1024 events (four 16-byte non-temporal
-// loads per lane).  Per segment:
+// A wave walks its trials in segments of 1024 events (four non-temporal loads per
+// lane: 16 bytes of int32 IDs, or 12 bytes of the YET's packed 3-byte copy, which
+// cuts the dominant stream by a quarter).  Per segment:
 //   filter  each lane tests the LDS bit of its 16 events (one LDS read each, all
 //           issued together); only events whose occurrence-net loss is nonzero pass;
 //   queue   passing events are appended to the wave's LDS queue in slot-then-lane
@@ -80,9 +81,19 @@ __device__ __forceinline__ BCur bcur_next(const TrialArgs &a, const BCur &c, uin
     return bcur_open(a, c.t + stride, n, bad);
 }
 
-__device__ __forceinline__ void bcur_load(const TrialArgs &a, const BCur &c, uint32_t n, int lane, u32x4 (&r)[kNch]) {
+// Event IDs of one segment in registers: int32 (four 16-byte loads per lane) or the
+// packed copy (four 12-byte loads per lane).
+template <bool P24> struct IdRegs;
+template <> struct IdRegs<false> { u32x4 r[kNch]; };
+template <> struct IdRegs<true> { u32x3 r[kNch]; };
+
+template <bool P24>
+__device__ __forceinline__ void bcur_load(const TrialArgs &a, const BCur &c, uint32_t n, int lane, IdRegs<P24> &g) {
     const bool live = c.t < n;
-    load_ids(a.ids, live ? c.sbase : 0, live ? seg_avail(c.sbase, c.o1, a.n_events) : 0, lane, r);
+    if constexpr (P24)
+        load_ids24(a.ids24, live ? c.sbase : 0, live ? seg_avail24(c.sbase, c.o1) : 0, lane, g.r);
+    else
+        load_ids(a.ids, live ? c.sbase : 0, live ? seg_avail(c.sbase, c.o1, a.n_events) : 0, lane, g.r);
 }
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t vals_rsrc(const TrialArgs &a) {
@@ -109,19 +120,27 @@ __device__ __forceinline__ void drain_queue(const TrialArgs &a, const uint32_t *
 // lane holds the event at position k*256 + 4*lane + j (s = 4k + j) of the segment;
 // it counts if that position lies in [lo, hi) and the event's filter bit is set.
 // lo < 4, so only lane 0 of the first load can hold events before the trial.
+// The int32 IDs are range-checked here (mx); the packed copy was checked when built.
+template <bool P24>
 __device__ __forceinline__ uint32_t seg_queue(const TrialArgs &a, const uint32_t *tab, uint32_t *q,
-                                              const u32x4 (&r)[kNch], int lane, int lo, int hi, uint32_t &mx,
+                                              const IdRegs<P24> &g, int lane, int lo, int hi, uint32_t &mx,
                                               double &dacc) {
     const uint32_t cmax = uint32_t(a.catalog) - 1u;
-    uint32_t e[kSlots], w[kSlots];
+    uint32_t id[kSlots], e[kSlots], w[kSlots];
 #pragma unroll
-    for (int s = 0; s < kSlots; s += 2) {
-        const uint32_t i0 = r[s >> 2][s & 3], i1 = r[s >> 2][(s & 3) + 1];
-        mx = max(mx, max(i0, i1));
-        e[s] = min(i0, cmax);
-        e[s + 1] = min(i1, cmax);
+    for (int k = 0; k < kNch; ++k) {
+        if constexpr (P24) {
+            unpack_ids24(g.r[k], id + 4 * k);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) id[4 * k + j] = g.r[k][j];
+            mx = max(mx, max(max(id[4 * k], id[4 * k + 1]), max(id[4 * k + 2], id[4 * k + 3])));
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        e[s] = min(id[s], cmax);
         w[s] = tab[e[s] >> 5];
-        w[s + 1] = tab[e[s + 1] >> 5];
     }
     const int l4 = lane * 4;
     bool f[kSlots];
@@ -186,7 +205,8 @@ struct Pending {
     double dacc;     // its values already resolved on the overflow path
 };
 
-__device__ __forceinline__ void issue(const TrialArgs &a, const uint32_t *tab, uint32_t *q, u32x4 (&r)[kNch],
+template <bool P24>
+__device__ __forceinline__ void issue(const TrialArgs &a, const uint32_t *tab, uint32_t *q, IdRegs<P24> &r,
                                       const BCur &cur, const BCur &nxt, uint32_t n, int lane, uint32_t &mx,
                                       double (&v)[kRows], Pending &p) {
     const int64_t h = cur.o1 - cur.sbase;
@@ -194,11 +214,11 @@ __device__ __forceinline__ void issue(const TrialArgs &a, const uint32_t *tab, u
     p.t = cur.t;
     p.last = bcur_last(cur) ? 1u : 0u;
     p.dacc = 0.0;
-    const uint32_t qn = seg_queue(a, tab, q, r, lane, int(cur.lo), hi, mx, p.dacc);
+    const uint32_t qn = seg_queue<P24>(a, tab, q, r, lane, int(cur.lo), hi, mx, p.dacc);
     seg_rows(a, tab, q, qn, lane, v);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
-    bcur_load(a, nxt, n, lane, r);
+    bcur_load<P24>(a, nxt, n, lane, r);
     asm volatile("" ::: "memory");
     __builtin_amdgcn_sched_barrier(0);
 }
@@ -217,6 +237,7 @@ __device__ __forceinline__ void retire(const TrialArgs &a, const Pending &p, con
     }
 }
 
+template <bool P24>
 __global__ __launch_bounds__(1024) void k_trial_ylt_bitmap(TrialArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t tab[kTabWords];
     __shared__ __attribute__((aligned(16))) uint32_t queues[kQueueWords];
@@ -232,9 +253,9 @@ __global__ __launch_bounds__(1024) void k_trial_ylt_bitmap(TrialArgs a) {
 
     BCur c0 = bcur_open(a, blockIdx.x * wpb + wave, n, bad);
     BCur c1 = bcur_next(a, c0, stride, n, bad);
-    u32x4 A[kNch], B[kNch];
-    bcur_load(a, c0, n, lane, A);
-    bcur_load(a, c1, n, lane, B);
+    IdRegs<P24> A, B;
+    bcur_load<P24>(a, c0, n, lane, A);
+    bcur_load<P24>(a, c1, n, lane, B);
 
     double vA[kRows], vB[kRows];
     Pending pA, pB;
@@ -250,14 +271,14 @@ __global__ __launch_bounds__(1024) void k_trial_ylt_bitmap(TrialArgs a) {
         pB.t = __builtin_amdgcn_readfirstlane(pB.t);
         pB.last = __builtin_amdgcn_readfirstlane(pB.last);
         const BCur c2 = bcur_next(a, c1, stride, n, bad);
-        issue(a, tab, q, A, c0, c2, n, lane, mx, vA, pA);
+        issue<P24>(a, tab, q, A, c0, c2, n, lane, mx, vA, pA);
         retire(a, pB, vB, n, lane, acc);
         if (c1.t >= n) {
             retire(a, pA, vA, n, lane, acc);
             break;
         }
         const BCur c3 = bcur_next(a, c2, stride, n, bad);
-        issue(a, tab, q, B, c1, c3, n, lane, mx, vB, pB);
+        issue<P24>(a, tab, q, B, c1, c3, n, lane, mx, vB, pB);
         retire(a, pA, vA, n, lane, acc);
         if (c2.t >= n) {
             retire(a, pB, vB, n, lane, acc);
@@ -273,7 +294,10 @@ __global__ __launch_bounds__(1024) void k_trial_ylt_bitmap(TrialArgs a) {
 size_t trial_bitmap_table_capacity() { return size_t(kTabWords) * 4; }
 
 hipError_t launch_trial_ylt_bitmap(const TrialArgs &a, int grid, int block, hipStream_t s) {
-    hipLaunchKernelGGL(k_trial_ylt_bitmap, dim3(grid), dim3(block), 0, s, a);
+    if (a.ids24)
+        hipLaunchKernelGGL(k_trial_ylt_bitmap<true>, dim3(grid), dim3(block), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_trial_ylt_bitmap<false>, dim3(grid), dim3(block), 0, s, a);
     return hipGetLastError();
 }
 

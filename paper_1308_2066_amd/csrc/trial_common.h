@@ -6,6 +6,7 @@
 namespace ara {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
 
 constexpr int kChunk = 256;               // events per wave-wide 16-byte load (64 lanes x 4)
 constexpr int kNch = 4;                   // loads per segment
@@ -88,6 +89,30 @@ __device__ __forceinline__ void load_ids(const int32_t *ids, int64_t sbase, int 
             }
         }
     }
+}
+
+// Packed IDs (3 bytes each, 12-byte groups of 4 events, zero-padded to whole groups):
+// the same segment layout as load_ids, one 12-byte load per lane and chunk.  sbase
+// and avail are multiples of 4, so each group is wholly inside or outside the record.
+__device__ __forceinline__ void load_ids24(const uint8_t *ids24, int64_t sbase, int avail, int lane, u32x3 (&r)[kNch]) {
+    __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)(ids24 + 3 * sbase), 0, avail * 3, kBufWord3);
+#pragma unroll
+    for (int k = 0; k < kNch; ++k)
+        r[k] = __builtin_amdgcn_raw_buffer_load_b96(rs, k * kChunk * 3 + lane * 12, 0, kNonTemporal);
+}
+
+__device__ __forceinline__ void unpack_ids24(const u32x3 &w, uint32_t *id) {
+    id[0] = w.x & 0xFFFFFFu;
+    id[1] = (w.x >> 24) | ((w.y << 8) & 0xFFFF00u);
+    id[2] = (w.y >> 16) | ((w.z << 16) & 0xFF0000u);
+    id[3] = w.z >> 8;
+}
+
+// Packed form: readable events from sbase up to the trial's end rounded up to a
+// whole group (the padded buffer always holds it), at most one segment.
+__device__ __forceinline__ int seg_avail24(int64_t sbase, int64_t o1) {
+    const int64_t a = ((o1 + 3) & ~int64_t(3)) - sbase;
+    return int(a < 0 ? 0 : (a > kSeg ? kSeg : a));
 }
 
 // Events readable from sbase for a trial ending at o1: up to the trial's end

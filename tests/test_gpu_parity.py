@@ -50,14 +50,20 @@ def S():
     return session
 
 
-def analyze(A, S, ctx, w, placement=0, precision=0, t0=0, t1=None, terms=None, block=0, grid_per_cu=0):
+def analyze(A, S, ctx, w, placement=0, precision=0, t0=0, t1=None, terms=None, block=0, grid_per_cu=0,
+            packing=1):
     import torch
     A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, placement)
     A.ara_set_option(ctx, A.ARA_OPT_BLOCK_THREADS, block)
     A.ara_set_option(ctx, A.ARA_OPT_GRID_PER_CU, grid_per_cu)
-    an = S.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts,
-                         terms if terms is not None else w.layer_terms, w.elt_terms, precision)
+    A.ara_set_option(ctx, A.ARA_OPT_YET_PACKING, packing)
     try:
+        an = S.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts,
+                             terms if terms is not None else w.layer_terms, w.elt_terms, precision)
+    finally:
+        A.ara_set_option(ctx, A.ARA_OPT_YET_PACKING, 1)
+    try:
+        assert A.ara_yet_info(an.yet)[2] == (3 if packing and w.n_events > 0 and w.catalog_size <= 1 << 24 else 4)
         t1 = w.n_trials if t1 is None else t1
         ylt = torch.empty(max(t1 - t0, 1), dtype=torch.float64, device="cuda")
         A.ara_analyze(ctx, an.yet, an.layer, t0, t1, ylt)
@@ -186,6 +192,8 @@ def test_plain_small_ylt(A, S, gpu_ctx, small, placement):
     ref = oracle.analyze_workload(small, threads=oracle.max_threads())
     got = analyze(A, S, gpu_ctx, small, placement)
     assert_ylt_close(got, ref, what="plain small")
+    got32 = analyze(A, S, gpu_ctx, small, placement, packing=0)
+    assert got32.tobytes() == got.tobytes()   # same events, same summation order
 
 
 def _catalog_lookup_reference(w, precision_f32=False):
@@ -274,6 +282,7 @@ def test_edge_trial_lengths(A, S, gpu_ctx, placement):
     ref = oracle.analyze_workload(w, per_event=True)
     got = analyze(A, S, gpu_ctx, w, placement)
     assert_ylt_close(got, ref)
+    assert analyze(A, S, gpu_ctx, w, placement, packing=0).tobytes() == got.tobytes()
     ev = analyze_events(A, S, gpu_ctx, w, placement)
     assert np.array_equal(ev["gross"], ref["gross"]) and np.array_equal(ev["occ"], ref["occ"])
     # sub-ranges of trials
@@ -289,7 +298,8 @@ def test_single_trial_and_last_partial_group(A, S, gpu_ctx):
         _say(f"single trial n={n}")
         ref = oracle.analyze_workload(w)
         for pl in PLACEMENTS:
-            assert_ylt_close(analyze(A, S, gpu_ctx, w, pl), ref, what=f"n={n} pl={pl}")
+            for pk in (1, 0):
+                assert_ylt_close(analyze(A, S, gpu_ctx, w, pl, packing=pk), ref, what=f"n={n} pl={pl} pk={pk}")
 
 
 def test_many_short_trials_and_empty_layer(A, S, gpu_ctx):
@@ -352,6 +362,26 @@ def test_risk_measures_large_k(A, gpu_ctx, n, kind):
     k = np.asarray(ranks_o, dtype=np.float64)
     bound = 2.0 * k * 2.0 ** -53 * np.asarray(tvar_o) + 1e-300
     assert np.all(np.abs(np.asarray(tvar) - tvar_o) <= bound), (tvar, tvar_o)
+
+
+def test_packed_copy_only_below_2_24(A, gpu_ctx):
+    import torch
+    _say("packed copy catalog limit")
+    ids = torch.zeros(8, dtype=torch.int32, device="cuda")
+    offs = torch.tensor([0, 5, 8], dtype=torch.int64, device="cuda")
+    for cat, want in [(1 << 24, 3), ((1 << 24) + 1, 4), (1, 3)]:
+        y = A.ara_yet_create(gpu_ctx, ids, offs, cat)
+        try:
+            assert A.ara_yet_info(y) == (8, 2, want)
+        finally:
+            A.ara_yet_release(y)
+    A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_PACKING, 0)
+    try:
+        y = A.ara_yet_create(gpu_ctx, ids, offs, 100)
+        assert A.ara_yet_info(y)[2] == 4
+        A.ara_yet_release(y)
+    finally:
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_PACKING, 1)
 
 
 # ----------------------------------------------------------------------------- errors
@@ -432,6 +462,7 @@ def test_paper_shape_reduced_f64(A, S, gpu_ctx, paper_reduced):
     for pl in [1, 3]:
         got2 = analyze(A, S, gpu_ctx, w, pl, terms=twin)
         assert_ylt_close(got2, ref2, what=f"twin placement {pl}")
+        assert analyze(A, S, gpu_ctx, w, pl, terms=twin, packing=0).tobytes() == got2.tobytes()
     # a 1M-event catalog does not fit LDS as a dense table: forcing it is refused
     with pytest.raises(A.AraError) as e:
         analyze(A, S, gpu_ctx, w, 2, terms=twin)
