@@ -109,9 +109,20 @@ def cpu_baseline(w, target_s: float):
     dt = run(n)
     ev = float(w.trial_offsets[n] - w.trial_offsets[0])
     log(f"cpu oracle: calibration {na} trials {ta:.2f}s, {nb} trials {tb:.2f}s; sample {n} trials {dt:.1f}s")
+    # the sequential role: one thread on a smaller first slice (about a quarter of the time)
+    n1 = int(min(w.n_trials, max(100, (target_s / 4) / (per * threads))))
+    t = time.perf_counter()
+    r1 = oracle.analyze(w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
+                        elt_terms=w.elt_terms, t_begin=0, t_end=n1, threads=1)
+    oracle.risk(r1["ylt"], w.return_periods)
+    dt1 = time.perf_counter() - t
+    ev1 = float(w.trial_offsets[n1] - w.trial_offsets[0])
+    log(f"cpu oracle 1 thread: {n1} trials {dt1:.1f}s")
     return {"value": ev / dt, "unit": "trial-events·layers/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} of {w.n_trials} trials ({int(ev)} trial-events, 1 layer) of the same workload, "
-                      f"dense tables built per call, YLT then PML/TVaR; {dt:.1f}s wall"}
+                      f"dense tables built per call, YLT then PML/TVaR; {dt:.1f}s wall",
+            "value_1_thread": ev1 / dt1,
+            "sample_1_thread": f"first {n1} trials ({int(ev1)} trial-events), {dt1:.1f}s wall"}
 
 
 def _counter_rows(path: str):
@@ -167,6 +178,34 @@ def derive_traffic(fetch_path: str, write_path: str, copy_mib: int, cmd: str):
     print("\n".join(lines))
 
 
+def summarize_counters(path: str, out_path: str, cmd: str):
+    """Per-dispatch means of every counter of a rocprofv3 --pmc run for the headline
+    kernel, with the L2 hit rate and busy fractions derived from them."""
+    rows = [r for r in _counter_rows(path) if TRIAL_KERNEL in r["Kernel_Name"]]
+    per = {}
+    for r in rows:
+        per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    m = {k: float(np.mean(v)) for k, v in per.items()}
+    n = len(next(iter(per.values()))) if per else 0
+    lines = [f"# rocprofv3 counters of {TRIAL_KERNEL}, 1,000,000 trials x 1000 events, catalog 1,000,000, "
+             f"16-ELT layer, binary64 (mean of {n} dispatches)", f"# command: {cmd}", ""]
+    lines += [f"{k}: {v:.6g}" for k, v in sorted(m.items())]
+    if "TCC_HIT_sum" in m and "TCC_MISS_sum" in m:
+        lines.append(f"derived L2 hit rate: {m['TCC_HIT_sum'] / (m['TCC_HIT_sum'] + m['TCC_MISS_sum']):.3f}")
+    if "GRBM_GUI_ACTIVE" in m:
+        cyc = m["GRBM_GUI_ACTIVE"] / 8          # summed over the 8 XCDs
+        lines.append(f"derived cycles per XCD: {cyc:.4g}")
+        if "TA_BUSY_avr" in m:
+            lines.append(f"derived TA busy fraction: {m['TA_BUSY_avr'] / cyc:.3f}")
+        if "TD_TD_BUSY_sum" in m:
+            lines.append(f"derived TD busy fraction (256 CUs): {m['TD_TD_BUSY_sum'] / 256 / cyc:.3f}")
+    if "SQ_WAIT_INST_ANY" in m and "SQ_WAVE_CYCLES" in m:
+        lines.append(f"derived wave time waiting on dependencies: {m['SQ_WAIT_INST_ANY'] / m['SQ_WAVE_CYCLES']:.3f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_stats(stats_csv: str, out_path: str, cmd: str, top: int = 16):
     """Short text summary of a rocprofv3 --stats kernel table."""
     import csv
@@ -205,12 +244,17 @@ def main():
     ap.add_argument("--profile-cmd", default="", help="command recorded in a written summary")
     ap.add_argument("--summarize-stats", nargs=2, metavar=("STATS_CSV", "OUT"),
                     help="write a text summary of a rocprofv3 kernel_stats.csv and exit")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("PMC_DIR", "OUT"),
+                    help="write the trial kernel's counter means from a rocprofv3 --pmc output and exit")
     args = ap.parse_args()
     if args.derive_traffic:
         derive_traffic(args.derive_traffic[0], args.derive_traffic[1], args.copy_probe_mib or 1024, args.profile_cmd)
         return
     if args.summarize_stats:
         summarize_stats(args.summarize_stats[0], args.summarize_stats[1], args.profile_cmd)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters[0], args.summarize_counters[1], args.profile_cmd)
         return
 
     if args.gpus != 1:
