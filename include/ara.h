@@ -97,8 +97,12 @@ typedef enum ara_option {
     ARA_OPT_PLACEMENT = 1,      /* an ara_placement value                                            */
     ARA_OPT_BLOCK_THREADS = 2,  /* threads per workgroup of the trial kernel: 256, 512 or 1024       */
     ARA_OPT_GRID_PER_CU = 3,    /* workgroups per compute unit of the trial kernel (1..64; 0 = auto)  */
-    ARA_OPT_YET_PACKING = 4     /* 1 (default): YETs created later also keep a packed copy of their
+    ARA_OPT_YET_PACKING = 4,    /* 1 (default): YETs created later also keep a packed copy of their
                                    event IDs when catalog_size <= 2^24; 0: never                      */
+    ARA_OPT_TRIAL_MODE = 5      /* dense-table YLT kernels: 0 (default) = one lane per trial when the
+                                   YET averages <= 256 occurrences per trial, else one wave per
+                                   trial; 1 = always a wave; 2 = always a lane.  A lane adds its
+                                   trial's values in time order (the sequential sum)               */
 } ara_option;
 
 typedef struct ara_ctx ara_ctx;
@@ -283,6 +287,102 @@ ara_status ara_sort_desc(ara_ctx *ctx, const double *in, int64_t n, double *out,
 ara_status ara_risk_measures(ara_ctx *ctx, const double *ylt, int64_t n, ara_mem ylt_mem,
                              const double *return_periods, int32_t n_rp, double *pml, double *tvar,
                              void *workspace, size_t workspace_bytes);
+
+/* ---------------------------------------------------------------- Batches
+ * Many analyses in one persistent launch: the layer loop of Algorithm 1 (one YET,
+ * many layers) and Section IV's portfolios, or independent analyses of different
+ * YETs, catalogs and trial counts.  A job is one (YET, layer, trial range) with its
+ * YLT destination; jobs may share YETs and layers.  Each job runs the same device
+ * code as ara_analyze with the context's options at ara_batch_create (placement,
+ * trial mode, YET packing), so its YLT equals ara_analyze's bit for bit.
+ *   ylt  device memory, trial_end - trial_begin doubles, written by ara_batch_run.
+ * The YETs and layers must outlive the batch; rebuilding a layer's tables
+ * (ara_layer_build, ara_layer_set_terms) between runs is allowed (the tables are
+ * rebuilt in place). */
+typedef struct ara_job {
+    const ara_yet *yet;
+    const ara_layer *layer;
+    int64_t trial_begin, trial_end;
+    double *ylt;
+} ara_job;
+
+typedef struct ara_batch ara_batch;
+
+/* Plans the batch: validates every job (as ara_analyze would) and uploads their
+ * descriptors.  Errors: those of ara_analyze's argument checks, ARA_E_OOM. */
+ara_status ara_batch_create(ara_ctx *ctx, const ara_job *jobs, int32_t n_jobs, ara_batch **out);
+
+/* Computes every job's YLT on the context's stream.  The jobs are split into work
+ * items of about equal occurrence counts (whole trials), which one persistent launch
+ * processes.  The first run of a batch tunes the split: it times a few candidates
+ * (each computes all YLTs), keeps the fastest for batches of this shape on this
+ * context, and captures the launch in a HIP graph (blocking); later runs replay the
+ * graph (non-blocking).  Input errors found on the device are reported by ara_sync. */
+ara_status ara_batch_run(ara_batch *batch);
+
+/* PML and TVaR of every job's YLT at the given return periods (as
+ * ara_risk_measures, bit for bit): pml[j * n_rp + r], tvar[j * n_rp + r].  YLTs of up
+ * to 16384 trials are sorted in one workgroup's LDS, all in one launch; longer ones
+ * with the radix sort.  Blocking.  Errors: ARA_E_EMPTY (an empty job),
+ * ARA_E_INVALID_ARG (return period < 1 or NaN, more than 256 of them). */
+ara_status ara_batch_risk(ara_batch *batch, const double *return_periods, int32_t n_rp, double *pml,
+                          double *tvar);
+
+/* The tuned schedule: work items, workgroups, occurrences per item, and whether runs
+ * replay a graph.  Any output pointer may be NULL. */
+ara_status ara_batch_info(const ara_batch *batch, int32_t *n_items, int32_t *grid, int64_t *events_per_item,
+                          int32_t *graph);
+
+ara_status ara_batch_release(ara_batch *batch);
+
+/* ---------------------------------------------------------------- Serving
+ * A pricing server (real-time pricing of layers, Section I and Section IV) keeps one
+ * YET and a pool of ELTs resident and answers requests -- a layer made of pool ELTs,
+ * its terms and a trial range -- with PML and TVaR at the server's return periods.
+ * A worker thread batches requests as they arrive: each iteration admits queued
+ * requests in arrival order into free slots (their number bounded by max_batch and by
+ * memory_budget / the bytes one slot holds), builds their layers' tables in place,
+ * runs all of them in one batched launch, computes their risk measures and completes
+ * them; requests arriving meanwhile wait for the next iteration (continuous
+ * batching).  Every result equals that of the same analysis run alone (ara_layer_create
+ * over the same pool ELTs + ara_analyze + ara_risk_measures) bit for bit.
+ * The server works on its own stream and error word; the context's options at
+ * ara_server_create apply.  The YET and the pool ELTs must outlive the server. */
+typedef struct ara_server ara_server;
+
+typedef struct ara_server_config {
+    int32_t max_batch;              /* requests per iteration, >= 1                        */
+    int64_t memory_budget;          /* bytes for slots (tables + YLT); 0 = 1/4 of free HBM  */
+    int32_t n_rp;                   /* return periods of every request, 1..16               */
+    const double *return_periods;   /* n_rp values >= 1 (copied)                            */
+} ara_server_config;
+
+/* Errors: ARA_E_INVALID_ARG (bad config, handles of another context, an empty pool or
+ * one ELT of another catalog), ARA_E_OOM (no slot fits the budget), ARA_E_DEVICE. */
+ara_status ara_server_create(ara_ctx *ctx, const ara_yet *yet, ara_elt *const *pool, int32_t n_pool,
+                             const ara_server_config *config, ara_server **out);
+
+/* Queues a request: ELTs pool[elt_index[0..n_elts)] (n_elts >= 1, in that order),
+ * layer terms, and trials [trial_begin, trial_end) (non-empty).  Returns at once with
+ * a ticket.  The pool ELTs' tables must not be rebuilt while the server runs.
+ * Errors: ARA_E_INVALID_ARG, ARA_E_BAD_TERMS, ARA_E_BUSY (the server is stopping). */
+ara_status ara_server_submit(ara_server *server, const int32_t *elt_index, int32_t n_elts,
+                             const ara_layer_terms *terms, int64_t trial_begin, int64_t trial_end,
+                             uint64_t *ticket);
+
+/* Waits for a request and returns its PML and TVaR (n_rp values each) and, if seconds
+ * is not NULL, the time from its submission to its completion (steady clock), then
+ * forgets the ticket.  Returns the request's status (device-detected input errors
+ * included).  ARA_E_INVALID_ARG for an unknown ticket. */
+ara_status ara_server_wait(ara_server *server, uint64_t ticket, double *pml, double *tvar, double *seconds);
+
+/* Iterations run, requests completed, the largest number of requests in one iteration,
+ * and the slot count.  Any output pointer may be NULL. */
+ara_status ara_server_stats(ara_server *server, int64_t *iterations, int64_t *completed, int32_t *max_in_iteration,
+                            int32_t *slots);
+
+/* Completes every queued request, stops the worker and frees the server. */
+ara_status ara_server_release(ara_server *server);
 
 #ifdef __cplusplus
 }

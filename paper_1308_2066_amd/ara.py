@@ -57,6 +57,7 @@ ARA_OPT_PLACEMENT = 1
 ARA_OPT_BLOCK_THREADS = 2
 ARA_OPT_GRID_PER_CU = 3
 ARA_OPT_YET_PACKING = 4
+ARA_OPT_TRIAL_MODE = 5
 
 ARA_BUILD_TABLES = 1
 
@@ -71,6 +72,16 @@ class ara_layer_terms(ctypes.Structure):
 
 class ara_elt_terms(ctypes.Structure):
     _fields_ = [("fx", ctypes.c_double), ("retention", ctypes.c_double), ("limit", ctypes.c_double)]
+
+
+class ara_job(ctypes.Structure):
+    _fields_ = [("yet", ctypes.c_void_p), ("layer", ctypes.c_void_p), ("trial_begin", ctypes.c_int64),
+                ("trial_end", ctypes.c_int64), ("ylt", ctypes.c_void_p)]
+
+
+class ara_server_config(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_int32), ("memory_budget", ctypes.c_int64), ("n_rp", ctypes.c_int32),
+                ("return_periods", ctypes.c_void_p)]
 
 
 _P = ctypes.c_void_p
@@ -108,6 +119,20 @@ _SIGS = {
     "ara_sort_workspace_size": (_ST, [_I64, ctypes.POINTER(ctypes.c_size_t)]),
     "ara_sort_desc": (_ST, [_P, _P, _I64, _P, _P, ctypes.c_size_t]),
     "ara_risk_measures": (_ST, [_P, _P, _I64, ctypes.c_int, _P, _I32, _P, _P, _P, ctypes.c_size_t]),
+    "ara_batch_create": (_ST, [_P, ctypes.POINTER(ara_job), _I32, ctypes.POINTER(_P)]),
+    "ara_batch_run": (_ST, [_P]),
+    "ara_batch_risk": (_ST, [_P, _P, _I32, _P, _P]),
+    "ara_batch_info": (_ST, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64),
+                             ctypes.POINTER(_I32)]),
+    "ara_batch_release": (_ST, [_P]),
+    "ara_server_create": (_ST, [_P, _P, ctypes.POINTER(_P), _I32, ctypes.POINTER(ara_server_config),
+                                ctypes.POINTER(_P)]),
+    "ara_server_submit": (_ST, [_P, _P, _I32, ctypes.POINTER(ara_layer_terms), _I64, _I64,
+                                ctypes.POINTER(ctypes.c_uint64)]),
+    "ara_server_wait": (_ST, [_P, ctypes.c_uint64, _P, _P, ctypes.POINTER(_D)]),
+    "ara_server_stats": (_ST, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32),
+                               ctypes.POINTER(_I32)]),
+    "ara_server_release": (_ST, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -175,6 +200,11 @@ class Elt:
 class Layer:
     def __init__(self, ptr, ctx, elts, catalog):
         self.ptr, self.ctx, self.elts, self.catalog_size = ptr, ctx, list(elts), catalog
+
+
+class Batch:
+    def __init__(self, ptr, ctx, keep, n_jobs):
+        self.ptr, self.ctx, self._keep, self.n_jobs = ptr, ctx, keep, n_jobs
 
 
 def _check(st: int, ctx: Optional[Ctx], where: str):
@@ -388,3 +418,97 @@ def ara_analyze_host(ctx: Ctx, yet: Yet, layer: Layer, trial_begin: int, trial_e
     _check(_lib.ara_analyze(ctx.ptr, yet.ptr, layer.ptr, int(trial_begin), int(trial_end), out.ctypes.data_as(_P),
                             ARA_MEM_HOST), ctx, "ara_analyze")
     return out
+
+
+# ----------------------------------------------------------------------------- batches
+def ara_batch_create(ctx: Ctx, jobs) -> Batch:
+    """jobs: sequence of (Yet, Layer, trial_begin, trial_end, ylt) with ylt a float64
+    GPU tensor of trial_end - trial_begin elements."""
+    import torch
+    arr = (ara_job * max(len(jobs), 1))()
+    keep = []
+    for i, (y, layer, t0, t1, ylt) in enumerate(jobs):
+        py = _dev_ptr(ylt, torch.float64, "ylt")
+        if ylt.numel() < t1 - t0:
+            raise ValueError("ylt shorter than the job's trial range")
+        arr[i] = ara_job(y.ptr, layer.ptr, int(t0), int(t1), py.value)
+        keep.append((y, layer, ylt))
+    out = _P()
+    _check(_lib.ara_batch_create(ctx.ptr, arr, len(jobs), ctypes.byref(out)), ctx, "ara_batch_create")
+    return Batch(out, ctx, keep, len(jobs))
+
+
+def ara_batch_run(b: Batch):
+    _check(_lib.ara_batch_run(b.ptr), b.ctx, "ara_batch_run")
+
+
+def ara_batch_risk(b: Batch, return_periods: Sequence[float]):
+    """(pml, tvar) numpy arrays of shape (n_jobs, n_rp) (blocking)."""
+    rp = np.ascontiguousarray(np.asarray(return_periods, dtype=np.float64))
+    pml = np.empty((b.n_jobs, rp.shape[0]), np.float64)
+    tvar = np.empty_like(pml)
+    _check(_lib.ara_batch_risk(b.ptr, rp.ctypes.data_as(_P), rp.shape[0], pml.ctypes.data_as(_P),
+                               tvar.ctypes.data_as(_P)), b.ctx, "ara_batch_risk")
+    return pml, tvar
+
+
+def ara_batch_info(b: Batch):
+    """(n_items, grid, events_per_item, graph)."""
+    n, g, e, gr = _I32(), _I32(), _I64(), _I32()
+    _check(_lib.ara_batch_info(b.ptr, ctypes.byref(n), ctypes.byref(g), ctypes.byref(e), ctypes.byref(gr)), b.ctx,
+           "ara_batch_info")
+    return int(n.value), int(g.value), int(e.value), int(gr.value)
+
+
+def ara_batch_release(b: Batch):
+    _check(_lib.ara_batch_release(b.ptr), b.ctx, "ara_batch_release")
+    b.ptr, b._keep = None, None
+
+
+# ----------------------------------------------------------------------------- serving
+class Server:
+    def __init__(self, ptr, ctx, keep, n_rp):
+        self.ptr, self.ctx, self._keep, self.n_rp = ptr, ctx, keep, n_rp
+
+
+def ara_server_create(ctx: Ctx, yet: Yet, pool: Sequence[Elt], return_periods: Sequence[float], max_batch: int = 32,
+                      memory_budget: int = 0) -> Server:
+    rp = np.ascontiguousarray(np.asarray(return_periods, dtype=np.float64))
+    arr = (_P * len(pool))(*[e.ptr for e in pool])
+    cfg = ara_server_config(int(max_batch), int(memory_budget), rp.shape[0], rp.ctypes.data_as(_P).value)
+    out = _P()
+    _check(_lib.ara_server_create(ctx.ptr, yet.ptr, arr, len(pool), ctypes.byref(cfg), ctypes.byref(out)), ctx,
+           "ara_server_create")
+    return Server(out, ctx, (yet, list(pool), rp), rp.shape[0])
+
+
+def ara_server_submit(s: Server, elt_index: Sequence[int], terms: Sequence[float], trial_begin: int,
+                      trial_end: int) -> int:
+    idx = np.ascontiguousarray(np.asarray(elt_index, dtype=np.int32))
+    t = ctypes.c_uint64()
+    _check(_lib.ara_server_submit(s.ptr, idx.ctypes.data_as(_P), idx.shape[0], ctypes.byref(_terms(terms)),
+                                  int(trial_begin), int(trial_end), ctypes.byref(t)), s.ctx, "ara_server_submit")
+    return int(t.value)
+
+
+def ara_server_wait(s: Server, ticket: int):
+    """(pml, tvar, seconds from submission to completion); blocks (the GIL is released)."""
+    pml = np.empty(s.n_rp, np.float64)
+    tvar = np.empty(s.n_rp, np.float64)
+    sec = _D()
+    _check(_lib.ara_server_wait(s.ptr, ctypes.c_uint64(int(ticket)), pml.ctypes.data_as(_P), tvar.ctypes.data_as(_P),
+                                ctypes.byref(sec)), s.ctx, "ara_server_wait")
+    return pml, tvar, float(sec.value)
+
+
+def ara_server_stats(s: Server):
+    """(iterations, completed, max requests in one iteration, slots)."""
+    it, done, mx, sl = _I64(), _I64(), _I32(), _I32()
+    _check(_lib.ara_server_stats(s.ptr, ctypes.byref(it), ctypes.byref(done), ctypes.byref(mx), ctypes.byref(sl)),
+           s.ctx, "ara_server_stats")
+    return int(it.value), int(done.value), int(mx.value), int(sl.value)
+
+
+def ara_server_release(s: Server):
+    _check(_lib.ara_server_release(s.ptr), s.ctx, "ara_server_release")
+    s.ptr, s._keep = None, None

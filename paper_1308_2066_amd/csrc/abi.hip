@@ -5,7 +5,14 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ara_internal.h"
@@ -25,6 +32,8 @@ struct ara_ctx {
     int block_threads = 0;           // 0 = automatic
     int grid_per_cu = 0;             // 0 = automatic
     int yet_packing = 1;             // keep a packed copy of YET IDs where they fit 24 bits
+    int trial_mode = 0;              // 0 = by trial length, 1 = wave per trial, 2 = lane per trial
+    std::map<std::string, int64_t> tuned;   // batch shape -> events per work item
     int live = 0;                    // handles alive on this context
     std::string msg;
 };
@@ -149,7 +158,8 @@ static int bitmap_qcap(int32_t catalog, int wpb, int lds_max) {
 }
 
 // Chooses where the layer's table lives during the trial kernel and the launch shape.
-static ara_status plan_trial(ara_ctx *c, const ara_layer *L, int64_t n_trials, TrialLaunch &tl) {
+// mean_len: mean occurrences per trial of the YET (decides lane or wave per trial)
+static ara_status plan_trial(ara_ctx *c, const ara_layer *L, int64_t n_trials, double mean_len, TrialLaunch &tl) {
     int pl = c->placement;
     const int64_t dense = int64_t(L->catalog) * 8;
     const int block_bitmap = c->block_threads ? c->block_threads : 1024;
@@ -174,7 +184,9 @@ static ara_status plan_trial(ara_ctx *c, const ara_layer *L, int64_t n_trials, T
     tl.f32 = L->f32;
     tl.lds_bytes = size_t(lds);
     tl.qcap = pl == ARA_PLACE_LDS_BITMAP ? qcap : 0;
-    tl.block = c->block_threads ? c->block_threads : (pl == ARA_PLACE_GLOBAL_DENSE ? 256 : 1024);
+    tl.lane = pl != ARA_PLACE_LDS_BITMAP &&
+              (c->trial_mode == 2 || (c->trial_mode == 0 && mean_len <= double(kLaneModeMaxMean)));
+    tl.block = c->block_threads ? c->block_threads : (pl == ARA_PLACE_GLOBAL_DENSE || tl.lane ? 256 : 1024);
     int per_cu = c->grid_per_cu;
     if (per_cu == 0) {
         const int by_threads = 2048 / tl.block;
@@ -183,8 +195,8 @@ static ara_status plan_trial(ara_ctx *c, const ara_layer *L, int64_t n_trials, T
         per_cu = std::max(1, std::min(by_threads, by_lds));
     }
     int64_t grid = int64_t(c->n_cu) * per_cu;
-    const int64_t wpb = tl.block / 64;                      // one wave per trial at a time
-    grid = std::min<int64_t>(grid, std::max<int64_t>(1, (n_trials + wpb - 1) / wpb));
+    const int64_t tpb = tl.lane ? tl.block : tl.block / 64;   // trials in flight per workgroup
+    grid = std::min<int64_t>(grid, std::max<int64_t>(1, (n_trials + tpb - 1) / tpb));
     tl.grid = int(grid);
     return ARA_OK;
 }
@@ -325,6 +337,10 @@ extern "C" ara_status ara_set_option(ara_ctx *c, int option, int64_t v) {
     case ARA_OPT_GRID_PER_CU:
         if (v < 0 || v > 64) return fail(c, ARA_E_INVALID_ARG, "bad workgroups per CU %lld", (long long)v);
         c->grid_per_cu = int(v);
+        return ARA_OK;
+    case ARA_OPT_TRIAL_MODE:
+        if (v < 0 || v > 2) return fail(c, ARA_E_INVALID_ARG, "bad trial mode %lld", (long long)v);
+        c->trial_mode = int(v);
         return ARA_OK;
     case ARA_OPT_YET_PACKING:
         if (v != 0 && v != 1) return fail(c, ARA_E_INVALID_ARG, "bad packing flag %lld", (long long)v);
@@ -614,7 +630,7 @@ extern "C" ara_status ara_layer_stats(ara_ctx *c, const ara_layer *L, int64_t *n
     if (!c || !L || L->ctx != c) return ARA_E_INVALID_ARG;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     TrialLaunch tl{};
-    ara_status s = plan_trial(c, L, 1 << 20, tl);
+    ara_status s = plan_trial(c, L, 1 << 20, 1e9, tl);
     if (s != ARA_OK) return s;
     if (placement) *placement = tl.placement;
     if (lds_bytes) *lds_bytes = int64_t(tl.lds_bytes);
@@ -681,7 +697,7 @@ extern "C" ara_status ara_analyze(ara_ctx *c, const ara_yet *y, const ara_layer 
     if (t1 == t0) return ARA_OK;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     TrialLaunch tl{};
-    s = plan_trial(c, L, t1 - t0, tl);
+    s = plan_trial(c, L, t1 - t0, y->n_trials ? double(y->n_events) / double(y->n_trials) : 0.0, tl);
     if (s != ARA_OK) return s;
     double *dst = ylt;
     if (mem == ARA_MEM_HOST) {
@@ -769,7 +785,7 @@ extern "C" ara_status ara_lookup(ara_ctx *c, const ara_layer *L, const int32_t *
     if (n == 0) return ARA_OK;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     TrialLaunch tl{};
-    ara_status s = plan_trial(c, L, 1 << 20, tl);
+    ara_status s = plan_trial(c, L, 1 << 20, 1e9, tl);
     if (s != ARA_OK) return s;
     const int32_t *di = ids;
     double *dg = g, *dout = o;
@@ -897,4 +913,674 @@ extern "C" ara_status ara_risk_measures(ara_ctx *c, const double *ylt, int64_t n
     if (owned) dev_free(w);
     dev_free(tmp);
     return s;
+}
+
+// ------------------------------------------------------------------ batches
+struct ara_batch {
+    ara_ctx *ctx;
+    std::vector<ara_job> jobs;
+    std::vector<BatchJob> hjobs;
+    std::vector<int64_t> mean_len;   // per job: occurrences per trial of its YET (at least 1)
+    std::string shape;               // key of the tuning cache
+    BatchJob *d_jobs = nullptr;
+    BatchItem *d_items = nullptr;
+    int32_t n_items = 0, per_wg = 0, grid = 0;
+    int64_t events_per_item = 0;
+    hipStream_t cap = nullptr;       // private stream the launch is captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    // risk measures
+    const double **d_ylts = nullptr;
+    int64_t *d_ns = nullptr, *d_ks = nullptr;
+    double *d_risk = nullptr;
+    int32_t risk_cap = 0;            // return periods d_ks/d_risk hold
+    void *ws = nullptr;              // sort workspace for YLTs too long for one workgroup
+    size_t ws_bytes = 0;
+    bool counted = false;            // counted in ctx->live
+};
+
+// Work items of job j (trials [tb, te), mean_len occurrences per trial) of about
+// `events` occurrences each: whole trials, at least one per lane (lane mode) or wave.
+static void split_items(int32_t j, int32_t mode, int64_t tb, int64_t te, int64_t mean_len, int64_t events,
+                        std::vector<BatchItem> &items) {
+    const int64_t unit = mode == kModeLaneLds || mode == kModeLaneGlobal ? 1024 : 16;
+    int64_t per = std::max<int64_t>(1, events / std::max<int64_t>(1, mean_len));
+    per = (per + unit - 1) / unit * unit;
+    for (int64_t t = tb; t < te; t += per) items.push_back(BatchItem{j, 0, t, std::min(te, t + per)});
+}
+
+// The work items of a batch, grouped by job in job order.
+static std::vector<BatchItem> batch_items(const ara_batch *b, int64_t events) {
+    std::vector<BatchItem> items;
+    for (size_t j = 0; j < b->jobs.size(); ++j)
+        split_items(int32_t(j), b->hjobs[j].mode, b->jobs[j].trial_begin, b->jobs[j].trial_end, b->mean_len[j], events,
+                    items);
+    return items;
+}
+
+// Workgroups and items per workgroup for n items (at most one workgroup per CU).
+static void batch_shape(int32_t n_items, int n_cu, int32_t &grid, int32_t &per_wg) {
+    grid = std::max(1, std::min(n_items, n_cu));
+    per_wg = (n_items + grid - 1) / grid;
+    grid = n_items > 0 ? (n_items + per_wg - 1) / std::max(1, per_wg) : 1;
+}
+
+static ara_status batch_set_items(ara_batch *b, int64_t events) {
+    ara_ctx *c = b->ctx;
+    const std::vector<BatchItem> items = batch_items(b, events);
+    dev_free(b->d_items);
+    b->d_items = nullptr;
+    b->n_items = int32_t(items.size());
+    if (b->n_items > 0) {
+        ara_status s = dev_alloc(c, &b->d_items, items.size() * sizeof(BatchItem), "batch items");
+        if (s != ARA_OK) return s;
+        HIP_OR_RETURN(c, hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice),
+                      "batch items upload");
+    }
+    batch_shape(b->n_items, c->n_cu, b->grid, b->per_wg);
+    b->events_per_item = events;
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t n_jobs, ara_batch **out) {
+    if (!c || !out || n_jobs < 0 || (n_jobs > 0 && !jobs)) return ARA_E_INVALID_ARG;
+    *out = nullptr;
+    HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    ara_batch *b = new (std::nothrow) ara_batch();
+    if (!b) return ARA_E_OOM;
+    b->ctx = c;
+    char key[160];
+    for (int32_t j = 0; j < n_jobs; ++j) {
+        const ara_job &jb = jobs[j];
+        ara_status s = check_analysis(c, jb.yet, jb.layer, jb.trial_begin, jb.trial_end);
+        if (s == ARA_OK && jb.trial_end > jb.trial_begin && !jb.ylt) s = fail(c, ARA_E_INVALID_ARG, "job %d: no YLT", j);
+        TrialLaunch tl{};
+        const double mean = jb.yet && jb.yet->n_trials ? double(jb.yet->n_events) / double(jb.yet->n_trials) : 0.0;
+        if (s == ARA_OK) s = plan_trial(c, jb.layer, jb.trial_end - jb.trial_begin, mean, tl);
+        if (s != ARA_OK) {
+            delete b;
+            return s;
+        }
+        BatchJob h{};
+        h.a = trial_args(jb.yet, jb.layer, jb.trial_begin, jb.trial_end, jb.ylt);
+        h.a.qcap = tl.qcap;
+        h.mode = batch_mode(tl, h.a.ids24 != nullptr);
+        h.placement = tl.placement;
+        b->jobs.push_back(jb);
+        b->hjobs.push_back(h);
+        b->mean_len.push_back(std::max<int64_t>(1, int64_t(std::llround(mean))));
+        std::snprintf(key, sizeof key, "%d:%lld:%lld:%d;", h.mode, (long long)(jb.trial_end - jb.trial_begin),
+                      (long long)b->mean_len.back(), jb.layer->catalog);
+        b->shape += key;
+    }
+    ara_status s = ARA_OK;
+    if (n_jobs > 0) {
+        s = dev_alloc(c, &b->d_jobs, b->hjobs.size() * sizeof(BatchJob), "batch jobs");
+        if (s == ARA_OK) {
+            hipError_t e = hipMemcpy(b->d_jobs, b->hjobs.data(), b->hjobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice);
+            if (e != hipSuccess) s = hip_fail(c, e, "batch jobs upload");
+        }
+    }
+    if (s != ARA_OK) {
+        ara_batch_release(b);
+        return s;
+    }
+    c->live++;
+    b->counted = true;
+    *out = b;
+    return ARA_OK;
+}
+
+// First run: time each candidate split (every candidate computes the same results),
+// keep the fastest for this batch shape, then capture the launch in a graph that
+// later runs replay on the context's stream.
+static ara_status batch_tune(ara_batch *b) {
+    ara_ctx *c = b->ctx;
+    auto it = c->tuned.find(b->shape);
+    if (it != c->tuned.end()) return batch_set_items(b, it->second);
+    static const int64_t kCandidates[] = {int64_t(1) << 16, int64_t(1) << 18, int64_t(1) << 20, int64_t(1) << 22};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OR_RETURN(c, hipEventCreate(&e0), "event");
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(c, e, "event");
+    }
+    int64_t best = kCandidates[0];
+    float best_ms = 1e30f;
+    ara_status s = ARA_OK;
+    for (int64_t cand : kCandidates) {
+        s = batch_set_items(b, cand);
+        if (s != ARA_OK) break;
+        e = hipEventRecord(e0, c->stream);
+        if (e == hipSuccess) e = launch_batch(b->d_jobs, b->d_items, b->n_items, b->per_wg, b->grid, c->stream);
+        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) {
+            s = hip_fail(c, e, "batch tuning run");
+            break;
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != ARA_OK) return s;
+    s = sync_and_check(c);
+    if (s != ARA_OK) return s;
+    c->tuned[b->shape] = best;
+    return batch_set_items(b, best);
+}
+
+static ara_status batch_capture(ara_batch *b) {
+    ara_ctx *c = b->ctx;
+    HIP_OR_RETURN(c, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream");
+    HIP_OR_RETURN(c, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
+    hipError_t e = launch_batch(b->d_jobs, b->d_items, b->n_items, b->per_wg, b->grid, b->cap);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->cap, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) b->graph = g;
+    else if (g) (void)hipGraphDestroy(g);
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    return e == hipSuccess ? ARA_OK : hip_fail(c, e, "batch graph");
+}
+
+extern "C" ara_status ara_batch_run(ara_batch *b) {
+    if (!b) return ARA_E_INVALID_ARG;
+    ara_ctx *c = b->ctx;
+    if (b->jobs.empty()) return ARA_OK;
+    HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    if (!b->exec) {
+        ara_status s = batch_tune(b);
+        if (s != ARA_OK) return s;
+        s = batch_capture(b);
+        if (s != ARA_OK) return s;
+        return ARA_OK;   // the tuning runs already computed every job
+    }
+    HIP_OR_RETURN(c, hipGraphLaunch(b->exec, c->stream), "batch graph launch");
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_batch_info(const ara_batch *b, int32_t *n_items, int32_t *grid, int64_t *events_per_item,
+                                    int32_t *graph) {
+    if (!b) return ARA_E_INVALID_ARG;
+    if (n_items) *n_items = b->n_items;
+    if (grid) *grid = b->grid;
+    if (events_per_item) *events_per_item = b->events_per_item;
+    if (graph) *graph = b->exec ? 1 : 0;
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_batch_risk(ara_batch *b, const double *rps, int32_t n_rp, double *pml, double *tvar) {
+    if (!b || n_rp < 0 || (n_rp > 0 && (!rps || !pml || !tvar))) return ARA_E_INVALID_ARG;
+    ara_ctx *c = b->ctx;
+    const int32_t nj = int32_t(b->jobs.size());
+    if (nj == 0 || n_rp == 0) return ARA_OK;
+    if (size_t(n_rp) * 2 > kStageDoubles) return fail(c, ARA_E_INVALID_ARG, "at most %zu return periods", kStageDoubles / 2);
+    for (int32_t j = 0; j < nj; ++j)
+        if (b->jobs[size_t(j)].trial_end == b->jobs[size_t(j)].trial_begin)
+            return fail(c, ARA_E_EMPTY, "job %d: risk measures of an empty YLT", j);
+    std::vector<int64_t> ks(size_t(nj) * size_t(n_rp));
+    for (int32_t j = 0; j < nj; ++j) {
+        const int64_t n = b->jobs[size_t(j)].trial_end - b->jobs[size_t(j)].trial_begin;
+        for (int32_t r = 0; r < n_rp; ++r)
+            if (ara_return_period_rank(n, rps[r], &ks[size_t(j) * n_rp + r]) != ARA_OK)
+                return fail(c, ARA_E_INVALID_ARG, "return period %g invalid (must be >= 1)", rps[r]);
+    }
+    HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    // device copies of the per-job inputs (once per return-period count)
+    if (!b->d_ylts) {
+        std::vector<const double *> yp(static_cast<size_t>(nj));
+        std::vector<int64_t> ns(static_cast<size_t>(nj));
+        for (int32_t j = 0; j < nj; ++j) {
+            yp[size_t(j)] = b->jobs[size_t(j)].ylt;
+            ns[size_t(j)] = b->jobs[size_t(j)].trial_end - b->jobs[size_t(j)].trial_begin;
+        }
+        ara_status s = dev_alloc(c, &b->d_ylts, size_t(nj) * sizeof(double *), "batch ylt list");
+        if (s == ARA_OK) s = dev_alloc(c, &b->d_ns, size_t(nj) * 8, "batch sizes");
+        if (s != ARA_OK) return s;
+        HIP_OR_RETURN(c, hipMemcpy(b->d_ylts, yp.data(), size_t(nj) * sizeof(double *), hipMemcpyHostToDevice), "upload");
+        HIP_OR_RETURN(c, hipMemcpy(b->d_ns, ns.data(), size_t(nj) * 8, hipMemcpyHostToDevice), "upload");
+    }
+    if (b->risk_cap < n_rp) {
+        dev_free(b->d_ks);
+        dev_free(b->d_risk);
+        b->d_ks = nullptr;
+        b->d_risk = nullptr;
+        ara_status s = dev_alloc(c, &b->d_ks, ks.size() * 8, "batch ranks");
+        if (s == ARA_OK) s = dev_alloc(c, &b->d_risk, size_t(nj) * 2 * size_t(n_rp) * 8, "batch risk");
+        if (s != ARA_OK) return s;
+        b->risk_cap = n_rp;
+    }
+    HIP_OR_RETURN(c, hipMemcpyAsync(b->d_ks, ks.data(), ks.size() * 8, hipMemcpyHostToDevice, c->stream), "upload ranks");
+    // short YLTs: one workgroup each, all in one launch; long ones: the radix sort
+    hipError_t e = launch_risk_batch(b->d_ylts, b->d_ns, b->d_ks, nj, n_rp, b->d_risk, c->stream);
+    std::vector<double> h(size_t(nj) * 2 * size_t(n_rp));
+    for (int32_t j = 0; j < nj && e == hipSuccess; ++j) {
+        const int64_t n = b->jobs[size_t(j)].trial_end - b->jobs[size_t(j)].trial_begin;
+        if (n <= kRiskLdsKeys) continue;
+        const size_t need = sort_workspace_bytes(n);
+        if (b->ws_bytes < need) {
+            e = hipStreamSynchronize(c->stream);
+            dev_free(b->ws);
+            b->ws = nullptr;
+            b->ws_bytes = 0;
+            if (e == hipSuccess) e = hipMalloc(&b->ws, need);
+            if (e != hipSuccess) break;
+            b->ws_bytes = need;
+        }
+        e = launch_sort_desc_keys(b->jobs[size_t(j)].ylt, n, b->ws, c->stream);
+        // groups of 16 return periods, laid out like ara_risk_measures' staging
+        if (e == hipSuccess) e = launch_risk(b->ws, n, &ks[size_t(j) * n_rp], n_rp, c->d_out, c->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(c->h_out, c->d_out, size_t(2 * n_rp) * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        for (int32_t base = 0; base < n_rp && e == hipSuccess; base += 16) {
+            const int32_t m = std::min<int32_t>(16, n_rp - base);
+            for (int32_t i = 0; i < m; ++i) {
+                h[size_t(j) * 2 * n_rp + base + i] = c->h_out[2 * base + i];
+                h[size_t(j) * 2 * n_rp + n_rp + base + i] = c->h_out[2 * base + m + i];
+            }
+        }
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "batch risk measures");
+    std::vector<double> small(size_t(nj) * 2 * size_t(n_rp));
+    HIP_OR_RETURN(c, hipMemcpyAsync(small.data(), b->d_risk, small.size() * 8, hipMemcpyDeviceToHost, c->stream),
+                  "download risk");
+    ara_status s = sync_and_check(c);
+    if (s != ARA_OK) return s;
+    for (int32_t j = 0; j < nj; ++j) {
+        const int64_t n = b->jobs[size_t(j)].trial_end - b->jobs[size_t(j)].trial_begin;
+        const double *src = n <= kRiskLdsKeys ? &small[size_t(j) * 2 * n_rp] : &h[size_t(j) * 2 * n_rp];
+        for (int32_t r = 0; r < n_rp; ++r) {
+            pml[size_t(j) * n_rp + r] = src[r];
+            tvar[size_t(j) * n_rp + r] = src[n_rp + r];
+        }
+    }
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_batch_release(ara_batch *b) {
+    if (!b) return ARA_E_INVALID_ARG;
+    ara_ctx *c = b->ctx;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    dev_free(b->d_jobs);
+    dev_free(b->d_items);
+    dev_free(b->d_ylts);
+    dev_free(b->d_ns);
+    dev_free(b->d_ks);
+    dev_free(b->d_risk);
+    dev_free(b->ws);
+    if (b->counted) c->live--;
+    delete b;
+    return ARA_OK;
+}
+
+// ------------------------------------------------------------------ serving
+namespace {
+
+struct ServerRequest {
+    std::vector<int32_t> elts;
+    ara_layer_terms terms;
+    int64_t t0 = 0, t1 = 0;
+    std::vector<double> pml, tvar;
+    ara_status status = ARA_OK;
+    bool done = false;
+    std::chrono::steady_clock::time_point submitted, finished;
+};
+
+struct ServerSlot {
+    ara_layer *L = nullptr;      // tables and a descriptor array for every pool ELT
+    double *ylt = nullptr;       // one YLT of the YET's length
+};
+
+}  // namespace
+
+struct ara_server {
+    ara_ctx *ctx = nullptr;           // the caller's context (handles, slot layers)
+    ara_ctx *pc = nullptr;            // private context of the worker: stream, error word, options
+    hipStream_t stream = nullptr;
+    const ara_yet *yet = nullptr;
+    std::vector<ara_elt *> pool;
+    std::vector<double> rps;
+    std::vector<ServerSlot> slots;
+    BatchJob *d_jobs = nullptr, *h_jobs = nullptr;
+    BatchItem *d_items = nullptr, *h_items = nullptr;
+    int32_t item_cap = 0;
+    EltDesc *h_descs = nullptr;       // pinned staging: every slot's descriptors
+    const double **d_ylts = nullptr;
+    int64_t *d_ns = nullptr, *d_ks = nullptr, *h_nks = nullptr;   // h_nks: ns then ks, pinned
+    double *d_res = nullptr, *h_res = nullptr;                    // [slot][2 * n_rp]
+    void *ws = nullptr;               // radix sort workspace for the YET's length
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<std::pair<uint64_t, ServerRequest *>> queue;
+    std::map<uint64_t, ServerRequest *> live;
+    uint64_t next_ticket = 1;
+    bool stopping = false;
+    int64_t iterations = 0, completed = 0;
+    int32_t max_seen = 0;
+};
+
+static constexpr int64_t kServerEventsPerItem = int64_t(1) << 18;
+
+// One iteration on the worker's stream: layers, one batched launch, risk measures.
+static ara_status server_iteration(ara_server *sv, const std::vector<ServerRequest *> &reqs) {
+    ara_ctx *pc = sv->pc;
+    const int32_t nr = int32_t(sv->rps.size());
+    const size_t np = sv->pool.size();
+    const int64_t mean = sv->yet->n_trials ? std::max<int64_t>(1, int64_t(std::llround(double(sv->yet->n_events) /
+                                                                                         double(sv->yet->n_trials))))
+                                           : 1;
+    std::vector<BatchItem> items;
+    for (size_t i = 0; i < reqs.size(); ++i) {
+        ServerRequest *r = reqs[i];
+        ara_layer *L = sv->slots[i].L;
+        EltDesc *hd = sv->h_descs + i * np;
+        // the slot layer keeps its member list (every pool ELT, for the ELTs' user counts);
+        // its descriptors, precision and terms become the request's
+        bool all_f32 = !r->elts.empty();
+        for (size_t k = 0; k < r->elts.size(); ++k) {
+            const ara_elt *e = sv->pool[size_t(r->elts[k])];
+            hd[k] = e->desc;
+            all_f32 = all_f32 && e->prec == ARA_F32;
+        }
+        L->f32 = all_f32;
+        L->terms = r->terms;
+        const int n = int(r->elts.size());
+        hipError_t e = hipSuccess;
+        if (n > 0) e = hipMemcpyAsync(L->d_descs, hd, sizeof(EltDesc) * size_t(n), hipMemcpyHostToDevice, sv->stream);
+        if (e == hipSuccess) e = launch_layer_combine(L->d_descs, n, L->catalog, L->f32, 0.0, 0.0, L->t, sv->stream);
+        if (e == hipSuccess)
+            e = launch_layer_filter(L->catalog, L->f32, r->terms.occ_retention, r->terms.occ_limit, L->t, sv->stream);
+        if (e != hipSuccess) return hip_fail(pc, e, "server layer build");
+        TrialLaunch tl{};
+        ara_status s = plan_trial(pc, L, r->t1 - r->t0, double(sv->yet->n_events) / double(std::max<int64_t>(1, sv->yet->n_trials)), tl);
+        if (s != ARA_OK) return s;
+        BatchJob &h = sv->h_jobs[i];
+        h.a = trial_args(sv->yet, L, r->t0, r->t1, sv->slots[i].ylt);
+        h.a.err = pc->d_err;
+        h.a.qcap = tl.qcap;
+        h.mode = batch_mode(tl, h.a.ids24 != nullptr);
+        h.placement = tl.placement;
+        split_items(int32_t(i), h.mode, r->t0, r->t1, mean, kServerEventsPerItem, items);
+    }
+    const int32_t nj = int32_t(reqs.size());
+    if (int32_t(items.size()) > sv->item_cap) return fail(pc, ARA_E_OOM, "server: %zu work items", items.size());
+    std::copy(items.begin(), items.end(), sv->h_items);
+    int32_t grid = 1, per_wg = 0;
+    batch_shape(int32_t(items.size()), pc->n_cu, grid, per_wg);
+    hipError_t e = hipMemcpyAsync(sv->d_jobs, sv->h_jobs, sizeof(BatchJob) * size_t(nj), hipMemcpyHostToDevice, sv->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sv->d_items, sv->h_items, sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice, sv->stream);
+    if (e == hipSuccess) e = launch_batch(sv->d_jobs, sv->d_items, int32_t(items.size()), per_wg, grid, sv->stream);
+    // risk measures: ranks per request, short YLTs in one launch, long ones one by one
+    int64_t *hn = sv->h_nks, *hk = sv->h_nks + sv->slots.size();
+    for (int32_t i = 0; i < nj && e == hipSuccess; ++i) {
+        const int64_t n = reqs[size_t(i)]->t1 - reqs[size_t(i)]->t0;
+        hn[i] = n;
+        for (int32_t r = 0; r < nr; ++r) (void)ara_return_period_rank(n, sv->rps[size_t(r)], &hk[size_t(i) * nr + r]);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(sv->d_ns, hn, 8 * size_t(nj), hipMemcpyHostToDevice, sv->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(sv->d_ks, hk, 8 * size_t(nj) * nr, hipMemcpyHostToDevice, sv->stream);
+    if (e == hipSuccess) e = launch_risk_batch(sv->d_ylts, sv->d_ns, sv->d_ks, nj, nr, sv->d_res, sv->stream);
+    for (int32_t i = 0; i < nj && e == hipSuccess; ++i) {
+        if (hn[i] <= kRiskLdsKeys) continue;
+        e = launch_sort_desc_keys(sv->slots[size_t(i)].ylt, hn[i], sv->ws, sv->stream);
+        if (e == hipSuccess) e = launch_risk(sv->ws, hn[i], &hk[size_t(i) * nr], nr, sv->d_res + size_t(i) * 2 * nr, sv->stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(sv->h_res, sv->d_res, sizeof(double) * 2 * size_t(nr) * nj, hipMemcpyDeviceToHost, sv->stream);
+    if (e != hipSuccess) return hip_fail(pc, e, "server iteration");
+    ara_status s = sync_and_check(pc);
+    if (s != ARA_OK) return s;
+    for (int32_t i = 0; i < nj; ++i) {
+        ServerRequest *r = reqs[size_t(i)];
+        r->pml.assign(sv->h_res + size_t(i) * 2 * nr, sv->h_res + size_t(i) * 2 * nr + nr);
+        r->tvar.assign(sv->h_res + size_t(i) * 2 * nr + nr, sv->h_res + size_t(i) * 2 * nr + 2 * nr);
+    }
+    return ARA_OK;
+}
+
+static void server_loop(ara_server *sv) {
+    (void)hipSetDevice(sv->pc->device);
+    for (;;) {
+        std::vector<std::pair<uint64_t, ServerRequest *>> take;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_work.wait(lk, [&] { return sv->stopping || !sv->queue.empty(); });
+            if (sv->queue.empty()) return;   // stopping, nothing left
+            while (!sv->queue.empty() && take.size() < sv->slots.size()) {
+                take.push_back(sv->queue.front());
+                sv->queue.pop_front();
+            }
+        }
+        std::vector<ServerRequest *> reqs;
+        for (auto &p : take) reqs.push_back(p.second);
+        const ara_status s = server_iteration(sv, reqs);
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            const auto now = std::chrono::steady_clock::now();
+            for (ServerRequest *r : reqs) {
+                r->status = s;
+                r->done = true;
+                r->finished = now;
+            }
+            sv->iterations++;
+            sv->completed += int64_t(reqs.size());
+            sv->max_seen = std::max(sv->max_seen, int32_t(reqs.size()));
+        }
+        sv->cv_done.notify_all();
+    }
+}
+
+static void server_free(ara_server *sv) {
+    for (ServerSlot &sl : sv->slots) {
+        if (sl.L) ara_layer_release(sl.L);
+        dev_free(sl.ylt);
+    }
+    dev_free(sv->d_jobs);
+    dev_free(sv->d_items);
+    dev_free(sv->d_ylts);
+    dev_free(sv->d_ns);
+    dev_free(sv->d_ks);
+    dev_free(sv->d_res);
+    dev_free(sv->ws);
+    if (sv->h_jobs) (void)hipHostFree(sv->h_jobs);
+    if (sv->h_items) (void)hipHostFree(sv->h_items);
+    if (sv->h_descs) (void)hipHostFree(sv->h_descs);
+    if (sv->h_nks) (void)hipHostFree(sv->h_nks);
+    if (sv->h_res) (void)hipHostFree(sv->h_res);
+    if (sv->pc) (void)ara_ctx_destroy(sv->pc);
+    if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    for (auto &p : sv->live) delete p.second;
+    delete sv;
+}
+
+extern "C" ara_status ara_server_create(ara_ctx *c, const ara_yet *y, ara_elt *const *pool, int32_t n_pool,
+                                       const ara_server_config *cfg, ara_server **out) {
+    if (!c || !out || !y || !cfg || !pool || n_pool < 1 || y->ctx != c) return ARA_E_INVALID_ARG;
+    *out = nullptr;
+    if (cfg->max_batch < 1 || cfg->n_rp < 1 || cfg->n_rp > 16 || !cfg->return_periods || cfg->memory_budget < 0)
+        return fail(c, ARA_E_INVALID_ARG, "server: bad configuration");
+    if (y->n_trials < 1) return fail(c, ARA_E_EMPTY, "server: the YET has no trials");
+    for (int32_t r = 0; r < cfg->n_rp; ++r) {
+        int64_t k = 0;
+        if (ara_return_period_rank(1, cfg->return_periods[r], &k) != ARA_OK)
+            return fail(c, ARA_E_INVALID_ARG, "server: return period %g invalid", cfg->return_periods[r]);
+    }
+    for (int32_t j = 0; j < n_pool; ++j)
+        if (!pool[j] || pool[j]->ctx != c || pool[j]->catalog != y->catalog)
+            return fail(c, ARA_E_INVALID_ARG, "server: pool ELT %d is NULL, of another context or catalog", j);
+    HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    // slots the budget allows: tables + descriptors + YLT per slot
+    const int32_t C = y->catalog;
+    const int32_t nblk = bitmap_blocks(C);
+    const int64_t slot_bytes = int64_t(C) * 8 * 3 + int64_t(nblk) * 24 + int64_t(n_pool) * int64_t(sizeof(EltDesc)) +
+                               y->n_trials * 8;
+    int64_t budget = cfg->memory_budget;
+    if (budget == 0) {
+        size_t fr = 0, tot = 0;
+        HIP_OR_RETURN(c, hipMemGetInfo(&fr, &tot), "memory info");
+        budget = int64_t(fr / 4);
+    }
+    const int32_t n_slots = int32_t(std::min<int64_t>(cfg->max_batch, budget / std::max<int64_t>(1, slot_bytes)));
+    if (n_slots < 1) return fail(c, ARA_E_OOM, "server: one slot needs %lld bytes, budget %lld", (long long)slot_bytes,
+                                 (long long)budget);
+    ara_server *sv = new (std::nothrow) ara_server();
+    if (!sv) return ARA_E_OOM;
+    sv->ctx = c;
+    sv->yet = y;
+    sv->pool.assign(pool, pool + n_pool);
+    sv->rps.assign(cfg->return_periods, cfg->return_periods + cfg->n_rp);
+    ara_status s = ARA_OK;
+    hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) s = hip_fail(c, e, "server stream");
+    if (s == ARA_OK) {
+        s = ara_ctx_create(c->device, sv->stream, &sv->pc);
+        if (s != ARA_OK) s = fail(c, s, "server context: %s", ara_last_error(nullptr));
+    }
+    if (s == ARA_OK) {
+        sv->pc->placement = c->placement;
+        sv->pc->block_threads = c->block_threads;
+        sv->pc->grid_per_cu = c->grid_per_cu;
+        sv->pc->trial_mode = c->trial_mode;
+        sv->pc->yet_packing = c->yet_packing;
+    }
+    const ara_layer_terms none{0.0, INFINITY, 0.0, INFINITY};
+    sv->slots.resize(size_t(n_slots));
+    for (int32_t i = 0; i < n_slots && s == ARA_OK; ++i) {
+        s = ara_layer_create(c, pool, n_pool, C, &none, &sv->slots[size_t(i)].L);
+        if (s == ARA_OK) s = dev_alloc(c, &sv->slots[size_t(i)].ylt, size_t(y->n_trials) * 8, "server ylt");
+    }
+    if (s == ARA_OK) (void)hipStreamSynchronize(c->stream);   // the slot layers' first builds
+    // a worst case of work items: every slot with the YET's longest possible range
+    const int64_t per_slot_items = y->n_trials / 16 + 2;
+    sv->item_cap = int32_t(std::min<int64_t>(int64_t(n_slots) * per_slot_items, int64_t(1) << 30));
+    if (s == ARA_OK) s = dev_alloc(c, &sv->d_jobs, sizeof(BatchJob) * size_t(n_slots), "server jobs");
+    if (s == ARA_OK) s = dev_alloc(c, &sv->d_items, sizeof(BatchItem) * size_t(sv->item_cap), "server items");
+    if (s == ARA_OK) s = dev_alloc(c, &sv->d_ylts, sizeof(double *) * size_t(n_slots), "server ylt list");
+    if (s == ARA_OK) s = dev_alloc(c, &sv->d_ns, 8 * size_t(n_slots), "server sizes");
+    if (s == ARA_OK) s = dev_alloc(c, &sv->d_ks, 8 * size_t(n_slots) * size_t(cfg->n_rp), "server ranks");
+    if (s == ARA_OK) s = dev_alloc(c, &sv->d_res, 16 * size_t(n_slots) * size_t(cfg->n_rp), "server results");
+    if (s == ARA_OK) s = dev_alloc(c, &sv->ws, sort_workspace_bytes(y->n_trials), "server sort workspace");
+    if (s == ARA_OK) {
+        e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_jobs), sizeof(BatchJob) * size_t(n_slots), hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_items), sizeof(BatchItem) * size_t(sv->item_cap),
+                              hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_descs), sizeof(EltDesc) * size_t(n_slots) * size_t(n_pool),
+                              hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_nks), 8 * size_t(n_slots) * size_t(1 + cfg->n_rp),
+                              hipHostMallocDefault);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_res), 16 * size_t(n_slots) * size_t(cfg->n_rp),
+                              hipHostMallocDefault);
+        if (e != hipSuccess) s = hip_fail(c, e, "server pinned staging");
+    }
+    if (s == ARA_OK) {
+        std::vector<const double *> yp(static_cast<size_t>(n_slots));
+        for (int32_t i = 0; i < n_slots; ++i) yp[size_t(i)] = sv->slots[size_t(i)].ylt;
+        e = hipMemcpy(sv->d_ylts, yp.data(), sizeof(double *) * size_t(n_slots), hipMemcpyHostToDevice);
+        if (e != hipSuccess) s = hip_fail(c, e, "server ylt list");
+    }
+    if (s != ARA_OK) {
+        server_free(sv);
+        return s;
+    }
+    try {
+        sv->worker = std::thread(server_loop, sv);
+    } catch (...) {
+        server_free(sv);
+        return fail(c, ARA_E_OOM, "server: cannot start the worker thread");
+    }
+    c->live++;
+    *out = sv;
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_server_submit(ara_server *sv, const int32_t *idx, int32_t n_elts, const ara_layer_terms *terms,
+                                       int64_t t0, int64_t t1, uint64_t *ticket) {
+    if (!sv || !ticket || n_elts < 1 || !idx) return ARA_E_INVALID_ARG;
+    if (n_elts > int32_t(sv->pool.size())) return ARA_E_INVALID_ARG;
+    for (int32_t k = 0; k < n_elts; ++k)
+        if (idx[k] < 0 || idx[k] >= int32_t(sv->pool.size())) return ARA_E_INVALID_ARG;
+    if (ara_check_layer_terms(terms) != ARA_OK) return ARA_E_BAD_TERMS;
+    if (t0 < 0 || t1 <= t0 || t1 > sv->yet->n_trials) return ARA_E_INVALID_ARG;
+    ServerRequest *r = new (std::nothrow) ServerRequest();
+    if (!r) return ARA_E_OOM;
+    r->elts.assign(idx, idx + n_elts);
+    r->terms = *terms;
+    r->t0 = t0;
+    r->t1 = t1;
+    r->submitted = std::chrono::steady_clock::now();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        if (sv->stopping) {
+            delete r;
+            return ARA_E_BUSY;
+        }
+        *ticket = sv->next_ticket++;
+        sv->live[*ticket] = r;
+        sv->queue.emplace_back(*ticket, r);
+    }
+    sv->cv_work.notify_one();
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_server_wait(ara_server *sv, uint64_t ticket, double *pml, double *tvar, double *seconds) {
+    if (!sv) return ARA_E_INVALID_ARG;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto it = sv->live.find(ticket);
+    if (it == sv->live.end()) return ARA_E_INVALID_ARG;
+    ServerRequest *r = it->second;
+    sv->cv_done.wait(lk, [&] { return r->done; });
+    sv->live.erase(it);
+    lk.unlock();
+    const ara_status s = r->status;
+    if (s == ARA_OK) {
+        if (pml) std::copy(r->pml.begin(), r->pml.end(), pml);
+        if (tvar) std::copy(r->tvar.begin(), r->tvar.end(), tvar);
+    }
+    if (seconds) *seconds = std::chrono::duration<double>(r->finished - r->submitted).count();
+    delete r;
+    return s;
+}
+
+extern "C" ara_status ara_server_stats(ara_server *sv, int64_t *iterations, int64_t *completed, int32_t *max_in_iteration,
+                                      int32_t *slots) {
+    if (!sv) return ARA_E_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (iterations) *iterations = sv->iterations;
+    if (completed) *completed = sv->completed;
+    if (max_in_iteration) *max_in_iteration = sv->max_seen;
+    if (slots) *slots = int32_t(sv->slots.size());
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_server_release(ara_server *sv) {
+    if (!sv) return ARA_E_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stopping = true;
+    }
+    sv->cv_work.notify_all();
+    if (sv->worker.joinable()) sv->worker.join();
+    ara_ctx *c = sv->ctx;
+    (void)hipSetDevice(c->device);
+    server_free(sv);
+    c->live--;
+    return ARA_OK;
 }

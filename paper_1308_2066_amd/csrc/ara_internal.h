@@ -109,12 +109,43 @@ struct TrialLaunch {
     int grid;           // workgroups
     size_t lds_bytes;
     int qcap;           // per-wave queue capacity (bitmap placement)
+    bool lane;          // one lane per trial (short trials, dense tables) instead of one wave
 };
+
+// Trials with at most this many occurrences on average go one per lane (dense tables).
+constexpr int kLaneModeMaxMean = 256;
 hipError_t launch_trial_ylt(const TrialArgs &a, const TrialLaunch &l, hipStream_t s);
 hipError_t launch_trial_events(const TrialArgs &a, bool f32, int grid, hipStream_t s);
 hipError_t launch_lookup(const TrialArgs &a, const TrialLaunch &l, const int32_t *ids, int64_t n, double *gross,
                          double *occ, hipStream_t s);
 hipError_t prepare_trial_kernels();
+
+// ---- batched analyses: jobs (a trial kernel's arguments + how they run) and work
+// items (a job's trial range), processed by one persistent launch
+enum BatchMode : int32_t {
+    kModeLaneLds = 0,      // lane per trial, dense table in LDS
+    kModeLaneGlobal = 1,   // lane per trial, dense table in HBM/L2
+    kModeWaveLds = 2,      // wave per trial, dense table in LDS
+    kModeWaveGlobal = 3,   // wave per trial, dense table in HBM/L2
+    kModeWaveBitmap = 4,   // wave per trial, LDS filter, int32 IDs
+    kModeWaveBitmap24 = 5  // wave per trial, LDS filter, packed IDs
+};
+struct BatchJob {
+    TrialArgs a;           // t_begin/t_end/ylt: the job's whole range
+    int32_t mode;          // BatchMode
+    int32_t placement;     // ara_placement of the table
+};
+struct BatchItem {
+    int32_t job;
+    int32_t pad_;
+    int64_t t0, t1;        // trials [t0, t1) of the job's YET
+};
+hipError_t launch_batch(const BatchJob *jobs, const BatchItem *items, int32_t n_items, int32_t per_wg, int grid,
+                        hipStream_t s);
+int32_t batch_mode(const TrialLaunch &l, bool packed);
+constexpr int kRiskLdsKeys = 16384;   // YLTs up to this length are sorted in one workgroup's LDS
+hipError_t launch_risk_batch(const double *const *ylts, const int64_t *ns, const int64_t *ks, int n_jobs, int n_k,
+                             double *out, hipStream_t s);
 // bitmap placement (static LDS: filter tables up to trial_bitmap_table_capacity() bytes + event queues)
 hipError_t launch_trial_ylt_bitmap(const TrialArgs &a, int grid, int block, hipStream_t s);
 size_t trial_bitmap_table_capacity();

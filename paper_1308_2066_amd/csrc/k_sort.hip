@@ -350,4 +350,84 @@ hipError_t launch_risk(const void *ws, int64_t n, const int64_t *ks, int n_k, do
     return hipSuccess;
 }
 
+// ---------------------------------------------------------------------------------
+// Batched risk measures of many small YLTs (n <= kRiskLdsKeys each): one workgroup
+// per YLT sorts its keys in LDS (bitonic network; the array is padded to a power of
+// two with the largest key, which sorts last) and then forms PML and TVaR from the
+// sorted keys with exactly the chunks and sums of k_risk_part/k_risk_final, so the
+// results equal those of ara_risk_measures on the same YLT bit for bit.
+__device__ __forceinline__ double sum256(double s, double *part) {
+    // the 256-thread tree of block_sum, threads >= 256 only keep the barriers
+    if (threadIdx.x < 256) part[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = 128; o >= 1; o >>= 1) {
+        if (int(threadIdx.x) < o) part[threadIdx.x] += part[threadIdx.x + o];
+        __syncthreads();
+    }
+    const double r = part[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__restrict__ ylts,
+                                                     const int64_t *__restrict__ ns, const int64_t *__restrict__ ks,
+                                                     int n_k, double *__restrict__ out) {
+    __shared__ uint64_t key[kRiskLdsKeys];
+    __shared__ double part[256];
+    __shared__ double chunk_sum[2];
+    const int j = blockIdx.x;
+    if (ns[j] < 1 || ns[j] > kRiskLdsKeys) return;   // longer YLTs take the radix sort
+    const int n = int(ns[j]);
+    const double *y = ylts[j];
+    int np = 1;
+    while (np < n) np <<= 1;
+    for (int i = threadIdx.x; i < np; i += blockDim.x) key[i] = i < n ? desc_key(y[i]) : ~0ull;
+    __syncthreads();
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int h = k >> 1; h > 0; h >>= 1) {
+            for (int i = threadIdx.x; i < np; i += blockDim.x) {
+                const int p = i ^ h;
+                if (p > i) {
+                    const uint64_t a = key[i], b = key[p];
+                    if ((a > b) == ((i & k) == 0)) {
+                        key[i] = b;
+                        key[p] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int r = 0; r < n_k; ++r) {
+        const int64_t k = ks[int64_t(j) * n_k + r];
+        int64_t chunk = (k + kRiskMaxBlocks - 1) / kRiskMaxBlocks;
+        chunk = chunk < kRiskChunk ? kRiskChunk : chunk;
+        const int nb = int((k + chunk - 1) / chunk);   // <= 2 here
+        for (int b = 0; b < nb; ++b) {
+            const int64_t lo = b * chunk, hi = lo + chunk < k ? lo + chunk : k;
+            double s = 0.0;
+            if (threadIdx.x < 256)
+                for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += key_value(key[i]);
+            s = sum256(s, part);
+            if (threadIdx.x == 0) chunk_sum[b] = s;
+            __syncthreads();
+        }
+        double s = 0.0;
+        if (threadIdx.x < 256)
+            for (int b = threadIdx.x; b < nb; b += 256) s += chunk_sum[b];
+        s = sum256(s, part);
+        if (threadIdx.x == 0) {
+            out[int64_t(j) * 2 * n_k + r] = key_value(key[k - 1]);
+            out[int64_t(j) * 2 * n_k + n_k + r] = s / double(k);
+        }
+    }
+}
+
+hipError_t launch_risk_batch(const double *const *ylts, const int64_t *ns, const int64_t *ks, int n_jobs, int n_k,
+                             double *out, hipStream_t s) {
+    if (n_jobs <= 0 || n_k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_risk_batch, dim3(unsigned(n_jobs)), dim3(1024), 0, s, ylts, ns, ks, n_k, out);
+    return hipGetLastError();
+}
+
 }  // namespace ara

@@ -7,6 +7,7 @@ namespace ara {
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x3 __attribute__((ext_vector_type(3)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kChunk = 256;               // events per wave-wide 16-byte load (64 lanes x 4)
 constexpr int kNch = 4;                   // loads per segment

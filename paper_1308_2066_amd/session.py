@@ -52,3 +52,36 @@ def open_analysis(ctx: ara.Ctx, event_ids: np.ndarray, trial_offsets: np.ndarray
                                           terms=t, precision=precision))
     layer = ara.ara_layer_create(ctx, handles, catalog_size, layer_terms)
     return Analysis(ctx, yet, handles, layer, yet.n_trials, yet.n_events)
+
+
+@dataclasses.dataclass
+class PortfolioHandles:
+    ctx: ara.Ctx
+    yet: ara.Yet
+    pool: List[ara.Elt]
+    layers: List[ara.Layer]
+
+    def release(self):
+        for layer in self.layers:
+            if layer.ptr:
+                ara.ara_layer_release(layer)
+        for e in self.pool:
+            if e.ptr:
+                ara.ara_elt_release(e)
+        if self.yet.ptr:
+            ara.ara_yet_release(self.yet)
+
+
+def open_portfolio(ctx: ara.Ctx, event_ids: np.ndarray, trial_offsets: np.ndarray, catalog_size: int,
+                   pool: Sequence[Tuple[np.ndarray, np.ndarray]],
+                   layers: Sequence[Tuple[Sequence[int], Sequence[float]]],
+                   precision: int = ara.ARA_F32) -> PortfolioHandles:
+    """Creates one YET, the ELTs of a pool and layers that each take some of them
+    (pool indices, layer terms)."""
+    yet = ara.ara_yet_create(ctx, to_device(np.asarray(event_ids, np.int32), ctx.device),
+                             to_device(np.asarray(trial_offsets, np.int64), ctx.device), catalog_size)
+    elts = [ara.ara_elt_create(ctx, to_device(np.asarray(ids, np.int32), ctx.device),
+                               to_device(np.asarray(losses, np.float64), ctx.device), catalog_size,
+                               precision=precision) for ids, losses in pool]
+    made = [ara.ara_layer_create(ctx, [elts[i] for i in idx], catalog_size, terms) for idx, terms in layers]
+    return PortfolioHandles(ctx, yet, elts, made)

@@ -32,7 +32,7 @@ import numpy as np
 SEED_BASE = 13082066
 
 __all__ = [
-    "SEED_BASE", "Workload", "uniform_ids", "yet_poisson", "yet_fixed", "yet_fixed_block",
+    "SEED_BASE", "Workload", "Portfolio", "portfolio_batched", "uniform_ids", "yet_poisson", "yet_fixed", "yet_fixed_block",
     "elt_sparse", "workload_plain_small", "workload_paper_scale", "random_tiny",
     "loguniform_terms",
 ]
@@ -177,6 +177,54 @@ def workload_paper_scale(seed: int = SEED_BASE + 1, n_trials: int = 1_000_000, p
     ids, offs = yet_fixed(seed, n_trials, per_trial, catalog)
     return Workload(f"paper-scale-{n_trials}x{per_trial}-{n_elts}elt-cat{catalog}", ids, offs, catalog, elts,
                     (1e5, 5e6, 1e6, 5e7), None, (10.0, 100.0, 250.0), seed)
+
+
+@dataclasses.dataclass
+class Portfolio:
+    """One YET analysed against many layers drawn from a shared pool of ELTs."""
+    name: str
+    event_ids: np.ndarray
+    trial_offsets: np.ndarray
+    catalog_size: int
+    pool: List[Tuple[np.ndarray, np.ndarray]]
+    layers: List[Tuple[List[int], Tuple[float, float, float, float]]]   # (pool indices, layer terms)
+    return_periods: Tuple[float, ...]
+    seed: int
+
+    @property
+    def n_trials(self) -> int:
+        return int(self.trial_offsets.shape[0] - 1)
+
+    @property
+    def n_events(self) -> int:
+        return int(self.event_ids.shape[0])
+
+    def layer_workload(self, j: int) -> Workload:
+        idx, terms = self.layers[j]
+        return Workload(f"{self.name}-layer{j}", self.event_ids, self.trial_offsets, self.catalog_size,
+                        [self.pool[i] for i in idx], terms, None, self.return_periods, self.seed)
+
+
+def portfolio_batched(seed: int = SEED_BASE + 2, n_layers: int = 64, pool_size: int = 256,
+                      max_elts: int = 32) -> Portfolio:
+    """Batched portfolio: the plain small YET (10,000 trials, Poisson(100) events,
+    10,000-event catalog) shared by n_layers layers; each layer takes U{1..max_elts}
+    distinct ELTs of a pool of pool_size ELTs that are dense over the catalog (every
+    event has a loss) with lognormal(11, 2.5) losses; each layer's occurrence and
+    aggregate (retention, limit) pairs are log-uniform on [1e4, 1e8], the smaller
+    value being the retention."""
+    base = workload_plain_small()
+    rng = np.random.default_rng([seed, 0xC3])
+    C = base.catalog_size
+    all_ids = np.arange(C, dtype=np.int32)
+    pool = [(all_ids, rng.lognormal(11.0, 2.5, size=C)) for _ in range(pool_size)]
+    layers = []
+    for _ in range(n_layers):
+        k = int(rng.integers(1, max_elts + 1))
+        idx = sorted(int(i) for i in rng.choice(pool_size, size=k, replace=False))
+        layers.append((idx, loguniform_terms(rng)))
+    return Portfolio(f"portfolio-{n_layers}x-pool{pool_size}", base.event_ids, base.trial_offsets, C, pool, layers,
+                     base.return_periods, seed)
 
 
 def random_tiny(rng: np.random.Generator, catalog_max: int = 8, elts_max: int = 6, trials_max: int = 8,

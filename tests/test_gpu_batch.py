@@ -1,0 +1,180 @@
+"""Batched analyses on the GPU: every job of a batch gives exactly the YLT of the
+plain single-analysis launch (same device code, same order of additions), graph
+replays repeat it, batched PML/TVaR equal ara_risk_measures, and the batched
+portfolio matches the oracle within the binary32-table bound."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A(ara_lib):
+    return ara_lib
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1308_2066_amd import session
+    return session
+
+
+def _plain(A, ctx, yet, layer, t0, t1):
+    import torch
+    y = torch.empty(max(t1 - t0, 1), dtype=torch.float64, device="cuda")
+    if t1 > t0:
+        A.ara_analyze(ctx, yet, layer, t0, t1, y)
+    A.ara_sync(ctx)
+    return y[: t1 - t0].cpu().numpy()
+
+
+def _edge(rng, lengths, catalog=5000, n_elts=3):
+    counts = np.asarray(lengths, np.int64)
+    offs = np.zeros(len(counts) + 1, np.int64)
+    np.cumsum(counts, out=offs[1:])
+    ids = rng.integers(0, catalog, size=int(offs[-1])).astype(np.int32)
+    elts = [synth.elt_sparse(rng, catalog // 3, catalog, 10.0, 2.0) for _ in range(n_elts)]
+    return synth.Workload("edge", ids, offs, catalog, elts, (5e4, 1e6, 2e5, math.inf), None, (2.0, 10.0), 0)
+
+
+def test_batch_equals_plain_launches(A, S, gpu_ctx):
+    """Jobs of three shapes in one batch: short trials over a 10k catalog (lane per
+    trial, LDS table), long trials over a 1M catalog (LDS filter, packed IDs), and
+    ragged trial lengths over a 5k catalog; whole and partial trial ranges."""
+    import torch
+    rng = np.random.default_rng(5)
+    small = synth.workload_plain_small()
+    paper = synth.workload_paper_scale(n_trials=20_000)
+    edge = _edge(rng, list(rng.integers(0, 3000, size=300)) + [0, 1, 4099, 1023, 1025])
+    layers, elts, yets = [], [], []
+
+    def track(an, own_yet=True):
+        layers.append(an.layer)
+        elts.extend(an.elts)
+        if own_yet:
+            yets.append(an.yet)
+        return an
+
+    try:
+        an_s = track(S.open_analysis(gpu_ctx, small.event_ids, small.trial_offsets, small.catalog_size, small.elts,
+                                     small.layer_terms))
+        # a second layer on the same YET: uncapped aggregate terms
+        an_s2 = track(S.open_analysis(gpu_ctx, None, None, small.catalog_size, small.elts,
+                                      (5e4, 1e6, 1e5, math.inf), yet=an_s.yet), own_yet=False)
+        an_p = track(S.open_analysis(gpu_ctx, paper.event_ids, paper.trial_offsets, paper.catalog_size, paper.elts,
+                                     (1e5, 5e6, 1.5e8, math.inf)))
+        an_e = track(S.open_analysis(gpu_ctx, edge.event_ids, edge.trial_offsets, edge.catalog_size, edge.elts,
+                                     edge.layer_terms))
+        specs = [(an_s.yet, an_s.layer, 0, small.n_trials), (an_s.yet, an_s2.layer, 0, small.n_trials),
+                 (an_s.yet, an_s.layer, 123, 4567), (an_p.yet, an_p.layer, 0, paper.n_trials),
+                 (an_p.yet, an_p.layer, 17, 9001), (an_e.yet, an_e.layer, 0, edge.n_trials),
+                 (an_e.yet, an_e.layer, 290, 305)]
+        want = [_plain(A, gpu_ctx, y, layer, t0, t1) for y, layer, t0, t1 in specs]
+        outs = [torch.full((max(t1 - t0, 1),), math.nan, dtype=torch.float64, device="cuda")
+                for _, _, t0, t1 in specs]
+        b = A.ara_batch_create(gpu_ctx, [(y, layer, t0, t1, o) for (y, layer, t0, t1), o in zip(specs, outs)])
+        try:
+            for rep in range(3):
+                _say(f"batch run {rep}")
+                for o in outs:
+                    o.fill_(math.nan)
+                A.ara_batch_run(b)
+                A.ara_sync(gpu_ctx)
+                for k, ((_, _, t0, t1), o) in enumerate(zip(specs, outs)):
+                    got = o[: t1 - t0].cpu().numpy()
+                    assert got.tobytes() == want[k].tobytes(), (rep, k)
+            n_items, grid, epi, graph = A.ara_batch_info(b)
+            assert graph == 1 and n_items >= len(specs) and grid >= 1 and epi > 0
+            rps = [1.0, 2.0, 10.0, 100.0, 250.0]
+            pml, tvar = A.ara_batch_risk(b, rps)
+            for k, (_, _, t0, t1) in enumerate(specs):
+                p1, v1 = A.ara_risk_measures(gpu_ctx, torch.from_numpy(want[k]).cuda(), rps)
+                assert pml[k].tobytes() == np.asarray(p1).tobytes(), k
+                assert tvar[k].tobytes() == np.asarray(v1).tobytes(), k
+        finally:
+            A.ara_batch_release(b)
+    finally:
+        for layer in layers:
+            A.ara_layer_release(layer)
+        for e in elts:
+            A.ara_elt_release(e)
+        for y in yets:
+            A.ara_yet_release(y)
+
+
+def test_batch_rejects_bad_jobs(A, S, gpu_ctx):
+    import torch
+    small = synth.workload_plain_small()
+    an = S.open_analysis(gpu_ctx, small.event_ids, small.trial_offsets, small.catalog_size, small.elts,
+                         small.layer_terms)
+    other = S.open_analysis(gpu_ctx, small.event_ids[:10], np.array([0, 10], np.int64), 20_000,
+                            [(np.array([1, 2], np.int32), np.array([3.0, 4.0]))], small.layer_terms)
+    try:
+        y = torch.empty(small.n_trials, dtype=torch.float64, device="cuda")
+        with pytest.raises(A.AraError) as e:
+            A.ara_batch_create(gpu_ctx, [(an.yet, other.layer, 0, 10, y)])      # catalogs differ
+        assert e.value.status == A.ARA_E_INVALID_ARG
+        with pytest.raises(A.AraError) as e:
+            A.ara_batch_create(gpu_ctx, [(an.yet, an.layer, 5, small.n_trials + 1, y)])
+        assert e.value.status == A.ARA_E_INVALID_ARG
+        b = A.ara_batch_create(gpu_ctx, [(an.yet, an.layer, 7, 7, y)])
+        try:
+            A.ara_batch_run(b)
+            with pytest.raises(A.AraError) as e:
+                A.ara_batch_risk(b, [10.0])
+            assert e.value.status == A.ARA_E_EMPTY
+        finally:
+            A.ara_batch_release(b)
+        b = A.ara_batch_create(gpu_ctx, [])
+        A.ara_batch_run(b)
+        A.ara_batch_release(b)
+    finally:
+        an.release()
+        other.release()
+
+
+def test_batched_portfolio_matches_oracle(A, S, gpu_ctx):
+    """The batched portfolio (one YET, 64 layers of 1-32 ELTs from a 256-ELT pool,
+    binary32 tables): every layer's YLT within the binary32 bound of the FP64 oracle
+    and equal to its plain launch."""
+    import torch
+    pf = synth.portfolio_batched()
+    h = S.open_portfolio(gpu_ctx, pf.event_ids, pf.trial_offsets, pf.catalog_size, pf.pool, pf.layers)
+    try:
+        outs = [torch.empty(pf.n_trials, dtype=torch.float64, device="cuda") for _ in pf.layers]
+        b = A.ara_batch_create(gpu_ctx, [(h.yet, layer, 0, pf.n_trials, o) for layer, o in zip(h.layers, outs)])
+        try:
+            A.ara_batch_run(b)
+            A.ara_batch_run(b)
+            A.ara_sync(gpu_ctx)
+            pml, tvar = A.ara_batch_risk(b, pf.return_periods)
+        finally:
+            A.ara_batch_release(b)
+        threads = oracle.max_threads()
+        for j in range(len(pf.layers)):
+            _say(f"portfolio layer {j}")
+            got = outs[j].cpu().numpy()
+            assert got.tobytes() == _plain(A, gpu_ctx, h.yet, h.layers[j], 0, pf.n_trials).tobytes(), j
+            w = pf.layer_workload(j)
+            ref = oracle.analyze_workload(w, threads=threads)
+            gross = ref["gross_total"]
+            tol = 2.0 ** -23 * 1.0001 * gross + 1e-12 * np.maximum(np.abs(ref["ylt"]), ref["occ_total"])
+            assert np.all(np.abs(got - ref["ylt"]) <= tol), j
+            ranks = [A.ara_return_period_rank(pf.n_trials, rp) for rp in pf.return_periods]
+            srt = np.sort(got)[::-1]
+            assert pml[j].tolist() == [srt[k - 1] for k in ranks]
+    finally:
+        h.release()

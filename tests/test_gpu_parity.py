@@ -51,9 +51,10 @@ def S():
 
 
 def analyze(A, S, ctx, w, placement=0, precision=0, t0=0, t1=None, terms=None, block=0, grid_per_cu=0,
-            packing=1):
+            packing=1, mode=0):
     import torch
     A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, placement)
+    A.ara_set_option(ctx, A.ARA_OPT_TRIAL_MODE, mode)
     A.ara_set_option(ctx, A.ARA_OPT_BLOCK_THREADS, block)
     A.ara_set_option(ctx, A.ARA_OPT_GRID_PER_CU, grid_per_cu)
     A.ara_set_option(ctx, A.ARA_OPT_YET_PACKING, packing)
@@ -74,6 +75,7 @@ def analyze(A, S, ctx, w, placement=0, precision=0, t0=0, t1=None, terms=None, b
         A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, 0)
         A.ara_set_option(ctx, A.ARA_OPT_BLOCK_THREADS, 0)
         A.ara_set_option(ctx, A.ARA_OPT_GRID_PER_CU, 0)
+        A.ara_set_option(ctx, A.ARA_OPT_TRIAL_MODE, 0)
 
 
 def analyze_events(A, S, ctx, w, placement=0, precision=0):
@@ -194,6 +196,24 @@ def test_plain_small_ylt(A, S, gpu_ctx, small, placement):
     assert_ylt_close(got, ref, what="plain small")
     got32 = analyze(A, S, gpu_ctx, small, placement, packing=0)
     assert got32.tobytes() == got.tobytes()   # same events, same summation order
+
+
+@pytest.mark.parametrize("placement", [2, 3])
+def test_lane_per_trial_is_the_sequential_sum(A, S, gpu_ctx, small, placement):
+    """A lane adds its trial's occurrence-net values in time order from +0.0, exactly
+    the oracle's cumulative total: the YLT equals the oracle's f(P_k) bit for bit.
+    The wave-per-trial form sums in another order (within tolerance)."""
+    rng = np.random.default_rng(77)
+    edge = _edge_workload(rng, [0, 1, 3, 4, 5, 255, 256, 257, 1023, 1025, 2049, 0, 7, 4099, 1, 2])
+    for w, name in [(small, "plain small"), (edge, "edge lengths")]:
+        _say(f"lane mode {name} placement={placement}")
+        ref = oracle.analyze_workload(w, threads=oracle.max_threads())
+        lane = analyze(A, S, gpu_ctx, w, placement, mode=2)
+        assert lane.tobytes() == ref["ylt_closed"].tobytes(), name
+        wave = analyze(A, S, gpu_ctx, w, placement, mode=1)
+        assert_ylt_close(wave, ref, what=name)
+        for block in (256, 1024):
+            assert analyze(A, S, gpu_ctx, w, placement, mode=2, block=block).tobytes() == lane.tobytes()
 
 
 def _catalog_lookup_reference(w, precision_f32=False):
