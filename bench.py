@@ -42,8 +42,8 @@ HBM_PEAK_GBS = 8000.0
 TRIAL_KERNEL = "k_trial_ylt_bitmap"
 # Sources that define the headline trial kernel; recorded counter readings stand
 # only while these are unchanged.
-TRIAL_KERNEL_SOURCES = ("paper_1308_2066_amd/csrc/k_trial_bitmap.hip", "paper_1308_2066_amd/csrc/trial_common.h",
-                        "paper_1308_2066_amd/csrc/ara_internal.h")
+TRIAL_KERNEL_SOURCES = ("paper_1308_2066_amd/csrc/k_trial_bitmap.hip", "paper_1308_2066_amd/csrc/trial_bitmap.h",
+                        "paper_1308_2066_amd/csrc/trial_common.h", "paper_1308_2066_amd/csrc/ara_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trial_ylt_bitmap.paper_1Mx1000_f64.traffic.txt")
 
 
@@ -295,13 +295,111 @@ def bench_portfolio(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_serving(args):
+    """Serving: a resident YET (10^6 trials of Poisson(100) events over a 10,000-event
+    catalog) and a 256-ELT pool; open-loop pricing requests (Poisson arrivals; U{1..32}
+    ELTs, log-uniform terms, 10^5-10^6 contiguous trials) answered with PML/TVaR.
+    Server: ara_server_submit at each arrival, latency = submission to completion as
+    the server measures it.  Plain: one thread takes requests in arrival order and
+    runs layer create + ara_analyze + ara_risk_measures + layer release; latency =
+    completion - arrival.  Same requests, same results."""
+    import threading
+    import torch
+    import synth
+    from paper_1308_2066_amd import ara, session
+
+    pf = synth.portfolio_batched(n_layers=1)
+    ids, offs, C = synth.serving_yet()
+    rps = list(pf.return_periods)
+    torch.cuda.set_device(0)
+    ctx = ara.ara_ctx_create(0, torch.cuda.current_stream())
+    h = session.open_portfolio(ctx, ids, offs, C, pf.pool, [])
+    n_trials = int(offs.shape[0] - 1)
+    ws = torch.empty(ara.ara_sort_workspace_size(n_trials), dtype=torch.uint8, device="cuda")
+    ylt = torch.empty(n_trials, dtype=torch.float64, device="cuda")
+    lines = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        reqs = synth.serving_requests(args.requests, n_trials, rate=rate)
+        # server
+        srv = ara.ara_server_create(ctx, h.yet, h.pool, rps, max_batch=32)
+        warm = [ara.ara_server_submit(srv, r[1], r[2], r[3], r[4]) for r in reqs[:8]]
+        for t in warm:
+            ara.ara_server_wait(srv, t)
+        tickets = [None] * len(reqs)
+        t_start = time.perf_counter()
+
+        def submitter():
+            for i, (at, idx, terms, t0, t1) in enumerate(reqs):
+                d = t_start + at - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = ara.ara_server_submit(srv, idx, terms, t0, t1)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        lat_s, res_s = [], []
+        for i in range(len(reqs)):
+            while tickets[i] is None:
+                time.sleep(0.0002)
+            pml, tvar, sec = ara.ara_server_wait(srv, tickets[i])
+            lat_s.append(sec)
+            res_s.append((pml, tvar))
+        th.join()
+        wall_s = time.perf_counter() - t_start
+        iters, done, most, slots = ara.ara_server_stats(srv)
+        ara.ara_server_release(srv)
+        # plain per-request launches, same arrival trace
+        lat_p, res_p = [], []
+        t_start = time.perf_counter()
+        for at, idx, terms, t0, t1 in reqs:
+            d = t_start + at - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            layer = ara.ara_layer_create(ctx, [h.pool[i] for i in idx], C, terms)
+            ara.ara_analyze(ctx, h.yet, layer, t0, t1, ylt[: t1 - t0])
+            pml, tvar = ara.ara_risk_measures(ctx, ylt[: t1 - t0], rps, ws)
+            ara.ara_layer_release(layer)
+            lat_p.append(time.perf_counter() - (t_start + at))
+            res_p.append((np.asarray(pml), np.asarray(tvar)))
+        wall_p = time.perf_counter() - t_start
+        same = all(a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
+                   for a, b in zip(res_s, res_p))
+        q = lambda v, p: float(np.percentile(np.asarray(v) * 1e3, p))
+        te = float(sum((r[4] - r[3]) for r in reqs)) * float(ids.shape[0]) / n_trials
+        log(f"serving rate {rate}/s: server p50 {q(lat_s, 50):.3f} ms p99 {q(lat_s, 99):.3f} ms "
+            f"({iters} iterations, max {most} per iteration, {slots} slots); plain p50 {q(lat_p, 50):.3f} ms "
+            f"p99 {q(lat_p, 99):.3f} ms; identical={same}")
+        lines.append({"rate_per_s": rate, "requests": len(reqs),
+                      "server": {"p50_ms": q(lat_s, 50), "p99_ms": q(lat_s, 99), "queries_per_s": len(reqs) / wall_s,
+                                 "iterations": iters, "max_per_iteration": most, "slots": slots},
+                      "plain": {"p50_ms": q(lat_p, 50), "p99_ms": q(lat_p, 99), "queries_per_s": len(reqs) / wall_p},
+                      "identical_results": bool(same), "trial_events_per_request": te / len(reqs)})
+    h.release()
+    ara.ara_ctx_destroy(ctx)
+    first = lines[0]
+    out = {
+        "metric": "p50/p99 quote latency (serving: 10^6-trial Poisson(100) YET, 256-ELT pool, 1-32 ELTs and "
+                  "10^5-10^6 trials per request)",
+        "value": first["server"]["p50_ms"], "unit": "ms", "n_gpus": 1, "steps": first["requests"], "warmup": 8,
+        "ms_per_step": first["server"]["p50_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64 arithmetic, f32 tables", "data": "synthetic",
+        "config": {"workload": "serving: resident YET of 10^6 trials (Poisson(100) events, catalog 10,000), 256 "
+                               "dense lognormal(11,2.5) ELTs, Poisson arrivals", "parallelism": "1 GPU"},
+        "rates": lines,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["paper", "small", "portfolio"], default="paper",
-                    help="portfolio: one YET x 64 layers, batched launch against per-layer launches")
+    ap.add_argument("--workload", choices=["paper", "small", "portfolio", "serving"], default="paper",
+                    help="portfolio: one YET x 64 layers, batched launch against per-layer launches; "
+                         "serving: pricing requests with Poisson arrivals, server against per-request launches")
+    ap.add_argument("--requests", type=int, default=600, help="serving: requests per rate")
+    ap.add_argument("--rates", default="50", help="serving: arrival rates per second, comma separated")
     ap.add_argument("--trials", type=int, default=1_000_000)
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
     ap.add_argument("--placement", type=int, default=0)
@@ -340,6 +438,8 @@ def main():
 
     if args.workload == "portfolio":
         return bench_portfolio(args)
+    if args.workload == "serving":
+        return bench_serving(args)
 
     t = time.time()
     if args.workload == "paper":

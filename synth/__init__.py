@@ -32,7 +32,7 @@ import numpy as np
 SEED_BASE = 13082066
 
 __all__ = [
-    "SEED_BASE", "Workload", "Portfolio", "portfolio_batched", "uniform_ids", "yet_poisson", "yet_fixed", "yet_fixed_block",
+    "SEED_BASE", "Workload", "Portfolio", "portfolio_batched", "serving_yet", "serving_requests", "uniform_ids", "yet_poisson", "yet_fixed", "yet_fixed_block",
     "elt_sparse", "workload_plain_small", "workload_paper_scale", "random_tiny",
     "loguniform_terms",
 ]
@@ -225,6 +225,48 @@ def portfolio_batched(seed: int = SEED_BASE + 2, n_layers: int = 64, pool_size: 
         layers.append((idx, loguniform_terms(rng)))
     return Portfolio(f"portfolio-{n_layers}x-pool{pool_size}", base.event_ids, base.trial_offsets, C, pool, layers,
                      base.return_periods, seed)
+
+
+def serving_yet(seed: int = SEED_BASE + 4, n_trials: int = 1_000_000):
+    """Resident YET of the serving workload: the plain small statistics (Poisson(100)
+    events per trial, IDs uniform over a 10,000-event catalog) at 10^6 trials.  With
+    iid uniform IDs, ordering a trial by iid uniform timestamps does not change the
+    distribution of its ID sequence, so the draw order is taken as the time order."""
+    rng = np.random.default_rng(seed)
+    counts = rng.poisson(100.0, size=n_trials).astype(np.int64)
+    offs = np.zeros(n_trials + 1, dtype=np.int64)
+    np.cumsum(counts, out=offs[1:])
+    n = int(offs[-1])
+    ids = np.empty(n, dtype=np.int32)
+    block = 1 << 22
+
+    def work(b):
+        lo = b * block
+        hi = min(n, lo + block)
+        ids[lo:hi] = uniform_ids(np.random.default_rng([seed, 0x5E, b]), hi - lo, 10_000)
+
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(work, range((n + block - 1) // block)))
+    return ids, offs, 10_000
+
+
+def serving_requests(n: int, n_trials: int, pool_size: int = 256, rate: float = 50.0, seed: int = SEED_BASE + 4,
+                     min_trials: int = 100_000, max_trials: int = 1_000_000):
+    """Pricing requests: Poisson arrivals at `rate` per second (times in seconds from
+    0); each takes U{1..32} distinct pool ELTs, log-uniform occurrence and aggregate
+    terms, and a contiguous range of U[min_trials, max_trials] trials with a uniform
+    start."""
+    rng = np.random.default_rng([seed, 0xC5])
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    out = []
+    for i in range(n):
+        k = int(rng.integers(1, 33))
+        idx = sorted(int(j) for j in rng.choice(pool_size, size=k, replace=False))
+        terms = loguniform_terms(rng)
+        length = int(rng.integers(min_trials, min(max_trials, n_trials) + 1))
+        t0 = int(rng.integers(0, n_trials - length + 1))
+        out.append((float(t[i]), idx, terms, t0, t0 + length))
+    return out
 
 
 def random_tiny(rng: np.random.Generator, catalog_max: int = 8, elts_max: int = 6, trials_max: int = 8,
