@@ -60,7 +60,7 @@ def _load():
             P = ctypes.c_void_p
             lib.oracle_analyze.restype = ctypes.c_int
             lib.oracle_analyze.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
-                                           P, P, P, P, ctypes.c_int, P, P, P, P, P, P, P, P, P, ctypes.c_int]
+                                           P, P, P, P, ctypes.c_int, P, P, P, P, P, P, P, P, P, P, ctypes.c_int]
             lib.oracle_rank.restype = ctypes.c_int64
             lib.oracle_rank.argtypes = [ctypes.c_int64, ctypes.c_double]
             lib.oracle_risk.restype = ctypes.c_int
@@ -89,7 +89,8 @@ def analyze(event_ids, trial_offsets, catalog_size: int, elts, layer_terms, elt_
     ``elts`` is a list of (ids int32, losses float64) pairs in the layer's order;
     ``elt_terms`` an optional list of (fx, retention, limit); ``layer_terms`` is
     (OccR, OccL, AggR, AggL).  Returns a dict with per-trial ``ylt``,
-    ``occ_total`` (P_k), ``gross_total`` and ``ylt_closed``; with ``per_event``
+    ``occ_total`` (P_k), ``gross_total``, ``ylt_closed`` and ``occ_max`` (the largest
+    occurrence-net loss); with ``per_event``
     also ``gross``, ``occ``, ``cum`` and ``ceded`` per occurrence.
     """
     lib = _load()
@@ -113,13 +114,14 @@ def analyze(event_ids, trial_offsets, catalog_size: int, elts, layer_terms, elt_
         et = np.ascontiguousarray(np.asarray(elt_terms, dtype=np.float64).reshape(n_elts, 3))
     lt = np.ascontiguousarray(np.asarray(layer_terms, dtype=np.float64).reshape(4))
     nt = t_end - t_begin
-    out = {k: np.empty(nt, dtype=np.float64) for k in ("ylt", "occ_total", "gross_total", "ylt_closed")}
+    out = {k: np.empty(nt, dtype=np.float64) for k in ("ylt", "occ_total", "gross_total", "ylt_closed", "occ_max")}
     nev = int(offs[t_end] - offs[t_begin]) if n_trials >= 0 and nt > 0 else 0
     ev = {k: (np.empty(nev, dtype=np.float64) if per_event else None) for k in ("gross", "occ", "cum", "ceded")}
     rc = lib.oracle_analyze(_ptr(ids), _ptr(offs), t_begin, t_end, int(catalog_size), n_elts, _ptr(eoff),
                             _ptr(pid), _ptr(plo), _ptr(et), 1 if dat_f32 else 0, _ptr(lt),
                             _ptr(out["ylt"]), _ptr(out["occ_total"]), _ptr(out["gross_total"]),
-                            _ptr(out["ylt_closed"]), _ptr(ev["gross"]), _ptr(ev["occ"]), _ptr(ev["cum"]),
+                            _ptr(out["ylt_closed"]), _ptr(out["occ_max"]), _ptr(ev["gross"]), _ptr(ev["occ"]),
+                            _ptr(ev["cum"]),
                             _ptr(ev["ceded"]), int(threads))
     if rc != 0:
         raise OracleError(rc)

@@ -113,6 +113,9 @@ static int build_dat(int32_t catalog, const int32_t *ids, const double *losses, 
  *   occ_total    P_k, the trial's sum of occurrence-net losses
  *   gross_total  G, the trial's sum of losses net of financial terms only
  *   ylt_closed   min(max(P_k - AggR, 0), AggL), the telescoped form of lr
+ *   occ_max      the trial's largest occurrence-net loss (0 for an empty trial): the
+ *                year's largest single occurrence after the occurrence terms, whose
+ *                distribution over trials is the occurrence exceedance curve
  * per-event outputs (length off[t_end] - off[t_begin], position relative to off[t_begin]; NULL to skip):
  *   ev_gross  loss of the occurrence summed over the layer's ELTs (after financial terms)
  *   ev_occ    after occurrence terms;  ev_cum  inclusive cumulative sum;  ev_ceded  ceded loss
@@ -121,7 +124,7 @@ int oracle_analyze(const int32_t *event_ids, const int64_t *trial_offsets, int64
                    int32_t catalog_size, int32_t n_elts, const int64_t *elt_offsets,
                    const int32_t *pair_ids, const double *pair_losses, const double *elt_terms,
                    int dat_f32, const double *layer_terms,
-                   double *ylt, double *occ_total, double *gross_total, double *ylt_closed,
+                   double *ylt, double *occ_total, double *gross_total, double *ylt_closed, double *occ_max,
                    double *ev_gross, double *ev_occ, double *ev_cum, double *ev_ceded, int n_threads) {
     if (!trial_offsets || !layer_terms || catalog_size < 1 || n_elts < 0 || t_begin < 0 || t_end < t_begin)
         return OR_E_INVALID_ARG;
@@ -217,6 +220,11 @@ int oracle_analyze(const int32_t *event_ids, const int64_t *trial_offsets, int64
                 if (occ_total) occ_total[r] = run;
                 if (gross_total) gross_total[r] = gsum;
                 if (ylt_closed) ylt_closed[r] = clamp_excess(run, AggR, AggL);
+                if (occ_max) {
+                    double m = 0.0;
+                    for (int64_t d = 0; d < k; ++d) m = lo[d] > m ? lo[d] : m;
+                    occ_max[r] = m;
+                }
                 if (ev_occ) for (int64_t d = 0; d < k; ++d) ev_occ[o - ev0 + d] = lo[d];
                 if (ev_cum) for (int64_t d = 0; d < k; ++d) ev_cum[o - ev0 + d] = P[d];
                 if (ev_ceded) for (int64_t d = 0; d < k; ++d) ev_ceded[o - ev0 + d] = c[d];

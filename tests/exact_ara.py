@@ -36,7 +36,8 @@ def excess(x: Fr, retention: Fr, limit: Optional[Fr]) -> Fr:
 
 def trial_exact(events: Sequence[int], elts: List[Dict[int, Fr]], elt_terms, layer_terms,
                 f32_losses: bool = False):
-    """Exact analysis of one trial.  Returns dict(lr, lr_closed, P, gross, occ, cum, ceded)."""
+    """Exact analysis of one trial.  Returns dict(lr, lr_closed, P, gross, occ, cum, ceded,
+    occ_max), occ_max being the largest occurrence-net loss (0 for an empty trial)."""
     occR, occL, aggR, aggL = (_q(layer_terms[0]), _q(layer_terms[1]), _q(layer_terms[2]), _q(layer_terms[3]))
     gross = []
     for e in events:
@@ -57,7 +58,8 @@ def trial_exact(events: Sequence[int], elts: List[Dict[int, Fr]], elt_terms, lay
     ceded = [F[i] - (F[i - 1] if i else Fr(0)) for i in range(len(F))]
     lr = sum(ceded, Fr(0))
     closed = excess(run, aggR, aggL)
-    return dict(lr=lr, lr_closed=closed, P=run, gross=gross, occ=occ, cum=cum, ceded=ceded)
+    occ_max = max(occ, default=Fr(0))
+    return dict(lr=lr, lr_closed=closed, P=run, gross=gross, occ=occ, cum=cum, ceded=ceded, occ_max=occ_max)
 
 
 def workload_exact(w, f32_losses: bool = False):

@@ -97,6 +97,7 @@ def test_exact_bruteforce_integer_inputs_bit_exact(financial):
         assert r["gross"].tolist() == [float(v) for e in ex for v in e["gross"]]
         assert r["occ"].tolist() == [float(v) for e in ex for v in e["occ"]]
         assert r["ceded"].tolist() == [float(v) for e in ex for v in e["ceded"]]
+        assert r["occ_max"].tolist() == [float(e["occ_max"]) for e in ex]
 
 
 @pytest.mark.parametrize("financial", [False, True])
@@ -112,6 +113,8 @@ def test_exact_bruteforce_real_losses_within_rounding(financial):
             scale = float(sum(e["gross"], Fr(0))) + float(e["P"]) + 1.0
             assert abs(r["ylt"][t] - float(e["lr"])) <= 1e-13 * scale
             assert abs(r["ylt_closed"][t] - float(e["lr_closed"])) <= 1e-13 * scale
+            # the largest occurrence-net loss: a max of values each within a few ulps
+            assert abs(r["occ_max"][t] - float(e["occ_max"])) <= 1e-14 * 8 * (float(e["occ_max"]) + 1e-300)
         # looked-up per-event gross is a short sum: within a few ulps
         g_ex = np.array([float(v) for e in ex for v in e["gross"]])
         assert np.all(np.abs(r["gross"] - g_ex) <= 1e-14 * (np.abs(g_ex) + 1e-300) * 8)
@@ -161,6 +164,23 @@ def test_single_occurrence_reduces_to_composed_clamps():
         occ = np.minimum(np.maximum(x - terms[0], 0.0), terms[1])
         expect = np.minimum(np.maximum(occ - terms[2], 0.0), terms[3])
         assert np.array_equal(r["ylt"], expect)
+
+
+def test_occurrence_maximum_bounds_and_single_occurrence():
+    """The largest occurrence-net loss is at most the trial's total and at most OccL,
+    equals the total for one-occurrence trials, and is 0 exactly for empty trials."""
+    rng = np.random.default_rng(41)
+    for _ in range(100):
+        w = synth.random_tiny(rng, integer_losses=False)
+        r = oracle.analyze_workload(w, per_event=True)
+        counts = np.diff(w.trial_offsets)
+        assert np.all(r["occ_max"] <= r["occ_total"])
+        assert np.all(r["occ_max"] <= w.layer_terms[1])
+        assert np.all(r["occ_max"][counts == 0] == 0.0)
+        assert np.array_equal(r["occ_max"][counts == 1], r["occ_total"][counts == 1])
+        for t in range(w.n_trials):
+            ev = r["occ"][w.trial_offsets[t] - w.trial_offsets[0]:w.trial_offsets[t + 1] - w.trial_offsets[0]]
+            assert r["occ_max"][t] == (ev.max() if ev.size else 0.0)
 
 
 def test_aggregate_differences_telescope():
