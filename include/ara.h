@@ -247,6 +247,15 @@ ara_status ara_layer_release(ara_layer *layer);
 ara_status ara_analyze(ara_ctx *ctx, const ara_yet *yet, const ara_layer *layer,
                        int64_t trial_begin, int64_t trial_end, double *ylt, ara_mem ylt_mem);
 
+/* Largest occurrence-net loss of every trial in [t0, t1) (after the occurrence terms
+ * of Section II-B step 3; 0 for an empty trial): the year's largest single occurrence,
+ * whose distribution over trials is the occurrence exceedance curve, so
+ * ara_risk_measures on it gives occurrence PML and TVaR.  A maximum: exact, the same
+ * bits in any order.  out: t1 - t0 doubles (mem as for ara_analyze).
+ * Errors: as for ara_analyze. */
+ara_status ara_analyze_occ_max(ara_ctx *ctx, const ara_yet *yet, const ara_layer *layer, int64_t t0, int64_t t1,
+                               double *out, ara_mem mem);
+
 /* Per-occurrence form of the analysis, the steps exactly as the basic algorithm
  * orders them: x_d (loss summed over the layer's ELTs after financial terms),
  * occ_d (after occurrence terms), cum_d (inclusive cumulative sum in time order),
@@ -327,6 +336,14 @@ ara_status ara_batch_run(ara_batch *batch);
  * ARA_E_INVALID_ARG (return period < 1 or NaN, more than 256 of them). */
 ara_status ara_batch_risk(ara_batch *batch, const double *return_periods, int32_t n_rp, double *pml,
                           double *tvar);
+
+/* Portfolio year loss table (Section IV: a portfolio of layers over one YET):
+ * out[t] = the sum over the batch's jobs, in job order from +0.0, of their YLTs' t-th
+ * entries.  Every job must cover the same number of trials; out is device memory of
+ * that many doubles.  Enqueued on the context's stream (after the batch's runs);
+ * ara_risk_measures on it gives the portfolio's PML and TVaR.
+ * Errors: ARA_E_INVALID_ARG (no jobs, or jobs of different trial counts). */
+ara_status ara_batch_portfolio(ara_batch *batch, double *out);
 
 /* The tuned schedule: work items, workgroups, occurrences per item, and whether runs
  * replay a graph.  Any output pointer may be NULL. */

@@ -122,6 +122,8 @@ _SIGS = {
     "ara_batch_create": (_ST, [_P, ctypes.POINTER(ara_job), _I32, ctypes.POINTER(_P)]),
     "ara_batch_run": (_ST, [_P]),
     "ara_batch_risk": (_ST, [_P, _P, _I32, _P, _P]),
+    "ara_batch_portfolio": (_ST, [_P, _P]),
+    "ara_analyze_occ_max": (_ST, [_P, _P, _P, _I64, _I64, _P, ctypes.c_int]),
     "ara_batch_info": (_ST, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64),
                              ctypes.POINTER(_I32)]),
     "ara_batch_release": (_ST, [_P]),
@@ -343,6 +345,13 @@ def ara_analyze(ctx: Ctx, yet: Yet, layer: Layer, trial_begin: int, trial_end: i
            "ara_analyze")
 
 
+def ara_analyze_occ_max(ctx: Ctx, yet: Yet, layer: Layer, t0: int, t1: int, out):
+    """Largest occurrence-net loss per trial of [t0, t1) into a float64 GPU tensor (asynchronous)."""
+    import torch
+    _check(_lib.ara_analyze_occ_max(ctx.ptr, yet.ptr, layer.ptr, int(t0), int(t1), _dev_ptr(out, torch.float64, "out"),
+                                    ARA_MEM_DEVICE), ctx, "ara_analyze_occ_max")
+
+
 def ara_analyze_events(ctx: Ctx, yet: Yet, layer: Layer, trial_begin: int, trial_end: int, ylt=None,
                        ev_gross=None, ev_occ=None, ev_cum=None, ev_ceded=None):
     """Per-occurrence outputs (float64 GPU tensors or None), asynchronous."""
@@ -450,6 +459,12 @@ def ara_batch_risk(b: Batch, return_periods: Sequence[float]):
     _check(_lib.ara_batch_risk(b.ptr, rp.ctypes.data_as(_P), rp.shape[0], pml.ctypes.data_as(_P),
                                tvar.ctypes.data_as(_P)), b.ctx, "ara_batch_risk")
     return pml, tvar
+
+
+def ara_batch_portfolio(b: Batch, out):
+    """Portfolio YLT (sum of the jobs' YLTs per trial, job order) into a float64 GPU tensor."""
+    import torch
+    _check(_lib.ara_batch_portfolio(b.ptr, _dev_ptr(out, torch.float64, "out")), b.ctx, "ara_batch_portfolio")
 
 
 def ara_batch_info(b: Batch):

@@ -725,6 +725,38 @@ extern "C" ara_status ara_analyze(ara_ctx *c, const ara_yet *y, const ara_layer 
     return s;
 }
 
+extern "C" ara_status ara_analyze_occ_max(ara_ctx *c, const ara_yet *y, const ara_layer *L, int64_t t0, int64_t t1,
+                                         double *out, ara_mem mem) {
+    ara_status s = check_analysis(c, y, L, t0, t1);
+    if (s != ARA_OK) return s;
+    if ((t1 > t0 && !out) || (mem != ARA_MEM_HOST && mem != ARA_MEM_DEVICE))
+        return fail(c, ARA_E_INVALID_ARG, "occurrence maxima: bad output");
+    if (t1 == t0) return ARA_OK;
+    HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    TrialLaunch tl{};
+    s = plan_trial(c, L, t1 - t0, 1e9, tl);
+    if (s != ARA_OK) return s;
+    const int by_lds = tl.lds_bytes > 0 ? std::max(1, int(c->lds_max / int64_t(tl.lds_bytes))) : 8;
+    const int64_t grid = std::min<int64_t>(int64_t(c->n_cu) * std::min(8, by_lds), (t1 - t0 + 255) / 256);
+    double *dst = out;
+    if (mem == ARA_MEM_HOST) {
+        s = dev_alloc(c, &dst, size_t(t1 - t0) * 8, "occurrence maxima staging");
+        if (s != ARA_OK) return s;
+    }
+    const TrialArgs a = trial_args(y, L, t0, t1, nullptr);
+    hipError_t e = launch_trial_occ_max(a, tl, int(std::max<int64_t>(1, grid)), dst, c->stream);
+    if (e != hipSuccess) s = hip_fail(c, e, "occurrence maxima");
+    if (s == ARA_OK && mem == ARA_MEM_HOST) {
+        e = hipMemcpyAsync(out, dst, size_t(t1 - t0) * 8, hipMemcpyDeviceToHost, c->stream);
+        s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "occurrence maxima download");
+    }
+    if (mem == ARA_MEM_HOST) {
+        (void)hipStreamSynchronize(c->stream);
+        dev_free(dst);
+    }
+    return s;
+}
+
 extern "C" ara_status ara_analyze_events(ara_ctx *c, const ara_yet *y, const ara_layer *L, int64_t t0, int64_t t1,
                                         double *ylt, double *g, double *o, double *cu, double *ce, ara_mem mem) {
     ara_status s = check_analysis(c, y, L, t0, t1);
@@ -1116,6 +1148,39 @@ extern "C" ara_status ara_batch_info(const ara_batch *b, int32_t *n_items, int32
     return ARA_OK;
 }
 
+// Device list of the jobs' YLT pointers and lengths (built once).
+static ara_status batch_ylt_list(ara_batch *b) {
+    if (b->d_ylts) return ARA_OK;
+    ara_ctx *c = b->ctx;
+    const size_t nj = b->jobs.size();
+    std::vector<const double *> yp(nj);
+    std::vector<int64_t> ns(nj);
+    for (size_t j = 0; j < nj; ++j) {
+        yp[j] = b->jobs[j].ylt;
+        ns[j] = b->jobs[j].trial_end - b->jobs[j].trial_begin;
+    }
+    ara_status s = dev_alloc(c, &b->d_ylts, nj * sizeof(double *), "batch ylt list");
+    if (s == ARA_OK) s = dev_alloc(c, &b->d_ns, nj * 8, "batch sizes");
+    if (s != ARA_OK) return s;
+    HIP_OR_RETURN(c, hipMemcpy(b->d_ylts, yp.data(), nj * sizeof(double *), hipMemcpyHostToDevice), "upload");
+    HIP_OR_RETURN(c, hipMemcpy(b->d_ns, ns.data(), nj * 8, hipMemcpyHostToDevice), "upload");
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_batch_portfolio(ara_batch *b, double *out) {
+    if (!b || !out) return ARA_E_INVALID_ARG;
+    ara_ctx *c = b->ctx;
+    if (b->jobs.empty()) return fail(c, ARA_E_INVALID_ARG, "portfolio of an empty batch");
+    const int64_t n = b->jobs[0].trial_end - b->jobs[0].trial_begin;
+    for (const ara_job &j : b->jobs)
+        if (j.trial_end - j.trial_begin != n) return fail(c, ARA_E_INVALID_ARG, "portfolio: jobs cover different trial counts");
+    HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    ara_status s = batch_ylt_list(b);
+    if (s != ARA_OK) return s;
+    const hipError_t e = launch_sum_ylts(b->d_ylts, int32_t(b->jobs.size()), n, out, c->stream);
+    return e == hipSuccess ? ARA_OK : hip_fail(c, e, "portfolio sum");
+}
+
 extern "C" ara_status ara_batch_risk(ara_batch *b, const double *rps, int32_t n_rp, double *pml, double *tvar) {
     if (!b || n_rp < 0 || (n_rp > 0 && (!rps || !pml || !tvar))) return ARA_E_INVALID_ARG;
     ara_ctx *c = b->ctx;
@@ -1133,19 +1198,9 @@ extern "C" ara_status ara_batch_risk(ara_batch *b, const double *rps, int32_t n_
                 return fail(c, ARA_E_INVALID_ARG, "return period %g invalid (must be >= 1)", rps[r]);
     }
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
-    // device copies of the per-job inputs (once per return-period count)
-    if (!b->d_ylts) {
-        std::vector<const double *> yp(static_cast<size_t>(nj));
-        std::vector<int64_t> ns(static_cast<size_t>(nj));
-        for (int32_t j = 0; j < nj; ++j) {
-            yp[size_t(j)] = b->jobs[size_t(j)].ylt;
-            ns[size_t(j)] = b->jobs[size_t(j)].trial_end - b->jobs[size_t(j)].trial_begin;
-        }
-        ara_status s = dev_alloc(c, &b->d_ylts, size_t(nj) * sizeof(double *), "batch ylt list");
-        if (s == ARA_OK) s = dev_alloc(c, &b->d_ns, size_t(nj) * 8, "batch sizes");
+    {
+        ara_status s = batch_ylt_list(b);
         if (s != ARA_OK) return s;
-        HIP_OR_RETURN(c, hipMemcpy(b->d_ylts, yp.data(), size_t(nj) * sizeof(double *), hipMemcpyHostToDevice), "upload");
-        HIP_OR_RETURN(c, hipMemcpy(b->d_ns, ns.data(), size_t(nj) * 8, hipMemcpyHostToDevice), "upload");
     }
     if (b->risk_cap < n_rp) {
         dev_free(b->d_ks);

@@ -116,6 +116,7 @@ struct TrialLaunch {
 constexpr int kLaneModeMaxMean = 256;
 hipError_t launch_trial_ylt(const TrialArgs &a, const TrialLaunch &l, hipStream_t s);
 hipError_t launch_trial_events(const TrialArgs &a, bool f32, int grid, hipStream_t s);
+hipError_t launch_trial_occ_max(const TrialArgs &a, const TrialLaunch &l, int grid, double *out, hipStream_t s);
 hipError_t launch_lookup(const TrialArgs &a, const TrialLaunch &l, const int32_t *ids, int64_t n, double *gross,
                          double *occ, hipStream_t s);
 hipError_t prepare_trial_kernels();
@@ -143,6 +144,7 @@ struct BatchItem {
 hipError_t launch_batch(const BatchJob *jobs, const BatchItem *items, int32_t n_items, int32_t per_wg, int grid,
                         hipStream_t s);
 int32_t batch_mode(const TrialLaunch &l, bool packed);
+hipError_t launch_sum_ylts(const double *const *ylts, int32_t n_jobs, int64_t n, double *out, hipStream_t s);
 constexpr int kRiskLdsKeys = 16384;   // YLTs up to this length are sorted in one workgroup's LDS
 hipError_t launch_risk_batch(const double *const *ylts, const int64_t *ns, const int64_t *ks, int n_jobs, int n_k,
                              double *out, hipStream_t s);

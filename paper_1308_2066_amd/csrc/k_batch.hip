@@ -11,6 +11,8 @@
 #include "trial_dense.h"
 #include "trial_bitmap.h"
 
+#include <algorithm>
+
 namespace ara {
 
 // A wave-uniform copy of a descriptor, read through the scalar data path (constant
@@ -79,6 +81,24 @@ __global__ __launch_bounds__(1024) void k_batch(const BatchJob *__restrict__ job
             break;
         }
     }
+}
+
+// Portfolio year losses: out[t] = sum over jobs j = 0, 1, ... (in that order) of
+// ylts[j][t], one thread per trial.
+__global__ __launch_bounds__(256) void k_sum_ylts(const double *const *__restrict__ ylts, int32_t n_jobs, int64_t n,
+                                                  double *__restrict__ out) {
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < n; t += int64_t(gridDim.x) * blockDim.x) {
+        double s = 0.0;
+        for (int32_t j = 0; j < n_jobs; ++j) s += ylts[j][t];
+        out[t] = s;
+    }
+}
+
+hipError_t launch_sum_ylts(const double *const *ylts, int32_t n_jobs, int64_t n, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int64_t grid = std::min<int64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_sum_ylts, dim3(unsigned(grid)), dim3(256), 0, s, ylts, n_jobs, n, out);
+    return hipGetLastError();
 }
 
 int32_t batch_mode(const TrialLaunch &l, bool packed) {

@@ -49,6 +49,62 @@ __global__ __launch_bounds__(1024) void k_trial_ylt_lane(TrialArgs a) {
 }
 
 // ---------------------------------------------------------------------------------
+// Largest occurrence-net loss of each trial (lane per trial): a maximum, so exact in
+// any order.  Its distribution over trials is the occurrence exceedance curve.
+template <int PL>
+__device__ __forceinline__ double occ_value(const TrialArgs &a, const uint32_t *lds, uint32_t id) {
+    if (PL == ARA_PLACE_LDS_BITMAP) {
+        const uint32_t w = lds[id >> 5];
+        return ((w >> (id & 31u)) & 1u) ? a.vals[bitmap_rank(lds, a.nblk, id)] : 0.0;
+    } else if (PL == ARA_PLACE_LDS_DENSE) {
+        return reinterpret_cast<const double *>(lds)[id];
+    }
+    return a.occ[id];
+}
+
+template <int PL>
+__global__ __launch_bounds__(1024) void k_trial_occ_max(TrialArgs a, double *__restrict__ out) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t lds[];
+    stage_lds<PL>(a, lds);
+    const uint32_t C = uint32_t(a.catalog);
+    const i32x4 *ids4 = reinterpret_cast<const i32x4 *>(a.ids);
+    uint32_t bad = 0;
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t t = a.t_begin + int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < a.t_end; t += stride) {
+        int64_t o0 = a.offs[t], o1 = a.offs[t + 1];
+        if (!(o0 >= 0 && o0 <= o1 && o1 <= a.n_events)) {
+            bad |= ERR_OFFSETS;
+            o0 = o1 = 0;
+        }
+        double m = 0.0;
+        for (int64_t g = o0 >> 2; 4 * g < o1; ++g) {
+            int32_t id4[4];
+            if (4 * g + 4 <= a.n_events) {
+                const i32x4 x = ids4[g];
+                id4[0] = x.x, id4[1] = x.y, id4[2] = x.z, id4[3] = x.w;
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) id4[j] = 4 * g + j < a.n_events ? a.ids[4 * g + j] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t pos = 4 * g + j;
+                const uint32_t id = uint32_t(id4[j]);
+                if (pos < o0 || pos >= o1) continue;
+                if (id >= C) {
+                    bad |= ERR_ID_RANGE;
+                    continue;
+                }
+                const double v = occ_value<PL>(a, lds, id);
+                m = v > m ? v : m;
+            }
+        }
+        out[t - a.t_begin] = m;
+    }
+    if (bad) atomicOr(a.err, bad);
+}
+
+// ---------------------------------------------------------------------------------
 // Per-occurrence form: every quantity of the basic algorithm, with the cumulative
 // sum as a wave-wide inclusive scan (lane-local over 4 consecutive events, then a
 // 64-lane scan, plus the carry from the previous 256 events).
@@ -172,6 +228,8 @@ hipError_t prepare_trial_kernels() {
     if (e != hipSuccess) return e;
     ARA_SET_LDS(k_trial_ylt<ARA_PLACE_LDS_DENSE>)
     ARA_SET_LDS(k_trial_ylt_lane<ARA_PLACE_LDS_DENSE>)
+    ARA_SET_LDS(k_trial_occ_max<ARA_PLACE_LDS_DENSE>)
+    ARA_SET_LDS(k_trial_occ_max<ARA_PLACE_LDS_BITMAP>)
     ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_BITMAP, double>))
     ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_DENSE, double>))
     ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_BITMAP, float>))
@@ -195,6 +253,21 @@ hipError_t launch_trial_ylt(const TrialArgs &a, const TrialLaunch &l, hipStream_
             hipLaunchKernelGGL(k_trial_ylt_lane<ARA_PLACE_GLOBAL_DENSE>, dim3(l.grid), dim3(l.block), 0, s, a);
         else
             hipLaunchKernelGGL(k_trial_ylt<ARA_PLACE_GLOBAL_DENSE>, dim3(l.grid), dim3(l.block), 0, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_trial_occ_max(const TrialArgs &a, const TrialLaunch &l, int grid, double *out, hipStream_t s) {
+    switch (l.placement) {
+    case ARA_PLACE_LDS_BITMAP:
+        hipLaunchKernelGGL(k_trial_occ_max<ARA_PLACE_LDS_BITMAP>, dim3(grid), dim3(256), l.lds_bytes, s, a, out);
+        break;
+    case ARA_PLACE_LDS_DENSE:
+        hipLaunchKernelGGL(k_trial_occ_max<ARA_PLACE_LDS_DENSE>, dim3(grid), dim3(256), l.lds_bytes, s, a, out);
+        break;
+    default:
+        hipLaunchKernelGGL(k_trial_occ_max<ARA_PLACE_GLOBAL_DENSE>, dim3(grid), dim3(256), 0, s, a, out);
         break;
     }
     return hipGetLastError();

@@ -32,7 +32,8 @@ import numpy as np
 SEED_BASE = 13082066
 
 __all__ = [
-    "SEED_BASE", "Workload", "Portfolio", "portfolio_batched", "serving_yet", "serving_requests", "uniform_ids", "yet_poisson", "yet_fixed", "yet_fixed_block",
+    "SEED_BASE", "Workload", "Portfolio", "portfolio_batched", "serving_yet", "serving_requests", "uneven_analyses",
+    "uniform_ids", "yet_poisson", "yet_fixed", "yet_fixed_block",
     "elt_sparse", "workload_plain_small", "workload_paper_scale", "random_tiny",
     "loguniform_terms",
 ]
@@ -227,6 +228,21 @@ def portfolio_batched(seed: int = SEED_BASE + 2, n_layers: int = 64, pool_size: 
                      base.return_periods, seed)
 
 
+def _ids_blocks(key, n: int, catalog: int, block: int = 1 << 22) -> np.ndarray:
+    """n uniform IDs over the catalog, drawn in blocks of `block` with independent
+    streams default_rng(key + [block index]) on a thread pool."""
+    ids = np.empty(n, dtype=np.int32)
+
+    def work(b):
+        lo = b * block
+        hi = min(n, lo + block)
+        ids[lo:hi] = uniform_ids(np.random.default_rng(list(key) + [b]), hi - lo, catalog)
+
+    with ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(work, range((n + block - 1) // block)))
+    return ids
+
+
 def serving_yet(seed: int = SEED_BASE + 4, n_trials: int = 1_000_000):
     """Resident YET of the serving workload: the plain small statistics (Poisson(100)
     events per trial, IDs uniform over a 10,000-event catalog) at 10^6 trials.  With
@@ -236,18 +252,7 @@ def serving_yet(seed: int = SEED_BASE + 4, n_trials: int = 1_000_000):
     counts = rng.poisson(100.0, size=n_trials).astype(np.int64)
     offs = np.zeros(n_trials + 1, dtype=np.int64)
     np.cumsum(counts, out=offs[1:])
-    n = int(offs[-1])
-    ids = np.empty(n, dtype=np.int32)
-    block = 1 << 22
-
-    def work(b):
-        lo = b * block
-        hi = min(n, lo + block)
-        ids[lo:hi] = uniform_ids(np.random.default_rng([seed, 0x5E, b]), hi - lo, 10_000)
-
-    with ThreadPoolExecutor(_threads()) as ex:
-        list(ex.map(work, range((n + block - 1) // block)))
-    return ids, offs, 10_000
+    return _ids_blocks([seed, 0x5E], int(offs[-1]), 10_000), offs, 10_000
 
 
 def serving_requests(n: int, n_trials: int, pool_size: int = 256, rate: float = 50.0, seed: int = SEED_BASE + 4,
@@ -266,6 +271,31 @@ def serving_requests(n: int, n_trials: int, pool_size: int = 256, rate: float = 
         length = int(rng.integers(min_trials, min(max_trials, n_trials) + 1))
         t0 = int(rng.integers(0, n_trials - length + 1))
         out.append((float(t[i]), idx, terms, t0, t0 + length))
+    return out
+
+
+def uneven_analyses(n: int = 256, seed: int = SEED_BASE + 3, trials=(10_000, 500_000), mean=(200.0, 2000.0),
+                    catalog=(100_000, 1_000_000), max_elts: int = 16, nnz: int = 20_000) -> List[Workload]:
+    """Independent analyses of uneven shapes: trials log-uniform in `trials`, events
+    per trial Poisson with a mean uniform in `mean`, catalogs uniform in `catalog`,
+    U{1..max_elts} ELTs of `nnz` distinct events with lognormal(10, 2) losses; layer
+    terms occurrence 1e5/5e6, aggregate 1e6/5e7.  With iid uniform IDs the draw order
+    is taken as the time order (ordering by iid timestamps leaves the distribution of
+    the ID sequence unchanged)."""
+    out = []
+    for a in range(n):
+        rng = np.random.default_rng([seed, 0xC4, a])
+        n_t = int(round(math.exp(rng.uniform(math.log(trials[0]), math.log(trials[1])))))
+        mu = float(rng.uniform(*mean))
+        C = int(rng.integers(catalog[0], catalog[1] + 1))
+        k = int(rng.integers(1, max_elts + 1))
+        counts = rng.poisson(mu, size=n_t).astype(np.int64)
+        offs = np.zeros(n_t + 1, dtype=np.int64)
+        np.cumsum(counts, out=offs[1:])
+        ids = _ids_blocks([seed, 0xC4, a], int(offs[-1]), C)
+        elts = [elt_sparse(rng, min(nnz, C), C, 10.0, 2.0) for _ in range(k)]
+        out.append(Workload(f"uneven-{a}-{n_t}x{mu:.0f}-cat{C}-{k}elt", ids, offs, C, elts, (1e5, 5e6, 1e6, 5e7), None,
+                            (10.0, 100.0, 250.0), seed))
     return out
 
 

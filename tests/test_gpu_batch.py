@@ -155,14 +155,23 @@ def test_batched_portfolio_matches_oracle(A, S, gpu_ctx):
     h = S.open_portfolio(gpu_ctx, pf.event_ids, pf.trial_offsets, pf.catalog_size, pf.pool, pf.layers)
     try:
         outs = [torch.empty(pf.n_trials, dtype=torch.float64, device="cuda") for _ in pf.layers]
+        port = torch.empty(pf.n_trials, dtype=torch.float64, device="cuda")
         b = A.ara_batch_create(gpu_ctx, [(h.yet, layer, 0, pf.n_trials, o) for layer, o in zip(h.layers, outs)])
         try:
             A.ara_batch_run(b)
             A.ara_batch_run(b)
+            A.ara_batch_portfolio(b, port)
             A.ara_sync(gpu_ctx)
             pml, tvar = A.ara_batch_risk(b, pf.return_periods)
         finally:
             A.ara_batch_release(b)
+        # portfolio YLT: the layers' YLTs added per trial in layer order from +0.0
+        want = np.zeros(pf.n_trials)
+        for o in outs:
+            want = want + o.cpu().numpy()
+        assert port.cpu().numpy().tobytes() == want.tobytes()
+        port_tol = np.zeros(pf.n_trials)
+        port_ref = np.zeros(pf.n_trials)
         threads = oracle.max_threads()
         for j in range(len(pf.layers)):
             _say(f"portfolio layer {j}")
@@ -173,8 +182,44 @@ def test_batched_portfolio_matches_oracle(A, S, gpu_ctx):
             gross = ref["gross_total"]
             tol = 2.0 ** -23 * 1.0001 * gross + 1e-12 * np.maximum(np.abs(ref["ylt"]), ref["occ_total"])
             assert np.all(np.abs(got - ref["ylt"]) <= tol), j
+            port_ref = port_ref + ref["ylt"]
+            port_tol = port_tol + tol
             ranks = [A.ara_return_period_rank(pf.n_trials, rp) for rp in pf.return_periods]
             srt = np.sort(got)[::-1]
             assert pml[j].tolist() == [srt[k - 1] for k in ranks]
+        # the portfolio against the sum of the oracle's layer YLTs (64 terms of rounding added)
+        assert np.all(np.abs(port.cpu().numpy() - port_ref) <= port_tol + 64 * 2.0 ** -52 * np.abs(port_ref))
     finally:
         h.release()
+
+
+def test_uneven_analyses_batch_equals_plain(A, S, gpu_ctx):
+    """Independent analyses of different YETs, catalogs (100k-1M: LDS filter), trial
+    counts and lengths in one batch: each YLT equals its plain launch bit for bit,
+    and the oracle within tolerance (first trials of each)."""
+    import torch
+    ws = synth.uneven_analyses(n=10, trials=(1_000, 20_000))
+    opened = []
+    try:
+        for w in ws:
+            opened.append(S.open_analysis(gpu_ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts,
+                                          w.layer_terms))
+        outs = [torch.empty(w.n_trials, dtype=torch.float64, device="cuda") for w in ws]
+        b = A.ara_batch_create(gpu_ctx, [(an.yet, an.layer, 0, w.n_trials, o) for an, w, o in zip(opened, ws, outs)])
+        try:
+            A.ara_batch_run(b)
+            A.ara_batch_run(b)
+            A.ara_sync(gpu_ctx)
+        finally:
+            A.ara_batch_release(b)
+        for an, w, o in zip(opened, ws, outs):
+            _say(f"uneven {w.name}")
+            got = o.cpu().numpy()
+            assert got.tobytes() == _plain(A, gpu_ctx, an.yet, an.layer, 0, w.n_trials).tobytes(), w.name
+            ref = oracle.analyze(w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms, t_end=200,
+                                 threads=oracle.max_threads())
+            tol = 1e-12 * np.maximum(np.abs(ref["ylt"]), ref["occ_total"])
+            assert np.all(np.abs(got[:200] - ref["ylt"]) <= tol), w.name
+    finally:
+        for an in opened:
+            an.release()

@@ -216,6 +216,38 @@ def test_lane_per_trial_is_the_sequential_sum(A, S, gpu_ctx, small, placement):
             assert analyze(A, S, gpu_ctx, w, placement, mode=2, block=block).tobytes() == lane.tobytes()
 
 
+def test_occurrence_maximum_bit_exact(A, S, gpu_ctx, small, paper_reduced):
+    """Largest occurrence-net loss per trial: a maximum of bit-exact table values, so
+    it equals the oracle's bit for bit in every placement (ragged and empty trials
+    included); occurrence PML comes from ara_risk_measures on it."""
+    import torch
+    rng = np.random.default_rng(31)
+    edge = _edge_workload(rng, [0, 1, 3, 4, 5, 255, 256, 257, 1023, 1025, 2049, 0, 7, 4099, 1, 2])
+    for w, pls in [(small, [1, 2, 3]), (edge, [1, 2, 3]), (paper_reduced, [1, 3])]:
+        ref = oracle.analyze_workload(w, threads=oracle.max_threads())["occ_max"]
+        for pl in pls:
+            _say(f"occurrence maxima {w.name} placement={pl}")
+            A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, pl)
+            an = S.open_analysis(gpu_ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
+                                 w.elt_terms)
+            try:
+                out = torch.full((w.n_trials,), math.nan, dtype=torch.float64, device="cuda")
+                A.ara_analyze_occ_max(gpu_ctx, an.yet, an.layer, 0, w.n_trials, out)
+                A.ara_sync(gpu_ctx)
+                got = out.cpu().numpy()
+                assert got.tobytes() == ref.tobytes(), (w.name, pl)
+                sub = torch.empty(5, dtype=torch.float64, device="cuda")
+                A.ara_analyze_occ_max(gpu_ctx, an.yet, an.layer, 3, 8, sub)
+                A.ara_sync(gpu_ctx)
+                assert sub.cpu().numpy().tobytes() == ref[3:8].tobytes()
+            finally:
+                an.release()
+                A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, 0)
+        pml, _ = A.ara_risk_measures(gpu_ctx, torch.from_numpy(ref).cuda(), [10.0, 100.0])
+        pml_o, _, _, _ = oracle.risk(ref, [10.0, 100.0])
+        assert np.asarray(pml).tobytes() == np.asarray(pml_o).tobytes()
+
+
 def _catalog_lookup_reference(w, precision_f32=False):
     ids = np.arange(w.catalog_size, dtype=np.int32)
     offs = np.array([0, w.catalog_size], np.int64)
