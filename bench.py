@@ -290,7 +290,8 @@ def bench_portfolio(args):
                                f"log-uniform terms", "layers": L, "parallelism": "1 GPU"},
         "plain_per_layer": {"ms_per_step": ms_p, "value": te / (ms_p * 1e-3)},
         "speedup_vs_plain": ms_p / ms_b, "identical_results": bool(same),
-        "schedule": {"items": n_items, "workgroups": grid, "events_per_item": epi, "graph": bool(graph)},
+        "schedule": {"items": n_items, "workgroups": grid, "events_per_item": epi, "graph": bool(graph & 1),
+                     "interleaved": bool(graph & 2)},
     }
     print(json.dumps(out), flush=True)
 
@@ -455,7 +456,8 @@ def bench_uneven(args):
                      "frac": alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": alg, "moved_bytes": moved},
         "plain_per_analysis": {"ms_per_step": ms_p, "value": ev / (ms_p * 1e-3)},
         "speedup_vs_plain": ms_p / ms_b, "identical_results": bool(same),
-        "schedule": {"items": n_items, "workgroups": grid, "events_per_item": epi, "graph": bool(graph)},
+        "schedule": {"items": n_items, "workgroups": grid, "events_per_item": epi, "graph": bool(graph & 1),
+                     "interleaved": bool(graph & 2)},
     }
     print(json.dumps(out), flush=True)
 

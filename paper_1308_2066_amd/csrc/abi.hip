@@ -33,7 +33,7 @@ struct ara_ctx {
     int grid_per_cu = 0;             // 0 = automatic
     int yet_packing = 1;             // keep a packed copy of YET IDs where they fit 24 bits
     int trial_mode = 0;              // 0 = by trial length, 1 = wave per trial, 2 = lane per trial
-    std::map<std::string, int64_t> tuned;   // batch shape -> events per work item
+    std::map<std::string, std::pair<int64_t, bool>> tuned;   // batch shape -> (events per item, interleave)
     int live = 0;                    // handles alive on this context
     std::string msg;
 };
@@ -956,8 +956,10 @@ struct ara_batch {
     std::string shape;               // key of the tuning cache
     BatchJob *d_jobs = nullptr;
     BatchItem *d_items = nullptr;
-    int32_t n_items = 0, per_wg = 0, grid = 0;
+    int32_t n_items = 0, grid = 0;   // grid: the largest of the per-mode launches
+    int32_t mode_off[kBatchModes] = {}, mode_cnt[kBatchModes] = {};
     int64_t events_per_item = 0;
+    bool interleave = false;         // workgroups take every G-th item (else contiguous runs)
     hipStream_t cap = nullptr;       // private stream the launch is captured on
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -981,12 +983,18 @@ static void split_items(int32_t j, int32_t mode, int64_t tb, int64_t te, int64_t
     for (int64_t t = tb; t < te; t += per) items.push_back(BatchItem{j, 0, t, std::min(te, t + per)});
 }
 
-// The work items of a batch, grouped by job in job order.
-static std::vector<BatchItem> batch_items(const ara_batch *b, int64_t events) {
+// Work items of many jobs grouped by mode (kernel), then by job in job order; off/cnt
+// give each mode's range of the list.
+static std::vector<BatchItem> group_items(const std::vector<BatchJob> &hjobs, const int64_t *tb, const int64_t *te,
+                                          const std::vector<int64_t> &mean_len, int64_t events, int32_t *off,
+                                          int32_t *cnt) {
     std::vector<BatchItem> items;
-    for (size_t j = 0; j < b->jobs.size(); ++j)
-        split_items(int32_t(j), b->hjobs[j].mode, b->jobs[j].trial_begin, b->jobs[j].trial_end, b->mean_len[j], events,
-                    items);
+    for (int m = 0; m < kBatchModes; ++m) {
+        off[m] = int32_t(items.size());
+        for (size_t j = 0; j < hjobs.size(); ++j)
+            if (hjobs[j].mode == m) split_items(int32_t(j), m, tb[j], te[j], mean_len[j], events, items);
+        cnt[m] = int32_t(items.size()) - off[m];
+    }
     return items;
 }
 
@@ -997,9 +1005,33 @@ static void batch_shape(int32_t n_items, int n_cu, int32_t &grid, int32_t &per_w
     grid = n_items > 0 ? (n_items + per_wg - 1) / std::max(1, per_wg) : 1;
 }
 
+// One persistent launch per mode present, in mode order; interleave: workgroups take
+// every G-th item instead of a contiguous run.
+static hipError_t launch_grouped(const BatchJob *d_jobs, const BatchItem *d_items, const int32_t *off,
+                                 const int32_t *cnt, int n_cu, bool interleave, hipStream_t s) {
+    for (int m = 0; m < kBatchModes; ++m) {
+        if (cnt[m] == 0) continue;
+        int32_t grid = 1, per_wg = 0;
+        batch_shape(cnt[m], n_cu, grid, per_wg);
+        if (interleave) {
+            grid = std::max(1, std::min(cnt[m], n_cu));
+            per_wg = 0;
+        }
+        const hipError_t e = launch_batch(m, d_jobs, d_items + off[m], cnt[m], per_wg, grid, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 static ara_status batch_set_items(ara_batch *b, int64_t events) {
     ara_ctx *c = b->ctx;
-    const std::vector<BatchItem> items = batch_items(b, events);
+    std::vector<int64_t> tb, te;
+    for (const ara_job &j : b->jobs) {
+        tb.push_back(j.trial_begin);
+        te.push_back(j.trial_end);
+    }
+    const std::vector<BatchItem> items = group_items(b->hjobs, tb.data(), te.data(), b->mean_len, events, b->mode_off,
+                                                     b->mode_cnt);
     dev_free(b->d_items);
     b->d_items = nullptr;
     b->n_items = int32_t(items.size());
@@ -1009,7 +1041,12 @@ static ara_status batch_set_items(ara_batch *b, int64_t events) {
         HIP_OR_RETURN(c, hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice),
                       "batch items upload");
     }
-    batch_shape(b->n_items, c->n_cu, b->grid, b->per_wg);
+    b->grid = 0;
+    for (int m = 0; m < kBatchModes; ++m) {
+        int32_t g = 1, per = 0;
+        if (b->mode_cnt[m]) batch_shape(b->mode_cnt[m], c->n_cu, g, per);
+        if (b->mode_cnt[m]) b->grid = std::max(b->grid, g);
+    }
     b->events_per_item = events;
     return ARA_OK;
 }
@@ -1069,8 +1106,11 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
 static ara_status batch_tune(ara_batch *b) {
     ara_ctx *c = b->ctx;
     auto it = c->tuned.find(b->shape);
-    if (it != c->tuned.end()) return batch_set_items(b, it->second);
-    static const int64_t kCandidates[] = {int64_t(1) << 16, int64_t(1) << 18, int64_t(1) << 20, int64_t(1) << 22};
+    if (it != c->tuned.end()) {
+        b->interleave = it->second.second;
+        return batch_set_items(b, it->second.first);
+    }
+    static const int64_t kEvents[] = {int64_t(1) << 16, int64_t(1) << 18, int64_t(1) << 20, int64_t(1) << 22};
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OR_RETURN(c, hipEventCreate(&e0), "event");
     hipError_t e = hipEventCreate(&e1);
@@ -1078,25 +1118,29 @@ static ara_status batch_tune(ara_batch *b) {
         (void)hipEventDestroy(e0);
         return hip_fail(c, e, "event");
     }
-    int64_t best = kCandidates[0];
+    std::pair<int64_t, bool> best{kEvents[0], false};
     float best_ms = 1e30f;
     ara_status s = ARA_OK;
-    for (int64_t cand : kCandidates) {
-        s = batch_set_items(b, cand);
+    for (int64_t ev : kEvents) {
+        s = batch_set_items(b, ev);
         if (s != ARA_OK) break;
-        e = hipEventRecord(e0, c->stream);
-        if (e == hipSuccess) e = launch_batch(b->d_jobs, b->d_items, b->n_items, b->per_wg, b->grid, c->stream);
-        if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        for (bool inter : {false, true}) {
+            e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess)
+                e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, inter, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = {ev, inter};
+            }
+        }
         if (e != hipSuccess) {
             s = hip_fail(c, e, "batch tuning run");
             break;
-        }
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = cand;
         }
     }
     (void)hipEventDestroy(e0);
@@ -1105,14 +1149,15 @@ static ara_status batch_tune(ara_batch *b) {
     s = sync_and_check(c);
     if (s != ARA_OK) return s;
     c->tuned[b->shape] = best;
-    return batch_set_items(b, best);
+    b->interleave = best.second;
+    return batch_set_items(b, best.first);
 }
 
 static ara_status batch_capture(ara_batch *b) {
     ara_ctx *c = b->ctx;
     HIP_OR_RETURN(c, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream");
     HIP_OR_RETURN(c, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
-    hipError_t e = launch_batch(b->d_jobs, b->d_items, b->n_items, b->per_wg, b->grid, b->cap);
+    hipError_t e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, b->interleave, b->cap);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e == hipSuccess) e = e2;
@@ -1144,7 +1189,7 @@ extern "C" ara_status ara_batch_info(const ara_batch *b, int32_t *n_items, int32
     if (n_items) *n_items = b->n_items;
     if (grid) *grid = b->grid;
     if (events_per_item) *events_per_item = b->events_per_item;
-    if (graph) *graph = b->exec ? 1 : 0;
+    if (graph) *graph = (b->exec ? 1 : 0) | (b->interleave ? 2 : 0);
     return ARA_OK;
 }
 
@@ -1311,6 +1356,7 @@ struct ara_server {
     BatchJob *d_jobs = nullptr, *h_jobs = nullptr;
     BatchItem *d_items = nullptr, *h_items = nullptr;
     int32_t item_cap = 0;
+    int32_t mode_off[kBatchModes] = {}, mode_cnt[kBatchModes] = {};
     EltDesc *h_descs = nullptr;       // pinned staging: every slot's descriptors
     const double **d_ylts = nullptr;
     int64_t *d_ns = nullptr, *d_ks = nullptr, *h_nks = nullptr;   // h_nks: ns then ks, pinned
@@ -1368,17 +1414,24 @@ static ara_status server_iteration(ara_server *sv, const std::vector<ServerReque
         h.a.qcap = tl.qcap;
         h.mode = batch_mode(tl, h.a.ids24 != nullptr);
         h.placement = tl.placement;
-        split_items(int32_t(i), h.mode, r->t0, r->t1, mean, kServerEventsPerItem, items);
+    }
+    {
+        std::vector<BatchJob> hj(sv->h_jobs, sv->h_jobs + reqs.size());
+        std::vector<int64_t> tb, te, ml(reqs.size(), mean);
+        for (ServerRequest *r : reqs) {
+            tb.push_back(r->t0);
+            te.push_back(r->t1);
+        }
+        items = group_items(hj, tb.data(), te.data(), ml, kServerEventsPerItem, sv->mode_off, sv->mode_cnt);
     }
     const int32_t nj = int32_t(reqs.size());
     if (int32_t(items.size()) > sv->item_cap) return fail(pc, ARA_E_OOM, "server: %zu work items", items.size());
     std::copy(items.begin(), items.end(), sv->h_items);
-    int32_t grid = 1, per_wg = 0;
-    batch_shape(int32_t(items.size()), pc->n_cu, grid, per_wg);
     hipError_t e = hipMemcpyAsync(sv->d_jobs, sv->h_jobs, sizeof(BatchJob) * size_t(nj), hipMemcpyHostToDevice, sv->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(sv->d_items, sv->h_items, sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice, sv->stream);
-    if (e == hipSuccess) e = launch_batch(sv->d_jobs, sv->d_items, int32_t(items.size()), per_wg, grid, sv->stream);
+    if (e == hipSuccess)
+        e = launch_grouped(sv->d_jobs, sv->d_items, sv->mode_off, sv->mode_cnt, pc->n_cu, true, sv->stream);
     // risk measures: ranks per request, short YLTs in one launch, long ones one by one
     int64_t *hn = sv->h_nks, *hk = sv->h_nks + sv->slots.size();
     for (int32_t i = 0; i < nj && e == hipSuccess; ++i) {

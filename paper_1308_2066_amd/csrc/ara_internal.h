@@ -141,8 +141,9 @@ struct BatchItem {
     int32_t pad_;
     int64_t t0, t1;        // trials [t0, t1) of the job's YET
 };
-hipError_t launch_batch(const BatchJob *jobs, const BatchItem *items, int32_t n_items, int32_t per_wg, int grid,
-                        hipStream_t s);
+constexpr int kBatchModes = 6;
+hipError_t launch_batch(int32_t mode, const BatchJob *jobs, const BatchItem *items, int32_t n_items, int32_t per_wg,
+                        int grid, hipStream_t s);
 int32_t batch_mode(const TrialLaunch &l, bool packed);
 hipError_t launch_sum_ylts(const double *const *ylts, int32_t n_jobs, int64_t n, double *out, hipStream_t s);
 constexpr int kRiskLdsKeys = 16384;   // YLTs up to this length are sorted in one workgroup's LDS
