@@ -28,6 +28,7 @@ struct ara_ctx {
     double *d_out = nullptr;         // small device result staging
     double *h_out = nullptr;         // pinned host mirror of d_out
     uint32_t *h_err = nullptr;       // pinned host error word
+    uint32_t *h_plan = nullptr;      // pinned copy of a radix sort's pass plan
     int placement = ARA_PLACE_AUTO;
     int block_threads = 0;           // 0 = automatic
     int grid_per_cu = 0;             // 0 = automatic
@@ -288,6 +289,10 @@ extern "C" ara_status ara_ctx_create(int device, void *hip_stream, ara_ctx **out
         step = "pinned error word";
         e = hipHostMalloc(reinterpret_cast<void **>(&c->h_err), 64, hipHostMallocDefault);
     }
+    if (e == hipSuccess) {
+        step = "pinned sort plan";
+        e = hipHostMalloc(reinterpret_cast<void **>(&c->h_plan), 32 * sizeof(uint32_t), hipHostMallocDefault);
+    }
     if (e == hipSuccess) { step = "clear error word"; e = launch_fill_u32(c->d_err, 64, 0u, c->stream); }
     if (e == hipSuccess) { step = "synchronize"; e = hipStreamSynchronize(c->stream); }
     if (e != hipSuccess) {
@@ -297,6 +302,7 @@ extern "C" ara_status ara_ctx_create(int device, void *hip_stream, ara_ctx **out
         dev_free(c->d_out);
         if (c->h_out) (void)hipHostFree(c->h_out);
         if (c->h_err) (void)hipHostFree(c->h_err);
+        if (c->h_plan) (void)hipHostFree(c->h_plan);
         delete c;
         return ARA_E_DEVICE;
     }
@@ -313,6 +319,7 @@ extern "C" ara_status ara_ctx_destroy(ara_ctx *c) {
     dev_free(c->d_out);
     if (c->h_out) (void)hipHostFree(c->h_out);
     if (c->h_err) (void)hipHostFree(c->h_err);
+    if (c->h_plan) (void)hipHostFree(c->h_plan);
     delete c;
     return ARA_OK;
 }
@@ -887,7 +894,7 @@ extern "C" ara_status ara_sort_desc(ara_ctx *c, const double *in, int64_t n, dou
     bool owned = false;
     ara_status s = workspace_for(c, n, ws, ws_bytes, &w, &owned);
     if (s != ARA_OK) return s;
-    hipError_t e = launch_sort_desc_keys(in, n, w, c->stream);
+    hipError_t e = launch_sort_desc_keys(in, n, w, c->stream);   // stays asynchronous
     if (e == hipSuccess) e = launch_sort_decode(w, n, out, c->stream);
     s = e == hipSuccess ? ARA_OK : hip_fail(c, e, "sort");
     if (owned) {
@@ -926,7 +933,7 @@ extern "C" ara_status ara_risk_measures(ara_ctx *c, const double *ylt, int64_t n
     bool owned = false;
     s = workspace_for(c, n, ws, ws_bytes, &w, &owned);
     if (s == ARA_OK) {
-        hipError_t e = launch_sort_desc_keys(dy, n, w, c->stream);
+        hipError_t e = launch_sort_desc_keys(dy, n, w, c->stream, c->h_plan);
         if (e == hipSuccess && n_rp > 0) e = launch_risk(w, n, ks.data(), n_rp, c->d_out, c->stream);
         if (e == hipSuccess && n_rp > 0)
             e = hipMemcpyAsync(c->h_out, c->d_out, size_t(2 * n_rp) * 8, hipMemcpyDeviceToHost, c->stream);
@@ -1274,7 +1281,7 @@ extern "C" ara_status ara_batch_risk(ara_batch *b, const double *rps, int32_t n_
             if (e != hipSuccess) break;
             b->ws_bytes = need;
         }
-        e = launch_sort_desc_keys(b->jobs[size_t(j)].ylt, n, b->ws, c->stream);
+        e = launch_sort_desc_keys(b->jobs[size_t(j)].ylt, n, b->ws, c->stream, c->h_plan);
         // groups of 16 return periods, laid out like ara_risk_measures' staging
         if (e == hipSuccess) e = launch_risk(b->ws, n, &ks[size_t(j) * n_rp], n_rp, c->d_out, c->stream);
         if (e == hipSuccess)
@@ -1444,7 +1451,7 @@ static ara_status server_iteration(ara_server *sv, const std::vector<ServerReque
     if (e == hipSuccess) e = launch_risk_batch(sv->d_ylts, sv->d_ns, sv->d_ks, nj, nr, sv->d_res, sv->stream);
     for (int32_t i = 0; i < nj && e == hipSuccess; ++i) {
         if (hn[i] <= kRiskLdsKeys) continue;
-        e = launch_sort_desc_keys(sv->slots[size_t(i)].ylt, hn[i], sv->ws, sv->stream);
+        e = launch_sort_desc_keys(sv->slots[size_t(i)].ylt, hn[i], sv->ws, sv->stream, pc->h_plan);
         if (e == hipSuccess) e = launch_risk(sv->ws, hn[i], &hk[size_t(i) * nr], nr, sv->d_res + size_t(i) * 2 * nr, sv->stream);
     }
     if (e == hipSuccess)

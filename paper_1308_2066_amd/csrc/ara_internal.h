@@ -155,7 +155,8 @@ size_t trial_bitmap_table_capacity();
 
 // ---- order statistics
 size_t sort_workspace_bytes(int64_t n);
-hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStream_t s);   // sorted keys -> ws
+hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStream_t s,
+                                 uint32_t *host_plan = nullptr);   // sorted keys -> ws
 hipError_t launch_sort_decode(const void *ws, int64_t n, double *out, hipStream_t s);
 hipError_t launch_risk(const void *ws, int64_t n, const int64_t *ks, int n_k, double *out_pml_tvar,
                        hipStream_t s);

@@ -254,7 +254,11 @@ __global__ __launch_bounds__(256) void k_sort_decode(SortWs w, int64_t n, double
 }
 
 // Sorted descending keys of `in` end in the workspace key buffer the plan names.
-hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStream_t s) {
+// host_plan: pinned host memory of 32 words, or null.  With it, the host reads the
+// pass plan (one small copy and a wait) and launches only the passes that reorder
+// keys; without it every pass is launched and trivial ones return at once (for
+// callers that must not block).
+hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStream_t s, uint32_t *host_plan) {
     if (n <= 0) return hipSuccess;
     SortWs w = sort_ws(ws, n);
     const int64_t tiles = sort_tiles(n);
@@ -264,7 +268,15 @@ hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStrea
     hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(256), 0, s, w.hist, n, w.plan);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    bool skip[kPasses] = {};
+    if (host_plan) {
+        e = hipMemcpyAsync(host_plan, w.plan, 32 * sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        for (int p = 0; p < kPasses; ++p) skip[p] = host_plan[16 + p] != 0;
+    }
     for (int pass = 0; pass < kPasses; ++pass) {
+        if (skip[pass]) continue;
         hipLaunchKernelGGL(k_sort_count, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, w, n, pass, tiles);
         hipLaunchKernelGGL(k_sort_offsets, dim3(1), dim3(256), 0, s, w, pass, tiles);
         hipLaunchKernelGGL(k_sort_scatter, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, w, n, pass, tiles);

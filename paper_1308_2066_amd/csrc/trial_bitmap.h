@@ -143,7 +143,8 @@ __device__ __forceinline__ uint32_t seg_queue(const TrialArgs &a, const uint32_t
     }
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
-        e[s] = min(id[s], cmax);
+        // the packed copy was checked against the catalog when it was built
+        e[s] = P24 ? id[s] : min(id[s], cmax);
         w[s] = tab[e[s] >> 5];
     }
     const int l4 = lane * 4;

@@ -248,6 +248,27 @@ def test_occurrence_maximum_bit_exact(A, S, gpu_ctx, small, paper_reduced):
         assert np.asarray(pml).tobytes() == np.asarray(pml_o).tobytes()
 
 
+def test_bitmap_queue_overflow_all_events_flagged(A, S, gpu_ctx):
+    """Every catalog event has a nonzero occurrence-net loss, so every 256-event load
+    flags more events than the per-wave queue holds: the queue is resolved early,
+    slot by slot.  Checked against the oracle, with both ID encodings."""
+    rng = np.random.default_rng(97)
+    C = 40_000                                   # > 20,480 events: the LDS filter placement
+    ids_all = np.arange(C, dtype=np.int32)
+    elts = [(ids_all, rng.lognormal(8.0, 1.0, size=C)), (ids_all[::3].copy(), rng.lognormal(9.0, 1.0, size=len(ids_all[::3])))]
+    lengths = [2000, 1, 0, 1023, 1024, 1025, 4100, 3, 257, 2048] * 8
+    counts = np.asarray(lengths, np.int64)
+    offs = np.zeros(len(counts) + 1, np.int64)
+    np.cumsum(counts, out=offs[1:])
+    ids = rng.integers(0, C, size=int(offs[-1])).astype(np.int32)
+    w = synth.Workload("all-flagged", ids, offs, C, elts, (0.0, INF, 0.0, INF), None, (2.0,), 0)
+    _say("bitmap queue overflow")
+    ref = oracle.analyze_workload(w, threads=oracle.max_threads())
+    got = analyze(A, S, gpu_ctx, w, 1)
+    assert_ylt_close(got, ref, what="all flagged")
+    assert analyze(A, S, gpu_ctx, w, 1, packing=0).tobytes() == got.tobytes()
+
+
 def _catalog_lookup_reference(w, precision_f32=False):
     ids = np.arange(w.catalog_size, dtype=np.int32)
     offs = np.array([0, w.catalog_size], np.int64)
