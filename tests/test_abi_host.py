@@ -81,3 +81,14 @@ def test_no_device_is_reported_cleanly(ara_lib):
     out = ctypes.c_void_p()
     assert lib.ara_ctx_create(0, None, ctypes.byref(out)) == ara_lib.ARA_E_DEVICE
     assert out.value is None
+
+
+def test_c_client_compiles_against_header(ara_lib, tmp_path):
+    """A plain C11 program using only include/ara.h links against libara.so (gcc,
+    -Wall -Werror) and resolves it through its rpath: the boundary needs no Python."""
+    import subprocess
+    import __graft_entry__ as g
+    exe = g.build_c_client(str(tmp_path / "ara_c_client"))
+    r = subprocess.run(["ldd", exe], capture_output=True, text=True, check=True)
+    line = [ln for ln in r.stdout.splitlines() if "libara.so" in ln]
+    assert line and "not found" not in line[0], r.stdout
