@@ -39,21 +39,30 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-TRIAL_KERNEL = "k_trial_ylt_bitmap"
-# Sources that define the headline trial kernel; recorded counter readings stand
-# only while these are unchanged.
-TRIAL_KERNEL_SOURCES = ("paper_1308_2066_amd/csrc/k_trial_bitmap.hip", "paper_1308_2066_amd/csrc/trial_bitmap.h",
-                        "paper_1308_2066_amd/csrc/trial_common.h", "paper_1308_2066_amd/csrc/ara_internal.h")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_trial_ylt_bitmap.paper_1Mx1000_f64.traffic.txt")
+# The headline trial kernel of each placement that the paper-scale workload can take,
+# and the sources that define it (recorded counter readings stand only while these
+# are unchanged).  The paper-scale YET has a catalog-binned copy, so the default
+# placement is the tiled kernel; ARA_PLACE_LDS_BITMAP (--placement 1) measures the
+# LDS-filter kernel that reads the packed copy.
+KERNELS = {
+    "k_trial_tiled": ("paper_1308_2066_amd/csrc/k_trial_tiled.hip", "paper_1308_2066_amd/csrc/trial_common.h",
+                      "paper_1308_2066_amd/csrc/ara_internal.h"),
+    "k_trial_ylt_bitmap": ("paper_1308_2066_amd/csrc/k_trial_bitmap.hip", "paper_1308_2066_amd/csrc/trial_bitmap.h",
+                           "paper_1308_2066_amd/csrc/trial_common.h", "paper_1308_2066_amd/csrc/ara_internal.h"),
+}
+
+
+def traffic_file(kernel: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}.paper_1Mx1000_f64.traffic.txt")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_source_digest() -> str:
+def kernel_source_digest(kernel: str) -> str:
     h = hashlib.sha256()
-    for rel in TRIAL_KERNEL_SOURCES:
+    for rel in KERNELS[kernel]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(rel.encode() + b"\0" + f.read() + b"\0")
     return h.hexdigest()
@@ -70,18 +79,28 @@ def read_kv(path: str) -> dict:
     return out
 
 
-def recorded_traffic(args):
+def recorded_traffic(args, kernel: str):
     """HBM bytes per launch of the headline trial kernel from the committed counter
     summary, if it was taken on this workload with the current kernel sources."""
     if not (args.workload == "paper" and args.trials == 1_000_000 and args.precision == "f64"
-            and args.placement in (0, 1) and not args.block and not args.grid_per_cu and not args.no_packing):
+            and not args.block and not args.grid_per_cu and not args.no_packing and not args.no_binning):
         return None, "no counter summary for this configuration"
-    if not os.path.exists(TRAFFIC_FILE):
+    path = traffic_file(kernel)
+    if kernel not in KERNELS or not os.path.exists(path):
         return None, "no counter summary recorded"
-    kv = read_kv(TRAFFIC_FILE)
-    if kv.get("source_sha256") != kernel_source_digest():
+    kv = read_kv(path)
+    if kv.get("source_sha256") != kernel_source_digest(kernel):
         return None, "kernel changed since the counters were taken"
-    return float(kv["traffic_bytes"]), os.path.relpath(TRAFFIC_FILE, ROOT)
+    return float(kv["traffic_bytes"]), os.path.relpath(path, ROOT)
+
+
+def headline_kernel_in(rows) -> str:
+    """The headline trial kernel a rocprofv3 run recorded (the tiled kernel when present)."""
+    names = {r["Kernel_Name"] for r in rows}
+    for k in KERNELS:
+        if any(k in n for n in names):
+            return k
+    raise SystemExit(f"none of {list(KERNELS)} in the recorded dispatches")
 
 
 def cpu_baseline(w, target_s: float):
@@ -141,13 +160,14 @@ def derive_traffic(fetch_path: str, write_path: str, copy_mib: int, cmd: str):
     per dispatch, each scaled by the same counter's reading for the plain device
     copy of copy_mib MiB that the profiled run ends with."""
     copy_bytes = copy_mib << 20
+    kernel = headline_kernel_in(_counter_rows(fetch_path))
 
     def per_dispatch(path, counter):
         rows = [r for r in _counter_rows(path) if r["Counter_Name"] == counter]
-        kern = [float(r["Counter_Value"]) for r in rows if TRIAL_KERNEL in r["Kernel_Name"]]
+        kern = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
         copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
         if not kern or not copies:
-            raise SystemExit(f"{path}: no {TRIAL_KERNEL} or copy dispatches with {counter}")
+            raise SystemExit(f"{path}: no {kernel} or copy dispatches with {counter}")
         big = max(copies, key=lambda r: int(r["Grid_Size"]))
         return float(np.mean(kern)), len(kern), float(big["Counter_Value"])
 
@@ -157,13 +177,13 @@ def derive_traffic(fetch_path: str, write_path: str, copy_mib: int, cmd: str):
     w_scale = copy_bytes / 1024.0 / wc
     traffic = (fk * f_scale + wk * w_scale) * 1024.0
     lines = [
-        f"# HBM traffic of {TRIAL_KERNEL}, 1,000,000 trials x 1000 events, catalog 1,000,000, 16-ELT layer, binary64",
+        f"# HBM traffic of {kernel}, 1,000,000 trials x 1000 events, catalog 1,000,000, 16-ELT layer, binary64",
         f"# FETCH_SIZE pass: {cmd.format(counter='FETCH_SIZE')}",
         f"# WRITE_SIZE pass: {cmd.format(counter='WRITE_SIZE')}",
         "# Each counter is scaled by its own reading for a plain device copy of copy_bytes (the profiled run",
         "# ends with one): fetch_scale = copy KiB / FETCH_SIZE of the copy, likewise write_scale.",
-        f"kernel: {TRIAL_KERNEL}",
-        f"source_sha256: {kernel_source_digest()}",
+        f"kernel: {kernel}",
+        f"source_sha256: {kernel_source_digest(kernel)}",
         f"fetch_kib_per_dispatch: {fk:.1f}  (mean of {fn} dispatches)",
         f"write_kib_per_dispatch: {wk:.1f}  (mean of {wn} dispatches)",
         f"copy_bytes: {copy_bytes}",
@@ -173,7 +193,7 @@ def derive_traffic(fetch_path: str, write_path: str, copy_mib: int, cmd: str):
         f"write_scale: {w_scale:.4f}",
         f"traffic_bytes: {traffic:.6g}",
     ]
-    with open(TRAFFIC_FILE, "w") as f:
+    with open(traffic_file(kernel), "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
 
@@ -181,13 +201,15 @@ def derive_traffic(fetch_path: str, write_path: str, copy_mib: int, cmd: str):
 def summarize_counters(path: str, out_path: str, cmd: str):
     """Per-dispatch means of every counter of a rocprofv3 --pmc run for the headline
     kernel, with the L2 hit rate and busy fractions derived from them."""
-    rows = [r for r in _counter_rows(path) if TRIAL_KERNEL in r["Kernel_Name"]]
+    all_rows = _counter_rows(path)
+    kernel = headline_kernel_in(all_rows)
+    rows = [r for r in all_rows if kernel in r["Kernel_Name"]]
     per = {}
     for r in rows:
         per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
     m = {k: float(np.mean(v)) for k, v in per.items()}
     n = len(next(iter(per.values()))) if per else 0
-    lines = [f"# rocprofv3 counters of {TRIAL_KERNEL}, 1,000,000 trials x 1000 events, catalog 1,000,000, "
+    lines = [f"# rocprofv3 counters of {kernel}, 1,000,000 trials x 1000 events, catalog 1,000,000, "
              f"16-ELT layer, binary64 (mean of {n} dispatches)", f"# command: {cmd}", ""]
     lines += [f"{k}: {v:.6g}" for k, v in sorted(m.items())]
     if "TCC_HIT_sum" in m and "TCC_MISS_sum" in m:
@@ -479,6 +501,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid-per-cu", type=int, default=0)
     ap.add_argument("--no-packing", action="store_true", help="stream int32 IDs instead of the packed YET copy")
+    ap.add_argument("--no-binning", action="store_true", help="no catalog-binned YET copy (no tiled kernel)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle sample time (0 = skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
@@ -534,6 +557,7 @@ def main():
     ara.ara_set_option(ctx, ara.ARA_OPT_BLOCK_THREADS, args.block)
     ara.ara_set_option(ctx, ara.ARA_OPT_GRID_PER_CU, args.grid_per_cu)
     ara.ara_set_option(ctx, ara.ARA_OPT_YET_PACKING, 0 if args.no_packing else 1)
+    ara.ara_set_option(ctx, ara.ARA_OPT_YET_BINNING, 0 if args.no_binning else 1)
     prec = ara.ARA_F32 if args.precision == "f32" else ara.ARA_F64
     t = time.time()
     an = session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
@@ -542,6 +566,12 @@ def main():
     log(f"uploaded + validated in {time.time() - t:.1f}s")
     n_flagged, placement, lds_bytes = ara.ara_layer_stats(ctx, an.layer)
     id_bytes = ara.ara_yet_info(an.yet)[2]
+    # the layer alone would take the LDS filter; with the YET's binned copy the
+    # analysis takes the tiled kernel unless a placement is forced
+    if id_bytes == 2 and placement == ara.ARA_PLACE_LDS_BITMAP and args.placement in (0, ara.ARA_PLACE_LDS_TILES):
+        placement = ara.ARA_PLACE_LDS_TILES
+    kernel = {ara.ARA_PLACE_LDS_TILES: "k_trial_tiled", ara.ARA_PLACE_LDS_BITMAP: "k_trial_ylt_bitmap"}.get(
+        placement, "k_trial_ylt")
     log(f"placement={ara.PLACEMENT_NAMES.get(placement, placement)} lds={lds_bytes} flagged={n_flagged}")
 
     ylt = torch.empty(w.n_trials, dtype=torch.float64, device="cuda")
@@ -576,10 +606,18 @@ def main():
         f"(min {min(kern_ms):.4f}, max {max(kern_ms):.4f}); PML {pml.tolist()} TVaR {tvar.tolist()}")
 
     nblk = (w.catalog_size + 127) // 128
-    # algorithmic bytes are defined on int32 event IDs; the kernel may stream the
-    # YET's packed 3-byte copy, reported beside them as moved_bytes
+    # algorithmic bytes are defined on int32 event IDs and int64 trial offsets; the
+    # kernels stream other forms, reported beside them as moved_bytes: the packed
+    # 3-byte copy with the same offsets, or the binned 2-byte copy with a 4-byte
+    # offset per (catalog bin, trial) instead of the trial offsets
     alg_bytes = 4 * w.n_events + 8 * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * n_flagged
-    moved_bytes = alg_bytes - (4 - id_bytes) * w.n_events
+    if kernel == "k_trial_tiled":
+        n_bins = (w.catalog_size + 32767) // 32768
+        moved_bytes = 2 * w.n_events + 4 * n_bins * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * n_flagged
+    else:
+        ib = 3 if not args.no_packing and w.catalog_size <= 1 << 24 else 4   # the packed copy, else int32
+        moved_bytes = alg_bytes - (4 - ib) * w.n_events
+        id_bytes = ib
     achieved = alg_bytes / (k_avg * 1e-3) / 1e9
     te = float(w.n_events)   # trial-events x layers (1 layer)
     value = te / (ms_step * 1e-3)
@@ -595,7 +633,7 @@ def main():
     ara.ara_ctx_destroy(ctx)
 
     cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
-    traffic, traffic_note = recorded_traffic(args)
+    traffic, traffic_note = recorded_traffic(args, kernel)
 
     out = {
         "metric": "trial-events·layers/s (1M trials x 1000 events, 16-ELT layer, whole path incl. sort + PML/TVaR)",
@@ -615,7 +653,7 @@ def main():
                    "placement": ara.PLACEMENT_NAMES.get(placement, str(placement)), "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": TRIAL_KERNEL if placement == ara.ARA_PLACE_LDS_BITMAP else "k_trial_ylt",
+                     "kernel": kernel,
                      "kernel_ms": k_avg, "algorithmic_bytes": alg_bytes, "yet_id_bytes": id_bytes,
                      "moved_bytes": moved_bytes, "traffic_source": traffic_note},
         "cpu_baseline": cpu,

@@ -89,7 +89,11 @@ typedef enum ara_placement {
     ARA_PLACE_AUTO = 0,         /* pick from the catalog size (default)                              */
     ARA_PLACE_LDS_BITMAP = 1,   /* LDS: 1 bit/event "occurrence loss nonzero" + ranks; values in L2  */
     ARA_PLACE_LDS_DENSE = 2,    /* LDS: the whole combined table (small catalogs)                    */
-    ARA_PLACE_GLOBAL_DENSE = 3  /* HBM/L2: the whole combined table, gathered per occurrence         */
+    ARA_PLACE_GLOBAL_DENSE = 3, /* HBM/L2: the whole combined table, gathered per occurrence         */
+    ARA_PLACE_LDS_TILES = 4     /* LDS: the filter and its nonzero values, one catalog tile at a time,
+                                   each tile's occurrences streamed from the YET's binned copy (needs
+                                   one: see ara_yet_create).  AUTO picks it when the YET has a binned
+                                   copy and the dense table does not fit in LDS                    */
 } ara_placement;
 
 /* Context options (ara_set_option). */
@@ -99,10 +103,12 @@ typedef enum ara_option {
     ARA_OPT_GRID_PER_CU = 3,    /* workgroups per compute unit of the trial kernel (1..64; 0 = auto)  */
     ARA_OPT_YET_PACKING = 4,    /* 1 (default): YETs created later also keep a packed copy of their
                                    event IDs when catalog_size <= 2^24; 0: never                      */
-    ARA_OPT_TRIAL_MODE = 5      /* dense-table YLT kernels: 0 (default) = one lane per trial when the
+    ARA_OPT_TRIAL_MODE = 5,     /* dense-table YLT kernels: 0 (default) = one lane per trial when the
                                    YET averages <= 256 occurrences per trial, else one wave per
                                    trial; 1 = always a wave; 2 = always a lane.  A lane adds its
                                    trial's values in time order (the sequential sum)               */
+    ARA_OPT_YET_BINNING = 6     /* 1 (default): YETs created later also keep a catalog-binned copy
+                                   where it applies (see ara_yet_create); 0: never                 */
 } ara_option;
 
 typedef struct ara_ctx ara_ctx;
@@ -168,6 +174,15 @@ ara_status ara_sync(ara_ctx *ctx);
  * endian, in 12-byte groups of 4 events), owned by the handle; the YLT kernels then
  * stream that copy (3 instead of 4 bytes per occurrence).  Borrowed arrays must not
  * change while the handle lives: later analyses may read either form.
+ * Binned copy: when ARA_OPT_YET_BINNING is 1, the catalog is larger than a dense
+ * table in LDS (more than 20480 events) and at most 2^24 events, every trial has
+ * fewer than 2^31 occurrences in each 2^15-event catalog bin, and the per-bin offsets
+ * (4 bytes per trial and bin) stay below a quarter of the 2-byte IDs, the library also
+ * stores the occurrences regrouped by catalog bin: bin by bin, each trial's
+ * occurrences of that bin's events in time order as 2-byte IDs within the bin, with
+ * per-(bin, trial) offsets.  Analyses of layers whose table does not fit in LDS then
+ * read that copy (ARA_PLACE_LDS_TILES).  If the device has no memory for it, the
+ * handle is created without it.
  * Errors: ARA_E_INVALID_ARG, ARA_E_EVENT_ID_RANGE, ARA_E_BAD_OFFSETS, ARA_E_OOM, ARA_E_DEVICE. */
 ara_status ara_yet_create(ara_ctx *ctx, const int32_t *event_ids, int64_t n_events,
                           const int64_t *trial_offsets, int64_t n_trials, int32_t catalog_size,
@@ -175,7 +190,8 @@ ara_status ara_yet_create(ara_ctx *ctx, const int32_t *event_ids, int64_t n_even
 ara_status ara_yet_release(ara_yet *yet);
 
 /* Sizes of a YET handle and the bytes per event ID of the form the YLT kernels read
- * (4, or 3 with a packed copy).  Any output pointer may be NULL. */
+ * for layers whose table does not fit in LDS: 2 with a binned copy, else 3 with a
+ * packed copy, else 4.  Any output pointer may be NULL. */
 ara_status ara_yet_info(const ara_yet *yet, int64_t *n_events, int64_t *n_trials, int32_t *id_bytes);
 
 /* ---------------------------------------------------------------- Event Loss Table

@@ -52,17 +52,19 @@ ARA_PLACE_AUTO = 0
 ARA_PLACE_LDS_BITMAP = 1
 ARA_PLACE_LDS_DENSE = 2
 ARA_PLACE_GLOBAL_DENSE = 3
+ARA_PLACE_LDS_TILES = 4
 
 ARA_OPT_PLACEMENT = 1
 ARA_OPT_BLOCK_THREADS = 2
 ARA_OPT_GRID_PER_CU = 3
 ARA_OPT_YET_PACKING = 4
 ARA_OPT_TRIAL_MODE = 5
+ARA_OPT_YET_BINNING = 6
 
 ARA_BUILD_TABLES = 1
 
 PLACEMENT_NAMES = {ARA_PLACE_LDS_BITMAP: "lds_bitmap", ARA_PLACE_LDS_DENSE: "lds_dense",
-                   ARA_PLACE_GLOBAL_DENSE: "global_dense"}
+                   ARA_PLACE_GLOBAL_DENSE: "global_dense", ARA_PLACE_LDS_TILES: "lds_tiles"}
 
 
 class ara_layer_terms(ctypes.Structure):
@@ -275,8 +277,9 @@ def ara_yet_release(y: Yet):
 
 
 def ara_yet_info(y: Yet):
-    """(n_events, n_trials, id_bytes): id_bytes is 3 when the YLT kernels read the
-    handle's packed copy of the event IDs, else 4."""
+    """(n_events, n_trials, id_bytes): id_bytes is 2 when the handle has a catalog-binned
+    copy (read by the tiled kernel for layers whose table does not fit in LDS), else 3
+    with a packed copy of the event IDs, else 4."""
     ne, nt, b = _I64(), _I64(), _I32()
     _check(_lib.ara_yet_info(y.ptr, ctypes.byref(ne), ctypes.byref(nt), ctypes.byref(b)), y.ctx, "ara_yet_info")
     return int(ne.value), int(nt.value), int(b.value)

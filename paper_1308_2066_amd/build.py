@@ -17,7 +17,8 @@ LIB = os.path.join(PKG, "libara.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["abi.hip", "k_ingest.hip", "k_layer.hip", "k_trial.hip", "k_trial_bitmap.hip", "k_batch.hip", "k_sort.hip"]
+SOURCES = ["abi.hip", "k_ingest.hip", "k_bin.hip", "k_layer.hip", "k_trial.hip", "k_trial_bitmap.hip", "k_trial_tiled.hip",
+           "k_batch.hip", "k_sort.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

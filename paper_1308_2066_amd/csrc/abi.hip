@@ -33,6 +33,7 @@ struct ara_ctx {
     int block_threads = 0;           // 0 = automatic
     int grid_per_cu = 0;             // 0 = automatic
     int yet_packing = 1;             // keep a packed copy of YET IDs where they fit 24 bits
+    int yet_binning = 1;             // keep a catalog-binned copy of YET IDs where it applies
     int trial_mode = 0;              // 0 = by trial length, 1 = wave per trial, 2 = lane per trial
     std::map<std::string, std::pair<int64_t, bool>> tuned;   // batch shape -> (events per item, interleave)
     int live = 0;                    // handles alive on this context
@@ -47,6 +48,12 @@ struct ara_yet {
     int32_t catalog;
     bool owns;
     uint8_t *ids24;    // packed copy (owned), or null
+    // catalog-binned copy (owned), or null ids16
+    uint16_t *ids16 = nullptr;
+    uint32_t *boff = nullptr;     // n_bins rows of `stride` entries
+    int64_t *region = nullptr;    // n_bins + 1 element offsets
+    int64_t stride = 0;
+    int32_t n_bins = 0;
 };
 
 struct ara_elt {
@@ -159,16 +166,36 @@ static int bitmap_qcap(int32_t catalog, int wpb, int lds_max) {
 }
 
 // Chooses where the layer's table lives during the trial kernel and the launch shape.
-// mean_len: mean occurrences per trial of the YET (decides lane or wave per trial)
-static ara_status plan_trial(ara_ctx *c, const ara_layer *L, int64_t n_trials, double mean_len, TrialLaunch &tl) {
+// mean_len: mean occurrences per trial of the YET (decides lane or wave per trial);
+// tiles: kNoTiles for paths without a tiled kernel (a forced tiled placement runs them
+// with the LDS bitmap), else whether the YET has a catalog-binned copy.
+enum { kNoTiles = -1 };
+static ara_status plan_trial(ara_ctx *c, const ara_layer *L, int64_t n_trials, double mean_len, TrialLaunch &tl,
+                             int tiles = kNoTiles) {
     int pl = c->placement;
+    const bool binned = tiles > 0;
+    if (pl == ARA_PLACE_LDS_TILES && tiles == kNoTiles) pl = ARA_PLACE_LDS_BITMAP;
     const int64_t dense = int64_t(L->catalog) * 8;
     const int block_bitmap = c->block_threads ? c->block_threads : 1024;
     const int qcap = bitmap_qcap(L->catalog, block_bitmap / 64, c->lds_max);
     if (pl == ARA_PLACE_AUTO) {
         if (dense <= c->lds_max) pl = ARA_PLACE_LDS_DENSE;
+        else if (binned && c->lds_max >= kLdsMaxBytes) pl = ARA_PLACE_LDS_TILES;
         else if (qcap > 0) pl = ARA_PLACE_LDS_BITMAP;
         else pl = ARA_PLACE_GLOBAL_DENSE;
+    }
+    if (pl == ARA_PLACE_LDS_TILES) {
+        if (!binned || c->lds_max < kLdsMaxBytes)
+            return fail(c, ARA_E_UNSUPPORTED, "tiled placement needs a YET with a binned copy and %d bytes of LDS",
+                        kLdsMaxBytes);
+        tl.placement = pl;
+        tl.f32 = L->f32;
+        tl.lds_bytes = size_t(kLdsMaxBytes);
+        tl.qcap = 0;
+        tl.lane = false;
+        tl.block = kTiledWaves * 64;
+        tl.grid = int(std::max<int64_t>(1, std::min<int64_t>(c->n_cu, (n_trials + 63) / 64)));
+        return ARA_OK;
     }
     int64_t lds = 0;
     if (pl == ARA_PLACE_LDS_DENSE) {
@@ -334,7 +361,7 @@ extern "C" ara_status ara_set_option(ara_ctx *c, int option, int64_t v) {
     if (!c) return ARA_E_INVALID_ARG;
     switch (option) {
     case ARA_OPT_PLACEMENT:
-        if (v < ARA_PLACE_AUTO || v > ARA_PLACE_GLOBAL_DENSE) return fail(c, ARA_E_INVALID_ARG, "bad placement %lld", (long long)v);
+        if (v < ARA_PLACE_AUTO || v > ARA_PLACE_LDS_TILES) return fail(c, ARA_E_INVALID_ARG, "bad placement %lld", (long long)v);
         c->placement = int(v);
         return ARA_OK;
     case ARA_OPT_BLOCK_THREADS:
@@ -353,6 +380,10 @@ extern "C" ara_status ara_set_option(ara_ctx *c, int option, int64_t v) {
         if (v != 0 && v != 1) return fail(c, ARA_E_INVALID_ARG, "bad packing flag %lld", (long long)v);
         c->yet_packing = int(v);
         return ARA_OK;
+    case ARA_OPT_YET_BINNING:
+        if (v != 0 && v != 1) return fail(c, ARA_E_INVALID_ARG, "bad binning flag %lld", (long long)v);
+        c->yet_binning = int(v);
+        return ARA_OK;
     default:
         return fail(c, ARA_E_INVALID_ARG, "unknown option %d", option);
     }
@@ -365,6 +396,70 @@ extern "C" ara_status ara_sync(ara_ctx *c) {
 }
 
 // ------------------------------------------------------------------ YET
+static void yet_free_binned(ara_yet *y) {
+    dev_free(y->ids16);
+    dev_free(y->boff);
+    dev_free(y->region);
+    y->ids16 = nullptr;
+    y->boff = nullptr;
+    y->region = nullptr;
+    y->n_bins = 0;
+}
+
+// Builds the catalog-binned copy when it applies (see ara_yet_create); the YET is
+// usable without it, so running out of device memory only skips it.
+static ara_status yet_build_binned(ara_ctx *c, ara_yet *y) {
+    const int32_t nb = catalog_bins(y->catalog);
+    const int64_t n = y->n_trials;
+    if (!c->yet_binning || y->n_events == 0 || n == 0 || int64_t(y->catalog) * 8 <= int64_t(c->lds_max) ||
+        y->catalog > kMaxPackedCatalog || nb > kMaxBins || (n + 1 + 4095) / 4096 > 65535 ||
+        4.0 * double(nb) * double(n) > 0.25 * 2.0 * double(y->n_events))
+        return ARA_OK;
+    y->stride = (n + 1 + 3) & ~int64_t(3);
+    uint32_t *sums = nullptr;
+    ara_status s = dev_alloc(c, &y->boff, size_t(nb) * size_t(y->stride) * 4, "binned yet offsets");
+    if (s == ARA_OK) s = dev_alloc(c, &sums, bin_scan_scratch_words(n + 1, nb) * 4, "binned yet scan");
+    if (s == ARA_OK) {
+        hipError_t e = launch_bin_count(y->ids, y->offs, n, nb, y->boff, y->stride, c->stream);
+        if (e == hipSuccess) e = launch_bin_scan(y->boff, y->stride, n + 1, nb, sums, c->stream);
+        std::vector<uint32_t> len(static_cast<size_t>(nb));
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(len.data(), 4, y->boff + n, size_t(y->stride) * 4, 4, size_t(nb), hipMemcpyDeviceToHost,
+                                 c->stream);
+        s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet offsets");
+        std::vector<int64_t> region(static_cast<size_t>(nb) + 1, 0);
+        bool fits = true;
+        for (int32_t b = 0; s == ARA_OK && b < nb; ++b) {
+            fits = fits && len[size_t(b)] < (1u << 31);
+            region[size_t(b) + 1] = region[size_t(b)] + ((int64_t(len[size_t(b)]) + 7) & ~int64_t(7));
+        }
+        if (s == ARA_OK && !fits) {
+            dev_free(sums);
+            yet_free_binned(y);
+            return ARA_OK;
+        }
+        if (s == ARA_OK) s = dev_alloc(c, &y->region, region.size() * 8, "binned yet regions");
+        if (s == ARA_OK) s = dev_alloc(c, &y->ids16, size_t(region.back()) * 2 + 16, "binned yet ids");
+        if (s == ARA_OK) {
+            e = hipMemcpy(y->region, region.data(), region.size() * 8, hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = launch_bin_scatter(y->ids, y->offs, n, nb, y->boff, y->stride, y->region, y->ids16, c->stream);
+            s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet scatter");
+        }
+    }
+    dev_free(sums);
+    if (s == ARA_OK) {
+        y->n_bins = nb;
+        return ARA_OK;
+    }
+    yet_free_binned(y);
+    if (s == ARA_E_OOM) {
+        c->msg.clear();
+        return ARA_OK;
+    }
+    return s;
+}
+
 extern "C" ara_status ara_yet_create(ara_ctx *c, const int32_t *ids, int64_t n_events, const int64_t *offs,
                                     int64_t n_trials, int32_t catalog, ara_mem mem, ara_yet **out) {
     if (!c || !out) return ARA_E_INVALID_ARG;
@@ -408,12 +503,14 @@ extern "C" ara_status ara_yet_create(ara_ctx *c, const int32_t *ids, int64_t n_e
             s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "pack yet");
         }
     }
+    if (s == ARA_OK) s = yet_build_binned(c, y);
     if (s != ARA_OK) {
         if (y->owns) {
             dev_free(const_cast<int32_t *>(y->ids));
             dev_free(const_cast<int64_t *>(y->offs));
         }
         dev_free(y->ids24);
+        yet_free_binned(y);
         delete y;
         return s;
     }
@@ -431,6 +528,7 @@ extern "C" ara_status ara_yet_release(ara_yet *y) {
         dev_free(const_cast<int64_t *>(y->offs));
     }
     dev_free(y->ids24);
+    yet_free_binned(y);
     y->ctx->live--;
     delete y;
     return ARA_OK;
@@ -440,7 +538,7 @@ extern "C" ara_status ara_yet_info(const ara_yet *y, int64_t *n_events, int64_t 
     if (!y) return ARA_E_INVALID_ARG;
     if (n_events) *n_events = y->n_events;
     if (n_trials) *n_trials = y->n_trials;
-    if (id_bytes) *id_bytes = y->ids24 ? 3 : 4;
+    if (id_bytes) *id_bytes = y->ids16 ? 2 : (y->ids24 ? 3 : 4);
     return ARA_OK;
 }
 
@@ -563,6 +661,8 @@ static void layer_free(ara_layer *L) {
     dev_free(L->t.base32);
     dev_free(L->t.vals);
     dev_free(L->t.n_flagged);
+    dev_free(L->t.tiles);
+    dev_free(L->t.n_tiles);
     delete L;
 }
 
@@ -603,6 +703,8 @@ extern "C" ara_status ara_layer_create(ara_ctx *c, ara_elt *const *elts, int32_t
     if (s == ARA_OK) s = dev_alloc(c, &L->t.base32, align16(size_t(bitmap_supers(nblk)) * 4), "layer rank bases");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.vals, size_t(catalog) * 8, "layer values");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.n_flagged, 16, "layer count");
+    if (s == ARA_OK) s = dev_alloc(c, &L->t.tiles, sizeof(Tile) * size_t(max_tiles(catalog)), "layer tiles");
+    if (s == ARA_OK) s = dev_alloc(c, &L->t.n_tiles, 16, "layer tile count");
     if (s == ARA_OK && n_elts > 0) {
         hipError_t e = hipMemcpy(L->d_descs, d.data(), sizeof(EltDesc) * size_t(n_elts), hipMemcpyHostToDevice);
         if (e != hipSuccess) s = hip_fail(c, e, "layer descriptors upload");
@@ -688,6 +790,27 @@ static TrialArgs trial_args(const ara_yet *y, const ara_layer *L, int64_t t0, in
     return a;
 }
 
+// Arguments of the tiled trial kernel for trials [t0, t1) over `grid` workgroups.
+static TiledArgs tiled_args(const ara_yet *y, const ara_layer *L, int64_t t0, int64_t t1, double *ylt, int grid) {
+    TiledArgs a{};
+    a.ids16 = y->ids16;
+    a.region = y->region;
+    a.boff = y->boff;
+    a.stride = y->stride;
+    a.t_begin = t0;
+    a.t_end = t1;
+    a.per_wg = (t1 - t0 + grid - 1) / std::max(1, grid);
+    a.bitmap = L->t.bitmap;
+    a.rank = L->t.rank;
+    a.vals = L->t.vals;
+    a.tiles = L->t.tiles;
+    a.n_tiles = L->t.n_tiles;
+    a.agg_r = L->terms.agg_retention;
+    a.agg_l = L->terms.agg_limit;
+    a.ylt = ylt;
+    return a;
+}
+
 static ara_status check_analysis(ara_ctx *c, const ara_yet *y, const ara_layer *L, int64_t t0, int64_t t1) {
     if (!c || !y || !L || y->ctx != c || L->ctx != c) return ARA_E_INVALID_ARG;
     if (t0 < 0 || t1 < t0 || t1 > y->n_trials) return fail(c, ARA_E_INVALID_ARG, "trial range [%lld, %lld) outside [0, %lld)",
@@ -704,7 +827,8 @@ extern "C" ara_status ara_analyze(ara_ctx *c, const ara_yet *y, const ara_layer 
     if (t1 == t0) return ARA_OK;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     TrialLaunch tl{};
-    s = plan_trial(c, L, t1 - t0, y->n_trials ? double(y->n_events) / double(y->n_trials) : 0.0, tl);
+    s = plan_trial(c, L, t1 - t0, y->n_trials ? double(y->n_events) / double(y->n_trials) : 0.0, tl,
+                   y->ids16 ? 1 : 0);
     if (s != ARA_OK) return s;
     double *dst = ylt;
     if (mem == ARA_MEM_HOST) {
@@ -716,6 +840,10 @@ extern "C" ara_status ara_analyze(ara_ctx *c, const ara_yet *y, const ara_layer 
     hipError_t e = hipSuccess;
     for (int64_t tb = t0; tb < t1 && e == hipSuccess; tb += kMaxTrialsPerLaunch) {
         const int64_t te = std::min(t1, tb + kMaxTrialsPerLaunch);
+        if (tl.placement == ARA_PLACE_LDS_TILES) {
+            e = launch_trial_tiled(tiled_args(y, L, tb, te, dst + (tb - t0), tl.grid), tl.grid, c->stream);
+            continue;
+        }
         TrialArgs a = trial_args(y, L, tb, te, dst + (tb - t0));
         a.qcap = tl.qcap;
         e = launch_trial_ylt(a, tl, c->stream);
@@ -960,6 +1088,7 @@ struct ara_batch {
     std::vector<ara_job> jobs;
     std::vector<BatchJob> hjobs;
     std::vector<int64_t> mean_len;   // per job: occurrences per trial of its YET (at least 1)
+    std::vector<std::pair<TiledArgs, int>> tiled;   // jobs run by the tiled kernel, with their grids
     std::string shape;               // key of the tuning cache
     BatchJob *d_jobs = nullptr;
     BatchItem *d_items = nullptr;
@@ -1013,9 +1142,11 @@ static void batch_shape(int32_t n_items, int n_cu, int32_t &grid, int32_t &per_w
 }
 
 // One persistent launch per mode present, in mode order; interleave: workgroups take
-// every G-th item instead of a contiguous run.
+// every G-th item instead of a contiguous run.  Jobs of the tiled kernel follow, one
+// launch each.
 static hipError_t launch_grouped(const BatchJob *d_jobs, const BatchItem *d_items, const int32_t *off,
-                                 const int32_t *cnt, int n_cu, bool interleave, hipStream_t s) {
+                                 const int32_t *cnt, int n_cu, bool interleave, hipStream_t s,
+                                 const std::vector<std::pair<TiledArgs, int>> &tiled) {
     for (int m = 0; m < kBatchModes; ++m) {
         if (cnt[m] == 0) continue;
         int32_t grid = 1, per_wg = 0;
@@ -1025,6 +1156,10 @@ static hipError_t launch_grouped(const BatchJob *d_jobs, const BatchItem *d_item
             per_wg = 0;
         }
         const hipError_t e = launch_batch(m, d_jobs, d_items + off[m], cnt[m], per_wg, grid, s);
+        if (e != hipSuccess) return e;
+    }
+    for (const auto &ta : tiled) {
+        const hipError_t e = launch_trial_tiled(ta.first, ta.second, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1072,7 +1207,7 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
         if (s == ARA_OK && jb.trial_end > jb.trial_begin && !jb.ylt) s = fail(c, ARA_E_INVALID_ARG, "job %d: no YLT", j);
         TrialLaunch tl{};
         const double mean = jb.yet && jb.yet->n_trials ? double(jb.yet->n_events) / double(jb.yet->n_trials) : 0.0;
-        if (s == ARA_OK) s = plan_trial(c, jb.layer, jb.trial_end - jb.trial_begin, mean, tl);
+        if (s == ARA_OK) s = plan_trial(c, jb.layer, jb.trial_end - jb.trial_begin, mean, tl, jb.yet->ids16 ? 1 : 0);
         if (s != ARA_OK) {
             delete b;
             return s;
@@ -1082,6 +1217,8 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
         h.a.qcap = tl.qcap;
         h.mode = batch_mode(tl, h.a.ids24 != nullptr);
         h.placement = tl.placement;
+        if (h.mode == kModeTiled && jb.trial_end > jb.trial_begin)
+            b->tiled.emplace_back(tiled_args(jb.yet, jb.layer, jb.trial_begin, jb.trial_end, jb.ylt, tl.grid), tl.grid);
         b->jobs.push_back(jb);
         b->hjobs.push_back(h);
         b->mean_len.push_back(std::max<int64_t>(1, int64_t(std::llround(mean))));
@@ -1134,7 +1271,7 @@ static ara_status batch_tune(ara_batch *b) {
         for (bool inter : {false, true}) {
             e = hipEventRecord(e0, c->stream);
             if (e == hipSuccess)
-                e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, inter, c->stream);
+                e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, inter, c->stream, b->tiled);
             if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -1164,7 +1301,7 @@ static ara_status batch_capture(ara_batch *b) {
     ara_ctx *c = b->ctx;
     HIP_OR_RETURN(c, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream");
     HIP_OR_RETURN(c, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
-    hipError_t e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, b->interleave, b->cap);
+    hipError_t e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, b->interleave, b->cap, b->tiled);
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e == hipSuccess) e = e2;
@@ -1391,6 +1528,7 @@ static ara_status server_iteration(ara_server *sv, const std::vector<ServerReque
                                                                                          double(sv->yet->n_trials))))
                                            : 1;
     std::vector<BatchItem> items;
+    std::vector<std::pair<TiledArgs, int>> tiled;
     for (size_t i = 0; i < reqs.size(); ++i) {
         ServerRequest *r = reqs[i];
         ara_layer *L = sv->slots[i].L;
@@ -1413,7 +1551,8 @@ static ara_status server_iteration(ara_server *sv, const std::vector<ServerReque
             e = launch_layer_filter(L->catalog, L->f32, r->terms.occ_retention, r->terms.occ_limit, L->t, sv->stream);
         if (e != hipSuccess) return hip_fail(pc, e, "server layer build");
         TrialLaunch tl{};
-        ara_status s = plan_trial(pc, L, r->t1 - r->t0, double(sv->yet->n_events) / double(std::max<int64_t>(1, sv->yet->n_trials)), tl);
+        ara_status s = plan_trial(pc, L, r->t1 - r->t0, double(sv->yet->n_events) / double(std::max<int64_t>(1, sv->yet->n_trials)), tl,
+                                  sv->yet->ids16 ? 1 : 0);
         if (s != ARA_OK) return s;
         BatchJob &h = sv->h_jobs[i];
         h.a = trial_args(sv->yet, L, r->t0, r->t1, sv->slots[i].ylt);
@@ -1421,6 +1560,8 @@ static ara_status server_iteration(ara_server *sv, const std::vector<ServerReque
         h.a.qcap = tl.qcap;
         h.mode = batch_mode(tl, h.a.ids24 != nullptr);
         h.placement = tl.placement;
+        if (h.mode == kModeTiled)
+            tiled.emplace_back(tiled_args(sv->yet, L, r->t0, r->t1, sv->slots[i].ylt, tl.grid), tl.grid);
     }
     {
         std::vector<BatchJob> hj(sv->h_jobs, sv->h_jobs + reqs.size());
@@ -1438,7 +1579,7 @@ static ara_status server_iteration(ara_server *sv, const std::vector<ServerReque
     if (e == hipSuccess)
         e = hipMemcpyAsync(sv->d_items, sv->h_items, sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice, sv->stream);
     if (e == hipSuccess)
-        e = launch_grouped(sv->d_jobs, sv->d_items, sv->mode_off, sv->mode_cnt, pc->n_cu, true, sv->stream);
+        e = launch_grouped(sv->d_jobs, sv->d_items, sv->mode_off, sv->mode_cnt, pc->n_cu, true, sv->stream, tiled);
     // risk measures: ranks per request, short YLTs in one launch, long ones one by one
     int64_t *hn = sv->h_nks, *hk = sv->h_nks + sv->slots.size();
     for (int32_t i = 0; i < nj && e == hipSuccess; ++i) {

@@ -37,6 +37,8 @@ struct EltDesc {
 //   base32  per superblock (32768 events): number of flagged events before it
 //   occ     catalog binary64 values: occurrence-net loss min(max(comb[e]-OccR,0),OccL)
 //   vals    occ values of the flagged events, in event order (binary64)
+//   tiles   the filter cut into LDS-sized tiles for the tiled trial kernel
+struct Tile;
 struct LayerTables {
     void *comb = nullptr;
     double *occ = nullptr;
@@ -46,6 +48,8 @@ struct LayerTables {
     uint32_t *base32 = nullptr;
     double *vals = nullptr;
     uint32_t *n_flagged = nullptr;
+    Tile *tiles = nullptr;
+    uint32_t *n_tiles = nullptr;
     int32_t nblk = 0;
 };
 
@@ -129,7 +133,8 @@ enum BatchMode : int32_t {
     kModeWaveLds = 2,      // wave per trial, dense table in LDS
     kModeWaveGlobal = 3,   // wave per trial, dense table in HBM/L2
     kModeWaveBitmap = 4,   // wave per trial, LDS filter, int32 IDs
-    kModeWaveBitmap24 = 5  // wave per trial, LDS filter, packed IDs
+    kModeWaveBitmap24 = 5, // wave per trial, LDS filter, packed IDs
+    kModeTiled = 6         // the tiled kernel, launched on its own (not part of k_batch)
 };
 struct BatchJob {
     TrialArgs a;           // t_begin/t_end/ylt: the job's whole range
@@ -152,6 +157,67 @@ hipError_t launch_risk_batch(const double *const *ylts, const int64_t *ns, const
 // bitmap placement (static LDS: filter tables up to trial_bitmap_table_capacity() bytes + event queues)
 hipError_t launch_trial_ylt_bitmap(const TrialArgs &a, int grid, int block, hipStream_t s);
 size_t trial_bitmap_table_capacity();
+
+// ---- catalog-binned YET copy and the tiled trial kernel
+// The catalog is cut into bins of 2^15 events.  The binned copy holds, bin by bin
+// (bin-major), every trial's occurrences of that bin's events in trial order (time
+// order within a trial) as 15-bit IDs local to the bin, one uint16 each.  Region b
+// starts at element region[b] (a multiple of 8); boff[b * stride + t] is where trial
+// t's run starts inside region b (trial t's occurrences of bin b are
+// [boff[b][t], boff[b][t + 1])), t = 0..n_trials.
+constexpr int kBinShift = 15;
+constexpr int32_t kBinEvents = 1 << kBinShift;
+constexpr int kBlocksPerBin = kBinEvents / kEventsPerBlock;   // 256
+constexpr int kMaxBins = 512;                                 // catalogs up to 2^24 events
+inline int32_t catalog_bins(int32_t catalog) { return (catalog + kBinEvents - 1) / kBinEvents; }
+
+hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_trials, int32_t n_bins,
+                            uint32_t *boff, int64_t stride, hipStream_t s);
+hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, int32_t n_bins, uint32_t *block_sums,
+                           hipStream_t s);
+size_t bin_scan_scratch_words(int64_t n_entries, int32_t n_bins);
+hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_trials, int32_t n_bins,
+                              const uint32_t *boff, int64_t stride, const int64_t *region, uint16_t *ids16,
+                              hipStream_t s);
+
+// A tile of a layer's occurrence filter: 128-event blocks [blk_lo, blk_hi) of the
+// catalog, overlapping bins [bin_lo, bin_hi); rank_lo flagged events precede it and
+// n_vals lie in it.  In LDS: the blocks' bits (4 words each), a uint16 per word
+// (flagged events of the tile before the word), then the tile's flagged values.
+struct Tile {
+    int32_t blk_lo, blk_hi;
+    int32_t bin_lo, bin_hi;
+    uint32_t rank_lo, n_vals;
+};
+constexpr int kTiledWaves = 16;                 // waves per workgroup of the tiled kernel
+constexpr int kTiledQueue = 256;                // per-wave queue of flagged occurrences
+constexpr int kTiledWaveTrials = 128;           // trials per wave and pass (an LDS sum each)
+// LDS left for the tile after the per-wave queues (and a write slot per lane) and
+// per-trial sums
+constexpr int kTiledLdsBytes = kLdsMaxBytes - kTiledWaves * ((kTiledQueue + 64) * 4 + kTiledWaveTrials * 8);
+__host__ __device__ inline size_t tile_rank_offset(int32_t nb) { return size_t(nb) * 16; }
+__host__ __device__ inline size_t tile_vals_offset(int32_t nb) { return tile_rank_offset(nb) + align16(size_t(nb) * 8); }
+__host__ __device__ inline size_t tile_bytes(int32_t nb, uint32_t nv) { return tile_vals_offset(nb) + size_t(nv) * 8; }
+inline int32_t max_tiles(int32_t catalog) { return bitmap_blocks(catalog) + catalog_bins(catalog) + 1; }
+hipError_t launch_layer_tiles(const uint32_t *rank, const uint32_t *n_flagged, int32_t nblk, int32_t n_bins,
+                              Tile *tiles, uint32_t *n_tiles, hipStream_t s);
+
+struct TiledArgs {
+    const uint16_t *ids16;
+    const int64_t *region;      // n_bins + 1 element offsets
+    const uint32_t *boff;
+    int64_t stride;             // entries per boff row
+    int64_t t_begin, t_end;
+    int64_t per_wg;             // trials per workgroup (a multiple of 64)
+    const uint32_t *bitmap;     // the layer's filter (see LayerTables)
+    const uint32_t *rank;
+    const double *vals;
+    const Tile *tiles;
+    const uint32_t *n_tiles;
+    double agg_r, agg_l;
+    double *ylt;
+};
+hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s);
 
 // ---- order statistics
 size_t sort_workspace_bytes(int64_t n);

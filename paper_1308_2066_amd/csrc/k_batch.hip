@@ -99,6 +99,7 @@ hipError_t launch_sum_ylts(const double *const *ylts, int32_t n_jobs, int64_t n,
 int32_t batch_mode(const TrialLaunch &l, bool packed) {
     switch (l.placement) {
     case ARA_PLACE_LDS_BITMAP: return packed ? kModeWaveBitmap24 : kModeWaveBitmap;
+    case ARA_PLACE_LDS_TILES: return kModeTiled;
     case ARA_PLACE_LDS_DENSE: return l.lane ? kModeLaneLds : kModeWaveLds;
     default: return l.lane ? kModeLaneGlobal : kModeWaveGlobal;
     }

@@ -119,6 +119,59 @@ __global__ __launch_bounds__(256) void k_layer_compact(const double *__restrict_
     vals[idx] = occ[e];
 }
 
+// Tiles of the filter for the tiled trial kernel: consecutive 128-event blocks whose
+// bits, per-block counts and flagged values fit kTiledLdsBytes.  Whole catalog bins
+// are added while they fit (a tile then reads each of its bins' occurrences once);
+// a bin too dense to fit alone is cut at block boundaries.  One thread: at most a
+// few hundred bins, and block steps only inside bins that must be cut.
+__global__ void k_layer_tiles(const uint32_t *__restrict__ rank, const uint32_t *__restrict__ n_flagged, int32_t nblk,
+                              int32_t n_bins, Tile *__restrict__ tiles, uint32_t *__restrict__ n_tiles) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const uint32_t total = *n_flagged;
+    auto rk = [&](int32_t b) { return b >= nblk ? total : rank[b]; };
+    auto fits = [&](int32_t lo, int32_t hi) { return tile_bytes(hi - lo, rk(hi) - rk(lo)) <= size_t(kTiledLdsBytes); };
+    uint32_t nt = 0;
+    auto emit = [&](int32_t lo, int32_t hi) {
+        Tile t;
+        t.blk_lo = lo;
+        t.blk_hi = hi;
+        t.bin_lo = lo / kBlocksPerBin;
+        t.bin_hi = (hi - 1) / kBlocksPerBin + 1;
+        t.rank_lo = rk(lo);
+        t.n_vals = rk(hi) - rk(lo);
+        tiles[nt++] = t;
+    };
+    int32_t lo = 0, hi = 0;   // the open tile: blocks [lo, hi)
+    for (int32_t bin = 0; bin < n_bins; ++bin) {
+        const int32_t b0 = bin * kBlocksPerBin, b1 = min(b0 + kBlocksPerBin, nblk);
+        if (fits(lo, b1)) {
+            hi = b1;
+            continue;
+        }
+        if (hi > lo) emit(lo, hi);
+        lo = hi = b0;
+        if (fits(b0, b1)) {
+            hi = b1;
+            continue;
+        }
+        for (int32_t b = b0; b < b1; ++b) {
+            if (!fits(lo, b + 1)) {
+                emit(lo, b);
+                lo = b;
+            }
+            hi = b + 1;
+        }
+    }
+    if (hi > lo) emit(lo, hi);
+    *n_tiles = nt;
+}
+
+hipError_t launch_layer_tiles(const uint32_t *rank, const uint32_t *n_flagged, int32_t nblk, int32_t n_bins,
+                              Tile *tiles, uint32_t *n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(k_layer_tiles, dim3(1), dim3(64), 0, s, rank, n_flagged, nblk, n_bins, tiles, n_tiles);
+    return hipGetLastError();
+}
+
 hipError_t launch_layer_combine(const EltDesc *d, int n_elts, int32_t catalog, bool f32, double, double,
                                 const LayerTables &t, hipStream_t s) {
     const unsigned blocks = unsigned((int64_t(catalog) + 255) / 256);
@@ -149,7 +202,9 @@ hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double o
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_layer_compact, dim3(ev_blocks), dim3(256), 0, s, t.occ, catalog, t.bitmap, t.rank, t.vals);
-    return hipGetLastError();
+    e = hipGetLastError();
+    if (e != hipSuccess || !t.tiles) return e;
+    return launch_layer_tiles(t.rank, t.n_flagged, t.nblk, catalog_bins(catalog), t.tiles, t.n_tiles, s);
 }
 
 }  // namespace ara

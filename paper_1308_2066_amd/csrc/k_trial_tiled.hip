@@ -1,0 +1,306 @@
+// Tiled trial kernel: the YLT path for catalogs whose occurrence-net values do not
+// fit in LDS as one table.
+//
+// Per trial it computes what the bitmap kernel computes (Section II-B, steps 1-4):
+//   ylt = min(max(P - AggR, 0), AggL),  P = sum over the trial's occurrences of the
+//   occurrence-net loss of their event,
+// which telescopes from the basic algorithm's per-occurrence ceded losses.  P is a
+// sum, so its terms may be taken in any grouping; here they are grouped by catalog
+// tile.  The layer's filter (one bit per event, per-block counts) and its nonzero
+// values are cut into tiles that fit in LDS together (k_layer_tiles).  A persistent
+// workgroup owns a range of trials; for each tile it stages the tile in LDS, then
+// its waves stream the occurrences of the tile's bins from the binned YET copy
+// (k_bin.hip), so that every lookup is an LDS access and the only HBM traffic is
+// the stream of 2-byte IDs.
+//
+// Per wave and bin, the occurrences of the wave's 128 trials are one contiguous
+// span, read in windows of up to 2048 (16 coalesced rows of 64 lanes x 2 IDs):
+//   filter  each ID's LDS bit; flagged occurrences are appended to the wave's LDS
+//           queue with their position in the window;
+//   drain   64 entries at a time: the value from LDS, the trial by binary search
+//           over the window's trial boundaries (held one per lane), and an LDS
+//           add into that trial's sum (one binary64 per trial of the wave).
+// A trial's P is therefore added in a fixed order (tiles, bins, windows, queue
+// rows, and lanes within a row as the LDS unit orders an instruction's conflicting
+// adds): the same bits on every run on a given device.
+#include "trial_common.h"
+
+namespace ara {
+
+constexpr int kTileWords = kTiledLdsBytes / 4;
+// trials per wave and pass: a window spans at most 63 trials (one boundary per lane),
+// so 126 trials make exactly two windows per bin when a bin's span fits two
+constexpr int kWaveTrials = 126;
+static_assert(kWaveTrials <= kTiledWaveTrials, "per-trial sums");
+constexpr int kPassTrials = kWaveTrials * kTiledWaves;   // trials per workgroup pass
+constexpr int kWinRows = 16;
+constexpr int kWindow = kWinRows * 128;            // occurrences per window
+
+// Wave-uniform reads of tables the kernel never writes, through the scalar data
+// path (constant address space): values land in scalar registers, so buffer
+// descriptors built from them stay scalar.
+template <typename V>
+__device__ __forceinline__ V sload(const V *p) {
+    typedef const __attribute__((address_space(4))) V *cptr;
+    return *(cptr)p;
+}
+
+__device__ __forceinline__ Tile load_tile(const Tile *tiles, uint32_t k) {
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(tiles + k);
+    Tile t;
+    t.blk_lo = int32_t(sload(w + 0));
+    t.blk_hi = int32_t(sload(w + 1));
+    t.bin_lo = int32_t(sload(w + 2));
+    t.bin_hi = int32_t(sload(w + 3));
+    t.rank_lo = sload(w + 4);
+    t.n_vals = sload(w + 5);
+    return t;
+}
+
+// Stage tile T (whole workgroup; the caller brackets it with barriers): the bits,
+// per-word counts of the tile's flagged events before the word, the values.
+__device__ __forceinline__ void stage_tile(const TiledArgs &a, const Tile &T, uint32_t *tab) {
+    const int32_t nb = T.blk_hi - T.blk_lo;
+    u32x4 *l4 = reinterpret_cast<u32x4 *>(tab);
+    const u32x4 *g4 = reinterpret_cast<const u32x4 *>(a.bitmap) + T.blk_lo;
+    uint16_t *r16 = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(tab) + tile_rank_offset(nb));
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+        const u32x4 W = g4[i];
+        l4[i] = W;
+        const uint32_t r0 = a.rank[T.blk_lo + i] - T.rank_lo;
+        const uint32_t r1 = r0 + __popc(W.x), r2 = r1 + __popc(W.y), r3 = r2 + __popc(W.z);
+        r16[4 * i + 0] = uint16_t(r0);
+        r16[4 * i + 1] = uint16_t(r1);
+        r16[4 * i + 2] = uint16_t(r2);
+        r16[4 * i + 3] = uint16_t(r3);
+    }
+    double *v = reinterpret_cast<double *>(reinterpret_cast<char *>(tab) + tile_vals_offset(nb));
+    for (uint32_t i = threadIdx.x; i < T.n_vals; i += blockDim.x) v[i] = a.vals[T.rank_lo + i];
+}
+
+// One wave's cursor over the windows of a tile: bin b, next position ws, and jl =
+// the trial (relative to the wave's first trial T0) whose run contains ws.
+struct TCur {
+    int32_t b;        // current bin (>= bin_hi: done)
+    uint32_t ws, e;   // next position and end of the wave's span in region b
+    uint32_t jl;
+};
+
+struct TWin {
+    uint32_t v[kWinRows];   // IDs: row r, lane l -> positions ws2 + 128 r + 2 l, +1
+    uint32_t bnd;           // boundary of trial jl + lane in region b (clamped to the span end)
+};
+
+// Open bins from b on until one has occurrences of the wave's trials.
+__device__ __forceinline__ void tcur_seek(const TiledArgs &a, const Tile &T, int64_t T0, int64_t T1, TCur &c) {
+    while (c.b < T.bin_hi) {
+        const uint32_t *row = a.boff + int64_t(c.b) * a.stride;
+        c.ws = sload(row + T0);
+        c.e = sload(row + T1);
+        c.jl = 0;
+        if (c.ws < c.e) return;
+        ++c.b;
+    }
+}
+
+__device__ __forceinline__ TCur tcur_uniform(const TCur &c) {
+    TCur u;
+    u.b = __builtin_amdgcn_readfirstlane(c.b);
+    u.ws = __builtin_amdgcn_readfirstlane(c.ws);
+    u.e = __builtin_amdgcn_readfirstlane(c.e);
+    u.jl = __builtin_amdgcn_readfirstlane(c.jl);
+    return u;
+}
+
+// Issue the loads of the window at c (boundaries first, then IDs); a finished cursor
+// issues the same loads with empty buffer records (no memory access).
+__device__ __forceinline__ void twin_load(const TiledArgs &a, const Tile &T, const TCur &c, int64_t T0, int64_t T1,
+                                          int lane, TWin &w) {
+    const bool live = c.b < T.bin_hi;
+    const int32_t b = live ? c.b : 0;
+    const uint32_t *row = a.boff + int64_t(b) * a.stride;
+    const int64_t nbnd = T1 - T0 + 1;   // boundaries T0 .. T1
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(row + T0), 0, live ? int(nbnd * 4) : 0, kBufWord3);
+    const uint32_t jb = min(c.jl + uint32_t(lane), uint32_t(nbnd - 1));
+    w.bnd = __builtin_amdgcn_raw_buffer_load_b32(rb, int(jb * 4u), 0, 0);
+    const uint32_t ws2 = c.ws & ~1u;
+    const uint32_t hi = min(ws2 + uint32_t(kWindow), c.e);
+    const uint32_t bytes = live ? ((hi + 1u) & ~1u) * 2u : 0u;
+    const __amdgpu_buffer_rsrc_t ri =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(a.ids16 + sload(a.region + b)), 0, int(bytes), kBufWord3);
+#pragma unroll
+    for (int r = 0; r < kWinRows; ++r)
+        w.v[r] = __builtin_amdgcn_raw_buffer_load_b32(ri, int((ws2 + uint32_t(128 * r + 2 * lane)) * 2u), 0, kNonTemporal);
+}
+
+// Resolve queue entries [0, qn) of the current window: value, trial, add to the
+// trial's sum.
+__device__ __forceinline__ void tiled_drain(const uint32_t *tab, int32_t nb, const uint32_t *q, uint32_t qn,
+                                            double *sums, uint32_t ws2, int32_t id_off, uint32_t bnd, uint32_t jl,
+                                            int lane) {
+    const uint16_t *r16 = reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(tab) + tile_rank_offset(nb));
+    const double *vals = reinterpret_cast<const double *>(reinterpret_cast<const char *>(tab) + tile_vals_offset(nb));
+    for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+        const bool act = r0 + uint32_t(lane) < qn;
+        const uint32_t ent = act ? q[r0 + lane] : 0u;
+        const uint32_t p = ws2 + (ent >> kBinShift);
+        // largest i with boundary(jl + i) <= p: the trial of position p (all lanes take
+        // part: each reads other lanes' boundaries)
+        uint32_t i = 0;
+#pragma unroll
+        for (uint32_t step = 32; step >= 1; step >>= 1) {
+            const uint32_t cand = i + step;
+            const uint32_t bc = uint32_t(__builtin_amdgcn_ds_bpermute(int(cand << 2), int(bnd)));
+            i = bc <= p ? cand : i;
+        }
+        if (act) {
+            const uint32_t x = uint32_t(int32_t(ent & uint32_t(kBinEvents - 1)) + id_off);
+            const uint32_t wi = x >> 5;
+            const uint32_t rk = uint32_t(r16[wi]) + __popc(tab[wi] & ((1u << (x & 31u)) - 1u));
+            __hip_atomic_fetch_add(sums + (jl + i), vals[rk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+    }
+}
+
+constexpr int kHalfRows = kWinRows / 2;
+constexpr int kQueueStride = kTiledQueue + 64;   // per wave: the queue, then a slot per lane for unflagged writes
+
+// Filter and drain one window [ws, we) of bin c.b (IDs in w), eight rows at a time:
+// first every row's LDS filter words are read (the reads overlap), then each ID
+// slot (64 IDs) is compacted into the queue by its flag mask (unflagged lanes write
+// a slot of their own past the queue, so the writes need no branch).  Rows wholly
+// inside the window skip the position checks; PART: the tile holds only part of the
+// bin, so IDs outside [lo_l, hi_l) are skipped.
+template <bool PART>
+__device__ __forceinline__ void tiled_window(const Tile &T, const uint32_t *tab, uint32_t *q, double *sums,
+                                             const TCur &c, uint32_t we, const TWin &w, int lane) {
+    const int32_t nb = T.blk_hi - T.blk_lo;
+    const int32_t bin_blk0 = c.b * kBlocksPerBin;
+    const uint32_t lo_l = uint32_t(max(T.blk_lo - bin_blk0, 0)) * kEventsPerBlock;
+    const uint32_t hi_l = uint32_t(min(T.blk_hi - bin_blk0, kBlocksPerBin)) * kEventsPerBlock;
+    const int32_t id_off = (bin_blk0 - T.blk_lo) * kEventsPerBlock;   // a multiple of 128
+    const uint32_t ws2 = c.ws & ~1u;
+    const uint32_t len = we - c.ws;
+    const uint32_t lane_rel = uint32_t(2 * lane) << kBinShift;
+    const uint32_t spare = uint32_t(kTiledQueue + lane);
+    uint32_t qn = 0;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        uint32_t w0[kHalfRows], w1[kHalfRows];
+        if (ws2 + uint32_t(128 * kHalfRows * h) >= we) break;   // the rest of the window is empty
+#pragma unroll
+        for (int k = 0; k < kHalfRows; ++k) {
+            const uint32_t v = w.v[h * kHalfRows + k];
+            uint32_t x0 = uint32_t(int32_t(v & 0xFFFFu) + id_off), x1 = uint32_t(int32_t(v >> 16) + id_off);
+            if (PART) {
+                // outside the tile: read word 0 (the flag is discarded below)
+                x0 = (v & 0xFFFFu) - lo_l < hi_l - lo_l ? x0 : 0u;
+                x1 = (v >> 16) - lo_l < hi_l - lo_l ? x1 : 0u;
+            }
+            // whole-bin tiles: every 15-bit ID of the bin is inside the tile
+            w0[k] = tab[x0 >> 5];
+            w1[k] = tab[x1 >> 5];
+        }
+#pragma unroll
+        for (int k = 0; k < kHalfRows; ++k) {
+            const int r = h * kHalfRows + k;
+            if (qn > uint32_t(kTiledQueue - 128)) {
+                tiled_drain(tab, nb, q, qn, sums, ws2, id_off, w.bnd, c.jl, lane);
+                qn = 0;
+            }
+            const uint32_t base = ws2 + uint32_t(128 * r);
+            if (base >= we) break;   // rows past the window's end hold no occurrence of it
+            const uint32_t v = w.v[r];
+            const bool edge = !(base >= c.ws && base + 128u <= we);
+            const uint32_t rel = lane_rel + (uint32_t(128 * r) << kBinShift);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const uint32_t l = e ? v >> 16 : v & 0xFFFFu;
+                // flags as a wave mask: the bit of tile event x sits at x mod 32 = ID mod
+                // 32 (id_off is a multiple of 32); then the tile's ID range and the
+                // window's lanes
+                uint64_t m = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(e ? w1[k] : w0[k], l, 1) != 0u);
+                if (PART) m &= __builtin_amdgcn_ballot_w64(l - lo_l < hi_l - lo_l);
+                if (edge) m &= __builtin_amdgcn_ballot_w64(base + uint32_t(2 * lane + e) - c.ws < len);
+                const uint32_t at = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), qn));
+                q[__builtin_amdgcn_inverse_ballot_w64(m) ? at : spare] = (rel + (uint32_t(e) << kBinShift)) | l;
+                qn += uint32_t(__popcll(m));
+            }
+        }
+    }
+    tiled_drain(tab, nb, q, qn, sums, ws2, id_off, w.bnd, c.jl, lane);
+}
+
+__global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
+    __shared__ __attribute__((aligned(16))) uint32_t tab[kTileWords];
+    __shared__ uint32_t queues[kTiledWaves * kQueueStride];
+    __shared__ double wsums[kTiledWaves * kTiledWaveTrials];
+    const int lane = threadIdx.x & 63;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t *q = queues + wave * kQueueStride;
+    double *sums = wsums + wave * kTiledWaveTrials;
+    const uint32_t nt = sload(a.n_tiles);
+    const int64_t wg0 = a.t_begin + int64_t(blockIdx.x) * a.per_wg;
+    const int64_t wg1 = min(wg0 + a.per_wg, a.t_end);
+    for (int64_t pass = wg0; pass < wg1; pass += kPassTrials) {
+        // the pass's trials split evenly over the waves (at most 128 each)
+        const int64_t span = min(int64_t(kPassTrials), wg1 - pass);
+        const int64_t per_wave = (span + kTiledWaves - 1) / kTiledWaves;
+        const int64_t T0 = min(pass + int64_t(wave) * per_wave, pass + span);
+        const int64_t T1 = min(T0 + per_wave, pass + span);
+#pragma unroll
+        for (int k = 0; k < kTiledWaveTrials / 64; ++k) sums[lane + 64 * k] = 0.0;
+        for (uint32_t k = 0; k < nt; ++k) {
+            const Tile T = load_tile(a.tiles, k);
+            __syncthreads();
+            stage_tile(a, T, tab);
+            __syncthreads();
+            if (T0 >= T1) continue;
+            TCur c;
+            c.b = T.bin_lo;
+            tcur_seek(a, T, T0, T1, c);
+            c = tcur_uniform(c);
+            TWin A;
+            twin_load(a, T, c, T0, T1, lane, A);
+            while (c.b < T.bin_hi) {
+                // this window ends at the span end, after 2048 positions, or where trial
+                // jl + 63 starts (so its trials are jl .. jl + 62: one per boundary lane)
+                const uint32_t b63 = uint32_t(__builtin_amdgcn_readlane(int(A.bnd), 63));
+                const uint32_t we = min(min((c.ws & ~1u) + uint32_t(kWindow), c.e), max(b63, c.ws));
+                // next cursor: the trial containing we, or the next bin
+                TCur n = c;
+                const uint64_t le = __builtin_amdgcn_ballot_w64(A.bnd <= we);
+                n.jl = c.jl + uint32_t(__popcll(le)) - 1u;
+                n.ws = we;
+                if (we >= c.e) {
+                    n.b = c.b + 1;
+                    tcur_seek(a, T, T0, T1, n);
+                }
+                n = tcur_uniform(n);
+                TWin B;
+                twin_load(a, T, n, T0, T1, lane, B);
+                if (T.blk_lo > c.b * kBlocksPerBin || T.blk_hi < (c.b + 1) * kBlocksPerBin)
+                    tiled_window<true>(T, tab, q, sums, c, we, A, lane);
+                else
+                    tiled_window<false>(T, tab, q, sums, c, we, A, lane);
+                c = n;
+                A = B;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < kTiledWaveTrials / 64; ++k) {
+            const int64_t t = T0 + lane + 64 * k;
+            if (t < T1) a.ylt[t - a.t_begin] = excess(sums[lane + 64 * k], a.agg_r, a.agg_l);
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s) {
+    hipLaunchKernelGGL(k_trial_tiled, dim3(grid), dim3(kTiledWaves * 64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace ara

@@ -251,42 +251,37 @@ __device__ __forceinline__ void bitmap_wave_run(const TrialArgs &a, const uint32
     const uint32_t n = uint32_t(a.t_end - a.t_begin);
     uint32_t bad = 0, mx = 0;
 
-    BCur c0 = bcur_open(a, first, n, bad);
-    BCur c1 = bcur_next(a, c0, stride, n, bad);
+    BCur c0 = bcur_uniform(bcur_open(a, first, n, bad));
+    BCur c1 = bcur_uniform(bcur_next(a, c0, stride, n, bad));
+    // The prologue issues what a loop iteration leaves in flight (IDs, value reads of
+    // an empty segment, IDs), so the waits at the loop's top are the same on entry.
     IdRegs<P24> A, B;
+    double vA[kRows], vB[kRows];
     bcur_load<P24>(a, c0, n, lane, A);
+    seg_rows(a, tab, q, 0u, lane, vB);
     bcur_load<P24>(a, c1, n, lane, B);
 
-    double vA[kRows], vB[kRows];
     Pending pA, pB;
     pB.t = n;
     pB.last = 0;
     pB.dacc = 0.0;
-#pragma unroll
-    for (int k = 0; k < kRows; ++k) vB[k] = 0.0;
     double acc = 0.0;
+    // One exit, at the top: a segment past the last trial is issued as an empty one
+    // (no IDs, no queued events) rather than leaving the loop in the middle, so the
+    // compiler's wait counts at the top do not assume an empty pipeline.
     while (c0.t < n) {
-        c0 = bcur_uniform(c0);
-        c1 = bcur_uniform(c1);
         pB.t = __builtin_amdgcn_readfirstlane(pB.t);
         pB.last = __builtin_amdgcn_readfirstlane(pB.last);
-        const BCur c2 = bcur_next(a, c1, stride, n, bad);
+        const BCur c2 = bcur_uniform(bcur_next(a, c1, stride, n, bad));
         issue<P24>(a, tab, q, A, c0, c2, n, lane, mx, vA, pA);
         retire(a, pB, vB, n, lane, acc);
-        if (c1.t >= n) {
-            retire(a, pA, vA, n, lane, acc);
-            break;
-        }
-        const BCur c3 = bcur_next(a, c2, stride, n, bad);
+        const BCur c3 = bcur_uniform(bcur_next(a, c2, stride, n, bad));
         issue<P24>(a, tab, q, B, c1, c3, n, lane, mx, vB, pB);
         retire(a, pA, vA, n, lane, acc);
-        if (c2.t >= n) {
-            retire(a, pB, vB, n, lane, acc);
-            break;
-        }
         c0 = c2;
         c1 = c3;
     }
+    retire(a, pB, vB, n, lane, acc);
     if (mx > uint32_t(a.catalog) - 1u) bad |= ERR_ID_RANGE;
     if (bad) atomicOr(a.err, bad);
 }

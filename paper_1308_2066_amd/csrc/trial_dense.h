@@ -108,11 +108,11 @@ __device__ __forceinline__ void seg_lookup(const TrialArgs &a, const uint32_t *l
             const bool valid = rel >= lo && rel < hi;
             const bool inr = id < C;
             if (valid && !inr) bad |= ERR_ID_RANGE;
-            v[s] = 0.0;
-            if (valid && inr) {
-                const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(vr, id * 8u, 0, 0));
-                v[s] = __builtin_bit_cast(double, q);
-            }
+            // always issued (slots outside the trial read past the record: 0, no
+            // memory access), so the count of loads in flight is the same on every path
+            const uint32_t off = valid && inr ? id * 8u : 0xFFFFFFF8u;
+            const uint2 q = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(vr, off, 0, 0));
+            v[s] = __builtin_bit_cast(double, q);
         }
     }
 }
@@ -159,24 +159,27 @@ __device__ __forceinline__ void dense_wave_run(const TrialArgs &a, uint32_t *lds
 
     Cursor c0, c1;
     open_trial(a, first, c0, bad);
+    c0 = uniform_cursor(c0);
     u32x4 A[kNch], B[kNch];
     load_seg(a, c0, lane, A);
-    c1 = seg_next(a, c0, stride, bad);
+    c1 = uniform_cursor(seg_next(a, c0, stride, bad));
     load_seg(a, c1, lane, B);
 
     double acc = 0.0;
+    // One exit, at the top: a segment past the wave's last trial is stepped as an
+    // empty one (no events) rather than leaving the loop in the middle, so the
+    // compiler's wait counts at the top do not assume an empty pipeline.
     while (c0.t < a.t_end) {
         // segment c0 (in A) while c1 (in B) is in flight; A then receives c2
-        const Cursor c2 = seg_next(a, c1, stride, bad);
+        const Cursor c2 = uniform_cursor(seg_next(a, c1, stride, bad));
         seg_step<PL>(a, lds, q, A, c0, c2, lane, bad, acc);
         if (seg_last(c0)) {
             finish_trial(a, c0.t, acc, lane);
             acc = 0.0;
         }
-        if (c1.t >= a.t_end) break;
-        const Cursor c3 = seg_next(a, c2, stride, bad);
+        const Cursor c3 = uniform_cursor(seg_next(a, c2, stride, bad));
         seg_step<PL>(a, lds, q, B, c1, c3, lane, bad, acc);
-        if (seg_last(c1)) {
+        if (c1.t < a.t_end && seg_last(c1)) {
             finish_trial(a, c1.t, acc, lane);
             acc = 0.0;
         }

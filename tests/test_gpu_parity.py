@@ -51,20 +51,25 @@ def S():
 
 
 def analyze(A, S, ctx, w, placement=0, precision=0, t0=0, t1=None, terms=None, block=0, grid_per_cu=0,
-            packing=1, mode=0):
+            packing=1, mode=0, binning=1):
     import torch
     A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, placement)
     A.ara_set_option(ctx, A.ARA_OPT_TRIAL_MODE, mode)
     A.ara_set_option(ctx, A.ARA_OPT_BLOCK_THREADS, block)
     A.ara_set_option(ctx, A.ARA_OPT_GRID_PER_CU, grid_per_cu)
     A.ara_set_option(ctx, A.ARA_OPT_YET_PACKING, packing)
+    A.ara_set_option(ctx, A.ARA_OPT_YET_BINNING, binning)
     try:
         an = S.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts,
                              terms if terms is not None else w.layer_terms, w.elt_terms, precision)
     finally:
         A.ara_set_option(ctx, A.ARA_OPT_YET_PACKING, 1)
+        A.ara_set_option(ctx, A.ARA_OPT_YET_BINNING, 1)
     try:
-        assert A.ara_yet_info(an.yet)[2] == (3 if packing and w.n_events > 0 and w.catalog_size <= 1 << 24 else 4)
+        # 2-byte binned copy where it applies (large catalogs), else 3-byte packed, else int32
+        ib = A.ara_yet_info(an.yet)[2]
+        plain = 3 if packing and w.n_events > 0 and w.catalog_size <= 1 << 24 else 4
+        assert ib == plain or (binning and ib == 2 and w.catalog_size > 20480), (ib, plain)
         t1 = w.n_trials if t1 is None else t1
         ylt = torch.empty(max(t1 - t0, 1), dtype=torch.float64, device="cuda")
         A.ara_analyze(ctx, an.yet, an.layer, t0, t1, ylt)

@@ -1,0 +1,198 @@
+"""The tiled YLT kernel (catalog-binned YET copy, filter and values in LDS one tile at
+a time) against the oracle and against the LDS-bitmap kernel.
+
+Bar: binary64 YLT within 1e-12 * max(|y|, P_k) of the oracle (the tiled kernel adds a
+trial's occurrence-net losses grouped by catalog tile, another order of the same
+non-negative terms); the same bits on every run; batched jobs equal plain launches
+bit for bit."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+INF = math.inf
+TILES = 4          # ARA_PLACE_LDS_TILES
+BITMAP = 1         # ARA_PLACE_LDS_BITMAP
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def A(ara_lib):
+    return ara_lib
+
+
+@pytest.fixture(scope="module")
+def S():
+    from paper_1308_2066_amd import session
+    return session
+
+
+def _open(A, S, ctx, w, terms=None, binning=1, precision=0):
+    A.ara_set_option(ctx, A.ARA_OPT_YET_BINNING, binning)
+    try:
+        return S.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts,
+                               terms if terms is not None else w.layer_terms, w.elt_terms, precision)
+    finally:
+        A.ara_set_option(ctx, A.ARA_OPT_YET_BINNING, 1)
+
+
+def _run(A, ctx, an, placement, t0=0, t1=None):
+    import torch
+    t1 = an_trials(A, an) if t1 is None else t1
+    A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, placement)
+    try:
+        y = torch.full((max(t1 - t0, 1),), math.nan, dtype=torch.float64, device="cuda")
+        if t1 > t0:
+            A.ara_analyze(ctx, an.yet, an.layer, t0, t1, y)
+        A.ara_sync(ctx)
+        return y[: t1 - t0].cpu().numpy()
+    finally:
+        A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, 0)
+
+
+def an_trials(A, an):
+    return A.ara_yet_info(an.yet)[1]
+
+
+def _close(got, ref, what=""):
+    y, P = ref["ylt"], ref["occ_total"]
+    tol = 1e-12 * np.maximum(np.abs(y), P)
+    bad = np.nonzero(~(np.abs(got - y) <= tol))[0]
+    assert bad.size == 0, f"{what}: {bad.size} trials off; first {bad[:5]} got {got[bad[:5]]} want {y[bad[:5]]}"
+
+
+def _workload(rng, lengths, catalog, n_elts=4, nnz=None, mu=10.0, sigma=2.0, terms=(5e4, 1e6, 2e5, INF),
+              id_sampler=None):
+    lengths = np.asarray(lengths, np.int64)
+    offs = np.zeros(len(lengths) + 1, np.int64)
+    offs[1:] = np.cumsum(lengths)
+    n = int(offs[-1])
+    ids = (id_sampler(n) if id_sampler else rng.integers(0, catalog, size=n)).astype(np.int32)
+    nnz = nnz or catalog // 3
+    elts = [synth.elt_sparse(rng, nnz, catalog, mu, sigma) for _ in range(n_elts)]
+    return synth.Workload("tiled", ids, offs, catalog, elts, terms, None, (10.0,), 0)
+
+
+def _tiles_vs_oracle_and_bitmap(A, S, ctx, w, what, sub_ranges=()):
+    an = _open(A, S, ctx, w)
+    try:
+        assert A.ara_yet_info(an.yet)[2] == 2, "binned copy expected"
+        got = _run(A, ctx, an, 0)
+        assert A.ara_layer_stats(ctx, an.layer)[1] in (BITMAP, TILES)
+        again = _run(A, ctx, an, TILES)
+        assert again.tobytes() == got.tobytes(), "auto placement must pick the tiled kernel here"
+        ref = oracle.analyze_workload(w, threads=oracle.max_threads())
+        _close(got, ref, what)
+        _close(_run(A, ctx, an, BITMAP), ref, what + " (bitmap)")
+        for t0, t1 in sub_ranges:
+            sub = _run(A, ctx, an, 0, t0, t1)
+            _close(sub, {k: v[t0:t1] for k, v in ref.items()}, f"{what} [{t0}, {t1})")
+        return got
+    finally:
+        an.release()
+
+
+def test_paper_shape_many_tiles(A, S, gpu_ctx):
+    """1M-event catalog, 16 ELTs: about a dozen tiles of whole bins; unsaturated
+    aggregate terms so every YLT value is checked."""
+    w = synth.workload_paper_scale(n_trials=8_000)
+    w = w.with_terms((1e5, 5e6, 1.5e8, INF))
+    _say("tiled paper shape 8k x 1000")
+    _tiles_vs_oracle_and_bitmap(A, S, gpu_ctx, w, "paper shape", sub_ranges=[(0, 1), (17, 4113), (7999, 8000)])
+
+
+def test_dense_layer_splits_bins(A, S, gpu_ctx):
+    """Every event flagged (values of a whole bin do not fit in LDS): tiles cut inside
+    bins, each reading its bin's occurrences and keeping its own IDs."""
+    rng = np.random.default_rng(301)
+    C = 100_003                                  # not a multiple of the bin size
+    ids_all = np.arange(C, dtype=np.int32)
+    elts = [(ids_all, rng.lognormal(8.0, 1.0, size=C))]
+    lengths = list(rng.integers(200, 1500, size=600)) + [0, 1, 4099, 2, 0]
+    w = _workload(rng, lengths, C)
+    w = synth.Workload("dense", w.event_ids, w.trial_offsets, C, elts, (0.0, INF, 0.0, INF), None, (2.0,), 0)
+    _say("tiled dense layer")
+    _tiles_vs_oracle_and_bitmap(A, S, gpu_ctx, w, "dense", sub_ranges=[(3, 299), (600, 605)])
+
+
+def test_ragged_and_empty_runs(A, S, gpu_ctx):
+    """Ragged trial lengths, empty trials, long runs of trials without occurrences in
+    a bin (IDs concentrated in a few bins), a catalog that ends inside a bin."""
+    rng = np.random.default_rng(302)
+    C = 70_001
+    lengths = [0] * 70 + list(rng.integers(0, 400, size=500)) + [0] * 200 + [5000, 1, 1, 3000] + [0] * 64 + [7]
+
+    def concentrated(n):
+        # most occurrences in bins 0 and 2, a few in the partial last bin
+        pick = rng.random(n)
+        out = rng.integers(0, 32768, size=n)
+        out = np.where(pick < 0.5, out, rng.integers(65536, 70_001, size=n))
+        return out
+
+    w = _workload(rng, lengths, C, n_elts=3, nnz=20_000, id_sampler=concentrated)
+    _say("tiled ragged runs")
+    _tiles_vs_oracle_and_bitmap(A, S, gpu_ctx, w, "ragged", sub_ranges=[(0, 70), (69, 71), (560, 839)])
+
+
+def test_single_tile_and_determinism(A, S, gpu_ctx):
+    """A catalog whose whole filter and values fit one tile; runs repeat bit for bit;
+    without the binned copy the bitmap kernel gives the same values within the bound."""
+    rng = np.random.default_rng(303)
+    w = _workload(rng, rng.integers(500, 1500, size=3000), 60_000, nnz=3_000)
+    _say("tiled single tile")
+    got = _tiles_vs_oracle_and_bitmap(A, S, gpu_ctx, w, "one tile")
+    an = _open(A, S, gpu_ctx, w)
+    try:
+        for _ in range(3):
+            assert _run(A, gpu_ctx, an, 0).tobytes() == got.tobytes()
+    finally:
+        an.release()
+    an = _open(A, S, gpu_ctx, w, binning=0)
+    try:
+        assert A.ara_yet_info(an.yet)[2] == 3
+        with pytest.raises(A.AraError) as e:
+            _run(A, gpu_ctx, an, TILES)
+        assert e.value.status == A.ARA_E_UNSUPPORTED
+        _close(_run(A, gpu_ctx, an, 0), oracle.analyze_workload(w, threads=oracle.max_threads()), "no binned copy")
+    finally:
+        an.release()
+
+
+def test_batch_with_tiled_jobs_equals_plain(A, S, gpu_ctx):
+    """Tiled jobs inside a batch (beside dense-table jobs) give the plain launch's bits."""
+    import torch
+    rng = np.random.default_rng(304)
+    w1 = _workload(rng, rng.integers(300, 1200, size=2000), 200_000)
+    w2 = synth.workload_plain_small()
+    a1, a2 = _open(A, S, gpu_ctx, w1), _open(A, S, gpu_ctx, w2)
+    try:
+        specs = [(a1, 0, w1.n_trials), (a1, 11, 1500), (a2, 0, w2.n_trials)]
+        want = [_run(A, gpu_ctx, an, 0, t0, t1) for an, t0, t1 in specs]
+        outs = [torch.full((t1 - t0,), math.nan, dtype=torch.float64, device="cuda") for _, t0, t1 in specs]
+        b = A.ara_batch_create(gpu_ctx, [(an.yet, an.layer, t0, t1, o) for (an, t0, t1), o in zip(specs, outs)])
+        try:
+            for rep in range(3):
+                _say(f"tiled batch run {rep}")
+                for o in outs:
+                    o.fill_(math.nan)
+                A.ara_batch_run(b)
+                A.ara_sync(gpu_ctx)
+                for k, o in enumerate(outs):
+                    assert o.cpu().numpy().tobytes() == want[k].tobytes(), (rep, k)
+        finally:
+            A.ara_batch_release(b)
+    finally:
+        a1.release()
+        a2.release()
