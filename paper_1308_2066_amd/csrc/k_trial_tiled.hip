@@ -137,14 +137,15 @@ __device__ __forceinline__ void twin_load(const TiledArgs &a, const Tile &T, con
 // Resolve queue entries [0, qn) of the current window: value, trial, add to the
 // trial's sum.
 __device__ __forceinline__ void tiled_drain(const uint32_t *tab, int32_t nb, const uint32_t *q, uint32_t qn,
-                                            double *sums, uint32_t ws2, int32_t id_off, uint32_t bnd, uint32_t jl,
-                                            int lane) {
+                                            double *sums, uint32_t ws2, uint32_t ws, uint32_t we, int32_t id_off,
+                                            uint32_t bnd, uint32_t jl, int lane) {
     const uint16_t *r16 = reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(tab) + tile_rank_offset(nb));
     const double *vals = reinterpret_cast<const double *>(reinterpret_cast<const char *>(tab) + tile_vals_offset(nb));
     for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
-        const bool act = r0 + uint32_t(lane) < qn;
-        const uint32_t ent = act ? q[r0 + lane] : 0u;
+        const bool in_q = r0 + uint32_t(lane) < qn;
+        const uint32_t ent = in_q ? q[r0 + lane] : 0u;
         const uint32_t p = ws2 + (ent >> kBinShift);
+        const bool act = in_q && p - ws < we - ws;   // rows at the window's edges queue a few outside it
         // largest i with boundary(jl + i) <= p: the trial of position p (all lanes take
         // part: each reads other lanes' boundaries)
         uint32_t i = 0;
@@ -166,12 +167,42 @@ __device__ __forceinline__ void tiled_drain(const uint32_t *tab, int32_t nb, con
 constexpr int kHalfRows = kWinRows / 2;
 constexpr int kQueueStride = kTiledQueue + 64;   // per wave: the queue, then a slot per lane for unflagged writes
 
+// LDS byte address of the filter word of bin-local ID l (bits `lo`.. of v hold l):
+// word (l + id_off) / 32 of the tile, id_off a multiple of 128 folded into woff.
+template <int LO>
+__device__ __forceinline__ uint32_t word_addr(uint32_t v, uint32_t woff) {
+    return (__builtin_amdgcn_ubfe(v, LO + 5, kBinShift - 5) << 2) + woff;
+}
+
+// Queue one ID slot (64 IDs, one per lane): mask m of the flagged lanes; entry
+// values ent.  Unflagged lanes write their own slot past the queue.
+__device__ __forceinline__ void queue_slot(uint32_t *q, uint64_t m, uint32_t &qn, uint32_t ent, uint32_t spare) {
+    const uint32_t at = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)) + qn;
+    q[__builtin_amdgcn_inverse_ballot_w64(m) ? at : spare] = ent;
+    qn += uint32_t(__popcll(m));
+}
+
+// Filter one row (IDs in v, filter words w0/w1) into the queue.  Positions outside
+// the window are queued too and dropped when the queue is resolved.  PART: the tile
+// holds part of the bin (IDs outside [lo_l, hi_l) are dropped).
+template <bool PART>
+__device__ __forceinline__ void filter_row(uint32_t *q, uint32_t &qn, uint32_t v, uint32_t w0, uint32_t w1,
+                                           uint32_t lo_l, uint32_t hi_l, uint32_t rel, uint32_t spare) {
+    const uint32_t l0 = v & 0xFFFFu, l1 = v >> 16;
+    // the bit of tile event x sits at x mod 32 = ID mod 32 (id_off is a multiple of 32)
+    uint64_t m0 = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(w0, v, 1) != 0u);
+    uint64_t m1 = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(w1, l1, 1) != 0u);
+    if (PART) {
+        m0 &= __builtin_amdgcn_ballot_w64(l0 - lo_l < hi_l - lo_l);
+        m1 &= __builtin_amdgcn_ballot_w64(l1 - lo_l < hi_l - lo_l);
+    }
+    queue_slot(q, m0, qn, rel | l0, spare);
+    queue_slot(q, m1, qn, (rel + (1u << kBinShift)) | l1, spare);
+}
+
 // Filter and drain one window [ws, we) of bin c.b (IDs in w), eight rows at a time:
-// first every row's LDS filter words are read (the reads overlap), then each ID
-// slot (64 IDs) is compacted into the queue by its flag mask (unflagged lanes write
-// a slot of their own past the queue, so the writes need no branch).  Rows wholly
-// inside the window skip the position checks; PART: the tile holds only part of the
-// bin, so IDs outside [lo_l, hi_l) are skipped.
+// first every row's LDS filter words are read (the reads overlap), then each row is
+// filtered into the queue.  PART: the tile holds only part of the bin.
 template <bool PART>
 __device__ __forceinline__ void tiled_window(const Tile &T, const uint32_t *tab, uint32_t *q, double *sums,
                                              const TCur &c, uint32_t we, const TWin &w, int lane) {
@@ -180,56 +211,45 @@ __device__ __forceinline__ void tiled_window(const Tile &T, const uint32_t *tab,
     const uint32_t lo_l = uint32_t(max(T.blk_lo - bin_blk0, 0)) * kEventsPerBlock;
     const uint32_t hi_l = uint32_t(min(T.blk_hi - bin_blk0, kBlocksPerBin)) * kEventsPerBlock;
     const int32_t id_off = (bin_blk0 - T.blk_lo) * kEventsPerBlock;   // a multiple of 128
+    const uint32_t woff = uint32_t(id_off) >> 3;   // byte offset of the bin's first word (when id_off >= 0)
     const uint32_t ws2 = c.ws & ~1u;
-    const uint32_t len = we - c.ws;
     const uint32_t lane_rel = uint32_t(2 * lane) << kBinShift;
     const uint32_t spare = uint32_t(kTiledQueue + lane);
     uint32_t qn = 0;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        uint32_t w0[kHalfRows], w1[kHalfRows];
         if (ws2 + uint32_t(128 * kHalfRows * h) >= we) break;   // the rest of the window is empty
+        uint32_t w0[kHalfRows], w1[kHalfRows];
 #pragma unroll
         for (int k = 0; k < kHalfRows; ++k) {
             const uint32_t v = w.v[h * kHalfRows + k];
-            uint32_t x0 = uint32_t(int32_t(v & 0xFFFFu) + id_off), x1 = uint32_t(int32_t(v >> 16) + id_off);
             if (PART) {
-                // outside the tile: read word 0 (the flag is discarded below)
-                x0 = (v & 0xFFFFu) - lo_l < hi_l - lo_l ? x0 : 0u;
-                x1 = (v >> 16) - lo_l < hi_l - lo_l ? x1 : 0u;
+                // IDs outside the tile read word 0 (their flags are dropped)
+                const uint32_t l0 = v & 0xFFFFu, l1 = v >> 16;
+                const uint32_t x0 = l0 - lo_l < hi_l - lo_l ? uint32_t(int32_t(l0) + id_off) : 0u;
+                const uint32_t x1 = l1 - lo_l < hi_l - lo_l ? uint32_t(int32_t(l1) + id_off) : 0u;
+                w0[k] = tab[x0 >> 5];
+                w1[k] = tab[x1 >> 5];
+            } else {
+                // whole-bin tiles: every 15-bit ID of the bin is inside the tile
+                w0[k] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + word_addr<0>(v, woff));
+                w1[k] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + word_addr<16>(v, woff));
             }
-            // whole-bin tiles: every 15-bit ID of the bin is inside the tile
-            w0[k] = tab[x0 >> 5];
-            w1[k] = tab[x1 >> 5];
         }
 #pragma unroll
         for (int k = 0; k < kHalfRows; ++k) {
             const int r = h * kHalfRows + k;
-            if (qn > uint32_t(kTiledQueue - 128)) {
-                tiled_drain(tab, nb, q, qn, sums, ws2, id_off, w.bnd, c.jl, lane);
-                qn = 0;
-            }
             const uint32_t base = ws2 + uint32_t(128 * r);
             if (base >= we) break;   // rows past the window's end hold no occurrence of it
-            const uint32_t v = w.v[r];
-            const bool edge = !(base >= c.ws && base + 128u <= we);
-            const uint32_t rel = lane_rel + (uint32_t(128 * r) << kBinShift);
-#pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                const uint32_t l = e ? v >> 16 : v & 0xFFFFu;
-                // flags as a wave mask: the bit of tile event x sits at x mod 32 = ID mod
-                // 32 (id_off is a multiple of 32); then the tile's ID range and the
-                // window's lanes
-                uint64_t m = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(e ? w1[k] : w0[k], l, 1) != 0u);
-                if (PART) m &= __builtin_amdgcn_ballot_w64(l - lo_l < hi_l - lo_l);
-                if (edge) m &= __builtin_amdgcn_ballot_w64(base + uint32_t(2 * lane + e) - c.ws < len);
-                const uint32_t at = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), qn));
-                q[__builtin_amdgcn_inverse_ballot_w64(m) ? at : spare] = (rel + (uint32_t(e) << kBinShift)) | l;
-                qn += uint32_t(__popcll(m));
+            if (qn > uint32_t(kTiledQueue - 128)) {
+                tiled_drain(tab, nb, q, qn, sums, ws2, c.ws, we, id_off, w.bnd, c.jl, lane);
+                qn = 0;
             }
+            const uint32_t rel = lane_rel + (uint32_t(128 * r) << kBinShift);
+            filter_row<PART>(q, qn, w.v[r], w0[k], w1[k], lo_l, hi_l, rel, spare);
         }
     }
-    tiled_drain(tab, nb, q, qn, sums, ws2, id_off, w.bnd, c.jl, lane);
+    tiled_drain(tab, nb, q, qn, sums, ws2, c.ws, we, id_off, w.bnd, c.jl, lane);
 }
 
 __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
