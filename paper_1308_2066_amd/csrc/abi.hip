@@ -805,6 +805,7 @@ static TiledArgs tiled_args(const ara_yet *y, const ara_layer *L, int64_t t0, in
     a.vals = L->t.vals;
     a.tiles = L->t.tiles;
     a.n_tiles = L->t.n_tiles;
+    a.nblk = L->t.nblk;
     a.agg_r = L->terms.agg_retention;
     a.agg_l = L->terms.agg_limit;
     a.ylt = ylt;

@@ -182,8 +182,10 @@ hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n
 
 // A tile of a layer's occurrence filter: 128-event blocks [blk_lo, blk_hi) of the
 // catalog, overlapping bins [bin_lo, bin_hi); rank_lo flagged events precede it and
-// n_vals lie in it.  In LDS: the blocks' bits (4 words each), a uint16 per word
-// (flagged events of the tile before the word), then the tile's flagged values.
+// n_vals lie in it.  In LDS: the bits of every block of those bins (4 words each,
+// zero outside [blk_lo, blk_hi), so that each bin starts 4 KB after the previous
+// one), a uint16 per word (flagged events of the tile before the word), then the
+// tile's flagged values.
 struct Tile {
     int32_t blk_lo, blk_hi;
     int32_t bin_lo, bin_hi;
@@ -199,6 +201,12 @@ __host__ __device__ inline size_t tile_rank_offset(int32_t nb) { return size_t(n
 __host__ __device__ inline size_t tile_vals_offset(int32_t nb) { return tile_rank_offset(nb) + align16(size_t(nb) * 8); }
 __host__ __device__ inline size_t tile_bytes(int32_t nb, uint32_t nv) { return tile_vals_offset(nb) + size_t(nv) * 8; }
 inline int32_t max_tiles(int32_t catalog) { return bitmap_blocks(catalog) + catalog_bins(catalog) + 1; }
+// Blocks held in LDS for a tile of blocks [lo, hi): its bins whole (clamped to the catalog).
+__host__ __device__ inline int32_t tile_span_blocks(int32_t lo, int32_t hi, int32_t nblk) {
+    const int32_t b0 = lo / kBlocksPerBin * kBlocksPerBin;
+    const int32_t b1 = ((hi - 1) / kBlocksPerBin + 1) * kBlocksPerBin;
+    return (b1 < nblk ? b1 : nblk) - b0;
+}
 hipError_t launch_layer_tiles(const uint32_t *rank, const uint32_t *n_flagged, int32_t nblk, int32_t n_bins,
                               Tile *tiles, uint32_t *n_tiles, hipStream_t s);
 
@@ -214,6 +222,8 @@ struct TiledArgs {
     const double *vals;
     const Tile *tiles;
     const uint32_t *n_tiles;
+    int32_t nblk;               // 128-event blocks of the catalog
+    int32_t pad_;
     double agg_r, agg_l;
     double *ylt;
 };

@@ -120,8 +120,8 @@ __global__ __launch_bounds__(256) void k_layer_compact(const double *__restrict_
 }
 
 // Tiles of the filter for the tiled trial kernel: consecutive 128-event blocks whose
-// bits, per-block counts and flagged values fit kTiledLdsBytes.  Whole catalog bins
-// are added while they fit (a tile then reads each of its bins' occurrences once);
+// bits (padded to whole bins), per-word counts and flagged values fit
+// kTiledLdsBytes.  Whole catalog bins are added while they fit (a tile then reads each of its bins' occurrences once);
 // a bin too dense to fit alone is cut at block boundaries.  One thread: at most a
 // few hundred bins, and block steps only inside bins that must be cut.
 __global__ void k_layer_tiles(const uint32_t *__restrict__ rank, const uint32_t *__restrict__ n_flagged, int32_t nblk,
@@ -129,7 +129,9 @@ __global__ void k_layer_tiles(const uint32_t *__restrict__ rank, const uint32_t 
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     const uint32_t total = *n_flagged;
     auto rk = [&](int32_t b) { return b >= nblk ? total : rank[b]; };
-    auto fits = [&](int32_t lo, int32_t hi) { return tile_bytes(hi - lo, rk(hi) - rk(lo)) <= size_t(kTiledLdsBytes); };
+    auto fits = [&](int32_t lo, int32_t hi) {
+        return tile_bytes(tile_span_blocks(lo, hi, nblk), rk(hi) - rk(lo)) <= size_t(kTiledLdsBytes);
+    };
     uint32_t nt = 0;
     auto emit = [&](int32_t lo, int32_t hi) {
         Tile t;

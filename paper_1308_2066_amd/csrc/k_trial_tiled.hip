@@ -57,17 +57,22 @@ __device__ __forceinline__ Tile load_tile(const Tile *tiles, uint32_t k) {
     return t;
 }
 
-// Stage tile T (whole workgroup; the caller brackets it with barriers): the bits,
-// per-word counts of the tile's flagged events before the word, the values.
-__device__ __forceinline__ void stage_tile(const TiledArgs &a, const Tile &T, uint32_t *tab) {
-    const int32_t nb = T.blk_hi - T.blk_lo;
+// Stage tile T (whole workgroup; the caller brackets it with barriers): the bits of
+// its bins' blocks (zero outside the tile's own blocks), per-word counts of the
+// tile's flagged events before the word, the values.  nb = blocks held.
+__device__ __forceinline__ void stage_tile(const TiledArgs &a, const Tile &T, int32_t nb, uint32_t *tab) {
+    const int32_t b0 = T.bin_lo * kBlocksPerBin;
     u32x4 *l4 = reinterpret_cast<u32x4 *>(tab);
-    const u32x4 *g4 = reinterpret_cast<const u32x4 *>(a.bitmap) + T.blk_lo;
     uint16_t *r16 = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(tab) + tile_rank_offset(nb));
     for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-        const u32x4 W = g4[i];
+        const int32_t blk = b0 + i;
+        u32x4 W = {0u, 0u, 0u, 0u};
+        uint32_t r0 = 0;
+        if (blk >= T.blk_lo && blk < T.blk_hi) {
+            W = reinterpret_cast<const u32x4 *>(a.bitmap)[blk];
+            r0 = a.rank[blk] - T.rank_lo;
+        }
         l4[i] = W;
-        const uint32_t r0 = a.rank[T.blk_lo + i] - T.rank_lo;
         const uint32_t r1 = r0 + __popc(W.x), r2 = r1 + __popc(W.y), r3 = r2 + __popc(W.z);
         r16[4 * i + 0] = uint16_t(r0);
         r16[4 * i + 1] = uint16_t(r1);
@@ -137,7 +142,7 @@ __device__ __forceinline__ void twin_load(const TiledArgs &a, const Tile &T, con
 // Resolve queue entries [0, qn) of the current window: value, trial, add to the
 // trial's sum.
 __device__ __forceinline__ void tiled_drain(const uint32_t *tab, int32_t nb, const uint32_t *q, uint32_t qn,
-                                            double *sums, uint32_t ws2, uint32_t ws, uint32_t we, int32_t id_off,
+                                            double *sums, uint32_t ws2, uint32_t ws, uint32_t we, uint32_t id_off,
                                             uint32_t bnd, uint32_t jl, int lane) {
     const uint16_t *r16 = reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(tab) + tile_rank_offset(nb));
     const double *vals = reinterpret_cast<const double *>(reinterpret_cast<const char *>(tab) + tile_vals_offset(nb));
@@ -156,7 +161,7 @@ __device__ __forceinline__ void tiled_drain(const uint32_t *tab, int32_t nb, con
             i = bc <= p ? cand : i;
         }
         if (act) {
-            const uint32_t x = uint32_t(int32_t(ent & uint32_t(kBinEvents - 1)) + id_off);
+            const uint32_t x = (ent & uint32_t(kBinEvents - 1)) + id_off;
             const uint32_t wi = x >> 5;
             const uint32_t rk = uint32_t(r16[wi]) + __popc(tab[wi] & ((1u << (x & 31u)) - 1u));
             __hip_atomic_fetch_add(sums + (jl + i), vals[rk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
@@ -167,11 +172,12 @@ __device__ __forceinline__ void tiled_drain(const uint32_t *tab, int32_t nb, con
 constexpr int kHalfRows = kWinRows / 2;
 constexpr int kQueueStride = kTiledQueue + 64;   // per wave: the queue, then a slot per lane for unflagged writes
 
-// LDS byte address of the filter word of bin-local ID l (bits `lo`.. of v hold l):
-// word (l + id_off) / 32 of the tile, id_off a multiple of 128 folded into woff.
+// LDS byte address of the filter word of the bin-local ID in bits LO.. of v: bin
+// k of the tile starts at byte 4096 k (woff), and a word address within a bin is
+// below 4096, so the two are combined with an OR.
 template <int LO>
 __device__ __forceinline__ uint32_t word_addr(uint32_t v, uint32_t woff) {
-    return (__builtin_amdgcn_ubfe(v, LO + 5, kBinShift - 5) << 2) + woff;
+    return ((v >> (LO + 3)) & 0xFFCu) | woff;
 }
 
 // Queue one ID slot (64 IDs, one per lane): mask m of the flagged lanes; entry
@@ -182,36 +188,15 @@ __device__ __forceinline__ void queue_slot(uint32_t *q, uint64_t m, uint32_t &qn
     qn += uint32_t(__popcll(m));
 }
 
-// Filter one row (IDs in v, filter words w0/w1) into the queue.  Positions outside
-// the window are queued too and dropped when the queue is resolved.  PART: the tile
-// holds part of the bin (IDs outside [lo_l, hi_l) are dropped).
-template <bool PART>
-__device__ __forceinline__ void filter_row(uint32_t *q, uint32_t &qn, uint32_t v, uint32_t w0, uint32_t w1,
-                                           uint32_t lo_l, uint32_t hi_l, uint32_t rel, uint32_t spare) {
-    const uint32_t l0 = v & 0xFFFFu, l1 = v >> 16;
-    // the bit of tile event x sits at x mod 32 = ID mod 32 (id_off is a multiple of 32)
-    uint64_t m0 = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(w0, v, 1) != 0u);
-    uint64_t m1 = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(w1, l1, 1) != 0u);
-    if (PART) {
-        m0 &= __builtin_amdgcn_ballot_w64(l0 - lo_l < hi_l - lo_l);
-        m1 &= __builtin_amdgcn_ballot_w64(l1 - lo_l < hi_l - lo_l);
-    }
-    queue_slot(q, m0, qn, rel | l0, spare);
-    queue_slot(q, m1, qn, (rel + (1u << kBinShift)) | l1, spare);
-}
-
 // Filter and drain one window [ws, we) of bin c.b (IDs in w), eight rows at a time:
-// first every row's LDS filter words are read (the reads overlap), then each row is
-// filtered into the queue.  PART: the tile holds only part of the bin.
-template <bool PART>
-__device__ __forceinline__ void tiled_window(const Tile &T, const uint32_t *tab, uint32_t *q, double *sums,
-                                             const TCur &c, uint32_t we, const TWin &w, int lane) {
-    const int32_t nb = T.blk_hi - T.blk_lo;
-    const int32_t bin_blk0 = c.b * kBlocksPerBin;
-    const uint32_t lo_l = uint32_t(max(T.blk_lo - bin_blk0, 0)) * kEventsPerBlock;
-    const uint32_t hi_l = uint32_t(min(T.blk_hi - bin_blk0, kBlocksPerBin)) * kEventsPerBlock;
-    const int32_t id_off = (bin_blk0 - T.blk_lo) * kEventsPerBlock;   // a multiple of 128
-    const uint32_t woff = uint32_t(id_off) >> 3;   // byte offset of the bin's first word (when id_off >= 0)
+// first every row's LDS filter words are read (the reads overlap), then each ID
+// slot is compacted into the queue by its flag mask.  Positions outside the window
+// (at its edge rows) are queued too and dropped when the queue is resolved; IDs
+// outside the tile's own blocks meet zero bits.
+__device__ __forceinline__ void tiled_window(const Tile &T, int32_t nb, const uint32_t *tab, uint32_t *q,
+                                             double *sums, const TCur &c, uint32_t we, const TWin &w, int lane) {
+    const uint32_t id_off = uint32_t(c.b - T.bin_lo) << kBinShift;   // first tile event of the bin
+    const uint32_t woff = id_off >> 3;                                // its filter word, in bytes
     const uint32_t ws2 = c.ws & ~1u;
     const uint32_t lane_rel = uint32_t(2 * lane) << kBinShift;
     const uint32_t spare = uint32_t(kTiledQueue + lane);
@@ -223,18 +208,8 @@ __device__ __forceinline__ void tiled_window(const Tile &T, const uint32_t *tab,
 #pragma unroll
         for (int k = 0; k < kHalfRows; ++k) {
             const uint32_t v = w.v[h * kHalfRows + k];
-            if (PART) {
-                // IDs outside the tile read word 0 (their flags are dropped)
-                const uint32_t l0 = v & 0xFFFFu, l1 = v >> 16;
-                const uint32_t x0 = l0 - lo_l < hi_l - lo_l ? uint32_t(int32_t(l0) + id_off) : 0u;
-                const uint32_t x1 = l1 - lo_l < hi_l - lo_l ? uint32_t(int32_t(l1) + id_off) : 0u;
-                w0[k] = tab[x0 >> 5];
-                w1[k] = tab[x1 >> 5];
-            } else {
-                // whole-bin tiles: every 15-bit ID of the bin is inside the tile
-                w0[k] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + word_addr<0>(v, woff));
-                w1[k] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + word_addr<16>(v, woff));
-            }
+            w0[k] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + word_addr<0>(v, woff));
+            w1[k] = *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(tab) + word_addr<16>(v, woff));
         }
 #pragma unroll
         for (int k = 0; k < kHalfRows; ++k) {
@@ -245,8 +220,13 @@ __device__ __forceinline__ void tiled_window(const Tile &T, const uint32_t *tab,
                 tiled_drain(tab, nb, q, qn, sums, ws2, c.ws, we, id_off, w.bnd, c.jl, lane);
                 qn = 0;
             }
+            const uint32_t v = w.v[r];
             const uint32_t rel = lane_rel + (uint32_t(128 * r) << kBinShift);
-            filter_row<PART>(q, qn, w.v[r], w0[k], w1[k], lo_l, hi_l, rel, spare);
+            // the bit of an ID sits at ID mod 32 of its word
+            const uint64_t m0 = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(w0[k], v, 1) != 0u);
+            const uint64_t m1 = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(w1[k], v >> 16, 1) != 0u);
+            queue_slot(q, m0, qn, rel | (v & 0xFFFFu), spare);
+            queue_slot(q, m1, qn, (rel + (1u << kBinShift)) | (v >> 16), spare);
         }
     }
     tiled_drain(tab, nb, q, qn, sums, ws2, c.ws, we, id_off, w.bnd, c.jl, lane);
@@ -273,8 +253,9 @@ __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
         for (int k = 0; k < kTiledWaveTrials / 64; ++k) sums[lane + 64 * k] = 0.0;
         for (uint32_t k = 0; k < nt; ++k) {
             const Tile T = load_tile(a.tiles, k);
+            const int32_t nb = tile_span_blocks(T.blk_lo, T.blk_hi, a.nblk);
             __syncthreads();
-            stage_tile(a, T, tab);
+            stage_tile(a, T, nb, tab);
             __syncthreads();
             if (T0 >= T1) continue;
             TCur c;
@@ -300,10 +281,7 @@ __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
                 n = tcur_uniform(n);
                 TWin B;
                 twin_load(a, T, n, T0, T1, lane, B);
-                if (T.blk_lo > c.b * kBlocksPerBin || T.blk_hi < (c.b + 1) * kBlocksPerBin)
-                    tiled_window<true>(T, tab, q, sums, c, we, A, lane);
-                else
-                    tiled_window<false>(T, tab, q, sums, c, we, A, lane);
+                tiled_window(T, nb, tab, q, sums, c, we, A, lane);
                 c = n;
                 A = B;
             }
