@@ -196,3 +196,35 @@ def test_batch_with_tiled_jobs_equals_plain(A, S, gpu_ctx):
     finally:
         a1.release()
         a2.release()
+
+
+def test_several_passes_per_workgroup(A, S, gpu_ctx):
+    """600,000 short trials: each persistent workgroup owns more trials than one pass
+    (2016) holds, so the per-trial sums are reset and the tiles restaged per pass;
+    a 70,000-event catalog in three bins, binary32 tables (too large for the dense LDS
+    table) and non-identity ELT terms."""
+    rng = np.random.default_rng(305)
+    C = 70_000
+    n = 600_000
+    lengths = rng.integers(25, 46, size=n)
+    w = _workload(rng, lengths, C, n_elts=3, nnz=12_000)
+    w = synth.Workload("passes", w.event_ids, w.trial_offsets, C, w.elts, w.layer_terms,
+                       [(1.1, 100.0, 2e6), (1.0, 0.0, INF), (0.9, 0.0, INF)], (10.0,), 0)
+    _say("tiled several passes")
+    an = _open(A, S, gpu_ctx, w, precision=A.ARA_F32)
+    try:
+        assert A.ara_yet_info(an.yet)[2] == 2
+        got = _run(A, gpu_ctx, an, 0)
+        assert A.ara_layer_stats(gpu_ctx, an.layer)[1] in (BITMAP, TILES)
+        assert _run(A, gpu_ctx, an, TILES).tobytes() == got.tobytes(), "auto placement must pick the tiled kernel"
+        ref = oracle.analyze_workload(w, threads=oracle.max_threads(), dat_f32=True)
+        tol = 2.0 ** -23 * 1.0001 * ref["gross_total"] + 1e-12 * np.maximum(np.abs(ref["ylt"]), ref["occ_total"])
+        bad = np.nonzero(~(np.abs(got - ref["ylt"]) <= tol))[0]
+        assert bad.size == 0, (bad[:5], got[bad[:5]], ref["ylt"][bad[:5]])
+        assert _run(A, gpu_ctx, an, 0).tobytes() == got.tobytes()
+        sub = _run(A, gpu_ctx, an, 0, 123_457, 599_999)
+        assert sub.tobytes() == _run(A, gpu_ctx, an, 0, 123_457, 599_999).tobytes()
+        bad = np.nonzero(~(np.abs(sub - ref["ylt"][123_457:599_999]) <= tol[123_457:599_999]))[0]
+        assert bad.size == 0
+    finally:
+        an.release()
