@@ -193,7 +193,7 @@ struct Tile {
 };
 constexpr int kTiledWaves = 16;                 // waves per workgroup of the tiled kernel
 constexpr int kTiledQueue = 256;                // per-wave queue of flagged occurrences
-constexpr int kTiledWaveTrials = 128;           // trials per wave and pass (an LDS sum each)
+constexpr int kTiledWaveTrials = 256;           // trials per wave and pass (an LDS sum each)
 // LDS left for the tile after the per-wave queues (and a write slot per lane) and
 // per-trial sums
 constexpr int kTiledLdsBytes = kLdsMaxBytes - kTiledWaves * ((kTiledQueue + 64) * 4 + kTiledWaveTrials * 8);

@@ -13,7 +13,7 @@
 // (k_bin.hip), so that every lookup is an LDS access and the only HBM traffic is
 // the stream of 2-byte IDs.
 //
-// Per wave and bin, the occurrences of the wave's 128 trials are one contiguous
+// Per wave and bin, the occurrences of the wave's trials (up to 252) are one contiguous
 // span, read in windows of up to 2048 (16 coalesced rows of 64 lanes x 2 IDs):
 //   filter  each ID's LDS bit; flagged occurrences are appended to the wave's LDS
 //           queue with their position in the window;
@@ -29,8 +29,10 @@ namespace ara {
 
 constexpr int kTileWords = kTiledLdsBytes / 4;
 // trials per wave and pass: a window spans at most 63 trials (one boundary per lane),
-// so 126 trials make exactly two windows per bin when a bin's span fits two
-constexpr int kWaveTrials = 126;
+// so 252 trials make exactly four windows per bin when a bin's span fits four.  A
+// pass of 16 waves then covers 4032 trials: one pass per workgroup for a million
+// trials on 256 CUs (each pass stages every tile once)
+constexpr int kWaveTrials = 252;
 static_assert(kWaveTrials <= kTiledWaveTrials, "per-trial sums");
 constexpr int kPassTrials = kWaveTrials * kTiledWaves;   // trials per workgroup pass
 constexpr int kWinRows = 16;
@@ -139,34 +141,62 @@ __device__ __forceinline__ void twin_load(const TiledArgs &a, const Tile &T, con
         w.v[r] = __builtin_amdgcn_raw_buffer_load_b32(ri, int((ws2 + uint32_t(128 * r + 2 * lane)) * 2u), 0, kNonTemporal);
 }
 
-// Resolve queue entries [0, qn) of the current window: value, trial, add to the
-// trial's sum.
+// Resolve N rows of queue entries from r0 on (entries below qn) of the current
+// window: value, trial, add to the trial's sum.  Two rows at a time interleave their
+// dependent LDS round trips; the adds keep row order.
+template <int N>
+__device__ __forceinline__ void drain_rows(const uint32_t *tab, const uint16_t *r16, const double *vals,
+                                           const uint32_t *q, uint32_t r0, uint32_t qn, double *sums_jl, uint32_t ws2,
+                                           uint32_t ws, uint32_t we, uint32_t id_off, uint32_t bnd, int lane) {
+    uint32_t p[N], i4[N];
+    double v[N];
+    bool act[N];
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        const uint32_t at = r0 + uint32_t(64 * n + lane);
+        const bool in_q = at < qn;
+        const uint32_t ent = in_q ? q[at] : 0u;
+        p[n] = ws2 + (ent >> kBinShift);
+        act[n] = in_q && p[n] - ws < we - ws;   // rows at the window's edges queue a few outside it
+        // the value does not depend on the trial, so its reads overlap the search below;
+        // lanes past the queue's end read the bin's first word (a valid address) and
+        // add nothing
+        const uint32_t x = (ent & uint32_t(kBinEvents - 1)) + id_off;
+        const uint32_t wi = x >> 5;
+        const uint32_t rk = uint32_t(r16[wi]) + __popc(tab[wi] & ((1u << (x & 31u)) - 1u));
+        v[n] = vals[rk];
+        i4[n] = 0;
+    }
+    // largest i with boundary(jl + i) <= p: the trial of position p (all lanes take
+    // part: each reads other lanes' boundaries); i4 = 4 i, the lane's byte address
+#pragma unroll
+    for (uint32_t step4 = 128; step4 >= 4; step4 >>= 1) {
+#pragma unroll
+        for (int n = 0; n < N; ++n) {
+            const uint32_t cand4 = i4[n] | step4;
+            const uint32_t bc = uint32_t(__builtin_amdgcn_ds_bpermute(int(cand4), int(bnd)));
+            i4[n] = bc <= p[n] ? cand4 : i4[n];
+        }
+    }
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+        if (act[n]) {
+            double *dst = reinterpret_cast<double *>(reinterpret_cast<char *>(sums_jl) + 2u * i4[n]);
+            __hip_atomic_fetch_add(dst, v[n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+    }
+}
+
+// Resolve queue entries [0, qn) of the current window.
 __device__ __forceinline__ void tiled_drain(const uint32_t *tab, int32_t nb, const uint32_t *q, uint32_t qn,
                                             double *sums, uint32_t ws2, uint32_t ws, uint32_t we, uint32_t id_off,
                                             uint32_t bnd, uint32_t jl, int lane) {
     const uint16_t *r16 = reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(tab) + tile_rank_offset(nb));
     const double *vals = reinterpret_cast<const double *>(reinterpret_cast<const char *>(tab) + tile_vals_offset(nb));
-    for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
-        const bool in_q = r0 + uint32_t(lane) < qn;
-        const uint32_t ent = in_q ? q[r0 + lane] : 0u;
-        const uint32_t p = ws2 + (ent >> kBinShift);
-        const bool act = in_q && p - ws < we - ws;   // rows at the window's edges queue a few outside it
-        // largest i with boundary(jl + i) <= p: the trial of position p (all lanes take
-        // part: each reads other lanes' boundaries)
-        uint32_t i = 0;
-#pragma unroll
-        for (uint32_t step = 32; step >= 1; step >>= 1) {
-            const uint32_t cand = i + step;
-            const uint32_t bc = uint32_t(__builtin_amdgcn_ds_bpermute(int(cand << 2), int(bnd)));
-            i = bc <= p ? cand : i;
-        }
-        if (act) {
-            const uint32_t x = (ent & uint32_t(kBinEvents - 1)) + id_off;
-            const uint32_t wi = x >> 5;
-            const uint32_t rk = uint32_t(r16[wi]) + __popc(tab[wi] & ((1u << (x & 31u)) - 1u));
-            __hip_atomic_fetch_add(sums + (jl + i), vals[rk], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        }
-    }
+    uint32_t r0 = 0;
+    for (; r0 + 128 < qn; r0 += 192) drain_rows<3>(tab, r16, vals, q, r0, qn, sums + jl, ws2, ws, we, id_off, bnd, lane);
+    for (; r0 + 64 < qn; r0 += 128) drain_rows<2>(tab, r16, vals, q, r0, qn, sums + jl, ws2, ws, we, id_off, bnd, lane);
+    if (r0 < qn) drain_rows<1>(tab, r16, vals, q, r0, qn, sums + jl, ws2, ws, we, id_off, bnd, lane);
 }
 
 constexpr int kHalfRows = kWinRows / 2;
@@ -183,7 +213,7 @@ __device__ __forceinline__ uint32_t word_addr(uint32_t v, uint32_t woff) {
 // Queue one ID slot (64 IDs, one per lane): mask m of the flagged lanes; entry
 // values ent.  Unflagged lanes write their own slot past the queue.
 __device__ __forceinline__ void queue_slot(uint32_t *q, uint64_t m, uint32_t &qn, uint32_t ent, uint32_t spare) {
-    const uint32_t at = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)) + qn;
+    const uint32_t at = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), qn));
     q[__builtin_amdgcn_inverse_ballot_w64(m) ? at : spare] = ent;
     qn += uint32_t(__popcll(m));
 }
@@ -232,6 +262,30 @@ __device__ __forceinline__ void tiled_window(const Tile &T, int32_t nb, const ui
     tiled_drain(tab, nb, q, qn, sums, ws2, c.ws, we, id_off, w.bnd, c.jl, lane);
 }
 
+// One window of cursor c (its IDs in cur): find where it ends, advance c to the next
+// window and issue that window's loads into nxt, then filter and drain this one.
+__device__ __forceinline__ void tiled_step(const TiledArgs &a, const Tile &T, int64_t T0, int64_t T1, int32_t nb,
+                                           const uint32_t *tab, uint32_t *q, double *sums, int lane, TCur &c,
+                                           const TWin &cur, TWin &nxt) {
+    // this window ends at the span end, after 2048 positions, or where trial jl + 63
+    // starts (so its trials are jl .. jl + 62: one per boundary lane)
+    const uint32_t b63 = uint32_t(__builtin_amdgcn_readlane(int(cur.bnd), 63));
+    const uint32_t we = min(min((c.ws & ~1u) + uint32_t(kWindow), c.e), max(b63, c.ws));
+    // next cursor: the trial containing we, or the next bin
+    TCur n = c;
+    const uint64_t le = __builtin_amdgcn_ballot_w64(cur.bnd <= we);
+    n.jl = c.jl + uint32_t(__popcll(le)) - 1u;
+    n.ws = we;
+    if (we >= c.e) {
+        n.b = c.b + 1;
+        tcur_seek(a, T, T0, T1, n);
+    }
+    n = tcur_uniform(n);
+    twin_load(a, T, n, T0, T1, lane, nxt);
+    tiled_window(T, nb, tab, q, sums, c, we, cur, lane);
+    c = n;
+}
+
 __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t tab[kTileWords];
     __shared__ uint32_t queues[kTiledWaves * kQueueStride];
@@ -265,24 +319,8 @@ __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
             TWin A;
             twin_load(a, T, c, T0, T1, lane, A);
             while (c.b < T.bin_hi) {
-                // this window ends at the span end, after 2048 positions, or where trial
-                // jl + 63 starts (so its trials are jl .. jl + 62: one per boundary lane)
-                const uint32_t b63 = uint32_t(__builtin_amdgcn_readlane(int(A.bnd), 63));
-                const uint32_t we = min(min((c.ws & ~1u) + uint32_t(kWindow), c.e), max(b63, c.ws));
-                // next cursor: the trial containing we, or the next bin
-                TCur n = c;
-                const uint64_t le = __builtin_amdgcn_ballot_w64(A.bnd <= we);
-                n.jl = c.jl + uint32_t(__popcll(le)) - 1u;
-                n.ws = we;
-                if (we >= c.e) {
-                    n.b = c.b + 1;
-                    tcur_seek(a, T, T0, T1, n);
-                }
-                n = tcur_uniform(n);
                 TWin B;
-                twin_load(a, T, n, T0, T1, lane, B);
-                tiled_window(T, nb, tab, q, sums, c, we, A, lane);
-                c = n;
+                tiled_step(a, T, T0, T1, nb, tab, q, sums, lane, c, A, B);
                 A = B;
             }
         }

@@ -199,13 +199,13 @@ def test_batch_with_tiled_jobs_equals_plain(A, S, gpu_ctx):
 
 
 def test_several_passes_per_workgroup(A, S, gpu_ctx):
-    """600,000 short trials: each persistent workgroup owns more trials than one pass
-    (2016) holds, so the per-trial sums are reset and the tiles restaged per pass;
+    """1,200,000 short trials: each persistent workgroup owns more trials than one pass
+    (4032) holds, so the per-trial sums are reset and the tiles restaged per pass;
     a 70,000-event catalog in three bins, binary32 tables (too large for the dense LDS
     table) and non-identity ELT terms."""
     rng = np.random.default_rng(305)
     C = 70_000
-    n = 600_000
+    n = 1_200_000
     lengths = rng.integers(25, 46, size=n)
     w = _workload(rng, lengths, C, n_elts=3, nnz=12_000)
     w = synth.Workload("passes", w.event_ids, w.trial_offsets, C, w.elts, w.layer_terms,
@@ -222,9 +222,9 @@ def test_several_passes_per_workgroup(A, S, gpu_ctx):
         bad = np.nonzero(~(np.abs(got - ref["ylt"]) <= tol))[0]
         assert bad.size == 0, (bad[:5], got[bad[:5]], ref["ylt"][bad[:5]])
         assert _run(A, gpu_ctx, an, 0).tobytes() == got.tobytes()
-        sub = _run(A, gpu_ctx, an, 0, 123_457, 599_999)
-        assert sub.tobytes() == _run(A, gpu_ctx, an, 0, 123_457, 599_999).tobytes()
-        bad = np.nonzero(~(np.abs(sub - ref["ylt"][123_457:599_999]) <= tol[123_457:599_999]))[0]
+        sub = _run(A, gpu_ctx, an, 0, 123_457, 1_199_999)
+        assert sub.tobytes() == _run(A, gpu_ctx, an, 0, 123_457, 1_199_999).tobytes()
+        bad = np.nonzero(~(np.abs(sub - ref["ylt"][123_457:1_199_999]) <= tol[123_457:1_199_999]))[0]
         assert bad.size == 0
     finally:
         an.release()
