@@ -646,9 +646,10 @@ static ara_status layer_enqueue_build(ara_layer *L, int flags) {
         e = launch_elt_clear(L->d_descs, n, L->catalog, c->stream);
         if (e == hipSuccess) e = launch_elt_scatter(L->d_descs, n, L->max_pairs, L->catalog, c->d_err, c->stream);
     }
-    if (e == hipSuccess) e = launch_layer_combine(L->d_descs, n, L->catalog, L->f32, 0.0, 0.0, L->t, c->stream);
-    if (e != hipSuccess) return hip_fail(c, e, "layer build");
-    return layer_enqueue_filter(L);
+    if (e == hipSuccess)
+        e = launch_layer_tables(L->d_descs, n, L->catalog, L->f32, L->terms.occ_retention, L->terms.occ_limit, L->t,
+                                c->stream);
+    return e == hipSuccess ? ARA_OK : hip_fail(c, e, "layer build");
 }
 
 static void layer_free(ara_layer *L) {
@@ -1547,9 +1548,9 @@ static ara_status server_iteration(ara_server *sv, const std::vector<ServerReque
         const int n = int(r->elts.size());
         hipError_t e = hipSuccess;
         if (n > 0) e = hipMemcpyAsync(L->d_descs, hd, sizeof(EltDesc) * size_t(n), hipMemcpyHostToDevice, sv->stream);
-        if (e == hipSuccess) e = launch_layer_combine(L->d_descs, n, L->catalog, L->f32, 0.0, 0.0, L->t, sv->stream);
         if (e == hipSuccess)
-            e = launch_layer_filter(L->catalog, L->f32, r->terms.occ_retention, r->terms.occ_limit, L->t, sv->stream);
+            e = launch_layer_tables(L->d_descs, n, L->catalog, L->f32, r->terms.occ_retention, r->terms.occ_limit, L->t,
+                                    sv->stream);
         if (e != hipSuccess) return hip_fail(pc, e, "server layer build");
         TrialLaunch tl{};
         ara_status s = plan_trial(pc, L, r->t1 - r->t0, double(sv->yet->n_events) / double(std::max<int64_t>(1, sv->yet->n_trials)), tl,

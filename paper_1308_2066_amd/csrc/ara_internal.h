@@ -101,8 +101,10 @@ hipError_t launch_yet_pack(const int32_t *ids, int64_t n_events, uint8_t *packed
 hipError_t launch_elt_clear(const EltDesc *d, int n_elts, int32_t catalog, hipStream_t s);
 hipError_t launch_elt_scatter(const EltDesc *d, int n_elts, int64_t max_pairs, int32_t catalog, uint32_t *err,
                               hipStream_t s);
-hipError_t launch_layer_combine(const EltDesc *d, int n_elts, int32_t catalog, bool f32, double occ_r, double occ_l,
-                                const LayerTables &t, hipStream_t s);
+// combined table, occurrence filter, ranks, tiles and compacted values of a layer
+hipError_t launch_layer_tables(const EltDesc *d, int n_elts, int32_t catalog, bool f32, double occ_r, double occ_l,
+                               const LayerTables &t, hipStream_t s);
+// the same from an existing combined table (new occurrence terms)
 hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double occ_l, const LayerTables &t,
                                hipStream_t s);
 
@@ -207,8 +209,6 @@ __host__ __device__ inline int32_t tile_span_blocks(int32_t lo, int32_t hi, int3
     const int32_t b1 = ((hi - 1) / kBlocksPerBin + 1) * kBlocksPerBin;
     return (b1 < nblk ? b1 : nblk) - b0;
 }
-hipError_t launch_layer_tiles(const uint32_t *rank, const uint32_t *n_flagged, int32_t nblk, int32_t n_bins,
-                              Tile *tiles, uint32_t *n_tiles, hipStream_t s);
 
 struct TiledArgs {
     const uint16_t *ids16;

@@ -26,21 +26,6 @@ __device__ __forceinline__ double excess(double x, double retention, double limi
 }
 
 template <typename V>
-__global__ __launch_bounds__(256) void k_layer_combine(const EltDesc *__restrict__ d, int n_elts, int32_t catalog,
-                                                       V *__restrict__ comb) {
-    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= catalog) return;
-    double s = 0.0;
-    for (int j = 0; j < n_elts; ++j) {
-        const EltDesc &t = d[j];
-        double x = t.f32 ? double(reinterpret_cast<const float *>(t.dat)[e]) : reinterpret_cast<const double *>(t.dat)[e];
-        if (!t.identity) x = excess(t.fx * x, t.retention, t.limit);
-        s = s + x;
-    }
-    comb[e] = V(s);
-}
-
-template <typename V>
 __global__ __launch_bounds__(256) void k_layer_bitmap(const V *__restrict__ comb, int32_t catalog, double occ_r,
                                                       double occ_l, double *__restrict__ occ,
                                                       uint32_t *__restrict__ bitmap, int64_t n_words) {
@@ -60,20 +45,74 @@ __global__ __launch_bounds__(256) void k_layer_bitmap(const V *__restrict__ comb
     if (lane == 1) bitmap[w0 + 1] = uint32_t(m >> 32);
 }
 
-// Exclusive prefix of per-block set-bit counts.  Single workgroup of 1024.
+// The combined table and the occurrence filter in one pass over the catalog: per
+// event, the ELTs' terms-applied losses added in listed order from +0.0 (rounded to
+// the table's type), then the operations of k_layer_bitmap on the stored value.
+template <typename V>
+__global__ __launch_bounds__(256) void k_layer_combine_bitmap(const EltDesc *__restrict__ d, int n_elts,
+                                                              int32_t catalog, V *__restrict__ comb, double occ_r,
+                                                              double occ_l, double *__restrict__ occ,
+                                                              uint32_t *__restrict__ bitmap, int64_t n_words) {
+    const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    bool flag = false;
+    if (e < catalog) {
+        double s = 0.0;
+        for (int j = 0; j < n_elts; ++j) {
+            const EltDesc &t = d[j];
+            double x = t.f32 ? double(reinterpret_cast<const float *>(t.dat)[e]) : reinterpret_cast<const double *>(t.dat)[e];
+            if (!t.identity) x = excess(t.fx * x, t.retention, t.limit);
+            s = s + x;
+        }
+        const V c = V(s);
+        comb[e] = c;
+        const double o = excess(double(c), occ_r, occ_l);
+        occ[e] = o;
+        flag = o > 0.0;
+    }
+    const uint64_t m = __ballot(flag);
+    const int lane = threadIdx.x & 63;
+    const int64_t w0 = (e - lane) >> 5;   // even; n_words is a multiple of 4
+    if (w0 >= n_words) return;
+    if (lane == 0) bitmap[w0] = uint32_t(m);
+    if (lane == 1) bitmap[w0 + 1] = uint32_t(m >> 32);
+}
+
+// Exclusive prefix of per-block set-bit counts (rank), the same split into a 16-bit
+// offset within its superblock of 256 blocks and a 32-bit base per superblock
+// (rel16/base32: a smaller table to keep in LDS), and the total.  Single workgroup
+// of 1024.  With `tiles`, thread 0 then cuts the filter into tiles for the tiled
+// trial kernel (below).
+__device__ void plan_tiles(const uint32_t *rank, const uint32_t *at_bin, uint32_t total, int32_t nblk,
+                           int32_t n_bins, Tile *tiles, uint32_t *n_tiles);
+
 __global__ __launch_bounds__(1024) void k_layer_rank(const uint32_t *__restrict__ bitmap, int32_t nblk,
-                                                     uint32_t *__restrict__ rank, uint32_t *__restrict__ n_flagged) {
+                                                     uint32_t *__restrict__ rank, uint32_t *__restrict__ n_flagged,
+                                                     uint16_t *__restrict__ rel16, uint32_t *__restrict__ base32,
+                                                     int32_t n_bins, Tile *__restrict__ tiles,
+                                                     uint32_t *__restrict__ n_tiles) {
+    // each thread takes 8 consecutive blocks (their loads issued together), so a
+    // catalog of up to 2^20 events is one round of loads and one scan
+    constexpr int kPer = 8, kChunk = 1024 * kPer;
+    static_assert(kChunk % kBlocksPerSuper == 0 && kBlocksPerSuper % kPer == 0 && kBlocksPerBin == kBlocksPerSuper,
+                  "superblocks and bins are whole in a chunk and start at a thread's first block");
     __shared__ uint32_t wsum[16];
+    __shared__ uint32_t sbase[kChunk / kBlocksPerSuper];
+    __shared__ uint32_t at_bin[kMaxBins + 1];   // counts at bin starts, for the planner
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     uint32_t carry = 0;
-    for (int32_t base = 0; base < nblk; base += 1024) {
-        const int32_t b = base + tid;
-        uint32_t c = 0;
-        if (b < nblk) {
-            const uint4 q = reinterpret_cast<const uint4 *>(bitmap)[b];
-            c = __popc(q.x) + __popc(q.y) + __popc(q.z) + __popc(q.w);
+    for (int32_t base = 0; base < nblk; base += kChunk) {
+        const int32_t b0 = base + tid * kPer;
+        uint4 q[kPer];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j)
+            q[j] = b0 + j < nblk ? reinterpret_cast<const uint4 *>(bitmap)[b0 + j] : make_uint4(0u, 0u, 0u, 0u);
+        uint32_t c[kPer], tot = 0;
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            c[j] = __popc(q[j].x) + __popc(q[j].y) + __popc(q[j].z) + __popc(q[j].w);
+            tot += c[j];
         }
-        uint32_t inc = c;   // inclusive wave scan
+        uint32_t inc = tot;   // inclusive wave scan of the threads' totals
         for (int o = 1; o < 64; o <<= 1) {
             uint32_t y = __shfl_up(inc, o, 64);
             if (lane >= o) inc += y;
@@ -85,23 +124,31 @@ __global__ __launch_bounds__(1024) void k_layer_rank(const uint32_t *__restrict_
             if (k < w) before += wsum[k];
             total += wsum[k];
         }
-        if (b < nblk) rank[b] = carry + before + inc - c;
+        uint32_t r = carry + before + inc - tot;
+        if (b0 % kBlocksPerSuper == 0 && b0 < nblk) {
+            const int32_t sb = b0 / kBlocksPerSuper;
+            sbase[(b0 - base) / kBlocksPerSuper] = r;
+            base32[sb] = r;
+            if (sb < kMaxBins) at_bin[sb] = r;
+        }
+        __syncthreads();
+        const uint32_t sr = sbase[(b0 - base) / kBlocksPerSuper];
+#pragma unroll
+        for (int j = 0; j < kPer; ++j) {
+            if (b0 + j < nblk) {
+                rank[b0 + j] = r;
+                rel16[b0 + j] = uint16_t(r - sr);
+            }
+            r += c[j];
+        }
         carry += total;
         __syncthreads();
     }
-    if (tid == 0) *n_flagged = carry;
-}
-
-// rel16/base32: the per-block rank split into a 16-bit offset within its superblock
-// of 256 blocks and a 32-bit base per superblock (a smaller table to keep in LDS).
-__global__ __launch_bounds__(256) void k_layer_rank16(const uint32_t *__restrict__ rank, int32_t nblk,
-                                                      uint16_t *__restrict__ rel16, uint32_t *__restrict__ base32) {
-    const int32_t b = int32_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (b >= nblk) return;
-    const int32_t sb = b / kBlocksPerSuper;
-    const uint32_t base = rank[sb * kBlocksPerSuper];
-    rel16[b] = uint16_t(rank[b] - base);
-    if (b % kBlocksPerSuper == 0) base32[sb] = base;
+    if (tid != 0) return;
+    *n_flagged = carry;
+    if (!tiles) return;
+    at_bin[n_bins] = carry;
+    plan_tiles(rank, at_bin, carry, nblk, n_bins, tiles, n_tiles);
 }
 
 __global__ __launch_bounds__(256) void k_layer_compact(const double *__restrict__ occ, int32_t catalog,
@@ -121,14 +168,15 @@ __global__ __launch_bounds__(256) void k_layer_compact(const double *__restrict_
 
 // Tiles of the filter for the tiled trial kernel: consecutive 128-event blocks whose
 // bits (padded to whole bins), per-word counts and flagged values fit
-// kTiledLdsBytes.  Whole catalog bins are added while they fit (a tile then reads each of its bins' occurrences once);
-// a bin too dense to fit alone is cut at block boundaries.  One thread: at most a
-// few hundred bins, and block steps only inside bins that must be cut.
-__global__ void k_layer_tiles(const uint32_t *__restrict__ rank, const uint32_t *__restrict__ n_flagged, int32_t nblk,
-                              int32_t n_bins, Tile *__restrict__ tiles, uint32_t *__restrict__ n_tiles) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const uint32_t total = *n_flagged;
-    auto rk = [&](int32_t b) { return b >= nblk ? total : rank[b]; };
+// kTiledLdsBytes.  Whole catalog bins are added while they fit (a tile then reads
+// each of its bins' occurrences once); a bin too dense to fit alone is cut at block
+// boundaries.  One thread, after the ranks are written: at most a few hundred bins
+// (their start counts in LDS), and block steps only inside bins that must be cut.
+__device__ void plan_tiles(const uint32_t *rank, const uint32_t *at_bin, uint32_t total, int32_t nblk,
+                           int32_t n_bins, Tile *tiles, uint32_t *n_tiles) {
+    auto rk = [&](int32_t b) {
+        return b >= nblk ? total : (b % kBlocksPerBin == 0 ? at_bin[b / kBlocksPerBin] : rank[b]);
+    };
     auto fits = [&](int32_t lo, int32_t hi) {
         return tile_bytes(tile_span_blocks(lo, hi, nblk), rk(hi) - rk(lo)) <= size_t(kTiledLdsBytes);
     };
@@ -168,24 +216,39 @@ __global__ void k_layer_tiles(const uint32_t *__restrict__ rank, const uint32_t 
     *n_tiles = nt;
 }
 
-hipError_t launch_layer_tiles(const uint32_t *rank, const uint32_t *n_flagged, int32_t nblk, int32_t n_bins,
-                              Tile *tiles, uint32_t *n_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_layer_tiles, dim3(1), dim3(64), 0, s, rank, n_flagged, nblk, n_bins, tiles, n_tiles);
+// Ranks (with rel16/base32 and, for catalogs of at most kMaxBins bins, the tiles:
+// tiles serve only YETs with a catalog-binned copy) and the compacted values.
+static hipError_t launch_rank_compact(int32_t catalog, const LayerTables &t, hipStream_t s) {
+    const int32_t n_bins = catalog_bins(catalog);
+    Tile *tiles = t.tiles && n_bins <= kMaxBins ? t.tiles : nullptr;
+    hipLaunchKernelGGL(k_layer_rank, dim3(1), dim3(1024), 0, s, t.bitmap, t.nblk, t.rank, t.n_flagged, t.rel16,
+                       t.base32, n_bins, tiles, t.n_tiles);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned ev_blocks = unsigned((int64_t(catalog) + 255) / 256);
+    hipLaunchKernelGGL(k_layer_compact, dim3(ev_blocks), dim3(256), 0, s, t.occ, catalog, t.bitmap, t.rank, t.vals);
     return hipGetLastError();
 }
 
-hipError_t launch_layer_combine(const EltDesc *d, int n_elts, int32_t catalog, bool f32, double, double,
-                                const LayerTables &t, hipStream_t s) {
-    const unsigned blocks = unsigned((int64_t(catalog) + 255) / 256);
-    if (f32) hipLaunchKernelGGL(k_layer_combine<float>, dim3(blocks), dim3(256), 0, s, d, n_elts, catalog, (float *)t.comb);
-    else hipLaunchKernelGGL(k_layer_combine<double>, dim3(blocks), dim3(256), 0, s, d, n_elts, catalog, (double *)t.comb);
-    return hipGetLastError();
+hipError_t launch_layer_tables(const EltDesc *d, int n_elts, int32_t catalog, bool f32, double occ_r, double occ_l,
+                               const LayerTables &t, hipStream_t s) {
+    // the bitmap covers nblk*128 event slots = nblk*2 waves; launch whole waves only
+    const unsigned blocks = unsigned((int64_t(t.nblk) * kEventsPerBlock + 255) / 256);
+    if (f32) {
+        hipLaunchKernelGGL(k_layer_combine_bitmap<float>, dim3(blocks), dim3(256), 0, s, d, n_elts, catalog,
+                           (float *)t.comb, occ_r, occ_l, t.occ, t.bitmap, int64_t(t.nblk) * 4);
+    } else {
+        hipLaunchKernelGGL(k_layer_combine_bitmap<double>, dim3(blocks), dim3(256), 0, s, d, n_elts, catalog,
+                           (double *)t.comb, occ_r, occ_l, t.occ, t.bitmap, int64_t(t.nblk) * 4);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_rank_compact(catalog, t, s);
 }
 
 hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double occ_l, const LayerTables &t,
                                hipStream_t s) {
-    const unsigned ev_blocks = unsigned((int64_t(catalog) + 255) / 256);
-    // bitmap covers nblk*128 event slots = nblk*2 waves; launch whole waves only
+    // the bitmap covers nblk*128 event slots = nblk*2 waves; launch whole waves only
     const unsigned bm_threads_blocks = unsigned((int64_t(t.nblk) * kEventsPerBlock + 255) / 256);
     if (f32) {
         hipLaunchKernelGGL(k_layer_bitmap<float>, dim3(bm_threads_blocks), dim3(256), 0, s, (const float *)t.comb,
@@ -196,17 +259,7 @@ hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double o
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_layer_rank, dim3(1), dim3(1024), 0, s, t.bitmap, t.nblk, t.rank, t.n_flagged);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_layer_rank16, dim3(unsigned((t.nblk + 255) / 256)), dim3(256), 0, s, t.rank, t.nblk, t.rel16,
-                       t.base32);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_layer_compact, dim3(ev_blocks), dim3(256), 0, s, t.occ, catalog, t.bitmap, t.rank, t.vals);
-    e = hipGetLastError();
-    if (e != hipSuccess || !t.tiles) return e;
-    return launch_layer_tiles(t.rank, t.n_flagged, t.nblk, catalog_bins(catalog), t.tiles, t.n_tiles, s);
+    return launch_rank_compact(catalog, t, s);
 }
 
 }  // namespace ara

@@ -6,8 +6,8 @@
 // LSD radix sort of 64-bit keys, 8-bit digits, 8 passes.  A binary64 value maps to
 // an unsigned key whose order is the value order (sign flip for non-negatives,
 // complement for negatives, -0.0 canonicalised to +0.0); descending order sorts the
-// complemented key ascending.  The encoding pass also counts the digits of all 8
-// passes; a pass in which every key has the same digit is skipped on the device
+// complemented key ascending.  The encoding pass also finds the digits in which
+// keys differ; a pass in which every key has the same digit is skipped on the device
 // (capped YLTs often hold one value many times).  Each other pass: per-tile digit
 // counts, exclusive offsets per (digit, tile), and a stable scatter in which every
 // wave ranks its keys by matching digits across lanes with 8 ballots.
@@ -35,13 +35,14 @@ __device__ __forceinline__ double key_value(uint64_t k) {
 
 static inline int64_t sort_tiles(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
-// Workspace: two key buffers, per-(digit, tile) counts, the 8 digit histograms of
-// all keys, and the pass plan (which buffer holds the keys before each pass, and
-// which passes leave the order unchanged because every key has the same digit).
+// Workspace: two key buffers, per-(digit, tile) counts, the encoding's digit
+// differences (one 64-bit word per workgroup), and the pass plan (which buffer holds
+// the keys before each pass, and which passes leave the order unchanged because
+// every key has the same digit).
 struct SortWs {
     uint64_t *a, *b;
     uint32_t *counts;   // [256][tiles]
-    uint32_t *hist;     // [8][256]
+    uint32_t *hist;     // 8 KB: the encoding's per-workgroup digit differences (uint64)
     uint32_t *plan;     // plan[p]: keys before pass p are in b (1) or a (0), p = 0..8;
                         // plan[16 + p]: pass p is skipped
     double *part;       // [kRiskGroup][kRiskMaxBlocks] partial sums of the top-k keys
@@ -76,62 +77,52 @@ __device__ __forceinline__ const uint64_t *cur_keys(const SortWs &w, int pass) {
     return w.plan[pass] ? w.b : w.a;
 }
 
-__global__ __launch_bounds__(256) void k_sort_init(uint32_t *hist, uint32_t *plan) {
-    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) hist[i] = 0;
-    if (threadIdx.x < 32) plan[threadIdx.x] = 0;
-}
+// Encode values into descending-order keys.  A pass leaves the order unchanged when
+// every key has the same digit in it; so each workgroup also ORs key ^ (the first
+// key) over its keys, and a pass is skipped when that digit of the OR over all
+// workgroups is zero.  A wave reads 8 rows of 64 values at a time.
+constexpr int kEncodeBlocks = 256;   // workgroups of k_sort_encode (one OR slot each)
 
-// Encode values into descending-order keys and count the digits of all 8 passes.
-// Lanes that share the wave's first lane's digit add their count once (year losses
-// often repeat one value, e.g. an aggregate limit); the others add their own.
 __global__ __launch_bounds__(256) void k_sort_encode(const double *__restrict__ in, int64_t n,
-                                                     uint64_t *__restrict__ keys, uint32_t *__restrict__ hist) {
-    __shared__ uint32_t h[8][256];
-    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) (&h[0][0])[i] = 0;
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
+                                                     uint64_t *__restrict__ keys, uint64_t *__restrict__ diff) {
+    constexpr int kRows = 8;
+    __shared__ uint64_t wdiff[4];
+    const uint64_t k0 = desc_key(in[0]);
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    // every lane of a wave runs the same number of iterations (ballots need the whole wave)
-    const int64_t start = int64_t(blockIdx.x) * blockDim.x + (threadIdx.x & ~63);
-    for (int64_t i0 = start; i0 < n; i0 += stride) {
-        const int64_t i = i0 + lane;
-        const bool valid = i < n;
-        uint64_t k = 0;
-        if (valid) {
-            k = desc_key(in[i]);
-            keys[i] = k;
+    uint64_t d = 0;
+    for (int64_t i0 = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i0 < n; i0 += kRows * stride) {
+        uint64_t k[kRows];
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) {
+            const int64_t i = i0 + r * stride;
+            k[r] = i < n ? desc_key(in[i]) : k0;
         }
 #pragma unroll
-        for (int p = 0; p < 8; ++p) {
-            const uint32_t d = uint32_t(k >> (8 * p)) & 255u;
-            const uint32_t d0 = __builtin_amdgcn_readfirstlane(d);   // lane 0 is always valid
-            const uint64_t same = __builtin_amdgcn_ballot_w64(valid && d == d0);
-            if (valid && d != d0) atomicAdd(&h[p][d], 1u);
-            if (lane == 0) atomicAdd(&h[p][d0], uint32_t(__popcll(same)));
+        for (int r = 0; r < kRows; ++r) {
+            const int64_t i = i0 + r * stride;
+            if (i < n) keys[i] = k[r];
+            d |= k[r] ^ k0;
         }
     }
+    for (int o = 32; o >= 1; o >>= 1) d |= __shfl_xor(d, o, 64);
+    if ((threadIdx.x & 63) == 0) wdiff[threadIdx.x >> 6] = d;
     __syncthreads();
-    for (int i = threadIdx.x; i < 8 * 256; i += blockDim.x) {
-        const uint32_t v = (&h[0][0])[i];
-        if (v) atomicAdd(hist + i, v);
-    }
+    if (threadIdx.x == 0) diff[blockIdx.x] = wdiff[0] | wdiff[1] | wdiff[2] | wdiff[3];
 }
 
-// Pass p leaves the order unchanged when one digit value holds all n keys; then
-// its kernels do nothing and the keys stay in the same buffer.
-__global__ __launch_bounds__(256) void k_sort_plan(const uint32_t *__restrict__ hist, int64_t n, uint32_t *__restrict__ plan) {
-    __shared__ uint32_t triv[kPasses];
-    if (threadIdx.x < kPasses) triv[threadIdx.x] = 0;
-    __syncthreads();
-    for (int p = 0; p < kPasses; ++p)
-        if (int64_t(hist[p * 256 + threadIdx.x]) == n) triv[p] = 1;   // at most one digit per pass
-    __syncthreads();
+// The plan: which buffer holds the keys before each pass, and which passes are skipped.
+__global__ __launch_bounds__(64) void k_sort_plan(const uint64_t *__restrict__ diff, int n_slots,
+                                                  uint32_t *__restrict__ plan) {
+    uint64_t d = 0;
+    for (int i = threadIdx.x; i < n_slots; i += 64) d |= diff[i];
+    for (int o = 32; o >= 1; o >>= 1) d |= __shfl_xor(d, o, 64);
     if (threadIdx.x != 0) return;
     uint32_t sel = 0;
     plan[0] = 0;
     for (int p = 0; p < kPasses; ++p) {
-        plan[16 + p] = triv[p];
-        sel = triv[p] ? sel : 1u - sel;
+        const uint32_t triv = ((d >> (8 * p)) & 255u) == 0 ? 1u : 0u;
+        plan[16 + p] = triv;
+        sel = triv ? sel : 1u - sel;
         plan[p + 1] = sel;
     }
 }
@@ -262,10 +253,10 @@ hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStrea
     if (n <= 0) return hipSuccess;
     SortWs w = sort_ws(ws, n);
     const int64_t tiles = sort_tiles(n);
-    const unsigned eb = unsigned(std::min<int64_t>((n + 255) / 256, 256));
-    hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, s, w.hist, w.plan);
-    hipLaunchKernelGGL(k_sort_encode, dim3(eb), dim3(256), 0, s, in, n, w.a, w.hist);
-    hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(256), 0, s, w.hist, n, w.plan);
+    const unsigned eb = unsigned(std::min<int64_t>((n + 255) / 256, kEncodeBlocks));   // <= 1024 slots fit
+    uint64_t *diff = reinterpret_cast<uint64_t *>(w.hist);
+    hipLaunchKernelGGL(k_sort_encode, dim3(eb), dim3(256), 0, s, in, n, w.a, diff);
+    hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(64), 0, s, diff, int(eb), w.plan);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     bool skip[kPasses] = {};
@@ -319,8 +310,21 @@ __global__ __launch_bounds__(256) void k_risk_part(SortWs w, RiskKs ks) {
     const int64_t k = ks.k[r], chunk = ks.chunk[r];
     const int64_t lo = int64_t(blockIdx.x) * chunk;
     const int64_t hi = lo + chunk < k ? lo + chunk : k;
+    // each thread adds its keys lo + t, lo + t + 256, ... in that order; 8 are read
+    // before they are added.  Slots past hi add +0.0, which changes no sum here: the
+    // running sum starts at +0.0 and round-to-nearest addition never makes it -0.0.
+    constexpr int kAhead = 8;
     double s = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) s += key_value(keys[i]);
+    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kAhead * blockDim.x) {
+        double v[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            const int64_t i = i0 + int64_t(u) * blockDim.x;
+            v[u] = i < hi ? key_value(keys[i]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) s += v[u];
+    }
     s = block_sum(s, part);
     if (threadIdx.x == 0) w.part[r * kRiskMaxBlocks + blockIdx.x] = s;   // 0 past k
 }

@@ -61,12 +61,23 @@ __device__ __forceinline__ Tile load_tile(const Tile *tiles, uint32_t k) {
 
 // Stage tile T (whole workgroup; the caller brackets it with barriers): the bits of
 // its bins' blocks (zero outside the tile's own blocks), per-word counts of the
-// tile's flagged events before the word, the values.  nb = blocks held.
+// tile's flagged events before the word, the values.  nb = blocks held.  Each thread
+// issues its first values' loads (up to 8) before the filter words' and stores them
+// after, so the staging waits for one round trip (two for tiles of over 8192 values).
 __device__ __forceinline__ void stage_tile(const TiledArgs &a, const Tile &T, int32_t nb, uint32_t *tab) {
+    constexpr uint32_t kThreads = kTiledWaves * 64, kUnroll = 8;
+    double *v = reinterpret_cast<double *>(reinterpret_cast<char *>(tab) + tile_vals_offset(nb));
+    const double *src = a.vals + T.rank_lo;
+    double t[kUnroll];
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const uint32_t i = threadIdx.x + u * kThreads;
+        t[u] = i < T.n_vals ? src[i] : 0.0;
+    }
     const int32_t b0 = T.bin_lo * kBlocksPerBin;
     u32x4 *l4 = reinterpret_cast<u32x4 *>(tab);
     uint16_t *r16 = reinterpret_cast<uint16_t *>(reinterpret_cast<char *>(tab) + tile_rank_offset(nb));
-    for (int i = threadIdx.x; i < nb; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nb; i += kThreads) {
         const int32_t blk = b0 + i;
         u32x4 W = {0u, 0u, 0u, 0u};
         uint32_t r0 = 0;
@@ -81,8 +92,23 @@ __device__ __forceinline__ void stage_tile(const TiledArgs &a, const Tile &T, in
         r16[4 * i + 2] = uint16_t(r2);
         r16[4 * i + 3] = uint16_t(r3);
     }
-    double *v = reinterpret_cast<double *>(reinterpret_cast<char *>(tab) + tile_vals_offset(nb));
-    for (uint32_t i = threadIdx.x; i < T.n_vals; i += blockDim.x) v[i] = a.vals[T.rank_lo + i];
+#pragma unroll
+    for (uint32_t u = 0; u < kUnroll; ++u) {
+        const uint32_t i = threadIdx.x + u * kThreads;
+        if (i < T.n_vals) v[i] = t[u];
+    }
+    for (uint32_t i0 = threadIdx.x + kUnroll * kThreads; i0 < T.n_vals; i0 += kUnroll * kThreads) {
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            const uint32_t i = i0 + u * kThreads;
+            t[u] = i < T.n_vals ? src[i] : 0.0;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kUnroll; ++u) {
+            const uint32_t i = i0 + u * kThreads;
+            if (i < T.n_vals) v[i] = t[u];
+        }
+    }
 }
 
 // One wave's cursor over the windows of a tile: bin b, next position ws, and jl =
@@ -298,7 +324,7 @@ __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
     const int64_t wg0 = a.t_begin + int64_t(blockIdx.x) * a.per_wg;
     const int64_t wg1 = min(wg0 + a.per_wg, a.t_end);
     for (int64_t pass = wg0; pass < wg1; pass += kPassTrials) {
-        // the pass's trials split evenly over the waves (at most 128 each)
+        // the pass's trials split evenly over the waves (at most 252 each)
         const int64_t span = min(int64_t(kPassTrials), wg1 - pass);
         const int64_t per_wave = (span + kTiledWaves - 1) / kTiledWaves;
         const int64_t T0 = min(pass + int64_t(wave) * per_wave, pass + span);
@@ -308,16 +334,18 @@ __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
         for (uint32_t k = 0; k < nt; ++k) {
             const Tile T = load_tile(a.tiles, k);
             const int32_t nb = tile_span_blocks(T.blk_lo, T.blk_hi, a.nblk);
-            __syncthreads();
-            stage_tile(a, T, nb, tab);
-            __syncthreads();
-            if (T0 >= T1) continue;
+            // the first window's loads read no LDS: they are issued before the tile is
+            // staged, so their latency overlaps the staging's
             TCur c;
-            c.b = T.bin_lo;
+            c.b = T0 < T1 ? T.bin_lo : T.bin_hi;
+            c.ws = c.e = c.jl = 0;
             tcur_seek(a, T, T0, T1, c);
             c = tcur_uniform(c);
             TWin A;
             twin_load(a, T, c, T0, T1, lane, A);
+            __syncthreads();
+            stage_tile(a, T, nb, tab);
+            __syncthreads();
             while (c.b < T.bin_hi) {
                 TWin B;
                 tiled_step(a, T, T0, T1, nb, tab, q, sums, lane, c, A, B);
