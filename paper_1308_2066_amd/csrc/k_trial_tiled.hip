@@ -17,11 +17,12 @@
 // span, read in windows of up to 2048 (16 coalesced rows of 64 lanes x 2 IDs):
 //   filter  each ID's LDS bit; flagged occurrences are appended to the wave's LDS
 //           queue with their position in the window;
-//   drain   64 entries at a time: the value from LDS, the trial by binary search
-//           over the window's trial boundaries (held one per lane), and an LDS
-//           add into that trial's sum (one binary64 per trial of the wave).
+//   drain   up to three rows of 64 entries at a time: the value from LDS, the
+//           trial by search over the window's trial boundaries (held one per
+//           lane), and an LDS add into that trial's sum (one binary64 per trial of
+//           the wave).
 // A trial's P is therefore added in a fixed order (tiles, bins, windows, queue
-// rows, and lanes within a row as the LDS unit orders an instruction's conflicting
+// entries, and lanes within an instruction as the LDS unit orders its conflicting
 // adds): the same bits on every run on a given device.
 #include "trial_common.h"
 
@@ -168,8 +169,11 @@ __device__ __forceinline__ void twin_load(const TiledArgs &a, const Tile &T, con
 }
 
 // Resolve N rows of queue entries from r0 on (entries below qn) of the current
-// window: value, trial, add to the trial's sum.  Two rows at a time interleave their
-// dependent LDS round trips; the adds keep row order.
+// window: value, trial, add to the trial's sum.  The rows interleave their dependent
+// LDS round trips.  Lane l takes entries r0 + N l + n (n < N), so the 64 adds of one
+// instruction fall N entries apart, mostly in different trials (adds to one address
+// in one instruction are serialised); the order of a trial's adds is fixed by the
+// queue.
 template <int N>
 __device__ __forceinline__ void drain_rows(const uint32_t *tab, const uint16_t *r16, const double *vals,
                                            const uint32_t *q, uint32_t r0, uint32_t qn, double *sums_jl, uint32_t ws2,
@@ -179,7 +183,7 @@ __device__ __forceinline__ void drain_rows(const uint32_t *tab, const uint16_t *
     bool act[N];
 #pragma unroll
     for (int n = 0; n < N; ++n) {
-        const uint32_t at = r0 + uint32_t(64 * n + lane);
+        const uint32_t at = r0 + uint32_t(lane) * N + uint32_t(n);
         const bool in_q = at < qn;
         const uint32_t ent = in_q ? q[at] : 0u;
         p[n] = ws2 + (ent >> kBinShift);
@@ -193,10 +197,20 @@ __device__ __forceinline__ void drain_rows(const uint32_t *tab, const uint16_t *
         v[n] = vals[rk];
         i4[n] = 0;
     }
-    // largest i with boundary(jl + i) <= p: the trial of position p (all lanes take
-    // part: each reads other lanes' boundaries); i4 = 4 i, the lane's byte address
+    // largest i with boundary(jl + i) <= p: the trial of position p.  The
+    // boundaries of lanes 8, 16, .., 56 are compared as scalars, then three steps
+    // read other lanes' boundaries (all lanes take part); i4 = 4 i, the lane's
+    // byte address
+    uint32_t s8[7];
 #pragma unroll
-    for (uint32_t step4 = 128; step4 >= 4; step4 >>= 1) {
+    for (int j = 0; j < 7; ++j) s8[j] = uint32_t(__builtin_amdgcn_readlane(int(bnd), 8 * (j + 1)));
+#pragma unroll
+    for (int n = 0; n < N; ++n) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) i4[n] += p[n] >= s8[j] ? 32u : 0u;
+    }
+#pragma unroll
+    for (uint32_t step4 = 16; step4 >= 4; step4 >>= 1) {
 #pragma unroll
         for (int n = 0; n < N; ++n) {
             const uint32_t cand4 = i4[n] | step4;
