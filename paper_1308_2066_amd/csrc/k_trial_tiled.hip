@@ -7,7 +7,7 @@
 // which telescopes from the basic algorithm's per-occurrence ceded losses.  P is a
 // sum, so its terms may be taken in any grouping; here they are grouped by catalog
 // tile.  The layer's filter (one bit per event, per-block counts) and its nonzero
-// values are cut into tiles that fit in LDS together (k_layer_tiles).  A persistent
+// values are cut into tiles that fit in LDS together (plan_tiles).  A persistent
 // workgroup owns a range of trials; for each tile it stages the tile in LDS, then
 // its waves stream the occurrences of the tile's bins from the binned YET copy
 // (k_bin.hip), so that every lookup is an LDS access and the only HBM traffic is
