@@ -98,6 +98,7 @@ __global__ __launch_bounds__(1024) void k_layer_rank(const uint32_t *__restrict_
     __shared__ uint32_t wsum[16];
     __shared__ uint32_t sbase[kChunk / kBlocksPerSuper];
     __shared__ uint32_t at_bin[kMaxBins + 1];   // counts at bin starts, for the planner
+    __shared__ uint32_t rk[kChunk];             // the chunk's ranks, for coalesced stores
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     uint32_t carry = 0;
     for (int32_t base = 0; base < nblk; base += kChunk) {
@@ -131,15 +132,17 @@ __global__ __launch_bounds__(1024) void k_layer_rank(const uint32_t *__restrict_
             base32[sb] = r;
             if (sb < kMaxBins) at_bin[sb] = r;
         }
-        __syncthreads();
-        const uint32_t sr = sbase[(b0 - base) / kBlocksPerSuper];
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
-            if (b0 + j < nblk) {
-                rank[b0 + j] = r;
-                rel16[b0 + j] = uint16_t(r - sr);
-            }
+            rk[tid * kPer + j] = r;
             r += c[j];
+        }
+        __syncthreads();
+        // written out from LDS by consecutive threads (one CU's stores coalesce)
+        for (int k = tid; k < kChunk && base + k < nblk; k += 1024) {
+            const uint32_t v = rk[k];
+            rank[base + k] = v;
+            rel16[base + k] = uint16_t(v - sbase[k / kBlocksPerSuper]);
         }
         carry += total;
         __syncthreads();

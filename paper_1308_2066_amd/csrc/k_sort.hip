@@ -50,7 +50,7 @@ struct SortWs {
 
 constexpr int kRiskGroup = 16;        // return periods per launch
 constexpr int kRiskMaxBlocks = 1024;  // partial sums per return period
-constexpr int kRiskChunk = 8192;      // keys per partial sum, at least
+constexpr int kRiskChunk = 2048;      // keys per partial sum, at least (8 per thread)
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__rest
                                                      int n_k, double *__restrict__ out) {
     __shared__ uint64_t key[kRiskLdsKeys];
     __shared__ double part[256];
-    __shared__ double chunk_sum[2];
+    __shared__ double chunk_sum[kRiskLdsKeys / kRiskChunk];
     const int j = blockIdx.x;
     if (ns[j] < 1 || ns[j] > kRiskLdsKeys) return;   // longer YLTs take the radix sort
     const int n = int(ns[j]);
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__rest
         const int64_t k = ks[int64_t(j) * n_k + r];
         int64_t chunk = (k + kRiskMaxBlocks - 1) / kRiskMaxBlocks;
         chunk = chunk < kRiskChunk ? kRiskChunk : chunk;
-        const int nb = int((k + chunk - 1) / chunk);   // <= 2 here
+        const int nb = int((k + chunk - 1) / chunk);   // <= kRiskLdsKeys / kRiskChunk here
         for (int b = 0; b < nb; ++b) {
             const int64_t lo = b * chunk, hi = lo + chunk < k ? lo + chunk : k;
             double s = 0.0;
