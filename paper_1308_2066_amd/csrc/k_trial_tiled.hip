@@ -14,7 +14,7 @@
 // the stream of 2-byte IDs.
 //
 // Per wave and bin, the occurrences of the wave's trials (up to 252) are one contiguous
-// span, read in windows of up to 2048 (16 coalesced rows of 64 lanes x 2 IDs):
+// span, read in windows of up to 1024 (8 coalesced rows of 64 lanes x 2 IDs):
 //   filter  each ID's LDS bit; flagged occurrences are appended to the wave's LDS
 //           queue with their position in the window;
 //   drain   up to three rows of 64 entries at a time: the value from LDS, the
@@ -30,13 +30,14 @@ namespace ara {
 
 constexpr int kTileWords = kTiledLdsBytes / 4;
 // trials per wave and pass: a window spans at most 63 trials (one boundary per lane),
-// so 252 trials make exactly four windows per bin when a bin's span fits four.  A
+// so 252 trials need at least four windows per bin (more where a window fills its
+// 1024 positions first: about eight at 32 occurrences per trial and bin).  A
 // pass of 16 waves then covers 4032 trials: one pass per workgroup for a million
 // trials on 256 CUs (each pass stages every tile once)
 constexpr int kWaveTrials = 252;
 static_assert(kWaveTrials <= kTiledWaveTrials, "per-trial sums");
 constexpr int kPassTrials = kWaveTrials * kTiledWaves;   // trials per workgroup pass
-constexpr int kWinRows = 16;
+constexpr int kWinRows = 8;   // 8 rows ran 1% faster than 16 (and 12 rows 3% slower)
 constexpr int kWindow = kWinRows * 128;            // occurrences per window
 
 // Wave-uniform reads of tables the kernel never writes, through the scalar data
@@ -258,7 +259,7 @@ __device__ __forceinline__ void queue_slot(uint32_t *q, uint64_t m, uint32_t &qn
     qn += uint32_t(__popcll(m));
 }
 
-// Filter and drain one window [ws, we) of bin c.b (IDs in w), eight rows at a time:
+// Filter and drain one window [ws, we) of bin c.b (IDs in w), half a window at a time:
 // first every row's LDS filter words are read (the reads overlap), then each ID
 // slot is compacted into the queue by its flag mask.  Positions outside the window
 // (at its edge rows) are queued too and dropped when the queue is resolved; IDs
@@ -307,7 +308,7 @@ __device__ __forceinline__ void tiled_window(const Tile &T, int32_t nb, const ui
 __device__ __forceinline__ void tiled_step(const TiledArgs &a, const Tile &T, int64_t T0, int64_t T1, int32_t nb,
                                            const uint32_t *tab, uint32_t *q, double *sums, int lane, TCur &c,
                                            const TWin &cur, TWin &nxt) {
-    // this window ends at the span end, after 2048 positions, or where trial jl + 63
+    // this window ends at the span end, after kWindow positions, or where trial jl + 63
     // starts (so its trials are jl .. jl + 62: one per boundary lane)
     const uint32_t b63 = uint32_t(__builtin_amdgcn_readlane(int(cur.bnd), 63));
     const uint32_t we = min(min((c.ws & ~1u) + uint32_t(kWindow), c.e), max(b63, c.ws));
