@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 INF = math.inf
 TILES = 4          # ARA_PLACE_LDS_TILES
 BITMAP = 1         # ARA_PLACE_LDS_BITMAP
+GLOBAL_DENSE = 3   # ARA_PLACE_GLOBAL_DENSE
 
 
 def _say(msg):
@@ -226,5 +227,29 @@ def test_several_passes_per_workgroup(A, S, gpu_ctx):
         assert sub.tobytes() == _run(A, gpu_ctx, an, 0, 123_457, 1_199_999).tobytes()
         bad = np.nonzero(~(np.abs(sub - ref["ylt"][123_457:1_199_999]) <= tol[123_457:1_199_999]))[0]
         assert bad.size == 0
+    finally:
+        an.release()
+
+
+def test_large_catalog_many_bins_and_rank_chunks(A, S, gpu_ctx):
+    """A 3,000,003-event catalog: 92 bins (tiles over many bins, a last bin cut short)
+    and 23,438 filter blocks, which the rank kernel takes in three chunks of 8192; the
+    flagged count equals the one computed here from the ELTs, and the YLT matches the
+    oracle and the global dense-table kernel."""
+    w = synth.workload_paper_scale(n_trials=20_000, catalog=3_000_003, n_elts=8, nnz=200_000)
+    w = w.with_terms((1e5, 5e6, 1.5e8, INF))
+    _say("tiled large catalog 3M, 20k x 1000")
+    an = _open(A, S, gpu_ctx, w)
+    try:
+        assert A.ara_yet_info(an.yet)[2] == 2, "binned copy expected"
+        got = _run(A, gpu_ctx, an, 0)
+        assert _run(A, gpu_ctx, an, TILES).tobytes() == got.tobytes(), "auto placement must pick the tiled kernel"
+        ref = oracle.analyze_workload(w, threads=oracle.max_threads())
+        _close(got, ref, "large catalog")
+        _close(_run(A, gpu_ctx, an, GLOBAL_DENSE), ref, "large catalog (global dense table)")
+        comb = np.zeros(w.catalog_size)
+        for ids, loss in w.elts:   # layer order, binary64, from +0.0: the combined table
+            comb[ids] += loss
+        assert A.ara_layer_stats(gpu_ctx, an.layer)[0] == int(np.count_nonzero(comb > w.layer_terms[0]))
     finally:
         an.release()
