@@ -289,8 +289,23 @@ def bench_portfolio(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / args.steps, r
 
+    pout = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def step_portfolio():
+        # every layer's YLT, the portfolio YLT (their per-trial sum, in job order) and
+        # its PML/TVaR
+        ara.ara_batch_run(b)
+        ara.ara_batch_portfolio(b, pout)
+        return ara.ara_risk_measures(ctx, pout, rps, ws)
+
     ms_b, (pml_b, tvar_b) = timed(step_batched)
+    ms_pf, (pml_pf, tvar_pf) = timed(step_portfolio)
     ms_p, res_p = timed(step_plain)
+    # the portfolio YLT is the job-order sum of the layers' YLTs
+    acc = np.zeros(n)
+    for o in outs:
+        acc = acc + o.cpu().numpy()
+    pf_same = pout.cpu().numpy().tobytes() == acc.tobytes()
     same = all(outs[j].cpu().numpy().tobytes() == plain[j].cpu().numpy().tobytes() for j in range(L))
     same = same and all(pml_b[j].tobytes() == np.asarray(res_p[j][0]).tobytes() and
                         tvar_b[j].tobytes() == np.asarray(res_p[j][1]).tobytes() for j in range(L))
@@ -312,8 +327,80 @@ def bench_portfolio(args):
                                f"log-uniform terms", "layers": L, "parallelism": "1 GPU"},
         "plain_per_layer": {"ms_per_step": ms_p, "value": te / (ms_p * 1e-3)},
         "speedup_vs_plain": ms_p / ms_b, "identical_results": bool(same),
+        "portfolio_ylt": {"ms_per_step": ms_pf, "value": te / (ms_pf * 1e-3),
+                          "pml": [float(x) for x in pml_pf], "tvar": [float(x) for x in tvar_pf],
+                          "equals_job_order_sum": bool(pf_same)},
         "schedule": {"items": n_items, "workgroups": grid, "events_per_item": epi, "graph": bool(graph & 1),
                      "interleaved": bool(graph & 2)},
+    }
+    print(json.dumps(out), flush=True)
+
+
+def bench_events(args):
+    """Per-occurrence outputs and occurrence maxima (the per-event outputs, OEP input
+    and non-identity financial terms): the paper-scale shape at 10^5 trials (10^8
+    occurrences, 1M-event catalog, 16 ELTs with fx/retention/limit terms).  A step of
+    ara_analyze_events writes the gross, occurrence-net, cumulative and ceded loss of
+    every occurrence and the YLT; ara_analyze_occ_max writes each trial's largest
+    occurrence-net loss.  Each is timed with HIP events on the context's stream."""
+    import torch
+    import synth
+    from paper_1308_2066_amd import ara, session
+
+    w = synth.workload_paper_scale(n_trials=args.trials if args.trials != 1_000_000 else 100_000)
+    elt_terms = [(1.0 + 0.01 * j, 1e3 * j, 2e7 + 1e6 * j) for j in range(len(w.elts))]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    ctx = ara.ara_ctx_create(0, stream)
+    an = session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms, elt_terms,
+                               ara.ARA_F64)
+    n, e = w.n_trials, w.n_events
+    ylt = torch.empty(n, dtype=torch.float64, device="cuda")
+    ev = [torch.empty(e, dtype=torch.float64, device="cuda") for _ in range(4)]
+    occ_max = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        e1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            e0[i].record(stream)
+            fn()
+            e1[i].record(stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / args.steps
+        return wall, float(np.mean([e0[i].elapsed_time(e1[i]) for i in range(args.steps)]))
+
+    ms_ev, k_ev = timed(lambda: ara.ara_analyze_events(ctx, an.yet, an.layer, 0, n, ylt, *ev))
+    ms_om, k_om = timed(lambda: ara.ara_analyze_occ_max(ctx, an.yet, an.layer, 0, n, occ_max))
+    # the per-occurrence ceded losses of a trial add up to its year loss (telescoping;
+    # reported as the largest relative difference, a sanity check beside the tests)
+    offs = np.asarray(w.trial_offsets)
+    has = offs[1:] > offs[:-1]
+    ceded = ev[3].cpu().numpy()
+    y = ylt.cpu().numpy()
+    sums = np.add.reduceat(ceded, offs[:-1][has])
+    ceded_rel = float(np.max(np.abs(sums - y[has]) / np.maximum(np.abs(y[has]), 1.0))) if has.any() else 0.0
+    an.release()
+    ara.ara_ctx_destroy(ctx)
+    ev_bytes = 4 * e + 8 * (n + 1) + 32 * e + 8 * n          # IDs, offsets, 4 outputs, YLT
+    log(f"events: step {ms_ev:.3f} ms (kernel {k_ev:.3f} ms); occ_max {ms_om:.3f} ms (kernel {k_om:.3f} ms)")
+    out = {
+        "metric": "trial-events/s (per-occurrence outputs: gross, occurrence-net, cumulative, ceded; 10^5 trials "
+                  "x 1000 events, 16-ELT layer with financial terms)",
+        "value": e / (ms_ev * 1e-3), "unit": "trial-events/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_ev, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{w.name} with ELT terms (fx 1.00-1.15, retention 0-15e3, limit 2e7-3.5e7)",
+                   "trials": n, "events": e, "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": ev_bytes / (k_ev * 1e-3) / 1e9, "peak": 8000.0, "unit": "GB/s",
+                     "frac": ev_bytes / (k_ev * 1e-3) / 1e9 / 8000.0, "traffic": None, "kernel": "k_trial_events",
+                     "kernel_ms": k_ev, "algorithmic_bytes": ev_bytes},
+        "ceded_sum_vs_ylt_max_rel_diff": ceded_rel,
+        "occ_max": {"ms_per_step": ms_om, "kernel_ms": k_om, "value": e / (ms_om * 1e-3), "unit": "trial-events/s"},
     }
     print(json.dumps(out), flush=True)
 
@@ -478,6 +565,9 @@ def bench_uneven(args):
                      "frac": alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": alg, "moved_bytes": moved},
         "plain_per_analysis": {"ms_per_step": ms_p, "value": ev / (ms_p * 1e-3)},
         "speedup_vs_plain": ms_p / ms_b, "identical_results": bool(same),
+        "portfolio_ylt": {"ms_per_step": ms_pf, "value": te / (ms_pf * 1e-3),
+                          "pml": [float(x) for x in pml_pf], "tvar": [float(x) for x in tvar_pf],
+                          "equals_job_order_sum": bool(pf_same)},
         "schedule": {"items": n_items, "workgroups": grid, "events_per_item": epi, "graph": bool(graph & 1),
                      "interleaved": bool(graph & 2)},
     }
@@ -489,7 +579,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["paper", "small", "portfolio", "serving", "uneven"], default="paper",
+    ap.add_argument("--workload", choices=["paper", "small", "portfolio", "serving", "uneven", "events"], default="paper",
                     help="portfolio: one YET x 64 layers, batched launch against per-layer launches; "
                          "serving: pricing requests with Poisson arrivals, server against per-request launches")
     ap.add_argument("--requests", type=int, default=600, help="serving: requests per rate")
@@ -534,6 +624,8 @@ def main():
 
     if args.workload == "portfolio":
         return bench_portfolio(args)
+    if args.workload == "events":
+        return bench_events(args)
     if args.workload == "serving":
         return bench_serving(args)
     if args.workload == "uneven":

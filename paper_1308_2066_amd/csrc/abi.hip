@@ -871,7 +871,7 @@ extern "C" ara_status ara_analyze_occ_max(ara_ctx *c, const ara_yet *y, const ar
     if (t1 == t0) return ARA_OK;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     TrialLaunch tl{};
-    s = plan_trial(c, L, t1 - t0, 1e9, tl);
+    s = plan_trial(c, L, t1 - t0, 1e9, tl, y->ids16 ? 1 : 0);
     if (s != ARA_OK) return s;
     const int by_lds = tl.lds_bytes > 0 ? std::max(1, int(c->lds_max / int64_t(tl.lds_bytes))) : 8;
     const int64_t grid = std::min<int64_t>(int64_t(c->n_cu) * std::min(8, by_lds), (t1 - t0 + 255) / 256);
@@ -880,8 +880,19 @@ extern "C" ara_status ara_analyze_occ_max(ara_ctx *c, const ara_yet *y, const ar
         s = dev_alloc(c, &dst, size_t(t1 - t0) * 8, "occurrence maxima staging");
         if (s != ARA_OK) return s;
     }
-    const TrialArgs a = trial_args(y, L, t0, t1, nullptr);
-    hipError_t e = launch_trial_occ_max(a, tl, int(std::max<int64_t>(1, grid)), dst, c->stream);
+    hipError_t e = hipSuccess;
+    if (tl.placement == ARA_PLACE_LDS_TILES) {
+        // the tiled kernel with a maximum in place of the sum (trial indices inside a
+        // launch are 32-bit: very long ranges are split)
+        constexpr int64_t kMaxTrialsPerLaunch = int64_t(1) << 30;
+        for (int64_t tb = t0; tb < t1 && e == hipSuccess; tb += kMaxTrialsPerLaunch) {
+            const int64_t te = std::min(t1, tb + kMaxTrialsPerLaunch);
+            e = launch_trial_tiled(tiled_args(y, L, tb, te, dst + (tb - t0), tl.grid), tl.grid, c->stream, true);
+        }
+    } else {
+        const TrialArgs a = trial_args(y, L, t0, t1, nullptr);
+        e = launch_trial_occ_max(a, tl, int(std::max<int64_t>(1, grid)), dst, c->stream);
+    }
     if (e != hipSuccess) s = hip_fail(c, e, "occurrence maxima");
     if (s == ARA_OK && mem == ARA_MEM_HOST) {
         e = hipMemcpyAsync(out, dst, size_t(t1 - t0) * 8, hipMemcpyDeviceToHost, c->stream);

@@ -227,7 +227,8 @@ struct TiledArgs {
     double agg_r, agg_l;
     double *ylt;
 };
-hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s);
+// occ_max: each trial's largest occurrence-net loss into a.ylt instead of the YLT
+hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s, bool occ_max = false);
 
 // ---- order statistics
 size_t sort_workspace_bytes(int64_t n);

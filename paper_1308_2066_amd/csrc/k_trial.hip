@@ -104,6 +104,15 @@ __global__ __launch_bounds__(1024) void k_trial_occ_max(TrialArgs a, double *__r
     if (bad) atomicOr(a.err, bad);
 }
 
+// Four consecutive binary64 outputs from element pos on (8-byte aligned), if out is set.
+typedef double f64x2_u __attribute__((ext_vector_type(2), aligned(8)));
+__device__ __forceinline__ void store4(double *out, int64_t pos, const double *v) {
+    if (!out) return;
+    f64x2_u *p = reinterpret_cast<f64x2_u *>(out + pos);
+    p[0] = f64x2_u{v[0], v[1]};
+    p[1] = f64x2_u{v[2], v[3]};
+}
+
 // ---------------------------------------------------------------------------------
 // Per-occurrence form: every quantity of the basic algorithm, with the cumulative
 // sum as a wave-wide inclusive scan (lane-local over 4 consecutive events, then a
@@ -162,16 +171,27 @@ __global__ __launch_bounds__(256) void k_trial_events(TrialArgs a) {
                 }
                 double Fprev = __shfl_up(F[3], 1, 64);
                 if (lane == 0) Fprev = carryF;
+                double ced[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const double ced = F[j] - (j == 0 ? Fprev : F[j - 1]);
-                    if (ok[j]) {
-                        lr += ced;
-                        const int64_t pos = c.sbase + k * kChunk + lane * 4 + j - ev0;
-                        if (a.ev_gross) a.ev_gross[pos] = x[j];
-                        if (a.ev_occ) a.ev_occ[pos] = o[j];
-                        if (a.ev_cum) a.ev_cum[pos] = P[j];
-                        if (a.ev_ceded) a.ev_ceded[pos] = ced;
+                    ced[j] = F[j] - (j == 0 ? Fprev : F[j - 1]);
+                    if (ok[j]) lr += ced[j];
+                }
+                const int64_t pos0 = c.sbase + k * kChunk + lane * 4 - ev0;
+                if (ok[0] && ok[1] && ok[2] && ok[3]) {
+                    // a lane's four consecutive outputs as two 16-byte stores per array
+                    store4(a.ev_gross, pos0, x);
+                    store4(a.ev_occ, pos0, o);
+                    store4(a.ev_cum, pos0, P);
+                    store4(a.ev_ceded, pos0, ced);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        if (!ok[j]) continue;
+                        if (a.ev_gross) a.ev_gross[pos0 + j] = x[j];
+                        if (a.ev_occ) a.ev_occ[pos0 + j] = o[j];
+                        if (a.ev_cum) a.ev_cum[pos0 + j] = P[j];
+                        if (a.ev_ceded) a.ev_ceded[pos0 + j] = ced[j];
                     }
                 }
                 carryP = __shfl(P[3], 63, 64);

@@ -175,7 +175,7 @@ __device__ __forceinline__ void twin_load(const TiledArgs &a, const Tile &T, con
 // instruction fall N entries apart, mostly in different trials (adds to one address
 // in one instruction are serialised); the order of a trial's adds is fixed by the
 // queue.
-template <int N>
+template <bool MAX, int N>
 __device__ __forceinline__ void drain_rows(const uint32_t *tab, const uint16_t *r16, const double *vals,
                                            const uint32_t *q, uint32_t r0, uint32_t qn, double *sums_jl, uint32_t ws2,
                                            uint32_t ws, uint32_t we, uint32_t id_off, uint32_t bnd, int lane) {
@@ -223,21 +223,26 @@ __device__ __forceinline__ void drain_rows(const uint32_t *tab, const uint16_t *
     for (int n = 0; n < N; ++n) {
         if (act[n]) {
             double *dst = reinterpret_cast<double *>(reinterpret_cast<char *>(sums_jl) + 2u * i4[n]);
-            __hip_atomic_fetch_add(dst, v[n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            if (MAX)   // occurrence-net losses are >= +0.0: their bits order as their values
+                __hip_atomic_fetch_max(reinterpret_cast<uint64_t *>(dst), __builtin_bit_cast(uint64_t, v[n]),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            else
+                __hip_atomic_fetch_add(dst, v[n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         }
     }
 }
 
 // Resolve queue entries [0, qn) of the current window.
+template <bool MAX>
 __device__ __forceinline__ void tiled_drain(const uint32_t *tab, int32_t nb, const uint32_t *q, uint32_t qn,
                                             double *sums, uint32_t ws2, uint32_t ws, uint32_t we, uint32_t id_off,
                                             uint32_t bnd, uint32_t jl, int lane) {
     const uint16_t *r16 = reinterpret_cast<const uint16_t *>(reinterpret_cast<const char *>(tab) + tile_rank_offset(nb));
     const double *vals = reinterpret_cast<const double *>(reinterpret_cast<const char *>(tab) + tile_vals_offset(nb));
     uint32_t r0 = 0;
-    for (; r0 + 128 < qn; r0 += 192) drain_rows<3>(tab, r16, vals, q, r0, qn, sums + jl, ws2, ws, we, id_off, bnd, lane);
-    for (; r0 + 64 < qn; r0 += 128) drain_rows<2>(tab, r16, vals, q, r0, qn, sums + jl, ws2, ws, we, id_off, bnd, lane);
-    if (r0 < qn) drain_rows<1>(tab, r16, vals, q, r0, qn, sums + jl, ws2, ws, we, id_off, bnd, lane);
+    for (; r0 + 128 < qn; r0 += 192) drain_rows<MAX, 3>(tab, r16, vals, q, r0, qn, sums + jl, ws2, ws, we, id_off, bnd, lane);
+    for (; r0 + 64 < qn; r0 += 128) drain_rows<MAX, 2>(tab, r16, vals, q, r0, qn, sums + jl, ws2, ws, we, id_off, bnd, lane);
+    if (r0 < qn) drain_rows<MAX, 1>(tab, r16, vals, q, r0, qn, sums + jl, ws2, ws, we, id_off, bnd, lane);
 }
 
 constexpr int kHalfRows = kWinRows / 2;
@@ -264,6 +269,7 @@ __device__ __forceinline__ void queue_slot(uint32_t *q, uint64_t m, uint32_t &qn
 // slot is compacted into the queue by its flag mask.  Positions outside the window
 // (at its edge rows) are queued too and dropped when the queue is resolved; IDs
 // outside the tile's own blocks meet zero bits.
+template <bool MAX>
 __device__ __forceinline__ void tiled_window(const Tile &T, int32_t nb, const uint32_t *tab, uint32_t *q,
                                              double *sums, const TCur &c, uint32_t we, const TWin &w, int lane) {
     const uint32_t id_off = uint32_t(c.b - T.bin_lo) << kBinShift;   // first tile event of the bin
@@ -288,7 +294,7 @@ __device__ __forceinline__ void tiled_window(const Tile &T, int32_t nb, const ui
             const uint32_t base = ws2 + uint32_t(128 * r);
             if (base >= we) break;   // rows past the window's end hold no occurrence of it
             if (qn > uint32_t(kTiledQueue - 128)) {
-                tiled_drain(tab, nb, q, qn, sums, ws2, c.ws, we, id_off, w.bnd, c.jl, lane);
+                tiled_drain<MAX>(tab, nb, q, qn, sums, ws2, c.ws, we, id_off, w.bnd, c.jl, lane);
                 qn = 0;
             }
             const uint32_t v = w.v[r];
@@ -300,11 +306,12 @@ __device__ __forceinline__ void tiled_window(const Tile &T, int32_t nb, const ui
             queue_slot(q, m1, qn, (rel + (1u << kBinShift)) | (v >> 16), spare);
         }
     }
-    tiled_drain(tab, nb, q, qn, sums, ws2, c.ws, we, id_off, w.bnd, c.jl, lane);
+    tiled_drain<MAX>(tab, nb, q, qn, sums, ws2, c.ws, we, id_off, w.bnd, c.jl, lane);
 }
 
 // One window of cursor c (its IDs in cur): find where it ends, advance c to the next
 // window and issue that window's loads into nxt, then filter and drain this one.
+template <bool MAX>
 __device__ __forceinline__ void tiled_step(const TiledArgs &a, const Tile &T, int64_t T0, int64_t T1, int32_t nb,
                                            const uint32_t *tab, uint32_t *q, double *sums, int lane, TCur &c,
                                            const TWin &cur, TWin &nxt) {
@@ -323,10 +330,13 @@ __device__ __forceinline__ void tiled_step(const TiledArgs &a, const Tile &T, in
     }
     n = tcur_uniform(n);
     twin_load(a, T, n, T0, T1, lane, nxt);
-    tiled_window(T, nb, tab, q, sums, c, we, cur, lane);
+    tiled_window<MAX>(T, nb, tab, q, sums, c, we, cur, lane);
     c = n;
 }
 
+// MAX = false: the YLT (sums of the occurrence-net losses, then the aggregate terms);
+// MAX = true: each trial's largest occurrence-net loss (0 for none).
+template <bool MAX>
 __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t tab[kTileWords];
     __shared__ uint32_t queues[kTiledWaves * kQueueStride];
@@ -363,7 +373,7 @@ __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
             __syncthreads();
             while (c.b < T.bin_hi) {
                 TWin B;
-                tiled_step(a, T, T0, T1, nb, tab, q, sums, lane, c, A, B);
+                tiled_step<MAX>(a, T, T0, T1, nb, tab, q, sums, lane, c, A, B);
                 A = B;
             }
         }
@@ -371,14 +381,15 @@ __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
 #pragma unroll
         for (int k = 0; k < kTiledWaveTrials / 64; ++k) {
             const int64_t t = T0 + lane + 64 * k;
-            if (t < T1) a.ylt[t - a.t_begin] = excess(sums[lane + 64 * k], a.agg_r, a.agg_l);
+            if (t < T1) a.ylt[t - a.t_begin] = MAX ? sums[lane + 64 * k] : excess(sums[lane + 64 * k], a.agg_r, a.agg_l);
         }
         __builtin_amdgcn_wave_barrier();
     }
 }
 
-hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(k_trial_tiled, dim3(grid), dim3(kTiledWaves * 64), 0, s, a);
+hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s, bool occ_max) {
+    if (occ_max) hipLaunchKernelGGL(k_trial_tiled<true>, dim3(grid), dim3(kTiledWaves * 64), 0, s, a);
+    else hipLaunchKernelGGL(k_trial_tiled<false>, dim3(grid), dim3(kTiledWaves * 64), 0, s, a);
     return hipGetLastError();
 }
 

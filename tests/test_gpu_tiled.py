@@ -86,6 +86,37 @@ def _workload(rng, lengths, catalog, n_elts=4, nnz=None, mu=10.0, sigma=2.0, ter
     return synth.Workload("tiled", ids, offs, catalog, elts, terms, None, (10.0,), 0)
 
 
+def _occ_max(A, ctx, an, placement, t0, t1):
+    import torch
+    A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, placement)
+    try:
+        out = torch.full((max(t1 - t0, 1),), math.nan, dtype=torch.float64, device="cuda")
+        if t1 > t0:
+            A.ara_analyze_occ_max(ctx, an.yet, an.layer, t0, t1, out)
+        A.ara_sync(ctx)
+        return out[: t1 - t0].cpu().numpy()
+    finally:
+        A.ara_set_option(ctx, A.ARA_OPT_PLACEMENT, 0)
+
+
+def _check_occ_max(A, ctx, an, ref, what, sub_ranges=(), f32=False):
+    """Occurrence maxima through the tiled kernel (a maximum of table values): with
+    binary64 tables the oracle's bits, whole and on sub-ranges.  With binary32 tables
+    the combined table is rounded to binary32 before the occurrence terms (the oracle
+    rounds each ELT's table only): the bits of the LDS-filter kernel, which reads the
+    same tables, and the oracle's values within that rounding."""
+    n = an_trials(A, an)
+    got = _occ_max(A, ctx, an, TILES, 0, n)
+    want = _occ_max(A, ctx, an, BITMAP, 0, n) if f32 else ref["occ_max"]
+    assert got.tobytes() == want.tobytes(), f"{what}: occurrence maxima differ"
+    if f32:
+        bound = 2.0 ** -23 * 1.0001 * ref["gross_total"]
+        assert np.all(np.abs(got - ref["occ_max"]) <= bound), what
+    assert _occ_max(A, ctx, an, 0, 0, n).tobytes() == got.tobytes(), "auto placement must pick the tiled kernel"
+    for t0, t1 in sub_ranges:
+        assert _occ_max(A, ctx, an, 0, t0, t1).tobytes() == want[t0:t1].tobytes(), (what, t0, t1)
+
+
 def _tiles_vs_oracle_and_bitmap(A, S, ctx, w, what, sub_ranges=()):
     an = _open(A, S, ctx, w)
     try:
@@ -100,6 +131,7 @@ def _tiles_vs_oracle_and_bitmap(A, S, ctx, w, what, sub_ranges=()):
         for t0, t1 in sub_ranges:
             sub = _run(A, ctx, an, 0, t0, t1)
             _close(sub, {k: v[t0:t1] for k, v in ref.items()}, f"{what} [{t0}, {t1})")
+        _check_occ_max(A, ctx, an, ref, what, sub_ranges)
         return got
     finally:
         an.release()
@@ -227,6 +259,7 @@ def test_several_passes_per_workgroup(A, S, gpu_ctx):
         assert sub.tobytes() == _run(A, gpu_ctx, an, 0, 123_457, 1_199_999).tobytes()
         bad = np.nonzero(~(np.abs(sub - ref["ylt"][123_457:1_199_999]) <= tol[123_457:1_199_999]))[0]
         assert bad.size == 0
+        _check_occ_max(A, gpu_ctx, an, ref, "several passes", [(123_457, 1_199_999)], f32=True)
     finally:
         an.release()
 
@@ -251,5 +284,6 @@ def test_large_catalog_many_bins_and_rank_chunks(A, S, gpu_ctx):
         for ids, loss in w.elts:   # layer order, binary64, from +0.0: the combined table
             comb[ids] += loss
         assert A.ara_layer_stats(gpu_ctx, an.layer)[0] == int(np.count_nonzero(comb > w.layer_terms[0]))
+        _check_occ_max(A, gpu_ctx, an, ref, "large catalog", [(5, 19_999)])
     finally:
         an.release()
