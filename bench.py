@@ -565,9 +565,6 @@ def bench_uneven(args):
                      "frac": alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": alg, "moved_bytes": moved},
         "plain_per_analysis": {"ms_per_step": ms_p, "value": ev / (ms_p * 1e-3)},
         "speedup_vs_plain": ms_p / ms_b, "identical_results": bool(same),
-        "portfolio_ylt": {"ms_per_step": ms_pf, "value": te / (ms_pf * 1e-3),
-                          "pml": [float(x) for x in pml_pf], "tvar": [float(x) for x in tvar_pf],
-                          "equals_job_order_sum": bool(pf_same)},
         "schedule": {"items": n_items, "workgroups": grid, "events_per_item": epi, "graph": bool(graph & 1),
                      "interleaved": bool(graph & 2)},
     }
