@@ -611,8 +611,8 @@ def main():
         return
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design note, not implemented)"}))
+        print(json.dumps({"error": "the analysis runs on one GPU only; --gpus must be 1 "
+                                   "(sharding across GPUs is described, not implemented)"}))
         sys.exit(2)
 
     import torch
