@@ -166,28 +166,52 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(SortWs w, int64_t n
     w.counts[int64_t(threadIdx.x) * tiles + blockIdx.x] = hist[threadIdx.x];
 }
 
-// Exclusive offsets of every (digit, tile): thread d sums row d, the 256 row
-// totals are scanned, and each row is rewritten as its running prefix.
-__global__ __launch_bounds__(256) void k_sort_offsets(SortWs w, int pass, int64_t tiles) {
+// Exclusive offsets of every (digit, tile): the counts are stored digit-major, so
+// the offset of (d, t) is the exclusive prefix sum of the flat array up to (d, t).
+// One workgroup scans it in chunks of 4096 (four consecutive counts per thread);
+// the next chunk's counts are read before the current one is scanned.
+__global__ __launch_bounds__(1024) void k_sort_offsets(SortWs w, int pass, int64_t tiles) {
     if (w.plan[16 + pass]) return;
-    __shared__ uint32_t tot[256];
-    const int d = threadIdx.x;
-    uint32_t *row = w.counts + int64_t(d) * tiles;
-    uint32_t s = 0;
-    for (int64_t t = 0; t < tiles; ++t) s += row[t];
-    tot[d] = s;
-    __syncthreads();
-    for (int o = 1; o < 256; o <<= 1) {
-        const uint32_t v = d >= o ? tot[d - o] : 0u;
+    __shared__ uint32_t wsum[16];
+    const int64_t n = int64_t(256) * tiles;
+    uint32_t *c = w.counts;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    auto load = [&](int64_t base, uint32_t *v) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = base + 4 * tid + j;
+            v[j] = i < n ? c[i] : 0u;
+        }
+    };
+    uint32_t cur[4], nxt[4];
+    load(0, cur);
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < n; base += 4096) {
+        load(base + 4096, nxt);
+        const uint32_t t = cur[0] + cur[1] + cur[2] + cur[3];
+        uint32_t inc = t;   // inclusive wave scan of the threads' sums
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wsum[wv] = inc;
         __syncthreads();
-        tot[d] += v;
+        uint32_t before = 0, total = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < wv) before += wsum[k];
+            total += wsum[k];
+        }
+        uint32_t run = carry + before + inc - t;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t i = base + 4 * tid + j;
+            if (i < n) c[i] = run;
+            run += cur[j];
+        }
+        carry += total;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
         __syncthreads();
-    }
-    uint32_t run = tot[d] - s;
-    for (int64_t t = 0; t < tiles; ++t) {
-        const uint32_t v = row[t];
-        row[t] = run;
-        run += v;
     }
 }
 
@@ -269,7 +293,7 @@ hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStrea
     for (int pass = 0; pass < kPasses; ++pass) {
         if (skip[pass]) continue;
         hipLaunchKernelGGL(k_sort_count, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, w, n, pass, tiles);
-        hipLaunchKernelGGL(k_sort_offsets, dim3(1), dim3(256), 0, s, w, pass, tiles);
+        hipLaunchKernelGGL(k_sort_offsets, dim3(1), dim3(1024), 0, s, w, pass, tiles);
         hipLaunchKernelGGL(k_sort_scatter, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, w, n, pass, tiles);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
