@@ -657,6 +657,7 @@ static void layer_free(ara_layer *L) {
     dev_free(L->t.comb);
     dev_free(L->t.occ);
     dev_free(L->t.bitmap);
+    dev_free(L->t.nz);
     dev_free(L->t.rank);
     dev_free(L->t.rel16);
     dev_free(L->t.base32);
@@ -699,6 +700,7 @@ extern "C" ara_status ara_layer_create(ara_ctx *c, ara_elt *const *elts, int32_t
     if (s == ARA_OK) s = dev_alloc(c, &L->t.comb, size_t(catalog) * (all_f32 ? 4 : 8), "layer combined table");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.occ, size_t(catalog) * 8, "layer occurrence table");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.bitmap, size_t(nblk) * 16, "layer bitmap");
+    if (s == ARA_OK) s = dev_alloc(c, &L->t.nz, size_t(nblk) * 16, "layer nonzero bitmap");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.rank, size_t(nblk) * 4, "layer ranks");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.rel16, align16(size_t(nblk) * 2), "layer relative ranks");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.base32, align16(size_t(bitmap_supers(nblk)) * 4), "layer rank bases");
@@ -779,6 +781,7 @@ static TrialArgs trial_args(const ara_yet *y, const ara_layer *L, int64_t t0, in
     a.comb = L->t.comb;
     a.occ = L->t.occ;
     a.bitmap = L->t.bitmap;
+    a.nz = L->t.nz;
     a.rel16 = L->t.rel16;
     a.base32 = L->t.base32;
     a.vals = L->t.vals;
@@ -941,9 +944,7 @@ extern "C" ara_status ara_analyze_events(ara_ctx *c, const ara_yet *y, const ara
     a.ev_occ = dev[2];
     a.ev_cum = dev[3];
     a.ev_ceded = dev[4];
-    const int64_t waves = t1 - t0;
-    const int grid = int(std::min<int64_t>(int64_t(c->n_cu) * 8, (waves + 3) / 4));
-    hipError_t e = launch_trial_events(a, L->f32, std::max(grid, 1), c->stream);
+    hipError_t e = launch_trial_events(a, L->f32, c->n_cu, c->lds_max, c->stream);
     s = e == hipSuccess ? ARA_OK : hip_fail(c, e, "event kernel");
     if (mem == ARA_MEM_HOST) {
         for (int k = 0; k < 5 && s == ARA_OK; ++k)

@@ -43,6 +43,7 @@ struct LayerTables {
     void *comb = nullptr;
     double *occ = nullptr;
     uint32_t *bitmap = nullptr;
+    uint32_t *nz = nullptr;         // one bit per event: combined loss nonzero (bitmap's layout)
     uint32_t *rank = nullptr;
     uint16_t *rel16 = nullptr;
     uint32_t *base32 = nullptr;
@@ -81,6 +82,7 @@ struct TrialArgs {
     const void *comb;        // combined table (binary64, or binary32 when f32)
     const double *occ;       // occurrence-net table over the catalog
     const uint32_t *bitmap;  // occurrence filter (see LayerTables)
+    const uint32_t *nz;      // combined loss nonzero, one bit per event (see LayerTables)
     const uint16_t *rel16;
     const uint32_t *base32;
     const double *vals;
@@ -121,7 +123,7 @@ struct TrialLaunch {
 // Trials with at most this many occurrences on average go one per lane (dense tables).
 constexpr int kLaneModeMaxMean = 256;
 hipError_t launch_trial_ylt(const TrialArgs &a, const TrialLaunch &l, hipStream_t s);
-hipError_t launch_trial_events(const TrialArgs &a, bool f32, int grid, hipStream_t s);
+hipError_t launch_trial_events(const TrialArgs &a, bool f32, int n_cu, int lds_max, hipStream_t s);
 hipError_t launch_trial_occ_max(const TrialArgs &a, const TrialLaunch &l, int grid, double *out, hipStream_t s);
 hipError_t launch_lookup(const TrialArgs &a, const TrialLaunch &l, const int32_t *ids, int64_t n, double *gross,
                          double *occ, hipStream_t s);

@@ -52,9 +52,10 @@ template <typename V>
 __global__ __launch_bounds__(256) void k_layer_combine_bitmap(const EltDesc *__restrict__ d, int n_elts,
                                                               int32_t catalog, V *__restrict__ comb, double occ_r,
                                                               double occ_l, double *__restrict__ occ,
-                                                              uint32_t *__restrict__ bitmap, int64_t n_words) {
+                                                              uint32_t *__restrict__ bitmap,
+                                                              uint32_t *__restrict__ nz, int64_t n_words) {
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    bool flag = false;
+    bool flag = false, nonzero = false;
     if (e < catalog) {
         double s = 0.0;
         for (int j = 0; j < n_elts; ++j) {
@@ -65,16 +66,20 @@ __global__ __launch_bounds__(256) void k_layer_combine_bitmap(const EltDesc *__r
         }
         const V c = V(s);
         comb[e] = c;
+        nonzero = c != V(0);
         const double o = excess(double(c), occ_r, occ_l);
         occ[e] = o;
         flag = o > 0.0;
     }
     const uint64_t m = __ballot(flag);
+    const uint64_t z = __ballot(nonzero);
     const int lane = threadIdx.x & 63;
     const int64_t w0 = (e - lane) >> 5;   // even; n_words is a multiple of 4
     if (w0 >= n_words) return;
     if (lane == 0) bitmap[w0] = uint32_t(m);
     if (lane == 1) bitmap[w0 + 1] = uint32_t(m >> 32);
+    if (lane == 2) nz[w0] = uint32_t(z);
+    if (lane == 3) nz[w0 + 1] = uint32_t(z >> 32);
 }
 
 // Exclusive prefix of per-block set-bit counts (rank), the same split into a 16-bit
@@ -239,10 +244,10 @@ hipError_t launch_layer_tables(const EltDesc *d, int n_elts, int32_t catalog, bo
     const unsigned blocks = unsigned((int64_t(t.nblk) * kEventsPerBlock + 255) / 256);
     if (f32) {
         hipLaunchKernelGGL(k_layer_combine_bitmap<float>, dim3(blocks), dim3(256), 0, s, d, n_elts, catalog,
-                           (float *)t.comb, occ_r, occ_l, t.occ, t.bitmap, int64_t(t.nblk) * 4);
+                           (float *)t.comb, occ_r, occ_l, t.occ, t.bitmap, t.nz, int64_t(t.nblk) * 4);
     } else {
         hipLaunchKernelGGL(k_layer_combine_bitmap<double>, dim3(blocks), dim3(256), 0, s, d, n_elts, catalog,
-                           (double *)t.comb, occ_r, occ_l, t.occ, t.bitmap, int64_t(t.nblk) * 4);
+                           (double *)t.comb, occ_r, occ_l, t.occ, t.bitmap, t.nz, int64_t(t.nblk) * 4);
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

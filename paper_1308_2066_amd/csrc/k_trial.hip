@@ -116,9 +116,18 @@ __device__ __forceinline__ void store4(double *out, int64_t pos, const double *v
 // ---------------------------------------------------------------------------------
 // Per-occurrence form: every quantity of the basic algorithm, with the cumulative
 // sum as a wave-wide inclusive scan (lane-local over 4 consecutive events, then a
-// 64-lane scan, plus the carry from the previous 256 events).
-template <typename V>
-__global__ __launch_bounds__(256) void k_trial_events(TrialArgs a) {
+// 64-lane scan, plus the carry from the previous 256 events).  NZ: the layer's
+// "combined loss nonzero" bits are staged in LDS and only events with a set bit
+// read the combined table (the others' gross loss is +0.0, as the table holds).
+template <typename V, bool NZ>
+__global__ __launch_bounds__(1024) void k_trial_events(TrialArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint32_t nzl[];
+    if (NZ) {
+        const u32x4 *src = reinterpret_cast<const u32x4 *>(a.nz);
+        u32x4 *dst = reinterpret_cast<u32x4 *>(nzl);
+        for (int i = threadIdx.x; i < a.nblk; i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+    }
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wpb = __builtin_amdgcn_readfirstlane(blockDim.x >> 6);
@@ -147,7 +156,9 @@ __global__ __launch_bounds__(256) void k_trial_events(TrialArgs a) {
                     const bool inr = id < C;
                     if (valid && !inr) bad |= ERR_ID_RANGE;
                     ok[j] = valid && inr;
-                    x[j] = ok[j] ? double(comb[id]) : 0.0;
+                    const uint32_t idc = ok[j] ? id : 0u;   // lanes outside the trial read word 0
+                    const bool look = NZ ? ok[j] && ((nzl[idc >> 5] >> (idc & 31u)) & 1u) : ok[j];
+                    x[j] = look ? double(comb[id]) : 0.0;
                     o[j] = ok[j] ? excess(x[j], a.occ_r, a.occ_l) : 0.0;
                 }
                 p[0] = o[0];
@@ -254,6 +265,8 @@ hipError_t prepare_trial_kernels() {
     ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_DENSE, double>))
     ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_BITMAP, float>))
     ARA_SET_LDS((k_lookup<ARA_PLACE_LDS_DENSE, float>))
+    ARA_SET_LDS((k_trial_events<double, true>))
+    ARA_SET_LDS((k_trial_events<float, true>))
 #undef ARA_SET_LDS
     return hipSuccess;
 }
@@ -293,9 +306,19 @@ hipError_t launch_trial_occ_max(const TrialArgs &a, const TrialLaunch &l, int gr
     return hipGetLastError();
 }
 
-hipError_t launch_trial_events(const TrialArgs &a, bool f32, int grid, hipStream_t s) {
-    if (f32) hipLaunchKernelGGL(k_trial_events<float>, dim3(grid), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(k_trial_events<double>, dim3(grid), dim3(256), 0, s, a);
+hipError_t launch_trial_events(const TrialArgs &a, bool f32, int n_cu, int lds_max, hipStream_t s) {
+    const int64_t waves = a.t_end - a.t_begin;
+    const size_t nz_bytes = size_t(a.nblk) * 16;
+    if (a.nz && nz_bytes <= size_t(lds_max)) {
+        // one workgroup of 16 waves per CU holds the bits
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(n_cu, (waves + 15) / 16)));
+        if (f32) hipLaunchKernelGGL((k_trial_events<float, true>), dim3(grid), dim3(1024), nz_bytes, s, a);
+        else hipLaunchKernelGGL((k_trial_events<double, true>), dim3(grid), dim3(1024), nz_bytes, s, a);
+    } else {
+        const int grid = int(std::max<int64_t>(1, std::min<int64_t>(int64_t(n_cu) * 8, (waves + 3) / 4)));
+        if (f32) hipLaunchKernelGGL((k_trial_events<float, false>), dim3(grid), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((k_trial_events<double, false>), dim3(grid), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -285,5 +285,22 @@ def test_large_catalog_many_bins_and_rank_chunks(A, S, gpu_ctx):
             comb[ids] += loss
         assert A.ara_layer_stats(gpu_ctx, an.layer)[0] == int(np.count_nonzero(comb > w.layer_terms[0]))
         _check_occ_max(A, gpu_ctx, an, ref, "large catalog", [(5, 19_999)])
+        # per-occurrence outputs: the catalog's nonzero bits (366 KB) exceed LDS, so the
+        # kernel reads the combined table for every occurrence; gross and occurrence-net
+        # losses are table values (bit-exact), the cumulative sums within the summation bound
+        import torch
+        t0, t1 = 100, 1100
+        e0, e1 = int(w.trial_offsets[t0]), int(w.trial_offsets[t1])
+        ev = {k: torch.full((e1 - e0,), math.nan, dtype=torch.float64, device="cuda")
+              for k in ("gross", "occ", "cum", "ceded")}
+        ylt = torch.full((t1 - t0,), math.nan, dtype=torch.float64, device="cuda")
+        A.ara_analyze_events(gpu_ctx, an.yet, an.layer, t0, t1, ylt, ev["gross"], ev["occ"], ev["cum"], ev["ceded"])
+        A.ara_sync(gpu_ctx)
+        ref_ev = oracle.analyze_workload(w, t_begin=t0, t_end=t1, per_event=True, threads=oracle.max_threads())
+        assert np.array_equal(ev["gross"].cpu().numpy(), ref_ev["gross"])
+        assert np.array_equal(ev["occ"].cpu().numpy(), ref_ev["occ"])
+        cum = ev["cum"].cpu().numpy()
+        assert np.all(np.abs(cum - ref_ev["cum"]) <= 1e-12 * np.maximum(np.abs(ref_ev["cum"]), 1.0))
+        _close(ylt.cpu().numpy(), ref_ev, "large catalog events")
     finally:
         an.release()
