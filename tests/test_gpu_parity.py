@@ -593,3 +593,17 @@ def test_paper_shape_reduced_f32_tables(A, S, gpu_ctx, paper_reduced):
         assert np.array_equal(g.cpu().numpy(), gross32.astype(np.float32).astype(np.float64))
     finally:
         an.release()
+    # per-occurrence gross losses through the binary32 tables (the events kernel reads
+    # the combined table only where its nonzero bit is set): the same table values
+    nt = 500
+    e1 = int(w.trial_offsets[nt])
+    an = S.open_analysis(gpu_ctx, w.event_ids[:e1], w.trial_offsets[: nt + 1], w.catalog_size, w.elts,
+                         w.layer_terms, None, 1)
+    try:
+        gev = torch.full((e1,), math.nan, dtype=torch.float64, device="cuda")
+        A.ara_analyze_events(gpu_ctx, an.yet, an.layer, 0, nt, None, gev, None, None, None)
+        A.ara_sync(gpu_ctx)
+        want = gross32.astype(np.float32).astype(np.float64)[w.event_ids[:e1]]
+        assert np.array_equal(gev.cpu().numpy(), want)
+    finally:
+        an.release()
