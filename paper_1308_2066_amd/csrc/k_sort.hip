@@ -409,6 +409,52 @@ __device__ __forceinline__ double sum256(double s, double *part) {
     return r;
 }
 
+// Ascending bitonic sort of key[0, np) in LDS by a workgroup of 1024 threads; np is a
+// power of two, equal to 1024 E when E > 1 (else at most 1024).  Stages whose pairs
+// lie within a thread's E consecutive keys run in registers without barriers; the
+// others go through LDS, each thread taking whole pairs (q-th pair: bit log2(h) of
+// its lower index is 0).
+template <int E>
+__device__ __forceinline__ void bitonic_sort_lds(uint64_t *key, int np) {
+    const int tid = threadIdx.x;
+    for (int k = 2; k <= np; k <<= 1) {
+        for (int h = k >> 1; h >= E; h >>= 1) {
+            for (int q = tid; q < np / 2; q += 1024) {
+                const int i = ((q & ~(h - 1)) << 1) | (q & (h - 1));
+                const int p = i | h;
+                const uint64_t a = key[i], b = key[p];
+                if ((a > b) == ((i & k) == 0)) {
+                    key[i] = b;
+                    key[p] = a;
+                }
+            }
+            __syncthreads();
+        }
+        if (E > 1) {
+            const int base = E * tid;
+            uint64_t r[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e) r[e] = key[base + e];
+#pragma unroll
+            for (int hh = E / 2; hh > 0; hh >>= 1) {
+                if (hh > (k >> 1)) continue;   // the merge of size k has no stage hh
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if (e & hh) continue;
+                    const bool asc = ((base + e) & k) == 0;
+                    const uint64_t a = r[e], b = r[e | hh];
+                    const bool sw = (a > b) == asc;
+                    r[e] = sw ? b : a;
+                    r[e | hh] = sw ? a : b;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < E; ++e) key[base + e] = r[e];
+            __syncthreads();
+        }
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__restrict__ ylts,
                                                      const int64_t *__restrict__ ns, const int64_t *__restrict__ ks,
                                                      int n_k, double *__restrict__ out) {
@@ -423,20 +469,12 @@ __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__rest
     while (np < n) np <<= 1;
     for (int i = threadIdx.x; i < np; i += blockDim.x) key[i] = i < n ? desc_key(y[i]) : ~0ull;
     __syncthreads();
-    for (int k = 2; k <= np; k <<= 1) {
-        for (int h = k >> 1; h > 0; h >>= 1) {
-            for (int i = threadIdx.x; i < np; i += blockDim.x) {
-                const int p = i ^ h;
-                if (p > i) {
-                    const uint64_t a = key[i], b = key[p];
-                    if ((a > b) == ((i & k) == 0)) {
-                        key[i] = b;
-                        key[p] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
+    switch (np) {
+    case 16384: bitonic_sort_lds<16>(key, np); break;
+    case 8192: bitonic_sort_lds<8>(key, np); break;
+    case 4096: bitonic_sort_lds<4>(key, np); break;
+    case 2048: bitonic_sort_lds<2>(key, np); break;
+    default: bitonic_sort_lds<1>(key, np); break;
     }
     for (int r = 0; r < n_k; ++r) {
         const int64_t k = ks[int64_t(j) * n_k + r];

@@ -223,3 +223,35 @@ def test_uneven_analyses_batch_equals_plain(A, S, gpu_ctx):
     finally:
         for an in opened:
             an.release()
+
+
+def test_batch_risk_every_lds_sort_size(A, S, gpu_ctx):
+    """Batched PML/TVaR sort each short YLT in one workgroup's LDS; the sort's register
+    stages depend on the padded length (2^k for k <= 14).  Lengths on both sides of
+    each power of two, up to one past the LDS limit (the radix sort): the same bits
+    as ara_risk_measures on the plain YLT."""
+    import torch
+    w = synth.workload_paper_scale(n_trials=20_000)
+    lengths = [1, 2, 3, 1000, 1024, 1025, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 16383, 16384, 16385]
+    an = S.open_analysis(gpu_ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, (1e5, 5e6, 1.5e8, math.inf))
+    try:
+        outs = [torch.full((n,), math.nan, dtype=torch.float64, device="cuda") for n in lengths]
+        b = A.ara_batch_create(gpu_ctx, [(an.yet, an.layer, 7, 7 + n, o) for n, o in zip(lengths, outs)])
+        try:
+            _say("batch risk LDS sort sizes")
+            A.ara_batch_run(b)
+            A.ara_sync(gpu_ctx)
+            rps = [1.0, 1.5, 10.0, 100.0, 250.0, 1e4]
+            pml, tvar = A.ara_batch_risk(b, rps)
+            for k, (n, o) in enumerate(zip(lengths, outs)):
+                p1, v1 = A.ara_risk_measures(gpu_ctx, o, rps)
+                assert pml[k].tobytes() == np.asarray(p1).tobytes(), n
+                assert tvar[k].tobytes() == np.asarray(v1).tobytes(), n
+                # and the sorted order is right: PML at the rank rule's k
+                y = np.sort(o.cpu().numpy())[::-1]
+                for r, rp in enumerate(rps):
+                    assert pml[k][r] == y[A.ara_return_period_rank(n, rp) - 1], (n, rp)
+        finally:
+            A.ara_batch_release(b)
+    finally:
+        an.release()
