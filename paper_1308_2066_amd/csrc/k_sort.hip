@@ -455,6 +455,65 @@ __device__ __forceinline__ void bitonic_sort_lds(uint64_t *key, int np) {
     }
 }
 
+// The same sort for np = 16384 (16 keys per thread) with the stages on index bits >= 4
+// taken four bits at a time: a thread loads the 16 keys whose indices differ only in
+// a 4-bit field at bit lo (the other 10 bits from its thread index), runs the stages
+// on those bits in registers and writes them back: one barrier per group instead of
+// one per stage.
+__device__ __forceinline__ void bitonic_sort_lds_16k(uint64_t *key) {
+    constexpr int np = 16384;
+    const int tid = threadIdx.x;
+    for (int k = 2; k <= np; k <<= 1) {
+        int hb = 31 - __builtin_clz(uint32_t(k)) - 1;   // the merge's highest stage bit
+        while (hb >= 4) {
+            const int lo = hb - 3 > 4 ? hb - 3 : 4;        // group: bits [lo, hb], field [lo, lo + 3]
+            const int base = ((tid >> lo) << (lo + 4)) | (tid & ((1 << lo) - 1));
+            uint64_t r[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) r[e] = key[base | (e << lo)];
+#pragma unroll
+            for (int d = 3; d >= 0; --d) {
+                if (lo + d > hb) continue;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    if (e & (1 << d)) continue;
+                    const int f = e | (1 << d);
+                    const bool asc = ((base | (e << lo)) & k) == 0;
+                    const uint64_t a = r[e], b = r[f];
+                    const bool sw = (a > b) == asc;
+                    r[e] = sw ? b : a;
+                    r[f] = sw ? a : b;
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 16; ++e) key[base | (e << lo)] = r[e];
+            __syncthreads();
+            hb = lo - 1;
+        }
+        // bits 3..0: the thread's 16 consecutive keys
+        const int base = 16 * tid;
+        uint64_t r[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) r[e] = key[base + e];
+#pragma unroll
+        for (int hh = 8; hh > 0; hh >>= 1) {
+            if (hh > (k >> 1)) continue;
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                if (e & hh) continue;
+                const bool asc = ((base + e) & k) == 0;
+                const uint64_t a = r[e], b = r[e | hh];
+                const bool sw = (a > b) == asc;
+                r[e] = sw ? b : a;
+                r[e | hh] = sw ? a : b;
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) key[base + e] = r[e];
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__restrict__ ylts,
                                                      const int64_t *__restrict__ ns, const int64_t *__restrict__ ks,
                                                      int n_k, double *__restrict__ out) {
@@ -470,7 +529,7 @@ __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__rest
     for (int i = threadIdx.x; i < np; i += blockDim.x) key[i] = i < n ? desc_key(y[i]) : ~0ull;
     __syncthreads();
     switch (np) {
-    case 16384: bitonic_sort_lds<16>(key, np); break;
+    case 16384: bitonic_sort_lds_16k(key); break;
     case 8192: bitonic_sort_lds<8>(key, np); break;
     case 4096: bitonic_sort_lds<4>(key, np); break;
     case 2048: bitonic_sort_lds<2>(key, np); break;
