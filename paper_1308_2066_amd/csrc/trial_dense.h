@@ -207,19 +207,24 @@ __device__ __forceinline__ void dense_lane_run(const TrialArgs &a, const uint32_
             o0 = o1 = 0;
         }
         double P = 0.0;
-        for (int64_t g = o0 >> 2; 4 * g < o1; ++g) {
-            int32_t id4[4];
-            if (4 * g + 4 <= a.n_events) {
-                const i32x4 x = ids4[g];
-                id4[0] = x.x, id4[1] = x.y, id4[2] = x.z, id4[3] = x.w;
-            } else {   // the YET's last, partial group: no read past its end
+        // 16 IDs (four 16-byte groups) are read before they are added, in time order
+        for (int64_t g0 = o0 >> 2; 4 * g0 < o1; g0 += 4) {
+            int32_t id16[16];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) id4[j] = 4 * g + j < a.n_events ? a.ids[4 * g + j] : 0;
+            for (int u = 0; u < 4; ++u) {
+                const int64_t g = g0 + u;
+                if (4 * g + 4 <= a.n_events) {
+                    const i32x4 x = ids4[g];
+                    id16[4 * u] = x.x, id16[4 * u + 1] = x.y, id16[4 * u + 2] = x.z, id16[4 * u + 3] = x.w;
+                } else {   // past the YET's last full group: no read past its end
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) id16[4 * u + j] = 4 * g + j < a.n_events ? a.ids[4 * g + j] : 0;
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t pos = 4 * g + j;
-                const uint32_t id = uint32_t(id4[j]);
+            for (int j = 0; j < 16; ++j) {
+                const int64_t pos = 4 * g0 + j;
+                const uint32_t id = uint32_t(id16[j]);
                 const bool valid = pos >= o0 && pos < o1;
                 bad |= valid && id >= C ? uint32_t(ERR_ID_RANGE) : 0u;
                 const double v = tab[id < C ? id : C - 1u];
