@@ -77,19 +77,24 @@ __global__ __launch_bounds__(1024) void k_trial_occ_max(TrialArgs a, double *__r
             o0 = o1 = 0;
         }
         double m = 0.0;
-        for (int64_t g = o0 >> 2; 4 * g < o1; ++g) {
-            int32_t id4[4];
-            if (4 * g + 4 <= a.n_events) {
-                const i32x4 x = ids4[g];
-                id4[0] = x.x, id4[1] = x.y, id4[2] = x.z, id4[3] = x.w;
-            } else {
+        // 16 IDs (four 16-byte groups) are read before they are looked up
+        for (int64_t g0 = o0 >> 2; 4 * g0 < o1; g0 += 4) {
+            int32_t id16[16];
 #pragma unroll
-                for (int j = 0; j < 4; ++j) id4[j] = 4 * g + j < a.n_events ? a.ids[4 * g + j] : 0;
+            for (int u = 0; u < 4; ++u) {
+                const int64_t g = g0 + u;
+                if (4 * g + 4 <= a.n_events) {
+                    const i32x4 x = ids4[g];
+                    id16[4 * u] = x.x, id16[4 * u + 1] = x.y, id16[4 * u + 2] = x.z, id16[4 * u + 3] = x.w;
+                } else {   // past the YET's last full group: no read past its end
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) id16[4 * u + j] = 4 * g + j < a.n_events ? a.ids[4 * g + j] : 0;
+                }
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t pos = 4 * g + j;
-                const uint32_t id = uint32_t(id4[j]);
+            for (int j = 0; j < 16; ++j) {
+                const int64_t pos = 4 * g0 + j;
+                const uint32_t id = uint32_t(id16[j]);
                 if (pos < o0 || pos >= o1) continue;
                 if (id >= C) {
                     bad |= ERR_ID_RANGE;
