@@ -20,6 +20,7 @@ constexpr int kSortPerThread = 16;
 constexpr int kSortTile = kSortThreads * kSortPerThread;   // 4096 keys
 constexpr int kWavesPerTile = kSortThreads / 64;            // 4, each owns 1024 consecutive keys
 constexpr int kPasses = 8;
+static_assert(kSortThreads == 256, "the count and scatter kernels take one digit per thread");
 
 __device__ __forceinline__ uint64_t desc_key(double d) {
     uint64_t u = __builtin_bit_cast(uint64_t, d + 0.0);   // -0.0 + 0.0 == +0.0
@@ -43,6 +44,7 @@ struct SortWs {
     uint64_t *a, *b;
     uint32_t *counts;   // [256][tiles]
     uint32_t *hist;     // 8 KB: the encoding's per-workgroup digit differences (uint64)
+    uint32_t *dtotal;   // [256] keys per digit in the current pass (in the second half of hist)
     uint32_t *plan;     // plan[p]: keys before pass p are in b (1) or a (0), p = 0..8;
                         // plan[16 + p]: pass p is skipped
     double *part;       // [kRiskGroup][kRiskMaxBlocks] partial sums of the top-k keys
@@ -68,6 +70,7 @@ static SortWs sort_ws(void *ws, int64_t n) {
     w.b = reinterpret_cast<uint64_t *>(p + keys);
     w.counts = reinterpret_cast<uint32_t *>(p + 2 * keys);
     w.hist = reinterpret_cast<uint32_t *>(p + 2 * keys + counts);
+    w.dtotal = w.hist + 1024;   // after kEncodeBlocks 64-bit slots
     w.plan = reinterpret_cast<uint32_t *>(p + 2 * keys + counts + align256(8 * 256 * 4));
     w.part = reinterpret_cast<double *>(p + 2 * keys + counts + align256(8 * 256 * 4) + 256);
     return w;
@@ -166,29 +169,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(SortWs w, int64_t n
     w.counts[int64_t(threadIdx.x) * tiles + blockIdx.x] = hist[threadIdx.x];
 }
 
-// Exclusive offsets of every (digit, tile): the counts are stored digit-major, so
-// the offset of (d, t) is the exclusive prefix sum of the flat array up to (d, t).
-// One workgroup scans it in chunks of 4096 (four consecutive counts per thread);
-// the next chunk's counts are read before the current one is scanned.
-__global__ __launch_bounds__(1024) void k_sort_offsets(SortWs w, int pass, int64_t tiles) {
+// Exclusive offsets within each digit's row of tile counts: one workgroup per digit
+// scans its row in place, in chunks of 1024 (four consecutive counts per thread), and
+// stores the row's total in w.dtotal.  The scatter adds the prefix of the totals over
+// the smaller digits, so the offset of (d, t) is that of the flat digit-major array.
+__global__ __launch_bounds__(256) void k_sort_rowscan(SortWs w, int pass, int64_t tiles) {
     if (w.plan[16 + pass]) return;
-    __shared__ uint32_t wsum[16];
-    const int64_t n = int64_t(256) * tiles;
-    uint32_t *c = w.counts;
+    __shared__ uint32_t wsum[4];
+    uint32_t *c = w.counts + int64_t(blockIdx.x) * tiles;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    auto load = [&](int64_t base, uint32_t *v) {
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < tiles; base += 1024) {
+        uint32_t v[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t i = base + 4 * tid + j;
-            v[j] = i < n ? c[i] : 0u;
+            v[j] = i < tiles ? c[i] : 0u;
         }
-    };
-    uint32_t cur[4], nxt[4];
-    load(0, cur);
-    uint32_t carry = 0;
-    for (int64_t base = 0; base < n; base += 4096) {
-        load(base + 4096, nxt);
-        const uint32_t t = cur[0] + cur[1] + cur[2] + cur[3];
+        const uint32_t t = v[0] + v[1] + v[2] + v[3];
         uint32_t inc = t;   // inclusive wave scan of the threads' sums
         for (int o = 1; o < 64; o <<= 1) {
             const uint32_t y = __shfl_up(inc, o, 64);
@@ -196,23 +194,20 @@ __global__ __launch_bounds__(1024) void k_sort_offsets(SortWs w, int pass, int64
         }
         if (lane == 63) wsum[wv] = inc;
         __syncthreads();
-        uint32_t before = 0, total = 0;
-        for (int k = 0; k < 16; ++k) {
-            if (k < wv) before += wsum[k];
-            total += wsum[k];
-        }
+        uint32_t before = 0;
+        for (int k = 0; k < wv; ++k) before += wsum[k];
+        const uint32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
         uint32_t run = carry + before + inc - t;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t i = base + 4 * tid + j;
-            if (i < n) c[i] = run;
-            run += cur[j];
+            if (i < tiles) c[i] = run;
+            run += v[j];
         }
         carry += total;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
         __syncthreads();
     }
+    if (tid == 0) w.dtotal[blockIdx.x] = carry;
 }
 
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t n, int pass, int64_t tiles) {
@@ -223,8 +218,19 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t
     uint64_t *out = w.plan[pass] ? w.a : w.b;
     const int shift = 8 * pass;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __shared__ uint32_t wtot[kWavesPerTile];
     for (int k = 0; k < kWavesPerTile; ++k) whist[k][threadIdx.x] = 0;
+    // keys in the smaller digits: exclusive scan of the digit totals
+    const uint32_t dt = w.dtotal[threadIdx.x];
+    uint32_t dinc = dt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(dinc, o, 64);
+        if (lane >= o) dinc += y;
+    }
+    if (lane == 63) wtot[wv] = dinc;
     __syncthreads();
+    uint32_t dbase = dinc - dt;
+    for (int k = 0; k < wv; ++k) dbase += wtot[k];
     const int64_t base = int64_t(blockIdx.x) * kSortTile + wv * 1024;
     uint64_t key[kSortPerThread];
     uint32_t rank[kSortPerThread];
@@ -245,7 +251,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t
     __syncthreads();
     {
         const int d = threadIdx.x;
-        uint32_t run = w.counts[int64_t(d) * tiles + blockIdx.x];
+        uint32_t run = dbase + w.counts[int64_t(d) * tiles + blockIdx.x];
         for (int k = 0; k < kWavesPerTile; ++k) {
             woff[k][d] = run;
             run += whist[k][d];
@@ -293,7 +299,7 @@ hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStrea
     for (int pass = 0; pass < kPasses; ++pass) {
         if (skip[pass]) continue;
         hipLaunchKernelGGL(k_sort_count, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, w, n, pass, tiles);
-        hipLaunchKernelGGL(k_sort_offsets, dim3(1), dim3(1024), 0, s, w, pass, tiles);
+        hipLaunchKernelGGL(k_sort_rowscan, dim3(256), dim3(256), 0, s, w, pass, tiles);
         hipLaunchKernelGGL(k_sort_scatter, dim3(unsigned(tiles)), dim3(kSortThreads), 0, s, w, n, pass, tiles);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
