@@ -15,12 +15,13 @@
 
 namespace ara {
 
-constexpr int kSortThreads = 256;
-constexpr int kSortPerThread = 16;
+constexpr int kSortThreads = 1024;
+constexpr int kSortPerThread = 4;
 constexpr int kSortTile = kSortThreads * kSortPerThread;   // 4096 keys
-constexpr int kWavesPerTile = kSortThreads / 64;            // 4, each owns 1024 consecutive keys
+constexpr int kWavesPerTile = kSortThreads / 64;            // 16
+constexpr int kWaveKeys = 64 * kSortPerThread;              // consecutive keys a wave owns
 constexpr int kPasses = 8;
-static_assert(kSortThreads == 256, "the count and scatter kernels take one digit per thread");
+static_assert(kSortThreads >= 256 && kSortThreads % 64 == 0, "the first 256 threads take one digit each");
 
 __device__ __forceinline__ uint64_t desc_key(double d) {
     uint64_t u = __builtin_bit_cast(uint64_t, d + 0.0);   // -0.0 + 0.0 == +0.0
@@ -150,9 +151,9 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(SortWs w, int64_t n
     const uint64_t *keys = cur_keys(w, pass);
     const int shift = 8 * pass;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    hist[threadIdx.x] = 0;
+    if (threadIdx.x < 256) hist[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t base = int64_t(blockIdx.x) * kSortTile + wv * 1024;
+    const int64_t base = int64_t(blockIdx.x) * kSortTile + wv * kWaveKeys;
     uint32_t d[kSortPerThread];
 #pragma unroll
     for (int r = 0; r < kSortPerThread; ++r) {
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(SortWs w, int64_t n
         if (valid && (m & lanes_below(lane)) == 0) atomicAdd(&hist[d[r]], uint32_t(__popcll(m)));
     }
     __syncthreads();
-    w.counts[int64_t(threadIdx.x) * tiles + blockIdx.x] = hist[threadIdx.x];
+    if (threadIdx.x < 256) w.counts[int64_t(threadIdx.x) * tiles + blockIdx.x] = hist[threadIdx.x];
 }
 
 // Exclusive offsets within each digit's row of tile counts: one workgroup per digit
@@ -218,20 +219,23 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t
     uint64_t *out = w.plan[pass] ? w.a : w.b;
     const int shift = 8 * pass;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __shared__ uint32_t wtot[kWavesPerTile];
-    for (int k = 0; k < kWavesPerTile; ++k) whist[k][threadIdx.x] = 0;
-    // keys in the smaller digits: exclusive scan of the digit totals
-    const uint32_t dt = w.dtotal[threadIdx.x];
-    uint32_t dinc = dt;
-    for (int o = 1; o < 64; o <<= 1) {
-        const uint32_t y = __shfl_up(dinc, o, 64);
-        if (lane >= o) dinc += y;
+    __shared__ uint32_t wtot[4];
+    for (int i = threadIdx.x; i < kWavesPerTile * 256; i += kSortThreads) whist[i >> 8][i & 255] = 0;
+    // keys in the smaller digits: exclusive scan of the digit totals (first four waves)
+    uint32_t dt = 0, dinc = 0;
+    if (threadIdx.x < 256) {
+        dt = w.dtotal[threadIdx.x];
+        dinc = dt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(dinc, o, 64);
+            if (lane >= o) dinc += y;
+        }
+        if (lane == 63) wtot[wv] = dinc;
     }
-    if (lane == 63) wtot[wv] = dinc;
     __syncthreads();
     uint32_t dbase = dinc - dt;
-    for (int k = 0; k < wv; ++k) dbase += wtot[k];
-    const int64_t base = int64_t(blockIdx.x) * kSortTile + wv * 1024;
+    for (int k = 0; k < wv && k < 4; ++k) dbase += wtot[k];
+    const int64_t base = int64_t(blockIdx.x) * kSortTile + wv * kWaveKeys;
     uint64_t key[kSortPerThread];
     uint32_t rank[kSortPerThread];
 #pragma unroll
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t
         if (valid && below == 0) whist[wv][d] += uint32_t(__popcll(m));
     }
     __syncthreads();
-    {
+    if (threadIdx.x < 256) {
         const int d = threadIdx.x;
         uint32_t run = dbase + w.counts[int64_t(d) * tiles + blockIdx.x];
         for (int k = 0; k < kWavesPerTile; ++k) {
