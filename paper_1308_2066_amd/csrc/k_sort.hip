@@ -16,8 +16,8 @@
 namespace ara {
 
 constexpr int kSortThreads = 1024;
-constexpr int kSortPerThread = 4;
-constexpr int kSortTile = kSortThreads * kSortPerThread;   // 4096 keys
+constexpr int kSortPerThread = 2;
+constexpr int kSortTile = kSortThreads * kSortPerThread;   // 2048 keys
 constexpr int kWavesPerTile = kSortThreads / 64;            // 16
 constexpr int kWaveKeys = 64 * kSortPerThread;              // consecutive keys a wave owns
 constexpr int kPasses = 8;

@@ -401,7 +401,7 @@ def test_schedule_independence_and_determinism(A, S, gpu_ctx, small):
 
 
 # ----------------------------------------------------------------------------- sort
-@pytest.mark.parametrize("n", [1, 2, 63, 4095, 4096, 4097, 100_003, 1_000_000, 4_500_001])
+@pytest.mark.parametrize("n", [1, 2, 63, 2047, 2049, 4095, 4096, 4097, 100_003, 1_000_000, 4_500_001])
 def test_sort_bit_exact(A, gpu_ctx, n):
     import torch
     _say(f"sort n={n}")
