@@ -10,7 +10,9 @@
 // keys differ; a pass in which every key has the same digit is skipped on the device
 // (capped YLTs often hold one value many times).  Each other pass: per-tile digit
 // counts, exclusive offsets per (digit, tile), and a stable scatter in which every
-// wave ranks its keys by matching digits across lanes with 8 ballots.
+// wave ranks its keys by matching digits across lanes with 8 ballots; the tile's keys
+// are placed in LDS in output order first, so a store instruction writes runs of
+// consecutive output positions.
 #include "ara_internal.h"
 
 namespace ara {
@@ -214,12 +216,15 @@ __global__ __launch_bounds__(256) void k_sort_rowscan(SortWs w, int pass, int64_
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t n, int pass, int64_t tiles) {
     if (w.plan[16 + pass]) return;
     __shared__ uint32_t whist[kWavesPerTile][256];
-    __shared__ uint32_t woff[kWavesPerTile][256];
+    __shared__ uint32_t woff[kWavesPerTile][256];   // tile-local start of (wave, digit)
+    __shared__ uint32_t lstart[256];                // tile-local start of each digit
+    __shared__ uint32_t gstart[256];                // output index of the tile's first key of each digit
+    __shared__ uint64_t stage[kSortTile];           // the tile's keys in output order
+    __shared__ uint32_t wtot[4], ltot[4];
     const uint64_t *in = cur_keys(w, pass);
     uint64_t *out = w.plan[pass] ? w.a : w.b;
     const int shift = 8 * pass;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    __shared__ uint32_t wtot[4];
     for (int i = threadIdx.x; i < kWavesPerTile * 256; i += kSortThreads) whist[i >> 8][i & 255] = 0;
     // keys in the smaller digits: exclusive scan of the digit totals (first four waves)
     uint32_t dt = 0, dinc = 0;
@@ -235,7 +240,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t
     __syncthreads();
     uint32_t dbase = dinc - dt;
     for (int k = 0; k < wv && k < 4; ++k) dbase += wtot[k];
-    const int64_t base = int64_t(blockIdx.x) * kSortTile + wv * kWaveKeys;
+    const int64_t tile0 = int64_t(blockIdx.x) * kSortTile;
+    const int64_t base = tile0 + wv * kWaveKeys;
     uint64_t key[kSortPerThread];
     uint32_t rank[kSortPerThread];
 #pragma unroll
@@ -253,9 +259,24 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t
         if (valid && below == 0) whist[wv][d] += uint32_t(__popcll(m));
     }
     __syncthreads();
+    // tile-local start of each digit: exclusive scan of the tile's digit counts
+    uint32_t tt = 0, tinc = 0;
+    if (threadIdx.x < 256) {
+        for (int k = 0; k < kWavesPerTile; ++k) tt += whist[k][threadIdx.x];
+        tinc = tt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(tinc, o, 64);
+            if (lane >= o) tinc += y;
+        }
+        if (lane == 63) ltot[wv] = tinc;
+    }
+    __syncthreads();
     if (threadIdx.x < 256) {
         const int d = threadIdx.x;
-        uint32_t run = dbase + w.counts[int64_t(d) * tiles + blockIdx.x];
+        uint32_t run = tinc - tt;
+        for (int k = 0; k < wv; ++k) run += ltot[k];
+        lstart[d] = run;
+        gstart[d] = dbase + w.counts[int64_t(d) * tiles + blockIdx.x];
         for (int k = 0; k < kWavesPerTile; ++k) {
             woff[k][d] = run;
             run += whist[k][d];
@@ -264,11 +285,18 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(SortWs w, int64_t
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < kSortPerThread; ++r) {
-        const int64_t i = base + r * 64 + lane;
-        if (i < n) {
+        if (base + r * 64 + lane < n) {
             const uint32_t d = uint32_t(key[r] >> shift) & 255u;
-            out[woff[wv][d] + rank[r]] = key[r];
+            stage[woff[wv][d] + rank[r]] = key[r];
         }
+    }
+    __syncthreads();
+    // consecutive threads write consecutive keys of a digit's run
+    const int tile_n = int(std::min<int64_t>(kSortTile, n - tile0));
+    for (int i = threadIdx.x; i < tile_n; i += kSortThreads) {
+        const uint64_t k = stage[i];
+        const uint32_t d = uint32_t(k >> shift) & 255u;
+        out[gstart[d] + uint32_t(i) - lstart[d]] = k;
     }
 }
 
