@@ -109,13 +109,14 @@ __global__ __launch_bounds__(1024) void k_trial_occ_max(TrialArgs a, double *__r
     if (bad) atomicOr(a.err, bad);
 }
 
-// Four consecutive binary64 outputs from element pos on (8-byte aligned), if out is set.
+// Four consecutive binary64 outputs from element pos on (8-byte aligned), if out is set;
+// non-temporal, since the outputs are written once and not read back by the kernel.
 typedef double f64x2_u __attribute__((ext_vector_type(2), aligned(8)));
 __device__ __forceinline__ void store4(double *out, int64_t pos, const double *v) {
     if (!out) return;
     f64x2_u *p = reinterpret_cast<f64x2_u *>(out + pos);
-    p[0] = f64x2_u{v[0], v[1]};
-    p[1] = f64x2_u{v[2], v[3]};
+    __builtin_nontemporal_store(f64x2_u{v[0], v[1]}, p);
+    __builtin_nontemporal_store(f64x2_u{v[2], v[3]}, p + 1);
 }
 
 // ---------------------------------------------------------------------------------
