@@ -109,20 +109,18 @@ __global__ __launch_bounds__(1024) void k_trial_occ_max(TrialArgs a, double *__r
     if (bad) atomicOr(a.err, bad);
 }
 
-// Four consecutive binary64 outputs from element pos on (8-byte aligned), if out is set;
+// Two consecutive binary64 outputs from element pos on (8-byte aligned), if out is set;
 // non-temporal, since the outputs are written once and not read back by the kernel.
 typedef double f64x2_u __attribute__((ext_vector_type(2), aligned(8)));
-__device__ __forceinline__ void store4(double *out, int64_t pos, const double *v) {
+__device__ __forceinline__ void store2(double *out, int64_t pos, double v0, double v1) {
     if (!out) return;
-    f64x2_u *p = reinterpret_cast<f64x2_u *>(out + pos);
-    __builtin_nontemporal_store(f64x2_u{v[0], v[1]}, p);
-    __builtin_nontemporal_store(f64x2_u{v[2], v[3]}, p + 1);
+    __builtin_nontemporal_store(f64x2_u{v0, v1}, reinterpret_cast<f64x2_u *>(out + pos));
 }
 
 // ---------------------------------------------------------------------------------
 // Per-occurrence form: every quantity of the basic algorithm, with the cumulative
-// sum as a wave-wide inclusive scan (lane-local over 4 consecutive events, then a
-// 64-lane scan, plus the carry from the previous 256 events).  NZ: the layer's
+// sum as wave-wide inclusive scans (lane-local over 2 consecutive events, then a
+// 64-lane scan, plus the carry from the previous 128 events).  NZ: the layer's
 // "combined loss nonzero" bits are staged in LDS and only events with a set bit
 // read the combined table (the others' gross loss is +0.0, as the table holds).
 template <typename V, bool NZ>
@@ -152,12 +150,28 @@ __global__ __launch_bounds__(1024) void k_trial_events(TrialArgs a) {
             int lo, hi;
             seg_bounds(c, lo, hi);
             for (int k = 0; k < kNch && k * kChunk < hi; ++k) {
-                double x[4], o[4], p[4], F[4];
+                // lane l takes events 2l, 2l+1 and 128+2l, 129+2l of the chunk (its IDs
+                // fetched from the lanes that loaded them), so that one store instruction
+                // writes 64 consecutive pairs of an output array
+                const bool odd = lane & 1;
+                const int s0 = lane >> 1, s1 = 32 + (lane >> 1);
+                uint32_t idv[4];
+                {
+                    const uint32_t ax = __shfl(r[k][0], s0, 64), ay = __shfl(r[k][1], s0, 64);
+                    const uint32_t az = __shfl(r[k][2], s0, 64), aw = __shfl(r[k][3], s0, 64);
+                    const uint32_t bx = __shfl(r[k][0], s1, 64), by = __shfl(r[k][1], s1, 64);
+                    const uint32_t bz = __shfl(r[k][2], s1, 64), bw = __shfl(r[k][3], s1, 64);
+                    idv[0] = odd ? az : ax;
+                    idv[1] = odd ? aw : ay;
+                    idv[2] = odd ? bz : bx;
+                    idv[3] = odd ? bw : by;
+                }
+                double x[4], o[4], P[4], F[4];
                 bool ok[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int rel = k * kChunk + lane * 4 + j;
-                    const uint32_t id = r[k][j];
+                    const int rel = k * kChunk + (j < 2 ? 0 : 128) + 2 * lane + (j & 1);
+                    const uint32_t id = idv[j];
                     const bool valid = rel >= lo && rel < hi;
                     const bool inr = id < C;
                     if (valid && !inr) bad |= ERR_ID_RANGE;
@@ -167,52 +181,47 @@ __global__ __launch_bounds__(1024) void k_trial_events(TrialArgs a) {
                     x[j] = look ? double(comb[id]) : 0.0;
                     o[j] = ok[j] ? excess(x[j], a.occ_r, a.occ_l) : 0.0;
                 }
-                p[0] = o[0];
-                p[1] = p[0] + o[1];
-                p[2] = p[1] + o[2];
-                p[3] = p[2] + o[3];
-                double inc = p[3];
+                // cumulative sums: the chunk's first 128 events, then its last 128
 #pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const double y = __shfl_up(inc, d, 64);
-                    if (lane >= d) inc += y;
-                }
-                double ex = __shfl_up(inc, 1, 64);
-                if (lane == 0) ex = 0.0;
-                const double base = carryP + ex;
-                double P[4];
+                for (int h = 0; h < 2; ++h) {
+                    const double q0 = o[2 * h], q1 = o[2 * h] + o[2 * h + 1];
+                    double inc = q1;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    P[j] = base + p[j];
-                    F[j] = excess(P[j], a.agg_r, a.agg_l);
-                }
-                double Fprev = __shfl_up(F[3], 1, 64);
-                if (lane == 0) Fprev = carryF;
-                double ced[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    ced[j] = F[j] - (j == 0 ? Fprev : F[j - 1]);
-                    if (ok[j]) lr += ced[j];
-                }
-                const int64_t pos0 = c.sbase + k * kChunk + lane * 4 - ev0;
-                if (ok[0] && ok[1] && ok[2] && ok[3]) {
-                    // a lane's four consecutive outputs as two 16-byte stores per array
-                    store4(a.ev_gross, pos0, x);
-                    store4(a.ev_occ, pos0, o);
-                    store4(a.ev_cum, pos0, P);
-                    store4(a.ev_ceded, pos0, ced);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        if (!ok[j]) continue;
-                        if (a.ev_gross) a.ev_gross[pos0 + j] = x[j];
-                        if (a.ev_occ) a.ev_occ[pos0 + j] = o[j];
-                        if (a.ev_cum) a.ev_cum[pos0 + j] = P[j];
-                        if (a.ev_ceded) a.ev_ceded[pos0 + j] = ced[j];
+                    for (int d = 1; d < 64; d <<= 1) {
+                        const double y = __shfl_up(inc, d, 64);
+                        if (lane >= d) inc += y;
                     }
+                    double ex = __shfl_up(inc, 1, 64);
+                    if (lane == 0) ex = 0.0;
+                    const double base = carryP + ex;
+                    P[2 * h] = base + q0;
+                    P[2 * h + 1] = base + q1;
+                    F[2 * h] = excess(P[2 * h], a.agg_r, a.agg_l);
+                    F[2 * h + 1] = excess(P[2 * h + 1], a.agg_r, a.agg_l);
+                    double Fprev = __shfl_up(F[2 * h + 1], 1, 64);
+                    if (lane == 0) Fprev = carryF;
+                    double ced[2] = {F[2 * h] - Fprev, F[2 * h + 1] - F[2 * h]};
+                    if (ok[2 * h]) lr += ced[0];
+                    if (ok[2 * h + 1]) lr += ced[1];
+                    const int64_t pos0 = c.sbase + k * kChunk + 128 * h + 2 * lane - ev0;
+                    if (ok[2 * h] && ok[2 * h + 1]) {
+                        store2(a.ev_gross, pos0, x[2 * h], x[2 * h + 1]);
+                        store2(a.ev_occ, pos0, o[2 * h], o[2 * h + 1]);
+                        store2(a.ev_cum, pos0, P[2 * h], P[2 * h + 1]);
+                        store2(a.ev_ceded, pos0, ced[0], ced[1]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < 2; ++j) {
+                            if (!ok[2 * h + j]) continue;
+                            if (a.ev_gross) a.ev_gross[pos0 + j] = x[2 * h + j];
+                            if (a.ev_occ) a.ev_occ[pos0 + j] = o[2 * h + j];
+                            if (a.ev_cum) a.ev_cum[pos0 + j] = P[2 * h + j];
+                            if (a.ev_ceded) a.ev_ceded[pos0 + j] = ced[j];
+                        }
+                    }
+                    carryP = __shfl(P[2 * h + 1], 63, 64);
+                    carryF = __shfl(F[2 * h + 1], 63, 64);
                 }
-                carryP = __shfl(P[3], 63, 64);
-                carryF = __shfl(F[3], 63, 64);
             }
             if (seg_last(c)) break;
             c.sbase += kSeg;
