@@ -164,9 +164,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_count(SortWs w, int64_t n
     }
 #pragma unroll
     for (int r = 0; r < kSortPerThread; ++r) {
-        const bool valid = base + r * 64 + lane < n;
-        const uint64_t m = match_digit(d[r], valid);
-        if (valid && (m & lanes_below(lane)) == 0) atomicAdd(&hist[d[r]], uint32_t(__popcll(m)));
+        if (base + r * 64 + lane < n) atomicAdd(&hist[d[r]], 1u);
     }
     __syncthreads();
     if (threadIdx.x < 256) w.counts[int64_t(threadIdx.x) * tiles + blockIdx.x] = hist[threadIdx.x];
