@@ -73,7 +73,7 @@ static SortWs sort_ws(void *ws, int64_t n) {
     w.b = reinterpret_cast<uint64_t *>(p + keys);
     w.counts = reinterpret_cast<uint32_t *>(p + 2 * keys);
     w.hist = reinterpret_cast<uint32_t *>(p + 2 * keys + counts);
-    w.dtotal = w.hist + 1024;   // after kEncodeBlocks 64-bit slots
+    w.dtotal = w.hist + 1024;   // after 512 64-bit slots of encoding differences
     w.plan = reinterpret_cast<uint32_t *>(p + 2 * keys + counts + align256(8 * 256 * 4));
     w.part = reinterpret_cast<double *>(p + 2 * keys + counts + align256(8 * 256 * 4) + 256);
     return w;
@@ -88,11 +88,12 @@ __device__ __forceinline__ const uint64_t *cur_keys(const SortWs &w, int pass) {
 // key) over its keys, and a pass is skipped when that digit of the OR over all
 // workgroups is zero.  A wave reads 8 rows of 64 values at a time.
 constexpr int kEncodeBlocks = 256;   // workgroups of k_sort_encode (one OR slot each)
+static_assert(kEncodeBlocks <= 512, "the OR slots end where the digit totals start");
 
-__global__ __launch_bounds__(256) void k_sort_encode(const double *__restrict__ in, int64_t n,
+__global__ __launch_bounds__(1024) void k_sort_encode(const double *__restrict__ in, int64_t n,
                                                      uint64_t *__restrict__ keys, uint64_t *__restrict__ diff) {
     constexpr int kRows = 8;
-    __shared__ uint64_t wdiff[4];
+    __shared__ uint64_t wdiff[16];
     const uint64_t k0 = desc_key(in[0]);
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     uint64_t d = 0;
@@ -113,7 +114,11 @@ __global__ __launch_bounds__(256) void k_sort_encode(const double *__restrict__ 
     for (int o = 32; o >= 1; o >>= 1) d |= __shfl_xor(d, o, 64);
     if ((threadIdx.x & 63) == 0) wdiff[threadIdx.x >> 6] = d;
     __syncthreads();
-    if (threadIdx.x == 0) diff[blockIdx.x] = wdiff[0] | wdiff[1] | wdiff[2] | wdiff[3];
+    if (threadIdx.x == 0) {
+        uint64_t o = 0;
+        for (int k = 0; k < 16; ++k) o |= wdiff[k];
+        diff[blockIdx.x] = o;
+    }
 }
 
 // The plan: which buffer holds the keys before each pass, and which passes are skipped.
@@ -313,9 +318,9 @@ hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStrea
     if (n <= 0) return hipSuccess;
     SortWs w = sort_ws(ws, n);
     const int64_t tiles = sort_tiles(n);
-    const unsigned eb = unsigned(std::min<int64_t>((n + 255) / 256, kEncodeBlocks));   // <= 1024 slots fit
+    const unsigned eb = unsigned(std::min<int64_t>((n + 255) / 256, kEncodeBlocks));
     uint64_t *diff = reinterpret_cast<uint64_t *>(w.hist);
-    hipLaunchKernelGGL(k_sort_encode, dim3(eb), dim3(256), 0, s, in, n, w.a, diff);
+    hipLaunchKernelGGL(k_sort_encode, dim3(eb), dim3(1024), 0, s, in, n, w.a, diff);
     hipLaunchKernelGGL(k_sort_plan, dim3(1), dim3(64), 0, s, diff, int(eb), w.plan);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
