@@ -353,7 +353,9 @@ def _edge_workload(rng, lengths, catalog=5000, n_elts=3, lead=0):
 @pytest.mark.parametrize("placement", PLACEMENTS)
 def test_edge_trial_lengths(A, S, gpu_ctx, placement):
     rng = np.random.default_rng(55)
-    lengths = [0, 1, 3, 4, 5, 255, 256, 257, 1023, 1024, 1025, 2047, 2049, 3000, 0, 0, 7, 4099, 1, 2]
+    # the tail: lengths about the half of a 256-occurrence chunk in the per-occurrence kernel
+    lengths = [0, 1, 3, 4, 5, 255, 256, 257, 1023, 1024, 1025, 2047, 2049, 3000, 0, 0, 7, 4099, 1, 2,
+               127, 128, 129, 131]
     w = _edge_workload(rng, lengths)
     assert w.n_events % 4 != 0
     _say(f"edge lengths placement={placement} n_events={w.n_events}")
@@ -363,6 +365,10 @@ def test_edge_trial_lengths(A, S, gpu_ctx, placement):
     assert analyze(A, S, gpu_ctx, w, placement, packing=0).tobytes() == got.tobytes()
     ev = analyze_events(A, S, gpu_ctx, w, placement)
     assert np.array_equal(ev["gross"], ref["gross"]) and np.array_equal(ev["occ"], ref["occ"])
+    Pk = np.repeat(ref["occ_total"], np.diff(w.trial_offsets))
+    assert np.all(np.abs(ev["cum"] - ref["cum"]) <= 1e-12 * Pk)
+    assert np.all(np.abs(ev["ceded"] - ref["ceded"]) <= 2e-12 * Pk)
+    assert_ylt_close(ev["ylt"], ref, what="events-mode ylt")
     # sub-ranges of trials
     for t0, t1 in [(0, 1), (3, 11), (13, 20), (5, 5), (19, 20)]:
         sub = analyze(A, S, gpu_ctx, w, placement, t0=t0, t1=t1)
