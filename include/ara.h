@@ -365,9 +365,9 @@ ara_status ara_batch_portfolio(ara_batch *batch, double *out);
  * bit 0 = runs replay a graph, bit 1 = workgroups take every G-th item (G workgroups)
  * rather than a contiguous run, so the grid works on few jobs at a time and their
  * tables share the L2.  Items and workgroups count the persistent launches only: a job
- * whose YET has a catalog-binned copy runs as a launch of the tiled kernel of its own
- * and adds no items (a batch of only such jobs reports 0 and 0).  Any output pointer
- * may be NULL. */
+ * whose placement is ARA_PLACE_LDS_TILES (as ara_analyze would choose it) runs as a
+ * launch of the tiled kernel of its own and adds no items (a batch of only such jobs
+ * reports 0 and 0).  Any output pointer may be NULL. */
 ara_status ara_batch_info(const ara_batch *batch, int32_t *n_items, int32_t *grid, int64_t *events_per_item,
                           int32_t *graph);
 
