@@ -28,6 +28,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ara_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+# The mutation test (tests/test_oracle_mutations.py) points this at a build of a copy
+# of ara_oracle.c with one planted mistake, to show that the pins catch it.
+_ALT_LIB = os.environ.get("ARA_ORACLE_LIB")
 _lock = threading.Lock()
 _lib = None
 
@@ -55,8 +58,11 @@ def _load():
     global _lib
     with _lock:
         if _lib is None:
-            build()
-            lib = ctypes.CDLL(_LIB)
+            if _ALT_LIB:
+                lib = ctypes.CDLL(_ALT_LIB)
+            else:
+                build()
+                lib = ctypes.CDLL(_LIB)
             P = ctypes.c_void_p
             lib.oracle_analyze.restype = ctypes.c_int
             lib.oracle_analyze.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,

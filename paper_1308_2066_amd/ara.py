@@ -380,24 +380,42 @@ def ara_sort_workspace_size(n: int) -> int:
     return int(b.value)
 
 
+def _workspace(values, workspace):
+    """The caller's sort workspace, or a torch allocation of ara_sort_workspace_size
+    bytes (the library then allocates nothing)."""
+    import torch
+    if workspace is None:
+        workspace = torch.empty(max(1, ara_sort_workspace_size(values.numel())), dtype=torch.uint8,
+                                device=values.device)
+    return workspace, _dev_ptr(workspace, torch.uint8, "workspace")
+
+
 def ara_sort_desc(ctx: Ctx, values, out, workspace=None):
+    """Descending sort of a float64 GPU tensor into out.  Asynchronous with a caller
+    workspace; with none, the binding allocates one through torch and waits for the
+    sort before it is released."""
     import torch
     pv = _dev_ptr(values, torch.float64, "values")
     po = _dev_ptr(out, torch.float64, "out")
-    pw, nw = (None, 0) if workspace is None else (_dev_ptr(workspace, torch.uint8, "workspace"), workspace.numel())
-    _check(_lib.ara_sort_desc(ctx.ptr, pv, values.numel(), po, pw, nw), ctx, "ara_sort_desc")
+    own = workspace is None
+    workspace, pw = _workspace(values, workspace)
+    _check(_lib.ara_sort_desc(ctx.ptr, pv, values.numel(), po, pw, workspace.numel()), ctx, "ara_sort_desc")
+    if own:
+        ara_sync(ctx)
 
 
 def ara_risk_measures(ctx: Ctx, ylt, return_periods: Sequence[float], workspace=None):
-    """(pml, tvar) numpy arrays for a float64 GPU tensor YLT (blocking)."""
+    """(pml, tvar) numpy arrays for a float64 GPU tensor YLT (blocking).  Without a
+    workspace the binding allocates one through torch."""
     import torch
     py = _dev_ptr(ylt, torch.float64, "ylt")
     rp = np.ascontiguousarray(np.asarray(return_periods, dtype=np.float64))
     pml = np.empty(rp.shape[0], np.float64)
     tvar = np.empty(rp.shape[0], np.float64)
-    pw, nw = (None, 0) if workspace is None else (_dev_ptr(workspace, torch.uint8, "workspace"), workspace.numel())
+    workspace, pw = _workspace(ylt, workspace)     # blocking call: a torch workspace may go after it
     _check(_lib.ara_risk_measures(ctx.ptr, py, ylt.numel(), ARA_MEM_DEVICE, rp.ctypes.data_as(_P), rp.shape[0],
-                                  pml.ctypes.data_as(_P), tvar.ctypes.data_as(_P), pw, nw), ctx, "ara_risk_measures")
+                                  pml.ctypes.data_as(_P), tvar.ctypes.data_as(_P), pw, workspace.numel()), ctx,
+           "ara_risk_measures")
     return pml, tvar
 
 

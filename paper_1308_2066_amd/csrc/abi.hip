@@ -80,6 +80,7 @@ struct ara_layer {
     EltDesc *d_descs;    // device copy of the member ELTs' descriptors
     int64_t max_pairs;
     LayerTables t;
+    uint64_t terms_gen = 0;   // incremented by every ara_layer_set_terms
 };
 
 static constexpr size_t kStageDoubles = 512;   // 2 x 256 return periods
@@ -728,6 +729,7 @@ extern "C" ara_status ara_layer_set_terms(ara_ctx *c, ara_layer *L, const ara_la
     if (ara_check_layer_terms(terms) != ARA_OK) return fail(c, ARA_E_BAD_TERMS, "layer: invalid layer terms");
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     L->terms = *terms;
+    L->terms_gen++;
     return layer_enqueue_filter(L);
 }
 
@@ -1103,6 +1105,8 @@ struct ara_batch {
     std::vector<BatchJob> hjobs;
     std::vector<int64_t> mean_len;   // per job: occurrences per trial of its YET (at least 1)
     std::vector<std::pair<TiledArgs, int>> tiled;   // jobs run by the tiled kernel, with their grids
+    std::vector<int32_t> tiled_job;  // the job of each entry of `tiled`
+    std::vector<uint64_t> terms_gen; // per job: its layer's terms generation when last uploaded
     std::string shape;               // key of the tuning cache
     BatchJob *d_jobs = nullptr;
     BatchItem *d_items = nullptr;
@@ -1231,8 +1235,11 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
         h.a.qcap = tl.qcap;
         h.mode = batch_mode(tl, h.a.ids24 != nullptr);
         h.placement = tl.placement;
-        if (h.mode == kModeTiled && jb.trial_end > jb.trial_begin)
+        if (h.mode == kModeTiled && jb.trial_end > jb.trial_begin) {
             b->tiled.emplace_back(tiled_args(jb.yet, jb.layer, jb.trial_begin, jb.trial_end, jb.ylt, tl.grid), tl.grid);
+            b->tiled_job.push_back(j);
+        }
+        b->terms_gen.push_back(jb.layer->terms_gen);
         b->jobs.push_back(jb);
         b->hjobs.push_back(h);
         b->mean_len.push_back(std::max<int64_t>(1, int64_t(std::llround(mean))));
@@ -1260,9 +1267,11 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
 
 // First run: time each candidate split (every candidate computes the same results),
 // keep the fastest for this batch shape, then capture the launch in a graph that
-// later runs replay on the context's stream.
-static ara_status batch_tune(ara_batch *b) {
+// later runs replay on the context's stream.  *computed: whether the timed runs
+// wrote every job's YLT (not so when the shape was already tuned on this context).
+static ara_status batch_tune(ara_batch *b, bool *computed) {
     ara_ctx *c = b->ctx;
+    *computed = false;
     auto it = c->tuned.find(b->shape);
     if (it != c->tuned.end()) {
         b->interleave = it->second.second;
@@ -1306,6 +1315,7 @@ static ara_status batch_tune(ara_batch *b) {
     if (s != ARA_OK) return s;
     s = sync_and_check(c);
     if (s != ARA_OK) return s;
+    *computed = true;
     c->tuned[b->shape] = best;
     b->interleave = best.second;
     return batch_set_items(b, best.first);
@@ -1325,17 +1335,59 @@ static ara_status batch_capture(ara_batch *b) {
     return e == hipSuccess ? ARA_OK : hip_fail(c, e, "batch graph");
 }
 
+// Layer terms are copied into the job descriptors and the tiled launches' arguments:
+// after ara_layer_set_terms on a member layer, refresh both (and re-capture the graph,
+// whose tiled launches hold their arguments by value).
+static ara_status batch_refresh_terms(ara_batch *b) {
+    ara_ctx *c = b->ctx;
+    bool changed = false;
+    for (size_t j = 0; j < b->jobs.size(); ++j) {
+        const ara_layer *L = b->jobs[j].layer;
+        if (L->terms_gen == b->terms_gen[j]) continue;
+        changed = true;
+        b->terms_gen[j] = L->terms_gen;
+        TrialArgs &a = b->hjobs[j].a;
+        a.occ_r = L->terms.occ_retention;
+        a.occ_l = L->terms.occ_limit;
+        a.agg_r = L->terms.agg_retention;
+        a.agg_l = L->terms.agg_limit;
+    }
+    if (!changed) return ARA_OK;
+    for (size_t k = 0; k < b->tiled.size(); ++k) {
+        const ara_layer *L = b->jobs[size_t(b->tiled_job[k])].layer;
+        b->tiled[k].first.agg_r = L->terms.agg_retention;
+        b->tiled[k].first.agg_l = L->terms.agg_limit;
+    }
+    // earlier runs on the stream may still read the descriptors
+    HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "stream synchronize");
+    HIP_OR_RETURN(c, hipMemcpy(b->d_jobs, b->hjobs.data(), b->hjobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice),
+                  "batch jobs upload");
+    if (b->exec && !b->tiled.empty()) {
+        (void)hipGraphExecDestroy(b->exec);
+        (void)hipGraphDestroy(b->graph);
+        b->exec = nullptr;
+        b->graph = nullptr;
+        if (b->cap) (void)hipStreamDestroy(b->cap);
+        b->cap = nullptr;
+        return batch_capture(b);
+    }
+    return ARA_OK;
+}
+
 extern "C" ara_status ara_batch_run(ara_batch *b) {
     if (!b) return ARA_E_INVALID_ARG;
     ara_ctx *c = b->ctx;
     if (b->jobs.empty()) return ARA_OK;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    ara_status s = batch_refresh_terms(b);
+    if (s != ARA_OK) return s;
     if (!b->exec) {
-        ara_status s = batch_tune(b);
+        bool computed = false;
+        s = batch_tune(b, &computed);
         if (s != ARA_OK) return s;
         s = batch_capture(b);
         if (s != ARA_OK) return s;
-        return ARA_OK;   // the tuning runs already computed every job
+        if (computed) return ARA_OK;   // the tuning runs already computed every job
     }
     HIP_OR_RETURN(c, hipGraphLaunch(b->exec, c->stream), "batch graph launch");
     return ARA_OK;

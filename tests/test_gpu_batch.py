@@ -255,3 +255,68 @@ def test_batch_risk_every_lds_sort_size(A, S, gpu_ctx):
             A.ara_batch_release(b)
     finally:
         an.release()
+
+
+def test_second_batch_of_a_tuned_shape_computes_on_its_first_run(A, S, gpu_ctx):
+    """Two batches of the same shape on one context: the second takes the first's tuned
+    schedule (no tuning runs) and still writes every YLT on its first run."""
+    import torch
+    rng = np.random.default_rng(11)
+    w = _edge(rng, list(rng.integers(50, 900, size=700)), catalog=7000)
+    an = S.open_analysis(gpu_ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms)
+    try:
+        specs = [(0, w.n_trials), (5, 333)]
+        want = [_plain(A, gpu_ctx, an.yet, an.layer, t0, t1) for t0, t1 in specs]
+        for rep in range(2):
+            _say(f"same-shape batch {rep}")
+            outs = [torch.full((t1 - t0,), math.nan, dtype=torch.float64, device="cuda") for t0, t1 in specs]
+            b = A.ara_batch_create(gpu_ctx, [(an.yet, an.layer, t0, t1, o) for (t0, t1), o in zip(specs, outs)])
+            try:
+                A.ara_batch_run(b)
+                A.ara_sync(gpu_ctx)
+                for k, o in enumerate(outs):
+                    assert o.cpu().numpy().tobytes() == want[k].tobytes(), (rep, k)
+            finally:
+                A.ara_batch_release(b)
+    finally:
+        an.release()
+
+
+def test_set_terms_between_batch_runs(A, S, gpu_ctx):
+    """Re-pricing a member layer (ara_layer_set_terms) between runs of a batch: the next
+    run uses the new occurrence and aggregate terms, for a dense-table job and a tiled
+    job alike (each equal to a plain launch with the new terms, bit for bit)."""
+    import torch
+    small = synth.workload_plain_small()
+    big = synth.workload_paper_scale(n_trials=6_000, catalog=200_000, n_elts=4, nnz=30_000)
+    a1 = S.open_analysis(gpu_ctx, small.event_ids, small.trial_offsets, small.catalog_size, small.elts,
+                         small.layer_terms)
+    a2 = S.open_analysis(gpu_ctx, big.event_ids, big.trial_offsets, big.catalog_size, big.elts,
+                         (1e5, 5e6, 1e8, math.inf))
+    try:
+        assert A.ara_yet_info(a2.yet)[2] == 2, "the second job should take the tiled kernel"
+        specs = [(a1, 0, small.n_trials), (a2, 0, big.n_trials), (a2, 17, 4000)]
+        outs = [torch.full((t1 - t0,), math.nan, dtype=torch.float64, device="cuda") for _, t0, t1 in specs]
+        b = A.ara_batch_create(gpu_ctx, [(an.yet, an.layer, t0, t1, o) for (an, t0, t1), o in zip(specs, outs)])
+        try:
+            terms_seq = [None, ((2e4, 2e6, 1e5, 4e6), (5e4, 1e7, 3e8, 2e8)), ((0.0, math.inf, 0.0, math.inf),) * 2]
+            for rep, terms in enumerate(terms_seq):
+                _say(f"batch re-priced {rep}")
+                if terms is not None:
+                    A.ara_layer_set_terms(gpu_ctx, a1.layer, terms[0])
+                    A.ara_layer_set_terms(gpu_ctx, a2.layer, terms[1])
+                for o in outs:
+                    o.fill_(math.nan)
+                A.ara_batch_run(b)
+                A.ara_sync(gpu_ctx)
+                for k, ((an, t0, t1), o) in enumerate(zip(specs, outs)):
+                    assert o.cpu().numpy().tobytes() == _plain(A, gpu_ctx, an.yet, an.layer, t0, t1).tobytes(), (rep, k)
+            # the last terms pass everything through: the YLT is the summed gross losses
+            ref = oracle.analyze_workload(big.with_terms((0.0, math.inf, 0.0, math.inf)), threads=oracle.max_threads())
+            got = outs[1].cpu().numpy()
+            assert np.all(np.abs(got - ref["ylt"]) <= 1e-12 * np.maximum(np.abs(ref["ylt"]), ref["occ_total"]))
+        finally:
+            A.ara_batch_release(b)
+    finally:
+        a1.release()
+        a2.release()
