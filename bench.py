@@ -456,7 +456,8 @@ def bench_serving(args):
             res_s.append((pml, tvar))
         th.join()
         wall_s = time.perf_counter() - t_start
-        iters, done, most, slots = ara.ara_server_stats(srv)
+        st = ara.ara_server_stats(srv)
+        iters, most, slots = st["iterations"], st["max_in_iteration"], st["slots"]
         ara.ara_server_release(srv)
         # plain per-request launches, same arrival trace
         lat_p, res_p = [], []
@@ -481,7 +482,8 @@ def bench_serving(args):
             f"p99 {q(lat_p, 99):.3f} ms; identical={same}")
         lines.append({"rate_per_s": rate, "requests": len(reqs),
                       "server": {"p50_ms": q(lat_s, 50), "p99_ms": q(lat_s, 99), "queries_per_s": len(reqs) / wall_s,
-                                 "iterations": iters, "max_per_iteration": most, "slots": slots},
+                                 "iterations": iters, "max_per_iteration": most, "slots": slots,
+                                 "max_in_flight": st["max_in_flight"], "held_for_memory": st["held"]},
                       "plain": {"p50_ms": q(lat_p, 50), "p99_ms": q(lat_p, 99), "queries_per_s": len(reqs) / wall_p},
                       "identical_results": bool(same), "trial_events_per_request": te / len(reqs)})
     h.release()

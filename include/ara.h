@@ -377,33 +377,47 @@ ara_status ara_batch_release(ara_batch *batch);
  * A pricing server (real-time pricing of layers, Section I and Section IV) keeps one
  * YET and a pool of ELTs resident and answers requests -- a layer made of pool ELTs,
  * its terms and a trial range -- with PML and TVaR at the server's return periods.
- * A worker thread batches requests as they arrive: each iteration admits queued
- * requests in arrival order into free slots (their number bounded by max_batch and by
- * memory_budget / the bytes one slot holds), builds their layers' tables in place,
- * runs all of them in one batched launch, computes their risk measures and completes
- * them; requests arriving meanwhile wait for the next iteration (continuous
- * batching).  Every result equals that of the same analysis run alone (ara_layer_create
- * over the same pool ELTs + ara_analyze + ara_risk_measures) bit for bit.
- * The server works on its own stream and error word; the context's options at
+ *
+ * Continuous batching: a worker thread keeps two lanes, each with its own stream,
+ * slots (a layer's tables each) and staging.  Whenever a lane is free and requests are
+ * queued, it admits them in arrival order into that lane's free slots and enqueues one
+ * iteration for them -- their layers' tables built in place, all their YLTs in one
+ * batched launch, their risk measures, the copy of the results to the host -- without
+ * waiting for the other lane's iteration: requests that arrive while one iteration is
+ * on the GPU join the next, which runs beside it.  Iterations complete in launch order.
+ *
+ * Admission by memory: memory_budget bytes (0 = a quarter of free HBM) hold the slots'
+ * tables (2 lanes x slots_per_lane x slot_bytes, at most half of the budget, and at
+ * most max_batch slots per lane) and an arena for the YLTs of admitted requests (the
+ * rest).  A request is admitted when its lane has a free slot and its own YLT (8 bytes
+ * per trial of its range) fits in the arena beside those of the requests in flight;
+ * otherwise it, and every request after it, waits for an iteration to complete.
+ *
+ * Every result equals that of the same analysis run alone (ara_layer_create over the
+ * same pool ELTs + ara_analyze + ara_risk_measures) bit for bit: each request runs the
+ * same device code over the same inputs in the same order, whatever it is batched with.
+ * The server works on its own streams and error words; the context's options at
  * ara_server_create apply.  The YET and the pool ELTs must outlive the server. */
 typedef struct ara_server ara_server;
 
 typedef struct ara_server_config {
-    int32_t max_batch;              /* requests per iteration, >= 1                        */
-    int64_t memory_budget;          /* bytes for slots (tables + YLT); 0 = 1/4 of free HBM  */
-    int32_t n_rp;                   /* return periods of every request, 1..16               */
-    const double *return_periods;   /* n_rp values >= 1 (copied)                            */
+    int32_t max_batch;              /* slots per lane (requests per iteration), >= 1            */
+    int64_t memory_budget;          /* bytes for slots' tables + the YLT arena; 0 = 1/4 of free HBM */
+    int32_t n_rp;                   /* return periods of every request, 1..16                   */
+    const double *return_periods;   /* n_rp values >= 1 (copied)                                */
 } ara_server_config;
 
 /* Errors: ARA_E_INVALID_ARG (bad config, handles of another context, an empty pool or
- * one ELT of another catalog), ARA_E_OOM (no slot fits the budget), ARA_E_DEVICE. */
+ * one ELT of another catalog), ARA_E_OOM (the budget holds no two slots and an arena,
+ * or device memory ran out), ARA_E_DEVICE. */
 ara_status ara_server_create(ara_ctx *ctx, const ara_yet *yet, ara_elt *const *pool, int32_t n_pool,
                              const ara_server_config *config, ara_server **out);
 
 /* Queues a request: ELTs pool[elt_index[0..n_elts)] (n_elts >= 1, in that order),
  * layer terms, and trials [trial_begin, trial_end) (non-empty).  Returns at once with
  * a ticket.  The pool ELTs' tables must not be rebuilt while the server runs.
- * Errors: ARA_E_INVALID_ARG, ARA_E_BAD_TERMS, ARA_E_BUSY (the server is stopping). */
+ * Errors: ARA_E_INVALID_ARG, ARA_E_BAD_TERMS, ARA_E_OOM (its YLT alone is larger than
+ * the arena), ARA_E_BUSY (the server is stopping). */
 ara_status ara_server_submit(ara_server *server, const int32_t *elt_index, int32_t n_elts,
                              const ara_layer_terms *terms, int64_t trial_begin, int64_t trial_end,
                              uint64_t *ticket);
@@ -414,10 +428,20 @@ ara_status ara_server_submit(ara_server *server, const int32_t *elt_index, int32
  * included).  ARA_E_INVALID_ARG for an unknown ticket. */
 ara_status ara_server_wait(ara_server *server, uint64_t ticket, double *pml, double *tvar, double *seconds);
 
-/* Iterations run, requests completed, the largest number of requests in one iteration,
- * and the slot count.  Any output pointer may be NULL. */
-ara_status ara_server_stats(ara_server *server, int64_t *iterations, int64_t *completed, int32_t *max_in_iteration,
-                            int32_t *slots);
+typedef struct ara_server_stats_t {
+    int64_t iterations;        /* iterations completed                                         */
+    int64_t completed;         /* requests completed                                           */
+    int64_t held;              /* times the next queued request waited for arena space          */
+    int32_t max_in_iteration;  /* most requests in one iteration                               */
+    int32_t max_in_flight;     /* most requests admitted and not yet completed at one time      */
+    int32_t slots;             /* slots over both lanes                                        */
+    int32_t pad_;
+    int64_t slot_bytes;        /* device bytes of one slot's tables                            */
+    int64_t arena_bytes;       /* device bytes of the YLT arena                                */
+} ara_server_stats_t;
+
+/* Counters and sizes of the server.  Errors: ARA_E_INVALID_ARG (NULL). */
+ara_status ara_server_stats(ara_server *server, ara_server_stats_t *stats);
 
 /* Completes every queued request, stops the worker and frees the server. */
 ara_status ara_server_release(ara_server *server);

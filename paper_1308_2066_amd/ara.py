@@ -81,6 +81,12 @@ class ara_job(ctypes.Structure):
                 ("trial_end", ctypes.c_int64), ("ylt", ctypes.c_void_p)]
 
 
+class ara_server_stats_t(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("completed", ctypes.c_int64), ("held", ctypes.c_int64),
+                ("max_in_iteration", ctypes.c_int32), ("max_in_flight", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("slot_bytes", ctypes.c_int64), ("arena_bytes", ctypes.c_int64)]
+
+
 class ara_server_config(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("memory_budget", ctypes.c_int64), ("n_rp", ctypes.c_int32),
                 ("return_periods", ctypes.c_void_p)]
@@ -134,8 +140,7 @@ _SIGS = {
     "ara_server_submit": (_ST, [_P, _P, _I32, ctypes.POINTER(ara_layer_terms), _I64, _I64,
                                 ctypes.POINTER(ctypes.c_uint64)]),
     "ara_server_wait": (_ST, [_P, ctypes.c_uint64, _P, _P, ctypes.POINTER(_D)]),
-    "ara_server_stats": (_ST, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32),
-                               ctypes.POINTER(_I32)]),
+    "ara_server_stats": (_ST, [_P, _P]),
     "ara_server_release": (_ST, [_P]),
 }
 for _name, (_res, _args) in _SIGS.items():
@@ -537,12 +542,12 @@ def ara_server_wait(s: Server, ticket: int):
     return pml, tvar, float(sec.value)
 
 
-def ara_server_stats(s: Server):
-    """(iterations, completed, max requests in one iteration, slots)."""
-    it, done, mx, sl = _I64(), _I64(), _I32(), _I32()
-    _check(_lib.ara_server_stats(s.ptr, ctypes.byref(it), ctypes.byref(done), ctypes.byref(mx), ctypes.byref(sl)),
-           s.ctx, "ara_server_stats")
-    return int(it.value), int(done.value), int(mx.value), int(sl.value)
+def ara_server_stats(s: Server) -> dict:
+    """Counters and sizes: iterations, completed, held, max_in_iteration, max_in_flight,
+    slots, slot_bytes, arena_bytes."""
+    st = ara_server_stats_t()
+    _check(_lib.ara_server_stats(s.ptr, ctypes.byref(st)), s.ctx, "ara_server_stats")
+    return {k: int(getattr(st, k)) for k, _ in ara_server_stats_t._fields_ if k != "pad_"}
 
 
 def ara_server_release(s: Server):

@@ -1048,21 +1048,49 @@ extern "C" ara_status ara_sort_desc(ara_ctx *c, const double *in, int64_t n, dou
     return s;
 }
 
+// Ranks of the return periods for n losses (host); ARA_E_INVALID_ARG for a bad period.
+static ara_status risk_ranks(ara_ctx *c, int64_t n, const double *rps, int32_t n_rp, std::vector<int64_t> &ks) {
+    if (size_t(n_rp) * 2 > kStageDoubles) return fail(c, ARA_E_INVALID_ARG, "at most %zu return periods", kStageDoubles / 2);
+    ks.resize(static_cast<size_t>(n_rp));
+    for (int32_t i = 0; i < n_rp; ++i)
+        if (ara_return_period_rank(n, rps[i], &ks[size_t(i)]) != ARA_OK)
+            return fail(c, ARA_E_INVALID_ARG, "return period %g invalid (must be >= 1)", rps[i]);
+    return ARA_OK;
+}
+
+// Sort of the device YLT dy into workspace w, PML/TVaR of the ranks, results to the
+// host (blocking).  Allocates nothing.
+static ara_status risk_on_device(ara_ctx *c, const double *dy, int64_t n, const std::vector<int64_t> &ks, double *pml,
+                                 double *tvar, void *w) {
+    const int32_t n_rp = int32_t(ks.size());
+    hipError_t e = launch_sort_desc_keys(dy, n, w, c->stream, c->h_plan);
+    if (e == hipSuccess && n_rp > 0) e = launch_risk(w, n, ks.data(), n_rp, c->d_out, c->stream);
+    if (e == hipSuccess && n_rp > 0)
+        e = hipMemcpyAsync(c->h_out, c->d_out, size_t(2 * n_rp) * 8, hipMemcpyDeviceToHost, c->stream);
+    ara_status s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "risk measures");
+    if (s != ARA_OK) return s;
+    for (int32_t base = 0; base < n_rp; base += 16) {
+        const int32_t m = std::min<int32_t>(16, n_rp - base);
+        for (int32_t i = 0; i < m; ++i) {
+            pml[base + i] = c->h_out[2 * base + i];
+            tvar[base + i] = c->h_out[2 * base + m + i];
+        }
+    }
+    return ARA_OK;
+}
+
 extern "C" ara_status ara_risk_measures(ara_ctx *c, const double *ylt, int64_t n, ara_mem mem, const double *rps,
                                        int32_t n_rp, double *pml, double *tvar, void *ws, size_t ws_bytes) {
     if (!c || n < 0 || n_rp < 0 || (n_rp > 0 && (!rps || !pml || !tvar)) || (mem != ARA_MEM_HOST && mem != ARA_MEM_DEVICE))
         return ARA_E_INVALID_ARG;
     if (n == 0) return fail(c, ARA_E_EMPTY, "risk measures of an empty YLT");
     if (!ylt) return ARA_E_INVALID_ARG;
-    if (size_t(n_rp) * 2 > kStageDoubles) return fail(c, ARA_E_INVALID_ARG, "at most %zu return periods", kStageDoubles / 2);
-    std::vector<int64_t> ks(static_cast<size_t>(n_rp));
-    for (int32_t i = 0; i < n_rp; ++i)
-        if (ara_return_period_rank(n, rps[i], &ks[size_t(i)]) != ARA_OK)
-            return fail(c, ARA_E_INVALID_ARG, "return period %g invalid (must be >= 1)", rps[i]);
+    std::vector<int64_t> ks;
+    ara_status s = risk_ranks(c, n, rps, n_rp, ks);
+    if (s != ARA_OK) return s;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     const double *dy = ylt;
     double *tmp = nullptr;
-    ara_status s = ARA_OK;
     if (mem == ARA_MEM_HOST) {
         s = dev_alloc(c, &tmp, size_t(n) * 8, "ylt upload");
         if (s != ARA_OK) return s;
@@ -1076,22 +1104,7 @@ extern "C" ara_status ara_risk_measures(ara_ctx *c, const double *ylt, int64_t n
     void *w = nullptr;
     bool owned = false;
     s = workspace_for(c, n, ws, ws_bytes, &w, &owned);
-    if (s == ARA_OK) {
-        hipError_t e = launch_sort_desc_keys(dy, n, w, c->stream, c->h_plan);
-        if (e == hipSuccess && n_rp > 0) e = launch_risk(w, n, ks.data(), n_rp, c->d_out, c->stream);
-        if (e == hipSuccess && n_rp > 0)
-            e = hipMemcpyAsync(c->h_out, c->d_out, size_t(2 * n_rp) * 8, hipMemcpyDeviceToHost, c->stream);
-        s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "risk measures");
-        if (s == ARA_OK) {
-            for (int32_t base = 0; base < n_rp; base += 16) {
-                const int32_t m = std::min<int32_t>(16, n_rp - base);
-                for (int32_t i = 0; i < m; ++i) {
-                    pml[base + i] = c->h_out[2 * base + i];
-                    tvar[base + i] = c->h_out[2 * base + m + i];
-                }
-            }
-        }
-    }
+    if (s == ARA_OK) s = risk_on_device(c, dy, n, ks, pml, tvar, w);
     if (owned || tmp) (void)hipStreamSynchronize(c->stream);
     if (owned) dev_free(w);
     dev_free(tmp);
@@ -1536,42 +1549,81 @@ extern "C" ara_status ara_batch_release(ara_batch *b) {
 }
 
 // ------------------------------------------------------------------ serving
+// The worker keeps two lanes -- a private context (stream, error word, staging) with its
+// own slot layers, job and item arrays and sort workspace each -- and launches an
+// iteration on a free lane as soon as requests are queued, without waiting for the
+// other lane's iteration: requests that arrive while one iteration runs on the GPU are
+// admitted into the next one, whose work is enqueued (and runs) alongside it.  A
+// request's YLT lives in an arena shared by the lanes; it is admitted, in arrival
+// order, when a slot of the lane is free and its YLT fits in the arena.  Iterations
+// complete in launch order (the worker waits on each lane's completion event), so the
+// arena works as a ring: requests take ranges at its head and give them back in the
+// order they took them.
 namespace {
 
 struct ServerRequest {
     std::vector<int32_t> elts;
     ara_layer_terms terms;
     int64_t t0 = 0, t1 = 0;
+    int64_t ylt_off = 0;        // its YLT: arena[ylt_off .. ylt_off + t1 - t0)
     std::vector<double> pml, tvar;
     ara_status status = ARA_OK;
     bool done = false;
     std::chrono::steady_clock::time_point submitted, finished;
 };
 
-struct ServerSlot {
-    ara_layer *L = nullptr;      // tables and a descriptor array for every pool ELT
-    double *ylt = nullptr;       // one YLT of the YET's length
+// Contiguous ranges of doubles taken at the head of a ring and given back oldest first.
+struct YltRing {
+    int64_t cap = 0, head = 0, used = 0;
+    std::deque<int64_t> spans;   // per live range: its length plus the end-of-ring gap skipped for it
+    bool take(int64_t n, int64_t &off) {
+        if (n > cap) return false;
+        if (used == 0) head = 0;
+        const int64_t skip = head + n > cap ? cap - head : 0;
+        if (used + skip + n > cap) return false;
+        off = skip ? 0 : head;
+        head = off + n == cap ? 0 : off + n;
+        used += skip + n;
+        spans.push_back(skip + n);
+        return true;
+    }
+    void give_oldest() {
+        used -= spans.front();
+        spans.pop_front();
+    }
+};
+
+struct ServerLane {
+    ara_ctx *pc = nullptr;            // private context: stream, error word, staging, options
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;        // recorded once the lane's results and error word are on the host
+    std::vector<ara_layer *> slots;   // one request's tables each (member list: every pool ELT)
+    BatchJob *d_jobs = nullptr, *h_jobs = nullptr;
+    BatchItem *d_items = nullptr, *h_items = nullptr;
+    int32_t item_cap = 0;
+    int32_t mode_off[kBatchModes] = {}, mode_cnt[kBatchModes] = {};
+    EltDesc *h_descs = nullptr;       // pinned: every slot's descriptors
+    const double **d_ylts = nullptr, **h_ylts = nullptr;
+    int64_t *d_ns = nullptr, *d_ks = nullptr, *h_nks = nullptr;   // h_nks: ns then ks, pinned
+    double *d_res = nullptr, *h_res = nullptr;                    // [slot][2 * n_rp]
+    void *ws = nullptr;               // radix sort workspace for the YET's length
+    std::vector<ServerRequest *> reqs;   // the iteration in flight (empty: the lane is free)
+    ara_status launch_status = ARA_OK;   // an error while enqueueing it (then its event is not waited on)
 };
 
 }  // namespace
 
 struct ara_server {
     ara_ctx *ctx = nullptr;           // the caller's context (handles, slot layers)
-    ara_ctx *pc = nullptr;            // private context of the worker: stream, error word, options
-    hipStream_t stream = nullptr;
     const ara_yet *yet = nullptr;
     std::vector<ara_elt *> pool;
     std::vector<double> rps;
-    std::vector<ServerSlot> slots;
-    BatchJob *d_jobs = nullptr, *h_jobs = nullptr;
-    BatchItem *d_items = nullptr, *h_items = nullptr;
-    int32_t item_cap = 0;
-    int32_t mode_off[kBatchModes] = {}, mode_cnt[kBatchModes] = {};
-    EltDesc *h_descs = nullptr;       // pinned staging: every slot's descriptors
-    const double **d_ylts = nullptr;
-    int64_t *d_ns = nullptr, *d_ks = nullptr, *h_nks = nullptr;   // h_nks: ns then ks, pinned
-    double *d_res = nullptr, *h_res = nullptr;                    // [slot][2 * n_rp]
-    void *ws = nullptr;               // radix sort workspace for the YET's length
+    ServerLane lanes[2];
+    std::deque<int> busy;             // lanes in flight, in launch order
+    double *arena = nullptr;          // YLTs of admitted requests
+    YltRing ring;
+    int32_t slots_per_lane = 0;
+    int64_t slot_bytes = 0;
     std::thread worker;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -1579,28 +1631,28 @@ struct ara_server {
     std::map<uint64_t, ServerRequest *> live;
     uint64_t next_ticket = 1;
     bool stopping = false;
-    int64_t iterations = 0, completed = 0;
-    int32_t max_seen = 0;
+    int64_t iterations = 0, completed = 0, held = 0;
+    int32_t max_seen = 0, in_flight = 0, max_in_flight = 0;
 };
 
 static constexpr int64_t kServerEventsPerItem = int64_t(1) << 18;
 
-// One iteration on the worker's stream: layers, one batched launch, risk measures.
-static ara_status server_iteration(ara_server *sv, const std::vector<ServerRequest *> &reqs) {
-    ara_ctx *pc = sv->pc;
+// Enqueues one iteration of requests `take` on lane `ln`: their layers' tables, one
+// batched launch of their YLTs, their PML/TVaR, the copies of results and error word to
+// the host, and the lane's completion event.  Nothing here waits for the device.
+static ara_status server_launch(ara_server *sv, ServerLane &ln, const std::vector<ServerRequest *> &take) {
+    ara_ctx *pc = ln.pc;
     const int32_t nr = int32_t(sv->rps.size());
     const size_t np = sv->pool.size();
-    const int64_t mean = sv->yet->n_trials ? std::max<int64_t>(1, int64_t(std::llround(double(sv->yet->n_events) /
-                                                                                         double(sv->yet->n_trials))))
-                                           : 1;
-    std::vector<BatchItem> items;
+    const int32_t nj = int32_t(take.size());
+    const double mean_len = double(sv->yet->n_events) / double(std::max<int64_t>(1, sv->yet->n_trials));
     std::vector<std::pair<TiledArgs, int>> tiled;
-    for (size_t i = 0; i < reqs.size(); ++i) {
-        ServerRequest *r = reqs[i];
-        ara_layer *L = sv->slots[i].L;
-        EltDesc *hd = sv->h_descs + i * np;
-        // the slot layer keeps its member list (every pool ELT, for the ELTs' user counts);
-        // its descriptors, precision and terms become the request's
+    for (int32_t i = 0; i < nj; ++i) {
+        ServerRequest *r = take[size_t(i)];
+        ara_layer *L = ln.slots[size_t(i)];
+        EltDesc *hd = ln.h_descs + size_t(i) * np;
+        // the slot layer keeps its member list (every pool ELT, for the ELTs' user
+        // counts); its descriptors, precision and terms become the request's
         bool all_f32 = !r->elts.empty();
         for (size_t k = 0; k < r->elts.size(); ++k) {
             const ara_elt *e = sv->pool[size_t(r->elts[k])];
@@ -1610,123 +1662,245 @@ static ara_status server_iteration(ara_server *sv, const std::vector<ServerReque
         L->f32 = all_f32;
         L->terms = r->terms;
         const int n = int(r->elts.size());
-        hipError_t e = hipSuccess;
-        if (n > 0) e = hipMemcpyAsync(L->d_descs, hd, sizeof(EltDesc) * size_t(n), hipMemcpyHostToDevice, sv->stream);
+        hipError_t e = hipMemcpyAsync(L->d_descs, hd, sizeof(EltDesc) * size_t(n), hipMemcpyHostToDevice, ln.stream);
         if (e == hipSuccess)
             e = launch_layer_tables(L->d_descs, n, L->catalog, L->f32, r->terms.occ_retention, r->terms.occ_limit, L->t,
-                                    sv->stream);
+                                    ln.stream);
         if (e != hipSuccess) return hip_fail(pc, e, "server layer build");
         TrialLaunch tl{};
-        ara_status s = plan_trial(pc, L, r->t1 - r->t0, double(sv->yet->n_events) / double(std::max<int64_t>(1, sv->yet->n_trials)), tl,
-                                  sv->yet->ids16 ? 1 : 0);
+        ara_status s = plan_trial(pc, L, r->t1 - r->t0, mean_len, tl, sv->yet->ids16 ? 1 : 0);
         if (s != ARA_OK) return s;
-        BatchJob &h = sv->h_jobs[i];
-        h.a = trial_args(sv->yet, L, r->t0, r->t1, sv->slots[i].ylt);
+        double *ylt = sv->arena + r->ylt_off;
+        BatchJob &h = ln.h_jobs[i];
+        h.a = trial_args(sv->yet, L, r->t0, r->t1, ylt);
         h.a.err = pc->d_err;
         h.a.qcap = tl.qcap;
         h.mode = batch_mode(tl, h.a.ids24 != nullptr);
         h.placement = tl.placement;
-        if (h.mode == kModeTiled)
-            tiled.emplace_back(tiled_args(sv->yet, L, r->t0, r->t1, sv->slots[i].ylt, tl.grid), tl.grid);
+        if (h.mode == kModeTiled) tiled.emplace_back(tiled_args(sv->yet, L, r->t0, r->t1, ylt, tl.grid), tl.grid);
+        ln.h_ylts[i] = ylt;
     }
+    std::vector<BatchItem> items;
     {
-        std::vector<BatchJob> hj(sv->h_jobs, sv->h_jobs + reqs.size());
-        std::vector<int64_t> tb, te, ml(reqs.size(), mean);
-        for (ServerRequest *r : reqs) {
+        std::vector<BatchJob> hj(ln.h_jobs, ln.h_jobs + nj);
+        std::vector<int64_t> tb, te, ml(size_t(nj), std::max<int64_t>(1, int64_t(std::llround(mean_len))));
+        for (ServerRequest *r : take) {
             tb.push_back(r->t0);
             te.push_back(r->t1);
         }
-        items = group_items(hj, tb.data(), te.data(), ml, kServerEventsPerItem, sv->mode_off, sv->mode_cnt);
+        items = group_items(hj, tb.data(), te.data(), ml, kServerEventsPerItem, ln.mode_off, ln.mode_cnt);
     }
-    const int32_t nj = int32_t(reqs.size());
-    if (int32_t(items.size()) > sv->item_cap) return fail(pc, ARA_E_OOM, "server: %zu work items", items.size());
-    std::copy(items.begin(), items.end(), sv->h_items);
-    hipError_t e = hipMemcpyAsync(sv->d_jobs, sv->h_jobs, sizeof(BatchJob) * size_t(nj), hipMemcpyHostToDevice, sv->stream);
+    if (int32_t(items.size()) > ln.item_cap) return fail(pc, ARA_E_OOM, "server: %zu work items", items.size());
+    std::copy(items.begin(), items.end(), ln.h_items);
+    hipError_t e = hipMemcpyAsync(ln.d_jobs, ln.h_jobs, sizeof(BatchJob) * size_t(nj), hipMemcpyHostToDevice, ln.stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(sv->d_items, sv->h_items, sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice, sv->stream);
+        e = hipMemcpyAsync(ln.d_items, ln.h_items, sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice, ln.stream);
     if (e == hipSuccess)
-        e = launch_grouped(sv->d_jobs, sv->d_items, sv->mode_off, sv->mode_cnt, pc->n_cu, true, sv->stream, tiled);
-    // risk measures: ranks per request, short YLTs in one launch, long ones one by one
-    int64_t *hn = sv->h_nks, *hk = sv->h_nks + sv->slots.size();
-    for (int32_t i = 0; i < nj && e == hipSuccess; ++i) {
-        const int64_t n = reqs[size_t(i)]->t1 - reqs[size_t(i)]->t0;
+        e = launch_grouped(ln.d_jobs, ln.d_items, ln.mode_off, ln.mode_cnt, pc->n_cu, true, ln.stream, tiled);
+    // risk measures: ranks per request, short YLTs in one launch, long ones by the radix
+    // sort (every pass launched: no host read of its plan, so nothing waits here)
+    int64_t *hn = ln.h_nks, *hk = ln.h_nks + sv->slots_per_lane;
+    for (int32_t i = 0; i < nj; ++i) {
+        const int64_t n = take[size_t(i)]->t1 - take[size_t(i)]->t0;
         hn[i] = n;
         for (int32_t r = 0; r < nr; ++r) (void)ara_return_period_rank(n, sv->rps[size_t(r)], &hk[size_t(i) * nr + r]);
     }
-    if (e == hipSuccess) e = hipMemcpyAsync(sv->d_ns, hn, 8 * size_t(nj), hipMemcpyHostToDevice, sv->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(sv->d_ks, hk, 8 * size_t(nj) * nr, hipMemcpyHostToDevice, sv->stream);
-    if (e == hipSuccess) e = launch_risk_batch(sv->d_ylts, sv->d_ns, sv->d_ks, nj, nr, sv->d_res, sv->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ln.d_ylts, ln.h_ylts, sizeof(double *) * size_t(nj), hipMemcpyHostToDevice, ln.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ln.d_ns, hn, 8 * size_t(nj), hipMemcpyHostToDevice, ln.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ln.d_ks, hk, 8 * size_t(nj) * nr, hipMemcpyHostToDevice, ln.stream);
+    if (e == hipSuccess) e = launch_risk_batch(ln.d_ylts, ln.d_ns, ln.d_ks, nj, nr, ln.d_res, ln.stream);
     for (int32_t i = 0; i < nj && e == hipSuccess; ++i) {
         if (hn[i] <= kRiskLdsKeys) continue;
-        e = launch_sort_desc_keys(sv->slots[size_t(i)].ylt, hn[i], sv->ws, sv->stream, pc->h_plan);
-        if (e == hipSuccess) e = launch_risk(sv->ws, hn[i], &hk[size_t(i) * nr], nr, sv->d_res + size_t(i) * 2 * nr, sv->stream);
+        e = launch_sort_desc_keys(ln.h_ylts[i], hn[i], ln.ws, ln.stream, nullptr);
+        if (e == hipSuccess) e = launch_risk(ln.ws, hn[i], &hk[size_t(i) * nr], nr, ln.d_res + size_t(i) * 2 * nr, ln.stream);
     }
     if (e == hipSuccess)
-        e = hipMemcpyAsync(sv->h_res, sv->d_res, sizeof(double) * 2 * size_t(nr) * nj, hipMemcpyDeviceToHost, sv->stream);
-    if (e != hipSuccess) return hip_fail(pc, e, "server iteration");
-    ara_status s = sync_and_check(pc);
-    if (s != ARA_OK) return s;
-    for (int32_t i = 0; i < nj; ++i) {
-        ServerRequest *r = reqs[size_t(i)];
-        r->pml.assign(sv->h_res + size_t(i) * 2 * nr, sv->h_res + size_t(i) * 2 * nr + nr);
-        r->tvar.assign(sv->h_res + size_t(i) * 2 * nr + nr, sv->h_res + size_t(i) * 2 * nr + 2 * nr);
+        e = hipMemcpyAsync(ln.h_res, ln.d_res, sizeof(double) * 2 * size_t(nr) * nj, hipMemcpyDeviceToHost, ln.stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(pc->h_err, pc->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, ln.stream);
+    if (e == hipSuccess) e = hipEventRecord(ln.done, ln.stream);
+    return e == hipSuccess ? ARA_OK : hip_fail(pc, e, "server iteration");
+}
+
+// Completes lane ln's iteration (the oldest in flight; its event has completed, or
+// enqueueing it failed): results to the requests, arena ranges back, the lane free.
+static void server_finish(ara_server *sv, ServerLane &ln) {
+    ara_ctx *pc = ln.pc;
+    const int32_t nr = int32_t(sv->rps.size());
+    ara_status s = ln.launch_status;
+    if (s == ARA_OK) {
+        const hipError_t e = hipEventSynchronize(ln.done);
+        if (e != hipSuccess) s = hip_fail(pc, e, "server iteration");
+    } else {
+        (void)hipStreamSynchronize(ln.stream);
     }
-    return ARA_OK;
+    if (s == ARA_OK && *pc->h_err) s = sync_and_check(pc);   // reports and clears the device error word
+    for (size_t i = 0; i < ln.reqs.size(); ++i) {
+        ServerRequest *r = ln.reqs[i];
+        if (s == ARA_OK) {
+            r->pml.assign(ln.h_res + i * 2 * nr, ln.h_res + i * 2 * nr + nr);
+            r->tvar.assign(ln.h_res + i * 2 * nr + nr, ln.h_res + i * 2 * nr + 2 * nr);
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        const auto now = std::chrono::steady_clock::now();
+        for (ServerRequest *r : ln.reqs) {
+            r->status = s;
+            r->done = true;
+            r->finished = now;
+            sv->ring.give_oldest();
+        }
+        sv->iterations++;
+        sv->completed += int64_t(ln.reqs.size());
+        sv->in_flight -= int32_t(ln.reqs.size());
+    }
+    ln.reqs.clear();
+    sv->cv_done.notify_all();
 }
 
 static void server_loop(ara_server *sv) {
-    (void)hipSetDevice(sv->pc->device);
+    (void)hipSetDevice(sv->ctx->device);
     for (;;) {
-        std::vector<std::pair<uint64_t, ServerRequest *>> take;
-        {
-            std::unique_lock<std::mutex> lk(sv->mu);
-            sv->cv_work.wait(lk, [&] { return sv->stopping || !sv->queue.empty(); });
-            if (sv->queue.empty()) return;   // stopping, nothing left
-            while (!sv->queue.empty() && take.size() < sv->slots.size()) {
-                take.push_back(sv->queue.front());
-                sv->queue.pop_front();
+        bool progressed = false;
+        // the oldest iteration in flight, if its results are on the host (iterations are
+        // completed in launch order: the arena's ranges return in the order taken)
+        if (!sv->busy.empty()) {
+            ServerLane &old = sv->lanes[sv->busy.front()];
+            if (old.launch_status != ARA_OK || hipEventQuery(old.done) != hipErrorNotReady) {
+                server_finish(sv, old);
+                sv->busy.pop_front();
+                progressed = true;
             }
         }
-        std::vector<ServerRequest *> reqs;
-        for (auto &p : take) reqs.push_back(p.second);
-        const ara_status s = server_iteration(sv, reqs);
+        int lane = -1;
+        for (int k = 0; k < 2 && lane < 0; ++k)
+            if (sv->lanes[k].reqs.empty()) lane = k;
+        bool head_held = false;
+        std::vector<ServerRequest *> take;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
-            const auto now = std::chrono::steady_clock::now();
-            for (ServerRequest *r : reqs) {
-                r->status = s;
-                r->done = true;
-                r->finished = now;
+            if (sv->stopping && sv->queue.empty() && sv->busy.empty()) return;
+            // admission in arrival order: a free slot of the lane and room for the YLT
+            while (lane >= 0 && !sv->queue.empty() && int32_t(take.size()) < sv->slots_per_lane) {
+                ServerRequest *r = sv->queue.front().second;
+                if (!sv->ring.take(r->t1 - r->t0, r->ylt_off)) {
+                    head_held = true;
+                    sv->held++;
+                    break;
+                }
+                take.push_back(r);
+                sv->queue.pop_front();
             }
-            sv->iterations++;
-            sv->completed += int64_t(reqs.size());
-            sv->max_seen = std::max(sv->max_seen, int32_t(reqs.size()));
+            sv->in_flight += int32_t(take.size());
+            sv->max_in_flight = std::max(sv->max_in_flight, sv->in_flight);
+            sv->max_seen = std::max(sv->max_seen, int32_t(take.size()));
         }
-        sv->cv_done.notify_all();
+        if (!take.empty()) {
+            ServerLane &ln = sv->lanes[lane];
+            ln.reqs = take;
+            ln.launch_status = server_launch(sv, ln, take);
+            sv->busy.push_back(lane);
+            progressed = true;
+        }
+        if (progressed) continue;
+        if (!sv->busy.empty()) {
+            if (lane >= 0 && !head_held) {
+                // a lane is free and nothing is queued: a new request wakes the worker at
+                // once; otherwise look at the iteration in flight again shortly
+                std::unique_lock<std::mutex> lk(sv->mu);
+                sv->cv_work.wait_for(lk, std::chrono::microseconds(50),
+                                     [&] { return sv->stopping || !sv->queue.empty(); });
+            } else {
+                // both lanes busy, or the next request waits for arena space: only the
+                // oldest iteration's completion can let work proceed
+                const ServerLane &old = sv->lanes[sv->busy.front()];
+                if (old.launch_status == ARA_OK) (void)hipEventSynchronize(old.done);
+            }
+        } else {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_work.wait(lk, [&] { return sv->stopping || !sv->queue.empty(); });
+        }
     }
 }
 
 static void server_free(ara_server *sv) {
-    for (ServerSlot &sl : sv->slots) {
-        if (sl.L) ara_layer_release(sl.L);
-        dev_free(sl.ylt);
+    for (ServerLane &ln : sv->lanes) {
+        for (ara_layer *L : ln.slots)
+            if (L) ara_layer_release(L);
+        dev_free(ln.d_jobs);
+        dev_free(ln.d_items);
+        dev_free(ln.d_ylts);
+        dev_free(ln.d_ns);
+        dev_free(ln.d_ks);
+        dev_free(ln.d_res);
+        dev_free(ln.ws);
+        if (ln.h_jobs) (void)hipHostFree(ln.h_jobs);
+        if (ln.h_items) (void)hipHostFree(ln.h_items);
+        if (ln.h_descs) (void)hipHostFree(ln.h_descs);
+        if (ln.h_ylts) (void)hipHostFree(ln.h_ylts);
+        if (ln.h_nks) (void)hipHostFree(ln.h_nks);
+        if (ln.h_res) (void)hipHostFree(ln.h_res);
+        if (ln.done) (void)hipEventDestroy(ln.done);
+        if (ln.pc) (void)ara_ctx_destroy(ln.pc);
+        if (ln.stream) (void)hipStreamDestroy(ln.stream);
     }
-    dev_free(sv->d_jobs);
-    dev_free(sv->d_items);
-    dev_free(sv->d_ylts);
-    dev_free(sv->d_ns);
-    dev_free(sv->d_ks);
-    dev_free(sv->d_res);
-    dev_free(sv->ws);
-    if (sv->h_jobs) (void)hipHostFree(sv->h_jobs);
-    if (sv->h_items) (void)hipHostFree(sv->h_items);
-    if (sv->h_descs) (void)hipHostFree(sv->h_descs);
-    if (sv->h_nks) (void)hipHostFree(sv->h_nks);
-    if (sv->h_res) (void)hipHostFree(sv->h_res);
-    if (sv->pc) (void)ara_ctx_destroy(sv->pc);
-    if (sv->stream) (void)hipStreamDestroy(sv->stream);
+    dev_free(sv->arena);
     for (auto &p : sv->live) delete p.second;
     delete sv;
+}
+
+// Device bytes of one slot: a layer's tables over the catalog and a descriptor per pool ELT.
+static int64_t server_slot_bytes(int32_t C, int32_t n_pool) {
+    const int64_t nblk = bitmap_blocks(C);
+    return int64_t(C) * 8 * 3 + nblk * (16 + 16 + 4) + int64_t(align16(size_t(nblk) * 2)) +
+           int64_t(align16(size_t(bitmap_supers(int32_t(nblk))) * 4)) + int64_t(sizeof(Tile)) * max_tiles(C) + 64 +
+           int64_t(n_pool) * int64_t(sizeof(EltDesc));
+}
+
+static ara_status server_lane_create(ara_ctx *c, ara_server *sv, ServerLane &ln, int32_t n_pool,
+                                     const ara_server_config *cfg) {
+    const ara_yet *y = sv->yet;
+    const int32_t ns = sv->slots_per_lane;
+    HIP_OR_RETURN(c, hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking), "server stream");
+    HIP_OR_RETURN(c, hipEventCreateWithFlags(&ln.done, hipEventDisableTiming), "server event");
+    ara_status s = ara_ctx_create(c->device, ln.stream, &ln.pc);
+    if (s != ARA_OK) return fail(c, s, "server context: %s", ara_last_error(nullptr));
+    ln.pc->placement = c->placement;
+    ln.pc->block_threads = c->block_threads;
+    ln.pc->grid_per_cu = c->grid_per_cu;
+    ln.pc->trial_mode = c->trial_mode;
+    ln.pc->yet_packing = c->yet_packing;
+    const ara_layer_terms none{0.0, INFINITY, 0.0, INFINITY};
+    ln.slots.assign(size_t(ns), nullptr);
+    for (int32_t i = 0; i < ns && s == ARA_OK; ++i)
+        s = ara_layer_create(c, sv->pool.data(), n_pool, y->catalog, &none, &ln.slots[size_t(i)]);
+    if (s != ARA_OK) return s;
+    // a worst case of work items: every slot with the YET's longest possible range
+    const int64_t per_slot_items = y->n_trials / 16 + 2;
+    ln.item_cap = int32_t(std::min<int64_t>(int64_t(ns) * per_slot_items, int64_t(1) << 30));
+    const size_t nr = size_t(cfg->n_rp);
+    s = dev_alloc(c, &ln.d_jobs, sizeof(BatchJob) * size_t(ns), "server jobs");
+    if (s == ARA_OK) s = dev_alloc(c, &ln.d_items, sizeof(BatchItem) * size_t(ln.item_cap), "server items");
+    if (s == ARA_OK) s = dev_alloc(c, &ln.d_ylts, sizeof(double *) * size_t(ns), "server ylt list");
+    if (s == ARA_OK) s = dev_alloc(c, &ln.d_ns, 8 * size_t(ns), "server sizes");
+    if (s == ARA_OK) s = dev_alloc(c, &ln.d_ks, 8 * size_t(ns) * nr, "server ranks");
+    if (s == ARA_OK) s = dev_alloc(c, &ln.d_res, 16 * size_t(ns) * nr, "server results");
+    if (s == ARA_OK) s = dev_alloc(c, &ln.ws, sort_workspace_bytes(y->n_trials), "server sort workspace");
+    if (s != ARA_OK) return s;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void **>(&ln.h_jobs), sizeof(BatchJob) * size_t(ns), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&ln.h_items), sizeof(BatchItem) * size_t(ln.item_cap),
+                          hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&ln.h_descs), sizeof(EltDesc) * size_t(ns) * sv->pool.size(),
+                          hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&ln.h_ylts), sizeof(double *) * size_t(ns), hipHostMallocDefault);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void **>(&ln.h_nks), 8 * size_t(ns) * (1 + nr), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void **>(&ln.h_res), 16 * size_t(ns) * nr, hipHostMallocDefault);
+    return e == hipSuccess ? ARA_OK : hip_fail(c, e, "server pinned staging");
 }
 
 extern "C" ara_status ara_server_create(ara_ctx *c, const ara_yet *y, ara_elt *const *pool, int32_t n_pool,
@@ -1745,78 +1919,33 @@ extern "C" ara_status ara_server_create(ara_ctx *c, const ara_yet *y, ara_elt *c
         if (!pool[j] || pool[j]->ctx != c || pool[j]->catalog != y->catalog)
             return fail(c, ARA_E_INVALID_ARG, "server: pool ELT %d is NULL, of another context or catalog", j);
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
-    // slots the budget allows: tables + descriptors + YLT per slot
-    const int32_t C = y->catalog;
-    const int32_t nblk = bitmap_blocks(C);
-    const int64_t slot_bytes = int64_t(C) * 8 * 3 + int64_t(nblk) * 24 + int64_t(n_pool) * int64_t(sizeof(EltDesc)) +
-                               y->n_trials * 8;
+    // the budget: slots' tables (at most half of it) and the YLT arena (the rest)
     int64_t budget = cfg->memory_budget;
     if (budget == 0) {
         size_t fr = 0, tot = 0;
         HIP_OR_RETURN(c, hipMemGetInfo(&fr, &tot), "memory info");
         budget = int64_t(fr / 4);
     }
-    const int32_t n_slots = int32_t(std::min<int64_t>(cfg->max_batch, budget / std::max<int64_t>(1, slot_bytes)));
-    if (n_slots < 1) return fail(c, ARA_E_OOM, "server: one slot needs %lld bytes, budget %lld", (long long)slot_bytes,
-                                 (long long)budget);
+    const int64_t slot_bytes = server_slot_bytes(y->catalog, n_pool);
+    const int32_t per_lane = int32_t(std::max<int64_t>(1, std::min<int64_t>(cfg->max_batch, budget / 2 / (2 * slot_bytes))));
+    const int64_t arena = (budget - 2 * int64_t(per_lane) * slot_bytes) / 8;
+    if (arena < 1)
+        return fail(c, ARA_E_OOM, "server: two slots need %lld bytes, budget %lld", (long long)(2 * slot_bytes),
+                    (long long)budget);
     ara_server *sv = new (std::nothrow) ara_server();
     if (!sv) return ARA_E_OOM;
     sv->ctx = c;
     sv->yet = y;
     sv->pool.assign(pool, pool + n_pool);
     sv->rps.assign(cfg->return_periods, cfg->return_periods + cfg->n_rp);
-    ara_status s = ARA_OK;
-    hipError_t e = hipStreamCreateWithFlags(&sv->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) s = hip_fail(c, e, "server stream");
+    sv->slots_per_lane = per_lane;
+    sv->slot_bytes = slot_bytes;
+    sv->ring.cap = arena;
+    ara_status s = dev_alloc(c, &sv->arena, size_t(arena) * 8, "server ylt arena");
+    for (int k = 0; k < 2 && s == ARA_OK; ++k) s = server_lane_create(c, sv, sv->lanes[k], n_pool, cfg);
     if (s == ARA_OK) {
-        s = ara_ctx_create(c->device, sv->stream, &sv->pc);
-        if (s != ARA_OK) s = fail(c, s, "server context: %s", ara_last_error(nullptr));
-    }
-    if (s == ARA_OK) {
-        sv->pc->placement = c->placement;
-        sv->pc->block_threads = c->block_threads;
-        sv->pc->grid_per_cu = c->grid_per_cu;
-        sv->pc->trial_mode = c->trial_mode;
-        sv->pc->yet_packing = c->yet_packing;
-    }
-    const ara_layer_terms none{0.0, INFINITY, 0.0, INFINITY};
-    sv->slots.resize(size_t(n_slots));
-    for (int32_t i = 0; i < n_slots && s == ARA_OK; ++i) {
-        s = ara_layer_create(c, pool, n_pool, C, &none, &sv->slots[size_t(i)].L);
-        if (s == ARA_OK) s = dev_alloc(c, &sv->slots[size_t(i)].ylt, size_t(y->n_trials) * 8, "server ylt");
-    }
-    if (s == ARA_OK) (void)hipStreamSynchronize(c->stream);   // the slot layers' first builds
-    // a worst case of work items: every slot with the YET's longest possible range
-    const int64_t per_slot_items = y->n_trials / 16 + 2;
-    sv->item_cap = int32_t(std::min<int64_t>(int64_t(n_slots) * per_slot_items, int64_t(1) << 30));
-    if (s == ARA_OK) s = dev_alloc(c, &sv->d_jobs, sizeof(BatchJob) * size_t(n_slots), "server jobs");
-    if (s == ARA_OK) s = dev_alloc(c, &sv->d_items, sizeof(BatchItem) * size_t(sv->item_cap), "server items");
-    if (s == ARA_OK) s = dev_alloc(c, &sv->d_ylts, sizeof(double *) * size_t(n_slots), "server ylt list");
-    if (s == ARA_OK) s = dev_alloc(c, &sv->d_ns, 8 * size_t(n_slots), "server sizes");
-    if (s == ARA_OK) s = dev_alloc(c, &sv->d_ks, 8 * size_t(n_slots) * size_t(cfg->n_rp), "server ranks");
-    if (s == ARA_OK) s = dev_alloc(c, &sv->d_res, 16 * size_t(n_slots) * size_t(cfg->n_rp), "server results");
-    if (s == ARA_OK) s = dev_alloc(c, &sv->ws, sort_workspace_bytes(y->n_trials), "server sort workspace");
-    if (s == ARA_OK) {
-        e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_jobs), sizeof(BatchJob) * size_t(n_slots), hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_items), sizeof(BatchItem) * size_t(sv->item_cap),
-                              hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_descs), sizeof(EltDesc) * size_t(n_slots) * size_t(n_pool),
-                              hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_nks), 8 * size_t(n_slots) * size_t(1 + cfg->n_rp),
-                              hipHostMallocDefault);
-        if (e == hipSuccess)
-            e = hipHostMalloc(reinterpret_cast<void **>(&sv->h_res), 16 * size_t(n_slots) * size_t(cfg->n_rp),
-                              hipHostMallocDefault);
-        if (e != hipSuccess) s = hip_fail(c, e, "server pinned staging");
-    }
-    if (s == ARA_OK) {
-        std::vector<const double *> yp(static_cast<size_t>(n_slots));
-        for (int32_t i = 0; i < n_slots; ++i) yp[size_t(i)] = sv->slots[size_t(i)].ylt;
-        e = hipMemcpy(sv->d_ylts, yp.data(), sizeof(double *) * size_t(n_slots), hipMemcpyHostToDevice);
-        if (e != hipSuccess) s = hip_fail(c, e, "server ylt list");
+        const hipError_t e = hipStreamSynchronize(c->stream);   // the slot layers' first builds
+        if (e != hipSuccess) s = hip_fail(c, e, "server slot layers");
     }
     if (s != ARA_OK) {
         server_free(sv);
@@ -1841,6 +1970,7 @@ extern "C" ara_status ara_server_submit(ara_server *sv, const int32_t *idx, int3
         if (idx[k] < 0 || idx[k] >= int32_t(sv->pool.size())) return ARA_E_INVALID_ARG;
     if (ara_check_layer_terms(terms) != ARA_OK) return ARA_E_BAD_TERMS;
     if (t0 < 0 || t1 <= t0 || t1 > sv->yet->n_trials) return ARA_E_INVALID_ARG;
+    if (t1 - t0 > sv->ring.cap) return ARA_E_OOM;   // its YLT alone exceeds the server's budget
     ServerRequest *r = new (std::nothrow) ServerRequest();
     if (!r) return ARA_E_OOM;
     r->elts.assign(idx, idx + n_elts);
@@ -1881,14 +2011,17 @@ extern "C" ara_status ara_server_wait(ara_server *sv, uint64_t ticket, double *p
     return s;
 }
 
-extern "C" ara_status ara_server_stats(ara_server *sv, int64_t *iterations, int64_t *completed, int32_t *max_in_iteration,
-                                      int32_t *slots) {
-    if (!sv) return ARA_E_INVALID_ARG;
+extern "C" ara_status ara_server_stats(ara_server *sv, ara_server_stats_t *st) {
+    if (!sv || !st) return ARA_E_INVALID_ARG;
     std::lock_guard<std::mutex> lk(sv->mu);
-    if (iterations) *iterations = sv->iterations;
-    if (completed) *completed = sv->completed;
-    if (max_in_iteration) *max_in_iteration = sv->max_seen;
-    if (slots) *slots = int32_t(sv->slots.size());
+    st->iterations = sv->iterations;
+    st->completed = sv->completed;
+    st->held = sv->held;
+    st->max_in_iteration = sv->max_seen;
+    st->max_in_flight = sv->max_in_flight;
+    st->slots = 2 * sv->slots_per_lane;
+    st->slot_bytes = sv->slot_bytes;
+    st->arena_bytes = sv->ring.cap * 8;
     return ARA_OK;
 }
 
