@@ -102,7 +102,8 @@ typedef enum ara_option {
     ARA_OPT_BLOCK_THREADS = 2,  /* threads per workgroup of the trial kernel: 256, 512 or 1024       */
     ARA_OPT_GRID_PER_CU = 3,    /* workgroups per compute unit of the trial kernel (1..64; 0 = auto)  */
     ARA_OPT_YET_PACKING = 4,    /* 1 (default): YETs created later also keep a packed copy of their
-                                   event IDs when catalog_size <= 2^24; 0: never                      */
+                                   event IDs when catalog_size <= 2^24 and they keep no binned
+                                   copy; 0: never                                                   */
     ARA_OPT_TRIAL_MODE = 5,     /* dense-table YLT kernels: 0 (default) = one lane per trial when the
                                    YET averages <= 256 occurrences per trial, else one wave per
                                    trial; 1 = always a wave; 2 = always a lane.  A lane adds its
@@ -169,11 +170,12 @@ ara_status ara_sync(ara_ctx *ctx);
  *   mem            ARA_MEM_DEVICE: both arrays are borrowed device pointers;
  *                  ARA_MEM_HOST: both are copied to the device.
  * Blocking: every ID and offset is checked on the device before returning.
- * Packed copy: when catalog_size <= 2^24 (and ARA_OPT_YET_PACKING is 1), the library
- * also stores the checked IDs in 3 bytes each (event i at bytes 3i..3i+2, little
- * endian, in 12-byte groups of 4 events), owned by the handle; the YLT kernels then
- * stream that copy (3 instead of 4 bytes per occurrence).  Borrowed arrays must not
- * change while the handle lives: later analyses may read either form.
+ * Packed copy: when catalog_size <= 2^24, ARA_OPT_YET_PACKING is 1 and the handle
+ * keeps no binned copy (below), the library also stores the checked IDs in 3 bytes
+ * each (event i at bytes 3i..3i+2, little endian, in 12-byte groups of 4 events),
+ * owned by the handle; the YLT kernels then stream that copy (3 instead of 4 bytes
+ * per occurrence).  Borrowed arrays must not change while the handle lives: later
+ * analyses may read either form.
  * Binned copy: when ARA_OPT_YET_BINNING is 1, the catalog is larger than a dense
  * table in LDS (more than 20480 events) and at most 2^24 events, every trial has
  * fewer than 2^31 occurrences in each 2^15-event catalog bin, and the per-bin offsets
@@ -181,8 +183,11 @@ ara_status ara_sync(ara_ctx *ctx);
  * stores the occurrences regrouped by catalog bin: bin by bin, each trial's
  * occurrences of that bin's events in time order as 2-byte IDs within the bin, with
  * per-(bin, trial) offsets.  Analyses of layers whose table does not fit in LDS then
- * read that copy (ARA_PLACE_LDS_TILES).  If the device has no memory for it, the
- * handle is created without it.
+ * read that copy (ARA_PLACE_LDS_TILES); other placements then stream the int32 IDs.
+ * If the device has no memory for it, the handle is created without it.  Device
+ * memory the handle adds to the caller's arrays: 2 bytes per occurrence (rounded up
+ * to 8 per bin) plus 4 bytes per (bin, trial + 1) with a binned copy, else 3 bytes per
+ * occurrence with a packed copy.
  * Errors: ARA_E_INVALID_ARG, ARA_E_EVENT_ID_RANGE, ARA_E_BAD_OFFSETS, ARA_E_OOM, ARA_E_DEVICE. */
 ara_status ara_yet_create(ara_ctx *ctx, const int32_t *event_ids, int64_t n_events,
                           const int64_t *trial_offsets, int64_t n_trials, int32_t catalog_size,
@@ -193,6 +198,20 @@ ara_status ara_yet_release(ara_yet *yet);
  * for layers whose table does not fit in LDS: 2 with a binned copy, else 3 with a
  * packed copy, else 4.  Any output pointer may be NULL. */
 ara_status ara_yet_info(const ara_yet *yet, int64_t *n_events, int64_t *n_trials, int32_t *id_bytes);
+
+/* The YET's catalog-binned copy (see ara_yet_create), copied to host memory, for
+ * checking and inspection.  Bin b holds catalog events [2^15 b, 2^15 (b + 1)).
+ *   n_bins      out: number of bins (0: the handle has no binned copy).
+ *   region      NULL, or int64[n_bins + 1], out: region b of the copy is elements
+ *               [region[b], region[b] + boff[b][n_trials]) (each region starts at
+ *               a multiple of 8 elements); region[n_bins] bounds the copy.
+ *   boff        NULL, or uint32[n_bins * (n_trials + 1)], out: boff[b (n_trials + 1) + t]
+ *               is where trial t's run starts in region b (row b ends with the
+ *               region's length).
+ *   ids16       NULL, or uint16[region[n_bins]], out: the copy (each ID within its bin).
+ * Call with NULL buffers first to learn n_bins and region.  Blocking (waits for the
+ * context's stream).  Errors: ARA_E_INVALID_ARG, ARA_E_DEVICE. */
+ara_status ara_yet_binned(const ara_yet *yet, int32_t *n_bins, int64_t *region, uint32_t *boff, uint16_t *ids16);
 
 /* ---------------------------------------------------------------- Event Loss Table
  * Creates an ELT handle (Section II-A item 2) and builds its direct access table

@@ -112,6 +112,7 @@ _SIGS = {
     "ara_yet_create": (_ST, [_P, _P, _I64, _P, _I64, _I32, ctypes.c_int, ctypes.POINTER(_P)]),
     "ara_yet_release": (_ST, [_P]),
     "ara_yet_info": (_ST, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
+    "ara_yet_binned": (_ST, [_P, ctypes.POINTER(_I32), _P, _P, _P]),
     "ara_elt_create": (_ST, [_P, _P, _P, _I64, _I32, ctypes.POINTER(ara_elt_terms), ctypes.c_int, ctypes.c_int,
                              ctypes.POINTER(_P)]),
     "ara_elt_release": (_ST, [_P]),
@@ -288,6 +289,23 @@ def ara_yet_info(y: Yet):
     ne, nt, b = _I64(), _I64(), _I32()
     _check(_lib.ara_yet_info(y.ptr, ctypes.byref(ne), ctypes.byref(nt), ctypes.byref(b)), y.ctx, "ara_yet_info")
     return int(ne.value), int(nt.value), int(b.value)
+
+
+def ara_yet_binned(y: Yet):
+    """The YET's catalog-binned copy as numpy arrays (region int64[n_bins + 1], boff
+    uint32[n_bins, n_trials + 1], ids16 uint16[region[-1]]), or None without one."""
+    import numpy as np
+    nb = _I32()
+    _check(_lib.ara_yet_binned(y.ptr, ctypes.byref(nb), None, None, None), y.ctx, "ara_yet_binned")
+    if nb.value == 0:
+        return None
+    region = np.zeros(nb.value + 1, np.int64)
+    _check(_lib.ara_yet_binned(y.ptr, ctypes.byref(nb), region.ctypes.data, None, None), y.ctx, "ara_yet_binned")
+    boff = np.zeros((nb.value, y.n_trials + 1), np.uint32)
+    ids16 = np.zeros(int(region[-1]), np.uint16)
+    _check(_lib.ara_yet_binned(y.ptr, ctypes.byref(nb), region.ctypes.data, boff.ctypes.data, ids16.ctypes.data),
+           y.ctx, "ara_yet_binned")
+    return region, boff, ids16
 
 
 def ara_elt_create(ctx: Ctx, event_ids, losses, catalog_size: int, terms: Optional[Sequence[float]] = None,

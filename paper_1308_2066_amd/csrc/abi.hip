@@ -444,7 +444,8 @@ static ara_status yet_build_binned(ara_ctx *c, ara_yet *y) {
         if (s == ARA_OK) {
             e = hipMemcpy(y->region, region.data(), region.size() * 8, hipMemcpyHostToDevice);
             if (e == hipSuccess)
-                e = launch_bin_scatter(y->ids, y->offs, n, nb, y->boff, y->stride, y->region, y->ids16, c->stream);
+                e = launch_bin_scatter(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->region, y->ids16,
+                                       c->stream);
             s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet scatter");
         }
     }
@@ -497,14 +498,17 @@ extern "C" ara_status ara_yet_create(ara_ctx *c, const int32_t *ids, int64_t n_e
     }
     hipError_t e = launch_validate_yet(y->ids, n_events, y->offs, n_trials, catalog, c->d_err, c->stream);
     ara_status s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "validate yet");
-    if (s == ARA_OK && c->yet_packing && n_events > 0 && catalog <= kMaxPackedCatalog) {
+    // the binned copy serves the tiled kernel; the packed copy the kernels that stream
+    // a whole trial's IDs.  A YET keeps one of them: with a binned copy the others
+    // stream the int32 IDs as given
+    if (s == ARA_OK) s = yet_build_binned(c, y);
+    if (s == ARA_OK && !y->ids16 && c->yet_packing && n_events > 0 && catalog <= kMaxPackedCatalog) {
         s = dev_alloc(c, &y->ids24, yet_packed_bytes(n_events), "packed yet ids");
         if (s == ARA_OK) {
             e = launch_yet_pack(y->ids, n_events, y->ids24, c->stream);
             s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "pack yet");
         }
     }
-    if (s == ARA_OK) s = yet_build_binned(c, y);
     if (s != ARA_OK) {
         if (y->owns) {
             dev_free(const_cast<int32_t *>(y->ids));
@@ -540,6 +544,25 @@ extern "C" ara_status ara_yet_info(const ara_yet *y, int64_t *n_events, int64_t 
     if (n_events) *n_events = y->n_events;
     if (n_trials) *n_trials = y->n_trials;
     if (id_bytes) *id_bytes = y->ids16 ? 2 : (y->ids24 ? 3 : 4);
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_yet_binned(const ara_yet *y, int32_t *n_bins, int64_t *region, uint32_t *boff,
+                                    uint16_t *ids16) {
+    if (!y || !n_bins) return ARA_E_INVALID_ARG;
+    ara_ctx *c = y->ctx;
+    *n_bins = y->ids16 ? y->n_bins : 0;
+    if (!y->ids16) return ARA_OK;
+    HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "binned copy");
+    const size_t nb = size_t(y->n_bins), cols = size_t(y->n_trials + 1);
+    std::vector<int64_t> reg(nb + 1);
+    HIP_OR_RETURN(c, hipMemcpy(reg.data(), y->region, (nb + 1) * 8, hipMemcpyDeviceToHost), "binned copy");
+    if (region) std::copy(reg.begin(), reg.end(), region);
+    if (boff)
+        HIP_OR_RETURN(c, hipMemcpy2D(boff, cols * 4, y->boff, size_t(y->stride) * 4, cols * 4, nb, hipMemcpyDeviceToHost),
+                      "binned copy");
+    if (ids16) HIP_OR_RETURN(c, hipMemcpy(ids16, y->ids16, size_t(reg[nb]) * 2, hipMemcpyDeviceToHost), "binned copy");
     return ARA_OK;
 }
 

@@ -180,9 +180,9 @@ hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_t
 hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, int32_t n_bins, uint32_t *block_sums,
                            hipStream_t s);
 size_t bin_scan_scratch_words(int64_t n_entries, int32_t n_bins);
-hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_trials, int32_t n_bins,
-                              const uint32_t *boff, int64_t stride, const int64_t *region, uint16_t *ids16,
-                              hipStream_t s);
+hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
+                              int32_t n_bins, const uint32_t *boff, int64_t stride, const int64_t *region,
+                              uint16_t *ids16, hipStream_t s);
 
 // A tile of a layer's occurrence filter: 128-event blocks [blk_lo, blk_hi) of the
 // catalog, overlapping bins [bin_lo, bin_hi); rank_lo flagged events precede it and

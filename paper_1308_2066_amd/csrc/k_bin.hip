@@ -15,29 +15,44 @@
 namespace ara {
 
 // boff[b][t] = number of trial t's occurrences in bin b; boff[b][n_trials] = 0.
-// One wave per trial, counting in an LDS histogram.
-__global__ __launch_bounds__(64) void k_bin_count(const int32_t *__restrict__ ids, const int64_t *__restrict__ offs,
-                                                  int64_t n_trials, int32_t n_bins, uint32_t *__restrict__ boff,
-                                                  int64_t stride) {
-    __shared__ uint32_t hist[kMaxBins];
-    const int lane = threadIdx.x;
+// One wave per trial (four per workgroup), counting in the wave's own LDS
+// histogram; a wave's LDS operations complete in order, so it needs no barrier.
+constexpr int kCountWaves = 4;
+
+__global__ __launch_bounds__(kCountWaves * 64) void k_bin_count(const int32_t *__restrict__ ids,
+                                                                const int64_t *__restrict__ offs, int64_t n_trials,
+                                                                int32_t n_bins, uint32_t *__restrict__ boff,
+                                                                int64_t stride) {
+    __shared__ uint32_t hist[kCountWaves][kMaxBins];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t *h = hist[wave];
     if (blockIdx.x == 0)
-        for (int32_t b = lane; b < n_bins; b += 64) boff[b * stride + n_trials] = 0u;
-    for (int64_t t = blockIdx.x; t < n_trials; t += gridDim.x) {
-        for (int32_t b = lane; b < n_bins; b += 64) hist[b] = 0u;
-        __syncthreads();
+        for (int32_t b = threadIdx.x; b < n_bins; b += kCountWaves * 64) boff[b * stride + n_trials] = 0u;
+    for (int64_t t = int64_t(blockIdx.x) * kCountWaves + wave; t < n_trials; t += int64_t(gridDim.x) * kCountWaves) {
+        for (int32_t b = lane; b < n_bins; b += 64) h[b] = 0u;
+        __builtin_amdgcn_wave_barrier();
         const int64_t o0 = offs[t], o1 = offs[t + 1];
-        for (int64_t i = o0 + lane; i < o1; i += 64) atomicAdd(&hist[uint32_t(ids[i]) >> kBinShift], 1u);
-        __syncthreads();
-        for (int32_t b = lane; b < n_bins; b += 64) boff[b * stride + t] = hist[b];
-        __syncthreads();
+        int64_t i = o0 + lane;
+        for (; i + 192 < o1; i += 256) {   // four loads in flight per lane
+            const uint32_t a = uint32_t(ids[i]), b = uint32_t(ids[i + 64]), c = uint32_t(ids[i + 128]),
+                           d = uint32_t(ids[i + 192]);
+            atomicAdd(&h[a >> kBinShift], 1u);
+            atomicAdd(&h[b >> kBinShift], 1u);
+            atomicAdd(&h[c >> kBinShift], 1u);
+            atomicAdd(&h[d >> kBinShift], 1u);
+        }
+        for (; i < o1; i += 64) atomicAdd(&h[uint32_t(ids[i]) >> kBinShift], 1u);
+        __builtin_amdgcn_wave_barrier();
+        for (int32_t b = lane; b < n_bins; b += 64) boff[b * stride + t] = h[b];
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
 hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_trials, int32_t n_bins,
                             uint32_t *boff, int64_t stride, hipStream_t s) {
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_trials, 65536));
-    hipLaunchKernelGGL(k_bin_count, dim3(unsigned(grid)), dim3(64), 0, s, ids, offs, n_trials, n_bins, boff, stride);
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n_trials + kCountWaves - 1) / kCountWaves, 65536));
+    hipLaunchKernelGGL(k_bin_count, dim3(unsigned(grid)), dim3(kCountWaves * 64), 0, s, ids, offs, n_trials, n_bins,
+                       boff, stride);
     return hipGetLastError();
 }
 
@@ -120,49 +135,126 @@ hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, in
 }
 
 // Writes each occurrence at region[b] + boff[b][t] + (its rank among trial t's
-// earlier occurrences of bin b): one wave per trial, 64 occurrences at a time; the
-// lanes of a chunk that share a bin are placed in lane order (stable).
-__global__ __launch_bounds__(64) void k_bin_scatter(const int32_t *__restrict__ ids, const int64_t *__restrict__ offs,
-                                                    int64_t n_trials, int32_t n_bins, const uint32_t *__restrict__ boff,
-                                                    int64_t stride, const int64_t *__restrict__ region,
-                                                    uint16_t *__restrict__ ids16) {
-    __shared__ int64_t cur[kMaxBins];   // next write position of the trial's run in each bin
-    const int lane = threadIdx.x;
-    for (int64_t t = blockIdx.x; t < n_trials; t += gridDim.x) {
-        for (int32_t b = lane; b < n_bins; b += 64) cur[b] = region[b] + int64_t(boff[b * stride + t]);
+// earlier occurrences of bin b).  A workgroup takes `per_block` consecutive trials;
+// their occurrences of bin b form one contiguous span of region b, so when the
+// block's occurrences fit in LDS they are placed there first (a counting sort by
+// bin) and each bin's span is then written with consecutive stores.  A block with
+// more occurrences than the LDS holds writes every occurrence to its place directly.
+// Either way a wave takes one trial at a time, 64 occurrences per step in time
+// order; lanes of a step that share a bin are ranked in lane order (the mask of
+// lanes with the same bin is found with one ballot per bit of the bin number), so
+// each run keeps the trial's time order.
+constexpr int kScatterWaves = 16;
+constexpr int kScatterCap = 61440;   // occurrences staged per workgroup (120 KB)
+
+int64_t bin_scatter_block_trials(int64_t n_events, int64_t n_trials) {
+    const double mean = n_trials > 0 ? double(n_events) / double(n_trials) : 0.0;
+    const double by_cap = mean > 0.0 ? 0.75 * double(kScatterCap) / mean : 4096.0;
+    return std::max<int64_t>(1, std::min<int64_t>(4096, int64_t(by_cap)));
+}
+
+// Rank of this lane among the lanes of `valid` whose bin equals its own, and their
+// number; nbits = bits needed for the largest bin number.
+__device__ __forceinline__ void same_bin_rank(uint32_t b, uint64_t valid, int nbits, uint32_t &rank, uint32_t &count) {
+    uint64_t m = valid;
+    for (int k = 0; k < nbits; ++k) {
+        const bool bit = (b >> k) & 1u;
+        const uint64_t ones = __builtin_amdgcn_ballot_w64(bit);
+        m &= bit ? ones : ~ones;
+    }
+    rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    count = uint32_t(__popcll(m));
+}
+
+__global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_t *__restrict__ ids,
+                                                                    const int64_t *__restrict__ offs, int64_t n_trials,
+                                                                    int32_t n_bins, const uint32_t *__restrict__ boff,
+                                                                    int64_t stride, const int64_t *__restrict__ region,
+                                                                    uint16_t *__restrict__ ids16, int64_t per_block) {
+    __shared__ uint16_t stage[kScatterCap];
+    __shared__ uint32_t cur[kScatterWaves][kMaxBins];   // next position of the wave's trial's run, per bin
+    __shared__ uint32_t lbase[kMaxBins + 1];            // start of bin b's span in `stage`
+    __shared__ uint32_t bstart[kMaxBins];               // boff[b][t0]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nbits = n_bins > 1 ? 32 - __builtin_clz(uint32_t(n_bins - 1)) : 0;
+    const int64_t t0 = int64_t(blockIdx.x) * per_block;
+    if (t0 >= n_trials) return;
+    const int64_t t1 = min(t0 + per_block, n_trials);
+    const bool staged = offs[t1] - offs[t0] <= int64_t(kScatterCap);
+    uint32_t *wc = cur[wave];
+    if (staged) {
+        for (int32_t b = threadIdx.x; b < n_bins; b += kScatterWaves * 64) {
+            const uint32_t s = boff[b * stride + t0];
+            bstart[b] = s;
+            lbase[b + 1] = boff[b * stride + t1] - s;
+        }
         __syncthreads();
+        if (wave == 0) {   // exclusive scan of the span lengths, 8 bins per lane
+            uint32_t v[8], own = 0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int32_t b = lane * 8 + k;
+                v[k] = b < n_bins ? lbase[b + 1] : 0u;
+                own += v[k];
+            }
+            uint32_t inc = own;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += y;
+            }
+            uint32_t run = inc - own;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int32_t b = lane * 8 + k;
+                if (b < n_bins) lbase[b] = run;
+                run += v[k];
+            }
+            if (lane == 63) lbase[n_bins] = run;
+        }
+        __syncthreads();
+    }
+    for (int64_t t = t0 + wave; t < t1; t += kScatterWaves) {
+        for (int32_t b = lane; b < n_bins; b += 64)
+            wc[b] = staged ? lbase[b] + boff[b * stride + t] - bstart[b] : boff[b * stride + t];
+        __builtin_amdgcn_wave_barrier();
         const int64_t o0 = offs[t], o1 = offs[t + 1];
         for (int64_t base = o0; base < o1; base += 64) {
             const int64_t i = base + lane;
             const bool valid = i < o1;
             const uint32_t id = valid ? uint32_t(ids[i]) : 0u;
-            const int32_t b = int32_t(id >> kBinShift);
-            uint64_t todo = __ballot(valid);
-            while (todo) {
-                const int leader = __builtin_ctzll(todo);
-                const int32_t bl = __builtin_amdgcn_readlane(b, leader);
-                const uint64_t m = __ballot(valid && b == bl);
-                const int64_t at = cur[bl];
-                if (valid && b == bl) {
-                    const uint32_t r = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-                    ids16[at + r] = uint16_t(id & uint32_t(kBinEvents - 1));
-                }
-                __syncthreads();
-                if (lane == leader) cur[bl] = at + __popcll(m);
-                __syncthreads();
-                todo &= ~m;
+            const uint32_t b = id >> kBinShift;
+            uint32_t rank, count;
+            same_bin_rank(b, __builtin_amdgcn_ballot_w64(valid), nbits, rank, count);
+            const uint32_t at = wc[b];
+            const uint16_t local = uint16_t(id & uint32_t(kBinEvents - 1));
+            if (valid) {
+                if (staged) stage[at + rank] = local;
+                else ids16[region[b] + int64_t(at + rank)] = local;
+                if (rank + 1 == count) wc[b] = at + count;
             }
+            __builtin_amdgcn_wave_barrier();
         }
-        __syncthreads();
+    }
+    if (!staged) return;
+    __syncthreads();
+    // each bin's span to its place in region b, consecutive lanes on consecutive IDs
+    for (int32_t b = wave; b < n_bins; b += kScatterWaves) {
+        const uint32_t l0 = lbase[b], len = lbase[b + 1] - l0;
+        uint16_t *dst = ids16 + region[b] + int64_t(bstart[b]);
+        for (uint32_t k = lane; k < len; k += 64) dst[k] = stage[l0 + k];
     }
 }
 
-hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_trials, int32_t n_bins,
-                              const uint32_t *boff, int64_t stride, const int64_t *region, uint16_t *ids16,
-                              hipStream_t s) {
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>(n_trials, 65536));
-    hipLaunchKernelGGL(k_bin_scatter, dim3(unsigned(grid)), dim3(64), 0, s, ids, offs, n_trials, n_bins, boff, stride,
-                       region, ids16);
+hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
+                              int32_t n_bins, const uint32_t *boff, int64_t stride, const int64_t *region,
+                              uint16_t *ids16, hipStream_t s) {
+    if (n_trials <= 0) return hipSuccess;
+    if (n_bins > kMaxBins) return hipErrorInvalidValue;
+    const int64_t per = bin_scatter_block_trials(n_events, n_trials);
+    const int64_t grid = (n_trials + per - 1) / per;
+    if (grid > int64_t(INT32_MAX)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bin_scatter, dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs, n_trials, n_bins,
+                       boff, stride, region, ids16, per);
     return hipGetLastError();
 }
 

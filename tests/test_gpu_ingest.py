@@ -1,0 +1,110 @@
+"""YET ingest: the catalog-binned copy against its definition, bit for bit.
+
+Definition (the layout the tiled trial kernel reads): the catalog is cut into bins
+of 2^15 events; region b holds, trial after trial, each trial's occurrences of bin-b
+events in time order, each as its ID minus 2^15 b; boff[b][t] is where trial t's run
+starts in region b, boff[b][n_trials] the region's length.  The expected copy below
+is that definition computed with numpy's stable sort (integer work: bit-exact)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+BIN_SHIFT = 15
+
+
+def _say(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _expected(ids: np.ndarray, offs: np.ndarray, catalog: int):
+    n_trials = len(offs) - 1
+    n_bins = (catalog + (1 << BIN_SHIFT) - 1) >> BIN_SHIFT
+    trial = np.repeat(np.arange(n_trials, dtype=np.int64), np.diff(offs))
+    b = ids.astype(np.int64) >> BIN_SHIFT
+    order = np.argsort(b * (n_trials + 1) + trial, kind="stable")
+    counts = np.zeros((n_bins, n_trials), np.int64)
+    np.add.at(counts, (b, trial), 1)
+    boff = np.zeros((n_bins, n_trials + 1), np.int64)
+    boff[:, 1:] = np.cumsum(counts, axis=1)
+    local = (ids[order] & ((1 << BIN_SHIFT) - 1)).astype(np.uint16)
+    per_bin = np.split(local, np.cumsum(boff[:, -1])[:-1])
+    return n_bins, boff, per_bin
+
+
+def _check_copy(A, y, ids, offs, catalog):
+    got = A.ara_yet_binned(y)
+    assert got is not None, "expected a binned copy"
+    region, boff, ids16 = got
+    n_bins, boff_x, per_bin = _expected(ids, offs, catalog)
+    assert len(region) == n_bins + 1 and region[0] == 0
+    assert np.all(region[:-1] % 8 == 0)
+    assert np.array_equal(boff.astype(np.int64), boff_x)
+    for b in range(n_bins):
+        assert region[b] + boff_x[b, -1] <= region[b + 1]
+        assert np.array_equal(ids16[region[b]:region[b] + boff_x[b, -1]], per_bin[b]), f"bin {b}"
+
+
+@pytest.mark.parametrize("case", ["poisson", "ragged_long_trial", "one_bin_heavy"])
+def test_binned_copy_matches_definition(ara_lib, gpu_ctx, case):
+    import torch
+    A = ara_lib
+    rng = np.random.default_rng({"poisson": 11, "ragged_long_trial": 12, "one_bin_heavy": 13}[case])
+    catalog = 200_003   # 7 bins, the last one partial
+    if case == "poisson":
+        lens = rng.poisson(300, size=5000)
+        lens[::97] = 0   # empty trials
+    elif case == "ragged_long_trial":
+        # a block of trials with more occurrences than one workgroup stages in LDS
+        lens = rng.poisson(40, size=3000)
+        lens[1234] = 90_000
+        lens[2999] = 70_001
+    else:
+        lens = rng.poisson(500, size=800)
+    offs = np.zeros(len(lens) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    ids = rng.integers(0, catalog, size=int(offs[-1]), dtype=np.int32)
+    if case == "one_bin_heavy":   # most occurrences in bin 3, so runs of one bin are long
+        heavy = rng.random(len(ids)) < 0.8
+        ids[heavy] = (3 << BIN_SHIFT) + rng.integers(0, 1 << BIN_SHIFT, size=int(heavy.sum()), dtype=np.int32)
+    _say(f"binned copy {case}: {len(lens)} trials, {len(ids)} occurrences")
+    y = A.ara_yet_create(gpu_ctx, torch.from_numpy(ids).cuda(), torch.from_numpy(offs).cuda(), catalog)
+    try:
+        assert A.ara_yet_info(y)[2] == 2
+        _check_copy(A, y, ids, offs, catalog)
+    finally:
+        A.ara_yet_release(y)
+
+
+def test_paper_scale_binned_copy(ara_lib, gpu_ctx):
+    """The paper-scale YET (10^6 trials x 1000 events, 10^6-event catalog): per-bin
+    totals over every occurrence, and every run of 2,000 sampled trials."""
+    import torch
+    A = ara_lib
+    w = synth.workload_paper_scale()
+    _say("paper-scale binned copy")
+    y = A.ara_yet_create(gpu_ctx, torch.from_numpy(w.event_ids).cuda(), torch.from_numpy(w.trial_offsets).cuda(),
+                         w.catalog_size)
+    try:
+        assert A.ara_yet_info(y)[2] == 2
+        region, boff, ids16 = A.ara_yet_binned(y)
+        n_bins = len(region) - 1
+        totals = np.bincount(w.event_ids >> BIN_SHIFT, minlength=n_bins)
+        assert np.array_equal(boff[:, -1].astype(np.int64), totals)
+        assert np.all(np.diff(boff.astype(np.int64), axis=1) >= 0)
+        rng = np.random.default_rng(5)
+        for t in np.sort(rng.choice(w.n_trials, size=2000, replace=False)):
+            tid = w.event_ids[w.trial_offsets[t]:w.trial_offsets[t + 1]]
+            tb = tid >> BIN_SHIFT
+            for b in range(n_bins):
+                run = ids16[region[b] + boff[b, t]:region[b] + boff[b, t + 1]]
+                want = (tid[tb == b] & ((1 << BIN_SHIFT) - 1)).astype(np.uint16)
+                assert np.array_equal(run, want), f"trial {t} bin {b}"
+    finally:
+        A.ara_yet_release(y)
