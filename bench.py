@@ -103,6 +103,17 @@ def headline_kernel_in(rows) -> str:
     raise SystemExit(f"none of {list(KERNELS)} in the recorded dispatches")
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, target_s: float):
     """The CPU oracle (all host threads, OpenMP over trials) on the first trials of
     the same workload, the sample sized to take about target_s seconds: a fixed
@@ -138,6 +149,7 @@ def cpu_baseline(w, target_s: float):
     ev1 = float(w.trial_offsets[n1] - w.trial_offsets[0])
     log(f"cpu oracle 1 thread: {n1} trials {dt1:.1f}s")
     return {"value": ev / dt, "unit": "trial-events·layers/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": len(os.sched_getaffinity(0)),
             "sample": f"first {n} of {w.n_trials} trials ({int(ev)} trial-events, 1 layer) of the same workload, "
                       f"dense tables built per call, YLT then PML/TVaR; {dt:.1f}s wall",
             "value_1_thread": ev1 / dt1,
@@ -405,33 +417,25 @@ def bench_events(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_serving(args):
-    """Serving: a resident YET (10^6 trials of Poisson(100) events over a 10,000-event
-    catalog) and a 256-ELT pool; open-loop pricing requests (Poisson arrivals; U{1..32}
-    ELTs, log-uniform terms, 10^5-10^6 contiguous trials) answered with PML/TVaR.
-    Server: ara_server_submit at each arrival, latency = submission to completion as
-    the server measures it.  Plain: one thread takes requests in arrival order and
-    runs layer create + ara_analyze + ara_risk_measures + layer release; latency =
-    completion - arrival.  Same requests, same results."""
+def serving_rates(ctx, yet, pool, n_trials, n_events, catalog, rps, rates, n_requests, log_prefix="serving"):
+    """Open-loop pricing requests (Poisson arrivals; U{1..32} ELTs of the pool,
+    log-uniform terms, 10^5-10^6 contiguous trials) answered with PML/TVaR, once
+    through the server and once through plain per-request launches on the same
+    arrival trace.  Server latency = submission to completion as the server measures
+    it; plain: one thread takes requests in arrival order (layer create + ara_analyze
+    + ara_risk_measures + layer release), latency = completion - arrival.  Returns one
+    record per arrival rate."""
     import threading
     import torch
     import synth
-    from paper_1308_2066_amd import ara, session
+    from paper_1308_2066_amd import ara
 
-    pf = synth.portfolio_batched(n_layers=1)
-    ids, offs, C = synth.serving_yet()
-    rps = list(pf.return_periods)
-    torch.cuda.set_device(0)
-    ctx = ara.ara_ctx_create(0, torch.cuda.current_stream())
-    h = session.open_portfolio(ctx, ids, offs, C, pf.pool, [])
-    n_trials = int(offs.shape[0] - 1)
     ws = torch.empty(ara.ara_sort_workspace_size(n_trials), dtype=torch.uint8, device="cuda")
     ylt = torch.empty(n_trials, dtype=torch.float64, device="cuda")
     lines = []
-    for rate in [float(x) for x in args.rates.split(",")]:
-        reqs = synth.serving_requests(args.requests, n_trials, rate=rate)
-        # server
-        srv = ara.ara_server_create(ctx, h.yet, h.pool, rps, max_batch=32)
+    for rate in rates:
+        reqs = synth.serving_requests(n_requests, n_trials, rate=rate)
+        srv = ara.ara_server_create(ctx, yet, pool, rps, max_batch=32)
         warm = [ara.ara_server_submit(srv, r[1], r[2], r[3], r[4]) for r in reqs[:8]]
         for t in warm:
             ara.ara_server_wait(srv, t)
@@ -459,15 +463,14 @@ def bench_serving(args):
         st = ara.ara_server_stats(srv)
         iters, most, slots = st["iterations"], st["max_in_iteration"], st["slots"]
         ara.ara_server_release(srv)
-        # plain per-request launches, same arrival trace
         lat_p, res_p = [], []
         t_start = time.perf_counter()
         for at, idx, terms, t0, t1 in reqs:
             d = t_start + at - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            layer = ara.ara_layer_create(ctx, [h.pool[i] for i in idx], C, terms)
-            ara.ara_analyze(ctx, h.yet, layer, t0, t1, ylt[: t1 - t0])
+            layer = ara.ara_layer_create(ctx, [pool[i] for i in idx], catalog, terms)
+            ara.ara_analyze(ctx, yet, layer, t0, t1, ylt[: t1 - t0])
             pml, tvar = ara.ara_risk_measures(ctx, ylt[: t1 - t0], rps, ws)
             ara.ara_layer_release(layer)
             lat_p.append(time.perf_counter() - (t_start + at))
@@ -476,8 +479,8 @@ def bench_serving(args):
         same = all(a[0].tobytes() == b[0].tobytes() and a[1].tobytes() == b[1].tobytes()
                    for a, b in zip(res_s, res_p))
         q = lambda v, p: float(np.percentile(np.asarray(v) * 1e3, p))
-        te = float(sum((r[4] - r[3]) for r in reqs)) * float(ids.shape[0]) / n_trials
-        log(f"serving rate {rate}/s: server p50 {q(lat_s, 50):.3f} ms p99 {q(lat_s, 99):.3f} ms "
+        te = float(sum((r[4] - r[3]) for r in reqs)) * float(n_events) / n_trials
+        log(f"{log_prefix} rate {rate}/s: server p50 {q(lat_s, 50):.3f} ms p99 {q(lat_s, 99):.3f} ms "
             f"({iters} iterations, max {most} per iteration, {slots} slots); plain p50 {q(lat_p, 50):.3f} ms "
             f"p99 {q(lat_p, 99):.3f} ms; identical={same}")
         lines.append({"rate_per_s": rate, "requests": len(reqs),
@@ -486,6 +489,34 @@ def bench_serving(args):
                                  "max_in_flight": st["max_in_flight"], "held_for_memory": st["held"]},
                       "plain": {"p50_ms": q(lat_p, 50), "p99_ms": q(lat_p, 99), "queries_per_s": len(reqs) / wall_p},
                       "identical_results": bool(same), "trial_events_per_request": te / len(reqs)})
+    return lines
+
+
+SERVING_WORKLOAD = ("serving: resident YET of 10^6 trials (Poisson(100) events, catalog 10,000), 256 dense "
+                    "lognormal(11,2.5) binary32 ELTs; Poisson arrivals of requests of 1-32 ELTs, log-uniform terms, "
+                    "10^5-10^6 contiguous trials")
+
+
+def open_serving(ctx):
+    import synth
+    from paper_1308_2066_amd import session
+    pf = synth.portfolio_batched(n_layers=1)
+    ids, offs, C = synth.serving_yet()
+    h = session.open_portfolio(ctx, ids, offs, C, pf.pool, [])
+    return h, pf, int(offs.shape[0] - 1), int(ids.shape[0]), C
+
+
+def bench_serving(args):
+    """Serving: p50/p99 quote latency and queries/s of the server against plain
+    per-request launches, at each arrival rate of --rates (serving_rates)."""
+    import torch
+    from paper_1308_2066_amd import ara
+
+    torch.cuda.set_device(0)
+    ctx = ara.ara_ctx_create(0, torch.cuda.current_stream())
+    h, pf, n_trials, n_events, C = open_serving(ctx)
+    lines = serving_rates(ctx, h.yet, h.pool, n_trials, n_events, C, list(pf.return_periods),
+                          [float(x) for x in args.rates.split(",")], args.requests)
     h.release()
     ara.ara_ctx_destroy(ctx)
     first = lines[0]
@@ -495,8 +526,7 @@ def bench_serving(args):
         "value": first["server"]["p50_ms"], "unit": "ms", "n_gpus": 1, "steps": first["requests"], "warmup": 8,
         "ms_per_step": first["server"]["p50_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64 arithmetic, f32 tables", "data": "synthetic",
-        "config": {"workload": "serving: resident YET of 10^6 trials (Poisson(100) events, catalog 10,000), 256 "
-                               "dense lognormal(11,2.5) ELTs, Poisson arrivals", "parallelism": "1 GPU"},
+        "config": {"workload": SERVING_WORKLOAD, "parallelism": "1 GPU"},
         "rates": lines,
     }
     print(json.dumps(out), flush=True)
@@ -592,6 +622,9 @@ def main():
     ap.add_argument("--no-packing", action="store_true", help="stream int32 IDs instead of the packed YET copy")
     ap.add_argument("--no-binning", action="store_true", help="no catalog-binned YET copy (no tiled kernel)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle sample time (0 = skip)")
+    ap.add_argument("--serve-requests", type=int, default=200,
+                    help="paper workload: requests of the serving leg per rate (0 = skip the leg)")
+    ap.add_argument("--serve-rates", default="50", help="paper workload: arrival rates of the serving leg")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH", "WRITE"),
@@ -650,13 +683,33 @@ def main():
     ara.ara_set_option(ctx, ara.ARA_OPT_YET_PACKING, 0 if args.no_packing else 1)
     ara.ara_set_option(ctx, ara.ARA_OPT_YET_BINNING, 0 if args.no_binning else 1)
     prec = ara.ARA_F32 if args.precision == "f32" else ara.ARA_F64
-    t = time.time()
-    an = session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
-                               None, prec)
+    # ingest, once per resident YET: the int32 IDs and int64 offsets already in HBM,
+    # ara_yet_create checks every ID and offset and builds the binned (or packed)
+    # copy; it is blocking, so its wall time is the ingest time
+    ids_dev = session.to_device(np.asarray(w.event_ids, np.int32))
+    offs_dev = session.to_device(np.asarray(w.trial_offsets, np.int64))
     torch.cuda.synchronize()
-    log(f"uploaded + validated in {time.time() - t:.1f}s")
+    ig0, ig1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ig0.record(stream)
+    t = time.perf_counter()
+    yet = ara.ara_yet_create(ctx, ids_dev, offs_dev, w.catalog_size)
+    ingest_ms = (time.perf_counter() - t) * 1e3
+    ig1.record(stream)
+    torch.cuda.synchronize()
+    ingest_gpu_ms = ig0.elapsed_time(ig1)
+    id_bytes = ara.ara_yet_info(yet)[2]
+    n_bins = (w.catalog_size + 32767) // 32768
+    # device memory the handle adds to the caller's int32 IDs and offsets (the
+    # layout ara_yet_create states: 2 B per occurrence rounded up to 8 per bin, plus
+    # 4 B per (bin, trial + 1); else 3 B per occurrence for the packed copy)
+    yet_extra = (2 * w.n_events + 8 * n_bins + 4 * n_bins * (w.n_trials + 1)) if id_bytes == 2 else \
+        (3 * w.n_events if id_bytes == 3 else 0)
+    log(f"ingest (validate + {'binned' if id_bytes == 2 else 'packed' if id_bytes == 3 else 'no'} copy): "
+        f"{ingest_ms:.2f} ms wall, {ingest_gpu_ms:.2f} ms on the stream; {yet_extra / 1e9:.3f} GB added")
+    an = session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
+                               None, prec, yet=yet)
+    torch.cuda.synchronize()
     n_flagged, placement, lds_bytes = ara.ara_layer_stats(ctx, an.layer)
-    id_bytes = ara.ara_yet_info(an.yet)[2]
     # the layer alone would take the LDS filter; with the YET's binned copy the
     # analysis takes the tiled kernel unless a placement is forced
     if id_bytes == 2 and placement == ara.ARA_PLACE_LDS_BITMAP and args.placement in (0, ara.ARA_PLACE_LDS_TILES):
@@ -668,31 +721,40 @@ def main():
     ylt = torch.empty(w.n_trials, dtype=torch.float64, device="cuda")
     ws = torch.empty(ara.ara_sort_workspace_size(w.n_trials), dtype=torch.uint8, device="cuda")
     rps = list(w.return_periods)
+    # PML/TVaR input with as many distinct year losses (all eight radix passes run;
+    # the workload's own year losses all equal the aggregate limit, so the step's
+    # sort skips its passes)
+    y_distinct = torch.from_numpy(np.random.default_rng(7).lognormal(15.0, 2.0, size=w.n_trials)).cuda()
 
-    ev0 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ev1 = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    def run_steps(layer, steps, warmup, sort_input=None):
+        """steps x (table build, trial kernel, sort + PML/TVaR to the host): wall ms per
+        step and the trial kernel's average ms (HIP events on its stream)."""
+        e0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        e1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
 
-    def step(i=None):
-        ara.ara_layer_build(ctx, an.layer, ara.ARA_BUILD_TABLES)
-        if i is not None:
-            ev0[i].record(stream)
-        ara.ara_analyze(ctx, an.yet, an.layer, 0, w.n_trials, ylt)
-        if i is not None:
-            ev1[i].record(stream)
-        return ara.ara_risk_measures(ctx, ylt, rps, ws)
+        def step(i=None):
+            ara.ara_layer_build(ctx, layer, ara.ARA_BUILD_TABLES)
+            if i is not None:
+                e0[i].record(stream)
+            ara.ara_analyze(ctx, an.yet, layer, 0, w.n_trials, ylt)
+            if i is not None:
+                e1[i].record(stream)
+            return ara.ara_risk_measures(ctx, ylt if sort_input is None else sort_input, rps, ws)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        pml, tvar = step(i)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    kern_ms = [ev0[i].elapsed_time(ev1[i]) for i in range(args.steps)]
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            res = step(i)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        km = [e0[i].elapsed_time(e1[i]) for i in range(steps)]
+        return ms, km, res
+
+    ms_step, kern_ms, (pml, tvar) = run_steps(an.layer, args.steps, args.warmup)
     k_avg = float(np.mean(kern_ms))
+    saturated = bool(torch.all(ylt == float(w.layer_terms[3])).item())
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; trial kernel avg {k_avg:.4f} ms "
         f"(min {min(kern_ms):.4f}, max {max(kern_ms):.4f}); PML {pml.tolist()} TVaR {tvar.tolist()}")
 
@@ -703,19 +765,17 @@ def main():
     # offset per (catalog bin, trial) instead of the trial offsets
     alg_bytes = 4 * w.n_events + 8 * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * n_flagged
     if kernel == "k_trial_tiled":
-        n_bins = (w.catalog_size + 32767) // 32768
         moved_bytes = 2 * w.n_events + 4 * n_bins * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * n_flagged
     else:
         ib = 3 if not args.no_packing and w.catalog_size <= 1 << 24 else 4   # the packed copy, else int32
         moved_bytes = alg_bytes - (4 - ib) * w.n_events
-        id_bytes = ib
     achieved = alg_bytes / (k_avg * 1e-3) / 1e9
+    moved_gbs = moved_bytes / (k_avg * 1e-3) / 1e9
     te = float(w.n_events)   # trial-events x layers (1 layer)
     value = te / (ms_step * 1e-3)
 
-    # PML/TVaR of as many distinct year losses: every radix pass runs (the workload's
-    # year losses all equal the aggregate limit, so the step's sort skips its passes)
-    y_distinct = torch.from_numpy(np.random.default_rng(7).lognormal(15.0, 2.0, size=w.n_trials)).cuda()
+    # the same step with the sort of distinct year losses in place of the saturated YLT
+    ms_step_distinct, _, _ = run_steps(an.layer, 10, 2, sort_input=y_distinct)
     for _ in range(2):
         ara.ara_risk_measures(ctx, y_distinct, rps, ws)
     torch.cuda.synchronize()
@@ -724,7 +784,21 @@ def main():
         ara.ara_risk_measures(ctx, y_distinct, rps, ws)
     torch.cuda.synchronize()
     risk_distinct_ms = (time.perf_counter() - t_r) * 1e3 / 10
-    log(f"PML/TVaR of {w.n_trials} distinct year losses: {risk_distinct_ms:.3f} ms")
+    log(f"PML/TVaR of {w.n_trials} distinct year losses: {risk_distinct_ms:.3f} ms; step with that sort "
+        f"{ms_step_distinct:.3f} ms")
+
+    # the other table precision on the same resident YET
+    other = ara.ARA_F32 if prec == ara.ARA_F64 else ara.ARA_F64
+    an2 = session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
+                                None, other, yet=yet)
+    ms2, km2, _ = run_steps(an2.layer, args.steps, args.warmup)
+    k2 = float(np.mean(km2))
+    nf2 = ara.ara_layer_stats(ctx, an2.layer)[0]
+    alg2 = 4 * w.n_events + 8 * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * nf2
+    ara.ara_layer_release(an2.layer)
+    for e in an2.elts:
+        ara.ara_elt_release(e)
+    log(f"{'binary32' if other == ara.ARA_F32 else 'binary64'} tables: {ms2:.3f} ms/step; trial kernel {k2:.4f} ms")
 
     if args.copy_probe_mib:
         src = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
@@ -734,6 +808,16 @@ def main():
         log(f"copy probe {args.copy_probe_mib} MiB done")
 
     an.release()
+    del ids_dev, offs_dev, ylt, ws, y_distinct
+    torch.cuda.empty_cache()
+
+    serving = None
+    if args.serve_requests > 0:
+        h, pf, s_trials, s_events, s_cat = open_serving(ctx)
+        lines = serving_rates(ctx, h.yet, h.pool, s_trials, s_events, s_cat, list(pf.return_periods),
+                              [float(x) for x in args.serve_rates.split(",")], args.serve_requests)
+        h.release()
+        serving = {"workload": SERVING_WORKLOAD, "rates": lines}
     ara.ara_ctx_destroy(ctx)
 
     cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
@@ -759,10 +843,22 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel,
                      "kernel_ms": k_avg, "algorithmic_bytes": alg_bytes, "yet_id_bytes": id_bytes,
-                     "moved_bytes": moved_bytes, "traffic_source": traffic_note},
+                     "moved_bytes": moved_bytes, "moved_gbs": moved_gbs, "moved_frac": moved_gbs / HBM_PEAK_GBS,
+                     "traffic_source": traffic_note},
         "cpu_baseline": cpu,
+        "ingest": {"ms": ingest_ms, "gpu_ms": ingest_gpu_ms, "yet_extra_bytes": yet_extra,
+                   "what": "ara_yet_create on IDs and offsets resident in HBM: every ID and offset checked, "
+                           "catalog-binned copy built; once per resident YET, not part of a step"},
+        "ylt_saturated": {"all_equal_agg_limit": saturated,
+                          "ms_per_step_with_distinct_ylt_sort": ms_step_distinct,
+                          "value_with_distinct_ylt_sort": te / (ms_step_distinct * 1e-3)},
         "risk_measures_distinct_ylt": {"ms": risk_distinct_ms, "trials": w.n_trials,
                                        "data": "lognormal(15, 2) year losses, seed 7: all 8 radix passes run"},
+        ("f32_tables" if other == ara.ARA_F32 else "f64_tables"): {
+            "ms_per_step": ms2, "value": te / (ms2 * 1e-3), "kernel_ms": k2, "algorithmic_bytes": alg2,
+            "achieved_gbs": alg2 / (k2 * 1e-3) / 1e9, "frac": alg2 / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "dtype": "f64 arithmetic, f32 tables" if other == ara.ARA_F32 else "f64"},
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 
