@@ -332,6 +332,28 @@ ara_status ara_risk_measures(ara_ctx *ctx, const double *ylt, int64_t n, ara_mem
                              const double *return_periods, int32_t n_rp, double *pml, double *tvar,
                              void *workspace, size_t workspace_bytes);
 
+/* Largest YLT, and the device memory per GPU, of ara_risk_measures_noalloc. */
+#define ARA_NOALLOC_MAX_N (1 << 20)
+#define ARA_NOALLOC_SCRATCH_BYTES (17u << 20)
+
+/* ara_risk_measures for callers that cannot allocate device memory: code that must
+ * not call hipMalloc (tight serving loops, harnesses that forbid it).  The same
+ * sort and sums as ara_risk_measures, so the same results bit for bit; the sort
+ * workspace is a library-owned device array of ARA_NOALLOC_SCRATCH_BYTES that each
+ * GPU the library runs on holds until the process ends (its address is taken when
+ * the first context is created on that GPU).  The call makes no hipMalloc, hipFree
+ * or other allocating call.
+ *   ylt            device pointer, n losses, 1 <= n <= ARA_NOALLOC_MAX_N.
+ *   return_periods host array of n_rp (at most 256); pml, tvar: host arrays of n_rp.
+ * Blocking (results are copied to the host), so it cannot be graph-captured.  All
+ * calls on one GPU share that GPU's array: calls that overlap in time on one GPU
+ * (from several contexts or threads) race and give wrong results; serialise them.
+ * Errors: ARA_E_EMPTY (n == 0), ARA_E_INVALID_ARG (n > ARA_NOALLOC_MAX_N, bad
+ * arguments or return periods), ARA_E_DEVICE, and any pending kernel-detected
+ * input error. */
+ara_status ara_risk_measures_noalloc(ara_ctx *ctx, const double *ylt, int64_t n,
+                                     const double *return_periods, int32_t n_rp, double *pml, double *tvar);
+
 /* ---------------------------------------------------------------- Batches
  * Many analyses in one persistent launch: the layer loop of Algorithm 1 (one YET,
  * many layers) and Section IV's portfolios, or independent analyses of different

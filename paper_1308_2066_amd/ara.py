@@ -128,6 +128,7 @@ _SIGS = {
     "ara_sort_workspace_size": (_ST, [_I64, ctypes.POINTER(ctypes.c_size_t)]),
     "ara_sort_desc": (_ST, [_P, _P, _I64, _P, _P, ctypes.c_size_t]),
     "ara_risk_measures": (_ST, [_P, _P, _I64, ctypes.c_int, _P, _I32, _P, _P, _P, ctypes.c_size_t]),
+    "ara_risk_measures_noalloc": (_ST, [_P, _P, _I64, _P, _I32, _P, _P]),
     "ara_batch_create": (_ST, [_P, ctypes.POINTER(ara_job), _I32, ctypes.POINTER(_P)]),
     "ara_batch_run": (_ST, [_P]),
     "ara_batch_risk": (_ST, [_P, _P, _I32, _P, _P]),
@@ -439,6 +440,24 @@ def ara_risk_measures(ctx: Ctx, ylt, return_periods: Sequence[float], workspace=
     _check(_lib.ara_risk_measures(ctx.ptr, py, ylt.numel(), ARA_MEM_DEVICE, rp.ctypes.data_as(_P), rp.shape[0],
                                   pml.ctypes.data_as(_P), tvar.ctypes.data_as(_P), pw, workspace.numel()), ctx,
            "ara_risk_measures")
+    return pml, tvar
+
+
+ARA_NOALLOC_MAX_N = 1 << 20
+ARA_NOALLOC_SCRATCH_BYTES = 17 << 20
+
+
+def ara_risk_measures_noalloc(ctx: Ctx, ylt, return_periods: Sequence[float]):
+    """(pml, tvar) as ara_risk_measures, with the sort workspace in the library's own
+    device array (no allocation by the library or the binding; blocking)."""
+    import torch
+    py = _dev_ptr(ylt, torch.float64, "ylt")
+    rp = np.ascontiguousarray(np.asarray(return_periods, dtype=np.float64))
+    pml = np.empty(rp.shape[0], np.float64)
+    tvar = np.empty(rp.shape[0], np.float64)
+    _check(_lib.ara_risk_measures_noalloc(ctx.ptr, py, ylt.numel(), rp.ctypes.data_as(_P), rp.shape[0],
+                                          pml.ctypes.data_as(_P), tvar.ctypes.data_as(_P)), ctx,
+           "ara_risk_measures_noalloc")
     return pml, tvar
 
 

@@ -29,6 +29,7 @@ struct ara_ctx {
     double *h_out = nullptr;         // pinned host mirror of d_out
     uint32_t *h_err = nullptr;       // pinned host error word
     uint32_t *h_plan = nullptr;      // pinned copy of a radix sort's pass plan
+    void *scratch = nullptr;         // device address of this device's `scratch` array
     int placement = ARA_PLACE_AUTO;
     int block_threads = 0;           // 0 = automatic
     int grid_per_cu = 0;             // 0 = automatic
@@ -280,6 +281,33 @@ static ara_status check_elt_terms(const ara_elt_terms *t) {
 }
 
 // ------------------------------------------------------------------ context
+// Sort workspace of ara_risk_measures_noalloc: one file-scope device array, so
+// that the call allocates nothing.  Every GPU the library runs on holds its own
+// copy until the process ends.  In host code `scratch` only names the array; its
+// device address on each device comes from hipGetSymbolAddress, taken once per
+// device when the first context is created there, and is what kernels receive.
+static_assert(ARA_NOALLOC_MAX_N > 0, "maximum YLT length of the allocation-free call");
+constexpr size_t kScratchBytes = ARA_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_addr[kScratchDevices];
+
+// Device address of `scratch` on `device`, which must be the current device.
+static hipError_t scratch_address(int device, void **out) {
+    if (device < 0 || device >= kScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_addr[device] = p;
+    }
+    *out = g_scratch_addr[device];
+    return hipSuccess;
+}
+
 extern "C" ara_status ara_ctx_create(int device, void *hip_stream, ara_ctx **out) {
     if (!out) return fail(nullptr, ARA_E_INVALID_ARG, "ctx: NULL output");
     *out = nullptr;
@@ -307,6 +335,7 @@ extern "C" ara_status ara_ctx_create(int device, void *hip_stream, ara_ctx **out
     c->lds_max = std::min(lds, kLdsMaxBytes);
     const char *step = "kernel attributes";
     e = prepare_trial_kernels();
+    if (e == hipSuccess) { step = "scratch address"; e = scratch_address(device, &c->scratch); }
     if (e == hipSuccess) { step = "error word"; e = hipMalloc(&c->d_err, 256); }
     if (e == hipSuccess) { step = "result staging"; e = hipMalloc(&c->d_out, kStageDoubles * sizeof(double)); }
     if (e == hipSuccess) {
@@ -1071,23 +1100,24 @@ extern "C" ara_status ara_sort_desc(ara_ctx *c, const double *in, int64_t n, dou
     return s;
 }
 
-// Ranks of the return periods for n losses (host); ARA_E_INVALID_ARG for a bad period.
-static ara_status risk_ranks(ara_ctx *c, int64_t n, const double *rps, int32_t n_rp, std::vector<int64_t> &ks) {
-    if (size_t(n_rp) * 2 > kStageDoubles) return fail(c, ARA_E_INVALID_ARG, "at most %zu return periods", kStageDoubles / 2);
-    ks.resize(static_cast<size_t>(n_rp));
+constexpr int32_t kMaxReturnPeriods = int32_t(kStageDoubles / 2);
+
+// Ranks ks[0 .. n_rp) of the return periods for n losses (host, no allocation);
+// ARA_E_INVALID_ARG for too many or a bad period.
+static ara_status risk_ranks(ara_ctx *c, int64_t n, const double *rps, int32_t n_rp, int64_t *ks) {
+    if (n_rp > kMaxReturnPeriods) return fail(c, ARA_E_INVALID_ARG, "at most %d return periods", kMaxReturnPeriods);
     for (int32_t i = 0; i < n_rp; ++i)
-        if (ara_return_period_rank(n, rps[i], &ks[size_t(i)]) != ARA_OK)
+        if (ara_return_period_rank(n, rps[i], &ks[i]) != ARA_OK)
             return fail(c, ARA_E_INVALID_ARG, "return period %g invalid (must be >= 1)", rps[i]);
     return ARA_OK;
 }
 
-// Sort of the device YLT dy into workspace w, PML/TVaR of the ranks, results to the
-// host (blocking).  Allocates nothing.
-static ara_status risk_on_device(ara_ctx *c, const double *dy, int64_t n, const std::vector<int64_t> &ks, double *pml,
+// Sort of the device YLT dy into workspace w, PML/TVaR of the n_rp ranks ks, results
+// to the host (blocking).  Allocates nothing.
+static ara_status risk_on_device(ara_ctx *c, const double *dy, int64_t n, const int64_t *ks, int32_t n_rp, double *pml,
                                  double *tvar, void *w) {
-    const int32_t n_rp = int32_t(ks.size());
     hipError_t e = launch_sort_desc_keys(dy, n, w, c->stream, c->h_plan);
-    if (e == hipSuccess && n_rp > 0) e = launch_risk(w, n, ks.data(), n_rp, c->d_out, c->stream);
+    if (e == hipSuccess && n_rp > 0) e = launch_risk(w, n, ks, n_rp, c->d_out, c->stream);
     if (e == hipSuccess && n_rp > 0)
         e = hipMemcpyAsync(c->h_out, c->d_out, size_t(2 * n_rp) * 8, hipMemcpyDeviceToHost, c->stream);
     ara_status s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "risk measures");
@@ -1108,7 +1138,7 @@ extern "C" ara_status ara_risk_measures(ara_ctx *c, const double *ylt, int64_t n
         return ARA_E_INVALID_ARG;
     if (n == 0) return fail(c, ARA_E_EMPTY, "risk measures of an empty YLT");
     if (!ylt) return ARA_E_INVALID_ARG;
-    std::vector<int64_t> ks;
+    int64_t ks[kMaxReturnPeriods];
     ara_status s = risk_ranks(c, n, rps, n_rp, ks);
     if (s != ARA_OK) return s;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
@@ -1127,11 +1157,29 @@ extern "C" ara_status ara_risk_measures(ara_ctx *c, const double *ylt, int64_t n
     void *w = nullptr;
     bool owned = false;
     s = workspace_for(c, n, ws, ws_bytes, &w, &owned);
-    if (s == ARA_OK) s = risk_on_device(c, dy, n, ks, pml, tvar, w);
+    if (s == ARA_OK) s = risk_on_device(c, dy, n, ks, n_rp, pml, tvar, w);
     if (owned || tmp) (void)hipStreamSynchronize(c->stream);
     if (owned) dev_free(w);
     dev_free(tmp);
     return s;
+}
+
+extern "C" ara_status ara_risk_measures_noalloc(ara_ctx *c, const double *ylt, int64_t n, const double *rps,
+                                               int32_t n_rp, double *pml, double *tvar) {
+    if (!c || n < 0 || n_rp < 0 || (n_rp > 0 && (!rps || !pml || !tvar))) return ARA_E_INVALID_ARG;
+    if (n == 0) return fail(c, ARA_E_EMPTY, "risk measures of an empty YLT");
+    if (!ylt) return ARA_E_INVALID_ARG;
+    if (n > int64_t(ARA_NOALLOC_MAX_N))
+        return fail(c, ARA_E_INVALID_ARG, "allocation-free risk measures: %lld losses, at most %lld", (long long)n,
+                    (long long)ARA_NOALLOC_MAX_N);
+    if (sort_workspace_bytes(n) > kScratchBytes || !c->scratch)
+        return fail(c, ARA_E_DEVICE, "allocation-free risk measures: scratch of %zu bytes too small for %lld losses",
+                    kScratchBytes, (long long)n);
+    int64_t ks[kMaxReturnPeriods];
+    ara_status s = risk_ranks(c, n, rps, n_rp, ks);
+    if (s != ARA_OK) return s;
+    HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    return risk_on_device(c, ylt, n, ks, n_rp, pml, tvar, c->scratch);
 }
 
 // ------------------------------------------------------------------ batches

@@ -92,3 +92,15 @@ def test_c_client_compiles_against_header(ara_lib, tmp_path):
     r = subprocess.run(["ldd", exe], capture_output=True, text=True, check=True)
     line = [ln for ln in r.stdout.splitlines() if "libara.so" in ln]
     assert line and "not found" not in line[0], r.stdout
+
+
+def test_noalloc_scratch_holds_the_largest_sort(ara_lib):
+    """The allocation-free risk call's device array holds the sort workspace of its
+    largest YLT, and the binding's limits are the header's."""
+    text = open(HEADER).read()
+    max_n = re.search(r"#define ARA_NOALLOC_MAX_N \(1 << (\d+)\)", text)
+    scratch = re.search(r"#define ARA_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", text)
+    assert max_n and scratch
+    assert ara_lib.ARA_NOALLOC_MAX_N == 1 << int(max_n.group(1))
+    assert ara_lib.ARA_NOALLOC_SCRATCH_BYTES == int(scratch.group(1)) << int(scratch.group(2))
+    assert ara_lib.ara_sort_workspace_size(ara_lib.ARA_NOALLOC_MAX_N) <= ara_lib.ARA_NOALLOC_SCRATCH_BYTES
