@@ -541,14 +541,33 @@ def bench_uneven(args):
     import synth
     from paper_1308_2066_amd import ara, session
 
-    t = time.time()
-    ws = synth.uneven_analyses(n=args.analyses)
-    ev = sum(w.n_events for w in ws)
-    log(f"generated {len(ws)} analyses, {ev} events in {time.time() - t:.1f}s")
     torch.cuda.set_device(0)
     ctx = ara.ara_ctx_create(0, torch.cuda.current_stream())
-    opened = [session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms)
-              for w in ws]
+    # generated one analysis at a time and kept on the device only (the full set is
+    # about 3.5e10 occurrences)
+    t = time.time()
+    shapes, opened = [], []
+    stopped = None
+    for w in synth.iter_uneven_analyses(n=args.analyses):
+        try:
+            opened.append(session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts,
+                                                w.layer_terms))
+        except (ara.AraError, torch.cuda.OutOfMemoryError) as exc:   # the largest set that fits
+            stopped = f"analysis {len(opened)} did not fit: {exc}"
+            log(stopped)
+            break
+        shapes.append((w.n_trials, w.n_events, w.catalog_size, len(w.elts)))
+        if len(opened) % 32 == 0:
+            log(f"{len(opened)} analyses resident ({time.time() - t:.1f}s)")
+    ev = sum(sh[1] for sh in shapes)
+    torch.cuda.synchronize()
+    log(f"generated and ingested {len(opened)} analyses, {ev} events in {time.time() - t:.1f}s")
+
+    class _W:   # the sizes the rest of this function reads
+        def __init__(self, sh):
+            self.n_trials, self.n_events, self.catalog_size, self.n_elts = sh
+
+    ws = [_W(sh) for sh in shapes]
     outs = [torch.empty(w.n_trials, dtype=torch.float64, device="cuda") for w in ws]
     plain = [torch.empty(w.n_trials, dtype=torch.float64, device="cuda") for w in ws]
     b = ara.ara_batch_create(ctx, [(an.yet, an.layer, 0, w.n_trials, o) for an, w, o in zip(opened, ws, outs)])
@@ -592,6 +611,7 @@ def bench_uneven(args):
         "data": "synthetic",
         "config": {"workload": f"{len(ws)} analyses: trials log-uniform 1e4-5e5, Poisson(200-2000) events, catalogs "
                                f"1e5-1e6, 1-16 ELTs x 20000 lognormal(10,2); {ev} events", "analyses": len(ws),
+                   "analyses_requested": args.analyses, "stopped": stopped,
                    "events": ev, "trials": trials, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": alg / (ms_b * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": alg, "moved_bytes": moved},

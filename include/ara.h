@@ -402,13 +402,25 @@ ara_status ara_batch_risk(ara_batch *batch, const double *return_periods, int32_
  * Errors: ARA_E_INVALID_ARG (no jobs, or jobs of different trial counts). */
 ara_status ara_batch_portfolio(ara_batch *batch, double *out);
 
+/* The context's batch schedules (the tuner's choice per batch shape: jobs' kernels,
+ * trial counts, mean trial lengths and catalogs) written to a text file, or read
+ * from one into the context, so that batches of a known shape skip the tuning runs
+ * in a later process.  A loaded entry replaces the context's entry for its shape.
+ * Host only.  Errors: ARA_E_INVALID_ARG (NULL arguments, a file that cannot be
+ * opened or written, a malformed line: then nothing is loaded). */
+ara_status ara_tune_cache_save(const ara_ctx *ctx, const char *path);
+ara_status ara_tune_cache_load(ara_ctx *ctx, const char *path);
+
 /* The tuned schedule: work items, workgroups, occurrences per item, and in `graph`
  * bit 0 = runs replay a graph, bit 1 = workgroups take every G-th item (G workgroups)
  * rather than a contiguous run, so the grid works on few jobs at a time and their
- * tables share the L2.  Items and workgroups count the persistent launches only: a job
- * whose placement is ARA_PLACE_LDS_TILES (as ara_analyze would choose it) runs as a
- * launch of the tiled kernel of its own and adds no items (a batch of only such jobs
- * reports 0 and 0).  Any output pointer may be NULL. */
+ * tables share the L2.  Items and workgroups count the persistent launches of the
+ * dense and filter placements only: the jobs whose placement is ARA_PLACE_LDS_TILES (as
+ * ara_analyze would choose it) run together in one more launch of the tiled kernel,
+ * whose items are the passes ara_analyze's launch would run for each of them (so the
+ * same YLT bits), costliest first, taken from a counter by whichever workgroup is free;
+ * they add nothing here (a batch of only such jobs reports 0 and 0).  Any output
+ * pointer may be NULL. */
 ara_status ara_batch_info(const ara_batch *batch, int32_t *n_items, int32_t *grid, int64_t *events_per_item,
                           int32_t *graph);
 

@@ -137,6 +137,8 @@ _SIGS = {
     "ara_batch_info": (_ST, [_P, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I64),
                              ctypes.POINTER(_I32)]),
     "ara_batch_release": (_ST, [_P]),
+    "ara_tune_cache_save": (_ST, [_P, ctypes.c_char_p]),
+    "ara_tune_cache_load": (_ST, [_P, ctypes.c_char_p]),
     "ara_server_create": (_ST, [_P, _P, ctypes.POINTER(_P), _I32, ctypes.POINTER(ara_server_config),
                                 ctypes.POINTER(_P)]),
     "ara_server_submit": (_ST, [_P, _P, _I32, ctypes.POINTER(ara_layer_terms), _I64, _I64,
@@ -536,6 +538,16 @@ def ara_batch_info(b: Batch):
     _check(_lib.ara_batch_info(b.ptr, ctypes.byref(n), ctypes.byref(g), ctypes.byref(e), ctypes.byref(gr)), b.ctx,
            "ara_batch_info")
     return int(n.value), int(g.value), int(e.value), int(gr.value)
+
+
+def ara_tune_cache_save(ctx: Ctx, path: str):
+    """Writes the context's tuned batch schedules to a text file."""
+    _check(_lib.ara_tune_cache_save(ctx.ptr, os.fsencode(path)), ctx, "ara_tune_cache_save")
+
+
+def ara_tune_cache_load(ctx: Ctx, path: str):
+    """Reads tuned batch schedules from a file written by ara_tune_cache_save."""
+    _check(_lib.ara_tune_cache_load(ctx.ptr, os.fsencode(path)), ctx, "ara_tune_cache_load")
 
 
 def ara_batch_release(b: Batch):

@@ -1112,12 +1112,11 @@ static ara_status risk_ranks(ara_ctx *c, int64_t n, const double *rps, int32_t n
     return ARA_OK;
 }
 
-// Sort of the device YLT dy into workspace w, PML/TVaR of the n_rp ranks ks, results
-// to the host (blocking).  Allocates nothing.
+// PML/TVaR of the n_rp ranks ks of the device YLT dy (radix selection in workspace
+// w), results to the host (blocking).  Allocates nothing.
 static ara_status risk_on_device(ara_ctx *c, const double *dy, int64_t n, const int64_t *ks, int32_t n_rp, double *pml,
                                  double *tvar, void *w) {
-    hipError_t e = launch_sort_desc_keys(dy, n, w, c->stream, c->h_plan);
-    if (e == hipSuccess && n_rp > 0) e = launch_risk(w, n, ks, n_rp, c->d_out, c->stream);
+    hipError_t e = launch_risk_select(dy, n, w, ks, n_rp, c->d_out, c->stream);
     if (e == hipSuccess && n_rp > 0)
         e = hipMemcpyAsync(c->h_out, c->d_out, size_t(2 * n_rp) * 8, hipMemcpyDeviceToHost, c->stream);
     ara_status s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "risk measures");
@@ -1188,8 +1187,12 @@ struct ara_batch {
     std::vector<ara_job> jobs;
     std::vector<BatchJob> hjobs;
     std::vector<int64_t> mean_len;   // per job: occurrences per trial of its YET (at least 1)
-    std::vector<std::pair<TiledArgs, int>> tiled;   // jobs run by the tiled kernel, with their grids
-    std::vector<int32_t> tiled_job;  // the job of each entry of `tiled`
+    std::vector<TiledArgs> tjobs;    // jobs run by the tiled kernel: their arguments
+    std::vector<int32_t> tiled_job;  // the job of each entry of `tjobs`
+    std::vector<TiledItem> titems;   // their passes (tjobs indices), one launch for all
+    TiledArgs *d_tjobs = nullptr;
+    TiledItem *d_titems = nullptr;
+    uint32_t *d_next = nullptr;      // the tiled launch's item counter
     std::vector<uint64_t> terms_gen; // per job: its layer's terms generation when last uploaded
     std::string shape;               // key of the tuning cache
     BatchJob *d_jobs = nullptr;
@@ -1246,9 +1249,16 @@ static void batch_shape(int32_t n_items, int n_cu, int32_t &grid, int32_t &per_w
 // One persistent launch per mode present, in mode order; interleave: workgroups take
 // every G-th item instead of a contiguous run.  Jobs of the tiled kernel follow, one
 // launch each.
+struct TiledBatch {
+    const TiledArgs *jobs = nullptr;
+    const TiledItem *items = nullptr;
+    int32_t n_items = 0;
+    uint32_t *next = nullptr;
+};
+
 static hipError_t launch_grouped(const BatchJob *d_jobs, const BatchItem *d_items, const int32_t *off,
                                  const int32_t *cnt, int n_cu, bool interleave, hipStream_t s,
-                                 const std::vector<std::pair<TiledArgs, int>> &tiled) {
+                                 const std::vector<std::pair<TiledArgs, int>> &tiled, const TiledBatch &tb = TiledBatch()) {
     for (int m = 0; m < kBatchModes; ++m) {
         if (cnt[m] == 0) continue;
         int32_t grid = 1, per_wg = 0;
@@ -1264,7 +1274,35 @@ static hipError_t launch_grouped(const BatchJob *d_jobs, const BatchItem *d_item
         const hipError_t e = launch_trial_tiled(ta.first, ta.second, s);
         if (e != hipSuccess) return e;
     }
+    if (tb.n_items > 0)
+        return launch_trial_tiled_items(tb.jobs, tb.items, tb.n_items, tb.next, std::min(tb.n_items, n_cu), s);
     return hipSuccess;
+}
+
+static TiledBatch batch_tiled(const ara_batch *b) {
+    TiledBatch t;
+    t.jobs = b->d_tjobs;
+    t.items = b->d_titems;
+    t.n_items = int32_t(b->titems.size());
+    t.next = b->d_next;
+    return t;
+}
+
+// The passes k_trial_tiled runs for a job of `grid` workgroups (trials [tb, te)), as
+// items of job index k, each with its cost (occurrences, plus a tile staging).
+static void tiled_passes(int32_t k, int64_t tb, int64_t te, int grid, double mean_len, double stage,
+                         std::vector<std::pair<double, TiledItem>> &out) {
+    const int64_t per_wg = (te - tb + grid - 1) / std::max(1, grid);
+    for (int w = 0; w < grid; ++w) {
+        const int64_t w0 = tb + int64_t(w) * per_wg, w1 = std::min(w0 + per_wg, te);
+        for (int64_t p = w0; p < w1; p += kTiledPassTrials) {
+            TiledItem it{};
+            it.job = k;
+            it.t0 = p;
+            it.t1 = std::min(p + int64_t(kTiledPassTrials), w1);
+            out.emplace_back(double(it.t1 - it.t0) * mean_len + stage, it);
+        }
+    }
 }
 
 static ara_status batch_set_items(ara_batch *b, int64_t events) {
@@ -1303,6 +1341,7 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
     if (!b) return ARA_E_OOM;
     b->ctx = c;
     char key[160];
+    std::vector<std::pair<double, TiledItem>> titems;
     for (int32_t j = 0; j < n_jobs; ++j) {
         const ara_job &jb = jobs[j];
         ara_status s = check_analysis(c, jb.yet, jb.layer, jb.trial_begin, jb.trial_end);
@@ -1320,8 +1359,10 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
         h.mode = batch_mode(tl, h.a.ids24 != nullptr);
         h.placement = tl.placement;
         if (h.mode == kModeTiled && jb.trial_end > jb.trial_begin) {
-            b->tiled.emplace_back(tiled_args(jb.yet, jb.layer, jb.trial_begin, jb.trial_end, jb.ylt, tl.grid), tl.grid);
+            b->tjobs.push_back(tiled_args(jb.yet, jb.layer, jb.trial_begin, jb.trial_end, jb.ylt, tl.grid));
             b->tiled_job.push_back(j);
+            tiled_passes(int32_t(b->tjobs.size() - 1), jb.trial_begin, jb.trial_end, tl.grid, mean,
+                         kTiledStageCost * double(jb.layer->catalog), titems);
         }
         b->terms_gen.push_back(jb.layer->terms_gen);
         b->jobs.push_back(jb);
@@ -1339,6 +1380,23 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
             if (e != hipSuccess) s = hip_fail(c, e, "batch jobs upload");
         }
     }
+    if (s == ARA_OK && !titems.empty()) {
+        // costliest passes first, so that the last ones taken are short
+        std::stable_sort(titems.begin(), titems.end(),
+                         [](const std::pair<double, TiledItem> &x, const std::pair<double, TiledItem> &y) {
+                             return x.first > y.first;
+                         });
+        for (const auto &it : titems) b->titems.push_back(it.second);
+        s = dev_alloc(c, &b->d_tjobs, b->tjobs.size() * sizeof(TiledArgs), "batch tiled jobs");
+        if (s == ARA_OK) s = dev_alloc(c, &b->d_titems, b->titems.size() * sizeof(TiledItem), "batch tiled items");
+        if (s == ARA_OK) s = dev_alloc(c, &b->d_next, 256, "batch tiled counter");
+        if (s == ARA_OK) {
+            hipError_t e = hipMemcpy(b->d_tjobs, b->tjobs.data(), b->tjobs.size() * sizeof(TiledArgs), hipMemcpyHostToDevice);
+            if (e == hipSuccess)
+                e = hipMemcpy(b->d_titems, b->titems.data(), b->titems.size() * sizeof(TiledItem), hipMemcpyHostToDevice);
+            if (e != hipSuccess) s = hip_fail(c, e, "batch tiled upload");
+        }
+    }
     if (s != ARA_OK) {
         ara_batch_release(b);
         return s;
@@ -1353,6 +1411,8 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
 // keep the fastest for this batch shape, then capture the launch in a graph that
 // later runs replay on the context's stream.  *computed: whether the timed runs
 // wrote every job's YLT (not so when the shape was already tuned on this context).
+constexpr int kTuneReps = 3;   // timings of each candidate (the fastest counts)
+
 static ara_status batch_tune(ara_batch *b, bool *computed) {
     ara_ctx *c = b->ctx;
     *computed = false;
@@ -1362,6 +1422,17 @@ static ara_status batch_tune(ara_batch *b, bool *computed) {
         return batch_set_items(b, it->second.first);
     }
     static const int64_t kEvents[] = {int64_t(1) << 16, int64_t(1) << 18, int64_t(1) << 20, int64_t(1) << 22};
+    {
+        ara_status s0 = batch_set_items(b, kEvents[0]);
+        if (s0 != ARA_OK) return s0;
+        int32_t persistent = 0;
+        for (int m = 0; m < kBatchModes; ++m) persistent += b->mode_cnt[m];
+        if (persistent == 0) {   // only tiled jobs: nothing to choose
+            c->tuned[b->shape] = {kEvents[0], false};
+            b->interleave = false;
+            return ARA_OK;
+        }
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_OR_RETURN(c, hipEventCreate(&e0), "event");
     hipError_t e = hipEventCreate(&e1);
@@ -1376,18 +1447,21 @@ static ara_status batch_tune(ara_batch *b, bool *computed) {
         s = batch_set_items(b, ev);
         if (s != ARA_OK) break;
         for (bool inter : {false, true}) {
-            e = hipEventRecord(e0, c->stream);
-            if (e == hipSuccess)
-                e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, inter, c->stream, b->tiled);
-            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float ms = 0.f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e != hipSuccess) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = {ev, inter};
+            for (int rep = 0; rep < kTuneReps && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, c->stream);
+                if (e == hipSuccess)
+                    e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, inter, c->stream, {},
+                                       batch_tiled(b));
+                if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && ms < best_ms) {
+                    best_ms = ms;
+                    best = {ev, inter};
+                }
             }
+            if (e != hipSuccess) break;
         }
         if (e != hipSuccess) {
             s = hip_fail(c, e, "batch tuning run");
@@ -1409,7 +1483,8 @@ static ara_status batch_capture(ara_batch *b) {
     ara_ctx *c = b->ctx;
     HIP_OR_RETURN(c, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking), "capture stream");
     HIP_OR_RETURN(c, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal), "begin capture");
-    hipError_t e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, b->interleave, b->cap, b->tiled);
+    hipError_t e = launch_grouped(b->d_jobs, b->d_items, b->mode_off, b->mode_cnt, c->n_cu, b->interleave, b->cap, {},
+                                  batch_tiled(b));
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(b->cap, &g);
     if (e == hipSuccess) e = e2;
@@ -1419,9 +1494,9 @@ static ara_status batch_capture(ara_batch *b) {
     return e == hipSuccess ? ARA_OK : hip_fail(c, e, "batch graph");
 }
 
-// Layer terms are copied into the job descriptors and the tiled launches' arguments:
-// after ara_layer_set_terms on a member layer, refresh both (and re-capture the graph,
-// whose tiled launches hold their arguments by value).
+// Layer terms are copied into the job descriptors and the tiled jobs' arguments, both
+// in device memory that the captured launches read: after ara_layer_set_terms on a
+// member layer, upload them again.
 static ara_status batch_refresh_terms(ara_batch *b) {
     ara_ctx *c = b->ctx;
     bool changed = false;
@@ -1437,24 +1512,18 @@ static ara_status batch_refresh_terms(ara_batch *b) {
         a.agg_l = L->terms.agg_limit;
     }
     if (!changed) return ARA_OK;
-    for (size_t k = 0; k < b->tiled.size(); ++k) {
+    for (size_t k = 0; k < b->tjobs.size(); ++k) {
         const ara_layer *L = b->jobs[size_t(b->tiled_job[k])].layer;
-        b->tiled[k].first.agg_r = L->terms.agg_retention;
-        b->tiled[k].first.agg_l = L->terms.agg_limit;
+        b->tjobs[k].agg_r = L->terms.agg_retention;
+        b->tjobs[k].agg_l = L->terms.agg_limit;
     }
     // earlier runs on the stream may still read the descriptors
     HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "stream synchronize");
     HIP_OR_RETURN(c, hipMemcpy(b->d_jobs, b->hjobs.data(), b->hjobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice),
                   "batch jobs upload");
-    if (b->exec && !b->tiled.empty()) {
-        (void)hipGraphExecDestroy(b->exec);
-        (void)hipGraphDestroy(b->graph);
-        b->exec = nullptr;
-        b->graph = nullptr;
-        if (b->cap) (void)hipStreamDestroy(b->cap);
-        b->cap = nullptr;
-        return batch_capture(b);
-    }
+    if (!b->tjobs.empty())
+        HIP_OR_RETURN(c, hipMemcpy(b->d_tjobs, b->tjobs.data(), b->tjobs.size() * sizeof(TiledArgs), hipMemcpyHostToDevice),
+                      "batch tiled jobs upload");
     return ARA_OK;
 }
 
@@ -1474,6 +1543,47 @@ extern "C" ara_status ara_batch_run(ara_batch *b) {
         if (computed) return ARA_OK;   // the tuning runs already computed every job
     }
     HIP_OR_RETURN(c, hipGraphLaunch(b->exec, c->stream), "batch graph launch");
+    return ARA_OK;
+}
+
+extern "C" ara_status ara_tune_cache_save(const ara_ctx *c, const char *path) {
+    if (!c || !path) return ARA_E_INVALID_ARG;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return ARA_E_INVALID_ARG;
+    std::fprintf(f, "# libara batch schedules: events per item, interleave, batch shape\n");
+    for (const auto &kv : c->tuned)
+        std::fprintf(f, "%lld %d %s\n", (long long)kv.second.first, kv.second.second ? 1 : 0, kv.first.c_str());
+    const bool ok = std::fflush(f) == 0;
+    std::fclose(f);
+    return ok ? ARA_OK : ARA_E_INVALID_ARG;
+}
+
+extern "C" ara_status ara_tune_cache_load(ara_ctx *c, const char *path) {
+    if (!c || !path) return ARA_E_INVALID_ARG;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(c, ARA_E_INVALID_ARG, "tuning cache %s: cannot open", path);
+    std::map<std::string, std::pair<int64_t, bool>> got;
+    char line[8192];
+    ara_status s = ARA_OK;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n') continue;
+        long long ev = 0;
+        int inter = 0, used = 0;
+        if (std::sscanf(line, "%lld %d %n", &ev, &inter, &used) != 2 || ev < 1 || (inter != 0 && inter != 1)) {
+            s = fail(c, ARA_E_INVALID_ARG, "tuning cache %s: bad line", path);
+            break;
+        }
+        std::string key(line + used);
+        while (!key.empty() && (key.back() == '\n' || key.back() == '\r')) key.pop_back();
+        if (key.empty()) {
+            s = fail(c, ARA_E_INVALID_ARG, "tuning cache %s: line without a shape", path);
+            break;
+        }
+        got[key] = {int64_t(ev), inter != 0};
+    }
+    std::fclose(f);
+    if (s != ARA_OK) return s;
+    for (const auto &kv : got) c->tuned[kv.first] = kv.second;
     return ARA_OK;
 }
 
@@ -1552,9 +1662,9 @@ extern "C" ara_status ara_batch_risk(ara_batch *b, const double *rps, int32_t n_
         b->risk_cap = n_rp;
     }
     HIP_OR_RETURN(c, hipMemcpyAsync(b->d_ks, ks.data(), ks.size() * 8, hipMemcpyHostToDevice, c->stream), "upload ranks");
-    // short YLTs: one workgroup each, all in one launch; long ones: the radix sort
+    // short YLTs: one workgroup each, all in one launch; long ones: radix selection,
+    // one after another in the workspace, each into its own results
     hipError_t e = launch_risk_batch(b->d_ylts, b->d_ns, b->d_ks, nj, n_rp, b->d_risk, c->stream);
-    std::vector<double> h(size_t(nj) * 2 * size_t(n_rp));
     for (int32_t j = 0; j < nj && e == hipSuccess; ++j) {
         const int64_t n = b->jobs[size_t(j)].trial_end - b->jobs[size_t(j)].trial_begin;
         if (n <= kRiskLdsKeys) continue;
@@ -1568,19 +1678,9 @@ extern "C" ara_status ara_batch_risk(ara_batch *b, const double *rps, int32_t n_
             if (e != hipSuccess) break;
             b->ws_bytes = need;
         }
-        e = launch_sort_desc_keys(b->jobs[size_t(j)].ylt, n, b->ws, c->stream, c->h_plan);
-        // groups of 16 return periods, laid out like ara_risk_measures' staging
-        if (e == hipSuccess) e = launch_risk(b->ws, n, &ks[size_t(j) * n_rp], n_rp, c->d_out, c->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(c->h_out, c->d_out, size_t(2 * n_rp) * 8, hipMemcpyDeviceToHost, c->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-        for (int32_t base = 0; base < n_rp && e == hipSuccess; base += 16) {
-            const int32_t m = std::min<int32_t>(16, n_rp - base);
-            for (int32_t i = 0; i < m; ++i) {
-                h[size_t(j) * 2 * n_rp + base + i] = c->h_out[2 * base + i];
-                h[size_t(j) * 2 * n_rp + n_rp + base + i] = c->h_out[2 * base + m + i];
-            }
-        }
+        // groups of 16 return periods: pml[m] then tvar[m] per group
+        e = launch_risk_select(b->jobs[size_t(j)].ylt, n, b->ws, &ks[size_t(j) * n_rp], n_rp,
+                               b->d_risk + size_t(j) * 2 * n_rp, c->stream);
     }
     if (e != hipSuccess) return hip_fail(c, e, "batch risk measures");
     std::vector<double> small(size_t(nj) * 2 * size_t(n_rp));
@@ -1590,10 +1690,16 @@ extern "C" ara_status ara_batch_risk(ara_batch *b, const double *rps, int32_t n_
     if (s != ARA_OK) return s;
     for (int32_t j = 0; j < nj; ++j) {
         const int64_t n = b->jobs[size_t(j)].trial_end - b->jobs[size_t(j)].trial_begin;
-        const double *src = n <= kRiskLdsKeys ? &small[size_t(j) * 2 * n_rp] : &h[size_t(j) * 2 * n_rp];
+        const double *src = &small[size_t(j) * 2 * n_rp];
         for (int32_t r = 0; r < n_rp; ++r) {
-            pml[size_t(j) * n_rp + r] = src[r];
-            tvar[size_t(j) * n_rp + r] = src[n_rp + r];
+            if (n <= kRiskLdsKeys) {   // the batched kernel: pml[n_rp], then tvar[n_rp]
+                pml[size_t(j) * n_rp + r] = src[r];
+                tvar[size_t(j) * n_rp + r] = src[n_rp + r];
+            } else {                   // the selection: per group of 16, pml[m] then tvar[m]
+                const int32_t base = r / 16 * 16, m = std::min<int32_t>(16, n_rp - base), i = r - base;
+                pml[size_t(j) * n_rp + r] = src[2 * base + i];
+                tvar[size_t(j) * n_rp + r] = src[2 * base + m + i];
+            }
         }
     }
     return ARA_OK;
@@ -1609,6 +1715,9 @@ extern "C" ara_status ara_batch_release(ara_batch *b) {
     if (b->cap) (void)hipStreamDestroy(b->cap);
     dev_free(b->d_jobs);
     dev_free(b->d_items);
+    dev_free(b->d_tjobs);
+    dev_free(b->d_titems);
+    dev_free(b->d_next);
     dev_free(b->d_ylts);
     dev_free(b->d_ns);
     dev_free(b->d_ks);
@@ -1768,8 +1877,8 @@ static ara_status server_launch(ara_server *sv, ServerLane &ln, const std::vecto
         e = hipMemcpyAsync(ln.d_items, ln.h_items, sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice, ln.stream);
     if (e == hipSuccess)
         e = launch_grouped(ln.d_jobs, ln.d_items, ln.mode_off, ln.mode_cnt, pc->n_cu, true, ln.stream, tiled);
-    // risk measures: ranks per request, short YLTs in one launch, long ones by the radix
-    // sort (every pass launched: no host read of its plan, so nothing waits here)
+    // risk measures: ranks per request, short YLTs in one launch, long ones by radix
+    // selection (nothing waits on the host here)
     int64_t *hn = ln.h_nks, *hk = ln.h_nks + sv->slots_per_lane;
     for (int32_t i = 0; i < nj; ++i) {
         const int64_t n = take[size_t(i)]->t1 - take[size_t(i)]->t0;
@@ -1783,8 +1892,8 @@ static ara_status server_launch(ara_server *sv, ServerLane &ln, const std::vecto
     if (e == hipSuccess) e = launch_risk_batch(ln.d_ylts, ln.d_ns, ln.d_ks, nj, nr, ln.d_res, ln.stream);
     for (int32_t i = 0; i < nj && e == hipSuccess; ++i) {
         if (hn[i] <= kRiskLdsKeys) continue;
-        e = launch_sort_desc_keys(ln.h_ylts[i], hn[i], ln.ws, ln.stream, nullptr);
-        if (e == hipSuccess) e = launch_risk(ln.ws, hn[i], &hk[size_t(i) * nr], nr, ln.d_res + size_t(i) * 2 * nr, ln.stream);
+        e = launch_risk_select(ln.h_ylts[i], hn[i], ln.ws, &hk[size_t(i) * nr], nr, ln.d_res + size_t(i) * 2 * nr,
+                               ln.stream);
     }
     if (e == hipSuccess)
         e = hipMemcpyAsync(ln.h_res, ln.d_res, sizeof(double) * 2 * size_t(nr) * nj, hipMemcpyDeviceToHost, ln.stream);

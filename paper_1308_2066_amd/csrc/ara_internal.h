@@ -197,7 +197,10 @@ struct Tile {
 };
 constexpr int kTiledWaves = 16;                 // waves per workgroup of the tiled kernel
 constexpr int kTiledQueue = 256;                // per-wave queue of flagged occurrences
-constexpr int kTiledWaveTrials = 256;           // trials per wave and pass (an LDS sum each)
+constexpr int kTiledWaveTrials = 256;           // LDS sums per wave (at least the trials per wave and pass)
+constexpr int kTiledPassTrials = 252 * kTiledWaves;   // trials per workgroup pass of the tiled kernel
+constexpr double kTiledStageCost = 0.25;        // a pass's tile staging, in occurrences per catalog event
+                                                // (orders a batch's passes; results do not depend on it)
 // LDS left for the tile after the per-wave queues (and a write slot per lane) and
 // per-trial sums
 constexpr int kTiledLdsBytes = kLdsMaxBytes - kTiledWaves * ((kTiledQueue + 64) * 4 + kTiledWaveTrials * 8);
@@ -231,13 +234,27 @@ struct TiledArgs {
 };
 // occ_max: each trial's largest occurrence-net loss into a.ylt instead of the YLT
 hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s, bool occ_max = false);
+// A pass of the tiled kernel as a work item: analysis `job`, trials [t0, t1).
+struct TiledItem {
+    int32_t job;
+    int32_t pad_;
+    int64_t t0, t1;
+};
+static_assert(sizeof(TiledItem) == 24, "six words");
+// The YLTs of many analyses' passes in one launch (device arrays; `next`: one word of
+// device memory, cleared by a fill kernel first, so the launch can be graph-captured).
+hipError_t launch_trial_tiled_items(const TiledArgs *jobs, const TiledItem *items, int32_t n_items, uint32_t *next,
+                                    int grid, hipStream_t s);
 
 // ---- order statistics
 size_t sort_workspace_bytes(int64_t n);
 hipError_t launch_sort_desc_keys(const double *in, int64_t n, void *ws, hipStream_t s,
                                  uint32_t *host_plan = nullptr);   // sorted keys -> ws
 hipError_t launch_sort_decode(const void *ws, int64_t n, double *out, hipStream_t s);
-hipError_t launch_risk(const void *ws, int64_t n, const int64_t *ks, int n_k, double *out_pml_tvar,
-                       hipStream_t s);
+// PML/TVaR of the n losses y (device) at ranks ks[0, n_k) by radix selection (no
+// sort): out holds, per group of up to 16 ranks, pml[m] then tvar[m].  ws: a sort
+// workspace for n.  Asynchronous; no host waits.
+hipError_t launch_risk_select(const double *y, int64_t n, void *ws, const int64_t *ks, int n_k, double *out_pml_tvar,
+                              hipStream_t s);
 
 }  // namespace ara

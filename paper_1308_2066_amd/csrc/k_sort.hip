@@ -3,6 +3,9 @@
 // the return period (the paper names both measures, Section I, but does not define
 // them; the engine's rank rule is ara_return_period_rank).
 //
+// PML and TVaR need no full sort (risk measures by selection, below); the sort is
+// kept for ara_sort_desc.
+//
 // LSD radix sort of 64-bit keys, 8-bit digits, 8 passes.  A binary64 value maps to
 // an unsigned key whose order is the value order (sign flip for non-negatives,
 // complement for negatives, -0.0 canonicalised to +0.0); descending order sorts the
@@ -50,12 +53,11 @@ struct SortWs {
     uint32_t *dtotal;   // [256] keys per digit in the current pass (in the second half of hist)
     uint32_t *plan;     // plan[p]: keys before pass p are in b (1) or a (0), p = 0..8;
                         // plan[16 + p]: pass p is skipped
-    double *part;       // [kRiskGroup][kRiskMaxBlocks] partial sums of the top-k keys
+    double *part;       // kRiskGroup * kRiskMaxBlocks doubles: the selection's digit counts
 };
 
 constexpr int kRiskGroup = 16;        // return periods per launch
 constexpr int kRiskMaxBlocks = 1024;  // partial sums per return period
-constexpr int kRiskChunk = 2048;      // keys per partial sum, at least (8 per thread)
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -350,95 +352,237 @@ hipError_t launch_sort_decode(const void *ws, int64_t n, double *out, hipStream_
     return hipGetLastError();
 }
 
-// PML = the k-th largest, TVaR = the mean of the k largest.  The top k keys are
-// summed in fixed chunks (one workgroup each, fixed stride and LDS tree), then the
-// chunk sums in chunk order: the result does not depend on scheduling.
-struct RiskKs {
-    int64_t k[kRiskGroup];
-    int64_t chunk[kRiskGroup];
+// ---------------------------------------------------------------------------------
+// Risk measures by radix selection.  PML(rp) = the k-th largest loss and TVaR(rp) =
+// the mean of the k largest, k = ara_return_period_rank(n, rp).  In descending-order
+// keys PML is the k-th smallest key K.  K is found digit by digit from the most
+// significant 8 bits down: pass p counts, for every rank, digit p of the keys that
+// share the digits chosen so far; the next kernel (every workgroup of it, from the
+// complete counts) picks the digit where the running count reaches the rank, and the
+// rank left within that digit carries on.  A digit in which every key agrees (the OR
+// of key ^ first key is zero there) is not counted.  The k largest losses are then
+// the losses whose key is below K, plus (k - their number) copies of PML, so
+//   TVaR = (sum of the losses whose key is below K + r * PML) / k,
+// r = the rank left after the last digit.  That sum is taken in a fixed order:
+// per tile of 2048 losses in index order, 256 slots (slot t adds the tile's losses
+// t, t + 256, ..., t + 1792 in turn; the others add +0.0) and a fixed tree over the
+// slots; then the tile sums, slot t adding tiles t, t + 256, ... in turn, and the
+// same tree.  k_risk_batch forms the same sums, so the batched and plain results
+// agree bit for bit.  Kernel boundaries order every step: no workgroup waits on
+// another.
+constexpr int kSelPerThread = 4;
+constexpr int kSelThreads = 1024;
+constexpr int kSelBlocks = 256;                         // most workgroups of a counting pass
+constexpr int kSelChunk = kSelThreads * kSelPerThread;  // keys per workgroup and round
+constexpr int kSelTile = 2048;                          // losses per tile of the TVaR sum
+static_assert(kSelTile == 8 * 256, "a tile is 8 losses for each of 256 slots");
+static_assert(kPasses * kRiskGroup * 256 * 4 <= kRiskGroup * kRiskMaxBlocks * 8, "selection counts fit the part region");
+static_assert(kSelTile == kSortTile && kRiskGroup * 8 <= 256 * 4, "tile sums fit the sort's per-tile counts");
+
+struct SelWs {
+    uint64_t *slots;    // [kSelBlocks]: OR over a workgroup's keys of key ^ (key of the first loss)
+    uint64_t *prefix;   // [kPasses + 1][kRiskGroup]: digits chosen before pass p (where keys differ)
+    int64_t *left;      // [kPasses + 1][kRiskGroup]: rank left among the keys that share them
+    uint32_t *count;    // [kPasses][kRiskGroup][256] digit counts
+    double *tile_sum;   // [kRiskGroup][tiles]
 };
 
-__device__ __forceinline__ double block_sum(double s, double *part) {
-    part[threadIdx.x] = s;
+// The selection's tables in the sort workspace (the sort's key buffers are unused).
+static SelWs sel_ws(void *ws, int64_t n) {
+    const SortWs w = sort_ws(ws, n);
+    SelWs q;
+    q.slots = reinterpret_cast<uint64_t *>(w.hist);
+    q.prefix = reinterpret_cast<uint64_t *>(w.hist + 1280);
+    q.left = reinterpret_cast<int64_t *>(w.hist + 1280 + 2 * kRiskGroup * (kPasses + 1));
+    q.count = reinterpret_cast<uint32_t *>(w.part);
+    q.tile_sum = reinterpret_cast<double *>(w.counts);
+    return q;
+}
+static_assert(1280 + 4 * kRiskGroup * (kPasses + 1) <= 2048, "selection state fits the 8 KB table");
+
+struct SelKs {
+    int64_t k[kRiskGroup];
+    int m;              // ranks in this group
+    int n_slots;        // workgroups of the counting passes (OR slots written)
+};
+
+// Digits (8 bits each) in which some key differs from the first: 0xFF in every such digit.
+__device__ __forceinline__ uint64_t varying_digits(uint64_t d) {
+    uint64_t m = 0;
+#pragma unroll
+    for (int p = 0; p < kPasses; ++p)
+        if ((d >> (8 * p)) & 255u) m |= 0xFFull << (8 * p);
+    return m;
+}
+
+// OR of the workgroups' slots (d: this thread's share), in every thread (after a barrier).
+__device__ __forceinline__ uint64_t slots_or(uint64_t d, uint64_t *lds) {
+    for (int o = 32; o >= 1; o >>= 1) d |= __shfl_xor(d, o, 64);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = d;
     __syncthreads();
-    for (int o = blockDim.x / 2; o >= 1; o >>= 1) {
-        if (int(threadIdx.x) < o) part[threadIdx.x] += part[threadIdx.x + o];
+    uint64_t r = 0;
+    for (int k = 0; k < int(blockDim.x >> 6); ++k) r |= lds[k];
+    return r;
+}
+
+// The selection state before pass p into pre/left (LDS, m ranks), and the digits in
+// which keys vary: p = 0 is the start (no digit chosen, the ranks themselves); for
+// p >= 1, the state before pass p - 1 with digit p - 1 picked from its complete counts
+// (unchanged when every key has the same digit there).  Every load is issued first, so
+// the workgroup waits for one round trip.  pre/left hold 2 kRiskGroup entries (the
+// upper half is scratch).  Whole workgroup (>= 256 threads); ends with a barrier.
+__device__ __forceinline__ uint64_t sel_state(const SelWs &q, const SelKs &ks, int p, uint64_t *pre, int64_t *left,
+                                              uint64_t *lds, uint32_t (*wsum)[4]) {
+    const int tid = threadIdx.x, lane = tid & 63, m = ks.m;
+    const uint64_t slot = tid < ks.n_slots ? q.slots[tid] : 0ull;
+    uint64_t pr = 0;
+    int64_t lf = 0;
+    if (tid < m) {
+        pr = p > 0 ? q.prefix[(p - 1) * kRiskGroup + tid] : 0ull;
+        lf = p > 0 ? q.left[(p - 1) * kRiskGroup + tid] : ks.k[tid];
+    }
+    uint32_t c[kRiskGroup];
+    const uint32_t *cnt = q.count + size_t(p > 0 ? p - 1 : 0) * kRiskGroup * 256;
+#pragma unroll
+    for (int r = 0; r < kRiskGroup; ++r) c[r] = p > 0 && r < m && tid < 256 ? cnt[r * 256 + tid] : 0u;
+    if (tid < m) {
+        pre[tid] = pr;
+        left[tid] = lf;
+        pre[kRiskGroup + tid] = 0ull;   // the digit picked (every count row has one)
+        left[kRiskGroup + tid] = lf;
+    }
+    const uint64_t vary = varying_digits(slots_or(slot, lds));   // its barrier also publishes pre/left
+    const int shift = 56 - 8 * (p - 1);
+    if (p == 0 || ((vary >> shift) & 255u) == 0) {
         __syncthreads();
+        return vary;
     }
-    return part[0];
+    // inclusive scans of the m count rows over the digits (threads 0..255), then the pick
+    uint32_t inc[kRiskGroup];
+#pragma unroll
+    for (int r = 0; r < kRiskGroup; ++r) {
+        inc[r] = c[r];
+        if (r >= m) continue;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(inc[r], o, 64);
+            if (lane >= o) inc[r] += t;
+        }
+        if (lane == 63 && tid < 256) wsum[r][tid >> 6] = inc[r];
+    }
+    __syncthreads();
+    if (tid < 256) {
+#pragma unroll
+        for (int r = 0; r < kRiskGroup; ++r) {
+            if (r >= m) continue;
+            uint32_t before = inc[r] - c[r];
+            for (int k = 0; k < (tid >> 6); ++k) before += wsum[r][k];
+            const int64_t l = left[r];
+            if (int64_t(before) < l && l <= int64_t(before) + int64_t(c[r])) {   // one digit per rank
+                pre[kRiskGroup + r] = uint64_t(tid);
+                left[kRiskGroup + r] = l - int64_t(before);
+            }
+        }
+    }
+    __syncthreads();
+    if (tid < m) {
+        pre[tid] |= pre[kRiskGroup + tid] << shift;
+        left[tid] = left[kRiskGroup + tid];
+    }
+    __syncthreads();
+    return vary;
 }
 
-__global__ __launch_bounds__(256) void k_risk_part(SortWs w, RiskKs ks) {
-    __shared__ double part[256];
-    const uint64_t *keys = cur_keys(w, kPasses);
-    const int r = blockIdx.y;
-    const int64_t k = ks.k[r], chunk = ks.chunk[r];
-    const int64_t lo = int64_t(blockIdx.x) * chunk;
-    const int64_t hi = lo + chunk < k ? lo + chunk : k;
-    // each thread adds its keys lo + t, lo + t + 256, ... in that order; 8 are read
-    // before they are added.  Slots past hi add +0.0, which changes no sum here: the
-    // running sum starts at +0.0 and round-to-nearest addition never makes it -0.0.
-    constexpr int kAhead = 8;
-    double s = 0.0;
-    for (int64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kAhead * blockDim.x) {
-        double v[kAhead];
+// Clears the counts, starts every rank with no digit chosen (state before pass 0) and
+// writes each workgroup's OR slot.
+__global__ __launch_bounds__(kSelThreads) void k_sel_prep(const double *__restrict__ y, int64_t n, SelWs q, SelKs ks) {
+    __shared__ uint64_t wdiff[kSelThreads / 64];
+    const int tid = threadIdx.x;
+    for (int i = blockIdx.x * kSelThreads + tid; i < kPasses * kRiskGroup * 256; i += gridDim.x * kSelThreads)
+        q.count[i] = 0u;
+    if (blockIdx.x == 0 && tid < kRiskGroup) {
+        q.prefix[tid] = 0ull;
+        q.left[tid] = tid < ks.m ? ks.k[tid] : 0;
+    }
+    const uint64_t k0 = desc_key(y[0]);
+    uint64_t d = 0;
+    for (int64_t i = int64_t(blockIdx.x) * kSelThreads + tid; i < n; i += int64_t(gridDim.x) * kSelThreads)
+        d |= desc_key(y[i]) ^ k0;
+    for (int o = 32; o >= 1; o >>= 1) d |= __shfl_xor(d, o, 64);
+    if ((tid & 63) == 0) wdiff[tid >> 6] = d;
+    __syncthreads();
+    if (tid == 0) {
+        uint64_t o = 0;
+        for (int k = 0; k < kSelThreads / 64; ++k) o |= wdiff[k];
+        q.slots[blockIdx.x] = o;
+    }
+}
+
+// Counting pass p (digit bits [56 - 8p, 64 - 8p)) of the keys that share the digits
+// chosen before it; workgroup 0 also records that state.
+__global__ __launch_bounds__(kSelThreads) void k_sel_pass(const double *__restrict__ y, int64_t n, SelWs q, SelKs ks,
+                                                        int pass) {
+    __shared__ uint32_t hist[kRiskGroup][256];
+    __shared__ uint64_t lds[kSelThreads / 64];
+    __shared__ uint64_t pre[2 * kRiskGroup];
+    __shared__ int64_t left[2 * kRiskGroup];
+    __shared__ uint32_t wsum[kRiskGroup][4];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int m = ks.m;
+    const uint64_t vary = sel_state(q, ks, pass, pre, left, lds, wsum);
+    if (pass > 0 && blockIdx.x == 0 && tid < m) {
+        q.prefix[pass * kRiskGroup + tid] = pre[tid];
+        q.left[pass * kRiskGroup + tid] = left[tid];
+    }
+    const int shift = 56 - 8 * pass;
+    if (((vary >> shift) & 255u) == 0) return;   // every key has the same digit here
+    // compare keys on the chosen digits that vary (the others agree everywhere)
+    const uint64_t above = shift == 56 ? 0ull : ~0ull << (shift + 8);
+    const uint64_t cmp = above & vary;
+    for (int i = tid; i < kRiskGroup * 256; i += kSelThreads) hist[i >> 8][i & 255] = 0u;
+    __syncthreads();
+    for (int64_t b0 = int64_t(blockIdx.x) * kSelChunk; b0 < n; b0 += int64_t(gridDim.x) * kSelChunk) {
+        uint64_t key[kSelPerThread];
+        bool ok[kSelPerThread];
 #pragma unroll
-        for (int u = 0; u < kAhead; ++u) {
-            const int64_t i = i0 + int64_t(u) * blockDim.x;
-            v[u] = i < hi ? key_value(keys[i]) : 0.0;
+        for (int u = 0; u < kSelPerThread; ++u) {
+            const int64_t i = b0 + u * kSelThreads + tid;
+            ok[u] = i < n;
+            key[u] = ok[u] ? desc_key(y[i]) : 0ull;
         }
 #pragma unroll
-        for (int u = 0; u < kAhead; ++u) s += v[u];
-    }
-    s = block_sum(s, part);
-    if (threadIdx.x == 0) w.part[r * kRiskMaxBlocks + blockIdx.x] = s;   // 0 past k
-}
-
-__global__ __launch_bounds__(256) void k_risk_final(SortWs w, RiskKs ks, int n_k, int nb, double *__restrict__ out) {
-    __shared__ double part[256];
-    const uint64_t *keys = cur_keys(w, kPasses);
-    const int r = blockIdx.x;
-    const int64_t k = ks.k[r];
-    double s = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) s += w.part[r * kRiskMaxBlocks + b];
-    s = block_sum(s, part);
-    if (threadIdx.x == 0) {
-        out[r] = key_value(keys[k - 1]);
-        out[n_k + r] = s / double(k);
-    }
-}
-
-hipError_t launch_risk(const void *ws, int64_t n, const int64_t *ks, int n_k, double *out, hipStream_t s) {
-    SortWs w = sort_ws(const_cast<void *>(ws), n);
-    for (int base = 0; base < n_k; base += kRiskGroup) {
-        RiskKs r{};
-        const int m = std::min(kRiskGroup, n_k - base);
-        int64_t nb = 1;
-        for (int i = 0; i < m; ++i) {
-            const int64_t k = ks[base + i];
-            int64_t chunk = (k + kRiskMaxBlocks - 1) / kRiskMaxBlocks;
-            chunk = chunk < kRiskChunk ? kRiskChunk : chunk;
-            r.k[i] = k;
-            r.chunk[i] = chunk;
-            nb = std::max(nb, (k + chunk - 1) / chunk);
+        for (int u = 0; u < kSelPerThread; ++u) {
+            const uint32_t dg = uint32_t(key[u] >> shift) & 255u;
+            for (int r = 0; r < m; ++r) {
+                const bool match = ok[u] && ((key[u] ^ pre[r]) & cmp) == 0;
+                const uint64_t mm = __ballot(match);
+                if (mm == 0) continue;
+                const int lead = __ffsll(static_cast<unsigned long long>(mm)) - 1;
+                const uint32_t d0 = uint32_t(__builtin_amdgcn_readlane(int(dg), lead));
+                if (__ballot(match && dg != d0) == 0) {   // one digit in the wave: one add
+                    if (lane == lead) atomicAdd(&hist[r][d0], uint32_t(__popcll(mm)));
+                } else if (match) {
+                    atomicAdd(&hist[r][dg], 1u);
+                }
+            }
         }
-        // out layout per group: pml[m], tvar[m]
-        hipLaunchKernelGGL(k_risk_part, dim3(unsigned(nb), unsigned(m)), dim3(256), 0, s, w, r);
-        hipLaunchKernelGGL(k_risk_final, dim3(unsigned(m)), dim3(256), 0, s, w, r, m, int(nb), out + 2 * base);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
     }
-    return hipSuccess;
+    __syncthreads();
+    uint32_t *cnt = q.count + size_t(pass) * kRiskGroup * 256;
+    for (int i = tid; i < m * 256; i += kSelThreads)
+        if (hist[i >> 8][i & 255]) atomicAdd(&cnt[i], hist[i >> 8][i & 255]);
 }
 
-// ---------------------------------------------------------------------------------
-// Batched risk measures of many small YLTs (n <= kRiskLdsKeys each): one workgroup
-// per YLT sorts its keys in LDS (bitonic network; the array is padded to a power of
-// two with the largest key, which sorts last) and then forms PML and TVaR from the
-// sorted keys with exactly the chunks and sums of k_risk_part/k_risk_final, so the
-// results equal those of ara_risk_measures on the same YLT bit for bit.
-__device__ __forceinline__ double sum256(double s, double *part) {
-    // the 256-thread tree of block_sum, threads >= 256 only keep the barriers
+// 256-slot sum of one tile's losses below key K: v and kv are the slot's 8 losses
+// (+0.0 past the end) and their keys.
+__device__ __forceinline__ double slot_sum_below(const double (&v)[8], const uint64_t (&kv)[8], uint64_t K) {
+    double s = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += kv[u] < K ? v[u] : 0.0;
+    return s;
+}
+
+// Fixed tree over 256 slot values (threads >= 256 only keep the barriers).
+__device__ __forceinline__ double tree256(double s, double *part) {
     if (threadIdx.x < 256) part[threadIdx.x] = s;
     __syncthreads();
     for (int o = 128; o >= 1; o >>= 1) {
@@ -450,6 +594,88 @@ __device__ __forceinline__ double sum256(double s, double *part) {
     return r;
 }
 
+// Loads slot t's 8 losses of tile [lo, lo + 2048) (canonical +0.0 for -0.0; +0.0 past n).
+__device__ __forceinline__ void tile_slot(const double *y, int64_t n, int64_t lo, double (&v)[8], uint64_t (&kv)[8]) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int64_t i = lo + int64_t(threadIdx.x) + 256 * u;
+        v[u] = i < n && threadIdx.x < 256 ? y[i] + 0.0 : 0.0;
+        kv[u] = desc_key(v[u]);
+    }
+}
+
+// The last digit's pick, then each tile's sum of the losses below each rank's K (one
+// 256-thread workgroup per tile); workgroup 0 records the final state.
+__global__ __launch_bounds__(256) void k_sel_sum(const double *__restrict__ y, int64_t n, SelWs q, SelKs ks) {
+    __shared__ double part[256];
+    __shared__ uint64_t lds[4];
+    __shared__ uint64_t pre[2 * kRiskGroup];
+    __shared__ int64_t left[2 * kRiskGroup];
+    __shared__ uint32_t wsum[kRiskGroup][4];
+    const int tid = threadIdx.x, m = ks.m;
+    const int64_t tiles = (n + kSelTile - 1) / kSelTile;
+    const uint64_t k0 = desc_key(y[0]);
+    double v[8];
+    uint64_t kv[8];
+    tile_slot(y, n, int64_t(blockIdx.x) * kSelTile, v, kv);   // loads issued with the state's
+    const uint64_t vary = sel_state(q, ks, kPasses, pre, left, lds, wsum);
+    if (blockIdx.x == 0 && tid < m) {
+        q.prefix[kPasses * kRiskGroup + tid] = (pre[tid] & vary) | (k0 & ~vary);   // K
+        q.left[kPasses * kRiskGroup + tid] = left[tid];
+    }
+    for (int r = 0; r < m; ++r) {
+        const double s = tree256(slot_sum_below(v, kv, (pre[r] & vary) | (k0 & ~vary)), part);
+        if (tid == 0) q.tile_sum[int64_t(r) * tiles + blockIdx.x] = s;
+    }
+}
+
+// PML and TVaR of each rank from the final state and the tile sums (one workgroup).
+__global__ __launch_bounds__(256) void k_sel_final(int64_t n, SelWs q, SelKs ks, double *__restrict__ out) {
+    __shared__ double part[256];
+    const int tid = threadIdx.x, m = ks.m;
+    const int64_t tiles = (n + kSelTile - 1) / kSelTile;
+    for (int r = 0; r < m; ++r) {
+        double s = 0.0;
+        for (int64_t t = tid; t < tiles; t += 256) s += q.tile_sum[int64_t(r) * tiles + t];
+        s = tree256(s, part);
+        if (tid == 0) {
+            const double pml = key_value(q.prefix[kPasses * kRiskGroup + r]);
+            out[r] = pml;
+            out[m + r] = (s + double(q.left[kPasses * kRiskGroup + r]) * pml) / double(ks.k[r]);
+        }
+    }
+}
+
+hipError_t launch_risk_select(const double *y, int64_t n, void *ws, const int64_t *ks, int n_k, double *out,
+                              hipStream_t s) {
+    if (n <= 0 || n_k <= 0) return hipSuccess;
+    const SelWs q = sel_ws(ws, n);
+    const int blocks = int(std::min<int64_t>(kSelBlocks, (n + kSelChunk - 1) / kSelChunk));
+    const unsigned tiles = unsigned((n + kSelTile - 1) / kSelTile);
+    for (int base = 0; base < n_k; base += kRiskGroup) {
+        SelKs g{};
+        g.m = std::min(kRiskGroup, n_k - base);
+        g.n_slots = blocks;
+        for (int i = 0; i < g.m; ++i) g.k[i] = ks[base + i];
+        // out layout per group: pml[m], tvar[m]
+        hipLaunchKernelGGL(k_sel_prep, dim3(unsigned(blocks)), dim3(kSelThreads), 0, s, y, n, q, g);
+        for (int p = 0; p < kPasses; ++p)
+            hipLaunchKernelGGL(k_sel_pass, dim3(unsigned(blocks)), dim3(kSelThreads), 0, s, y, n, q, g, p);
+        hipLaunchKernelGGL(k_sel_sum, dim3(tiles), dim3(256), 0, s, y, n, q, g);
+        hipLaunchKernelGGL(k_sel_final, dim3(1), dim3(256), 0, s, n, q, g, out + 2 * base);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------
+// Batched risk measures of many small YLTs (n <= kRiskLdsKeys each): one workgroup
+// per YLT sorts its keys in LDS (bitonic network; the array is padded to a power of
+// two with the largest key, which sorts last), reads PML and the number of keys
+// below it from the sorted keys, and forms TVaR with exactly the tile and slot sums
+// of k_sel_sum, so the results equal those of ara_risk_measures on the same YLT bit
+// for bit.
 // Ascending bitonic sort of key[0, np) in LDS by a workgroup of 1024 threads; np is a
 // power of two, equal to 1024 E when E > 1 (else at most 1024).  Stages whose pairs
 // lie within a thread's E consecutive keys run in registers without barriers; the
@@ -560,7 +786,8 @@ __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__rest
                                                      int n_k, double *__restrict__ out) {
     __shared__ uint64_t key[kRiskLdsKeys];
     __shared__ double part[256];
-    __shared__ double chunk_sum[kRiskLdsKeys / kRiskChunk];
+    __shared__ double tile_s[kRiskLdsKeys / kSelTile];
+    __shared__ int below;
     const int j = blockIdx.x;
     if (ns[j] < 1 || ns[j] > kRiskLdsKeys) return;   // longer YLTs take the radix sort
     const int n = int(ns[j]);
@@ -576,28 +803,37 @@ __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__rest
     case 2048: bitonic_sort_lds<2>(key, np); break;
     default: bitonic_sort_lds<1>(key, np); break;
     }
+    const int nt = (n + kSelTile - 1) / kSelTile;   // <= kRiskLdsKeys / kSelTile
     for (int r = 0; r < n_k; ++r) {
         const int64_t k = ks[int64_t(j) * n_k + r];
-        int64_t chunk = (k + kRiskMaxBlocks - 1) / kRiskMaxBlocks;
-        chunk = chunk < kRiskChunk ? kRiskChunk : chunk;
-        const int nb = int((k + chunk - 1) / chunk);   // <= kRiskLdsKeys / kRiskChunk here
-        for (int b = 0; b < nb; ++b) {
-            const int64_t lo = b * chunk, hi = lo + chunk < k ? lo + chunk : k;
-            double s = 0.0;
-            if (threadIdx.x < 256)
-                for (int64_t i = lo + threadIdx.x; i < hi; i += 256) s += key_value(key[i]);
-            s = sum256(s, part);
-            if (threadIdx.x == 0) chunk_sum[b] = s;
+        const uint64_t K = key[k - 1];
+        if (threadIdx.x == 0) {   // keys below K: the first index holding K
+            int lo = 0, hi = int(k) - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (key[mid] < K) lo = mid + 1;
+                else hi = mid;
+            }
+            below = lo;
+        }
+        for (int b = 0; b < nt; ++b) {
+            double v[8];
+            uint64_t kv[8];
+            tile_slot(y, n, int64_t(b) * kSelTile, v, kv);
+            const double s = tree256(slot_sum_below(v, kv, K), part);
+            if (threadIdx.x == 0) tile_s[b] = s;
             __syncthreads();
         }
         double s = 0.0;
         if (threadIdx.x < 256)
-            for (int b = threadIdx.x; b < nb; b += 256) s += chunk_sum[b];
-        s = sum256(s, part);
+            for (int b = threadIdx.x; b < nt; b += 256) s += tile_s[b];
+        s = tree256(s, part);
         if (threadIdx.x == 0) {
-            out[int64_t(j) * 2 * n_k + r] = key_value(key[k - 1]);
-            out[int64_t(j) * 2 * n_k + n_k + r] = s / double(k);
+            const double pml = key_value(K);
+            out[int64_t(j) * 2 * n_k + r] = pml;
+            out[int64_t(j) * 2 * n_k + n_k + r] = (s + double(k - below) * pml) / double(k);
         }
+        __syncthreads();
     }
 }
 

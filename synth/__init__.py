@@ -282,7 +282,12 @@ def uneven_analyses(n: int = 256, seed: int = SEED_BASE + 3, trials=(10_000, 500
     terms occurrence 1e5/5e6, aggregate 1e6/5e7.  With iid uniform IDs the draw order
     is taken as the time order (ordering by iid timestamps leaves the distribution of
     the ID sequence unchanged)."""
-    out = []
+    return list(iter_uneven_analyses(n, seed, trials, mean, catalog, max_elts, nnz))
+
+
+def iter_uneven_analyses(n: int = 256, seed: int = SEED_BASE + 3, trials=(10_000, 500_000), mean=(200.0, 2000.0),
+                         catalog=(100_000, 1_000_000), max_elts: int = 16, nnz: int = 20_000):
+    """uneven_analyses one analysis at a time (analysis a depends only on seed and a)."""
     for a in range(n):
         rng = np.random.default_rng([seed, 0xC4, a])
         n_t = int(round(math.exp(rng.uniform(math.log(trials[0]), math.log(trials[1])))))
@@ -294,9 +299,8 @@ def uneven_analyses(n: int = 256, seed: int = SEED_BASE + 3, trials=(10_000, 500
         np.cumsum(counts, out=offs[1:])
         ids = _ids_blocks([seed, 0xC4, a], int(offs[-1]), C)
         elts = [elt_sparse(rng, min(nnz, C), C, 10.0, 2.0) for _ in range(k)]
-        out.append(Workload(f"uneven-{a}-{n_t}x{mu:.0f}-cat{C}-{k}elt", ids, offs, C, elts, (1e5, 5e6, 1e6, 5e7), None,
-                            (10.0, 100.0, 250.0), seed))
-    return out
+        yield Workload(f"uneven-{a}-{n_t}x{mu:.0f}-cat{C}-{k}elt", ids, offs, C, elts, (1e5, 5e6, 1e6, 5e7), None,
+                       (10.0, 100.0, 250.0), seed)
 
 
 def random_tiny(rng: np.random.Generator, catalog_max: int = 8, elts_max: int = 6, trials_max: int = 8,

@@ -320,3 +320,46 @@ def test_set_terms_between_batch_runs(A, S, gpu_ctx):
     finally:
         a1.release()
         a2.release()
+
+
+def test_tuning_cache_round_trip(A, S, gpu_ctx, tmp_path):
+    """A batch shape tuned on one context, its schedule saved to a file and loaded into
+    a fresh context: the fresh context's batch of that shape takes the saved schedule
+    (no tuning runs), writes every YLT on its first run, and equals plain launches."""
+    import torch
+    rng = np.random.default_rng(23)
+    w = _edge(rng, list(rng.integers(40, 700, size=900)), catalog=6000)
+    path = str(tmp_path / "schedules.txt")
+    specs = [(0, w.n_trials), (11, 500)]
+    schedules = []
+    for ctx_rep in range(2):
+        ctx = gpu_ctx if ctx_rep == 0 else A.ara_ctx_create(0)
+        an = S.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms)
+        try:
+            if ctx_rep == 1:
+                A.ara_tune_cache_load(ctx, path)
+            _say(f"tuning cache context {ctx_rep}")
+            want = [_plain(A, ctx, an.yet, an.layer, t0, t1) for t0, t1 in specs]
+            outs = [torch.full((t1 - t0,), math.nan, dtype=torch.float64, device="cuda") for t0, t1 in specs]
+            b = A.ara_batch_create(ctx, [(an.yet, an.layer, t0, t1, o) for (t0, t1), o in zip(specs, outs)])
+            try:
+                A.ara_batch_run(b)
+                A.ara_sync(ctx)
+                for k, o in enumerate(outs):
+                    assert o.cpu().numpy().tobytes() == want[k].tobytes(), (ctx_rep, k)
+                schedules.append(A.ara_batch_info(b))
+            finally:
+                A.ara_batch_release(b)
+            if ctx_rep == 0:
+                A.ara_tune_cache_save(ctx, path)
+        finally:
+            an.release()
+            if ctx_rep == 1:
+                A.ara_ctx_destroy(ctx)
+    assert schedules[0] == schedules[1]
+    lines = [ln for ln in open(path) if not ln.startswith("#")]
+    assert len(lines) >= 1
+    bad = tmp_path / "bad.txt"
+    bad.write_text("not a schedule\n")
+    with pytest.raises(A.AraError):
+        A.ara_tune_cache_load(gpu_ctx, str(bad))
