@@ -213,26 +213,46 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
         }
         __syncthreads();
     }
+    // a trial's IDs are read a chunk of kChunkSteps steps of 64 ahead of the step
+    // that places them, so a wave waits for about one load per chunk rather than one
+    // per step
+    constexpr int kChunkSteps = 4;
     for (int64_t t = t0 + wave; t < t1; t += kScatterWaves) {
         for (int32_t b = lane; b < n_bins; b += 64)
             wc[b] = staged ? lbase[b] + boff[b * stride + t] - bstart[b] : boff[b * stride + t];
         __builtin_amdgcn_wave_barrier();
         const int64_t o0 = offs[t], o1 = offs[t + 1];
-        for (int64_t base = o0; base < o1; base += 64) {
-            const int64_t i = base + lane;
-            const bool valid = i < o1;
-            const uint32_t id = valid ? uint32_t(ids[i]) : 0u;
-            const uint32_t b = id >> kBinShift;
-            uint32_t rank, count;
-            same_bin_rank(b, __builtin_amdgcn_ballot_w64(valid), nbits, rank, count);
-            const uint32_t at = wc[b];
-            const uint16_t local = uint16_t(id & uint32_t(kBinEvents - 1));
-            if (valid) {
-                if (staged) stage[at + rank] = local;
-                else ids16[region[b] + int64_t(at + rank)] = local;
-                if (rank + 1 == count) wc[b] = at + count;
+        uint32_t cur[kChunkSteps];
+#pragma unroll
+        for (int u = 0; u < kChunkSteps; ++u) {
+            const int64_t i = o0 + 64 * u + lane;
+            cur[u] = i < o1 ? uint32_t(ids[i]) : 0u;
+        }
+        for (int64_t base = o0; base < o1; base += 64 * kChunkSteps) {
+            uint32_t nxt[kChunkSteps];
+#pragma unroll
+            for (int u = 0; u < kChunkSteps; ++u) {
+                const int64_t i = base + 64 * (kChunkSteps + u) + lane;
+                nxt[u] = i < o1 ? uint32_t(ids[i]) : 0u;
             }
-            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int u = 0; u < kChunkSteps; ++u) {
+                const bool valid = base + 64 * u + lane < o1;
+                const uint32_t id = cur[u];
+                const uint32_t b = id >> kBinShift;
+                uint32_t rank, count;
+                same_bin_rank(b, __builtin_amdgcn_ballot_w64(valid), nbits, rank, count);
+                const uint32_t at = wc[b];
+                const uint16_t local = uint16_t(id & uint32_t(kBinEvents - 1));
+                if (valid) {
+                    if (staged) stage[at + rank] = local;
+                    else ids16[region[b] + int64_t(at + rank)] = local;
+                    if (rank + 1 == count) wc[b] = at + count;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+#pragma unroll
+            for (int u = 0; u < kChunkSteps; ++u) cur[u] = nxt[u];
         }
     }
     if (!staged) return;

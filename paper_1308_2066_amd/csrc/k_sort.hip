@@ -357,48 +357,64 @@ hipError_t launch_sort_decode(const void *ws, int64_t n, double *out, hipStream_
 // the mean of the k largest, k = ara_return_period_rank(n, rp).  In descending-order
 // keys PML is the k-th smallest key K.  K is found digit by digit from the most
 // significant 8 bits down: pass p counts, for every rank, digit p of the keys that
-// share the digits chosen so far; the next kernel (every workgroup of it, from the
-// complete counts) picks the digit where the running count reaches the rank, and the
-// rank left within that digit carries on.  A digit in which every key agrees (the OR
-// of key ^ first key is zero there) is not counted.  The k largest losses are then
-// the losses whose key is below K, plus (k - their number) copies of PML, so
+// share the digits chosen so far (the rank's bucket); the next kernel (every
+// workgroup of it, from the complete counts) picks the digit where the running count
+// reaches the rank, and the rank left within that digit carries on.  A digit in which
+// every key agrees (the OR of key ^ first key is zero there) is not counted.  Once
+// every rank's bucket holds at most kCollect keys, that pass copies the buckets out
+// instead of counting, and one workgroup per rank sorts its bucket in LDS for K; the
+// later passes do nothing.  The k largest losses are the losses whose key is below K,
+// plus (k - their number) copies of PML, so
 //   TVaR = (sum of the losses whose key is below K + r * PML) / k,
-// r = the rank left after the last digit.  That sum is taken in a fixed order:
-// per tile of 2048 losses in index order, 256 slots (slot t adds the tile's losses
-// t, t + 256, ..., t + 1792 in turn; the others add +0.0) and a fixed tree over the
-// slots; then the tile sums, slot t adding tiles t, t + 256, ... in turn, and the
-// same tree.  k_risk_batch forms the same sums, so the batched and plain results
-// agree bit for bit.  Kernel boundaries order every step: no workgroup waits on
-// another.
+// r = the copies of K among the k largest.  That sum is taken in a fixed order: per
+// tile of 2048 losses in index order, 256 slots (slot t adds the tile's losses t,
+// t + 256, ..., t + 1792 in turn; the others add +0.0) and a fixed tree over the
+// slots; then the tile sums, slot t adding tiles t, t + 256, ... in turn, and the same
+// tree.  A YLT of at most kRiskLdsKeys losses is sorted whole in one workgroup's LDS
+// instead (k_risk_lds), with the same sums, so every path gives the same bits.
+// Kernel boundaries order every step: no workgroup waits on another.
 constexpr int kSelPerThread = 4;
 constexpr int kSelThreads = 1024;
 constexpr int kSelBlocks = 256;                         // most workgroups of a counting pass
 constexpr int kSelChunk = kSelThreads * kSelPerThread;  // keys per workgroup and round
 constexpr int kSelTile = 2048;                          // losses per tile of the TVaR sum
+constexpr int kCollect = 2048;                          // largest bucket sorted in LDS
 static_assert(kSelTile == 8 * 256, "a tile is 8 losses for each of 256 slots");
 static_assert(kPasses * kRiskGroup * 256 * 4 <= kRiskGroup * kRiskMaxBlocks * 8, "selection counts fit the part region");
 static_assert(kSelTile == kSortTile && kRiskGroup * 8 <= 256 * 4, "tile sums fit the sort's per-tile counts");
+static_assert(int64_t(kRiskGroup) * kCollect * 8 <= 2 * 8 * int64_t(kRiskLdsKeys + 1),
+              "the buckets fit the key buffers of YLTs longer than kRiskLdsKeys");
 
 struct SelWs {
     uint64_t *slots;    // [kSelBlocks]: OR over a workgroup's keys of key ^ (key of the first loss)
-    uint64_t *prefix;   // [kPasses + 1][kRiskGroup]: digits chosen before pass p (where keys differ)
-    int64_t *left;      // [kPasses + 1][kRiskGroup]: rank left among the keys that share them
+    uint64_t *prefix;   // [kPasses + 1][kRiskGroup]: digits chosen before pass p (where keys differ);
+                        // [kPasses]: K
+    int64_t *left;      // [kPasses + 1][kRiskGroup]: rank left among the keys of the bucket;
+                        // [kPasses]: copies of K among the k largest
+    uint32_t *bcount;   // [kPasses + 1][kRiskGroup]: keys in the bucket before pass p
+    uint32_t *ncand;    // [kRiskGroup]: keys copied out of each bucket
+    uint32_t *collected;// the pass that copied the buckets out (0: none)
     uint32_t *count;    // [kPasses][kRiskGroup][256] digit counts
+    uint64_t *cand;     // [kRiskGroup][kCollect] the buckets copied out (in the key buffers)
     double *tile_sum;   // [kRiskGroup][tiles]
 };
 
-// The selection's tables in the sort workspace (the sort's key buffers are unused).
+// The selection's tables in the sort workspace.
 static SelWs sel_ws(void *ws, int64_t n) {
     const SortWs w = sort_ws(ws, n);
     SelWs q;
     q.slots = reinterpret_cast<uint64_t *>(w.hist);
     q.prefix = reinterpret_cast<uint64_t *>(w.hist + 1280);
     q.left = reinterpret_cast<int64_t *>(w.hist + 1280 + 2 * kRiskGroup * (kPasses + 1));
+    q.bcount = w.hist + 1280 + 4 * kRiskGroup * (kPasses + 1);
+    q.ncand = q.bcount + kRiskGroup * (kPasses + 1);
+    q.collected = q.ncand + kRiskGroup;
     q.count = reinterpret_cast<uint32_t *>(w.part);
+    q.cand = w.a;
     q.tile_sum = reinterpret_cast<double *>(w.counts);
     return q;
 }
-static_assert(1280 + 4 * kRiskGroup * (kPasses + 1) <= 2048, "selection state fits the 8 KB table");
+static_assert(1280 + 5 * kRiskGroup * (kPasses + 1) + kRiskGroup + 1 <= 2048, "selection state fits the 8 KB table");
 
 struct SelKs {
     int64_t k[kRiskGroup];
@@ -425,21 +441,24 @@ __device__ __forceinline__ uint64_t slots_or(uint64_t d, uint64_t *lds) {
     return r;
 }
 
-// The selection state before pass p into pre/left (LDS, m ranks), and the digits in
-// which keys vary: p = 0 is the start (no digit chosen, the ranks themselves); for
-// p >= 1, the state before pass p - 1 with digit p - 1 picked from its complete counts
-// (unchanged when every key has the same digit there).  Every load is issued first, so
-// the workgroup waits for one round trip.  pre/left hold 2 kRiskGroup entries (the
-// upper half is scratch).  Whole workgroup (>= 256 threads); ends with a barrier.
-__device__ __forceinline__ uint64_t sel_state(const SelWs &q, const SelKs &ks, int p, uint64_t *pre, int64_t *left,
-                                              uint64_t *lds, uint32_t (*wsum)[4]) {
+// The selection state before pass p into pre/left/bc (LDS, m ranks), and the digits in
+// which keys vary: p = 0 is the start (no digit chosen, the ranks themselves, every key
+// in the bucket); for p >= 1, the state before pass p - 1 with digit p - 1 picked from
+// its complete counts (unchanged when every key has the same digit there).  Every load
+// is issued first, so the workgroup waits for one round trip.  pre/left/bc hold
+// 2 kRiskGroup entries (the upper half is scratch).  Whole workgroup (>= 256 threads);
+// ends with a barrier.
+__device__ __forceinline__ uint64_t sel_state(const SelWs &q, const SelKs &ks, int64_t n, int p, uint64_t *pre,
+                                              int64_t *left, uint32_t *bc, uint64_t *lds, uint32_t (*wsum)[4]) {
     const int tid = threadIdx.x, lane = tid & 63, m = ks.m;
     const uint64_t slot = tid < ks.n_slots ? q.slots[tid] : 0ull;
     uint64_t pr = 0;
     int64_t lf = 0;
+    uint32_t bn = 0;
     if (tid < m) {
         pr = p > 0 ? q.prefix[(p - 1) * kRiskGroup + tid] : 0ull;
         lf = p > 0 ? q.left[(p - 1) * kRiskGroup + tid] : ks.k[tid];
+        bn = p > 0 ? q.bcount[(p - 1) * kRiskGroup + tid] : uint32_t(n);
     }
     uint32_t c[kRiskGroup];
     const uint32_t *cnt = q.count + size_t(p > 0 ? p - 1 : 0) * kRiskGroup * 256;
@@ -448,8 +467,10 @@ __device__ __forceinline__ uint64_t sel_state(const SelWs &q, const SelKs &ks, i
     if (tid < m) {
         pre[tid] = pr;
         left[tid] = lf;
+        bc[tid] = bn;
         pre[kRiskGroup + tid] = 0ull;   // the digit picked (every count row has one)
         left[kRiskGroup + tid] = lf;
+        bc[kRiskGroup + tid] = bn;
     }
     const uint64_t vary = varying_digits(slots_or(slot, lds));   // its barrier also publishes pre/left
     const int shift = 56 - 8 * (p - 1);
@@ -480,6 +501,7 @@ __device__ __forceinline__ uint64_t sel_state(const SelWs &q, const SelKs &ks, i
             if (int64_t(before) < l && l <= int64_t(before) + int64_t(c[r])) {   // one digit per rank
                 pre[kRiskGroup + r] = uint64_t(tid);
                 left[kRiskGroup + r] = l - int64_t(before);
+                bc[kRiskGroup + r] = c[r];
             }
         }
     }
@@ -487,21 +509,21 @@ __device__ __forceinline__ uint64_t sel_state(const SelWs &q, const SelKs &ks, i
     if (tid < m) {
         pre[tid] |= pre[kRiskGroup + tid] << shift;
         left[tid] = left[kRiskGroup + tid];
+        bc[tid] = bc[kRiskGroup + tid];
     }
     __syncthreads();
     return vary;
 }
 
-// Clears the counts, starts every rank with no digit chosen (state before pass 0) and
-// writes each workgroup's OR slot.
+// Clears the counts and the bucket copies' state and writes each workgroup's OR slot.
 __global__ __launch_bounds__(kSelThreads) void k_sel_prep(const double *__restrict__ y, int64_t n, SelWs q, SelKs ks) {
     __shared__ uint64_t wdiff[kSelThreads / 64];
     const int tid = threadIdx.x;
     for (int i = blockIdx.x * kSelThreads + tid; i < kPasses * kRiskGroup * 256; i += gridDim.x * kSelThreads)
         q.count[i] = 0u;
-    if (blockIdx.x == 0 && tid < kRiskGroup) {
-        q.prefix[tid] = 0ull;
-        q.left[tid] = tid < ks.m ? ks.k[tid] : 0;
+    if (blockIdx.x == 0) {
+        if (tid < kRiskGroup) q.ncand[tid] = 0u;
+        if (tid == 0) *q.collected = 0u;
     }
     const uint64_t k0 = desc_key(y[0]);
     uint64_t d = 0;
@@ -517,27 +539,51 @@ __global__ __launch_bounds__(kSelThreads) void k_sel_prep(const double *__restri
     }
 }
 
-// Counting pass p (digit bits [56 - 8p, 64 - 8p)) of the keys that share the digits
-// chosen before it; workgroup 0 also records that state.
+// Pass p: with the state before it (workgroup 0 records it), either copies every
+// rank's bucket out (all of them small), or counts digit p of the bucket's keys;
+// nothing once the buckets have been copied out.
 __global__ __launch_bounds__(kSelThreads) void k_sel_pass(const double *__restrict__ y, int64_t n, SelWs q, SelKs ks,
                                                         int pass) {
     __shared__ uint32_t hist[kRiskGroup][256];
     __shared__ uint64_t lds[kSelThreads / 64];
     __shared__ uint64_t pre[2 * kRiskGroup];
     __shared__ int64_t left[2 * kRiskGroup];
+    __shared__ uint32_t bc[2 * kRiskGroup];
     __shared__ uint32_t wsum[kRiskGroup][4];
     const int tid = threadIdx.x, lane = tid & 63;
     const int m = ks.m;
-    const uint64_t vary = sel_state(q, ks, pass, pre, left, lds, wsum);
-    if (pass > 0 && blockIdx.x == 0 && tid < m) {
+    {
+        // the pass that copied the buckets out, if an earlier one did (this pass's own
+        // workgroup 0 may set it while the others run)
+        const uint32_t c = *q.collected;
+        if (c != 0u && c < uint32_t(pass)) return;
+    }
+    const uint64_t vary = sel_state(q, ks, n, pass, pre, left, bc, lds, wsum);
+    if (blockIdx.x == 0 && tid < m) {
         q.prefix[pass * kRiskGroup + tid] = pre[tid];
         q.left[pass * kRiskGroup + tid] = left[tid];
+        q.bcount[pass * kRiskGroup + tid] = bc[tid];
     }
-    const int shift = 56 - 8 * pass;
-    if (((vary >> shift) & 255u) == 0) return;   // every key has the same digit here
+    bool small = pass > 0;
+    for (int r = 0; r < m; ++r) small = small && bc[r] <= uint32_t(kCollect);
     // compare keys on the chosen digits that vary (the others agree everywhere)
+    const int shift = 56 - 8 * pass;
     const uint64_t above = shift == 56 ? 0ull : ~0ull << (shift + 8);
     const uint64_t cmp = above & vary;
+    if (small) {
+        if (blockIdx.x == 0 && tid == 0) *q.collected = uint32_t(pass);
+        for (int64_t i = int64_t(blockIdx.x) * kSelThreads + tid; i < n; i += int64_t(gridDim.x) * kSelThreads) {
+            const uint64_t key = desc_key(y[i]);
+            for (int r = 0; r < m; ++r) {
+                if (((key ^ pre[r]) & cmp) == 0) {
+                    const uint32_t at = atomicAdd(&q.ncand[r], 1u);
+                    q.cand[int64_t(r) * kCollect + at] = key;   // at < bucket size <= kCollect
+                }
+            }
+        }
+        return;
+    }
+    if (((vary >> shift) & 255u) == 0) return;   // every key has the same digit here
     for (int i = tid; i < kRiskGroup * 256; i += kSelThreads) hist[i >> 8][i & 255] = 0u;
     __syncthreads();
     for (int64_t b0 = int64_t(blockIdx.x) * kSelChunk; b0 < n; b0 += int64_t(gridDim.x) * kSelChunk) {
@@ -604,32 +650,24 @@ __device__ __forceinline__ void tile_slot(const double *y, int64_t n, int64_t lo
     }
 }
 
-// The last digit's pick, then each tile's sum of the losses below each rank's K (one
-// 256-thread workgroup per tile); workgroup 0 records the final state.
+// Each tile's sum of the losses below each rank's K (one 256-thread workgroup per tile).
 __global__ __launch_bounds__(256) void k_sel_sum(const double *__restrict__ y, int64_t n, SelWs q, SelKs ks) {
     __shared__ double part[256];
-    __shared__ uint64_t lds[4];
-    __shared__ uint64_t pre[2 * kRiskGroup];
-    __shared__ int64_t left[2 * kRiskGroup];
-    __shared__ uint32_t wsum[kRiskGroup][4];
+    __shared__ uint64_t K[kRiskGroup];
     const int tid = threadIdx.x, m = ks.m;
     const int64_t tiles = (n + kSelTile - 1) / kSelTile;
-    const uint64_t k0 = desc_key(y[0]);
     double v[8];
     uint64_t kv[8];
-    tile_slot(y, n, int64_t(blockIdx.x) * kSelTile, v, kv);   // loads issued with the state's
-    const uint64_t vary = sel_state(q, ks, kPasses, pre, left, lds, wsum);
-    if (blockIdx.x == 0 && tid < m) {
-        q.prefix[kPasses * kRiskGroup + tid] = (pre[tid] & vary) | (k0 & ~vary);   // K
-        q.left[kPasses * kRiskGroup + tid] = left[tid];
-    }
+    tile_slot(y, n, int64_t(blockIdx.x) * kSelTile, v, kv);
+    if (tid < m) K[tid] = q.prefix[kPasses * kRiskGroup + tid];
+    __syncthreads();
     for (int r = 0; r < m; ++r) {
-        const double s = tree256(slot_sum_below(v, kv, (pre[r] & vary) | (k0 & ~vary)), part);
+        const double s = tree256(slot_sum_below(v, kv, K[r]), part);
         if (tid == 0) q.tile_sum[int64_t(r) * tiles + blockIdx.x] = s;
     }
 }
 
-// PML and TVaR of each rank from the final state and the tile sums (one workgroup).
+// PML and TVaR of each rank from K, its copies and the tile sums (one workgroup).
 __global__ __launch_bounds__(256) void k_sel_final(int64_t n, SelWs q, SelKs ks, double *__restrict__ out) {
     __shared__ double part[256];
     const int tid = threadIdx.x, m = ks.m;
@@ -646,36 +684,6 @@ __global__ __launch_bounds__(256) void k_sel_final(int64_t n, SelWs q, SelKs ks,
     }
 }
 
-hipError_t launch_risk_select(const double *y, int64_t n, void *ws, const int64_t *ks, int n_k, double *out,
-                              hipStream_t s) {
-    if (n <= 0 || n_k <= 0) return hipSuccess;
-    const SelWs q = sel_ws(ws, n);
-    const int blocks = int(std::min<int64_t>(kSelBlocks, (n + kSelChunk - 1) / kSelChunk));
-    const unsigned tiles = unsigned((n + kSelTile - 1) / kSelTile);
-    for (int base = 0; base < n_k; base += kRiskGroup) {
-        SelKs g{};
-        g.m = std::min(kRiskGroup, n_k - base);
-        g.n_slots = blocks;
-        for (int i = 0; i < g.m; ++i) g.k[i] = ks[base + i];
-        // out layout per group: pml[m], tvar[m]
-        hipLaunchKernelGGL(k_sel_prep, dim3(unsigned(blocks)), dim3(kSelThreads), 0, s, y, n, q, g);
-        for (int p = 0; p < kPasses; ++p)
-            hipLaunchKernelGGL(k_sel_pass, dim3(unsigned(blocks)), dim3(kSelThreads), 0, s, y, n, q, g, p);
-        hipLaunchKernelGGL(k_sel_sum, dim3(tiles), dim3(256), 0, s, y, n, q, g);
-        hipLaunchKernelGGL(k_sel_final, dim3(1), dim3(256), 0, s, n, q, g, out + 2 * base);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
-// ---------------------------------------------------------------------------------
-// Batched risk measures of many small YLTs (n <= kRiskLdsKeys each): one workgroup
-// per YLT sorts its keys in LDS (bitonic network; the array is padded to a power of
-// two with the largest key, which sorts last), reads PML and the number of keys
-// below it from the sorted keys, and forms TVaR with exactly the tile and slot sums
-// of k_sel_sum, so the results equal those of ara_risk_measures on the same YLT bit
-// for bit.
 // Ascending bitonic sort of key[0, np) in LDS by a workgroup of 1024 threads; np is a
 // power of two, equal to 1024 E when E > 1 (else at most 1024).  Stages whose pairs
 // lie within a thread's E consecutive keys run in registers without barriers; the
@@ -781,17 +789,54 @@ __device__ __forceinline__ void bitonic_sort_lds_16k(uint64_t *key) {
     }
 }
 
-__global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__restrict__ ylts,
-                                                     const int64_t *__restrict__ ns, const int64_t *__restrict__ ks,
-                                                     int n_k, double *__restrict__ out) {
-    __shared__ uint64_t key[kRiskLdsKeys];
-    __shared__ double part[256];
-    __shared__ double tile_s[kRiskLdsKeys / kSelTile];
+// K and its copies among the k largest (final state) for rank blockIdx.x: from its
+// bucket copied out (sorted in LDS), else from the last digit's counts.
+__global__ __launch_bounds__(1024) void k_sel_finish(const double *__restrict__ y, int64_t n, SelWs q, SelKs ks) {
+    __shared__ uint64_t key[kCollect];
+    __shared__ uint64_t lds[16];
+    __shared__ uint64_t pre[2 * kRiskGroup];
+    __shared__ int64_t left[2 * kRiskGroup];
+    __shared__ uint32_t bc[2 * kRiskGroup];
+    __shared__ uint32_t wsum[kRiskGroup][4];
     __shared__ int below;
-    const int j = blockIdx.x;
-    if (ns[j] < 1 || ns[j] > kRiskLdsKeys) return;   // longer YLTs take the radix sort
-    const int n = int(ns[j]);
-    const double *y = ylts[j];
+    const int tid = threadIdx.x, r = blockIdx.x;
+    const uint32_t p = *q.collected;
+    if (p == 0) {   // every digit picked from counts: the state after the last digit
+        const uint64_t vary = sel_state(q, ks, n, kPasses, pre, left, bc, lds, wsum);
+        if (tid == 0) {
+            const uint64_t k0 = desc_key(y[0]);
+            q.prefix[kPasses * kRiskGroup + r] = (pre[r] & vary) | (k0 & ~vary);
+            q.left[kPasses * kRiskGroup + r] = left[r];
+        }
+        return;
+    }
+    const uint32_t nc = min(q.ncand[r], uint32_t(kCollect));
+    const int64_t lf = q.left[int64_t(p) * kRiskGroup + r];   // rank within the bucket
+    int np = 1;
+    while (np < int(nc)) np <<= 1;
+    for (int i = tid; i < np; i += 1024) key[i] = i < int(nc) ? q.cand[int64_t(r) * kCollect + i] : ~0ull;
+    __syncthreads();
+    if (np == 2048) bitonic_sort_lds<2>(key, np);
+    else bitonic_sort_lds<1>(key, np);
+    if (tid == 0) {
+        const uint64_t K = key[lf - 1];
+        int lo = 0, hi = int(lf) - 1;   // keys of the bucket below K: the first index holding K
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (key[mid] < K) lo = mid + 1;
+            else hi = mid;
+        }
+        below = lo;
+        q.prefix[kPasses * kRiskGroup + r] = K;
+        q.left[kPasses * kRiskGroup + r] = lf - below;
+    }
+}
+
+// PML/TVaR of the losses y[0, n) (n <= kRiskLdsKeys) at ranks k(0..n_k-1), sorted whole
+// in LDS by one workgroup of 1024 threads: out[r] = PML, out[n_k + r] = TVaR.
+template <typename RankAt>
+__device__ __forceinline__ void risk_lds(const double *y, int n, int n_k, RankAt k_at, double *out, uint64_t *key,
+                                         double *part, double *tile_s, int *below) {
     int np = 1;
     while (np < n) np <<= 1;
     for (int i = threadIdx.x; i < np; i += blockDim.x) key[i] = i < n ? desc_key(y[i]) : ~0ull;
@@ -805,7 +850,7 @@ __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__rest
     }
     const int nt = (n + kSelTile - 1) / kSelTile;   // <= kRiskLdsKeys / kSelTile
     for (int r = 0; r < n_k; ++r) {
-        const int64_t k = ks[int64_t(j) * n_k + r];
+        const int64_t k = k_at(r);
         const uint64_t K = key[k - 1];
         if (threadIdx.x == 0) {   // keys below K: the first index holding K
             int lo = 0, hi = int(k) - 1;
@@ -814,7 +859,7 @@ __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__rest
                 if (key[mid] < K) lo = mid + 1;
                 else hi = mid;
             }
-            below = lo;
+            *below = lo;
         }
         for (int b = 0; b < nt; ++b) {
             double v[8];
@@ -830,11 +875,66 @@ __global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__rest
         s = tree256(s, part);
         if (threadIdx.x == 0) {
             const double pml = key_value(K);
-            out[int64_t(j) * 2 * n_k + r] = pml;
-            out[int64_t(j) * 2 * n_k + n_k + r] = (s + double(k - below) * pml) / double(k);
+            out[r] = pml;
+            out[n_k + r] = (s + double(k - *below) * pml) / double(k);
         }
         __syncthreads();
     }
+}
+
+// One YLT of at most kRiskLdsKeys losses, ranks from the kernel arguments.
+__global__ __launch_bounds__(1024) void k_risk_lds(const double *__restrict__ y, int n, SelKs ks,
+                                                   double *__restrict__ out) {
+    __shared__ uint64_t key[kRiskLdsKeys];
+    __shared__ double part[256];
+    __shared__ double tile_s[kRiskLdsKeys / kSelTile];
+    __shared__ int below;
+    risk_lds(y, n, ks.m, [&](int r) { return ks.k[r]; }, out, key, part, tile_s, &below);
+}
+
+hipError_t launch_risk_select(const double *y, int64_t n, void *ws, const int64_t *ks, int n_k, double *out,
+                              hipStream_t s) {
+    if (n <= 0 || n_k <= 0) return hipSuccess;
+    const SelWs q = sel_ws(ws, n);
+    const int blocks = int(std::min<int64_t>(kSelBlocks, (n + kSelChunk - 1) / kSelChunk));
+    const unsigned tiles = unsigned((n + kSelTile - 1) / kSelTile);
+    for (int base = 0; base < n_k; base += kRiskGroup) {
+        SelKs g{};
+        g.m = std::min(kRiskGroup, n_k - base);
+        g.n_slots = blocks;
+        for (int i = 0; i < g.m; ++i) g.k[i] = ks[base + i];
+        // out layout per group: pml[m], tvar[m]
+        if (n <= kRiskLdsKeys) {
+            hipLaunchKernelGGL(k_risk_lds, dim3(1), dim3(1024), 0, s, y, int(n), g, out + 2 * base);
+        } else {
+            hipLaunchKernelGGL(k_sel_prep, dim3(unsigned(blocks)), dim3(kSelThreads), 0, s, y, n, q, g);
+            for (int p = 0; p < kPasses; ++p)
+                hipLaunchKernelGGL(k_sel_pass, dim3(unsigned(blocks)), dim3(kSelThreads), 0, s, y, n, q, g, p);
+            hipLaunchKernelGGL(k_sel_finish, dim3(unsigned(g.m)), dim3(1024), 0, s, y, n, q, g);
+            hipLaunchKernelGGL(k_sel_sum, dim3(tiles), dim3(256), 0, s, y, n, q, g);
+            hipLaunchKernelGGL(k_sel_final, dim3(1), dim3(256), 0, s, n, q, g, out + 2 * base);
+        }
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------------
+// Batched risk measures of many small YLTs (n <= kRiskLdsKeys each): one workgroup
+// per YLT, risk_lds, so the results equal those of ara_risk_measures on the same YLT
+// bit for bit.
+__global__ __launch_bounds__(1024) void k_risk_batch(const double *const *__restrict__ ylts,
+                                                     const int64_t *__restrict__ ns, const int64_t *__restrict__ ks,
+                                                     int n_k, double *__restrict__ out) {
+    __shared__ uint64_t key[kRiskLdsKeys];
+    __shared__ double part[256];
+    __shared__ double tile_s[kRiskLdsKeys / kSelTile];
+    __shared__ int below;
+    const int j = blockIdx.x;
+    if (ns[j] < 1 || ns[j] > kRiskLdsKeys) return;   // longer YLTs take the radix selection
+    risk_lds(ylts[j], int(ns[j]), n_k, [&](int r) { return ks[int64_t(j) * n_k + r]; }, out + int64_t(j) * 2 * n_k,
+             key, part, tile_s, &below);
 }
 
 hipError_t launch_risk_batch(const double *const *ylts, const int64_t *ns, const int64_t *ks, int n_jobs, int n_k,

@@ -448,6 +448,41 @@ def test_risk_measures_large_k(A, gpu_ctx, n, kind):
     assert np.all(np.abs(np.asarray(tvar) - tvar_o) <= bound), (tvar, tvar_o)
 
 
+@pytest.mark.parametrize("n,kind", [(16_384, "distinct"), (16_385, "distinct"), (50_000, "ties_at_k"),
+                                    (200_000, "tie_block"), (1_000_000, "distinct"), (123_457, "two_values")])
+def test_risk_measures_selection_paths(A, gpu_ctx, n, kind):
+    """PML/TVaR against the oracle on YLTs that take each path of the selection: the
+    one-workgroup sort (n <= 16384), buckets copied out and sorted with ties at the
+    k-th loss, a tie block larger than any bucket that can be copied (every digit
+    picked from counts), and two values only; ranks identical, PML bit-exact, TVaR
+    within the summation bound, and the same bits on a second call."""
+    import torch
+    _say(f"risk selection paths n={n} kind={kind}")
+    rng = np.random.default_rng(n * 7 + len(kind))
+    rps = [1.0, 2.0, 3.0, 10.0, 100.0, 250.0, 1000.0, float(n)]
+    y = rng.lognormal(13, 2.2, size=n)
+    if kind == "ties_at_k":
+        for rp in (10.0, 100.0):   # 300 copies of the loss at each rank
+            k = A.ara_return_period_rank(n, rp)
+            v = np.sort(y)[::-1][k - 1]
+            y[rng.choice(n, 300, replace=False)] = v
+    elif kind == "tie_block":
+        y[rng.random(n) < 0.4] = float(np.quantile(y, 0.9))
+    elif kind == "two_values":
+        y = np.where(rng.random(n) < 0.25, 7.5e6, 1.25e6)
+    pml_o, tvar_o, ranks_o, _ = oracle.risk(y, rps)
+    yt = torch.from_numpy(y).cuda()
+    pml, tvar = A.ara_risk_measures(gpu_ctx, yt, rps)
+    assert [A.ara_return_period_rank(n, rp) for rp in rps] == list(ranks_o)
+    assert np.asarray(pml).tobytes() == np.asarray(pml_o).tobytes()
+    k = np.asarray(ranks_o, dtype=np.float64)
+    bound = 2.0 * k * 2.0 ** -53 * np.asarray(tvar_o) + 1e-300
+    assert np.all(np.abs(np.asarray(tvar) - tvar_o) <= bound), (tvar, tvar_o)
+    pml2, tvar2 = A.ara_risk_measures(gpu_ctx, yt, rps)   # the same bits on a second call
+    assert np.asarray(pml2).tobytes() == np.asarray(pml).tobytes()
+    assert np.asarray(tvar2).tobytes() == np.asarray(tvar).tobytes()
+
+
 def test_packed_copy_only_below_2_24(A, gpu_ctx):
     import torch
     _say("packed copy catalog limit")
