@@ -436,27 +436,37 @@ static void yet_free_binned(ara_yet *y) {
     y->n_bins = 0;
 }
 
-// Builds the catalog-binned copy when it applies (see ara_yet_create); the YET is
-// usable without it, so running out of device memory only skips it.
-static ara_status yet_build_binned(ara_ctx *c, ara_yet *y) {
+// Whether a YET of these sizes gets a catalog-binned copy (see ara_yet_create).
+static bool yet_binning_applies(const ara_ctx *c, const ara_yet *y) {
     const int32_t nb = catalog_bins(y->catalog);
     const int64_t n = y->n_trials;
-    if (!c->yet_binning || y->n_events == 0 || n == 0 || int64_t(y->catalog) * 8 <= int64_t(c->lds_max) ||
-        y->catalog > kMaxPackedCatalog || nb > kMaxBins || (n + 1 + 4095) / 4096 > 65535 ||
-        4.0 * double(nb) * double(n) > 0.25 * 2.0 * double(y->n_events))
-        return ARA_OK;
+    return c->yet_binning && y->n_events > 0 && n > 0 && int64_t(y->catalog) * 8 > int64_t(c->lds_max) &&
+           y->catalog <= kMaxPackedCatalog && nb <= kMaxBins && (n + 1 + 4095) / 4096 <= 65535 &&
+           4.0 * double(nb) * double(n) <= 0.25 * 2.0 * double(y->n_events);
+}
+
+// Builds the catalog-binned copy when it applies; the YET is usable without it, so
+// running out of device memory only skips it.  Its count pass checks the offsets and
+// every event ID: *ids_checked tells whether it ran.
+static ara_status yet_build_binned(ara_ctx *c, ara_yet *y, bool *ids_checked) {
+    const int32_t nb = catalog_bins(y->catalog);
+    const int64_t n = y->n_trials;
+    *ids_checked = false;
+    if (!yet_binning_applies(c, y)) return ARA_OK;
     y->stride = (n + 1 + 3) & ~int64_t(3);
     uint32_t *sums = nullptr;
     ara_status s = dev_alloc(c, &y->boff, size_t(nb) * size_t(y->stride) * 4, "binned yet offsets");
     if (s == ARA_OK) s = dev_alloc(c, &sums, bin_scan_scratch_words(n + 1, nb) * 4, "binned yet scan");
     if (s == ARA_OK) {
-        hipError_t e = launch_bin_count(y->ids, y->offs, n, nb, y->boff, y->stride, c->stream);
+        hipError_t e = launch_bin_count(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->catalog, c->d_err,
+                                        c->stream);
         if (e == hipSuccess) e = launch_bin_scan(y->boff, y->stride, n + 1, nb, sums, c->stream);
         std::vector<uint32_t> len(static_cast<size_t>(nb));
         if (e == hipSuccess)
             e = hipMemcpy2DAsync(len.data(), 4, y->boff + n, size_t(y->stride) * 4, 4, size_t(nb), hipMemcpyDeviceToHost,
                                  c->stream);
         s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet offsets");
+        *ids_checked = e == hipSuccess;   // an ID outside the catalog shows in s
         std::vector<int64_t> region(static_cast<size_t>(nb) + 1, 0);
         bool fits = true;
         for (int32_t b = 0; s == ARA_OK && b < nb; ++b) {
@@ -525,12 +535,17 @@ extern "C" ara_status ara_yet_create(ara_ctx *c, const int32_t *ids, int64_t n_e
         y->ids = di;
         y->offs = doff;
     }
-    hipError_t e = launch_validate_yet(y->ids, n_events, y->offs, n_trials, catalog, c->d_err, c->stream);
-    ara_status s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "validate yet");
-    // the binned copy serves the tiled kernel; the packed copy the kernels that stream
-    // a whole trial's IDs.  A YET keeps one of them: with a binned copy the others
-    // stream the int32 IDs as given
-    if (s == ARA_OK) s = yet_build_binned(c, y);
+    // the binned copy's count pass checks the offsets and IDs; without it (or if it is
+    // skipped before that pass) the check runs on its own.  The binned copy serves the
+    // tiled kernel; the packed copy the kernels that stream a whole trial's IDs.  A YET
+    // keeps one of them: with a binned copy the others stream the int32 IDs as given
+    bool checked = false;
+    ara_status s = yet_binning_applies(c, y) ? yet_build_binned(c, y, &checked) : ARA_OK;
+    hipError_t e = hipSuccess;
+    if (s == ARA_OK && !checked) {
+        e = launch_validate_yet(y->ids, n_events, y->offs, n_trials, catalog, c->d_err, c->stream, true);
+        s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "validate yet");
+    }
     if (s == ARA_OK && !y->ids16 && c->yet_packing && n_events > 0 && catalog <= kMaxPackedCatalog) {
         s = dev_alloc(c, &y->ids24, yet_packed_bytes(n_events), "packed yet ids");
         if (s == ARA_OK) {

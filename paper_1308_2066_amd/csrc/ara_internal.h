@@ -97,7 +97,8 @@ struct TrialArgs {
 // ---- launchers (each enqueues on `s` and returns the launch status)
 hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s);
 hipError_t launch_validate_yet(const int32_t *ids, int64_t n_events, const int64_t *offs, int64_t n_trials,
-                               int32_t catalog, uint32_t *err, hipStream_t s);
+                               int32_t catalog, uint32_t *err, hipStream_t s,
+                               bool check_ids = true);
 size_t yet_packed_bytes(int64_t n_events);
 hipError_t launch_yet_pack(const int32_t *ids, int64_t n_events, uint8_t *packed, hipStream_t s);
 hipError_t launch_elt_clear(const EltDesc *d, int n_elts, int32_t catalog, hipStream_t s);
@@ -175,8 +176,10 @@ constexpr int kBlocksPerBin = kBinEvents / kEventsPerBlock;   // 256
 constexpr int kMaxBins = 512;                                 // catalogs up to 2^24 events
 inline int32_t catalog_bins(int32_t catalog) { return (catalog + kBinEvents - 1) / kBinEvents; }
 
-hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_trials, int32_t n_bins,
-                            uint32_t *boff, int64_t stride, hipStream_t s);
+// Also checks the YET (ERR_OFFSETS, ERR_ID_RANGE in err; bad offsets or IDs are not
+// followed or counted): the binned copy's count pass doubles as ingest's check.
+hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials, int32_t n_bins,
+                            uint32_t *boff, int64_t stride, int32_t catalog, uint32_t *err, hipStream_t s);
 hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, int32_t n_bins, uint32_t *block_sums,
                            hipStream_t s);
 size_t bin_scan_scratch_words(int64_t n_entries, int32_t n_bins);

@@ -10,6 +10,8 @@
 // region b, so a tile's occurrences of any trial range are one contiguous span per
 // bin.  The regrouping only changes which occurrences are read together; each
 // trial still has exactly its own occurrences.
+#include <type_traits>
+
 #include "ara_internal.h"
 
 namespace ara {
@@ -17,42 +19,61 @@ namespace ara {
 // boff[b][t] = number of trial t's occurrences in bin b; boff[b][n_trials] = 0.
 // One wave per trial (four per workgroup), counting in the wave's own LDS
 // histogram; a wave's LDS operations complete in order, so it needs no barrier.
+// The YET is checked on the way, as ara_yet_create states: a trial's offsets must lie
+// in [0, n_events] in order, the first be 0 and the last n_events (else ERR_OFFSETS
+// and the trial's IDs are not read), every ID be in [0, catalog) (else ERR_ID_RANGE
+// and the ID is not counted).
 constexpr int kCountWaves = 4;
 
 __global__ __launch_bounds__(kCountWaves * 64) void k_bin_count(const int32_t *__restrict__ ids,
-                                                                const int64_t *__restrict__ offs, int64_t n_trials,
-                                                                int32_t n_bins, uint32_t *__restrict__ boff,
-                                                                int64_t stride) {
+                                                                const int64_t *__restrict__ offs, int64_t n_events,
+                                                                int64_t n_trials, int32_t n_bins,
+                                                                uint32_t *__restrict__ boff, int64_t stride,
+                                                                int32_t catalog, uint32_t *err) {
     __shared__ uint32_t hist[kCountWaves][kMaxBins];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t cat = uint32_t(catalog);
     uint32_t *h = hist[wave];
+    bool bad = false, bad_offs = false;
     if (blockIdx.x == 0)
         for (int32_t b = threadIdx.x; b < n_bins; b += kCountWaves * 64) boff[b * stride + n_trials] = 0u;
     for (int64_t t = int64_t(blockIdx.x) * kCountWaves + wave; t < n_trials; t += int64_t(gridDim.x) * kCountWaves) {
         for (int32_t b = lane; b < n_bins; b += 64) h[b] = 0u;
         __builtin_amdgcn_wave_barrier();
-        const int64_t o0 = offs[t], o1 = offs[t + 1];
-        int64_t i = o0 + lane;
-        for (; i + 192 < o1; i += 256) {   // four loads in flight per lane
-            const uint32_t a = uint32_t(ids[i]), b = uint32_t(ids[i + 64]), c = uint32_t(ids[i + 128]),
-                           d = uint32_t(ids[i + 192]);
-            atomicAdd(&h[a >> kBinShift], 1u);
-            atomicAdd(&h[b >> kBinShift], 1u);
-            atomicAdd(&h[c >> kBinShift], 1u);
-            atomicAdd(&h[d >> kBinShift], 1u);
+        int64_t o0 = offs[t], o1 = offs[t + 1];
+        if (o0 < 0 || o1 < o0 || o1 > n_events || (t == 0 && o0 != 0) || (t == n_trials - 1 && o1 != n_events)) {
+            bad_offs = true;
+            o1 = o0;   // read none of this trial's IDs
         }
-        for (; i < o1; i += 64) atomicAdd(&h[uint32_t(ids[i]) >> kBinShift], 1u);
+        constexpr int kAhead = 16;   // loads in flight per lane (4 KB per wave: enough to keep HBM busy)
+        for (int64_t base = o0; base < o1; base += 64 * kAhead) {
+            uint32_t v[kAhead];
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                const int64_t i = base + 64 * u + lane;
+                v[u] = i < o1 ? uint32_t(ids[i]) : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < kAhead; ++u) {
+                if (base + 64 * u + lane >= o1) continue;
+                if (v[u] < cat) atomicAdd(&h[v[u] >> kBinShift], 1u);
+                else bad = true;
+            }
+        }
         __builtin_amdgcn_wave_barrier();
         for (int32_t b = lane; b < n_bins; b += 64) boff[b * stride + t] = h[b];
         __builtin_amdgcn_wave_barrier();
     }
+    const uint32_t flags = (__builtin_amdgcn_ballot_w64(bad) ? ERR_ID_RANGE : 0u) |
+                           (__builtin_amdgcn_ballot_w64(bad_offs) ? ERR_OFFSETS : 0u);
+    if (flags && lane == 0) atomicOr(err, flags);
 }
 
-hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_trials, int32_t n_bins,
-                            uint32_t *boff, int64_t stride, hipStream_t s) {
+hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials, int32_t n_bins,
+                            uint32_t *boff, int64_t stride, int32_t catalog, uint32_t *err, hipStream_t s) {
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n_trials + kCountWaves - 1) / kCountWaves, 65536));
-    hipLaunchKernelGGL(k_bin_count, dim3(unsigned(grid)), dim3(kCountWaves * 64), 0, s, ids, offs, n_trials, n_bins,
-                       boff, stride);
+    hipLaunchKernelGGL(k_bin_count, dim3(unsigned(grid)), dim3(kCountWaves * 64), 0, s, ids, offs, n_events, n_trials,
+                       n_bins, boff, stride, catalog, err);
     return hipGetLastError();
 }
 
@@ -154,10 +175,12 @@ int64_t bin_scatter_block_trials(int64_t n_events, int64_t n_trials) {
 }
 
 // Rank of this lane among the lanes of `valid` whose bin equals its own, and their
-// number; nbits = bits needed for the largest bin number.
-__device__ __forceinline__ void same_bin_rank(uint32_t b, uint64_t valid, int nbits, uint32_t &rank, uint32_t &count) {
+// number; NBITS = bits needed for the largest bin number.
+template <int NBITS>
+__device__ __forceinline__ void same_bin_rank(uint32_t b, uint64_t valid, uint32_t &rank, uint32_t &count) {
     uint64_t m = valid;
-    for (int k = 0; k < nbits; ++k) {
+#pragma unroll
+    for (int k = 0; k < NBITS; ++k) {
         const bool bit = (b >> k) & 1u;
         const uint64_t ones = __builtin_amdgcn_ballot_w64(bit);
         m &= bit ? ones : ~ones;
@@ -166,21 +189,25 @@ __device__ __forceinline__ void same_bin_rank(uint32_t b, uint64_t valid, int nb
     count = uint32_t(__popcll(m));
 }
 
+template <int NBITS, bool STAGED>
 __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_t *__restrict__ ids,
                                                                     const int64_t *__restrict__ offs, int64_t n_trials,
                                                                     int32_t n_bins, const uint32_t *__restrict__ boff,
                                                                     int64_t stride, const int64_t *__restrict__ region,
                                                                     uint16_t *__restrict__ ids16, int64_t per_block) {
-    __shared__ uint16_t stage[kScatterCap];
-    __shared__ uint32_t cur[kScatterWaves][kMaxBins];   // next position of the wave's trial's run, per bin
-    __shared__ uint32_t lbase[kMaxBins + 1];            // start of bin b's span in `stage`
-    __shared__ uint32_t bstart[kMaxBins];               // boff[b][t0]
+    constexpr int kBins = NBITS <= 6 ? 64 : kMaxBins;   // bins the LDS tables hold
+    __shared__ uint16_t stage[STAGED ? kScatterCap : 2];
+    __shared__ uint32_t cur[kScatterWaves][kBins];      // next position of the wave's trial's run, per bin
+    __shared__ uint32_t lbase[kBins + 1];               // start of bin b's span in `stage`
+    __shared__ uint32_t bstart[kBins];                  // boff[b][t0]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nbits = n_bins > 1 ? 32 - __builtin_clz(uint32_t(n_bins - 1)) : 0;
     const int64_t t0 = int64_t(blockIdx.x) * per_block;
     if (t0 >= n_trials) return;
     const int64_t t1 = min(t0 + per_block, n_trials);
-    const bool staged = offs[t1] - offs[t0] <= int64_t(kScatterCap);
+    // a block with more occurrences than the LDS holds is left to the unstaged launch
+    // (and the unstaged launch leaves the others)
+    if ((offs[t1] - offs[t0] <= int64_t(kScatterCap)) != STAGED) return;
+    constexpr bool staged = STAGED;
     uint32_t *wc = cur[wave];
     if (staged) {
         for (int32_t b = threadIdx.x; b < n_bins; b += kScatterWaves * 64) {
@@ -215,8 +242,8 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
     }
     // a trial's IDs are read a chunk of kChunkSteps steps of 64 ahead of the step
     // that places them, so a wave waits for about one load per chunk rather than one
-    // per step
-    constexpr int kChunkSteps = 4;
+    // per step, and enough bytes are in flight to keep HBM busy
+    constexpr int kChunkSteps = 16;   // 4 KB of IDs in flight per wave (a 1000-event trial at once)
     for (int64_t t = t0 + wave; t < t1; t += kScatterWaves) {
         for (int32_t b = lane; b < n_bins; b += 64)
             wc[b] = staged ? lbase[b] + boff[b * stride + t] - bstart[b] : boff[b * stride + t];
@@ -241,7 +268,7 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
                 const uint32_t id = cur[u];
                 const uint32_t b = id >> kBinShift;
                 uint32_t rank, count;
-                same_bin_rank(b, __builtin_amdgcn_ballot_w64(valid), nbits, rank, count);
+                same_bin_rank<NBITS>(b, __builtin_amdgcn_ballot_w64(valid), rank, count);
                 const uint32_t at = wc[b];
                 const uint16_t local = uint16_t(id & uint32_t(kBinEvents - 1));
                 if (valid) {
@@ -273,9 +300,34 @@ hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n
     const int64_t per = bin_scatter_block_trials(n_events, n_trials);
     const int64_t grid = (n_trials + per - 1) / per;
     if (grid > int64_t(INT32_MAX)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bin_scatter, dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs, n_trials, n_bins,
-                       boff, stride, region, ids16, per);
-    return hipGetLastError();
+    const int nbits = n_bins > 1 ? 32 - __builtin_clz(uint32_t(n_bins - 1)) : 0;
+    // one instantiation per bit count of the bin numbers (the rank's ballots unrolled),
+    // each launched for the staged blocks and then for the others
+    hipError_t e = hipSuccess;
+    auto launch = [&](auto nb_const) {
+        constexpr int NB = decltype(nb_const)::value;
+        hipLaunchKernelGGL((k_bin_scatter<NB, true>), dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs,
+                           n_trials, n_bins, boff, stride, region, ids16, per);
+        e = hipGetLastError();
+        if (e != hipSuccess) return;
+        hipLaunchKernelGGL((k_bin_scatter<NB, false>), dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs,
+                           n_trials, n_bins, boff, stride, region, ids16, per);
+        e = hipGetLastError();
+    };
+    switch (nbits) {
+    case 0: launch(std::integral_constant<int, 0>()); break;
+    case 1: launch(std::integral_constant<int, 1>()); break;
+    case 2: launch(std::integral_constant<int, 2>()); break;
+    case 3: launch(std::integral_constant<int, 3>()); break;
+    case 4: launch(std::integral_constant<int, 4>()); break;
+    case 5: launch(std::integral_constant<int, 5>()); break;
+    case 6: launch(std::integral_constant<int, 6>()); break;
+    case 7: launch(std::integral_constant<int, 7>()); break;
+    case 8: launch(std::integral_constant<int, 8>()); break;
+    case 9: launch(std::integral_constant<int, 9>()); break;
+    default: return hipErrorInvalidValue;
+    }
+    return e;
 }
 
 }  // namespace ara

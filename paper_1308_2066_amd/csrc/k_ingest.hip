@@ -24,18 +24,18 @@ hipError_t launch_fill_u32(uint32_t *p, size_t n, uint32_t v, hipStream_t s) {
 
 // One pass over the YET: every event ID in [0, catalog), offsets in CSR form.
 __global__ void k_validate_yet(const int32_t *__restrict__ ids, int64_t n_events, const int64_t *__restrict__ offs,
-                               int64_t n_trials, int32_t catalog, uint32_t *err) {
+                               int64_t n_trials, int32_t catalog, uint32_t *err, int check_ids) {
     const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     uint32_t bad = 0;
-    const int64_t n4 = n_events >> 2;
+    const int64_t n4 = check_ids ? n_events >> 2 : 0;
     const i32x4 *ids4 = reinterpret_cast<const i32x4 *>(ids);
     const uint32_t c = uint32_t(catalog);
     for (int64_t i = tid; i < n4; i += stride) {
         i32x4 v = __builtin_nontemporal_load(ids4 + i);
         if (uint32_t(v.x) >= c || uint32_t(v.y) >= c || uint32_t(v.z) >= c || uint32_t(v.w) >= c) bad |= ERR_ID_RANGE;
     }
-    for (int64_t i = (n4 << 2) + tid; i < n_events; i += stride)
+    for (int64_t i = (n4 << 2) + tid; check_ids && i < n_events; i += stride)
         if (uint32_t(ids[i]) >= c) bad |= ERR_ID_RANGE;
     for (int64_t t = tid; t <= n_trials; t += stride) {
         const int64_t o = offs[t];
@@ -48,8 +48,9 @@ __global__ void k_validate_yet(const int32_t *__restrict__ ids, int64_t n_events
 }
 
 hipError_t launch_validate_yet(const int32_t *ids, int64_t n_events, const int64_t *offs, int64_t n_trials,
-                               int32_t catalog, uint32_t *err, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate_yet, dim3(4096), dim3(256), 0, s, ids, n_events, offs, n_trials, catalog, err);
+                               int32_t catalog, uint32_t *err, hipStream_t s, bool check_ids) {
+    hipLaunchKernelGGL(k_validate_yet, dim3(4096), dim3(256), 0, s, ids, n_events, offs, n_trials, catalog, err,
+                       check_ids ? 1 : 0);
     return hipGetLastError();
 }
 

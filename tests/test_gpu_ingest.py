@@ -108,3 +108,37 @@ def test_paper_scale_binned_copy(ara_lib, gpu_ctx):
                 assert np.array_equal(run, want), f"trial {t} bin {b}"
     finally:
         A.ara_yet_release(y)
+
+
+@pytest.mark.parametrize("bad", [-1, 1_000_000, 2_000_000_000])
+def test_binned_yet_rejects_bad_ids_and_offsets(ara_lib, gpu_ctx, bad):
+    """A YET whose size takes the binned copy is checked in the copy's count pass:
+    one ID outside [0, catalog) anywhere (first trial, last trial, middle) fails the
+    creation with ARA_E_EVENT_ID_RANGE, bad offsets with ARA_E_BAD_OFFSETS, and the
+    context works afterwards."""
+    import torch
+    A = ara_lib
+    rng = np.random.default_rng(abs(bad) % 97)
+    n_trials, per = 3000, 400
+    C = 1_000_000
+    ids = rng.integers(0, C, size=n_trials * per).astype(np.int32)
+    offs = np.arange(0, n_trials * per + 1, per, dtype=np.int64)
+    for where in (0, ids.size - 1, ids.size // 2 + 13):
+        print(f"[case] binned yet bad id {bad} at {where}", flush=True)
+        bad_ids = ids.copy()
+        bad_ids[where] = bad
+        with pytest.raises(A.AraError) as e:
+            A.ara_yet_create(gpu_ctx, torch.from_numpy(bad_ids).cuda(), torch.from_numpy(offs).cuda(), C)
+        assert e.value.status == A.ARA_E_EVENT_ID_RANGE
+    for name, o in [("decreasing", np.concatenate([offs[:10], offs[9:10] - 1, offs[11:]])),
+                    ("last short", np.concatenate([offs[:-1], offs[-1:] - 1])),
+                    ("first not 0", offs + np.int64(1)), ("negative", np.concatenate([offs[:5], [-7], offs[6:]]))]:
+        print(f"[case] binned yet bad offsets: {name}", flush=True)
+        with pytest.raises(A.AraError) as e:
+            A.ara_yet_create(gpu_ctx, torch.from_numpy(ids).cuda(), torch.from_numpy(np.ascontiguousarray(o)).cuda(), C)
+        assert e.value.status == A.ARA_E_BAD_OFFSETS, name
+    yet = A.ara_yet_create(gpu_ctx, torch.from_numpy(ids).cuda(), torch.from_numpy(offs).cuda(), C)
+    try:
+        assert A.ara_yet_info(yet)[2] == 2, "this YET should keep a binned copy"
+    finally:
+        A.ara_yet_release(yet)
