@@ -718,7 +718,7 @@ def main():
     torch.cuda.synchronize()
     ingest_gpu_ms = ig0.elapsed_time(ig1)
     id_bytes = ara.ara_yet_info(yet)[2]
-    n_bins = (w.catalog_size + 32767) // 32768
+    n_bins = ara.ara_yet_binned_count(yet) if id_bytes == 2 else 0
     # device memory the handle adds to the caller's int32 IDs and offsets (the
     # layout ara_yet_create states: 2 B per occurrence rounded up to 8 per bin, plus
     # 4 B per (bin, trial + 1); else 3 B per occurrence for the packed copy)

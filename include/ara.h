@@ -90,10 +90,11 @@ typedef enum ara_placement {
     ARA_PLACE_LDS_BITMAP = 1,   /* LDS: 1 bit/event "occurrence loss nonzero" + ranks; values in L2  */
     ARA_PLACE_LDS_DENSE = 2,    /* LDS: the whole combined table (small catalogs)                    */
     ARA_PLACE_GLOBAL_DENSE = 3, /* HBM/L2: the whole combined table, gathered per occurrence         */
-    ARA_PLACE_LDS_TILES = 4     /* LDS: the filter and its nonzero values, one catalog tile at a time,
-                                   each tile's occurrences streamed from the YET's binned copy (needs
-                                   one: see ara_yet_create).  AUTO picks it when the YET has a binned
-                                   copy and the dense table does not fit in LDS                    */
+    ARA_PLACE_LDS_TILES = 4     /* LDS: the occurrence-net values of one 2^14-event catalog bin at a
+                                   time, each lane adding its trial's occurrences of the bin from the
+                                   YET's binned copy (needs one: see ara_yet_create).  AUTO picks it
+                                   when the YET has a binned copy and the dense table does not fit
+                                   in LDS                                                          */
 } ara_placement;
 
 /* Context options (ara_set_option). */
@@ -177,8 +178,8 @@ ara_status ara_sync(ara_ctx *ctx);
  * per occurrence).  Borrowed arrays must not change while the handle lives: later
  * analyses may read either form.
  * Binned copy: when ARA_OPT_YET_BINNING is 1, the catalog is larger than a dense
- * table in LDS (more than 20480 events) and at most 2^24 events, every trial has
- * fewer than 2^31 occurrences in each 2^15-event catalog bin, and the per-bin offsets
+ * table in LDS (more than 20480 events) and at most 2^23 events, every trial has
+ * fewer than 2^31 occurrences in each 2^14-event catalog bin, and the per-bin offsets
  * (4 bytes per trial and bin) stay below a quarter of the 2-byte IDs, the library also
  * stores the occurrences regrouped by catalog bin: bin by bin, each trial's
  * occurrences of that bin's events in time order as 2-byte IDs within the bin, with
@@ -200,7 +201,7 @@ ara_status ara_yet_release(ara_yet *yet);
 ara_status ara_yet_info(const ara_yet *yet, int64_t *n_events, int64_t *n_trials, int32_t *id_bytes);
 
 /* The YET's catalog-binned copy (see ara_yet_create), copied to host memory, for
- * checking and inspection.  Bin b holds catalog events [2^15 b, 2^15 (b + 1)).
+ * checking and inspection.  Bin b holds catalog events [2^14 b, 2^14 (b + 1)).
  *   n_bins      out: number of bins (0: the handle has no binned copy).
  *   region      NULL, or int64[n_bins + 1], out: region b of the copy is elements
  *               [region[b], region[b] + boff[b][n_trials]) (each region starts at

@@ -294,6 +294,13 @@ def ara_yet_info(y: Yet):
     return int(ne.value), int(nt.value), int(b.value)
 
 
+def ara_yet_binned_count(y: Yet) -> int:
+    """Number of catalog bins of the YET's binned copy (0 without one)."""
+    nb = _I32()
+    _check(_lib.ara_yet_binned(y.ptr, ctypes.byref(nb), None, None, None), y.ctx, "ara_yet_binned")
+    return int(nb.value)
+
+
 def ara_yet_binned(y: Yet):
     """The YET's catalog-binned copy as numpy arrays (region int64[n_bins + 1], boff
     uint32[n_bins, n_trials + 1], ids16 uint16[region[-1]]), or None without one."""

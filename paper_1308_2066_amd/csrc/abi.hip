@@ -731,8 +731,6 @@ static void layer_free(ara_layer *L) {
     dev_free(L->t.base32);
     dev_free(L->t.vals);
     dev_free(L->t.n_flagged);
-    dev_free(L->t.tiles);
-    dev_free(L->t.n_tiles);
     delete L;
 }
 
@@ -774,8 +772,6 @@ extern "C" ara_status ara_layer_create(ara_ctx *c, ara_elt *const *elts, int32_t
     if (s == ARA_OK) s = dev_alloc(c, &L->t.base32, align16(size_t(bitmap_supers(nblk)) * 4), "layer rank bases");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.vals, size_t(catalog) * 8, "layer values");
     if (s == ARA_OK) s = dev_alloc(c, &L->t.n_flagged, 16, "layer count");
-    if (s == ARA_OK) s = dev_alloc(c, &L->t.tiles, sizeof(Tile) * size_t(max_tiles(catalog)), "layer tiles");
-    if (s == ARA_OK) s = dev_alloc(c, &L->t.n_tiles, 16, "layer tile count");
     if (s == ARA_OK && n_elts > 0) {
         hipError_t e = hipMemcpy(L->d_descs, d.data(), sizeof(EltDesc) * size_t(n_elts), hipMemcpyHostToDevice);
         if (e != hipSuccess) s = hip_fail(c, e, "layer descriptors upload");
@@ -873,12 +869,9 @@ static TiledArgs tiled_args(const ara_yet *y, const ara_layer *L, int64_t t0, in
     a.t_begin = t0;
     a.t_end = t1;
     a.per_wg = (t1 - t0 + grid - 1) / std::max(1, grid);
-    a.bitmap = L->t.bitmap;
-    a.rank = L->t.rank;
-    a.vals = L->t.vals;
-    a.tiles = L->t.tiles;
-    a.n_tiles = L->t.n_tiles;
-    a.nblk = L->t.nblk;
+    a.occ = L->t.occ;
+    a.catalog = L->catalog;
+    a.n_bins = y->n_bins;
     a.agg_r = L->terms.agg_retention;
     a.agg_l = L->terms.agg_limit;
     a.ylt = ylt;
@@ -2049,7 +2042,7 @@ static void server_free(ara_server *sv) {
 static int64_t server_slot_bytes(int32_t C, int32_t n_pool) {
     const int64_t nblk = bitmap_blocks(C);
     return int64_t(C) * 8 * 3 + nblk * (16 + 16 + 4) + int64_t(align16(size_t(nblk) * 2)) +
-           int64_t(align16(size_t(bitmap_supers(int32_t(nblk))) * 4)) + int64_t(sizeof(Tile)) * max_tiles(C) + 64 +
+           int64_t(align16(size_t(bitmap_supers(int32_t(nblk))) * 4)) + 64 +
            int64_t(n_pool) * int64_t(sizeof(EltDesc));
 }
 

@@ -37,8 +37,6 @@ struct EltDesc {
 //   base32  per superblock (32768 events): number of flagged events before it
 //   occ     catalog binary64 values: occurrence-net loss min(max(comb[e]-OccR,0),OccL)
 //   vals    occ values of the flagged events, in event order (binary64)
-//   tiles   the filter cut into LDS-sized tiles for the tiled trial kernel
-struct Tile;
 struct LayerTables {
     void *comb = nullptr;
     double *occ = nullptr;
@@ -49,8 +47,6 @@ struct LayerTables {
     uint32_t *base32 = nullptr;
     double *vals = nullptr;
     uint32_t *n_flagged = nullptr;
-    Tile *tiles = nullptr;
-    uint32_t *n_tiles = nullptr;
     int32_t nblk = 0;
 };
 
@@ -164,16 +160,16 @@ hipError_t launch_trial_ylt_bitmap(const TrialArgs &a, int grid, int block, hipS
 size_t trial_bitmap_table_capacity();
 
 // ---- catalog-binned YET copy and the tiled trial kernel
-// The catalog is cut into bins of 2^15 events.  The binned copy holds, bin by bin
-// (bin-major), every trial's occurrences of that bin's events in trial order (time
-// order within a trial) as 15-bit IDs local to the bin, one uint16 each.  Region b
+// The catalog is cut into bins of 2^14 events (a bin's binary64 values fill most of
+// a workgroup's LDS).  The binned copy holds, bin by bin (bin-major), every trial's
+// occurrences of that bin's events in trial order (time order within a trial) as
+// 14-bit IDs local to the bin, one uint16 each.  Region b
 // starts at element region[b] (a multiple of 8); boff[b * stride + t] is where trial
 // t's run starts inside region b (trial t's occurrences of bin b are
 // [boff[b][t], boff[b][t + 1])), t = 0..n_trials.
-constexpr int kBinShift = 15;
+constexpr int kBinShift = 14;
 constexpr int32_t kBinEvents = 1 << kBinShift;
-constexpr int kBlocksPerBin = kBinEvents / kEventsPerBlock;   // 256
-constexpr int kMaxBins = 512;                                 // catalogs up to 2^24 events
+constexpr int kMaxBins = 512;                                 // catalogs up to 2^23 events
 inline int32_t catalog_bins(int32_t catalog) { return (catalog + kBinEvents - 1) / kBinEvents; }
 
 // Also checks the YET (ERR_OFFSETS, ERR_ID_RANGE in err; bad offsets or IDs are not
@@ -187,51 +183,24 @@ hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n
                               int32_t n_bins, const uint32_t *boff, int64_t stride, const int64_t *region,
                               uint16_t *ids16, hipStream_t s);
 
-// A tile of a layer's occurrence filter: 128-event blocks [blk_lo, blk_hi) of the
-// catalog, overlapping bins [bin_lo, bin_hi); rank_lo flagged events precede it and
-// n_vals lie in it.  In LDS: the bits of every block of those bins (4 words each,
-// zero outside [blk_lo, blk_hi), so that each bin starts 4 KB after the previous
-// one), a uint16 per word (flagged events of the tile before the word), then the
-// tile's flagged values.
-struct Tile {
-    int32_t blk_lo, blk_hi;
-    int32_t bin_lo, bin_hi;
-    uint32_t rank_lo, n_vals;
-};
 constexpr int kTiledWaves = 16;                 // waves per workgroup of the tiled kernel
-constexpr int kTiledQueue = 256;                // per-wave queue of flagged occurrences
-constexpr int kTiledWaveTrials = 256;           // LDS sums per wave (at least the trials per wave and pass)
-constexpr int kTiledPassTrials = 252 * kTiledWaves;   // trials per workgroup pass of the tiled kernel
-constexpr double kTiledStageCost = 0.25;        // a pass's tile staging, in occurrences per catalog event
+constexpr int kTiledWaveTrials = 252;           // trials per wave and pass (their sums are in LDS)
+constexpr int kTiledPassTrials = kTiledWaveTrials * kTiledWaves;   // trials per workgroup pass
+constexpr double kTiledStageCost = 0.25;        // a pass's bin staging, in occurrences per catalog event
                                                 // (orders a batch's passes; results do not depend on it)
-// LDS left for the tile after the per-wave queues (and a write slot per lane) and
-// per-trial sums
-constexpr int kTiledLdsBytes = kLdsMaxBytes - kTiledWaves * ((kTiledQueue + 64) * 4 + kTiledWaveTrials * 8);
-__host__ __device__ inline size_t tile_rank_offset(int32_t nb) { return size_t(nb) * 16; }
-__host__ __device__ inline size_t tile_vals_offset(int32_t nb) { return tile_rank_offset(nb) + align16(size_t(nb) * 8); }
-__host__ __device__ inline size_t tile_bytes(int32_t nb, uint32_t nv) { return tile_vals_offset(nb) + size_t(nv) * 8; }
-inline int32_t max_tiles(int32_t catalog) { return bitmap_blocks(catalog) + catalog_bins(catalog) + 1; }
-// Blocks held in LDS for a tile of blocks [lo, hi): its bins whole (clamped to the catalog).
-__host__ __device__ inline int32_t tile_span_blocks(int32_t lo, int32_t hi, int32_t nblk) {
-    const int32_t b0 = lo / kBlocksPerBin * kBlocksPerBin;
-    const int32_t b1 = ((hi - 1) / kBlocksPerBin + 1) * kBlocksPerBin;
-    return (b1 < nblk ? b1 : nblk) - b0;
-}
+static_assert(size_t(kBinEvents + 2) * 8 + size_t(kTiledWaves) * kTiledWaveTrials * 8 + 16 <= size_t(kLdsMaxBytes),
+              "a bin's binary64 values, the zero slot and the per-trial sums fit in LDS");
 
 struct TiledArgs {
-    const uint16_t *ids16;
-    const int64_t *region;      // n_bins + 1 element offsets
+    const uint16_t *ids16;      // the YET's catalog-binned copy (see ara_yet)
+    const int64_t *region;      // n_bins + 1 element offsets (multiples of 8)
     const uint32_t *boff;
     int64_t stride;             // entries per boff row
     int64_t t_begin, t_end;
-    int64_t per_wg;             // trials per workgroup (a multiple of 64)
-    const uint32_t *bitmap;     // the layer's filter (see LayerTables)
-    const uint32_t *rank;
-    const double *vals;
-    const Tile *tiles;
-    const uint32_t *n_tiles;
-    int32_t nblk;               // 128-event blocks of the catalog
-    int32_t pad_;
+    int64_t per_wg;             // trials per workgroup
+    const double *occ;          // the layer's occurrence-net values, one per catalog event
+    int32_t catalog;
+    int32_t n_bins;
     double agg_r, agg_l;
     double *ylt;
 };

@@ -82,87 +82,20 @@ __global__ __launch_bounds__(256) void k_layer_combine_bitmap(const EltDesc *__r
     if (lane == 3) nz[w0 + 1] = uint32_t(z >> 32);
 }
 
-// Tiles of the filter for the tiled trial kernel: consecutive 128-event blocks whose
-// bits (padded to whole bins), per-word counts and flagged values fit
-// kTiledLdsBytes.  Whole catalog bins are added while they fit (a tile then reads
-// each of its bins' occurrences once); a bin too dense to fit alone is cut at block
-// boundaries.  One thread, after the ranks are written: at most a few hundred bins
-// (their start counts in LDS, read through at_bin), and block steps, which read the
-// rank table, only inside bins that must be cut.  The counts at the open tile's ends
-// are kept, so each test of a longer tile reads one count.
-template <typename AtBin>
-__device__ __forceinline__ void plan_tiles(const uint32_t *rank, AtBin at_bin, uint32_t total, int32_t nblk,
-                                           int32_t n_bins, Tile *tiles, uint32_t *n_tiles) {
-    auto rk_bin = [&](int32_t b) -> uint32_t { return b >= nblk ? total : at_bin(b / kBlocksPerBin); };
-    auto rk_blk = [&](int32_t b) -> uint32_t {
-        return b >= nblk ? total : (b % kBlocksPerBin == 0 ? at_bin(b / kBlocksPerBin) : rank[b]);
-    };
-    auto fits = [&](int32_t lo, uint32_t r_lo, int32_t hi, uint32_t r_hi) {
-        return tile_bytes(tile_span_blocks(lo, hi, nblk), r_hi - r_lo) <= size_t(kTiledLdsBytes);
-    };
-    uint32_t nt = 0;
-    auto emit = [&](int32_t lo, uint32_t r_lo, int32_t hi, uint32_t r_hi) {
-        Tile t;
-        t.blk_lo = lo;
-        t.blk_hi = hi;
-        t.bin_lo = lo / kBlocksPerBin;
-        t.bin_hi = (hi - 1) / kBlocksPerBin + 1;
-        t.rank_lo = r_lo;
-        t.n_vals = r_hi - r_lo;
-        tiles[nt++] = t;
-    };
-    int32_t lo = 0, hi = 0;   // the open tile: blocks [lo, hi), counts r_lo, r_hi at its ends
-    uint32_t r_lo = rk_bin(0), r_hi = r_lo;
-    for (int32_t bin = 0; bin < n_bins; ++bin) {
-        const int32_t b0 = bin * kBlocksPerBin, b1 = min(b0 + kBlocksPerBin, nblk);
-        const uint32_t r1 = rk_bin(b1);
-        if (fits(lo, r_lo, b1, r1)) {
-            hi = b1;
-            r_hi = r1;
-            continue;
-        }
-        if (hi > lo) emit(lo, r_lo, hi, r_hi);
-        lo = hi = b0;
-        r_lo = r_hi = rk_bin(b0);
-        if (fits(b0, r_lo, b1, r1)) {
-            hi = b1;
-            r_hi = r1;
-            continue;
-        }
-        for (int32_t b = b0; b < b1; ++b) {   // hi == b on entry to each step
-            const uint32_t rb = rk_blk(b + 1);
-            if (!fits(lo, r_lo, b + 1, rb)) {
-                emit(lo, r_lo, b, r_hi);
-                lo = b;
-                r_lo = r_hi;
-            }
-            hi = b + 1;
-            r_hi = rb;
-        }
-    }
-    if (hi > lo) emit(lo, r_lo, hi, r_hi);
-    *n_tiles = nt;
-}
-
-
 // Exclusive prefix of per-block set-bit counts (rank), the same split into a 16-bit
 // offset within its superblock of 256 blocks and a 32-bit base per superblock
 // (rel16/base32: a smaller table to keep in LDS), and the total.  Single workgroup
-// of 1024.  With `tiles`, thread 0 then cuts the filter into tiles for the tiled
-// trial kernel (plan_tiles, above).
+// of 1024.
 __global__ __launch_bounds__(1024) void k_layer_rank(const uint32_t *__restrict__ bitmap, int32_t nblk,
                                                      uint32_t *__restrict__ rank, uint32_t *__restrict__ n_flagged,
-                                                     uint16_t *__restrict__ rel16, uint32_t *__restrict__ base32,
-                                                     int32_t n_bins, Tile *__restrict__ tiles,
-                                                     uint32_t *__restrict__ n_tiles) {
+                                                     uint16_t *__restrict__ rel16, uint32_t *__restrict__ base32) {
     // each thread takes 8 consecutive blocks (their loads issued together), so a
     // catalog of up to 2^20 events is one round of loads and one scan
     constexpr int kPer = 8, kChunk = 1024 * kPer;
-    static_assert(kChunk % kBlocksPerSuper == 0 && kBlocksPerSuper % kPer == 0 && kBlocksPerBin == kBlocksPerSuper,
-                  "superblocks and bins are whole in a chunk and start at a thread's first block");
+    static_assert(kChunk % kBlocksPerSuper == 0 && kBlocksPerSuper % kPer == 0,
+                  "superblocks are whole in a chunk and start at a thread's first block");
     __shared__ uint32_t wsum[16];
     __shared__ uint32_t sbase[kChunk / kBlocksPerSuper];
-    __shared__ uint32_t at_bin[kMaxBins + 1];   // counts at bin starts, for the planner
     __shared__ uint32_t rk[kChunk];             // the chunk's ranks, for coalesced stores
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     uint32_t carry = 0;
@@ -195,7 +128,6 @@ __global__ __launch_bounds__(1024) void k_layer_rank(const uint32_t *__restrict_
             const int32_t sb = b0 / kBlocksPerSuper;
             sbase[(b0 - base) / kBlocksPerSuper] = r;
             base32[sb] = r;
-            if (sb < kMaxBins) at_bin[sb] = r;
         }
 #pragma unroll
         for (int j = 0; j < kPer; ++j) {
@@ -212,11 +144,7 @@ __global__ __launch_bounds__(1024) void k_layer_rank(const uint32_t *__restrict_
         carry += total;
         __syncthreads();
     }
-    if (tid != 0) return;
-    *n_flagged = carry;
-    if (!tiles) return;
-    at_bin[n_bins] = carry;
-    plan_tiles(rank, [&](int32_t i) { return at_bin[i]; }, carry, nblk, n_bins, tiles, n_tiles);
+    if (tid == 0) *n_flagged = carry;
 }
 
 __global__ __launch_bounds__(256) void k_layer_compact(const double *__restrict__ occ, int32_t catalog,
@@ -234,13 +162,10 @@ __global__ __launch_bounds__(256) void k_layer_compact(const double *__restrict_
     vals[idx] = occ[e];
 }
 
-// Ranks (with rel16/base32 and, for catalogs of at most kMaxBins bins, the tiles:
-// tiles serve only YETs with a catalog-binned copy) and the compacted values.
+// Ranks (with rel16/base32) and the compacted values.
 static hipError_t launch_rank_compact(int32_t catalog, const LayerTables &t, hipStream_t s) {
-    const int32_t n_bins = catalog_bins(catalog);
-    Tile *tiles = t.tiles && n_bins <= kMaxBins ? t.tiles : nullptr;
     hipLaunchKernelGGL(k_layer_rank, dim3(1), dim3(1024), 0, s, t.bitmap, t.nblk, t.rank, t.n_flagged, t.rel16,
-                       t.base32, n_bins, tiles, t.n_tiles);
+                       t.base32);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const unsigned ev_blocks = unsigned((int64_t(catalog) + 255) / 256);

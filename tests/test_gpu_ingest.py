@@ -15,7 +15,7 @@ import pytest
 import synth
 
 pytestmark = pytest.mark.gpu
-BIN_SHIFT = 15
+BIN_SHIFT = 14
 
 
 def _say(msg):
@@ -56,13 +56,13 @@ def test_binned_copy_matches_definition(ara_lib, gpu_ctx, case):
     import torch
     A = ara_lib
     rng = np.random.default_rng({"poisson": 11, "ragged_long_trial": 12, "one_bin_heavy": 13}[case])
-    catalog = 200_003   # 7 bins, the last one partial
+    catalog = 200_003   # 13 bins, the last one partial
     if case == "poisson":
         lens = rng.poisson(300, size=5000)
         lens[::97] = 0   # empty trials
     elif case == "ragged_long_trial":
         # a block of trials with more occurrences than one workgroup stages in LDS
-        lens = rng.poisson(40, size=3000)
+        lens = rng.poisson(80, size=3000)
         lens[1234] = 90_000
         lens[2999] = 70_001
     else:
@@ -119,7 +119,7 @@ def test_binned_yet_rejects_bad_ids_and_offsets(ara_lib, gpu_ctx, bad):
     import torch
     A = ara_lib
     rng = np.random.default_rng(abs(bad) % 97)
-    n_trials, per = 3000, 400
+    n_trials, per = 3000, 600
     C = 1_000_000
     ids = rng.integers(0, C, size=n_trials * per).astype(np.int32)
     offs = np.arange(0, n_trials * per + 1, per, dtype=np.int64)

@@ -1,8 +1,9 @@
-"""The tiled YLT kernel (catalog-binned YET copy, filter and values in LDS one tile at
-a time) against the oracle and against the LDS-bitmap kernel.
+"""The tiled YLT kernel (catalog-binned YET copy, one catalog bin's occurrence-net
+values in LDS at a time, a lane per trial) against the oracle and against the
+LDS-bitmap kernel.
 
 Bar: binary64 YLT within 1e-12 * max(|y|, P_k) of the oracle (the tiled kernel adds a
-trial's occurrence-net losses grouped by catalog tile, another order of the same
+trial's occurrence-net losses grouped by catalog bin, another order of the same
 non-negative terms); the same bits on every run; batched jobs equal plain launches
 bit for bit."""
 from __future__ import annotations
@@ -138,8 +139,8 @@ def _tiles_vs_oracle_and_bitmap(A, S, ctx, w, what, sub_ranges=()):
 
 
 def test_paper_shape_many_tiles(A, S, gpu_ctx):
-    """1M-event catalog, 16 ELTs: about a dozen tiles of whole bins; unsaturated
-    aggregate terms so every YLT value is checked."""
+    """1M-event catalog, 16 ELTs: 62 bins staged in turn; unsaturated aggregate terms
+    so every YLT value is checked."""
     w = synth.workload_paper_scale(n_trials=8_000)
     w = w.with_terms((1e5, 5e6, 1.5e8, INF))
     _say("tiled paper shape 8k x 1000")
@@ -147,8 +148,9 @@ def test_paper_shape_many_tiles(A, S, gpu_ctx):
 
 
 def test_dense_layer_splits_bins(A, S, gpu_ctx):
-    """Every event flagged (values of a whole bin do not fit in LDS): tiles cut inside
-    bins, each reading its bin's occurrences and keeping its own IDs."""
+    """Every event flagged (no zero in any bin's values), trials of 0 to 4099
+    occurrences: runs longer than the prefetched 32 IDs read the rest when reached,
+    odd-starting runs drop the previous run's last ID."""
     rng = np.random.default_rng(301)
     C = 100_003                                  # not a multiple of the bin size
     ids_all = np.arange(C, dtype=np.int32)
@@ -180,8 +182,8 @@ def test_ragged_and_empty_runs(A, S, gpu_ctx):
 
 
 def test_single_tile_and_determinism(A, S, gpu_ctx):
-    """A catalog whose whole filter and values fit one tile; runs repeat bit for bit;
-    without the binned copy the bitmap kernel gives the same values within the bound."""
+    """A 60,000-event catalog (four bins); runs repeat bit for bit; without the binned
+    copy the bitmap kernel gives the same values within the bound."""
     rng = np.random.default_rng(303)
     w = _workload(rng, rng.integers(500, 1500, size=3000), 60_000, nnz=3_000)
     _say("tiled single tile")
@@ -233,13 +235,13 @@ def test_batch_with_tiled_jobs_equals_plain(A, S, gpu_ctx):
 
 def test_several_passes_per_workgroup(A, S, gpu_ctx):
     """1,200,000 short trials: each persistent workgroup owns more trials than one pass
-    (4032) holds, so the per-trial sums are reset and the tiles restaged per pass;
-    a 70,000-event catalog in three bins, binary32 tables (too large for the dense LDS
-    table) and non-identity ELT terms."""
+    (4032) holds, so the per-trial sums are reset and the bins restaged per pass;
+    a 70,000-event catalog in five bins (the last cut short), binary32 tables (too
+    large for the dense LDS table) and non-identity ELT terms."""
     rng = np.random.default_rng(305)
     C = 70_000
     n = 1_200_000
-    lengths = rng.integers(25, 46, size=n)
+    lengths = rng.integers(40, 61, size=n)
     w = _workload(rng, lengths, C, n_elts=3, nnz=12_000)
     w = synth.Workload("passes", w.event_ids, w.trial_offsets, C, w.elts, w.layer_terms,
                        [(1.1, 100.0, 2e6), (1.0, 0.0, INF), (0.9, 0.0, INF)], (10.0,), 0)
@@ -265,13 +267,14 @@ def test_several_passes_per_workgroup(A, S, gpu_ctx):
 
 
 def test_large_catalog_many_bins_and_rank_chunks(A, S, gpu_ctx):
-    """A 3,000,003-event catalog: 92 bins (tiles over many bins, a last bin cut short)
-    and 23,438 filter blocks, which the rank kernel takes in three chunks of 8192; the
-    flagged count equals the one computed here from the ELTs, and the YLT matches the
-    oracle and the global dense-table kernel."""
-    w = synth.workload_paper_scale(n_trials=20_000, catalog=3_000_003, n_elts=8, nnz=200_000)
+    """A 3,000,003-event catalog: 184 bins (a last bin cut short) and 23,438 filter
+    blocks, which the rank kernel takes in three chunks of 8192; the flagged count
+    equals the one computed here from the ELTs, and the YLT matches the oracle and the
+    global dense-table kernel.  2000 occurrences per trial, so that the per-(bin,
+    trial) offsets stay within a quarter of the binned IDs and the copy is kept."""
+    w = synth.workload_paper_scale(n_trials=20_000, per_trial=2000, catalog=3_000_003, n_elts=8, nnz=200_000)
     w = w.with_terms((1e5, 5e6, 1.5e8, INF))
-    _say("tiled large catalog 3M, 20k x 1000")
+    _say("tiled large catalog 3M, 20k x 2000")
     an = _open(A, S, gpu_ctx, w)
     try:
         assert A.ara_yet_info(an.yet)[2] == 2, "binned copy expected"
