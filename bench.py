@@ -782,10 +782,12 @@ def main():
     # algorithmic bytes are defined on int32 event IDs and int64 trial offsets; the
     # kernels stream other forms, reported beside them as moved_bytes: the packed
     # 3-byte copy with the same offsets, or the binned 2-byte copy with a 4-byte
-    # offset per (catalog bin, trial) instead of the trial offsets
+    # offset per (catalog bin, trial) instead of the trial offsets (the tiled kernel
+    # then reads the layer's binary64 occurrence-net table, once per workgroup pass
+    # from L2: counted once here)
     alg_bytes = 4 * w.n_events + 8 * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * n_flagged
     if kernel == "k_trial_tiled":
-        moved_bytes = 2 * w.n_events + 4 * n_bins * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * n_flagged
+        moved_bytes = 2 * w.n_events + 4 * n_bins * (w.n_trials + 1) + 8 * w.n_trials + 8 * w.catalog_size
     else:
         ib = 3 if not args.no_packing and w.catalog_size <= 1 << 24 else 4   # the packed copy, else int32
         moved_bytes = alg_bytes - (4 - ib) * w.n_events
