@@ -418,10 +418,10 @@ ara_status ara_tune_cache_load(ara_ctx *ctx, const char *path);
  * tables share the L2.  Items and workgroups count the persistent launches of the
  * dense and filter placements only: the jobs whose placement is ARA_PLACE_LDS_TILES (as
  * ara_analyze would choose it) run together in one more launch of the tiled kernel,
- * whose items are the passes ara_analyze's launch would run for each of them (so the
- * same YLT bits), costliest first, taken from a counter by whichever workgroup is free;
- * they add nothing here (a batch of only such jobs reports 0 and 0).  Any output
- * pointer may be NULL. */
+ * whose items are passes of up to 4032 trials of one job (a trial's YLT does not depend
+ * on the pass that holds it, so the same bits as ara_analyze), costliest first, taken
+ * from a counter by whichever workgroup is free; they add nothing here (a batch of only
+ * such jobs reports 0 and 0).  Any output pointer may be NULL. */
 ara_status ara_batch_info(const ara_batch *batch, int32_t *n_items, int32_t *grid, int64_t *events_per_item,
                           int32_t *graph);
 

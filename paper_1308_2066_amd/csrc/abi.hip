@@ -1296,20 +1296,22 @@ static TiledBatch batch_tiled(const ara_batch *b) {
     return t;
 }
 
-// The passes k_trial_tiled runs for a job of `grid` workgroups (trials [tb, te)), as
-// items of job index k, each with its cost (occurrences, plus a tile staging).
-static void tiled_passes(int32_t k, int64_t tb, int64_t te, int grid, double mean_len, double stage,
+// A tiled job's trials [tb, te) as work items of job index k: passes of nearly equal
+// size, as few as kTiledPassTrials allows (each pass stages every bin of the catalog
+// once), with each one's cost (occurrences, plus the staging).  A trial's YLT does not
+// depend on the pass that holds it (its lane adds the bins in order and each run's
+// occurrences in order), so the items give the plain launch's bits.
+static void tiled_passes(int32_t k, int64_t tb, int64_t te, double mean_len, double stage,
                          std::vector<std::pair<double, TiledItem>> &out) {
-    const int64_t per_wg = (te - tb + grid - 1) / std::max(1, grid);
-    for (int w = 0; w < grid; ++w) {
-        const int64_t w0 = tb + int64_t(w) * per_wg, w1 = std::min(w0 + per_wg, te);
-        for (int64_t p = w0; p < w1; p += kTiledPassTrials) {
-            TiledItem it{};
-            it.job = k;
-            it.t0 = p;
-            it.t1 = std::min(p + int64_t(kTiledPassTrials), w1);
-            out.emplace_back(double(it.t1 - it.t0) * mean_len + stage, it);
-        }
+    const int64_t n = te - tb;
+    const int64_t passes = (n + kTiledPassTrials - 1) / kTiledPassTrials;
+    const int64_t per = (n + passes - 1) / std::max<int64_t>(1, passes);
+    for (int64_t p = tb; p < te; p += per) {
+        TiledItem it{};
+        it.job = k;
+        it.t0 = p;
+        it.t1 = std::min(p + per, te);
+        out.emplace_back(double(it.t1 - it.t0) * mean_len + stage, it);
     }
 }
 
@@ -1369,7 +1371,7 @@ extern "C" ara_status ara_batch_create(ara_ctx *c, const ara_job *jobs, int32_t 
         if (h.mode == kModeTiled && jb.trial_end > jb.trial_begin) {
             b->tjobs.push_back(tiled_args(jb.yet, jb.layer, jb.trial_begin, jb.trial_end, jb.ylt, tl.grid));
             b->tiled_job.push_back(j);
-            tiled_passes(int32_t(b->tjobs.size() - 1), jb.trial_begin, jb.trial_end, tl.grid, mean,
+            tiled_passes(int32_t(b->tjobs.size() - 1), jb.trial_begin, jb.trial_end, mean,
                          kTiledStageCost * double(jb.layer->catalog), titems);
         }
         b->terms_gen.push_back(jb.layer->terms_gen);

@@ -186,7 +186,7 @@ hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n
 constexpr int kTiledWaves = 16;                 // waves per workgroup of the tiled kernel
 constexpr int kTiledWaveTrials = 252;           // trials per wave and pass (their sums are in LDS)
 constexpr int kTiledPassTrials = kTiledWaveTrials * kTiledWaves;   // trials per workgroup pass
-constexpr double kTiledStageCost = 0.25;        // a pass's bin staging, in occurrences per catalog event
+constexpr double kTiledStageCost = 0.5;         // a pass's bin staging, in occurrences per catalog event
                                                 // (orders a batch's passes; results do not depend on it)
 static_assert(size_t(kBinEvents + 2) * 8 + size_t(kTiledWaves) * kTiledWaveTrials * 8 + 16 <= size_t(kLdsMaxBytes),
               "a bin's binary64 values, the zero slot and the per-trial sums fit in LDS");

@@ -281,10 +281,10 @@ __device__ __forceinline__ TiledArgs load_args(const TiledArgs *jobs, int32_t j)
     return a;
 }
 
-// Many analyses in one launch (YLTs): the items are the passes that k_trial_tiled
-// would run for each analysis (the same trials per pass, so the same YLT bits), taken
-// in list order from a counter by whichever workgroup is free; a workgroup stops once
-// the counter passes the list.
+// Many analyses in one launch (YLTs): each item is a pass over up to kTiledPassTrials
+// trials of one analysis, taken in list order from a counter by whichever workgroup is
+// free; a workgroup stops once the counter passes the list.  A trial's YLT does not
+// depend on the pass that holds it, so these give the bits of k_trial_tiled.
 __global__ __launch_bounds__(1024) void k_trial_tiled_items(const TiledArgs *__restrict__ jobs,
                                                             const TiledItem *__restrict__ items, int32_t n_items,
                                                             uint32_t *__restrict__ next) {
