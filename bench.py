@@ -720,9 +720,9 @@ def main():
     id_bytes = ara.ara_yet_info(yet)[2]
     n_bins = ara.ara_yet_binned_count(yet) if id_bytes == 2 else 0
     # device memory the handle adds to the caller's int32 IDs and offsets (the
-    # layout ara_yet_create states: 2 B per occurrence rounded up to 8 per bin, plus
+    # layout ara_yet_create states: 2 B per occurrence plus 24 B per bin, plus
     # 4 B per (bin, trial + 1); else 3 B per occurrence for the packed copy)
-    yet_extra = (2 * w.n_events + 8 * n_bins + 4 * n_bins * (w.n_trials + 1)) if id_bytes == 2 else \
+    yet_extra = (2 * w.n_events + 24 * n_bins + 4 * n_bins * (w.n_trials + 1)) if id_bytes == 2 else \
         (3 * w.n_events if id_bytes == 3 else 0)
     log(f"ingest (validate + {'binned' if id_bytes == 2 else 'packed' if id_bytes == 3 else 'no'} copy): "
         f"{ingest_ms:.2f} ms wall, {ingest_gpu_ms:.2f} ms on the stream; {yet_extra / 1e9:.3f} GB added")

@@ -186,8 +186,8 @@ ara_status ara_sync(ara_ctx *ctx);
  * per-(bin, trial) offsets.  Analyses of layers whose table does not fit in LDS then
  * read that copy (ARA_PLACE_LDS_TILES); other placements then stream the int32 IDs.
  * If the device has no memory for it, the handle is created without it.  Device
- * memory the handle adds to the caller's arrays: 2 bytes per occurrence (rounded up
- * to 8 per bin) plus 4 bytes per (bin, trial + 1) with a binned copy, else 3 bytes per
+ * memory the handle adds to the caller's arrays: 2 bytes per occurrence plus 24
+ * bytes per bin plus 4 bytes per (bin, trial + 1) with a binned copy, else 3 bytes per
  * occurrence with a packed copy.
  * Errors: ARA_E_INVALID_ARG, ARA_E_EVENT_ID_RANGE, ARA_E_BAD_OFFSETS, ARA_E_OOM, ARA_E_DEVICE. */
 ara_status ara_yet_create(ara_ctx *ctx, const int32_t *event_ids, int64_t n_events,

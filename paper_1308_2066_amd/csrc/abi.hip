@@ -447,45 +447,59 @@ static bool yet_binning_applies(const ara_ctx *c, const ara_yet *y) {
 
 // Builds the catalog-binned copy when it applies; the YET is usable without it, so
 // running out of device memory only skips it.  Its count pass checks the offsets and
-// every event ID: *ids_checked tells whether it ran.
+// every event ID: *ids_checked tells whether it ran.  A YET of fewer than 2^31
+// occurrences has fewer than that in every bin: its copy is then sized from the
+// occurrence count (each region rounded up to 8 elements), the region starts are
+// computed on the device and the passes run back to back, with one wait at the end
+// (a bad ID or offset found by the count pass stops the later passes on the device).
+// Larger YETs read the bins' lengths back first to check them.
 static ara_status yet_build_binned(ara_ctx *c, ara_yet *y, bool *ids_checked) {
     const int32_t nb = catalog_bins(y->catalog);
     const int64_t n = y->n_trials;
     *ids_checked = false;
     if (!yet_binning_applies(c, y)) return ARA_OK;
     y->stride = (n + 1 + 3) & ~int64_t(3);
+    const bool one_wait = y->n_events < (int64_t(1) << 31);
     uint32_t *sums = nullptr;
     ara_status s = dev_alloc(c, &y->boff, size_t(nb) * size_t(y->stride) * 4, "binned yet offsets");
     if (s == ARA_OK) s = dev_alloc(c, &sums, bin_scan_scratch_words(n + 1, nb) * 4, "binned yet scan");
+    if (s == ARA_OK) s = dev_alloc(c, &y->region, size_t(nb + 1) * 8, "binned yet regions");
+    if (s == ARA_OK && one_wait)
+        s = dev_alloc(c, &y->ids16, size_t(y->n_events + 8 * int64_t(nb)) * 2 + 16, "binned yet ids");
     if (s == ARA_OK) {
         hipError_t e = launch_bin_count(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->catalog, c->d_err,
                                         c->stream);
         if (e == hipSuccess) e = launch_bin_scan(y->boff, y->stride, n + 1, nb, sums, c->stream);
-        std::vector<uint32_t> len(static_cast<size_t>(nb));
-        if (e == hipSuccess)
-            e = hipMemcpy2DAsync(len.data(), 4, y->boff + n, size_t(y->stride) * 4, 4, size_t(nb), hipMemcpyDeviceToHost,
-                                 c->stream);
-        s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet offsets");
-        *ids_checked = e == hipSuccess;   // an ID outside the catalog shows in s
-        std::vector<int64_t> region(static_cast<size_t>(nb) + 1, 0);
-        bool fits = true;
-        for (int32_t b = 0; s == ARA_OK && b < nb; ++b) {
-            fits = fits && len[size_t(b)] < (1u << 31);
-            region[size_t(b) + 1] = region[size_t(b)] + ((int64_t(len[size_t(b)]) + 7) & ~int64_t(7));
-        }
-        if (s == ARA_OK && !fits) {
-            dev_free(sums);
-            yet_free_binned(y);
-            return ARA_OK;
-        }
-        if (s == ARA_OK) s = dev_alloc(c, &y->region, region.size() * 8, "binned yet regions");
-        if (s == ARA_OK) s = dev_alloc(c, &y->ids16, size_t(region.back()) * 2 + 16, "binned yet ids");
-        if (s == ARA_OK) {
-            e = hipMemcpy(y->region, region.data(), region.size() * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = launch_bin_regions(y->boff, y->stride, n, nb, y->region, c->d_err, c->stream);
+        if (one_wait) {
             if (e == hipSuccess)
                 e = launch_bin_scatter(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->region, y->ids16,
-                                       c->stream);
-            s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet scatter");
+                                       c->d_err, c->stream);
+            s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet");
+            *ids_checked = e == hipSuccess;   // an ID outside the catalog shows in s
+        } else {
+            std::vector<uint32_t> len(static_cast<size_t>(nb));
+            int64_t total = 0;
+            if (e == hipSuccess)
+                e = hipMemcpy2DAsync(len.data(), 4, y->boff + n, size_t(y->stride) * 4, 4, size_t(nb),
+                                     hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(&total, y->region + nb, 8, hipMemcpyDeviceToHost, c->stream);
+            s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet offsets");
+            *ids_checked = e == hipSuccess;
+            bool fits = true;
+            for (int32_t b = 0; s == ARA_OK && b < nb; ++b) fits = fits && len[size_t(b)] < (1u << 31);
+            if (s == ARA_OK && !fits) {
+                dev_free(sums);
+                yet_free_binned(y);
+                return ARA_OK;
+            }
+            if (s == ARA_OK) s = dev_alloc(c, &y->ids16, size_t(total) * 2 + 16, "binned yet ids");
+            if (s == ARA_OK) {
+                e = launch_bin_scatter(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->region, y->ids16,
+                                       c->d_err, c->stream);
+                s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet scatter");
+            }
         }
     }
     dev_free(sums);

@@ -179,9 +179,13 @@ hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_e
 hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, int32_t n_bins, uint32_t *block_sums,
                            hipStream_t s);
 size_t bin_scan_scratch_words(int64_t n_entries, int32_t n_bins);
+// Region starts (n_bins + 1, int64, multiples of 8) from the scanned offsets.
+hipError_t launch_bin_regions(const uint32_t *boff, int64_t stride, int64_t n_trials, int32_t n_bins, int64_t *region,
+                              const uint32_t *err, hipStream_t s);
+// Both skip their work when *err is nonzero (the count pass found a bad ID or offset).
 hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
                               int32_t n_bins, const uint32_t *boff, int64_t stride, const int64_t *region,
-                              uint16_t *ids16, hipStream_t s);
+                              uint16_t *ids16, const uint32_t *err, hipStream_t s);
 
 constexpr int kTiledWaves = 16;                 // waves per workgroup of the tiled kernel
 constexpr int kTiledWaveTrials = 252;           // trials per wave and pass (their sums are in LDS)

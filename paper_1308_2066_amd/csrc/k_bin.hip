@@ -155,6 +155,44 @@ hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, in
     return hipGetLastError();
 }
 
+// Region starts from the scanned offsets: region[0] = 0, region[b + 1] = region[b] +
+// (bin b's length rounded up to 8), bin b's length being boff[b][n_trials] after the
+// scan.  One wave, up to 512 bins (8 per lane).  Skipped when the count pass found a
+// bad ID or offset (err set): the scatter is skipped then too.
+__global__ __launch_bounds__(64) void k_bin_regions(const uint32_t *__restrict__ boff, int64_t stride, int64_t n_trials,
+                                                    int32_t n_bins, int64_t *__restrict__ region,
+                                                    const uint32_t *__restrict__ err) {
+    if (*err != 0u) return;
+    const int lane = threadIdx.x;
+    int64_t v[8], own = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int32_t b = lane * 8 + k;
+        v[k] = b < n_bins ? (int64_t(boff[int64_t(b) * stride + n_trials]) + 7) & ~int64_t(7) : 0;
+        own += v[k];
+    }
+    int64_t inc = own;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    int64_t run = inc - own;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const int32_t b = lane * 8 + k;
+        if (b < n_bins) region[b] = run;
+        run += v[k];
+    }
+    if (lane == 63) region[n_bins] = inc;   // the total
+}
+
+hipError_t launch_bin_regions(const uint32_t *boff, int64_t stride, int64_t n_trials, int32_t n_bins, int64_t *region,
+                              const uint32_t *err, hipStream_t s) {
+    if (n_bins > kMaxBins || kMaxBins > 8 * 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bin_regions, dim3(1), dim3(64), 0, s, boff, stride, n_trials, n_bins, region, err);
+    return hipGetLastError();
+}
+
 // Writes each occurrence at region[b] + boff[b][t] + (its rank among trial t's
 // earlier occurrences of bin b).  A workgroup takes `per_block` consecutive trials;
 // their occurrences of bin b form one contiguous span of region b, so when the
@@ -194,7 +232,8 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
                                                                     const int64_t *__restrict__ offs, int64_t n_trials,
                                                                     int32_t n_bins, const uint32_t *__restrict__ boff,
                                                                     int64_t stride, const int64_t *__restrict__ region,
-                                                                    uint16_t *__restrict__ ids16, int64_t per_block) {
+                                                                    uint16_t *__restrict__ ids16, int64_t per_block,
+                                                                    const uint32_t *__restrict__ err) {
     constexpr int kBins = NBITS <= 6 ? 64 : kMaxBins;   // bins the LDS tables hold
     __shared__ uint16_t stage[STAGED ? kScatterCap : 2];
     __shared__ uint32_t cur[kScatterWaves][kBins];      // next position of the wave's trial's run, per bin
@@ -203,6 +242,8 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int64_t t0 = int64_t(blockIdx.x) * per_block;
     if (t0 >= n_trials) return;
+    // the count pass found a bad ID or offset: the counts do not describe the input
+    if (*err != 0u) return;
     const int64_t t1 = min(t0 + per_block, n_trials);
     // a block with more occurrences than the LDS holds is left to the unstaged launch
     // (and the unstaged launch leaves the others)
@@ -294,7 +335,7 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
 
 hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
                               int32_t n_bins, const uint32_t *boff, int64_t stride, const int64_t *region,
-                              uint16_t *ids16, hipStream_t s) {
+                              uint16_t *ids16, const uint32_t *err, hipStream_t s) {
     if (n_trials <= 0) return hipSuccess;
     if (n_bins > kMaxBins) return hipErrorInvalidValue;
     const int64_t per = bin_scatter_block_trials(n_events, n_trials);
@@ -307,11 +348,11 @@ hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n
     auto launch = [&](auto nb_const) {
         constexpr int NB = decltype(nb_const)::value;
         hipLaunchKernelGGL((k_bin_scatter<NB, true>), dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs,
-                           n_trials, n_bins, boff, stride, region, ids16, per);
+                           n_trials, n_bins, boff, stride, region, ids16, per, err);
         e = hipGetLastError();
         if (e != hipSuccess) return;
         hipLaunchKernelGGL((k_bin_scatter<NB, false>), dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs,
-                           n_trials, n_bins, boff, stride, region, ids16, per);
+                           n_trials, n_bins, boff, stride, region, ids16, per, err);
         e = hipGetLastError();
     };
     switch (nbits) {
