@@ -307,3 +307,35 @@ def test_large_catalog_many_bins_and_rank_chunks(A, S, gpu_ctx):
         _close(ylt.cpu().numpy(), ref_ev, "large catalog events")
     finally:
         an.release()
+
+
+def test_largest_binned_catalog(A, S, gpu_ctx):
+    """A 2^23-event catalog: 512 bins, the most a binned copy holds (the scatter's
+    9-bit bin numbers, every lane of the region kernel); the YLT and the occurrence
+    maxima of the tiled kernel match the oracle.  One event more (513 bins) keeps no
+    binned copy, and the analysis still matches the oracle."""
+    rng = np.random.default_rng(306)
+    C = 1 << 23
+    lengths = rng.integers(3500, 5500, size=1500)
+    w = _workload(rng, lengths, C, n_elts=2, nnz=200_000)
+    w = w.with_terms((5e4, 1e6, 2e8, INF))
+    _say("tiled largest binned catalog 2^23")
+    an = _open(A, S, gpu_ctx, w)
+    try:
+        assert A.ara_yet_info(an.yet)[2] == 2, "binned copy expected"
+        assert A.ara_yet_binned_count(an.yet) == 512
+        got = _run(A, gpu_ctx, an, 0)
+        assert _run(A, gpu_ctx, an, TILES).tobytes() == got.tobytes(), "auto placement must pick the tiled kernel"
+        ref = oracle.analyze_workload(w, threads=oracle.max_threads())
+        _close(got, ref, "2^23 catalog")
+        _check_occ_max(A, gpu_ctx, an, ref, "2^23 catalog", [(1, 1499)])
+    finally:
+        an.release()
+    w2 = synth.Workload("tiled", w.event_ids, w.trial_offsets, C + 1, w.elts, w.layer_terms, None, (10.0,), 0)
+    _say("catalog 2^23 + 1: no binned copy")
+    an = _open(A, S, gpu_ctx, w2)
+    try:
+        assert A.ara_yet_info(an.yet)[2] != 2
+        _close(_run(A, gpu_ctx, an, 0), oracle.analyze_workload(w2, threads=oracle.max_threads()), "2^23 + 1 catalog")
+    finally:
+        an.release()
