@@ -462,14 +462,13 @@ static ara_status yet_build_binned(ara_ctx *c, ara_yet *y, bool *ids_checked) {
     const bool one_wait = y->n_events < (int64_t(1) << 31);
     uint32_t *sums = nullptr;
     ara_status s = dev_alloc(c, &y->boff, size_t(nb) * size_t(y->stride) * 4, "binned yet offsets");
-    if (s == ARA_OK) s = dev_alloc(c, &sums, bin_scan_scratch_words(n + 1, nb) * 4, "binned yet scan");
+    if (s == ARA_OK) s = dev_alloc(c, &sums, bin_offsets_scratch_words(n, nb) * 4, "binned yet scan");
     if (s == ARA_OK) s = dev_alloc(c, &y->region, size_t(nb + 1) * 8, "binned yet regions");
     if (s == ARA_OK && one_wait)
         s = dev_alloc(c, &y->ids16, size_t(y->n_events + 8 * int64_t(nb)) * 2 + 16, "binned yet ids");
     if (s == ARA_OK) {
-        hipError_t e = launch_bin_count(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->catalog, c->d_err,
-                                        c->stream);
-        if (e == hipSuccess) e = launch_bin_scan(y->boff, y->stride, n + 1, nb, sums, c->stream);
+        hipError_t e = launch_bin_offsets(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->catalog, sums,
+                                          c->d_err, c->stream);
         if (e == hipSuccess) e = launch_bin_regions(y->boff, y->stride, n, nb, y->region, c->d_err, c->stream);
         if (one_wait) {
             if (e == hipSuccess)

@@ -53,6 +53,7 @@ struct LayerTables {
 constexpr int kEventsPerBlock = 128;        // events per bitmap block
 constexpr int kBlocksPerSuper = 256;        // bitmap blocks per rank superblock (32768 events)
 constexpr int kLdsMaxBytes = 160 * 1024;    // LDS per workgroup on gfx950
+constexpr int kBufWord3 = 0x00020000;       // raw buffer descriptor word 3 (32-bit data format)
 constexpr int kQueueRow = 64;               // queued events are processed one wave-row at a time
 constexpr int kQueueCapMax = 192;           // per-wave queue capacity (events), a multiple of kQueueRow
 constexpr int kQueueCapMin = 128;
@@ -172,13 +173,16 @@ constexpr int32_t kBinEvents = 1 << kBinShift;
 constexpr int kMaxBins = 512;                                 // catalogs up to 2^23 events
 inline int32_t catalog_bins(int32_t catalog) { return (catalog + kBinEvents - 1) / kBinEvents; }
 
-// Also checks the YET (ERR_OFFSETS, ERR_ID_RANGE in err; bad offsets or IDs are not
-// followed or counted): the binned copy's count pass doubles as ingest's check.
-hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials, int32_t n_bins,
-                            uint32_t *boff, int64_t stride, int32_t catalog, uint32_t *err, hipStream_t s);
-hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, int32_t n_bins, uint32_t *block_sums,
-                           hipStream_t s);
-size_t bin_scan_scratch_words(int64_t n_entries, int32_t n_bins);
+// boff[b][t] for t = 0..n_trials (stride a multiple of 4, at least n_trials + 1):
+// the exclusive prefix sums over trials of each trial's occurrence count in bin b,
+// so boff[b][n_trials] is bin b's length.  sums: bin_offsets_scratch_words(n_trials,
+// n_bins) words of scratch.  Also checks the YET (ERR_OFFSETS, ERR_ID_RANGE in err;
+// bad offsets or IDs are not followed or counted): the count pass doubles as
+// ingest's check.
+hipError_t launch_bin_offsets(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
+                              int32_t n_bins, uint32_t *boff, int64_t stride, int32_t catalog, uint32_t *sums,
+                              uint32_t *err, hipStream_t s);
+size_t bin_offsets_scratch_words(int64_t n_trials, int32_t n_bins);
 // Region starts (n_bins + 1, int64, multiples of 8) from the scanned offsets.
 hipError_t launch_bin_regions(const uint32_t *boff, int64_t stride, int64_t n_trials, int32_t n_bins, int64_t *region,
                               const uint32_t *err, hipStream_t s);

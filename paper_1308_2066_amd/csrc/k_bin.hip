@@ -2,14 +2,19 @@
 //
 // The trial kernel of Section III-B looks every occurrence up in a table over the
 // whole catalog.  When the layer's table does not fit in LDS, the tiled trial
-// kernel instead walks the catalog in LDS-sized tiles and, for each tile, streams
-// only the occurrences of that tile's events.  To make those occurrences contiguous
-// the YET is regrouped by catalog bin (2^15 events): region b holds, for every
-// trial in order, the trial's occurrences of bin-b events in time order, each as
-// its 15-bit ID within the bin.  boff[b][t] gives where trial t's run starts in
-// region b, so a tile's occurrences of any trial range are one contiguous span per
-// bin.  The regrouping only changes which occurrences are read together; each
-// trial still has exactly its own occurrences.
+// kernel instead walks the catalog one 2^14-event bin at a time, with the bin's
+// slice of the table in LDS, and for each bin streams only the occurrences of
+// that bin's events.  To make those occurrences contiguous the YET is regrouped by
+// bin: region b holds, for every trial in order, the trial's occurrences of bin-b
+// events in time order, each as its 14-bit ID within the bin (2 bytes).
+// boff[b][t] gives where trial t's run starts in region b, so the occurrences of
+// any trial range in one bin are one contiguous span.  The regrouping only changes
+// which occurrences are read together; each trial still has exactly its own
+// occurrences.
+//
+// The build runs count, row scans, region starts and scatter back to back on the
+// stream; the count pass checks the YET, and the later passes do nothing once it
+// has flagged an error.
 #include <type_traits>
 
 #include "ara_internal.h"
@@ -17,13 +22,41 @@
 namespace ara {
 
 // boff[b][t] = number of trial t's occurrences in bin b; boff[b][n_trials] = 0.
-// One wave per trial (four per workgroup), counting in the wave's own LDS
-// histogram; a wave's LDS operations complete in order, so it needs no barrier.
 // The YET is checked on the way, as ara_yet_create states: a trial's offsets must lie
 // in [0, n_events] in order, the first be 0 and the last n_events (else ERR_OFFSETS
 // and the trial's IDs are not read), every ID be in [0, catalog) (else ERR_ID_RANGE
 // and the ID is not counted).
+//
+// Up to 512 bins: one wave per trial (four per workgroup), counting in the wave's
+// own LDS histogram, then writing the counts, 4 bytes into each bin's row.
 constexpr int kCountWaves = 4;
+
+// One wave adds trial t's occurrences to the LDS histogram h (a wave's LDS
+// operations complete in order, so the caller needs no barrier before reading it).
+__device__ __forceinline__ void count_trial(const int32_t *__restrict__ ids, const int64_t *__restrict__ offs, int64_t t,
+                                            int64_t n_events, int64_t n_trials, uint32_t cat, int lane, uint32_t *h,
+                                            bool &bad, bool &bad_offs) {
+    int64_t o0 = offs[t], o1 = offs[t + 1];
+    if (o0 < 0 || o1 < o0 || o1 > n_events || (t == 0 && o0 != 0) || (t == n_trials - 1 && o1 != n_events)) {
+        bad_offs = true;
+        o1 = o0;   // read none of this trial's IDs
+    }
+    constexpr int kAhead = 16;   // loads in flight per lane (4 KB per wave: enough to keep HBM busy)
+    for (int64_t base = o0; base < o1; base += 64 * kAhead) {
+        uint32_t v[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            const int64_t i = base + 64 * u + lane;
+            v[u] = i < o1 ? uint32_t(ids[i]) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead; ++u) {
+            if (base + 64 * u + lane >= o1) continue;
+            if (v[u] < cat) atomicAdd(&h[v[u] >> kBinShift], 1u);
+            else bad = true;
+        }
+    }
+}
 
 __global__ __launch_bounds__(kCountWaves * 64) void k_bin_count(const int32_t *__restrict__ ids,
                                                                 const int64_t *__restrict__ offs, int64_t n_events,
@@ -40,26 +73,7 @@ __global__ __launch_bounds__(kCountWaves * 64) void k_bin_count(const int32_t *_
     for (int64_t t = int64_t(blockIdx.x) * kCountWaves + wave; t < n_trials; t += int64_t(gridDim.x) * kCountWaves) {
         for (int32_t b = lane; b < n_bins; b += 64) h[b] = 0u;
         __builtin_amdgcn_wave_barrier();
-        int64_t o0 = offs[t], o1 = offs[t + 1];
-        if (o0 < 0 || o1 < o0 || o1 > n_events || (t == 0 && o0 != 0) || (t == n_trials - 1 && o1 != n_events)) {
-            bad_offs = true;
-            o1 = o0;   // read none of this trial's IDs
-        }
-        constexpr int kAhead = 16;   // loads in flight per lane (4 KB per wave: enough to keep HBM busy)
-        for (int64_t base = o0; base < o1; base += 64 * kAhead) {
-            uint32_t v[kAhead];
-#pragma unroll
-            for (int u = 0; u < kAhead; ++u) {
-                const int64_t i = base + 64 * u + lane;
-                v[u] = i < o1 ? uint32_t(ids[i]) : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < kAhead; ++u) {
-                if (base + 64 * u + lane >= o1) continue;
-                if (v[u] < cat) atomicAdd(&h[v[u] >> kBinShift], 1u);
-                else bad = true;
-            }
-        }
+        count_trial(ids, offs, t, n_events, n_trials, cat, lane, h, bad, bad_offs);
         __builtin_amdgcn_wave_barrier();
         for (int32_t b = lane; b < n_bins; b += 64) boff[b * stride + t] = h[b];
         __builtin_amdgcn_wave_barrier();
@@ -69,12 +83,108 @@ __global__ __launch_bounds__(kCountWaves * 64) void k_bin_count(const int32_t *_
     if (flags && lane == 0) atomicOr(err, flags);
 }
 
-hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials, int32_t n_bins,
-                            uint32_t *boff, int64_t stride, int32_t catalog, uint32_t *err, hipStream_t s) {
-    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n_trials + kCountWaves - 1) / kCountWaves, 65536));
-    hipLaunchKernelGGL(k_bin_count, dim3(unsigned(grid)), dim3(kCountWaves * 64), 0, s, ids, offs, n_events, n_trials,
-                       n_bins, boff, stride, catalog, err);
-    return hipGetLastError();
+// Up to 64 bins (the paper-scale catalog has 62): a workgroup takes 64 consecutive
+// trials (a block) at a time and its waves count them into an LDS table, a row per
+// trial.  Each bin's 64 counts then become their exclusive prefix sums within the
+// block (one wave scan), written with one coalesced 256-byte store, and the block's
+// total goes to sums[b][block].  (The per-trial stores of the kernel above, 4 bytes
+// at a row stride apart, cost 0.3 ms more of a 10^9-occurrence ingest, and scanning
+// the counts in separate passes 0.2 ms more.)
+constexpr int kCountBlock = 64;
+
+__global__ __launch_bounds__(kCountWaves * 64) void k_bin_count_block(const int32_t *__restrict__ ids,
+                                                                      const int64_t *__restrict__ offs,
+                                                                      int64_t n_events, int64_t n_trials,
+                                                                      int32_t n_bins, uint32_t *__restrict__ boff,
+                                                                      int64_t stride, int32_t catalog,
+                                                                      uint32_t *__restrict__ sums, uint32_t *err) {
+    __shared__ uint32_t hist[kCountBlock][65];   // padded rows: a bin's column reads without bank conflicts
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t cat = uint32_t(catalog);
+    const int64_t nblk = (n_trials + kCountBlock - 1) / kCountBlock;
+    bool bad = false, bad_offs = false;
+    for (int64_t t0 = int64_t(blockIdx.x) * kCountBlock; t0 < n_trials; t0 += int64_t(gridDim.x) * kCountBlock) {
+        for (int i = threadIdx.x; i < kCountBlock * 65; i += kCountWaves * 64) (&hist[0][0])[i] = 0u;
+        __syncthreads();
+        for (int j = wave; j < kCountBlock; j += kCountWaves) {
+            const int64_t t = t0 + j;
+            if (t >= n_trials) break;
+            count_trial(ids, offs, t, n_events, n_trials, cat, lane, hist[j], bad, bad_offs);
+        }
+        __syncthreads();
+        for (int32_t b = wave; b < n_bins; b += kCountWaves) {
+            const uint32_t x = hist[lane][b];   // 0 past the last trial
+            uint32_t inc = x;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t y = __shfl_up(inc, o, 64);
+                if (lane >= o) inc += y;
+            }
+            if (t0 + lane < n_trials) boff[b * stride + t0 + lane] = inc - x;
+            if (lane == 63) sums[b * nblk + t0 / kCountBlock] = inc;
+        }
+        __syncthreads();
+    }
+    const uint32_t flags = (__builtin_amdgcn_ballot_w64(bad) ? ERR_ID_RANGE : 0u) |
+                           (__builtin_amdgcn_ballot_w64(bad_offs) ? ERR_OFFSETS : 0u);
+    if (flags && lane == 0) atomicOr(err, flags);
+}
+
+// The block totals of one bin (a workgroup per bin) become their exclusive prefix
+// sums, 16 per thread and 16384 per round; the bin's length goes to boff[b][n_trials].
+__global__ __launch_bounds__(1024) void k_bin_block_scan(uint32_t *__restrict__ sums, int64_t nblk,
+                                                         uint32_t *__restrict__ boff, int64_t stride,
+                                                         int64_t n_trials) {
+    __shared__ uint32_t wsum[16];
+    uint32_t *row = sums + int64_t(blockIdx.x) * nblk;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < nblk; c0 += 1024 * 16) {
+        const int64_t i0 = c0 + 16 * int64_t(threadIdx.x);
+        uint32_t v[16], own = 0;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            v[k] = i0 + k < nblk ? row[i0 + k] : 0u;
+            own += v[k];
+        }
+        uint32_t inc = own;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_up(inc, o, 64);
+            if (lane >= o) inc += y;
+        }
+        if (lane == 63) wsum[w] = inc;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < w) before += wsum[k];
+            total += wsum[k];
+        }
+        uint32_t run = carry + before + inc - own;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (i0 + k < nblk) row[i0 + k] = run;
+            run += v[k];
+        }
+        carry += total;
+        __syncthreads();   // wsum is reused
+    }
+    if (threadIdx.x == 0) boff[int64_t(blockIdx.x) * stride + n_trials] = carry;
+}
+
+// boff[b][t] += (prefix of bin b before trial t's block), t < n_trials: 4096 trials
+// per workgroup, 4 per thread (a block holds 64, so one prefix per thread).
+__global__ __launch_bounds__(1024) void k_bin_block_add(uint32_t *__restrict__ boff, int64_t stride, int64_t n_trials,
+                                                        const uint32_t *__restrict__ sums, int64_t nblk) {
+    typedef uint32_t u32x4b __attribute__((ext_vector_type(4)));
+    const int64_t t = int64_t(blockIdx.x) * 4096 + 4 * int64_t(threadIdx.x);
+    if (t >= n_trials) return;
+    const uint32_t add = sums[int64_t(blockIdx.y) * nblk + t / kCountBlock];
+    uint32_t *row = boff + int64_t(blockIdx.y) * stride;
+    if (t + 4 <= n_trials) {   // rows start 16-byte aligned (stride is a multiple of 4)
+        u32x4b *p = reinterpret_cast<u32x4b *>(row + t);
+        *p = *p + add;
+    } else {
+        for (int64_t k = t; k < n_trials; ++k) row[k] += add;   // leaves the length at n_trials
+    }
 }
 
 // Exclusive prefix sums along each boff row (entries 0..n_entries-1), in three
@@ -82,9 +192,6 @@ hipError_t launch_bin_count(const int32_t *ids, const int64_t *offs, int64_t n_e
 // totals), per block (add the block's offset).
 constexpr int kScanBlock = 4096;
 
-size_t bin_scan_scratch_words(int64_t n_entries, int32_t n_bins) {
-    return size_t((n_entries + kScanBlock - 1) / kScanBlock) * size_t(n_bins);
-}
 
 __global__ __launch_bounds__(1024) void k_bin_scan_local(uint32_t *__restrict__ boff, int64_t stride,
                                                          int64_t n_entries, uint32_t *__restrict__ sums) {
@@ -140,7 +247,7 @@ __global__ __launch_bounds__(1024) void k_bin_scan_add(uint32_t *__restrict__ bo
         if (i0 + k < n_entries) row[i0 + k] += add;
 }
 
-hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, int32_t n_bins, uint32_t *sums,
+static hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, int32_t n_bins, uint32_t *sums,
                            hipStream_t s) {
     const int64_t nblk = (n_entries + kScanBlock - 1) / kScanBlock;
     if (nblk > 65535 || n_bins > 65535) return hipErrorInvalidValue;
@@ -153,6 +260,40 @@ hipError_t launch_bin_scan(uint32_t *boff, int64_t stride, int64_t n_entries, in
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_bin_scan_add, grid, dim3(1024), 0, s, boff, stride, n_entries, sums);
     return hipGetLastError();
+}
+
+
+size_t bin_offsets_scratch_words(int64_t n_trials, int32_t n_bins) {
+    const int64_t per_row = n_bins <= 64 ? (n_trials + kCountBlock - 1) / kCountBlock
+                                         : (n_trials + 1 + kScanBlock - 1) / kScanBlock;
+    return size_t(per_row) * size_t(n_bins);
+}
+
+hipError_t launch_bin_offsets(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
+                              int32_t n_bins, uint32_t *boff, int64_t stride, int32_t catalog, uint32_t *sums,
+                              uint32_t *err, hipStream_t s) {
+    if (n_trials <= 0 || n_bins <= 0 || n_bins > kMaxBins) return hipErrorInvalidValue;
+    if ((stride & 3) || stride < n_trials + 1) return hipErrorInvalidValue;
+    hipError_t e;
+    if (n_bins <= 64) {
+        const int64_t nblk = (n_trials + kCountBlock - 1) / kCountBlock;
+        const int64_t add_blocks = (n_trials + 4095) / 4096;
+        if (add_blocks > 65535) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_bin_count_block, dim3(unsigned(std::min<int64_t>(nblk, 65536))), dim3(kCountWaves * 64),
+                           0, s, ids, offs, n_events, n_trials, n_bins, boff, stride, catalog, sums, err);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bin_block_scan, dim3(unsigned(n_bins)), dim3(1024), 0, s, sums, nblk, boff, stride,
+                           n_trials);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_bin_block_add, dim3(unsigned(add_blocks), unsigned(n_bins)), dim3(1024), 0, s, boff,
+                           stride, n_trials, sums, nblk);
+        return hipGetLastError();
+    }
+    const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n_trials + kCountWaves - 1) / kCountWaves, 65536));
+    hipLaunchKernelGGL(k_bin_count, dim3(unsigned(grid)), dim3(kCountWaves * 64), 0, s, ids, offs, n_events, n_trials,
+                       n_bins, boff, stride, catalog, err);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_bin_scan(boff, stride, n_trials + 1, n_bins, sums, s);
 }
 
 // Region starts from the scanned offsets: region[0] = 0, region[b + 1] = region[b] +
@@ -197,17 +338,28 @@ hipError_t launch_bin_regions(const uint32_t *boff, int64_t stride, int64_t n_tr
 // earlier occurrences of bin b).  A workgroup takes `per_block` consecutive trials;
 // their occurrences of bin b form one contiguous span of region b, so when the
 // block's occurrences fit in LDS they are placed there first (a counting sort by
-// bin) and each bin's span is then written with consecutive stores.  A block with
-// more occurrences than the LDS holds writes every occurrence to its place directly.
+// bin) and each bin's span is then written out whole.  A block with more
+// occurrences than the LDS holds writes every occurrence to its place directly.
+//
 // Either way a wave takes one trial at a time, 64 occurrences per step in time
 // order; lanes of a step that share a bin are ranked in lane order, so each run keeps
 // the trial's time order.  The mask of lanes with the same bin comes from LDS when
 // the bins fit a wave's table (at most 64: every lane ORs its bit into its bin's
-// word, reads the word back and clears it; ORs do not depend on the order the lanes
-// are taken in), else from one ballot per bit of the bin number (six ballots per
-// step cost 1.6 ms of a 10^9-occurrence ingest, the LDS masks 0.5 ms).
-constexpr int kScatterWaves = 16;
-constexpr int kScatterCap = 61440;   // occurrences staged per workgroup (120 KB)
+// word and reads the word back; ORs do not depend on the order the lanes are taken
+// in), else from one ballot per bit of the bin number (six ballots per step cost
+// 1.6 ms of a 10^9-occurrence ingest, the LDS masks 0.5 ms).  With at most 64 bins
+// and staging, lane l keeps bin l's next position in a register (read by the other
+// lanes with a cross-lane permute) and clears bin l's mask word after the step by
+// exchanging it for 0, which also gives it the bin's count for the step.
+//
+// Staging: 72 KB of LDS per 8-wave workgroup, so two workgroups share a CU and one
+// places occurrences while the other starts or writes out.  Each bin's span starts
+// in LDS at the same position modulo 8 as its destination, so it goes out in
+// aligned 16-byte stores with at most 7 IDs on either side (2-byte stores cost
+// 0.15 ms more of a 10^9-occurrence ingest, one 16-wave workgroup per CU 0.13 ms).
+constexpr int kScatterWaves = 8;
+constexpr int kScatterCap = 36864;   // IDs staged per workgroup (72 KB)
+constexpr int kScatterPad = 7;       // slack per bin for the alignment of its span
 
 int64_t bin_scatter_block_trials(int64_t n_events, int64_t n_trials) {
     const double mean = n_trials > 0 ? double(n_events) / double(n_trials) : 0.0;
@@ -238,12 +390,13 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
                                                                     uint16_t *__restrict__ ids16, int64_t per_block,
                                                                     const uint32_t *__restrict__ err) {
     constexpr int kBins = NBITS <= 6 ? 64 : kMaxBins;   // bins the LDS tables hold
-    __shared__ uint16_t stage[STAGED ? kScatterCap : 2];
+    __shared__ __attribute__((aligned(16))) uint16_t stage[STAGED ? kScatterCap : 8];
     __shared__ uint32_t cur[kScatterWaves][kBins];      // next position of the wave's trial's run, per bin
     __shared__ uint32_t lbase[kBins + 1];               // start of bin b's span in `stage`
     __shared__ uint32_t bstart[kBins];                  // boff[b][t0]
+    __shared__ uint32_t blen[kBins];                    // bin b's span length
     __shared__ uint64_t lanes_of[NBITS <= 6 ? kScatterWaves : 1][NBITS <= 6 ? 64 : 1];   // per wave and bin: its lanes
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t t0 = int64_t(blockIdx.x) * per_block;
     if (t0 >= n_trials) return;
     // the count pass found a bad ID or offset: the counts do not describe the input
@@ -251,7 +404,7 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
     const int64_t t1 = min(t0 + per_block, n_trials);
     // a block with more occurrences than the LDS holds is left to the unstaged launch
     // (and the unstaged launch leaves the others)
-    if ((offs[t1] - offs[t0] <= int64_t(kScatterCap)) != STAGED) return;
+    if ((offs[t1] - offs[t0] + int64_t(kScatterPad) * n_bins <= int64_t(kScatterCap)) != STAGED) return;
     constexpr bool staged = STAGED;
     uint32_t *wc = cur[wave];
     uint64_t *lm = lanes_of[NBITS <= 6 ? wave : 0];
@@ -263,12 +416,12 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
             lbase[b + 1] = boff[b * stride + t1] - s;
         }
         __syncthreads();
-        if (wave == 0) {   // exclusive scan of the span lengths, 8 bins per lane
+        if (wave == 0) {   // exclusive scan of the padded span lengths, 8 bins per lane
             uint32_t v[8], own = 0;
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int32_t b = lane * 8 + k;
-                v[k] = b < n_bins ? lbase[b + 1] : 0u;
+                v[k] = b < n_bins ? lbase[b + 1] + kScatterPad : 0u;
                 own += v[k];
             }
             uint32_t inc = own;
@@ -280,76 +433,158 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int32_t b = lane * 8 + k;
-                if (b < n_bins) lbase[b] = run;
+                if (b < n_bins) {   // the span starts at the destination's position modulo 8
+                    lbase[b] = run + ((bstart[b] - run) & 7u);
+                    blen[b] = v[k] - kScatterPad;
+                }
                 run += v[k];
             }
             if (lane == 63) lbase[n_bins] = run;
         }
         __syncthreads();
     }
-    // a trial's IDs are read a chunk of kChunkSteps steps of 64 ahead of the step
-    // that places them, so a wave waits for about one load per chunk rather than one
-    // per step, and enough bytes are in flight to keep HBM busy
-    constexpr int kChunkSteps = 16;   // 4 KB of IDs in flight per wave (a 1000-event trial at once)
-    for (int64_t t = t0 + wave; t < t1; t += kScatterWaves) {
-        for (int32_t b = lane; b < n_bins; b += 64)
-            wc[b] = staged ? lbase[b] + boff[b * stride + t] - bstart[b] : boff[b * stride + t];
-        __builtin_amdgcn_wave_barrier();
-        const int64_t o0 = offs[t], o1 = offs[t + 1];
-        uint32_t cur[kChunkSteps];
+    // A wave places its trials t0 + wave, t0 + wave + kScatterWaves, ... one chunk of
+    // kChunkSteps steps at a time.  Before it places a chunk it issues the loads of the
+    // next one, with the next trial's run starts and the offsets of the trial after
+    // that, all of them whatever the path (IDs past a trial's end read as 0 from the
+    // buffer record), so the count of outstanding loads is the same on every path and
+    // a wave waits only for the chunk it places (conditional loads made the compiler
+    // wait for every load in flight before each chunk: 0.35 ms more of a
+    // 10^9-occurrence ingest).
+    constexpr int kChunkSteps = 16, kChunkIds = 64 * kChunkSteps;
+    constexpr int kWB = (kBins + 63) / 64;
+    typedef int64_t i64x2 __attribute__((ext_vector_type(2)));
+    auto load_offs = [&](int64_t tt) -> i64x2 {   // offs[tt], offs[tt + 1], tt clamped to a trial
+        const int64_t tc = min(tt, n_trials - 1);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)(offs + tc), 0, 16, kBufWord3);
+        return __builtin_bit_cast(i64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0));
+    };
+    auto load_wb = [&](int64_t tt, uint32_t (&w)[kWB]) {   // boff[b][tt], b = lane + 64 k
+        const int64_t tc = min(tt, n_trials);
 #pragma unroll
-        for (int u = 0; u < kChunkSteps; ++u) {
-            const int64_t i = o0 + 64 * u + lane;
-            cur[u] = i < o1 ? uint32_t(ids[i]) : 0u;
+        for (int k = 0; k < kWB; ++k) w[k] = boff[min(lane + 64 * k, n_bins - 1) * stride + tc];
+    };
+    auto load_chunk = [&](int64_t start, int64_t end, uint32_t (&c)[kChunkSteps]) {
+        const int32_t avail = int32_t(max(int64_t(0), min(end - start, int64_t(kChunkIds))));
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc((void *)(ids + (avail ? start : 0)), 0, avail * 4, kBufWord3);
+#pragma unroll
+        for (int u = 0; u < kChunkSteps; ++u) c[u] = __builtin_amdgcn_raw_buffer_load_b32(rs, (64 * u + lane) * 4, 0, 0);
+    };
+    auto uniform = [](int64_t v) {   // a value the wave holds in every lane, in scalar registers
+        const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+        const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(uint64_t(v) >> 32))));
+        return int64_t((uint64_t(hi) << 32) | lo);
+    };
+    int64_t t = t0 + wave, o0 = 0, o1 = 0;
+    uint32_t cv[kChunkSteps], wb[kWB];
+    i64x2 pn;   // offsets of trial t + kScatterWaves
+    {
+        const i64x2 p = load_offs(t);
+        load_wb(t, wb);
+        pn = load_offs(t + kScatterWaves);
+        if (t < t1) {
+            o0 = uniform(p[0]);
+            o1 = uniform(p[1]);
         }
-        for (int64_t base = o0; base < o1; base += 64 * kChunkSteps) {
-            uint32_t nxt[kChunkSteps];
+        load_chunk(o0, o1, cv);
+    }
+    int64_t base = o0;
+    uint32_t curs = 0;   // NBITS <= 6, staged: lane l holds bin l's next position
+    while (t < t1) {
+        if (base == o0) {
+            if (NBITS <= 6 && staged) {
+                curs = lane < n_bins ? lbase[lane] + wb[0] - bstart[lane] : 0u;
+            } else {
 #pragma unroll
-            for (int u = 0; u < kChunkSteps; ++u) {
-                const int64_t i = base + 64 * (kChunkSteps + u) + lane;
-                nxt[u] = i < o1 ? uint32_t(ids[i]) : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < kChunkSteps; ++u) {
-                const bool valid = base + 64 * u + lane < o1;
-                const uint32_t id = cur[u];
-                const uint32_t b = id >> kBinShift;
-                uint32_t rank, count;
-                if (NBITS <= 6) {
-                    // the lanes of this step with bin b: every lane ORs its bit into its bin's
-                    // mask (an OR does not depend on the order the lanes are taken in), reads the
-                    // mask back and clears it
-                    const uint32_t bb = valid ? b : 63u;
-                    __hip_atomic_fetch_or(&lm[bb], valid ? uint64_t(1) << lane : uint64_t(0), __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_WAVEFRONT);
-                    const uint64_t m = lm[bb];
-                    __builtin_amdgcn_wave_barrier();
-                    lm[bb] = 0;
-                    rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-                    count = uint32_t(__popcll(m));
-                } else {
-                    same_bin_rank<NBITS>(b, __builtin_amdgcn_ballot_w64(valid), rank, count);
-                }
-                const uint32_t at = wc[b];
-                const uint16_t local = uint16_t(id & uint32_t(kBinEvents - 1));
-                if (valid) {
-                    if (staged) stage[at + rank] = local;
-                    else ids16[region[b] + int64_t(at + rank)] = local;
-                    if (rank + 1 == count) wc[b] = at + count;
+                for (int k = 0; k < kWB; ++k) {
+                    const int32_t b = lane + 64 * k;
+                    if (b < n_bins) wc[b] = staged ? lbase[b] + wb[k] - bstart[b] : wb[k];
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-#pragma unroll
-            for (int u = 0; u < kChunkSteps; ++u) cur[u] = nxt[u];
         }
+        // the next chunk: the rest of trial t, else the start of trial t + kScatterWaves
+        const bool same = base + kChunkIds < o1;
+        const int64_t nt = same ? t : t + kScatterWaves;
+        int64_t nb = same ? base + kChunkIds : uniform(pn[0]), ne = same ? o1 : uniform(pn[1]);
+        if (nt >= t1) nb = ne = 0;
+        uint32_t wbn[kWB], nxt[kChunkSteps];
+        load_wb(nt, wbn);
+        const i64x2 qn = load_offs(nt + kScatterWaves);
+        load_chunk(nb, ne, nxt);
+        const int32_t len = int32_t(min(o1 - base, int64_t(kChunkIds)));
+#pragma unroll
+        for (int u = 0; u < kChunkSteps; ++u) {
+            const bool valid = 64 * u + lane < len;
+            const uint32_t id = cv[u];
+            const uint32_t b = id >> kBinShift;
+            uint32_t rank, count;
+            if (NBITS <= 6 && staged) {
+                const uint32_t bb = valid ? b : 63u;
+                __hip_atomic_fetch_or(&lm[bb], valid ? uint64_t(1) << lane : uint64_t(0), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
+                const uint64_t m = lm[bb];
+                __builtin_amdgcn_wave_barrier();
+                // lane l takes bin l's mask and clears it in one exchange
+                const uint64_t ml = __hip_atomic_exchange(&lm[lane], uint64_t(0), __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_WAVEFRONT);
+                rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+                const uint32_t at = uint32_t(__builtin_amdgcn_ds_bpermute(int(b << 2), int(curs)));
+                if (valid) stage[at + rank] = uint16_t(id & uint32_t(kBinEvents - 1));
+                curs += uint32_t(__popcll(ml));
+                __builtin_amdgcn_wave_barrier();
+                continue;
+            }
+            if (NBITS <= 6) {
+                // the lanes of this step with bin b: every lane ORs its bit into its bin's
+                // mask (an OR does not depend on the order the lanes are taken in), reads the
+                // mask back and clears it
+                const uint32_t bb = valid ? b : 63u;
+                __hip_atomic_fetch_or(&lm[bb], valid ? uint64_t(1) << lane : uint64_t(0), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
+                const uint64_t m = lm[bb];
+                __builtin_amdgcn_wave_barrier();
+                lm[bb] = 0;
+                rank = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+                count = uint32_t(__popcll(m));
+            } else {
+                same_bin_rank<NBITS>(b, __builtin_amdgcn_ballot_w64(valid), rank, count);
+            }
+            const uint32_t at = wc[b];
+            const uint16_t local = uint16_t(id & uint32_t(kBinEvents - 1));
+            if (valid) {
+                if (staged) stage[at + rank] = local;
+                else ids16[region[b] + int64_t(at + rank)] = local;
+                if (rank + 1 == count) wc[b] = at + count;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+#pragma unroll
+        for (int u = 0; u < kChunkSteps; ++u) cv[u] = nxt[u];
+#pragma unroll
+        for (int k = 0; k < kWB; ++k) wb[k] = wbn[k];
+        if (!same) o0 = nb;
+        o1 = ne;
+        base = nb;
+        t = nt;
+        pn = qn;
     }
     if (!staged) return;
     __syncthreads();
-    // each bin's span to its place in region b, consecutive lanes on consecutive IDs
+    // each bin's span to its place in region b: up to 7 IDs to the first 16-byte
+    // boundary, whole 16-byte groups (consecutive lanes on consecutive groups), the rest
+    typedef uint32_t u32x4s __attribute__((ext_vector_type(4)));
     for (int32_t b = wave; b < n_bins; b += kScatterWaves) {
-        const uint32_t l0 = lbase[b], len = lbase[b + 1] - l0;
+        const uint32_t l0 = lbase[b], len = blen[b];
         uint16_t *dst = ids16 + region[b] + int64_t(bstart[b]);
-        for (uint32_t k = lane; k < len; k += 64) dst[k] = stage[l0 + k];
+        const uint32_t head = min(len, (8u - (bstart[b] & 7u)) & 7u);
+        const uint32_t n16 = (len - head) >> 3, tail = (len - head) & 7u;
+        if (uint32_t(lane) < head) dst[lane] = stage[l0 + lane];
+        const u32x4s *src16 = reinterpret_cast<const u32x4s *>(stage + l0 + head);
+        u32x4s *dst16 = reinterpret_cast<u32x4s *>(dst + head);
+        for (uint32_t k = lane; k < n16; k += 64) dst16[k] = src16[k];
+        if (uint32_t(lane) < tail) dst[head + 8 * n16 + lane] = stage[l0 + head + 8 * n16 + lane];
     }
 }
 

@@ -13,7 +13,6 @@ constexpr int kChunk = 256;               // events per wave-wide 16-byte load (
 constexpr int kNch = 4;                   // loads per segment
 constexpr int kSeg = kChunk * kNch;       // events per segment
 constexpr int kSlots = kNch * 4;          // events per lane per segment
-constexpr int kBufWord3 = 0x00020000;     // raw buffer descriptor word 3 (32-bit data format)
 constexpr int kNonTemporal = 2;           // cache policy of the ID stream loads
 
 // min(max(x - retention, 0), limit): the excess-of-loss clamp of Table I.
