@@ -1,8 +1,8 @@
 """YET ingest: the catalog-binned copy against its definition, bit for bit.
 
 Definition (the layout the tiled trial kernel reads): the catalog is cut into bins
-of 2^15 events; region b holds, trial after trial, each trial's occurrences of bin-b
-events in time order, each as its ID minus 2^15 b; boff[b][t] is where trial t's run
+of 2^14 events; region b holds, trial after trial, each trial's occurrences of bin-b
+events in time order, each as its ID minus 2^14 b; boff[b][t] is where trial t's run
 starts in region b, boff[b][n_trials] the region's length.  The expected copy below
 is that definition computed with numpy's stable sort (integer work: bit-exact)."""
 from __future__ import annotations
@@ -29,8 +29,7 @@ def _expected(ids: np.ndarray, offs: np.ndarray, catalog: int):
     trial = np.repeat(np.arange(n_trials, dtype=np.int64), np.diff(offs))
     b = ids.astype(np.int64) >> BIN_SHIFT
     order = np.argsort(b * (n_trials + 1) + trial, kind="stable")
-    counts = np.zeros((n_bins, n_trials), np.int64)
-    np.add.at(counts, (b, trial), 1)
+    counts = np.bincount(b * n_trials + trial, minlength=n_bins * n_trials).reshape(n_bins, n_trials)
     boff = np.zeros((n_bins, n_trials + 1), np.int64)
     boff[:, 1:] = np.cumsum(counts, axis=1)
     local = (ids[order] & ((1 << BIN_SHIFT) - 1)).astype(np.uint16)
@@ -51,13 +50,18 @@ def _check_copy(A, y, ids, offs, catalog):
         assert np.array_equal(ids16[region[b]:region[b] + boff_x[b, -1]], per_bin[b]), f"bin {b}"
 
 
-@pytest.mark.parametrize("case", ["poisson", "ragged_long_trial", "one_bin_heavy"])
+@pytest.mark.parametrize("case", ["poisson", "ragged_long_trial", "one_bin_heavy", "many_trials"])
 def test_binned_copy_matches_definition(ara_lib, gpu_ctx, case):
     import torch
     A = ara_lib
-    rng = np.random.default_rng({"poisson": 11, "ragged_long_trial": 12, "one_bin_heavy": 13}[case])
+    rng = np.random.default_rng({"poisson": 11, "ragged_long_trial": 12, "one_bin_heavy": 13, "many_trials": 14}[case])
     catalog = 200_003   # 13 bins, the last one partial
-    if case == "poisson":
+    if case == "many_trials":
+        # more 64-trial blocks per bin (17,188) than the block-total scan takes in one
+        # round (16,384), and a trial count that is not a multiple of 4
+        catalog = 30_001   # 2 bins
+        lens = rng.poisson(20, size=1_100_003)
+    elif case == "poisson":
         lens = rng.poisson(300, size=5000)
         lens[::97] = 0   # empty trials
     elif case == "ragged_long_trial":
