@@ -52,6 +52,14 @@ KERNELS = {
 }
 
 
+# the instantiation the headline figures time: the YLT kernel on 4-byte run starts
+KERNEL_INSTANCE = {"k_trial_tiled": "k_trial_tiled<false, false>"}
+
+
+def is_instance(kernel: str, name: str) -> bool:
+    return KERNEL_INSTANCE.get(kernel, kernel) in name
+
+
 def traffic_file(kernel: str) -> str:
     return os.path.join(ROOT, "profiles", f"{kernel}.paper_1Mx1000_f64.traffic.txt")
 
@@ -176,7 +184,7 @@ def derive_traffic(fetch_path: str, write_path: str, copy_mib: int, cmd: str):
 
     def per_dispatch(path, counter):
         rows = [r for r in _counter_rows(path) if r["Counter_Name"] == counter]
-        kern = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
+        kern = [float(r["Counter_Value"]) for r in rows if is_instance(kernel, r["Kernel_Name"])]
         copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"]]
         if not kern or not copies:
             raise SystemExit(f"{path}: no {kernel} or copy dispatches with {counter}")
@@ -215,7 +223,7 @@ def summarize_counters(path: str, out_path: str, cmd: str):
     kernel, with the L2 hit rate and busy fractions derived from them."""
     all_rows = _counter_rows(path)
     kernel = headline_kernel_in(all_rows)
-    rows = [r for r in all_rows if kernel in r["Kernel_Name"]]
+    rows = [r for r in all_rows if is_instance(kernel, r["Kernel_Name"])]
     per = {}
     for r in rows:
         per.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
@@ -730,11 +738,10 @@ def main():
     ingest_gpu_ms = sorted(x[1] for x in ingest_runs[1:])[1]
     id_bytes = ara.ara_yet_info(yet)[2]
     n_bins = ara.ara_yet_binned_count(yet) if id_bytes == 2 else 0
-    # device memory the handle adds to the caller's int32 IDs and offsets (the
-    # layout ara_yet_create states: 2 B per occurrence plus 24 B per bin, plus
-    # 4 B per (bin, trial + 1); else 3 B per occurrence for the packed copy)
-    yet_extra = (2 * w.n_events + 24 * n_bins + 4 * n_bins * (w.n_trials + 1)) if id_bytes == 2 else \
-        (3 * w.n_events if id_bytes == 3 else 0)
+    # device memory the handle adds to the caller's int32 IDs and offsets, as the
+    # library counts it: the binned copy (2 B per occurrence, its run starts, 3 or
+    # 4 B per (bin, trial), and region starts) or the packed one
+    yet_extra, run_bytes = ara.ara_yet_memory(yet)
     log(f"ingest (validate + {'binned' if id_bytes == 2 else 'packed' if id_bytes == 3 else 'no'} copy): "
         f"{ingest_ms:.2f} ms wall, {ingest_gpu_ms:.2f} ms on the stream (first call in the process "
         f"{ingest_first_ms:.2f} ms); {yet_extra / 1e9:.3f} GB added")
@@ -758,9 +765,10 @@ def main():
     # sort skips its passes)
     y_distinct = torch.from_numpy(np.random.default_rng(7).lognormal(15.0, 2.0, size=w.n_trials)).cuda()
 
-    def run_steps(layer, steps, warmup, sort_input=None):
+    def run_steps(layer, steps, warmup, sort_input=None, on_yet=None):
         """steps x (table build, trial kernel, sort + PML/TVaR to the host): wall ms per
         step and the trial kernel's average ms (HIP events on its stream)."""
+        y_handle = an.yet if on_yet is None else on_yet
         e0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
         e1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
 
@@ -768,7 +776,7 @@ def main():
             ara.ara_layer_build(ctx, layer, ara.ARA_BUILD_TABLES)
             if i is not None:
                 e0[i].record(stream)
-            ara.ara_analyze(ctx, an.yet, layer, 0, w.n_trials, ylt)
+            ara.ara_analyze(ctx, y_handle, layer, 0, w.n_trials, ylt)
             if i is not None:
                 e1[i].record(stream)
             return ara.ara_risk_measures(ctx, ylt if sort_input is None else sort_input, rps, ws)
@@ -793,13 +801,13 @@ def main():
     nblk = (w.catalog_size + 127) // 128
     # algorithmic bytes are defined on int32 event IDs and int64 trial offsets; the
     # kernels stream other forms, reported beside them as moved_bytes: the packed
-    # 3-byte copy with the same offsets, or the binned 2-byte copy with a 4-byte
-    # offset per (catalog bin, trial) instead of the trial offsets (the tiled kernel
+    # 3-byte copy with the same offsets, or the binned 2-byte copy with a 3- or 4-byte
+    # run start per (catalog bin, trial) instead of the trial offsets (the tiled kernel
     # then reads the layer's binary64 occurrence-net table, once per workgroup pass
     # from L2: counted once here)
     alg_bytes = 4 * w.n_events + 8 * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * n_flagged
     if kernel == "k_trial_tiled":
-        moved_bytes = 2 * w.n_events + 4 * n_bins * (w.n_trials + 1) + 8 * w.n_trials + 8 * w.catalog_size
+        moved_bytes = 2 * w.n_events + run_bytes * n_bins * (w.n_trials + 1) + 8 * w.n_trials + 8 * w.catalog_size
     else:
         ib = 3 if not args.no_packing and w.catalog_size <= 1 << 24 else 4   # the packed copy, else int32
         moved_bytes = alg_bytes - (4 - ib) * w.n_events
@@ -833,6 +841,48 @@ def main():
     for e in an2.elts:
         ara.ara_elt_release(e)
     log(f"{'binary32' if other == ara.ARA_F32 else 'binary64'} tables: {ms2:.3f} ms/step; trial kernel {k2:.4f} ms")
+
+    # a copy of the YET built with 3-byte run starts (less memory, a slower tiled
+    # kernel): its ingest after a first build, its memory, and the trial kernel on the
+    # two copies in alternating rounds of 5 launches (legs run one after the other in
+    # a process differ by more than the two forms do)
+    lean = None
+    if id_bytes == 2:
+        ara.ara_set_option(ctx, ara.ARA_OPT_YET_RUN_BYTES, 3)
+        try:
+            yet3 = None
+            lean_ingest = []
+            for _ in range(2):
+                if yet3 is not None:
+                    ara.ara_yet_release(yet3)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                yet3 = ara.ara_yet_create(ctx, ids_dev, offs_dev, w.catalog_size)
+                lean_ingest.append((time.perf_counter() - t) * 1e3)
+        finally:
+            ara.ara_set_option(ctx, ara.ARA_OPT_YET_RUN_BYTES, 4)
+        extra3, rb3 = ara.ara_yet_memory(yet3)
+        ara.ara_layer_build(ctx, an.layer, ara.ARA_BUILD_TABLES)
+        pair = [("own", an.yet), ("lean", yet3)]
+        kt = {k: [] for k, _ in pair}
+        for r in range(8):
+            for k, yh in (pair if r % 2 == 0 else pair[::-1]):
+                ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(5)]
+                for e0, e1 in ev:
+                    e0.record(stream)
+                    ara.ara_analyze(ctx, yh, an.layer, 0, w.n_trials, ylt)
+                    e1.record(stream)
+                torch.cuda.synchronize()
+                kt[k] += [e0.elapsed_time(e1) for e0, e1 in ev]
+        ara.ara_yet_release(yet3)
+        k_own, k3 = float(np.median(kt["own"])), float(np.median(kt["lean"]))
+        lean = {"run_bytes": rb3, "yet_extra_bytes": extra3, "ingest_ms": lean_ingest[-1],
+                "kernel_ms_median": k3, "kernel_ms_median_4byte": k_own,
+                "frac": alg_bytes / (k3 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "what": "the trial kernel on a copy of the YET with 3-byte run starts "
+                        "(ARA_OPT_YET_RUN_BYTES = 3) and on the 4-byte one, alternating rounds"}
+        log(f"{rb3}-byte run starts: {extra3 / 1e9:.3f} GB added, ingest {lean_ingest[-1]:.2f} ms; trial kernel "
+            f"median {k3:.4f} ms vs {k_own:.4f} ms with 4-byte run starts (alternating)")
 
     if args.copy_probe_mib:
         src = torch.empty(args.copy_probe_mib << 20, dtype=torch.uint8, device="cuda")
@@ -890,6 +940,7 @@ def main():
                           "value_with_distinct_ylt_sort": te / (ms_step_distinct * 1e-3)},
         "risk_measures_distinct_ylt": {"ms": risk_distinct_ms, "trials": w.n_trials,
                                        "data": "lognormal(15, 2) year losses, seed 7: all 8 radix passes run"},
+        "lean_yet": lean,
         ("f32_tables" if other == ara.ARA_F32 else "f64_tables"): {
             "ms_per_step": ms2, "value": te / (ms2 * 1e-3), "kernel_ms": k2, "algorithmic_bytes": alg2,
             "achieved_gbs": alg2 / (k2 * 1e-3) / 1e9, "frac": alg2 / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS,

@@ -109,8 +109,12 @@ typedef enum ara_option {
                                    YET averages <= 256 occurrences per trial, else one wave per
                                    trial; 1 = always a wave; 2 = always a lane.  A lane adds its
                                    trial's values in time order (the sequential sum)               */
-    ARA_OPT_YET_BINNING = 6     /* 1 (default): YETs created later also keep a catalog-binned copy
+    ARA_OPT_YET_BINNING = 6,    /* 1 (default): YETs created later also keep a catalog-binned copy
                                    where it applies (see ara_yet_create); 0: never                 */
+    ARA_OPT_YET_RUN_BYTES = 7   /* bytes per run start of binned copies built later: 4 (default), or
+                                   3 (with at most 64 bins and fewer than 2^31 occurrences; 4 when
+                                   a bin holds 2^24 occurrences or more): a quarter less memory for
+                                   the run starts, about 3% more time in the tiled kernel          */
 } ara_option;
 
 typedef struct ara_ctx ara_ctx;
@@ -186,9 +190,10 @@ ara_status ara_sync(ara_ctx *ctx);
  * per-(bin, trial) offsets.  Analyses of layers whose table does not fit in LDS then
  * read that copy (ARA_PLACE_LDS_TILES); other placements then stream the int32 IDs.
  * If the device has no memory for it, the handle is created without it.  Device
- * memory the handle adds to the caller's arrays: 2 bytes per occurrence plus 24
- * bytes per bin plus 4 bytes per (bin, trial + 1) with a binned copy, else 3 bytes per
- * occurrence with a packed copy.
+ * memory the handle adds to the caller's arrays (ara_yet_memory gives it exactly):
+ * with a binned copy 2 bytes per occurrence plus 4 bytes per (bin, trial + 2, rounded
+ * up to a multiple of 8), 3 with ARA_OPT_YET_RUN_BYTES = 3, plus about 24 bytes per
+ * bin, else 3 bytes per occurrence with a packed copy.
  * Errors: ARA_E_INVALID_ARG, ARA_E_EVENT_ID_RANGE, ARA_E_BAD_OFFSETS, ARA_E_OOM, ARA_E_DEVICE. */
 ara_status ara_yet_create(ara_ctx *ctx, const int32_t *event_ids, int64_t n_events,
                           const int64_t *trial_offsets, int64_t n_trials, int32_t catalog_size,
@@ -199,6 +204,14 @@ ara_status ara_yet_release(ara_yet *yet);
  * for layers whose table does not fit in LDS: 2 with a binned copy, else 3 with a
  * packed copy, else 4.  Any output pointer may be NULL. */
 ara_status ara_yet_info(const ara_yet *yet, int64_t *n_events, int64_t *n_trials, int32_t *id_bytes);
+
+/* Device memory held by a YET handle: its packed or binned copy, plus the copies of
+ * the caller's arrays when it was created from host memory (ARA_MEM_HOST).
+ *   device_bytes  out: that memory in bytes.
+ *   run_bytes     out: bytes per run start of the binned copy (3, or 4 when a bin
+ *                 holds 2^24 occurrences or more; 0 without a binned copy).
+ * Any output pointer may be NULL.  Errors: ARA_E_INVALID_ARG. */
+ara_status ara_yet_memory(const ara_yet *yet, int64_t *device_bytes, int32_t *run_bytes);
 
 /* The YET's catalog-binned copy (see ara_yet_create), copied to host memory, for
  * checking and inspection.  Bin b holds catalog events [2^14 b, 2^14 (b + 1)).

@@ -60,6 +60,7 @@ ARA_OPT_GRID_PER_CU = 3
 ARA_OPT_YET_PACKING = 4
 ARA_OPT_TRIAL_MODE = 5
 ARA_OPT_YET_BINNING = 6
+ARA_OPT_YET_RUN_BYTES = 7
 
 ARA_BUILD_TABLES = 1
 
@@ -113,6 +114,7 @@ _SIGS = {
     "ara_yet_release": (_ST, [_P]),
     "ara_yet_info": (_ST, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
     "ara_yet_binned": (_ST, [_P, ctypes.POINTER(_I32), _P, _P, _P]),
+    "ara_yet_memory": (_ST, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
     "ara_elt_create": (_ST, [_P, _P, _P, _I64, _I32, ctypes.POINTER(ara_elt_terms), ctypes.c_int, ctypes.c_int,
                              ctypes.POINTER(_P)]),
     "ara_elt_release": (_ST, [_P]),
@@ -299,6 +301,15 @@ def ara_yet_binned_count(y: Yet) -> int:
     nb = _I32()
     _check(_lib.ara_yet_binned(y.ptr, ctypes.byref(nb), None, None, None), y.ctx, "ara_yet_binned")
     return int(nb.value)
+
+
+def ara_yet_memory(y: Yet):
+    """(device_bytes, run_bytes): device memory the handle holds (its packed or binned
+    copy, plus its own copies of host arrays) and the bytes per run start of its binned
+    copy (3 or 4; 0 without one)."""
+    nb, rb = _I64(), _I32()
+    _check(_lib.ara_yet_memory(y.ptr, ctypes.byref(nb), ctypes.byref(rb)), y.ctx, "ara_yet_memory")
+    return int(nb.value), int(rb.value)
 
 
 def ara_yet_binned(y: Yet):

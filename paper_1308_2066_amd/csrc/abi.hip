@@ -35,6 +35,7 @@ struct ara_ctx {
     int grid_per_cu = 0;             // 0 = automatic
     int yet_packing = 1;             // keep a packed copy of YET IDs where they fit 24 bits
     int yet_binning = 1;             // keep a catalog-binned copy of YET IDs where it applies
+    int yet_run_bytes = 4;           // bytes per run start of the binned copy (3 or 4)
     int trial_mode = 0;              // 0 = by trial length, 1 = wave per trial, 2 = lane per trial
     std::map<std::string, std::pair<int64_t, bool>> tuned;   // batch shape -> (events per item, interleave)
     int live = 0;                    // handles alive on this context
@@ -51,10 +52,12 @@ struct ara_yet {
     uint8_t *ids24;    // packed copy (owned), or null
     // catalog-binned copy (owned), or null ids16
     uint16_t *ids16 = nullptr;
-    uint32_t *boff = nullptr;     // n_bins rows of `stride` entries
+    uint32_t *boff = nullptr;     // run starts: n_bins rows of `stride` entries, 4 bytes each,
+    uint8_t *boff24 = nullptr;    // or 3 bytes each (one of the two)
     int64_t *region = nullptr;    // n_bins + 1 element offsets
     int64_t stride = 0;
     int32_t n_bins = 0;
+    int64_t copy_bytes = 0;       // device memory of the packed or binned copy
 };
 
 struct ara_elt {
@@ -126,17 +129,22 @@ static ara_status err_bits_status(uint32_t bits) {
     return ARA_OK;
 }
 
-// Waits for the context stream, then reads and clears the device error word.
-static ara_status sync_and_check(ara_ctx *c) {
+// Waits for the context stream, then reads and clears the device error word.  With
+// `wide`, the ERR_BIN_WIDE bit (not an input error) is returned there.
+static ara_status sync_and_check(ara_ctx *c, bool *wide = nullptr) {
     HIP_OR_RETURN(c, hipMemcpyAsync(c->h_err, c->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream),
                   "read error word");
     HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "stream synchronize");
-    const uint32_t bits = *c->h_err;
+    uint32_t bits = *c->h_err;
     if (bits) {
         HIP_OR_RETURN(c, launch_fill_u32(c->d_err, 1, 0u, c->stream), "clear error word");
         HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "stream synchronize");
-        ara_status s = err_bits_status(bits);
-        return fail(c, s, "device-detected input error (bits 0x%x): %s", bits, ara_status_str(s));
+        if (wide) *wide = (bits & ERR_BIN_WIDE) != 0;
+        bits &= ~ERR_BIN_WIDE;
+        if (bits) {
+            ara_status s = err_bits_status(bits);
+            return fail(c, s, "device-detected input error (bits 0x%x): %s", bits, ara_status_str(s));
+        }
     }
     return ARA_OK;
 }
@@ -414,6 +422,10 @@ extern "C" ara_status ara_set_option(ara_ctx *c, int option, int64_t v) {
         if (v != 0 && v != 1) return fail(c, ARA_E_INVALID_ARG, "bad binning flag %lld", (long long)v);
         c->yet_binning = int(v);
         return ARA_OK;
+    case ARA_OPT_YET_RUN_BYTES:
+        if (v != 3 && v != 4) return fail(c, ARA_E_INVALID_ARG, "bad run start size %lld", (long long)v);
+        c->yet_run_bytes = int(v);
+        return ARA_OK;
     default:
         return fail(c, ARA_E_INVALID_ARG, "unknown option %d", option);
     }
@@ -429,9 +441,11 @@ extern "C" ara_status ara_sync(ara_ctx *c) {
 static void yet_free_binned(ara_yet *y) {
     dev_free(y->ids16);
     dev_free(y->boff);
+    dev_free(y->boff24);
     dev_free(y->region);
     y->ids16 = nullptr;
     y->boff = nullptr;
+    y->boff24 = nullptr;
     y->region = nullptr;
     y->n_bins = 0;
 }
@@ -452,58 +466,75 @@ static bool yet_binning_applies(const ara_ctx *c, const ara_yet *y) {
 // occurrence count (each region rounded up to 8 elements), the region starts are
 // computed on the device and the passes run back to back, with one wait at the end
 // (a bad ID or offset found by the count pass stops the later passes on the device).
-// Larger YETs read the bins' lengths back first to check them.
+// Larger YETs read the bins' lengths back first to check them.  Asked for 3-byte run
+// starts, a one-wait build of at most 64 bins writes them; if a bin turns out to hold
+// 2^24 occurrences or more (flagged on the device) it is built again with 4-byte ones.
 static ara_status yet_build_binned(ara_ctx *c, ara_yet *y, bool *ids_checked) {
     const int32_t nb = catalog_bins(y->catalog);
     const int64_t n = y->n_trials;
     *ids_checked = false;
     if (!yet_binning_applies(c, y)) return ARA_OK;
-    y->stride = (n + 1 + 3) & ~int64_t(3);
+    y->stride = (n + 2 + 7) & ~int64_t(7);   // see ara_yet: a multiple of 8, at least n + 2
     const bool one_wait = y->n_events < (int64_t(1) << 31);
+    // 3-byte run starts when asked for, unless a bin turns out too long for them
+    bool b24 = c->yet_run_bytes == 3 && one_wait && nb <= 64;
     uint32_t *sums = nullptr;
-    ara_status s = dev_alloc(c, &y->boff, size_t(nb) * size_t(y->stride) * 4, "binned yet offsets");
-    if (s == ARA_OK) s = dev_alloc(c, &sums, bin_offsets_scratch_words(n, nb) * 4, "binned yet scan");
+    size_t ids16_bytes = size_t(y->n_events + 8 * int64_t(nb)) * 2 + 16;
+    ara_status s = dev_alloc(c, &sums, bin_offsets_scratch_words(n, nb) * 4, "binned yet scan");
     if (s == ARA_OK) s = dev_alloc(c, &y->region, size_t(nb + 1) * 8, "binned yet regions");
-    if (s == ARA_OK && one_wait)
-        s = dev_alloc(c, &y->ids16, size_t(y->n_events + 8 * int64_t(nb)) * 2 + 16, "binned yet ids");
-    if (s == ARA_OK) {
-        hipError_t e = launch_bin_offsets(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->catalog, sums,
-                                          c->d_err, c->stream);
-        if (e == hipSuccess) e = launch_bin_regions(y->boff, y->stride, n, nb, y->region, c->d_err, c->stream);
+    if (s == ARA_OK && one_wait) s = dev_alloc(c, &y->ids16, ids16_bytes, "binned yet ids");
+    while (s == ARA_OK) {
+        // 3-byte form: 16 bytes of slack after the last row (the tiled kernel reads the
+        // aligned words around an entry, up to 2 bytes past its row)
+        if (b24) s = dev_alloc(c, &y->boff24, size_t(nb) * size_t(y->stride) * 3 + 16, "binned yet run starts");
+        else s = dev_alloc(c, &y->boff, size_t(nb) * size_t(y->stride) * 4, "binned yet run starts");
+        if (s != ARA_OK) break;
+        const RunStarts r{y->boff, y->boff24, y->stride};
+        hipError_t e = launch_bin_offsets(y->ids, y->offs, y->n_events, n, nb, r, y->catalog, sums, c->d_err,
+                                          c->stream);
+        if (e == hipSuccess) e = launch_bin_regions(r, n, nb, y->region, c->d_err, c->stream);
         if (one_wait) {
             if (e == hipSuccess)
-                e = launch_bin_scatter(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->region, y->ids16,
-                                       c->d_err, c->stream);
-            s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet");
+                e = launch_bin_scatter(y->ids, y->offs, y->n_events, n, nb, r, y->region, y->ids16, c->d_err, c->stream);
+            bool wide = false;
+            s = e == hipSuccess ? sync_and_check(c, &wide) : hip_fail(c, e, "binned yet");
             *ids_checked = e == hipSuccess;   // an ID outside the catalog shows in s
-        } else {
-            std::vector<uint32_t> len(static_cast<size_t>(nb));
-            int64_t total = 0;
-            if (e == hipSuccess)
-                e = hipMemcpy2DAsync(len.data(), 4, y->boff + n, size_t(y->stride) * 4, 4, size_t(nb),
-                                     hipMemcpyDeviceToHost, c->stream);
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(&total, y->region + nb, 8, hipMemcpyDeviceToHost, c->stream);
-            s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet offsets");
-            *ids_checked = e == hipSuccess;
-            bool fits = true;
-            for (int32_t b = 0; s == ARA_OK && b < nb; ++b) fits = fits && len[size_t(b)] < (1u << 31);
-            if (s == ARA_OK && !fits) {
-                dev_free(sums);
-                yet_free_binned(y);
-                return ARA_OK;
+            if (s == ARA_OK && wide) {   // a bin of 2^24 occurrences or more: again with 4-byte run starts
+                dev_free(y->boff24);
+                y->boff24 = nullptr;
+                b24 = false;
+                continue;
             }
-            if (s == ARA_OK) s = dev_alloc(c, &y->ids16, size_t(total) * 2 + 16, "binned yet ids");
-            if (s == ARA_OK) {
-                e = launch_bin_scatter(y->ids, y->offs, y->n_events, n, nb, y->boff, y->stride, y->region, y->ids16,
-                                       c->d_err, c->stream);
-                s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet scatter");
-            }
+            break;
         }
+        std::vector<uint32_t> len(static_cast<size_t>(nb));
+        int64_t total = 0;
+        if (e == hipSuccess)
+            e = hipMemcpy2DAsync(len.data(), 4, y->boff + n, size_t(y->stride) * 4, 4, size_t(nb),
+                                 hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(&total, y->region + nb, 8, hipMemcpyDeviceToHost, c->stream);
+        s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet offsets");
+        *ids_checked = e == hipSuccess;
+        bool fits = true;
+        for (int32_t b = 0; s == ARA_OK && b < nb; ++b) fits = fits && len[size_t(b)] < (1u << 31);
+        if (s == ARA_OK && !fits) {
+            dev_free(sums);
+            yet_free_binned(y);
+            return ARA_OK;
+        }
+        ids16_bytes = size_t(total) * 2 + 16;
+        if (s == ARA_OK) s = dev_alloc(c, &y->ids16, ids16_bytes, "binned yet ids");
+        if (s == ARA_OK) {
+            e = launch_bin_scatter(y->ids, y->offs, y->n_events, n, nb, r, y->region, y->ids16, c->d_err, c->stream);
+            s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "binned yet scatter");
+        }
+        break;
     }
     dev_free(sums);
     if (s == ARA_OK) {
         y->n_bins = nb;
+        y->copy_bytes = int64_t(ids16_bytes) + int64_t(nb + 1) * 8 + int64_t(nb) * y->stride * (y->boff24 ? 3 : 4) +
+                        (y->boff24 ? 16 : 0);
         return ARA_OK;
     }
     yet_free_binned(y);
@@ -562,6 +593,7 @@ extern "C" ara_status ara_yet_create(ara_ctx *c, const int32_t *ids, int64_t n_e
     if (s == ARA_OK && !y->ids16 && c->yet_packing && n_events > 0 && catalog <= kMaxPackedCatalog) {
         s = dev_alloc(c, &y->ids24, yet_packed_bytes(n_events), "packed yet ids");
         if (s == ARA_OK) {
+            y->copy_bytes = int64_t(yet_packed_bytes(n_events));
             e = launch_yet_pack(y->ids, n_events, y->ids24, c->stream);
             s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "pack yet");
         }
@@ -604,6 +636,13 @@ extern "C" ara_status ara_yet_info(const ara_yet *y, int64_t *n_events, int64_t 
     return ARA_OK;
 }
 
+extern "C" ara_status ara_yet_memory(const ara_yet *y, int64_t *device_bytes, int32_t *run_bytes) {
+    if (!y) return ARA_E_INVALID_ARG;
+    if (device_bytes) *device_bytes = y->copy_bytes + (y->owns ? y->n_events * 4 + (y->n_trials + 1) * 8 : 0);
+    if (run_bytes) *run_bytes = y->ids16 ? (y->boff24 ? 3 : 4) : 0;
+    return ARA_OK;
+}
+
 extern "C" ara_status ara_yet_binned(const ara_yet *y, int32_t *n_bins, int64_t *region, uint32_t *boff,
                                     uint16_t *ids16) {
     if (!y || !n_bins) return ARA_E_INVALID_ARG;
@@ -616,9 +655,16 @@ extern "C" ara_status ara_yet_binned(const ara_yet *y, int32_t *n_bins, int64_t 
     std::vector<int64_t> reg(nb + 1);
     HIP_OR_RETURN(c, hipMemcpy(reg.data(), y->region, (nb + 1) * 8, hipMemcpyDeviceToHost), "binned copy");
     if (region) std::copy(reg.begin(), reg.end(), region);
-    if (boff)
+    if (boff && y->boff) {
         HIP_OR_RETURN(c, hipMemcpy2D(boff, cols * 4, y->boff, size_t(y->stride) * 4, cols * 4, nb, hipMemcpyDeviceToHost),
                       "binned copy");
+    } else if (boff) {   // 3-byte run starts, widened
+        std::vector<uint8_t> b24(nb * cols * 3);
+        HIP_OR_RETURN(c, hipMemcpy2D(b24.data(), cols * 3, y->boff24, size_t(y->stride) * 3, cols * 3, nb,
+                                     hipMemcpyDeviceToHost), "binned copy");
+        for (size_t i = 0; i < nb * cols; ++i)
+            boff[i] = uint32_t(b24[3 * i]) | (uint32_t(b24[3 * i + 1]) << 8) | (uint32_t(b24[3 * i + 2]) << 16);
+    }
     if (ids16) HIP_OR_RETURN(c, hipMemcpy(ids16, y->ids16, size_t(reg[nb]) * 2, hipMemcpyDeviceToHost), "binned copy");
     return ARA_OK;
 }
@@ -878,6 +924,7 @@ static TiledArgs tiled_args(const ara_yet *y, const ara_layer *L, int64_t t0, in
     a.ids16 = y->ids16;
     a.region = y->region;
     a.boff = y->boff;
+    a.boff24 = y->boff24;
     a.stride = y->stride;
     a.t_begin = t0;
     a.t_end = t1;

@@ -14,6 +14,9 @@ namespace ara {
 
 // Error bits a kernel may set in the context's device error word.
 enum : uint32_t { ERR_ID_RANGE = 1u, ERR_OFFSETS = 2u, ERR_LOSS = 4u, ERR_DUP = 8u };
+// Not an input error: a bin of the binned copy is too long for 3-byte run starts (the
+// copy then keeps 4-byte ones).
+constexpr uint32_t ERR_BIN_WIDE = 16u;
 
 // Device-side description of one ELT: its sparse records, its direct access
 // table over the catalog, and its financial terms.
@@ -167,29 +170,49 @@ size_t trial_bitmap_table_capacity();
 // 14-bit IDs local to the bin, one uint16 each.  Region b
 // starts at element region[b] (a multiple of 8); boff[b * stride + t] is where trial
 // t's run starts inside region b (trial t's occurrences of bin b are
-// [boff[b][t], boff[b][t + 1])), t = 0..n_trials.
+// [boff[b][t], boff[b][t + 1])), t = 0..n_trials.  Asked for (ARA_OPT_YET_RUN_BYTES)
+// and with at most 64 bins the run starts are 3 bytes each (little-endian, row b at
+// byte 3 b stride) unless a bin holds 2^24 occurrences or more: a quarter less memory,
+// read as an unaligned 4-byte word whose top byte is dropped.  stride is a multiple of 8 and at least n_trials + 2, so
+// that word stays inside its row; the array has 16 bytes of slack after its last row.
 constexpr int kBinShift = 14;
 constexpr int32_t kBinEvents = 1 << kBinShift;
 constexpr int kMaxBins = 512;                                 // catalogs up to 2^23 events
 inline int32_t catalog_bins(int32_t catalog) { return (catalog + kBinEvents - 1) / kBinEvents; }
 
-// boff[b][t] for t = 0..n_trials (stride a multiple of 4, at least n_trials + 1):
-// the exclusive prefix sums over trials of each trial's occurrence count in bin b,
-// so boff[b][n_trials] is bin b's length.  sums: bin_offsets_scratch_words(n_trials,
-// n_bins) words of scratch.  Also checks the YET (ERR_OFFSETS, ERR_ID_RANGE in err;
-// bad offsets or IDs are not followed or counted): the count pass doubles as
-// ingest's check.
+// Run starts as the build writes them: 4 bytes each (abs), or 3 bytes each (b24, row
+// b at byte 3 b stride; at most 64 bins).  stride: a multiple of 8, at least
+// n_trials + 2.
+struct RunStarts {
+    uint32_t *abs;
+    uint8_t *b24;
+    int64_t stride;
+};
+__device__ __forceinline__ uint32_t run_at(const RunStarts &r, int64_t b, int64_t t) {
+    if (r.abs) return r.abs[b * r.stride + t];
+    uint32_t w;   // an unaligned word: this entry and the next one's first byte
+    __builtin_memcpy(&w, r.b24 + 3 * (b * r.stride + t), 4);
+    return w & 0xFFFFFFu;
+}
+
+// Run starts for t = 0..n_trials: the exclusive prefix sums over trials of each
+// trial's occurrence count in bin b, so run(b, n_trials) is bin b's length.  In the
+// 3-byte form a bin of 2^24 occurrences or more sets ERR_BIN_WIDE (its entries are
+// then not usable).  sums: bin_offsets_scratch_words(n_trials, n_bins) words of
+// scratch.  Also checks the YET (ERR_OFFSETS, ERR_ID_RANGE in err; bad offsets or IDs
+// are not followed or counted): the count pass doubles as ingest's check.
 hipError_t launch_bin_offsets(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
-                              int32_t n_bins, uint32_t *boff, int64_t stride, int32_t catalog, uint32_t *sums,
-                              uint32_t *err, hipStream_t s);
+                              int32_t n_bins, const RunStarts &r, int32_t catalog, uint32_t *sums, uint32_t *err,
+                              hipStream_t s);
 size_t bin_offsets_scratch_words(int64_t n_trials, int32_t n_bins);
-// Region starts (n_bins + 1, int64, multiples of 8) from the scanned offsets.
-hipError_t launch_bin_regions(const uint32_t *boff, int64_t stride, int64_t n_trials, int32_t n_bins, int64_t *region,
+// Region starts (n_bins + 1, int64, multiples of 8) from the bins' lengths.
+hipError_t launch_bin_regions(const RunStarts &r, int64_t n_trials, int32_t n_bins, int64_t *region,
                               const uint32_t *err, hipStream_t s);
-// Both skip their work when *err is nonzero (the count pass found a bad ID or offset).
+// Both skip their work when *err is nonzero (the count pass found a bad ID or offset,
+// or a bin too long for the 3-byte form).
 hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
-                              int32_t n_bins, const uint32_t *boff, int64_t stride, const int64_t *region,
-                              uint16_t *ids16, const uint32_t *err, hipStream_t s);
+                              int32_t n_bins, const RunStarts &r, const int64_t *region, uint16_t *ids16,
+                              const uint32_t *err, hipStream_t s);
 
 constexpr int kTiledWaves = 16;                 // waves per workgroup of the tiled kernel
 constexpr int kTiledWaveTrials = 252;           // trials per wave and pass (their sums are in LDS)
@@ -202,7 +225,8 @@ static_assert(size_t(kBinEvents + 2) * 8 + size_t(kTiledWaves) * kTiledWaveTrial
 struct TiledArgs {
     const uint16_t *ids16;      // the YET's catalog-binned copy (see ara_yet)
     const int64_t *region;      // n_bins + 1 element offsets (multiples of 8)
-    const uint32_t *boff;
+    const uint32_t *boff;       // run starts, 4 bytes each, or null
+    const uint8_t *boff24;      // or 3 bytes each (row b at byte 3 b stride)
     int64_t stride;             // entries per boff row
     int64_t t_begin, t_end;
     int64_t per_wg;             // trials per workgroup

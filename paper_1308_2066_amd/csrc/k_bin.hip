@@ -86,17 +86,22 @@ __global__ __launch_bounds__(kCountWaves * 64) void k_bin_count(const int32_t *_
 // Up to 64 bins (the paper-scale catalog has 62): a workgroup takes 64 consecutive
 // trials (a block) at a time and its waves count them into an LDS table, a row per
 // trial.  Each bin's 64 counts then become their exclusive prefix sums within the
-// block (one wave scan), written with one coalesced 256-byte store, and the block's
-// total goes to sums[b][block].  (The per-trial stores of the kernel above, 4 bytes
-// at a row stride apart, cost 0.3 ms more of a 10^9-occurrence ingest, and scanning
-// the counts in separate passes 0.2 ms more.)
+// block (one wave scan), written with one coalesced store (4-byte entries, or 3-byte
+// ones packed 4 to 12 bytes by every fourth lane), and the block's total goes to
+// sums[b][block]; the block's start is added afterwards.  In the 3-byte form the
+// entries up to the row's end are written (those past n_trials are padding), so the
+// entry at n_trials gets its block's prefix when it falls in the last block.  (The
+// per-trial stores of the kernel above, 4 bytes at a row stride apart, cost 0.3 ms
+// more of a 10^9-occurrence ingest, and scanning the counts in separate passes
+// 0.2 ms more.)
 constexpr int kCountBlock = 64;
+typedef uint32_t u32x3b __attribute__((ext_vector_type(3)));
 
+template <bool B24>
 __global__ __launch_bounds__(kCountWaves * 64) void k_bin_count_block(const int32_t *__restrict__ ids,
                                                                       const int64_t *__restrict__ offs,
                                                                       int64_t n_events, int64_t n_trials,
-                                                                      int32_t n_bins, uint32_t *__restrict__ boff,
-                                                                      int64_t stride, int32_t catalog,
+                                                                      int32_t n_bins, RunStarts r, int32_t catalog,
                                                                       uint32_t *__restrict__ sums, uint32_t *err) {
     __shared__ uint32_t hist[kCountBlock][65];   // padded rows: a bin's column reads without bank conflicts
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -112,14 +117,25 @@ __global__ __launch_bounds__(kCountWaves * 64) void k_bin_count_block(const int3
             count_trial(ids, offs, t, n_events, n_trials, cat, lane, hist[j], bad, bad_offs);
         }
         __syncthreads();
+        const int64_t t = t0 + lane;
         for (int32_t b = wave; b < n_bins; b += kCountWaves) {
             const uint32_t x = hist[lane][b];   // 0 past the last trial
             uint32_t inc = x;
-            for (int o = 1; o < 64; o <<= 1) {
-                const uint32_t y = __shfl_up(inc, o, 64);
-                if (lane >= o) inc += y;
+            for (int k = 1; k < 64; k <<= 1) {
+                const uint32_t y = __shfl_up(inc, k, 64);
+                if (lane >= k) inc += y;
             }
-            if (t0 + lane < n_trials) boff[b * stride + t0 + lane] = inc - x;
+            const uint32_t before = inc - x;
+            if (B24) {
+                const uint32_t v1 = __shfl_down(before, 1, 64), v2 = __shfl_down(before, 2, 64),
+                               v3 = __shfl_down(before, 3, 64);
+                if ((lane & 3) == 0 && t < r.stride) {   // t + 3 < stride too: both are multiples of 4
+                    const u32x3b w = {before | (v1 << 24), (v1 >> 8) | (v2 << 16), (v2 >> 16) | (v3 << 8)};
+                    *reinterpret_cast<u32x3b *>(r.b24 + 3 * (b * r.stride + t)) = w;   // 4-byte aligned
+                }
+            } else if (t < n_trials) {
+                r.abs[b * r.stride + t] = before;
+            }
             if (lane == 63) sums[b * nblk + t0 / kCountBlock] = inc;
         }
         __syncthreads();
@@ -130,10 +146,13 @@ __global__ __launch_bounds__(kCountWaves * 64) void k_bin_count_block(const int3
 }
 
 // The block totals of one bin (a workgroup per bin) become their exclusive prefix
-// sums, 16 per thread and 16384 per round; the bin's length goes to boff[b][n_trials].
-__global__ __launch_bounds__(1024) void k_bin_block_scan(uint32_t *__restrict__ sums, int64_t nblk,
-                                                         uint32_t *__restrict__ boff, int64_t stride,
-                                                         int64_t n_trials) {
+// sums in place, 16 per thread and 16384 per round; the bin's length goes to its
+// entry at n_trials (in the 3-byte form only when that entry starts a block of its
+// own: else the add below gives it), and a length of 2^24 or more in the 3-byte form
+// sets ERR_BIN_WIDE.
+template <bool B24>
+__global__ __launch_bounds__(1024) void k_bin_block_scan(uint32_t *__restrict__ sums, int64_t nblk, RunStarts r,
+                                                         int64_t n_trials, uint32_t *err) {
     __shared__ uint32_t wsum[16];
     uint32_t *row = sums + int64_t(blockIdx.x) * nblk;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -147,9 +166,9 @@ __global__ __launch_bounds__(1024) void k_bin_block_scan(uint32_t *__restrict__ 
             own += v[k];
         }
         uint32_t inc = own;
-        for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t y = __shfl_up(inc, o, 64);
-            if (lane >= o) inc += y;
+        for (int k = 1; k < 64; k <<= 1) {
+            const uint32_t y = __shfl_up(inc, k, 64);
+            if (lane >= k) inc += y;
         }
         if (lane == 63) wsum[w] = inc;
         __syncthreads();
@@ -167,19 +186,42 @@ __global__ __launch_bounds__(1024) void k_bin_block_scan(uint32_t *__restrict__ 
         carry += total;
         __syncthreads();   // wsum is reused
     }
-    if (threadIdx.x == 0) boff[int64_t(blockIdx.x) * stride + n_trials] = carry;
+    if (threadIdx.x != 0) return;
+    const int64_t at = int64_t(blockIdx.x) * r.stride + n_trials;
+    if (!B24) {
+        r.abs[at] = carry;
+        return;
+    }
+    if (carry >= (1u << 24)) atomicOr(err, ERR_BIN_WIDE);
+    // a whole word (3 at is a multiple of 4 here); its top byte is the next entry's, padding
+    if (n_trials % kCountBlock == 0) *reinterpret_cast<uint32_t *>(r.b24 + 3 * at) = carry;
 }
 
-// boff[b][t] += (prefix of bin b before trial t's block), t < n_trials: 4096 trials
-// per workgroup, 4 per thread (a block holds 64, so one prefix per thread).
-__global__ __launch_bounds__(1024) void k_bin_block_add(uint32_t *__restrict__ boff, int64_t stride, int64_t n_trials,
-                                                        const uint32_t *__restrict__ sums, int64_t nblk) {
+// Adds to each run start the start of its block in the bin (sums after the scan),
+// 4 entries per thread, 4096 per workgroup: the 4-byte entries t < n_trials (the one
+// at n_trials holds the length), or the 3-byte ones of every block that has trials,
+// as 12-byte groups (the last group may reach into padding).
+template <bool B24>
+__global__ __launch_bounds__(1024) void k_bin_block_add(RunStarts r, int64_t n_trials, const uint32_t *__restrict__ sums,
+                                                        int64_t nblk) {
     typedef uint32_t u32x4b __attribute__((ext_vector_type(4)));
     const int64_t t = int64_t(blockIdx.x) * 4096 + 4 * int64_t(threadIdx.x);
+    const int64_t b = blockIdx.y;
+    if (B24) {
+        if (t >= nblk * kCountBlock || t > n_trials) return;
+        const uint32_t add = sums[b * nblk + t / kCountBlock];
+        u32x3b *p = reinterpret_cast<u32x3b *>(r.b24 + 3 * (b * r.stride + t));   // 12 t: 4-byte aligned
+        const u32x3b w = *p;
+        const uint32_t v0 = (w[0] & 0xFFFFFFu) + add, v1 = ((w[0] >> 24) | (w[1] << 8)) + add,
+                       v2 = ((w[1] >> 16) | (w[2] << 16)) + add, v3 = (w[2] >> 8) + add;
+        *p = u32x3b{(v0 & 0xFFFFFFu) | (v1 << 24), ((v1 >> 8) & 0xFFFFu) | (v2 << 16),
+                    ((v2 >> 16) & 0xFFu) | (v3 << 8)};
+        return;
+    }
     if (t >= n_trials) return;
-    const uint32_t add = sums[int64_t(blockIdx.y) * nblk + t / kCountBlock];
-    uint32_t *row = boff + int64_t(blockIdx.y) * stride;
-    if (t + 4 <= n_trials) {   // rows start 16-byte aligned (stride is a multiple of 4)
+    const uint32_t add = sums[b * nblk + t / kCountBlock];
+    uint32_t *row = r.abs + b * r.stride;
+    if (t + 4 <= n_trials) {   // rows start 16-byte aligned (stride is a multiple of 8)
         u32x4b *p = reinterpret_cast<u32x4b *>(row + t);
         *p = *p + add;
     } else {
@@ -270,46 +312,57 @@ size_t bin_offsets_scratch_words(int64_t n_trials, int32_t n_bins) {
 }
 
 hipError_t launch_bin_offsets(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
-                              int32_t n_bins, uint32_t *boff, int64_t stride, int32_t catalog, uint32_t *sums,
-                              uint32_t *err, hipStream_t s) {
+                              int32_t n_bins, const RunStarts &r, int32_t catalog, uint32_t *sums, uint32_t *err,
+                              hipStream_t s) {
     if (n_trials <= 0 || n_bins <= 0 || n_bins > kMaxBins) return hipErrorInvalidValue;
-    if ((stride & 3) || stride < n_trials + 1) return hipErrorInvalidValue;
+    if ((r.stride & 7) || r.stride < n_trials + 2 || (r.abs == nullptr) == (r.b24 == nullptr)) return hipErrorInvalidValue;
+    if (r.b24 && n_bins > 64) return hipErrorInvalidValue;
     hipError_t e;
     if (n_bins <= 64) {
         const int64_t nblk = (n_trials + kCountBlock - 1) / kCountBlock;
-        const int64_t add_blocks = (n_trials + 4095) / 4096;
+        const int64_t add_blocks = (n_trials + 1 + 4095) / 4096;
         if (add_blocks > 65535) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_bin_count_block, dim3(unsigned(std::min<int64_t>(nblk, 65536))), dim3(kCountWaves * 64),
-                           0, s, ids, offs, n_events, n_trials, n_bins, boff, stride, catalog, sums, err);
+        const dim3 grid{unsigned(std::min<int64_t>(nblk, 65536))}, add_grid{unsigned(add_blocks), unsigned(n_bins)};
+        if (r.b24) {
+            hipLaunchKernelGGL(k_bin_count_block<true>, grid, dim3(kCountWaves * 64), 0, s, ids, offs, n_events,
+                               n_trials, n_bins, r, catalog, sums, err);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_bin_block_scan<true>, dim3(unsigned(n_bins)), dim3(1024), 0, s, sums, nblk, r,
+                               n_trials, err);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_bin_block_add<true>, add_grid, dim3(1024), 0, s, r, n_trials, sums, nblk);
+            return hipGetLastError();
+        }
+        hipLaunchKernelGGL(k_bin_count_block<false>, grid, dim3(kCountWaves * 64), 0, s, ids, offs, n_events, n_trials,
+                           n_bins, r, catalog, sums, err);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_bin_block_scan, dim3(unsigned(n_bins)), dim3(1024), 0, s, sums, nblk, boff, stride,
-                           n_trials);
+        hipLaunchKernelGGL(k_bin_block_scan<false>, dim3(unsigned(n_bins)), dim3(1024), 0, s, sums, nblk, r, n_trials,
+                           err);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_bin_block_add, dim3(unsigned(add_blocks), unsigned(n_bins)), dim3(1024), 0, s, boff,
-                           stride, n_trials, sums, nblk);
+        hipLaunchKernelGGL(k_bin_block_add<false>, add_grid, dim3(1024), 0, s, r, n_trials, sums, nblk);
         return hipGetLastError();
     }
     const int64_t grid = std::max<int64_t>(1, std::min<int64_t>((n_trials + kCountWaves - 1) / kCountWaves, 65536));
     hipLaunchKernelGGL(k_bin_count, dim3(unsigned(grid)), dim3(kCountWaves * 64), 0, s, ids, offs, n_events, n_trials,
-                       n_bins, boff, stride, catalog, err);
+                       n_bins, r.abs, r.stride, catalog, err);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return launch_bin_scan(boff, stride, n_trials + 1, n_bins, sums, s);
+    return launch_bin_scan(r.abs, r.stride, n_trials + 1, n_bins, sums, s);
 }
 
 // Region starts from the scanned offsets: region[0] = 0, region[b + 1] = region[b] +
-// (bin b's length rounded up to 8), bin b's length being boff[b][n_trials] after the
-// scan.  One wave, up to 512 bins (8 per lane).  Skipped when the count pass found a
-// bad ID or offset (err set): the scatter is skipped then too.
-__global__ __launch_bounds__(64) void k_bin_regions(const uint32_t *__restrict__ boff, int64_t stride, int64_t n_trials,
-                                                    int32_t n_bins, int64_t *__restrict__ region,
-                                                    const uint32_t *__restrict__ err) {
+// (bin b's length rounded up to 8), bin b's length being its run start at n_trials.
+// One wave, up to 512 bins (8 per lane).  Skipped when an error bit is set (a bad ID
+// or offset, or a bin too long for 3-byte run starts): the scatter is skipped then
+// too.
+__global__ __launch_bounds__(64) void k_bin_regions(RunStarts r, int64_t n_trials, int32_t n_bins,
+                                                    int64_t *__restrict__ region, const uint32_t *__restrict__ err) {
     if (*err != 0u) return;
     const int lane = threadIdx.x;
     int64_t v[8], own = 0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const int32_t b = lane * 8 + k;
-        v[k] = b < n_bins ? (int64_t(boff[int64_t(b) * stride + n_trials]) + 7) & ~int64_t(7) : 0;
+        v[k] = b < n_bins ? (int64_t(run_at(r, b, n_trials)) + 7) & ~int64_t(7) : 0;
         own += v[k];
     }
     int64_t inc = own;
@@ -327,14 +380,14 @@ __global__ __launch_bounds__(64) void k_bin_regions(const uint32_t *__restrict__
     if (lane == 63) region[n_bins] = inc;   // the total
 }
 
-hipError_t launch_bin_regions(const uint32_t *boff, int64_t stride, int64_t n_trials, int32_t n_bins, int64_t *region,
+hipError_t launch_bin_regions(const RunStarts &r, int64_t n_trials, int32_t n_bins, int64_t *region,
                               const uint32_t *err, hipStream_t s) {
     if (n_bins > kMaxBins || kMaxBins > 8 * 64) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_bin_regions, dim3(1), dim3(64), 0, s, boff, stride, n_trials, n_bins, region, err);
+    hipLaunchKernelGGL(k_bin_regions, dim3(1), dim3(64), 0, s, r, n_trials, n_bins, region, err);
     return hipGetLastError();
 }
 
-// Writes each occurrence at region[b] + boff[b][t] + (its rank among trial t's
+// Writes each occurrence at region[b] + run(b, t) + (its rank among trial t's
 // earlier occurrences of bin b).  A workgroup takes `per_block` consecutive trials;
 // their occurrences of bin b form one contiguous span of region b, so when the
 // block's occurrences fit in LDS they are placed there first (a counting sort by
@@ -385,15 +438,15 @@ __device__ __forceinline__ void same_bin_rank(uint32_t b, uint64_t valid, uint32
 template <int NBITS, bool STAGED>
 __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_t *__restrict__ ids,
                                                                     const int64_t *__restrict__ offs, int64_t n_trials,
-                                                                    int32_t n_bins, const uint32_t *__restrict__ boff,
-                                                                    int64_t stride, const int64_t *__restrict__ region,
+                                                                    int32_t n_bins, RunStarts r,
+                                                                    const int64_t *__restrict__ region,
                                                                     uint16_t *__restrict__ ids16, int64_t per_block,
                                                                     const uint32_t *__restrict__ err) {
     constexpr int kBins = NBITS <= 6 ? 64 : kMaxBins;   // bins the LDS tables hold
     __shared__ __attribute__((aligned(16))) uint16_t stage[STAGED ? kScatterCap : 8];
     __shared__ uint32_t cur[kScatterWaves][kBins];      // next position of the wave's trial's run, per bin
     __shared__ uint32_t lbase[kBins + 1];               // start of bin b's span in `stage`
-    __shared__ uint32_t bstart[kBins];                  // boff[b][t0]
+    __shared__ uint32_t bstart[kBins];                  // run(b, t0)
     __shared__ uint32_t blen[kBins];                    // bin b's span length
     __shared__ uint64_t lanes_of[NBITS <= 6 ? kScatterWaves : 1][NBITS <= 6 ? 64 : 1];   // per wave and bin: its lanes
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -411,9 +464,9 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
     if (NBITS <= 6) lm[lane] = 0;
     if (staged) {
         for (int32_t b = threadIdx.x; b < n_bins; b += kScatterWaves * 64) {
-            const uint32_t s = boff[b * stride + t0];
+            const uint32_t s = run_at(r, b, t0);
             bstart[b] = s;
-            lbase[b + 1] = boff[b * stride + t1] - s;
+            lbase[b + 1] = run_at(r, b, t1) - s;
         }
         __syncthreads();
         if (wave == 0) {   // exclusive scan of the padded span lengths, 8 bins per lane
@@ -459,10 +512,10 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
         const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void *)(offs + tc), 0, 16, kBufWord3);
         return __builtin_bit_cast(i64x2, __builtin_amdgcn_raw_buffer_load_b128(rs, 0, 0, 0));
     };
-    auto load_wb = [&](int64_t tt, uint32_t (&w)[kWB]) {   // boff[b][tt], b = lane + 64 k
+    auto load_wb = [&](int64_t tt, uint32_t (&w)[kWB]) {   // run(b, tt), b = lane + 64 k
         const int64_t tc = min(tt, n_trials);
 #pragma unroll
-        for (int k = 0; k < kWB; ++k) w[k] = boff[min(lane + 64 * k, n_bins - 1) * stride + tc];
+        for (int k = 0; k < kWB; ++k) w[k] = run_at(r, min(lane + 64 * k, n_bins - 1), tc);
     };
     auto load_chunk = [&](int64_t start, int64_t end, uint32_t (&c)[kChunkSteps]) {
         const int32_t avail = int32_t(max(int64_t(0), min(end - start, int64_t(kChunkIds))));
@@ -589,8 +642,8 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
 }
 
 hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
-                              int32_t n_bins, const uint32_t *boff, int64_t stride, const int64_t *region,
-                              uint16_t *ids16, const uint32_t *err, hipStream_t s) {
+                              int32_t n_bins, const RunStarts &r, const int64_t *region, uint16_t *ids16,
+                              const uint32_t *err, hipStream_t s) {
     if (n_trials <= 0) return hipSuccess;
     if (n_bins > kMaxBins) return hipErrorInvalidValue;
     const int64_t per = bin_scatter_block_trials(n_events, n_trials);
@@ -603,11 +656,11 @@ hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n
     auto launch = [&](auto nb_const) {
         constexpr int NB = decltype(nb_const)::value;
         hipLaunchKernelGGL((k_bin_scatter<NB, true>), dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs,
-                           n_trials, n_bins, boff, stride, region, ids16, per, err);
+                           n_trials, n_bins, r, region, ids16, per, err);
         e = hipGetLastError();
         if (e != hipSuccess) return;
         hipLaunchKernelGGL((k_bin_scatter<NB, false>), dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs,
-                           n_trials, n_bins, boff, stride, region, ids16, per, err);
+                           n_trials, n_bins, r, region, ids16, per, err);
         e = hipGetLastError();
     };
     switch (nbits) {

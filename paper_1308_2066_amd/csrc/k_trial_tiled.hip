@@ -168,7 +168,9 @@ __device__ __forceinline__ void unit_run(const double *tab, const uint16_t *base
 // unit u + 3 is issued once unit u is added.  No load is issued under a condition, so
 // that every wait counts only the loads issued after the one it waits for: bins past
 // the last give empty runs and restage the last bin.
-template <bool MAX>
+// B24: run starts in 3 bytes each, read as an unaligned 4-byte word (its top byte,
+// the next entry's first, masked off where the value is taken).
+template <bool MAX, bool B24>
 __device__ __forceinline__ void tiled_pass(const TiledArgs &a, int64_t pass, int64_t pass_end, double *tab, double *ws,
                                            int lane, uint32_t wave) {
     const int64_t span = pass_end - pass;
@@ -181,11 +183,21 @@ __device__ __forceinline__ void tiled_pass(const TiledArgs &a, int64_t pass, int
         if (64 * g + lane < kTiledWaveTrials) ws[64 * g + lane] = 0.0;
     // start of the run of trial T0 + 64 g + lane (the wave's span end past T1), and
     // the end of the group's last run (scalar)
-    auto run_start = [&](int32_t b, int g) -> uint32_t {
-        return a.boff[int64_t(b) * a.stride + min(T0 + 64 * g + lane, T1)];
+    constexpr uint32_t kRunMask = B24 ? 0xFFFFFFu : 0xFFFFFFFFu;
+    auto run_start = [&](int32_t b, int g) -> uint32_t {   // the word before masking
+        const int64_t i = int64_t(b) * a.stride + min(T0 + 64 * g + lane, T1);
+        if (!B24) return a.boff[i];
+        uint32_t w;
+        __builtin_memcpy(&w, a.boff24 + 3 * i, 4);
+        return w;
     };
     auto group_end = [&](int32_t b, int g) -> uint32_t {
-        return sload(a.boff + int64_t(b) * a.stride + min(T0 + 64 * g + 64, T1));
+        const int64_t i = int64_t(b) * a.stride + min(T0 + 64 * g + 64, T1);
+        if (!B24) return sload(a.boff + i);
+        // the two aligned words holding bytes 3 i .. 3 i + 2
+        const uint32_t *p = reinterpret_cast<const uint32_t *>(a.boff24 + ((3 * i) & ~int64_t(3)));
+        const uint64_t w = uint64_t(sload(p)) | (uint64_t(sload(p + 1)) << 32);
+        return uint32_t(w >> (8 * ((3 * i) & 3))) & kRunMask;
     };
     f64x2 st[kStageVecs];
     stage_load(a, 0, st);
@@ -194,10 +206,10 @@ __device__ __forceinline__ void tiled_pass(const TiledArgs &a, int64_t pass, int
     Unit U[3];
 #pragma unroll
     for (int g = 0; g < 3; ++g) {
-        U[g].s = run_start(0, g);
+        U[g].s = run_start(0, g) & kRunMask;
         unit_issue(rc, U[g]);
     }
-    uint32_t s3 = run_start(0, 3);
+    uint32_t s3 = run_start(0, 3) & kRunMask;
     uint32_t ge[kGroups];
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) ge[g] = group_end(0, g);
@@ -213,7 +225,7 @@ __device__ __forceinline__ void tiled_pass(const TiledArgs &a, int64_t pass, int
 #pragma unroll
             for (int g = 0; g < kGroups; ++g) {
                 const uint32_t x = run_start(bn, g), y = group_end(bn, g);
-                sn[g] = more ? x : 0u;
+                sn[g] = more ? x & kRunMask : 0u;
                 gn[g] = more ? y : 0u;
             }
             __syncthreads();   // every wave is done with the previous bin
@@ -255,7 +267,7 @@ __device__ __forceinline__ void tiled_pass(const TiledArgs &a, int64_t pass, int
 }
 
 // One analysis: workgroup w owns trials [t_begin + w per_wg, + per_wg), in passes.
-template <bool MAX>
+template <bool MAX, bool B24>
 __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
     __shared__ __attribute__((aligned(16))) double tab[kBinEvents + 2];   // a bin's values, the zero slot
     __shared__ double sums[kTiledWaves * kTiledWaveTrials];
@@ -265,8 +277,8 @@ __global__ __launch_bounds__(1024) void k_trial_tiled(TiledArgs a) {
     const int64_t wg0 = a.t_begin + int64_t(blockIdx.x) * a.per_wg;
     const int64_t wg1 = min(wg0 + a.per_wg, a.t_end);
     for (int64_t pass = wg0; pass < wg1; pass += kTiledPassTrials)
-        tiled_pass<MAX>(a, pass, min(pass + int64_t(kTiledPassTrials), wg1), tab, sums + wave * kTiledWaveTrials, lane,
-                        wave);
+        tiled_pass<MAX, B24>(a, pass, min(pass + int64_t(kTiledPassTrials), wg1), tab, sums + wave * kTiledWaveTrials,
+                             lane, wave);
 }
 
 // Analysis j's arguments from device memory, through the scalar data path.
@@ -305,7 +317,8 @@ __global__ __launch_bounds__(1024) void k_trial_tiled_items(const TiledArgs *__r
         const int64_t t0 = int64_t(uint64_t(sload(iw + 2)) | (uint64_t(sload(iw + 3)) << 32));
         const int64_t t1 = int64_t(uint64_t(sload(iw + 4)) | (uint64_t(sload(iw + 5)) << 32));
         const TiledArgs a = load_args(jobs, job);
-        tiled_pass<false>(a, t0, t1, tab, sums + wave * kTiledWaveTrials, lane, wave);
+        if (a.boff24) tiled_pass<false, true>(a, t0, t1, tab, sums + wave * kTiledWaveTrials, lane, wave);
+        else tiled_pass<false, false>(a, t0, t1, tab, sums + wave * kTiledWaveTrials, lane, wave);
     }
 }
 
@@ -319,8 +332,14 @@ hipError_t launch_trial_tiled_items(const TiledArgs *jobs, const TiledItem *item
 }
 
 hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s, bool occ_max) {
-    if (occ_max) hipLaunchKernelGGL(k_trial_tiled<true>, dim3(grid), dim3(kTiledWaves * 64), 0, s, a);
-    else hipLaunchKernelGGL(k_trial_tiled<false>, dim3(grid), dim3(kTiledWaves * 64), 0, s, a);
+    const dim3 g(grid), b(kTiledWaves * 64);
+    if (a.boff24) {
+        if (occ_max) hipLaunchKernelGGL((k_trial_tiled<true, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_trial_tiled<false, true>), g, b, 0, s, a);
+    } else {
+        if (occ_max) hipLaunchKernelGGL((k_trial_tiled<true, false>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_trial_tiled<false, false>), g, b, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -50,8 +50,9 @@ def _check_copy(A, y, ids, offs, catalog):
         assert np.array_equal(ids16[region[b]:region[b] + boff_x[b, -1]], per_bin[b]), f"bin {b}"
 
 
+@pytest.mark.parametrize("run_bytes", [4, 3])
 @pytest.mark.parametrize("case", ["poisson", "ragged_long_trial", "one_bin_heavy", "many_trials"])
-def test_binned_copy_matches_definition(ara_lib, gpu_ctx, case):
+def test_binned_copy_matches_definition(ara_lib, gpu_ctx, case, run_bytes):
     import torch
     A = ara_lib
     rng = np.random.default_rng({"poisson": 11, "ragged_long_trial": 12, "one_bin_heavy": 13, "many_trials": 14}[case])
@@ -77,26 +78,39 @@ def test_binned_copy_matches_definition(ara_lib, gpu_ctx, case):
     if case == "one_bin_heavy":   # most occurrences in bin 3, so runs of one bin are long
         heavy = rng.random(len(ids)) < 0.8
         ids[heavy] = (3 << BIN_SHIFT) + rng.integers(0, 1 << BIN_SHIFT, size=int(heavy.sum()), dtype=np.int32)
-    _say(f"binned copy {case}: {len(lens)} trials, {len(ids)} occurrences")
-    y = A.ara_yet_create(gpu_ctx, torch.from_numpy(ids).cuda(), torch.from_numpy(offs).cuda(), catalog)
+    _say(f"binned copy {case}, {run_bytes}-byte run starts: {len(lens)} trials, {len(ids)} occurrences")
+    A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_RUN_BYTES, run_bytes)
+    try:
+        y = A.ara_yet_create(gpu_ctx, torch.from_numpy(ids).cuda(), torch.from_numpy(offs).cuda(), catalog)
+    finally:
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_RUN_BYTES, 4)
     try:
         assert A.ara_yet_info(y)[2] == 2
+        assert A.ara_yet_memory(y)[1] == run_bytes
         _check_copy(A, y, ids, offs, catalog)
     finally:
         A.ara_yet_release(y)
 
 
 def test_paper_scale_binned_copy(ara_lib, gpu_ctx):
-    """The paper-scale YET (10^6 trials x 1000 events, 10^6-event catalog): per-bin
-    totals over every occurrence, and every run of 2,000 sampled trials."""
+    """The paper-scale YET (10^6 trials x 1000 events, 10^6-event catalog) with 3-byte
+    run starts: at most 2.2 GB added to the caller's arrays, per-bin totals over every
+    occurrence, and every run of 2,000 sampled trials."""
     import torch
     A = ara_lib
     w = synth.workload_paper_scale()
-    _say("paper-scale binned copy")
-    y = A.ara_yet_create(gpu_ctx, torch.from_numpy(w.event_ids).cuda(), torch.from_numpy(w.trial_offsets).cuda(),
-                         w.catalog_size)
+    _say("paper-scale binned copy, 3-byte run starts")
+    A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_RUN_BYTES, 3)
+    try:
+        y = A.ara_yet_create(gpu_ctx, torch.from_numpy(w.event_ids).cuda(), torch.from_numpy(w.trial_offsets).cuda(),
+                             w.catalog_size)
+    finally:
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_RUN_BYTES, 4)
     try:
         assert A.ara_yet_info(y)[2] == 2
+        extra, run_bytes = A.ara_yet_memory(y)
+        assert run_bytes == 3, "every bin is shorter than 2^24: 3-byte run starts"
+        assert extra <= 2.2e9, f"{extra} bytes added to the caller's arrays"
         region, boff, ids16 = A.ara_yet_binned(y)
         n_bins = len(region) - 1
         totals = np.bincount(w.event_ids >> BIN_SHIFT, minlength=n_bins)

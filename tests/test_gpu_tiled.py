@@ -41,13 +41,15 @@ def S():
     return session
 
 
-def _open(A, S, ctx, w, terms=None, binning=1, precision=0):
+def _open(A, S, ctx, w, terms=None, binning=1, precision=0, run_bytes=4):
     A.ara_set_option(ctx, A.ARA_OPT_YET_BINNING, binning)
+    A.ara_set_option(ctx, A.ARA_OPT_YET_RUN_BYTES, run_bytes)
     try:
         return S.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts,
                                terms if terms is not None else w.layer_terms, w.elt_terms, precision)
     finally:
         A.ara_set_option(ctx, A.ARA_OPT_YET_BINNING, 1)
+        A.ara_set_option(ctx, A.ARA_OPT_YET_RUN_BYTES, 4)
 
 
 def _run(A, ctx, an, placement, t0=0, t1=None):
@@ -339,3 +341,80 @@ def test_largest_binned_catalog(A, S, gpu_ctx):
         _close(_run(A, gpu_ctx, an, 0), oracle.analyze_workload(w2, threads=oracle.max_threads()), "2^23 + 1 catalog")
     finally:
         an.release()
+
+
+def test_long_bin_keeps_four_byte_run_starts(A, S, gpu_ctx):
+    """Asked for 3-byte run starts, a YET with a catalog bin of more than 2^24
+    occurrences gets 4-byte ones (the 3-byte build flags the bin and is redone), the
+    readout still gives the definition's bin lengths, and the tiled kernel on that
+    form matches the oracle (YLT and maxima)."""
+    rng = np.random.default_rng(307)
+    C = 100_000   # 7 bins
+    lengths = rng.integers(800, 1000, size=20_000)
+
+    def mostly_bin0(n):   # 97% of the occurrences in bin 0: about 17.5M > 2^24
+        x = rng.integers(0, C, size=n)
+        heavy = rng.random(n) < 0.97
+        x[heavy] = rng.integers(0, 1 << 14, size=int(heavy.sum()))
+        return x
+
+    w = _workload(rng, lengths, C, n_elts=2, id_sampler=mostly_bin0)
+    w = w.with_terms((5e4, 1e6, 2e8, INF))
+    _say(f"tiled long bin: {len(w.event_ids)} occurrences")
+    an = _open(A, S, gpu_ctx, w, run_bytes=3)
+    try:
+        assert A.ara_yet_info(an.yet)[2] == 2, "binned copy expected"
+        assert A.ara_yet_memory(an.yet)[1] == 4
+        region, boff, _ = A.ara_yet_binned(an.yet)
+        totals = np.bincount(w.event_ids >> 14, minlength=len(region) - 1)
+        assert totals[0] >= 1 << 24
+        assert np.array_equal(boff[:, -1].astype(np.int64), totals)
+        got = _run(A, gpu_ctx, an, 0)
+        assert _run(A, gpu_ctx, an, TILES).tobytes() == got.tobytes()
+        ref = oracle.analyze_workload(w, threads=oracle.max_threads())
+        _close(got, ref, "long bin")
+        _check_occ_max(A, gpu_ctx, an, ref, "long bin", [(0, 20_000), (7, 9_001)])
+    finally:
+        an.release()
+
+
+def test_three_byte_run_starts_same_bits(A, S, gpu_ctx):
+    """The same YET with 3-byte run starts (ARA_OPT_YET_RUN_BYTES = 3): less memory, the
+    same binned copy on readout, and the bits of the 4-byte form for the YLT and the
+    occurrence maxima -- on the paper's shape and on ragged runs, whole, on sub-ranges,
+    and in one batch holding both forms."""
+    import torch
+    rng = np.random.default_rng(308)
+    paper = synth.workload_paper_scale(n_trials=6_000).with_terms((1e5, 5e6, 1.5e8, INF))
+    lengths = [0] * 40 + list(rng.integers(0, 900, size=700)) + [4000, 1, 0, 2500] + [0] * 70 + [3]
+    ragged = _workload(rng, lengths, 150_001, n_elts=3, nnz=40_000)
+    for w, what in ((paper, "paper shape"), (ragged, "ragged")):
+        _say(f"3-byte run starts: {what}")
+        a4, a3 = _open(A, S, gpu_ctx, w), _open(A, S, gpu_ctx, w, run_bytes=3)
+        try:
+            (m4, r4), (m3, r3) = A.ara_yet_memory(a4.yet), A.ara_yet_memory(a3.yet)
+            assert (r4, r3) == (4, 3) and m3 < m4, (m4, r4, m3, r3)
+            (g4, b4, i4), (g3, b3, i3) = A.ara_yet_binned(a4.yet), A.ara_yet_binned(a3.yet)
+            assert np.array_equal(g4, g3) and np.array_equal(b4, b3), what
+            for b in range(len(g4) - 1):   # the runs (regions are padded to 8 IDs with unused slots)
+                assert np.array_equal(i4[g4[b]:g4[b] + b4[b, -1]], i3[g3[b]:g3[b] + b3[b, -1]]), (what, b)
+            n = w.n_trials
+            y4 = _run(A, gpu_ctx, a4, 0)
+            assert _run(A, gpu_ctx, a3, 0).tobytes() == y4.tobytes(), what
+            assert _run(A, gpu_ctx, a3, TILES).tobytes() == y4.tobytes(), what
+            for t0, t1 in ((0, 1), (13, n // 2 + 7), (n - 1, n)):
+                assert _run(A, gpu_ctx, a3, 0, t0, t1).tobytes() == y4[t0:t1].tobytes(), (what, t0, t1)
+            assert _occ_max(A, gpu_ctx, a3, TILES, 0, n).tobytes() == _occ_max(A, gpu_ctx, a4, TILES, 0, n).tobytes()
+            specs = [(a4, 0, n), (a3, 0, n), (a3, 5, n - 3)]
+            outs = [torch.full((t1 - t0,), math.nan, dtype=torch.float64, device="cuda") for _, t0, t1 in specs]
+            b = A.ara_batch_create(gpu_ctx, [(an.yet, an.layer, t0, t1, o) for (an, t0, t1), o in zip(specs, outs)])
+            try:
+                A.ara_batch_run(b)
+                A.ara_sync(gpu_ctx)
+                for (an, t0, t1), o in zip(specs, outs):
+                    assert o.cpu().numpy().tobytes() == y4[t0:t1].tobytes(), (what, t0, t1)
+            finally:
+                A.ara_batch_release(b)
+        finally:
+            a4.release()
+            a3.release()
