@@ -435,7 +435,7 @@ __device__ __forceinline__ void same_bin_rank(uint32_t b, uint64_t valid, uint32
     count = uint32_t(__popcll(m));
 }
 
-template <int NBITS, bool STAGED>
+template <int NBITS>
 __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_t *__restrict__ ids,
                                                                     const int64_t *__restrict__ offs, int64_t n_trials,
                                                                     int32_t n_bins, RunStarts r,
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
                                                                     uint16_t *__restrict__ ids16, int64_t per_block,
                                                                     const uint32_t *__restrict__ err) {
     constexpr int kBins = NBITS <= 6 ? 64 : kMaxBins;   // bins the LDS tables hold
-    __shared__ __attribute__((aligned(16))) uint16_t stage[STAGED ? kScatterCap : 8];
+    __shared__ __attribute__((aligned(16))) uint16_t stage[kScatterCap];
     __shared__ uint32_t cur[kScatterWaves][kBins];      // next position of the wave's trial's run, per bin
     __shared__ uint32_t lbase[kBins + 1];               // start of bin b's span in `stage`
     __shared__ uint32_t bstart[kBins];                  // run(b, t0)
@@ -455,10 +455,11 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
     // the count pass found a bad ID or offset: the counts do not describe the input
     if (*err != 0u) return;
     const int64_t t1 = min(t0 + per_block, n_trials);
-    // a block with more occurrences than the LDS holds is left to the unstaged launch
-    // (and the unstaged launch leaves the others)
-    if ((offs[t1] - offs[t0] + int64_t(kScatterPad) * n_bins <= int64_t(kScatterCap)) != STAGED) return;
-    constexpr bool staged = STAGED;
+    // a block with more occurrences than the LDS holds writes them to their places
+    // directly (the body below, compiled for each case)
+    const bool fits = offs[t1] - offs[t0] + int64_t(kScatterPad) * n_bins <= int64_t(kScatterCap);
+    auto body = [&](auto staged_case) {
+    constexpr bool staged = decltype(staged_case)::value;
     uint32_t *wc = cur[wave];
     uint64_t *lm = lanes_of[NBITS <= 6 ? wave : 0];
     if (NBITS <= 6) lm[lane] = 0;
@@ -639,6 +640,9 @@ __global__ __launch_bounds__(kScatterWaves * 64) void k_bin_scatter(const int32_
         for (uint32_t k = lane; k < n16; k += 64) dst16[k] = src16[k];
         if (uint32_t(lane) < tail) dst[head + 8 * n16 + lane] = stage[l0 + head + 8 * n16 + lane];
     }
+    };
+    if (fits) body(std::true_type{});
+    else body(std::false_type{});
 }
 
 hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n_events, int64_t n_trials,
@@ -650,16 +654,11 @@ hipError_t launch_bin_scatter(const int32_t *ids, const int64_t *offs, int64_t n
     const int64_t grid = (n_trials + per - 1) / per;
     if (grid > int64_t(INT32_MAX)) return hipErrorInvalidValue;
     const int nbits = n_bins > 1 ? 32 - __builtin_clz(uint32_t(n_bins - 1)) : 0;
-    // one instantiation per bit count of the bin numbers (the rank's ballots unrolled),
-    // each launched for the staged blocks and then for the others
+    // one instantiation per bit count of the bin numbers (the rank's ballots unrolled)
     hipError_t e = hipSuccess;
     auto launch = [&](auto nb_const) {
         constexpr int NB = decltype(nb_const)::value;
-        hipLaunchKernelGGL((k_bin_scatter<NB, true>), dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs,
-                           n_trials, n_bins, r, region, ids16, per, err);
-        e = hipGetLastError();
-        if (e != hipSuccess) return;
-        hipLaunchKernelGGL((k_bin_scatter<NB, false>), dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs,
+        hipLaunchKernelGGL((k_bin_scatter<NB>), dim3(unsigned(grid)), dim3(kScatterWaves * 64), 0, s, ids, offs,
                            n_trials, n_bins, r, region, ids16, per, err);
         e = hipGetLastError();
     };
