@@ -92,6 +92,45 @@ def test_binned_copy_matches_definition(ara_lib, gpu_ctx, case, run_bytes):
         A.ara_yet_release(y)
 
 
+@pytest.mark.parametrize("run_bytes", [4, 3])
+@pytest.mark.parametrize("shape", ["one_trial", "63_trials", "65_trials", "mostly_empty", "smallest_catalog"])
+def test_binned_copy_edge_shapes(ara_lib, gpu_ctx, shape, run_bytes):
+    """Trial counts either side of a 64-trial block, a single trial, trials that are
+    nearly all empty, and the smallest catalog that gets a binned copy (one event more
+    than a dense binary64 table in 160 KB of LDS): the copy against its definition."""
+    import torch
+    A = ara_lib
+    rng = np.random.default_rng({"one_trial": 21, "63_trials": 22, "65_trials": 23, "mostly_empty": 24,
+                                 "smallest_catalog": 25}[shape])
+    catalog = 20_481 if shape == "smallest_catalog" else 50_000
+    if shape == "one_trial":
+        lens = np.array([777])
+    elif shape == "63_trials":
+        lens = rng.integers(100, 300, size=63)
+    elif shape == "65_trials":
+        lens = rng.integers(100, 300, size=65)
+    elif shape == "mostly_empty":
+        lens = np.zeros(640, np.int64)
+        lens[[0, 63, 64, 639]] = [12_000, 1, 9_000, 16_000]
+    else:
+        lens = rng.integers(50, 150, size=200)
+    offs = np.zeros(len(lens) + 1, np.int64)
+    offs[1:] = np.cumsum(lens)
+    ids = rng.integers(0, catalog, size=int(offs[-1]), dtype=np.int32)
+    _say(f"binned copy edge shape {shape}, {run_bytes}-byte run starts: {len(lens)} trials, {len(ids)} occurrences")
+    A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_RUN_BYTES, run_bytes)
+    try:
+        y = A.ara_yet_create(gpu_ctx, torch.from_numpy(ids).cuda(), torch.from_numpy(offs).cuda(), catalog)
+    finally:
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_RUN_BYTES, 4)
+    try:
+        assert A.ara_yet_info(y)[2] == 2, "binned copy expected"
+        assert A.ara_yet_memory(y)[1] == run_bytes
+        _check_copy(A, y, ids, offs, catalog)
+    finally:
+        A.ara_yet_release(y)
+
+
 def test_paper_scale_binned_copy(ara_lib, gpu_ctx):
     """The paper-scale YET (10^6 trials x 1000 events, 10^6-event catalog) with 3-byte
     run starts: at most 2.2 GB added to the caller's arrays, per-bin totals over every
@@ -128,14 +167,23 @@ def test_paper_scale_binned_copy(ara_lib, gpu_ctx):
         A.ara_yet_release(y)
 
 
+@pytest.mark.parametrize("run_bytes", [4, 3])
 @pytest.mark.parametrize("bad", [-1, 1_000_000, 2_000_000_000])
-def test_binned_yet_rejects_bad_ids_and_offsets(ara_lib, gpu_ctx, bad):
+def test_binned_yet_rejects_bad_ids_and_offsets(ara_lib, gpu_ctx, bad, run_bytes):
     """A YET whose size takes the binned copy is checked in the copy's count pass:
     one ID outside [0, catalog) anywhere (first trial, last trial, middle) fails the
     creation with ARA_E_EVENT_ID_RANGE, bad offsets with ARA_E_BAD_OFFSETS, and the
-    context works afterwards."""
-    import torch
+    context works afterwards; with either run-start form."""
     A = ara_lib
+    A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_RUN_BYTES, run_bytes)
+    try:
+        _rejects_bad_ids_and_offsets(A, gpu_ctx, bad, run_bytes)
+    finally:
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_YET_RUN_BYTES, 4)
+
+
+def _rejects_bad_ids_and_offsets(A, gpu_ctx, bad, run_bytes):
+    import torch
     rng = np.random.default_rng(abs(bad) % 97)
     n_trials, per = 3000, 600
     C = 1_000_000
@@ -158,5 +206,6 @@ def test_binned_yet_rejects_bad_ids_and_offsets(ara_lib, gpu_ctx, bad):
     yet = A.ara_yet_create(gpu_ctx, torch.from_numpy(ids).cuda(), torch.from_numpy(offs).cuda(), C)
     try:
         assert A.ara_yet_info(yet)[2] == 2, "this YET should keep a binned copy"
+        assert A.ara_yet_memory(yet)[1] == run_bytes
     finally:
         A.ara_yet_release(yet)
