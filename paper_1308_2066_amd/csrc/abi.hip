@@ -24,7 +24,7 @@ struct ara_ctx {
     hipStream_t stream = nullptr;
     int n_cu = 0;
     int lds_max = 0;
-    uint32_t *d_err = nullptr;       // device error bits
+    uint32_t *d_err = nullptr;       // device error bits (word 0), then d_out
     double *d_out = nullptr;         // small device result staging
     double *h_out = nullptr;         // pinned host mirror of d_out
     uint32_t *h_err = nullptr;       // pinned host error word
@@ -121,6 +121,8 @@ static ara_status hip_fail(ara_ctx *c, hipError_t e, const char *what) {
 static bool bad_retention(double r) { return !(r >= 0.0) || std::isinf(r); }
 static bool bad_limit(double l) { return !(l >= 0.0); }
 
+constexpr size_t kErrBytes = 16;   // the error word and spare words before the result staging
+
 static ara_status err_bits_status(uint32_t bits) {
     if (bits & ERR_ID_RANGE) return ARA_E_EVENT_ID_RANGE;
     if (bits & ERR_OFFSETS) return ARA_E_BAD_OFFSETS;
@@ -130,10 +132,12 @@ static ara_status err_bits_status(uint32_t bits) {
 }
 
 // Waits for the context stream, then reads and clears the device error word.  With
-// `wide`, the ERR_BIN_WIDE bit (not an input error) is returned there.
-static ara_status sync_and_check(ara_ctx *c, bool *wide = nullptr) {
-    HIP_OR_RETURN(c, hipMemcpyAsync(c->h_err, c->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream),
-                  "read error word");
+// `wide`, the ERR_BIN_WIDE bit (not an input error) is returned there.  `copied`: the
+// caller has already queued the error word's copy to h_err.
+static ara_status sync_and_check(ara_ctx *c, bool *wide = nullptr, bool copied = false) {
+    if (!copied)
+        HIP_OR_RETURN(c, hipMemcpyAsync(c->h_err, c->d_err, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream),
+                      "read error word");
     HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "stream synchronize");
     uint32_t bits = *c->h_err;
     if (bits) {
@@ -344,28 +348,26 @@ extern "C" ara_status ara_ctx_create(int device, void *hip_stream, ara_ctx **out
     const char *step = "kernel attributes";
     e = prepare_trial_kernels();
     if (e == hipSuccess) { step = "scratch address"; e = scratch_address(device, &c->scratch); }
-    if (e == hipSuccess) { step = "error word"; e = hipMalloc(&c->d_err, 256); }
-    if (e == hipSuccess) { step = "result staging"; e = hipMalloc(&c->d_out, kStageDoubles * sizeof(double)); }
+    // the error word (and a spare word) followed by the result staging, on the device and
+    // pinned on the host, so one copy brings back results and error bits together
+    const size_t blk = kErrBytes + kStageDoubles * sizeof(double);
+    if (e == hipSuccess) { step = "error word and result staging"; e = hipMalloc(&c->d_err, blk); }
+    if (e == hipSuccess) c->d_out = reinterpret_cast<double *>(reinterpret_cast<char *>(c->d_err) + kErrBytes);
     if (e == hipSuccess) {
-        step = "pinned staging";
-        e = hipHostMalloc(reinterpret_cast<void **>(&c->h_out), kStageDoubles * sizeof(double), hipHostMallocDefault);
+        step = "pinned error word and staging";
+        e = hipHostMalloc(reinterpret_cast<void **>(&c->h_err), blk, hipHostMallocDefault);
     }
-    if (e == hipSuccess) {
-        step = "pinned error word";
-        e = hipHostMalloc(reinterpret_cast<void **>(&c->h_err), 64, hipHostMallocDefault);
-    }
+    if (e == hipSuccess) c->h_out = reinterpret_cast<double *>(reinterpret_cast<char *>(c->h_err) + kErrBytes);
     if (e == hipSuccess) {
         step = "pinned sort plan";
         e = hipHostMalloc(reinterpret_cast<void **>(&c->h_plan), 32 * sizeof(uint32_t), hipHostMallocDefault);
     }
-    if (e == hipSuccess) { step = "clear error word"; e = launch_fill_u32(c->d_err, 64, 0u, c->stream); }
+    if (e == hipSuccess) { step = "clear error word"; e = launch_fill_u32(c->d_err, kErrBytes / 4, 0u, c->stream); }
     if (e == hipSuccess) { step = "synchronize"; e = hipStreamSynchronize(c->stream); }
     if (e != hipSuccess) {
         (void)hipGetLastError();
         fail(nullptr, ARA_E_DEVICE, "ctx: %s: %s", step, hipGetErrorString(e));
         dev_free(c->d_err);
-        dev_free(c->d_out);
-        if (c->h_out) (void)hipHostFree(c->h_out);
         if (c->h_err) (void)hipHostFree(c->h_err);
         if (c->h_plan) (void)hipHostFree(c->h_plan);
         delete c;
@@ -380,10 +382,8 @@ extern "C" ara_status ara_ctx_destroy(ara_ctx *c) {
     if (c->live > 0) return fail(c, ARA_E_BUSY, "%d handles still alive on this context", c->live);
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    dev_free(c->d_err);
-    dev_free(c->d_out);
-    if (c->h_out) (void)hipHostFree(c->h_out);
-    if (c->h_err) (void)hipHostFree(c->h_err);
+    dev_free(c->d_err);   // with d_out
+    if (c->h_err) (void)hipHostFree(c->h_err);   // with h_out
     if (c->h_plan) (void)hipHostFree(c->h_plan);
     delete c;
     return ARA_OK;
@@ -1185,9 +1185,10 @@ static ara_status risk_ranks(ara_ctx *c, int64_t n, const double *rps, int32_t n
 static ara_status risk_on_device(ara_ctx *c, const double *dy, int64_t n, const int64_t *ks, int32_t n_rp, double *pml,
                                  double *tvar, void *w) {
     hipError_t e = launch_risk_select(dy, n, w, ks, n_rp, c->d_out, c->stream);
-    if (e == hipSuccess && n_rp > 0)
-        e = hipMemcpyAsync(c->h_out, c->d_out, size_t(2 * n_rp) * 8, hipMemcpyDeviceToHost, c->stream);
-    ara_status s = e == hipSuccess ? sync_and_check(c) : hip_fail(c, e, "risk measures");
+    // the error word and the results in one copy (they are adjacent)
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(c->h_err, c->d_err, kErrBytes + size_t(2 * n_rp) * 8, hipMemcpyDeviceToHost, c->stream);
+    ara_status s = e == hipSuccess ? sync_and_check(c, nullptr, true) : hip_fail(c, e, "risk measures");
     if (s != ARA_OK) return s;
     for (int32_t base = 0; base < n_rp; base += 16) {
         const int32_t m = std::min<int32_t>(16, n_rp - base);
