@@ -7,10 +7,10 @@
 // that bin's events.  To make those occurrences contiguous the YET is regrouped by
 // bin: region b holds, for every trial in order, the trial's occurrences of bin-b
 // events in time order, each as its 14-bit ID within the bin (2 bytes).
-// boff[b][t] gives where trial t's run starts in region b, so the occurrences of
-// any trial range in one bin are one contiguous span.  The regrouping only changes
-// which occurrences are read together; each trial still has exactly its own
-// occurrences.
+// The run start of trial t in region b (4 bytes, or 3 bytes when asked for and every
+// bin is shorter than 2^24) gives where its run starts, so the occurrences of any
+// trial range in one bin are one contiguous span.  The regrouping only changes which
+// occurrences are read together; each trial still has exactly its own occurrences.
 //
 // The build runs count, row scans, region starts and scatter back to back on the
 // stream; the count pass checks the YET, and the later passes do nothing once it
@@ -41,7 +41,7 @@ __device__ __forceinline__ void count_trial(const int32_t *__restrict__ ids, con
         bad_offs = true;
         o1 = o0;   // read none of this trial's IDs
     }
-    constexpr int kAhead = 16;   // loads in flight per lane (4 KB per wave: enough to keep HBM busy)
+    constexpr int kAhead = 16;   // loads in flight per lane (4 KB per wave)
     for (int64_t base = o0; base < o1; base += 64 * kAhead) {
         uint32_t v[kAhead];
 #pragma unroll
