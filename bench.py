@@ -230,7 +230,8 @@ def summarize_counters(path: str, out_path: str, cmd: str):
     m = {k: float(np.mean(v)) for k, v in per.items()}
     n = len(next(iter(per.values()))) if per else 0
     lines = [f"# rocprofv3 counters of {kernel}, 1,000,000 trials x 1000 events, catalog 1,000,000, "
-             f"16-ELT layer, binary64 (mean of {n} dispatches)", f"# command: {cmd}", ""]
+             f"16-ELT layer, binary64 (mean of {n} dispatches)", f"# command: {cmd}",
+             f"source_sha256: {kernel_source_digest(kernel)}", ""]
     lines += [f"{k}: {v:.6g}" for k, v in sorted(m.items())]
     if "TCC_HIT_sum" in m and "TCC_MISS_sum" in m:
         lines.append(f"derived L2 hit rate: {m['TCC_HIT_sum'] / (m['TCC_HIT_sum'] + m['TCC_MISS_sum']):.3f}")
