@@ -716,7 +716,8 @@ extern "C" ara_status ara_elt_create(ara_ctx *c, const int32_t *ids, const doubl
         }
     }
     const size_t vbytes = prec == ARA_F32 ? 4 : 8;
-    if (s == ARA_OK) s = dev_alloc(c, &t->dat, size_t(catalog) * vbytes, "elt table");
+    // whole 8-byte pairs: the combined-table build reads binary32 tables two entries at a time
+    if (s == ARA_OK) s = dev_alloc(c, &t->dat, (size_t(catalog) * vbytes + 7) & ~size_t(7), "elt table");
     if (s == ARA_OK) s = dev_alloc(c, &t->seen, (size_t(catalog) + 31) / 32 * 4, "elt seen bits");
     if (s == ARA_OK) s = dev_alloc(c, &t->d_desc, sizeof(EltDesc), "elt descriptor");
     if (s != ARA_OK) {

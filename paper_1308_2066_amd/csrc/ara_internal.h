@@ -24,8 +24,8 @@ struct EltDesc {
     const int32_t *pair_ids;
     const double *pair_losses;
     int64_t n_pairs;
-    void *dat;          // catalog entries, binary64 or binary32 (f32 != 0)
-    uint32_t *seen;     // one bit per catalog event, for duplicate detection
+    void *dat;          // catalog entries, binary64 or binary32 (f32 != 0); defined where seen
+    uint32_t *seen;     // one bit per catalog event: listed by the ELT (also detects duplicates)
     int32_t f32;
     int32_t identity;   // financial terms are (1, 0, +inf)
     double fx, retention, limit;

@@ -80,30 +80,31 @@ hipError_t launch_yet_pack(const int32_t *ids, int64_t n_events, uint8_t *packed
     return hipGetLastError();
 }
 
-// Zero each ELT's direct access table and its duplicate-detection bits.
-// grid.y = ELT index.
+// Zero each ELT's seen bits (grid.y = ELT index).  An entry of the direct access
+// table is defined only where its seen bit is set: the scatter sets the bit with
+// every value it writes, and readers take 0 where the bit is clear, so the table
+// itself (8 or 4 bytes per catalog event) is never cleared, only its bits (one
+// per event).
 __global__ void k_elt_clear(const EltDesc *__restrict__ d, int32_t catalog) {
     const EltDesc e = d[blockIdx.y];
-    const size_t words = e.f32 ? size_t(catalog) : size_t(catalog) * 2;   // 32-bit words of the table
     const size_t seen_words = (size_t(catalog) + 31) / 32;
-    uint32_t *dat = reinterpret_cast<uint32_t *>(e.dat);
     size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
     const size_t stride = size_t(gridDim.x) * blockDim.x;
-    for (size_t k = i; k < words; k += stride) dat[k] = 0u;
     for (size_t k = i; k < seen_words; k += stride) e.seen[k] = 0u;
 }
 
 hipError_t launch_elt_clear(const EltDesc *d, int n_elts, int32_t catalog, hipStream_t s) {
     if (n_elts <= 0) return hipSuccess;
-    size_t words = size_t(catalog) * 2;
+    const size_t words = (size_t(catalog) + 31) / 32;
     unsigned bx = unsigned(std::min<size_t>((words + 255) / 256, 1024));
     hipLaunchKernelGGL(k_elt_clear, dim3(bx, unsigned(n_elts)), dim3(256), 0, s, d, catalog);
     return hipGetLastError();
 }
 
-// Scatter the (event, loss) records of each ELT into its table (grid.y = ELT).
-// Rejects IDs outside the catalog, negative / NaN / infinite losses, and an
-// event listed twice (the seen bit was already set).
+// Scatter the (event, loss) records of each ELT into its table (grid.y = ELT),
+// setting each written event's seen bit.  Rejects IDs outside the catalog,
+// negative / NaN / infinite losses (neither written nor marked), and an event
+// listed twice (the seen bit was already set).
 __global__ void k_elt_scatter(const EltDesc *__restrict__ d, int32_t catalog, uint32_t *err) {
     const EltDesc e = d[blockIdx.y];
     uint32_t bad = 0;

@@ -48,33 +48,76 @@ __global__ __launch_bounds__(256) void k_layer_bitmap(const V *__restrict__ comb
 // The combined table and the occurrence filter in one pass over the catalog: per
 // event, the ELTs' terms-applied losses added in listed order from +0.0 (rounded to
 // the table's type), then the operations of k_layer_bitmap on the stored value.
+// An ELT's loss for an event it does not list is 0 (its terms still applied, as
+// for any loss): its table is read only where the event's seen bit is set, so a
+// wave fetches only the table lines that hold listed events.  A wave covers 64
+// consecutive events, two seen words per ELT: one load brings those words of 32
+// ELTs (lane 2i + h: word h of ELT i), each ELT's 64-bit mask is then read out
+// uniformly, a wave skips an ELT that lists none of its events, and the table
+// loads of 8 ELTs are issued before their values are added in order.  Those loads
+// are 8-byte buffer loads issued by every lane and for every ELT: a lane whose bit
+// is clear reads past the record (0, no memory access), so nothing branches around
+// a load.
 template <typename V>
 __global__ __launch_bounds__(256) void k_layer_combine_bitmap(const EltDesc *__restrict__ d, int n_elts,
                                                               int32_t catalog, V *__restrict__ comb, double occ_r,
                                                               double occ_l, double *__restrict__ occ,
                                                               uint32_t *__restrict__ bitmap,
                                                               uint32_t *__restrict__ nz, int64_t n_words) {
+    constexpr int kGroup = 8;
     const int64_t e = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int64_t e0 = e - lane;                       // multiple of 64: the wave's first event
+    const int64_t seen_words = (int64_t(catalog) + 31) >> 5;
     bool flag = false, nonzero = false;
-    if (e < catalog) {
+    if (e0 < catalog) {                                // wave-uniform
         double s = 0.0;
-        for (int j = 0; j < n_elts; ++j) {
-            const EltDesc &t = d[j];
-            double x = t.f32 ? double(reinterpret_cast<const float *>(t.dat)[e]) : reinterpret_cast<const double *>(t.dat)[e];
-            if (!t.identity) x = excess(t.fx * x, t.retention, t.limit);
-            s = s + x;
+        for (int jb = 0; jb < n_elts; jb += 32) {
+            const int jl = jb + (lane >> 1);
+            const int64_t wi = (e0 >> 5) + (lane & 1);
+            uint32_t wv = 0u;
+            if (jl < n_elts && wi < seen_words) wv = d[jl].seen[wi];
+            const int nj = n_elts - jb < 32 ? n_elts - jb : 32;
+            for (int i = 0; i < nj; i += kGroup) {   // i + k <= 31
+                uint64_t raw[kGroup];
+#pragma unroll
+                for (int k = 0; k < kGroup; ++k) {
+                    // past the last ELT: the lanes' words are 0, every lane reads past the record
+                    const EltDesc &t = d[jb + i + k < n_elts ? jb + i + k : n_elts - 1];
+                    const uint64_t m = uint64_t(uint32_t(__builtin_amdgcn_readlane(int(wv), 2 * (i + k)))) |
+                                       uint64_t(uint32_t(__builtin_amdgcn_readlane(int(wv), 2 * (i + k) + 1))) << 32;
+                    // binary32 tables: the aligned pair holding the entry (allocated in whole
+                    // pairs); catalog <= 2^28 events keeps byte offsets below 2^31
+                    const uint32_t rec = t.f32 ? (uint32_t(catalog) * 4u + 7u) & ~7u : uint32_t(catalog) * 8u;
+                    const uint32_t at = t.f32 ? (uint32_t(e) * 4u) & ~7u : uint32_t(e) * 8u;
+                    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc(t.dat, 0, int(rec), kBufWord3);
+                    raw[k] = __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(
+                                                              r, (m >> lane) & 1u ? at : 0xFFFFFFF8u, 0, 0));
+                }
+#pragma unroll
+                for (int k = 0; k < kGroup; ++k) {
+                    if (i + k < nj) {
+                        const EltDesc &t = d[jb + i + k];
+                        double v = t.f32 ? double(__builtin_bit_cast(float, uint32_t(raw[k] >> ((e & 1) * 32))))
+                                         : __builtin_bit_cast(double, raw[k]);
+                        if (!t.identity) v = excess(t.fx * v, t.retention, t.limit);
+                        s = s + v;
+                    }
+                }
+            }
         }
-        const V c = V(s);
-        comb[e] = c;
-        nonzero = c != V(0);
-        const double o = excess(double(c), occ_r, occ_l);
-        occ[e] = o;
-        flag = o > 0.0;
+        if (e < catalog) {
+            const V c = V(s);
+            comb[e] = c;
+            nonzero = c != V(0);
+            const double o = excess(double(c), occ_r, occ_l);
+            occ[e] = o;
+            flag = o > 0.0;
+        }
     }
     const uint64_t m = __ballot(flag);
     const uint64_t z = __ballot(nonzero);
-    const int lane = threadIdx.x & 63;
-    const int64_t w0 = (e - lane) >> 5;   // even; n_words is a multiple of 4
+    const int64_t w0 = e0 >> 5;   // even; n_words is a multiple of 4
     if (w0 >= n_words) return;
     if (lane == 0) bitmap[w0] = uint32_t(m);
     if (lane == 1) bitmap[w0 + 1] = uint32_t(m >> 32);

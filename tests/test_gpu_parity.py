@@ -306,6 +306,60 @@ def test_lookups_bit_exact_small(A, S, gpu_ctx, small, placement):
         A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, 0)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_rebuild_after_records_move_to_other_events(A, S, gpu_ctx, precision):
+    """An ELT's table holds values only where its seen bits are set.  The caller moves
+    every record of each ELT (borrowed device records, changed in place) to events it
+    did not list before and rebuilds with ARA_BUILD_TABLES: the events listed before
+    read 0 again.  Catalog lookups equal the oracle's for the new records bit for bit,
+    and the YLT (tiled kernel: a 50,000-event catalog) matches the oracle."""
+    import torch
+    _say(f"rebuild with moved records precision={precision}")
+    rng = np.random.default_rng(20251)
+    C = 50_000
+    ids, offs = synth.yet_poisson(rng, 3_000, 100.0, C)
+    elts = [synth.elt_sparse(rng, 5_000, C, 10.0, 2.0) for _ in range(3)]
+    et = [(1.0, 0.0, INF), (0.8, 2e3, 3e5), (1.0, 0.0, INF)]
+    terms = (5e4, 1e6, 2e5, 5e6)
+    moved = []
+    for e_ids, _ in elts:
+        free = np.setdiff1d(np.arange(C, dtype=np.int32), e_ids)
+        moved.append((rng.permutation(rng.choice(free, size=e_ids.size, replace=False)).astype(np.int32),
+                      rng.lognormal(10.0, 2.0, size=e_ids.size)))
+    an = S.open_analysis(gpu_ctx, ids, offs, C, elts, terms, et, precision)
+    try:
+        assert A.ara_yet_info(an.yet)[2] == 2   # the catalog-binned copy: the tiled kernel runs
+        for h, (m_ids, m_loss) in zip(an.elts, moved):
+            h._keep[0].copy_(torch.from_numpy(m_ids))
+            h._keep[1].copy_(torch.from_numpy(m_loss))
+        A.ara_layer_build(gpu_ctx, an.layer, A.ARA_BUILD_TABLES)
+        w = synth.Workload("moved", ids, offs, C, moved, terms, et, (10.0, 100.0), 0)
+        gross, occ = _catalog_lookup_reference(w, precision_f32=precision == 1)
+        if precision == 1:   # the binary32 combined table, then the occurrence terms in binary64
+            gross = gross.astype(np.float32).astype(np.float64)
+            occ = np.minimum(np.maximum(gross - terms[0], 0.0), terms[1])
+        cat = torch.arange(C, dtype=torch.int32, device="cuda")
+        g = torch.empty(C, dtype=torch.float64, device="cuda")
+        o = torch.empty_like(g)
+        A.ara_lookup(gpu_ctx, an.layer, cat, g, o)
+        ylt = torch.empty(w.n_trials, dtype=torch.float64, device="cuda")
+        A.ara_analyze(gpu_ctx, an.yet, an.layer, 0, w.n_trials, ylt)
+        A.ara_sync(gpu_ctx)
+        g, o = g.cpu().numpy(), o.cpu().numpy()
+        assert np.array_equal(g, gross)
+        assert np.array_equal(o, occ)
+        old = np.setdiff1d(np.concatenate([e_ids for e_ids, _ in elts]), np.concatenate([m for m, _ in moved]))
+        assert old.size > 0 and np.all(g[old] == 0.0)
+        ref = oracle.analyze_workload(w)
+        if precision == 0:
+            assert_ylt_close(ylt.cpu().numpy(), ref, what="moved records")
+        else:
+            bound = 2.0 ** -23 * 1.0001 * ref["gross_total"] + 1e-12 * ref["occ_total"]
+            assert np.all(np.abs(ylt.cpu().numpy() - ref["ylt"]) <= bound)
+    finally:
+        an.release()
+
+
 def test_plain_small_events_mode(A, S, gpu_ctx, small):
     _say("events mode plain small")
     ref = oracle.analyze_workload(small, per_event=True, threads=oracle.max_threads())
