@@ -85,6 +85,9 @@ struct ara_layer {
     int64_t max_pairs;
     LayerTables t;
     uint64_t terms_gen = 0;   // incremented by every ara_layer_set_terms
+    // t.rank, rel16, base32, n_flagged and vals match the current tables: rebuilds
+    // leave them to the first call whose kernel reads them (layer_ranks)
+    mutable bool ranks_ready = false;
 };
 
 static constexpr size_t kStageDoubles = 512;   // 2 x 256 return periods
@@ -762,11 +765,26 @@ extern "C" ara_status ara_elt_release(ara_elt *t) {
 // ------------------------------------------------------------------ layer
 static ara_status layer_enqueue_filter(ara_layer *L) {
     ara_ctx *c = L->ctx;
-    hipError_t e = launch_layer_filter(L->catalog, L->f32, L->terms.occ_retention, L->terms.occ_limit, L->t, c->stream);
+    L->ranks_ready = false;
+    hipError_t e = launch_layer_filter(L->catalog, L->f32, L->terms.occ_retention, L->terms.occ_limit, L->t, c->stream,
+                                       false);
     return e == hipSuccess ? ARA_OK : hip_fail(c, e, "layer filter");
 }
 
-static ara_status layer_enqueue_build(ara_layer *L, int flags) {
+// The filter-based kernels (LDS bitmap, lookups, events, occurrence maxima outside the
+// tiled path, batches) read the layer's ranks and compacted values; the tiled kernel
+// reads its occurrence values only.  Enqueued on the context's stream, before the
+// caller's kernels.
+static ara_status layer_ranks(const ara_layer *L) {
+    if (L->ranks_ready) return ARA_OK;
+    ara_ctx *c = L->ctx;
+    hipError_t e = launch_layer_ranks(L->catalog, L->t, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "layer ranks");
+    L->ranks_ready = true;
+    return ARA_OK;
+}
+
+static ara_status layer_enqueue_build(ara_layer *L, int flags, bool ranks) {
     ara_ctx *c = L->ctx;
     const int n = int(L->elts.size());
     hipError_t e = hipSuccess;
@@ -774,10 +792,13 @@ static ara_status layer_enqueue_build(ara_layer *L, int flags) {
         e = launch_elt_clear(L->d_descs, n, L->catalog, c->stream);
         if (e == hipSuccess) e = launch_elt_scatter(L->d_descs, n, L->max_pairs, L->catalog, c->d_err, c->stream);
     }
+    L->ranks_ready = false;
     if (e == hipSuccess)
         e = launch_layer_tables(L->d_descs, n, L->catalog, L->f32, L->terms.occ_retention, L->terms.occ_limit, L->t,
-                                c->stream);
-    return e == hipSuccess ? ARA_OK : hip_fail(c, e, "layer build");
+                                c->stream, ranks);
+    if (e != hipSuccess) return hip_fail(c, e, "layer build");
+    L->ranks_ready = ranks;
+    return ARA_OK;
 }
 
 static void layer_free(ara_layer *L) {
@@ -836,7 +857,7 @@ extern "C" ara_status ara_layer_create(ara_ctx *c, ara_elt *const *elts, int32_t
         hipError_t e = hipMemcpy(L->d_descs, d.data(), sizeof(EltDesc) * size_t(n_elts), hipMemcpyHostToDevice);
         if (e != hipSuccess) s = hip_fail(c, e, "layer descriptors upload");
     }
-    if (s == ARA_OK) s = layer_enqueue_build(L, 0);
+    if (s == ARA_OK) s = layer_enqueue_build(L, 0, true);
     if (s != ARA_OK) {
         layer_free(L);
         return s;
@@ -859,7 +880,7 @@ extern "C" ara_status ara_layer_set_terms(ara_ctx *c, ara_layer *L, const ara_la
 extern "C" ara_status ara_layer_build(ara_ctx *c, ara_layer *L, int flags) {
     if (!c || !L || L->ctx != c || (flags & ~ARA_BUILD_TABLES)) return ARA_E_INVALID_ARG;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
-    return layer_enqueue_build(L, flags);
+    return layer_enqueue_build(L, flags, false);
 }
 
 extern "C" ara_status ara_layer_stats(ara_ctx *c, const ara_layer *L, int64_t *n_flagged, int32_t *placement,
@@ -872,6 +893,8 @@ extern "C" ara_status ara_layer_stats(ara_ctx *c, const ara_layer *L, int64_t *n
     if (placement) *placement = tl.placement;
     if (lds_bytes) *lds_bytes = int64_t(tl.lds_bytes);
     if (n_flagged) {
+        s = layer_ranks(L);
+        if (s != ARA_OK) return s;
         HIP_OR_RETURN(c, hipMemcpyAsync(c->h_err + 1, L->t.n_flagged, 4, hipMemcpyDeviceToHost, c->stream), "read count");
         HIP_OR_RETURN(c, hipStreamSynchronize(c->stream), "stream synchronize");
         *n_flagged = int64_t(c->h_err[1]);
@@ -957,6 +980,7 @@ extern "C" ara_status ara_analyze(ara_ctx *c, const ara_yet *y, const ara_layer 
     TrialLaunch tl{};
     s = plan_trial(c, L, t1 - t0, y->n_trials ? double(y->n_events) / double(y->n_trials) : 0.0, tl,
                    y->ids16 ? 1 : 0);
+    if (s == ARA_OK && tl.placement != ARA_PLACE_LDS_TILES) s = layer_ranks(L);
     if (s != ARA_OK) return s;
     double *dst = ylt;
     if (mem == ARA_MEM_HOST) {
@@ -998,6 +1022,7 @@ extern "C" ara_status ara_analyze_occ_max(ara_ctx *c, const ara_yet *y, const ar
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     TrialLaunch tl{};
     s = plan_trial(c, L, t1 - t0, 1e9, tl, y->ids16 ? 1 : 0);
+    if (s == ARA_OK && tl.placement != ARA_PLACE_LDS_TILES) s = layer_ranks(L);
     if (s != ARA_OK) return s;
     const int by_lds = tl.lds_bytes > 0 ? std::max(1, int(c->lds_max / int64_t(tl.lds_bytes))) : 8;
     const int64_t grid = std::min<int64_t>(int64_t(c->n_cu) * std::min(8, by_lds), (t1 - t0 + 255) / 256);
@@ -1038,6 +1063,8 @@ extern "C" ara_status ara_analyze_events(ara_ctx *c, const ara_yet *y, const ara
     if (mem != ARA_MEM_HOST && mem != ARA_MEM_DEVICE) return fail(c, ARA_E_INVALID_ARG, "analyze_events: bad memory kind");
     if (t1 == t0) return ARA_OK;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    s = layer_ranks(L);
+    if (s != ARA_OK) return s;
     // number of occurrences in the range, from the device offsets
     HIP_OR_RETURN(c, hipMemcpyAsync(c->h_out, y->offs + t0, 8, hipMemcpyDeviceToHost, c->stream), "read offsets");
     HIP_OR_RETURN(c, hipMemcpyAsync(c->h_out + 1, y->offs + t1, 8, hipMemcpyDeviceToHost, c->stream), "read offsets");
@@ -1090,6 +1117,7 @@ extern "C" ara_status ara_lookup(ara_ctx *c, const ara_layer *L, const int32_t *
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     TrialLaunch tl{};
     ara_status s = plan_trial(c, L, 1 << 20, 1e9, tl);
+    if (s == ARA_OK) s = layer_ranks(L);
     if (s != ARA_OK) return s;
     const int32_t *di = ids;
     double *dg = g, *dout = o;
@@ -1605,6 +1633,7 @@ extern "C" ara_status ara_batch_run(ara_batch *b) {
     if (b->jobs.empty()) return ARA_OK;
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
     ara_status s = batch_refresh_terms(b);
+    for (size_t j = 0; j < b->jobs.size() && s == ARA_OK; ++j) s = layer_ranks(b->jobs[j].layer);
     if (s != ARA_OK) return s;
     if (!b->exec) {
         bool computed = false;

@@ -104,12 +104,16 @@ hipError_t launch_yet_pack(const int32_t *ids, int64_t n_events, uint8_t *packed
 hipError_t launch_elt_clear(const EltDesc *d, int n_elts, int32_t catalog, hipStream_t s);
 hipError_t launch_elt_scatter(const EltDesc *d, int n_elts, int64_t max_pairs, int32_t catalog, uint32_t *err,
                               hipStream_t s);
-// combined table, occurrence filter, ranks, tiles and compacted values of a layer
+// combined table, occurrence values and bitmaps of a layer; with `ranks`, also its
+// ranks, flagged count and compacted values (launch_layer_ranks)
 hipError_t launch_layer_tables(const EltDesc *d, int n_elts, int32_t catalog, bool f32, double occ_r, double occ_l,
-                               const LayerTables &t, hipStream_t s);
+                               const LayerTables &t, hipStream_t s, bool ranks = true);
 // the same from an existing combined table (new occurrence terms)
 hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double occ_l, const LayerTables &t,
-                               hipStream_t s);
+                               hipStream_t s, bool ranks = true);
+// ranks (rank, rel16, base32), flagged count and compacted values from the bitmap and
+// occurrence values: what the filter-based kernels read; the tiled kernel reads occ only
+hipError_t launch_layer_ranks(int32_t catalog, const LayerTables &t, hipStream_t s);
 
 struct TrialLaunch {
     int placement;      // ara_placement (resolved)

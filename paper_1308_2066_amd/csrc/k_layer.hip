@@ -205,8 +205,8 @@ __global__ __launch_bounds__(256) void k_layer_compact(const double *__restrict_
     vals[idx] = occ[e];
 }
 
-// Ranks (with rel16/base32) and the compacted values.
-static hipError_t launch_rank_compact(int32_t catalog, const LayerTables &t, hipStream_t s) {
+// Ranks (with rel16/base32), the flagged count and the compacted values.
+hipError_t launch_layer_ranks(int32_t catalog, const LayerTables &t, hipStream_t s) {
     hipLaunchKernelGGL(k_layer_rank, dim3(1), dim3(1024), 0, s, t.bitmap, t.nblk, t.rank, t.n_flagged, t.rel16,
                        t.base32);
     hipError_t e = hipGetLastError();
@@ -217,7 +217,7 @@ static hipError_t launch_rank_compact(int32_t catalog, const LayerTables &t, hip
 }
 
 hipError_t launch_layer_tables(const EltDesc *d, int n_elts, int32_t catalog, bool f32, double occ_r, double occ_l,
-                               const LayerTables &t, hipStream_t s) {
+                               const LayerTables &t, hipStream_t s, bool ranks) {
     // the bitmap covers nblk*128 event slots = nblk*2 waves; launch whole waves only
     const unsigned blocks = unsigned((int64_t(t.nblk) * kEventsPerBlock + 255) / 256);
     if (f32) {
@@ -228,12 +228,12 @@ hipError_t launch_layer_tables(const EltDesc *d, int n_elts, int32_t catalog, bo
                            (double *)t.comb, occ_r, occ_l, t.occ, t.bitmap, t.nz, int64_t(t.nblk) * 4);
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_rank_compact(catalog, t, s);
+    if (e != hipSuccess || !ranks) return e;
+    return launch_layer_ranks(catalog, t, s);
 }
 
 hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double occ_l, const LayerTables &t,
-                               hipStream_t s) {
+                               hipStream_t s, bool ranks) {
     // the bitmap covers nblk*128 event slots = nblk*2 waves; launch whole waves only
     const unsigned bm_threads_blocks = unsigned((int64_t(t.nblk) * kEventsPerBlock + 255) / 256);
     if (f32) {
@@ -244,8 +244,8 @@ hipError_t launch_layer_filter(int32_t catalog, bool f32, double occ_r, double o
                            catalog, occ_r, occ_l, t.occ, t.bitmap, int64_t(t.nblk) * 4);
     }
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_rank_compact(catalog, t, s);
+    if (e != hipSuccess || !ranks) return e;
+    return launch_layer_ranks(catalog, t, s);
 }
 
 }  // namespace ara

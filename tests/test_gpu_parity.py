@@ -350,12 +350,38 @@ def test_rebuild_after_records_move_to_other_events(A, S, gpu_ctx, precision):
         assert np.array_equal(o, occ)
         old = np.setdiff1d(np.concatenate([e_ids for e_ids, _ in elts]), np.concatenate([m for m, _ in moved]))
         assert old.size > 0 and np.all(g[old] == 0.0)
+
+        def check(got, ref, what):
+            if precision == 0:
+                assert_ylt_close(got, ref, what=what)
+            else:
+                bound = 2.0 ** -23 * 1.0001 * ref["gross_total"] + 1e-12 * ref["occ_total"]
+                assert np.all(np.abs(got - ref["ylt"]) <= bound), what
+
+        def bitmap_ylt():
+            # the LDS-bitmap kernel reads the layer's ranks and compacted values, which a
+            # rebuild leaves to the first call that needs them
+            A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, A.ARA_PLACE_LDS_BITMAP)
+            try:
+                out = torch.full((w.n_trials,), math.nan, dtype=torch.float64, device="cuda")
+                A.ara_analyze(gpu_ctx, an.yet, an.layer, 0, w.n_trials, out)
+                A.ara_sync(gpu_ctx)
+                return out.cpu().numpy()
+            finally:
+                A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, 0)
+
         ref = oracle.analyze_workload(w)
-        if precision == 0:
-            assert_ylt_close(ylt.cpu().numpy(), ref, what="moved records")
-        else:
-            bound = 2.0 ** -23 * 1.0001 * ref["gross_total"] + 1e-12 * ref["occ_total"]
-            assert np.all(np.abs(ylt.cpu().numpy() - ref["ylt"]) <= bound)
+        check(ylt.cpu().numpy(), ref, "moved records, tiled")
+        check(bitmap_ylt(), ref, "moved records, LDS bitmap")
+        assert A.ara_layer_stats(gpu_ctx, an.layer)[0] == int(np.count_nonzero(occ))
+        # new occurrence terms: the filter again, its ranks on first use
+        terms2 = (2e5, 5e5, 1e5, 3e6)
+        A.ara_layer_set_terms(gpu_ctx, an.layer, terms2)
+        w2 = w.with_terms(terms2)
+        ref2 = oracle.analyze_workload(w2)
+        check(bitmap_ylt(), ref2, "new terms, LDS bitmap")
+        occ2 = np.minimum(np.maximum(gross - terms2[0], 0.0), terms2[1])
+        assert A.ara_layer_stats(gpu_ctx, an.layer)[0] == int(np.count_nonzero(occ2))
     finally:
         an.release()
 
