@@ -541,23 +541,25 @@ def bench_serving(args):
     print(json.dumps(out), flush=True)
 
 
-def bench_uneven(args):
+UNEVEN_WORKLOAD = ("{n} analyses: trials log-uniform 1e4-5e5, Poisson(200-2000) events, catalogs 1e5-1e6, "
+                   "1-16 ELTs x 20000 lognormal(10,2); {ev} events")
+
+
+def uneven_batch(ctx, n_analyses, steps):
     """Uneven-instance batching: independent analyses (trials log-uniform 10^4-5x10^5,
     Poisson events per trial with means uniform in 200-2000, catalogs 10^5-10^6, 1-16
     ELTs of 20,000 lognormal(10,2) losses) run as one batch (graph replay) against one
-    ara_analyze per analysis.  Both give identical YLTs."""
+    ara_analyze per analysis.  Both give identical YLTs.  Returns the figures."""
     import torch
     import synth
     from paper_1308_2066_amd import ara, session
 
-    torch.cuda.set_device(0)
-    ctx = ara.ara_ctx_create(0, torch.cuda.current_stream())
     # generated one analysis at a time and kept on the device only (the full set is
     # about 3.5e10 occurrences)
     t = time.time()
     shapes, opened = [], []
     stopped = None
-    for w in synth.iter_uneven_analyses(n=args.analyses):
+    for w in synth.iter_uneven_analyses(n=n_analyses):
         try:
             opened.append(session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts,
                                                 w.layer_terms))
@@ -566,7 +568,7 @@ def bench_uneven(args):
             log(stopped)
             break
         shapes.append((w.n_trials, w.n_events, w.catalog_size, len(w.elts)))
-        if len(opened) % 32 == 0:
+        if len(opened) % 8 == 0:
             log(f"{len(opened)} analyses resident ({time.time() - t:.1f}s)")
     ev = sum(sh[1] for sh in shapes)
     torch.cuda.synchronize()
@@ -594,40 +596,57 @@ def bench_uneven(args):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    ms_b = timed(lambda: ara.ara_batch_run(b), args.steps)
+    ms_b = timed(lambda: ara.ara_batch_run(b), steps)
 
     def run_plain():
         for an, w, o in zip(opened, ws, plain):
             ara.ara_analyze(ctx, an.yet, an.layer, 0, w.n_trials, o)
 
-    ms_p = timed(run_plain, max(1, args.steps // 4))
+    ms_p = timed(run_plain, max(1, steps // 4))
     same = all(o.cpu().numpy().tobytes() == p.cpu().numpy().tobytes() for o, p in zip(outs, plain))
     n_items, grid, epi, graph = ara.ara_batch_info(b)
     id_bytes = [ara.ara_yet_info(an.yet)[2] for an in opened]
     ara.ara_batch_release(b)
     for an in opened:
         an.release()
-    ara.ara_ctx_destroy(ctx)
+    del outs, plain
+    torch.cuda.empty_cache()
     trials = sum(w.n_trials for w in ws)
     alg = 4 * ev + 16 * trials
     moved = sum(bts * w.n_events for bts, w in zip(id_bytes, ws)) + 16 * trials
     log(f"uneven: batched {ms_b:.3f} ms ({n_items} items, {grid} workgroups, {epi} events/item, graph={graph}); "
         f"plain {ms_p:.3f} ms; identical={same}")
+    return {"analyses": len(ws), "analyses_requested": n_analyses, "stopped": stopped, "events": ev,
+            "trials": trials, "ms": ms_b, "steps": steps, "value": ev / (ms_b * 1e-3), "alg_bytes": alg,
+            "moved_bytes": moved, "plain_ms": ms_p, "speedup_vs_plain": ms_p / ms_b, "identical_results": bool(same),
+            "schedule": {"items": n_items, "workgroups": grid, "events_per_item": epi, "graph": bool(graph & 1),
+                         "interleaved": bool(graph & 2)}}
+
+
+def bench_uneven(args):
+    """The uneven-instance batch as the bench line (see uneven_batch)."""
+    import torch
+    from paper_1308_2066_amd import ara
+
+    torch.cuda.set_device(0)
+    ctx = ara.ara_ctx_create(0, torch.cuda.current_stream())
+    u = uneven_batch(ctx, args.analyses, args.steps)
+    ara.ara_ctx_destroy(ctx)
+    ms_b, alg = u["ms"], u["alg_bytes"]
     out = {
-        "metric": f"trial-events·layers/s (uneven-instance batch: {len(ws)} independent analyses)",
-        "value": ev / (ms_b * 1e-3), "unit": "trial-events·layers/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "metric": f"trial-events·layers/s (uneven-instance batch: {u['analyses']} independent analyses)",
+        "value": u["value"], "unit": "trial-events·layers/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
         "ms_per_step": ms_b, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"{len(ws)} analyses: trials log-uniform 1e4-5e5, Poisson(200-2000) events, catalogs "
-                               f"1e5-1e6, 1-16 ELTs x 20000 lognormal(10,2); {ev} events", "analyses": len(ws),
-                   "analyses_requested": args.analyses, "stopped": stopped,
-                   "events": ev, "trials": trials, "parallelism": "1 GPU"},
+        "config": {"workload": UNEVEN_WORKLOAD.format(n=u["analyses"], ev=u["events"]), "analyses": u["analyses"],
+                   "analyses_requested": args.analyses, "stopped": u["stopped"],
+                   "events": u["events"], "trials": u["trials"], "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": alg / (ms_b * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": alg, "moved_bytes": moved},
-        "plain_per_analysis": {"ms_per_step": ms_p, "value": ev / (ms_p * 1e-3)},
-        "speedup_vs_plain": ms_p / ms_b, "identical_results": bool(same),
-        "schedule": {"items": n_items, "workgroups": grid, "events_per_item": epi, "graph": bool(graph & 1),
-                     "interleaved": bool(graph & 2)},
+                     "frac": alg / (ms_b * 1e-3) / 1e9 / HBM_PEAK_GBS, "algorithmic_bytes": alg,
+                     "moved_bytes": u["moved_bytes"]},
+        "plain_per_analysis": {"ms_per_step": u["plain_ms"], "value": u["events"] / (u["plain_ms"] * 1e-3)},
+        "speedup_vs_plain": u["speedup_vs_plain"], "identical_results": u["identical_results"],
+        "schedule": u["schedule"],
     }
     print(json.dumps(out), flush=True)
 
@@ -654,6 +673,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200,
                     help="paper workload: requests of the serving leg per rate (0 = skip the leg)")
     ap.add_argument("--serve-rates", default="50", help="paper workload: arrival rates of the serving leg")
+    ap.add_argument("--uneven-analyses", type=int, default=16,
+                    help="paper workload: analyses of the uneven-instance batch leg (0 = skip the leg)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (for counter calibration)")
     ap.add_argument("--derive-traffic", nargs=2, metavar=("FETCH", "WRITE"),
@@ -903,6 +924,15 @@ def main():
                               [float(x) for x in args.serve_rates.split(",")], args.serve_requests)
         h.release()
         serving = {"workload": SERVING_WORKLOAD, "rates": lines}
+    uneven = None
+    if args.uneven_analyses > 0:
+        u = uneven_batch(ctx, args.uneven_analyses, 10)
+        uneven = {"workload": UNEVEN_WORKLOAD.format(n=u["analyses"], ev=u["events"]),
+                  "ms_batched": u["ms"], "ms_plain": u["plain_ms"], "speedup_vs_plain": u["speedup_vs_plain"],
+                  "value": u["value"], "identical_results": u["identical_results"], "analyses": u["analyses"],
+                  "events": u["events"], "schedule": u["schedule"],
+                  "what": "independent analyses of different YETs, catalogs and trial counts: one ara_batch_run "
+                          "(graph replay) against one ara_analyze per analysis, YLTs compared bit for bit"}
     ara.ara_ctx_destroy(ctx)
 
     cpu = cpu_baseline(w, args.cpu_seconds) if args.cpu_seconds > 0 else None
@@ -947,6 +977,7 @@ def main():
             "achieved_gbs": alg2 / (k2 * 1e-3) / 1e9, "frac": alg2 / (k2 * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "dtype": "f64 arithmetic, f32 tables" if other == ara.ARA_F32 else "f64"},
         "serving": serving,
+        "uneven_batch": uneven,
     }
     print(json.dumps(out), flush=True)
 
