@@ -386,6 +386,53 @@ def test_rebuild_after_records_move_to_other_events(A, S, gpu_ctx, precision):
         an.release()
 
 
+def test_layer_of_40_mixed_precision_elts(A, S, gpu_ctx):
+    """A layer of 40 ELTs (more than the 32 whose seen bits one load brings in) whose
+    tables alternate binary64 and binary32, half of them with financial terms.  A
+    binary32 table stores each loss rounded to binary32, so the oracle takes those
+    ELTs' losses rounded beforehand: the combined table (binary64, as the layer mixes
+    precisions) then equals it bit for bit, and the YLT (tiled kernel) matches."""
+    import torch
+    from paper_1308_2066_amd import ara
+    _say("layer of 40 ELTs, mixed precision")
+    rng = np.random.default_rng(40_32)
+    C = 50_000
+    ids, offs = synth.yet_poisson(rng, 2_000, 100.0, C)
+    elts, et, precs = [], [], []
+    for j in range(40):
+        e_ids, e_loss = synth.elt_sparse(rng, 3_000, C, 10.0, 2.0)
+        elts.append((e_ids, e_loss))
+        et.append((0.9, 1e3, 4e5) if j % 4 >= 2 else (1.0, 0.0, INF))
+        precs.append(ara.ARA_F32 if j % 2 else ara.ARA_F64)
+    terms = (5e4, 1e6, 2e5, 5e6)
+    yet = ara.ara_yet_create(gpu_ctx, torch.from_numpy(ids).cuda(), torch.from_numpy(offs).cuda(), C)
+    handles = [ara.ara_elt_create(gpu_ctx, torch.from_numpy(e_ids).cuda(), torch.from_numpy(e_loss).cuda(), C,
+                                  terms=t, precision=pr)
+               for (e_ids, e_loss), t, pr in zip(elts, et, precs)]
+    layer = ara.ara_layer_create(gpu_ctx, handles, C, terms)
+    try:
+        assert A.ara_yet_info(yet)[2] == 2   # the catalog-binned copy: the tiled kernel runs
+        rounded = [(e_ids, e_loss.astype(np.float32).astype(np.float64) if pr == ara.ARA_F32 else e_loss)
+                   for (e_ids, e_loss), pr in zip(elts, precs)]
+        w = synth.Workload("mixed-40", ids, offs, C, rounded, terms, et, (10.0, 100.0), 0)
+        gross, occ = _catalog_lookup_reference(w)
+        cat = torch.arange(C, dtype=torch.int32, device="cuda")
+        g = torch.empty(C, dtype=torch.float64, device="cuda")
+        o = torch.empty_like(g)
+        A.ara_lookup(gpu_ctx, layer, cat, g, o)
+        ylt = torch.full((w.n_trials,), math.nan, dtype=torch.float64, device="cuda")
+        A.ara_analyze(gpu_ctx, yet, layer, 0, w.n_trials, ylt)
+        A.ara_sync(gpu_ctx)
+        assert np.array_equal(g.cpu().numpy(), gross)
+        assert np.array_equal(o.cpu().numpy(), occ)
+        assert_ylt_close(ylt.cpu().numpy(), oracle.analyze_workload(w), what="40 mixed ELTs")
+    finally:
+        ara.ara_layer_release(layer)
+        for h in handles:
+            ara.ara_elt_release(h)
+        ara.ara_yet_release(yet)
+
+
 def test_plain_small_events_mode(A, S, gpu_ctx, small):
     _say("events mode plain small")
     ref = oracle.analyze_workload(small, per_event=True, threads=oracle.max_threads())
