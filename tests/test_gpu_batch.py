@@ -322,6 +322,44 @@ def test_set_terms_between_batch_runs(A, S, gpu_ctx):
         a2.release()
 
 
+def test_rebuilt_layer_in_lds_bitmap_batch(A, S, gpu_ctx):
+    """Jobs on the LDS-bitmap placement read their layer's ranks and compacted values,
+    which a rebuild (ara_layer_build, ara_layer_set_terms) leaves to the first call that
+    needs them: ara_batch_run builds them before its kernels, so each run equals a
+    plain launch of the same placement after the same rebuild, bit for bit."""
+    import torch
+    big = synth.workload_paper_scale(n_trials=5_000, catalog=200_000, n_elts=4, nnz=30_000)
+    A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, A.ARA_PLACE_LDS_BITMAP)
+    an = S.open_analysis(gpu_ctx, big.event_ids, big.trial_offsets, big.catalog_size, big.elts,
+                         (1e5, 5e6, 1e8, math.inf))
+    try:
+        specs = [(0, big.n_trials), (123, 3_456)]
+        outs = [torch.full((t1 - t0,), math.nan, dtype=torch.float64, device="cuda") for t0, t1 in specs]
+        b = A.ara_batch_create(gpu_ctx, [(an.yet, an.layer, t0, t1, o) for (t0, t1), o in zip(specs, outs)])
+        try:
+            steps = [None, ("terms", (3e5, 2e6, 1e6, 4e6)), ("build", None), ("terms", (0.0, math.inf, 0.0, math.inf))]
+            for rep, step in enumerate(steps):
+                _say(f"LDS-bitmap batch after rebuild {rep}")
+                if step is not None and step[0] == "terms":
+                    A.ara_layer_set_terms(gpu_ctx, an.layer, step[1])
+                elif step is not None:
+                    A.ara_layer_build(gpu_ctx, an.layer, A.ARA_BUILD_TABLES)
+                for o in outs:
+                    o.fill_(math.nan)
+                A.ara_batch_run(b)
+                A.ara_sync(gpu_ctx)
+                got = [o.cpu().numpy() for o in outs]
+                for k, ((t0, t1), g) in enumerate(zip(specs, got)):
+                    assert g.tobytes() == _plain(A, gpu_ctx, an.yet, an.layer, t0, t1).tobytes(), (rep, k)
+            ref = oracle.analyze_workload(big.with_terms((0.0, math.inf, 0.0, math.inf)), threads=oracle.max_threads())
+            assert np.all(np.abs(got[0] - ref["ylt"]) <= 1e-12 * np.maximum(np.abs(ref["ylt"]), ref["occ_total"]))
+        finally:
+            A.ara_batch_release(b)
+    finally:
+        an.release()
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_PLACEMENT, 0)
+
+
 def test_tuning_cache_round_trip(A, S, gpu_ctx, tmp_path):
     """A batch shape tuned on one context, its schedule saved to a file and loaded into
     a fresh context: the fresh context's batch of that shape takes the saved schedule
