@@ -270,8 +270,11 @@ ara_status ara_layer_set_terms(ara_ctx *ctx, ara_layer *layer, const ara_layer_t
 
 /* Re-enqueues the layer's table builds: with ARA_BUILD_TABLES, each member ELT's
  * direct access table from its (resident) records, then the combined table and
- * the occurrence filter.  Asynchronous; record errors surface at the next
- * blocking call.  Errors: ARA_E_INVALID_ARG, ARA_E_DEVICE. */
+ * the occurrence filter.  The filter's ranks and compacted values, which only the
+ * filter-based placements, lookups, event outputs and batches read, are enqueued by
+ * the first such call (the tiled placement never needs them); ara_layer_set_terms
+ * does the same.  Asynchronous; record errors surface at the next blocking call.
+ * Errors: ARA_E_INVALID_ARG, ARA_E_DEVICE. */
 ara_status ara_layer_build(ara_ctx *ctx, ara_layer *layer, int flags);
 
 /* Blocking.  Number of catalog events whose occurrence-net loss is nonzero under
