@@ -433,6 +433,59 @@ def test_layer_of_40_mixed_precision_elts(A, S, gpu_ctx):
         ara.ara_yet_release(yet)
 
 
+def test_largest_catalog(A, S, gpu_ctx):
+    """The largest catalog the library accepts, 2^28 events (byte offsets into its
+    binary64 tables reach 2^31; no packed or binned YET copy, so the global-table
+    kernel runs): events at both ends of the catalog, a binary32 ELT beside binary64
+    ones.  Lookups bit-exact with the oracle, the YLT within the bound; a catalog of
+    one event more is rejected."""
+    import torch
+    from paper_1308_2066_amd import ara
+    _say("largest catalog, 2^28 events")
+    C = 1 << 28
+    rng = np.random.default_rng(1 << 28)
+    hot = np.unique(np.concatenate([np.arange(C - 3000, C), np.arange(0, 3000),
+                                    rng.choice(C, 6000, replace=False)])).astype(np.int32)
+    precs = [ara.ARA_F64, ara.ARA_F32, ara.ARA_F64]
+    elts, rounded = [], []
+    for pr in precs:
+        ids = np.unique(np.concatenate([[0, C - 2, C - 1], rng.choice(hot, 2000, replace=False)])).astype(np.int32)
+        loss = rng.lognormal(10.0, 2.0, ids.size)
+        elts.append((ids, loss))
+        rounded.append((ids, loss.astype(np.float32).astype(np.float64) if pr == ara.ARA_F32 else loss))
+    counts = rng.poisson(40.0, 300).astype(np.int64)
+    offs = np.zeros(counts.size + 1, np.int64)
+    np.cumsum(counts, out=offs[1:])
+    ev = rng.choice(hot, int(offs[-1])).astype(np.int32)
+    terms = (5e3, 1e6, 2e4, 5e6)
+    with pytest.raises(A.AraError) as e:
+        A.ara_elt_create(gpu_ctx, torch.from_numpy(elts[0][0]).cuda(), torch.from_numpy(elts[0][1]).cuda(), C + 1)
+    assert e.value.status == A.ARA_E_INVALID_ARG
+    yet = ara.ara_yet_create(gpu_ctx, torch.from_numpy(ev).cuda(), torch.from_numpy(offs).cuda(), C)
+    handles = [ara.ara_elt_create(gpu_ctx, torch.from_numpy(i).cuda(), torch.from_numpy(l).cuda(), C, precision=pr)
+               for (i, l), pr in zip(elts, precs)]
+    layer = ara.ara_layer_create(gpu_ctx, handles, C, terms)
+    try:
+        assert A.ara_yet_info(yet)[2] == 4   # int32 IDs only
+        q = torch.from_numpy(hot).cuda()
+        g = torch.full((hot.size,), math.nan, dtype=torch.float64, device="cuda")
+        o = torch.full_like(g, math.nan)
+        A.ara_lookup(gpu_ctx, layer, q, g, o)
+        ylt = torch.full((counts.size,), math.nan, dtype=torch.float64, device="cuda")
+        A.ara_analyze(gpu_ctx, yet, layer, 0, counts.size, ylt)
+        A.ara_sync(gpu_ctx)
+        look = oracle.analyze(hot, np.array([0, hot.size], np.int64), C, rounded, terms, per_event=True)
+        assert np.array_equal(g.cpu().numpy(), look["gross"])
+        assert np.array_equal(o.cpu().numpy(), look["occ"])
+        w = synth.Workload("largest-catalog", ev, offs, C, rounded, terms, None, (10.0, 100.0), 0)
+        assert_ylt_close(ylt.cpu().numpy(), oracle.analyze_workload(w), what="2^28-event catalog")
+    finally:
+        ara.ara_layer_release(layer)
+        for h in handles:
+            ara.ara_elt_release(h)
+        ara.ara_yet_release(yet)
+
+
 def test_plain_small_events_mode(A, S, gpu_ctx, small):
     _say("events mode plain small")
     ref = oracle.analyze_workload(small, per_event=True, threads=oracle.max_threads())
