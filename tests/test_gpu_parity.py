@@ -386,6 +386,49 @@ def test_rebuild_after_records_move_to_other_events(A, S, gpu_ctx, precision):
         an.release()
 
 
+def test_rebuild_detects_records_made_invalid_in_place(A, S, gpu_ctx, small):
+    """A rebuild re-checks the records: an event listed twice, a negative loss or an ID
+    outside the catalog, written into an ELT's borrowed device records, is reported by
+    the next blocking call; restoring the records and rebuilding gives the first
+    lookups and YLT again, bit for bit (every build starts from cleared seen bits)."""
+    import torch
+    _say("rebuild with records made invalid in place")
+    an = S.open_analysis(gpu_ctx, small.event_ids, small.trial_offsets, small.catalog_size, small.elts,
+                         small.layer_terms)
+    try:
+        cat = torch.arange(small.catalog_size, dtype=torch.int32, device="cuda")
+
+        def outputs():
+            g = torch.empty(small.catalog_size, dtype=torch.float64, device="cuda")
+            ylt = torch.empty(small.n_trials, dtype=torch.float64, device="cuda")
+            A.ara_lookup(gpu_ctx, an.layer, cat, g, None)
+            A.ara_analyze(gpu_ctx, an.yet, an.layer, 0, small.n_trials, ylt)
+            A.ara_sync(gpu_ctx)
+            return g.cpu().numpy().tobytes(), ylt.cpu().numpy().tobytes()
+
+        first = outputs()
+        ids, losses = an.elts[2]._keep
+        id_copy, loss_copy = ids.clone(), losses.clone()
+        for what, code in [("dup", A.ARA_E_DUP_EVENT), ("loss", A.ARA_E_BAD_LOSS),
+                           ("range", A.ARA_E_EVENT_ID_RANGE)]:
+            if what == "dup":
+                ids[7] = ids[1500]
+            elif what == "loss":
+                losses[11] = -1.0
+            else:
+                ids[13] = small.catalog_size
+            A.ara_layer_build(gpu_ctx, an.layer, A.ARA_BUILD_TABLES)
+            with pytest.raises(A.AraError) as e:
+                A.ara_sync(gpu_ctx)
+            assert e.value.status == code, what
+            ids.copy_(id_copy)
+            losses.copy_(loss_copy)
+            A.ara_layer_build(gpu_ctx, an.layer, A.ARA_BUILD_TABLES)
+            assert outputs() == first, what
+    finally:
+        an.release()
+
+
 def test_layer_of_40_mixed_precision_elts(A, S, gpu_ctx):
     """A layer of 40 ELTs (more than the 32 whose seen bits one load brings in) whose
     tables alternate binary64 and binary32, half of them with financial terms.  A
