@@ -787,12 +787,17 @@ def main():
     # sort skips its passes)
     y_distinct = torch.from_numpy(np.random.default_rng(7).lognormal(15.0, 2.0, size=w.n_trials)).cuda()
 
-    def run_steps(layer, steps, warmup, sort_input=None, on_yet=None):
+    def run_steps(layer, steps, warmup, sort_input=None, on_yet=None, call_ms=None):
         """steps x (table build, trial kernel, sort + PML/TVaR to the host): wall ms per
-        step and the trial kernel's average ms (HIP events on its stream)."""
+        step and the trial kernel's duration per step, from the HIP events the library
+        attaches to the kernel's launch on its stream (ARA_OPT_KERNEL_TIMING; read after
+        the step's own blocking risk call).  call_ms, if a list, also gets the time
+        between torch events recorded around the ara_analyze call, which adds any wait
+        of the GPU for that call's launch."""
         y_handle = an.yet if on_yet is None else on_yet
         e0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
         e1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        km = []
 
         def step(i=None):
             ara.ara_layer_build(ctx, layer, ara.ARA_BUILD_TABLES)
@@ -801,8 +806,12 @@ def main():
             ara.ara_analyze(ctx, y_handle, layer, 0, w.n_trials, ylt)
             if i is not None:
                 e1[i].record(stream)
-            return ara.ara_risk_measures(ctx, ylt if sort_input is None else sort_input, rps, ws)
+            r = ara.ara_risk_measures(ctx, ylt if sort_input is None else sort_input, rps, ws)
+            if i is not None:
+                km.append(ara.ara_kernel_ms(ctx))
+            return r
 
+        ara.ara_set_option(ctx, ara.ARA_OPT_KERNEL_TIMING, 1)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
@@ -811,13 +820,18 @@ def main():
             res = step(i)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
-        km = [e0[i].elapsed_time(e1[i]) for i in range(steps)]
+        ara.ara_set_option(ctx, ara.ARA_OPT_KERNEL_TIMING, 0)
+        if call_ms is not None:
+            call_ms.extend(e0[i].elapsed_time(e1[i]) for i in range(steps))
         return ms, km, res
 
-    ms_step, kern_ms, (pml, tvar) = run_steps(an.layer, args.steps, args.warmup)
+    call_ms = []
+    ms_step, kern_ms, (pml, tvar) = run_steps(an.layer, args.steps, args.warmup, call_ms=call_ms)
     k_avg = float(np.mean(kern_ms))
+    k_call = float(np.mean(call_ms))
     saturated = bool(torch.all(ylt == float(w.layer_terms[3])).item())
     log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; trial kernel avg {k_avg:.4f} ms "
+        f"({k_call:.4f} ms between events around the call) "
         f"(min {min(kern_ms):.4f}, max {max(kern_ms):.4f}); PML {pml.tolist()} TVaR {tvar.tolist()}")
 
     nblk = (w.catalog_size + 127) // 128
@@ -957,7 +971,11 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel,
-                     "kernel_ms": k_avg, "algorithmic_bytes": alg_bytes, "yet_id_bytes": id_bytes,
+                     "kernel_ms": k_avg, "kernel_ms_around_call": k_call,
+                     "kernel_timing": "HIP events attached to the trial kernel's launch on its stream "
+                                      "(ARA_OPT_KERNEL_TIMING), mean over the timed steps; "
+                                      "kernel_ms_around_call: torch events around the ara_analyze call",
+                     "algorithmic_bytes": alg_bytes, "yet_id_bytes": id_bytes,
                      "moved_bytes": moved_bytes, "moved_gbs": moved_gbs, "moved_frac": moved_gbs / HBM_PEAK_GBS,
                      "traffic_source": traffic_note},
         "cpu_baseline": cpu,

@@ -111,10 +111,15 @@ typedef enum ara_option {
                                    trial's values in time order (the sequential sum)               */
     ARA_OPT_YET_BINNING = 6,    /* 1 (default): YETs created later also keep a catalog-binned copy
                                    where it applies (see ara_yet_create); 0: never                 */
-    ARA_OPT_YET_RUN_BYTES = 7   /* bytes per run start of binned copies built later: 4 (default), or
+    ARA_OPT_YET_RUN_BYTES = 7,  /* bytes per run start of binned copies built later: 4 (default), or
                                    3 (with at most 64 bins and fewer than 2^31 occurrences; 4 when
                                    a bin holds 2^24 occurrences or more): a quarter less memory for
                                    the run starts, about 3% more time in the tiled kernel          */
+    ARA_OPT_KERNEL_TIMING = 8   /* 1: ara_analyze times its trial kernel with a pair of HIP events
+                                   (for the tiled kernel, events attached to its launch: the
+                                   start of its first dispatch and the end of its last; for the
+                                   others, recorded on the stream just around the launches);
+                                   ara_kernel_ms reads it.  0 (default): no timing             */
 } ara_option;
 
 typedef struct ara_ctx ara_ctx;
@@ -163,6 +168,11 @@ ara_status ara_set_option(ara_ctx *ctx, int option, int64_t value);
  * the first device-detected input error: ARA_E_EVENT_ID_RANGE, ARA_E_BAD_OFFSETS,
  * ARA_E_BAD_LOSS or ARA_E_DUP_EVENT.  ARA_E_DEVICE on a HIP runtime error. */
 ara_status ara_sync(ara_ctx *ctx);
+
+/* Blocking.  *ms = the duration of the trial kernel of the last ara_analyze call timed
+ * under ARA_OPT_KERNEL_TIMING (waits for it).  ARA_E_INVALID_ARG when no call was
+ * timed since the option was set; ARA_E_DEVICE on a HIP runtime error. */
+ara_status ara_kernel_ms(ara_ctx *ctx, float *ms);
 
 /* ---------------------------------------------------------------- Year Event Table
  * Creates a YET handle (Section II-A item 1; in memory as the paper's event-ID and

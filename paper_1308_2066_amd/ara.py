@@ -61,6 +61,7 @@ ARA_OPT_YET_PACKING = 4
 ARA_OPT_TRIAL_MODE = 5
 ARA_OPT_YET_BINNING = 6
 ARA_OPT_YET_RUN_BYTES = 7
+ARA_OPT_KERNEL_TIMING = 8
 
 ARA_BUILD_TABLES = 1
 
@@ -110,6 +111,7 @@ _SIGS = {
     "ara_ctx_set_stream": (_ST, [_P, _P]),
     "ara_set_option": (_ST, [_P, ctypes.c_int, _I64]),
     "ara_sync": (_ST, [_P]),
+    "ara_kernel_ms": (_ST, [_P, ctypes.POINTER(ctypes.c_float)]),
     "ara_yet_create": (_ST, [_P, _P, _I64, _P, _I64, _I32, ctypes.c_int, ctypes.POINTER(_P)]),
     "ara_yet_release": (_ST, [_P]),
     "ara_yet_info": (_ST, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I32)]),
@@ -268,6 +270,13 @@ def ara_set_option(ctx: Ctx, option: int, value: int):
 
 def ara_sync(ctx: Ctx):
     _check(_lib.ara_sync(ctx.ptr), ctx, "ara_sync")
+
+
+def ara_kernel_ms(ctx: Ctx) -> float:
+    """Duration of the last ara_analyze trial kernel timed under ARA_OPT_KERNEL_TIMING."""
+    ms = ctypes.c_float()
+    _check(_lib.ara_kernel_ms(ctx.ptr, ctypes.byref(ms)), ctx, "ara_kernel_ms")
+    return float(ms.value)
 
 
 def ara_yet_create(ctx: Ctx, event_ids, trial_offsets, catalog_size: int) -> Yet:

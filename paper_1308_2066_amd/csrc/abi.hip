@@ -37,6 +37,9 @@ struct ara_ctx {
     int yet_binning = 1;             // keep a catalog-binned copy of YET IDs where it applies
     int yet_run_bytes = 4;           // bytes per run start of the binned copy (3 or 4)
     int trial_mode = 0;              // 0 = by trial length, 1 = wave per trial, 2 = lane per trial
+    hipEvent_t k_start = nullptr;    // ARA_OPT_KERNEL_TIMING: the last timed trial kernel's events
+    hipEvent_t k_stop = nullptr;
+    bool timed = false;              // a launch was timed since the option was set
     std::map<std::string, std::pair<int64_t, bool>> tuned;   // batch shape -> (events per item, interleave)
     int live = 0;                    // handles alive on this context
     std::string msg;
@@ -386,6 +389,8 @@ extern "C" ara_status ara_ctx_destroy(ara_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     dev_free(c->d_err);   // with d_out
+    if (c->k_start) (void)hipEventDestroy(c->k_start);
+    if (c->k_stop) (void)hipEventDestroy(c->k_stop);
     if (c->h_err) (void)hipHostFree(c->h_err);   // with h_out
     if (c->h_plan) (void)hipHostFree(c->h_plan);
     delete c;
@@ -429,9 +434,32 @@ extern "C" ara_status ara_set_option(ara_ctx *c, int option, int64_t v) {
         if (v != 3 && v != 4) return fail(c, ARA_E_INVALID_ARG, "bad run start size %lld", (long long)v);
         c->yet_run_bytes = int(v);
         return ARA_OK;
+    case ARA_OPT_KERNEL_TIMING:
+        if (v != 0 && v != 1) return fail(c, ARA_E_INVALID_ARG, "bad timing flag %lld", (long long)v);
+        c->timed = false;
+        if (v == 0) {
+            (void)hipStreamSynchronize(c->stream);
+            if (c->k_start) (void)hipEventDestroy(c->k_start);
+            if (c->k_stop) (void)hipEventDestroy(c->k_stop);
+            c->k_start = c->k_stop = nullptr;
+            return ARA_OK;
+        }
+        HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+        if (!c->k_start) HIP_OR_RETURN(c, hipEventCreate(&c->k_start), "timing event");
+        if (!c->k_stop) HIP_OR_RETURN(c, hipEventCreate(&c->k_stop), "timing event");
+        return ARA_OK;
     default:
         return fail(c, ARA_E_INVALID_ARG, "unknown option %d", option);
     }
+}
+
+extern "C" ara_status ara_kernel_ms(ara_ctx *c, float *ms) {
+    if (!c || !ms) return ARA_E_INVALID_ARG;
+    if (!c->k_start || !c->timed) return fail(c, ARA_E_INVALID_ARG, "no trial kernel timed since timing was set");
+    HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
+    HIP_OR_RETURN(c, hipEventSynchronize(c->k_stop), "timing event");
+    HIP_OR_RETURN(c, hipEventElapsedTime(ms, c->k_start, c->k_stop), "timing event");
+    return ARA_OK;
 }
 
 extern "C" ara_status ara_sync(ara_ctx *c) {
@@ -989,17 +1017,23 @@ extern "C" ara_status ara_analyze(ara_ctx *c, const ara_yet *y, const ara_layer 
     }
     // trial indices inside a launch are 32-bit: split very long ranges
     constexpr int64_t kMaxTrialsPerLaunch = int64_t(1) << 30;
-    hipError_t e = hipSuccess;
+    const bool timing = c->k_start != nullptr, tiles = tl.placement == ARA_PLACE_LDS_TILES;
+    hipError_t e = timing && !tiles ? hipEventRecord(c->k_start, c->stream) : hipSuccess;
     for (int64_t tb = t0; tb < t1 && e == hipSuccess; tb += kMaxTrialsPerLaunch) {
         const int64_t te = std::min(t1, tb + kMaxTrialsPerLaunch);
-        if (tl.placement == ARA_PLACE_LDS_TILES) {
-            e = launch_trial_tiled(tiled_args(y, L, tb, te, dst + (tb - t0), tl.grid), tl.grid, c->stream);
+        if (tiles) {
+            // timed: events attached to the first launch's start and the last one's end
+            const bool first = tb == t0, last = te == t1;
+            e = launch_trial_tiled(tiled_args(y, L, tb, te, dst + (tb - t0), tl.grid), tl.grid, c->stream, false,
+                                   timing && first ? c->k_start : nullptr, timing && last ? c->k_stop : nullptr);
             continue;
         }
         TrialArgs a = trial_args(y, L, tb, te, dst + (tb - t0));
         a.qcap = tl.qcap;
         e = launch_trial_ylt(a, tl, c->stream);
     }
+    if (e == hipSuccess && timing && !tiles) e = hipEventRecord(c->k_stop, c->stream);
+    if (e == hipSuccess && timing) c->timed = true;
     if (e != hipSuccess) s = hip_fail(c, e, "trial kernel");
     if (s == ARA_OK && mem == ARA_MEM_HOST) {
         e = hipMemcpyAsync(ylt, dst, size_t(t1 - t0) * 8, hipMemcpyDeviceToHost, c->stream);

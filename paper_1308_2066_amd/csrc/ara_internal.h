@@ -240,8 +240,10 @@ struct TiledArgs {
     double agg_r, agg_l;
     double *ylt;
 };
-// occ_max: each trial's largest occurrence-net loss into a.ylt instead of the YLT
-hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s, bool occ_max = false);
+// occ_max: each trial's largest occurrence-net loss into a.ylt instead of the YLT;
+// start/stop (or null): HIP events attached to the launch (its dispatch's start and end)
+hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s, bool occ_max = false,
+                              hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // A pass of the tiled kernel as a work item: analysis `job`, trials [t0, t1).
 struct TiledItem {
     int32_t job;

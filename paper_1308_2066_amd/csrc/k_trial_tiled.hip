@@ -23,6 +23,8 @@
 //   while the previous bin is added, and written to LDS between two barriers.
 // A trial's P is added in a fixed order (bins, then positions): the same bits on
 // every run.  The per-trial sums live in LDS (one binary64 per trial of the wave).
+#include <hip/hip_ext.h>
+
 #include "trial_common.h"
 
 namespace ara {
@@ -331,14 +333,15 @@ hipError_t launch_trial_tiled_items(const TiledArgs *jobs, const TiledItem *item
     return hipGetLastError();
 }
 
-hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s, bool occ_max) {
+hipError_t launch_trial_tiled(const TiledArgs &a, int grid, hipStream_t s, bool occ_max, hipEvent_t start,
+                              hipEvent_t stop) {
     const dim3 g(grid), b(kTiledWaves * 64);
     if (a.boff24) {
-        if (occ_max) hipLaunchKernelGGL((k_trial_tiled<true, true>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_trial_tiled<false, true>), g, b, 0, s, a);
+        if (occ_max) hipExtLaunchKernelGGL((k_trial_tiled<true, true>), g, b, 0, s, start, stop, 0, a);
+        else hipExtLaunchKernelGGL((k_trial_tiled<false, true>), g, b, 0, s, start, stop, 0, a);
     } else {
-        if (occ_max) hipLaunchKernelGGL((k_trial_tiled<true, false>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_trial_tiled<false, false>), g, b, 0, s, a);
+        if (occ_max) hipExtLaunchKernelGGL((k_trial_tiled<true, false>), g, b, 0, s, start, stop, 0, a);
+        else hipExtLaunchKernelGGL((k_trial_tiled<false, false>), g, b, 0, s, start, stop, 0, a);
     }
     return hipGetLastError();
 }

@@ -529,6 +529,49 @@ def test_largest_catalog(A, S, gpu_ctx):
         ara.ara_yet_release(yet)
 
 
+def test_kernel_timing(A, S, gpu_ctx, small):
+    """ARA_OPT_KERNEL_TIMING: ara_kernel_ms reports the last timed ara_analyze's trial
+    kernel, for the tiled kernel (events attached to its launch) and another placement
+    (events around its launches): positive, and no longer than torch events recorded
+    around the whole call; without the option it is an error."""
+    import torch
+    _say("kernel timing")
+    rng = np.random.default_rng(77)
+    C = 50_000
+    ids, offs = synth.yet_poisson(rng, 4_000, 200.0, C)
+    elts = [synth.elt_sparse(rng, 5_000, C, 10.0, 2.0) for _ in range(3)]
+    tiled = S.open_analysis(gpu_ctx, ids, offs, C, elts, (5e4, 1e6, 2e5, 5e6))
+    plain = S.open_analysis(gpu_ctx, small.event_ids, small.trial_offsets, small.catalog_size, small.elts,
+                            small.layer_terms)
+    stream = torch.cuda.current_stream()
+    try:
+        assert A.ara_yet_info(tiled.yet)[2] == 2
+        with pytest.raises(A.AraError) as e:
+            A.ara_kernel_ms(gpu_ctx)
+        assert e.value.status == A.ARA_E_INVALID_ARG
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_KERNEL_TIMING, 1)
+        with pytest.raises(A.AraError):
+            A.ara_kernel_ms(gpu_ctx)          # nothing timed yet
+        for an in (tiled, plain):
+            n = an.n_trials
+            ylt = torch.empty(n, dtype=torch.float64, device="cuda")
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                A.ara_analyze(gpu_ctx, an.yet, an.layer, 0, n, ylt)
+                e1.record(stream)
+                A.ara_sync(gpu_ctx)
+                ms = A.ara_kernel_ms(gpu_ctx)
+                assert 0.0 < ms <= e0.elapsed_time(e1) * 1.001 + 1e-3, (ms, e0.elapsed_time(e1))
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_KERNEL_TIMING, 0)
+        with pytest.raises(A.AraError):
+            A.ara_kernel_ms(gpu_ctx)
+    finally:
+        A.ara_set_option(gpu_ctx, A.ARA_OPT_KERNEL_TIMING, 0)
+        tiled.release()
+        plain.release()
+
+
 def test_plain_small_events_mode(A, S, gpu_ctx, small):
     _say("events mode plain small")
     ref = oracle.analyze_workload(small, per_event=True, threads=oracle.max_threads())
