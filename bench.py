@@ -654,8 +654,10 @@ def bench_uneven(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    # the GPU's clocks take some tens of steps after the setup's idle spells to settle:
+    # 30 untimed steps, then 100 timed (about 60 ms at paper scale)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", choices=["paper", "small", "portfolio", "serving", "uneven", "events"], default="paper",
                     help="portfolio: one YET x 64 layers, batched launch against per-layer launches; "
                          "serving: pricing requests with Poisson arrivals, server against per-request launches")
@@ -787,52 +789,36 @@ def main():
     # sort skips its passes)
     y_distinct = torch.from_numpy(np.random.default_rng(7).lognormal(15.0, 2.0, size=w.n_trials)).cuda()
 
-    def run_steps(layer, steps, warmup, sort_input=None, on_yet=None, call_ms=None):
+    def run_steps(layer, steps, warmup, sort_input=None, on_yet=None):
         """steps x (table build, trial kernel, sort + PML/TVaR to the host): wall ms per
-        step and the trial kernel's duration per step, from the HIP events the library
-        attaches to the kernel's launch on its stream (ARA_OPT_KERNEL_TIMING; read after
-        the step's own blocking risk call).  call_ms, if a list, also gets the time
-        between torch events recorded around the ara_analyze call, which adds any wait
-        of the GPU for that call's launch."""
+        step, and the trial kernel's mean duration over the timed steps from the HIP
+        events the library attaches to the kernel's launch on its stream
+        (ARA_OPT_KERNEL_TIMING, a ring of one pair per timed step, read once after the
+        loop, so nothing runs on the host between the steps' calls)."""
         y_handle = an.yet if on_yet is None else on_yet
-        e0 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-        e1 = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-        km = []
 
-        def step(i=None):
+        def step():
             ara.ara_layer_build(ctx, layer, ara.ARA_BUILD_TABLES)
-            if i is not None:
-                e0[i].record(stream)
             ara.ara_analyze(ctx, y_handle, layer, 0, w.n_trials, ylt)
-            if i is not None:
-                e1[i].record(stream)
-            r = ara.ara_risk_measures(ctx, ylt if sort_input is None else sort_input, rps, ws)
-            if i is not None:
-                km.append(ara.ara_kernel_ms(ctx))
-            return r
+            return ara.ara_risk_measures(ctx, ylt if sort_input is None else sort_input, rps, ws)
 
-        ara.ara_set_option(ctx, ara.ARA_OPT_KERNEL_TIMING, 1)
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
+        ara.ara_set_option(ctx, ara.ARA_OPT_KERNEL_TIMING, steps)
         t0 = time.perf_counter()
-        for i in range(steps):
-            res = step(i)
+        for _ in range(steps):
+            res = step()
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3 / steps
+        k_mean = ara.ara_kernel_ms(ctx)
         ara.ara_set_option(ctx, ara.ARA_OPT_KERNEL_TIMING, 0)
-        if call_ms is not None:
-            call_ms.extend(e0[i].elapsed_time(e1[i]) for i in range(steps))
-        return ms, km, res
+        return ms, k_mean, res
 
-    call_ms = []
-    ms_step, kern_ms, (pml, tvar) = run_steps(an.layer, args.steps, args.warmup, call_ms=call_ms)
-    k_avg = float(np.mean(kern_ms))
-    k_call = float(np.mean(call_ms))
+    ms_step, k_avg, (pml, tvar) = run_steps(an.layer, args.steps, args.warmup)
     saturated = bool(torch.all(ylt == float(w.layer_terms[3])).item())
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; trial kernel avg {k_avg:.4f} ms "
-        f"({k_call:.4f} ms between events around the call) "
-        f"(min {min(kern_ms):.4f}, max {max(kern_ms):.4f}); PML {pml.tolist()} TVaR {tvar.tolist()}")
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step; trial kernel avg {k_avg:.4f} ms; "
+        f"PML {pml.tolist()} TVaR {tvar.tolist()}")
 
     nblk = (w.catalog_size + 127) // 128
     # algorithmic bytes are defined on int32 event IDs and int64 trial offsets; the
@@ -853,7 +839,7 @@ def main():
     value = te / (ms_step * 1e-3)
 
     # the same step with the sort of distinct year losses in place of the saturated YLT
-    ms_step_distinct, _, _ = run_steps(an.layer, 10, 2, sort_input=y_distinct)
+    ms_step_distinct, _, _ = run_steps(an.layer, args.steps, args.warmup, sort_input=y_distinct)
     for _ in range(2):
         ara.ara_risk_measures(ctx, y_distinct, rps, ws)
     torch.cuda.synchronize()
@@ -869,8 +855,7 @@ def main():
     other = ara.ARA_F32 if prec == ara.ARA_F64 else ara.ARA_F64
     an2 = session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
                                 None, other, yet=yet)
-    ms2, km2, _ = run_steps(an2.layer, args.steps, args.warmup)
-    k2 = float(np.mean(km2))
+    ms2, k2, _ = run_steps(an2.layer, args.steps, args.warmup)
     nf2 = ara.ara_layer_stats(ctx, an2.layer)[0]
     alg2 = 4 * w.n_events + 8 * (w.n_trials + 1) + 8 * w.n_trials + 20 * nblk + 8 * nf2
     ara.ara_layer_release(an2.layer)
@@ -971,10 +956,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel,
-                     "kernel_ms": k_avg, "kernel_ms_around_call": k_call,
+                     "kernel_ms": k_avg,
                      "kernel_timing": "HIP events attached to the trial kernel's launch on its stream "
-                                      "(ARA_OPT_KERNEL_TIMING), mean over the timed steps; "
-                                      "kernel_ms_around_call: torch events around the ara_analyze call",
+                                      "(ARA_OPT_KERNEL_TIMING), mean over the timed steps",
                      "algorithmic_bytes": alg_bytes, "yet_id_bytes": id_bytes,
                      "moved_bytes": moved_bytes, "moved_gbs": moved_gbs, "moved_frac": moved_gbs / HBM_PEAK_GBS,
                      "traffic_source": traffic_note},

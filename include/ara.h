@@ -115,10 +115,12 @@ typedef enum ara_option {
                                    3 (with at most 64 bins and fewer than 2^31 occurrences; 4 when
                                    a bin holds 2^24 occurrences or more): a quarter less memory for
                                    the run starts, about 3% more time in the tiled kernel          */
-    ARA_OPT_KERNEL_TIMING = 8   /* 1: ara_analyze times its trial kernel with a pair of HIP events
-                                   (for the tiled kernel, events attached to its launch: the
-                                   start of its first dispatch and the end of its last; for the
-                                   others, recorded on the stream just around the launches);
+    ARA_OPT_KERNEL_TIMING = 8   /* n in 1..4096: ara_analyze times its trial kernel with a pair of
+                                   HIP events, the pairs of the last n calls kept in a ring (for
+                                   the tiled kernel, events attached to its launch: the start of
+                                   its first dispatch and the end of its last; for the others,
+                                   recorded on the stream just around the launches); setting the
+                                   option waits for the stream and starts a new ring.
                                    ara_kernel_ms reads it.  0 (default): no timing             */
 } ara_option;
 
@@ -169,9 +171,10 @@ ara_status ara_set_option(ara_ctx *ctx, int option, int64_t value);
  * ARA_E_BAD_LOSS or ARA_E_DUP_EVENT.  ARA_E_DEVICE on a HIP runtime error. */
 ara_status ara_sync(ara_ctx *ctx);
 
-/* Blocking.  *ms = the duration of the trial kernel of the last ara_analyze call timed
- * under ARA_OPT_KERNEL_TIMING (waits for it).  ARA_E_INVALID_ARG when no call was
- * timed since the option was set; ARA_E_DEVICE on a HIP runtime error. */
+/* Blocking.  *ms = the mean duration of the trial kernels of the last min(k, n)
+ * ara_analyze calls timed under ARA_OPT_KERNEL_TIMING = n, k the calls timed since the
+ * option was set (waits for them).  ARA_E_INVALID_ARG when no call was timed since
+ * the option was set; ARA_E_DEVICE on a HIP runtime error. */
 ara_status ara_kernel_ms(ara_ctx *ctx, float *ms);
 
 /* ---------------------------------------------------------------- Year Event Table

@@ -37,9 +37,8 @@ struct ara_ctx {
     int yet_binning = 1;             // keep a catalog-binned copy of YET IDs where it applies
     int yet_run_bytes = 4;           // bytes per run start of the binned copy (3 or 4)
     int trial_mode = 0;              // 0 = by trial length, 1 = wave per trial, 2 = lane per trial
-    hipEvent_t k_start = nullptr;    // ARA_OPT_KERNEL_TIMING: the last timed trial kernel's events
-    hipEvent_t k_stop = nullptr;
-    bool timed = false;              // a launch was timed since the option was set
+    std::vector<hipEvent_t> k_ev;    // ARA_OPT_KERNEL_TIMING: a ring of (start, stop) event pairs
+    int64_t k_count = 0;             // trial kernels timed since the option was set
     std::map<std::string, std::pair<int64_t, bool>> tuned;   // batch shape -> (events per item, interleave)
     int live = 0;                    // handles alive on this context
     std::string msg;
@@ -94,6 +93,7 @@ struct ara_layer {
 };
 
 static constexpr size_t kStageDoubles = 512;   // 2 x 256 return periods
+static constexpr int64_t kMaxTimedLaunches = 4096;   // ARA_OPT_KERNEL_TIMING ring size
 static constexpr int32_t kMaxCatalog = 1 << 28; // byte offsets into catalog tables stay below 2^31
 static constexpr int32_t kMaxElts = 65535;      // ELT index is a grid dimension of the table builds
 static constexpr int32_t kMaxPackedCatalog = 1 << 24;   // IDs of a packed YET copy take 3 bytes
@@ -389,8 +389,7 @@ extern "C" ara_status ara_ctx_destroy(ara_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     dev_free(c->d_err);   // with d_out
-    if (c->k_start) (void)hipEventDestroy(c->k_start);
-    if (c->k_stop) (void)hipEventDestroy(c->k_stop);
+    for (hipEvent_t ev : c->k_ev) (void)hipEventDestroy(ev);
     if (c->h_err) (void)hipHostFree(c->h_err);   // with h_out
     if (c->h_plan) (void)hipHostFree(c->h_plan);
     delete c;
@@ -434,20 +433,25 @@ extern "C" ara_status ara_set_option(ara_ctx *c, int option, int64_t v) {
         if (v != 3 && v != 4) return fail(c, ARA_E_INVALID_ARG, "bad run start size %lld", (long long)v);
         c->yet_run_bytes = int(v);
         return ARA_OK;
-    case ARA_OPT_KERNEL_TIMING:
-        if (v != 0 && v != 1) return fail(c, ARA_E_INVALID_ARG, "bad timing flag %lld", (long long)v);
-        c->timed = false;
-        if (v == 0) {
-            (void)hipStreamSynchronize(c->stream);
-            if (c->k_start) (void)hipEventDestroy(c->k_start);
-            if (c->k_stop) (void)hipEventDestroy(c->k_stop);
-            c->k_start = c->k_stop = nullptr;
-            return ARA_OK;
-        }
+    case ARA_OPT_KERNEL_TIMING: {
+        if (v < 0 || v > kMaxTimedLaunches) return fail(c, ARA_E_INVALID_ARG, "bad timing ring size %lld", (long long)v);
         HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
-        if (!c->k_start) HIP_OR_RETURN(c, hipEventCreate(&c->k_start), "timing event");
-        if (!c->k_stop) HIP_OR_RETURN(c, hipEventCreate(&c->k_stop), "timing event");
+        (void)hipStreamSynchronize(c->stream);
+        for (hipEvent_t ev : c->k_ev) (void)hipEventDestroy(ev);
+        c->k_ev.clear();
+        c->k_count = 0;
+        for (int64_t i = 0; i < 2 * v; ++i) {
+            hipEvent_t ev = nullptr;
+            const hipError_t e = hipEventCreate(&ev);
+            if (e != hipSuccess) {
+                for (hipEvent_t x : c->k_ev) (void)hipEventDestroy(x);
+                c->k_ev.clear();
+                return hip_fail(c, e, "timing event");
+            }
+            c->k_ev.push_back(ev);
+        }
         return ARA_OK;
+    }
     default:
         return fail(c, ARA_E_INVALID_ARG, "unknown option %d", option);
     }
@@ -455,10 +459,18 @@ extern "C" ara_status ara_set_option(ara_ctx *c, int option, int64_t v) {
 
 extern "C" ara_status ara_kernel_ms(ara_ctx *c, float *ms) {
     if (!c || !ms) return ARA_E_INVALID_ARG;
-    if (!c->k_start || !c->timed) return fail(c, ARA_E_INVALID_ARG, "no trial kernel timed since timing was set");
+    if (c->k_ev.empty() || c->k_count == 0) return fail(c, ARA_E_INVALID_ARG, "no trial kernel timed since timing was set");
     HIP_OR_RETURN(c, hipSetDevice(c->device), "set device");
-    HIP_OR_RETURN(c, hipEventSynchronize(c->k_stop), "timing event");
-    HIP_OR_RETURN(c, hipEventElapsedTime(ms, c->k_start, c->k_stop), "timing event");
+    const int64_t n = int64_t(c->k_ev.size() / 2), m = std::min(c->k_count, n);
+    double sum = 0.0;
+    for (int64_t k = c->k_count - m; k < c->k_count; ++k) {
+        const size_t i = size_t(k % n);
+        float one = 0.0f;
+        HIP_OR_RETURN(c, hipEventSynchronize(c->k_ev[2 * i + 1]), "timing event");
+        HIP_OR_RETURN(c, hipEventElapsedTime(&one, c->k_ev[2 * i], c->k_ev[2 * i + 1]), "timing event");
+        sum += double(one);
+    }
+    *ms = float(sum / double(m));
     return ARA_OK;
 }
 
@@ -1017,23 +1029,25 @@ extern "C" ara_status ara_analyze(ara_ctx *c, const ara_yet *y, const ara_layer 
     }
     // trial indices inside a launch are 32-bit: split very long ranges
     constexpr int64_t kMaxTrialsPerLaunch = int64_t(1) << 30;
-    const bool timing = c->k_start != nullptr, tiles = tl.placement == ARA_PLACE_LDS_TILES;
-    hipError_t e = timing && !tiles ? hipEventRecord(c->k_start, c->stream) : hipSuccess;
+    const bool timing = !c->k_ev.empty(), tiles = tl.placement == ARA_PLACE_LDS_TILES;
+    const size_t slot = timing ? size_t(c->k_count % int64_t(c->k_ev.size() / 2)) : 0;
+    hipEvent_t t_start = timing ? c->k_ev[2 * slot] : nullptr, t_stop = timing ? c->k_ev[2 * slot + 1] : nullptr;
+    hipError_t e = timing && !tiles ? hipEventRecord(t_start, c->stream) : hipSuccess;
     for (int64_t tb = t0; tb < t1 && e == hipSuccess; tb += kMaxTrialsPerLaunch) {
         const int64_t te = std::min(t1, tb + kMaxTrialsPerLaunch);
         if (tiles) {
             // timed: events attached to the first launch's start and the last one's end
             const bool first = tb == t0, last = te == t1;
             e = launch_trial_tiled(tiled_args(y, L, tb, te, dst + (tb - t0), tl.grid), tl.grid, c->stream, false,
-                                   timing && first ? c->k_start : nullptr, timing && last ? c->k_stop : nullptr);
+                                   first ? t_start : nullptr, last ? t_stop : nullptr);
             continue;
         }
         TrialArgs a = trial_args(y, L, tb, te, dst + (tb - t0));
         a.qcap = tl.qcap;
         e = launch_trial_ylt(a, tl, c->stream);
     }
-    if (e == hipSuccess && timing && !tiles) e = hipEventRecord(c->k_stop, c->stream);
-    if (e == hipSuccess && timing) c->timed = true;
+    if (e == hipSuccess && timing && !tiles) e = hipEventRecord(t_stop, c->stream);
+    if (e == hipSuccess && timing) c->k_count++;
     if (e != hipSuccess) s = hip_fail(c, e, "trial kernel");
     if (s == ARA_OK && mem == ARA_MEM_HOST) {
         e = hipMemcpyAsync(ylt, dst, size_t(t1 - t0) * 8, hipMemcpyDeviceToHost, c->stream);

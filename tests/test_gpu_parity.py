@@ -530,10 +530,11 @@ def test_largest_catalog(A, S, gpu_ctx):
 
 
 def test_kernel_timing(A, S, gpu_ctx, small):
-    """ARA_OPT_KERNEL_TIMING: ara_kernel_ms reports the last timed ara_analyze's trial
-    kernel, for the tiled kernel (events attached to its launch) and another placement
-    (events around its launches): positive, and no longer than torch events recorded
-    around the whole call; without the option it is an error."""
+    """ARA_OPT_KERNEL_TIMING = n: ara_kernel_ms reports the mean trial-kernel time of the
+    last min(k, n) timed ara_analyze calls, for the tiled kernel (events attached to its
+    launch) and another placement (events around its launches): positive, and no longer
+    than torch events recorded around the same calls; without the option, or before a
+    timed call, it is an error."""
     import torch
     _say("kernel timing")
     rng = np.random.default_rng(77)
@@ -549,20 +550,27 @@ def test_kernel_timing(A, S, gpu_ctx, small):
         with pytest.raises(A.AraError) as e:
             A.ara_kernel_ms(gpu_ctx)
         assert e.value.status == A.ARA_E_INVALID_ARG
-        A.ara_set_option(gpu_ctx, A.ARA_OPT_KERNEL_TIMING, 1)
-        with pytest.raises(A.AraError):
-            A.ara_kernel_ms(gpu_ctx)          # nothing timed yet
+        for bad in (-1, 4097):
+            with pytest.raises(A.AraError):
+                A.ara_set_option(gpu_ctx, A.ARA_OPT_KERNEL_TIMING, bad)
         for an in (tiled, plain):
-            n = an.n_trials
-            ylt = torch.empty(n, dtype=torch.float64, device="cuda")
-            for _ in range(3):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                A.ara_analyze(gpu_ctx, an.yet, an.layer, 0, n, ylt)
-                e1.record(stream)
-                A.ara_sync(gpu_ctx)
+            for ring, calls in ((1, 3), (4, 3), (2, 5)):
+                A.ara_set_option(gpu_ctx, A.ARA_OPT_KERNEL_TIMING, ring)
+                with pytest.raises(A.AraError):
+                    A.ara_kernel_ms(gpu_ctx)          # nothing timed yet
+                n = an.n_trials
+                ylt = torch.empty(n, dtype=torch.float64, device="cuda")
+                around = []
+                for _ in range(calls):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    A.ara_analyze(gpu_ctx, an.yet, an.layer, 0, n, ylt)
+                    e1.record(stream)
+                    A.ara_sync(gpu_ctx)
+                    around.append(e0.elapsed_time(e1))
                 ms = A.ara_kernel_ms(gpu_ctx)
-                assert 0.0 < ms <= e0.elapsed_time(e1) * 1.001 + 1e-3, (ms, e0.elapsed_time(e1))
+                last = around[-min(ring, calls):]
+                assert 0.0 < ms <= float(np.mean(last)) * 1.001 + 1e-3, (ring, calls, ms, last)
         A.ara_set_option(gpu_ctx, A.ARA_OPT_KERNEL_TIMING, 0)
         with pytest.raises(A.AraError):
             A.ara_kernel_ms(gpu_ctx)
