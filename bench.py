@@ -739,13 +739,13 @@ def main():
     # ara_yet_create checks every ID and offset and builds the binned (or packed)
     # copy; it is blocking, so its wall time is the ingest time.  The first call in
     # the process also loads the library's kernels and makes its first device
-    # allocations: it is reported beside the median of the next five calls (each
+    # allocations: it is reported beside the median of the next nine calls (each
     # YET released before the next, the last one kept for the analysis).
     ids_dev = session.to_device(np.asarray(w.event_ids, np.int32))
     offs_dev = session.to_device(np.asarray(w.trial_offsets, np.int64))
     ingest_runs = []
     yet = None
-    for r in range(6):
+    for r in range(10):
         if yet is not None:
             ara.ara_yet_release(yet)
         torch.cuda.synchronize()
@@ -758,8 +758,9 @@ def main():
         torch.cuda.synchronize()
         ingest_runs.append((wall, ig0.elapsed_time(ig1)))
     ingest_first_ms = ingest_runs[0][0]
-    ingest_ms = sorted(x[0] for x in ingest_runs[1:])[2]
-    ingest_gpu_ms = sorted(x[1] for x in ingest_runs[1:])[2]
+    ingest_ms = float(np.median([x[0] for x in ingest_runs[1:]]))
+    ingest_gpu_ms = float(np.median([x[1] for x in ingest_runs[1:]]))
+    log("ingest calls (ms wall): " + " ".join(f"{x[0]:.2f}" for x in ingest_runs))
     id_bytes = ara.ara_yet_info(yet)[2]
     n_bins = ara.ara_yet_binned_count(yet) if id_bytes == 2 else 0
     # device memory the handle adds to the caller's int32 IDs and offsets, as the
@@ -967,7 +968,7 @@ def main():
                    "yet_extra_bytes": yet_extra,
                    "what": "ara_yet_create on IDs and offsets resident in HBM: every ID and offset checked, "
                            "catalog-binned copy built; once per resident YET, not part of a step; median of "
-                           "5 calls after the first, which also loads the kernels (first_call_ms)"},
+                           "9 calls after the first, which also loads the kernels (first_call_ms)"},
         "ylt_saturated": {"all_equal_agg_limit": saturated,
                           "ms_per_step_with_distinct_ylt_sort": ms_step_distinct,
                           "value_with_distinct_ylt_sort": te / (ms_step_distinct * 1e-3)},
