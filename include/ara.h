@@ -114,7 +114,7 @@ typedef enum ara_option {
     ARA_OPT_YET_RUN_BYTES = 7,  /* bytes per run start of binned copies built later: 4 (default), or
                                    3 (with at most 64 bins and fewer than 2^31 occurrences; 4 when
                                    a bin holds 2^24 occurrences or more): a quarter less memory for
-                                   the run starts, about 3% more time in the tiled kernel          */
+                                   the run starts, about 2% more time in the tiled kernel          */
     ARA_OPT_KERNEL_TIMING = 8   /* n in 1..4096: ara_analyze times its trial kernel with a pair of
                                    HIP events, the pairs of the last n calls kept in a ring (for
                                    the tiled kernel, events attached to its launch: the start of
