@@ -743,6 +743,16 @@ def main():
     # YET released before the next, the last one kept for the analysis).
     ids_dev = session.to_device(np.asarray(w.event_ids, np.int32))
     offs_dev = session.to_device(np.asarray(w.trial_offsets, np.int64))
+    # PML/TVaR input with as many distinct year losses (all eight radix passes run;
+    # the workload's own year losses all equal the aggregate limit, so the step's
+    # sort skips its passes).  Made here, before the GPU work that leads into the
+    # timed steps, so that no long host-only spell precedes them
+    y_distinct = torch.from_numpy(np.random.default_rng(7).lognormal(15.0, 2.0, size=w.n_trials)).cuda()
+    # the layer's ELTs and the layer itself need no YET: created here for the same reason
+    handles = [ara.ara_elt_create(ctx, session.to_device(np.asarray(i, np.int32)),
+                                  session.to_device(np.asarray(l, np.float64)), w.catalog_size, precision=prec)
+               for i, l in w.elts]
+    layer = ara.ara_layer_create(ctx, handles, w.catalog_size, w.layer_terms)
     ingest_runs = []
     yet = None
     for r in range(10):
@@ -770,8 +780,7 @@ def main():
     log(f"ingest (validate + {'binned' if id_bytes == 2 else 'packed' if id_bytes == 3 else 'no'} copy): "
         f"{ingest_ms:.2f} ms wall, {ingest_gpu_ms:.2f} ms on the stream (first call in the process "
         f"{ingest_first_ms:.2f} ms); {yet_extra / 1e9:.3f} GB added")
-    an = session.open_analysis(ctx, w.event_ids, w.trial_offsets, w.catalog_size, w.elts, w.layer_terms,
-                               None, prec, yet=yet)
+    an = session.Analysis(ctx, yet, handles, layer, w.n_trials, w.n_events)
     torch.cuda.synchronize()
     n_flagged, placement, lds_bytes = ara.ara_layer_stats(ctx, an.layer)
     # the layer alone would take the LDS filter; with the YET's binned copy the
@@ -785,10 +794,6 @@ def main():
     ylt = torch.empty(w.n_trials, dtype=torch.float64, device="cuda")
     ws = torch.empty(ara.ara_sort_workspace_size(w.n_trials), dtype=torch.uint8, device="cuda")
     rps = list(w.return_periods)
-    # PML/TVaR input with as many distinct year losses (all eight radix passes run;
-    # the workload's own year losses all equal the aggregate limit, so the step's
-    # sort skips its passes)
-    y_distinct = torch.from_numpy(np.random.default_rng(7).lognormal(15.0, 2.0, size=w.n_trials)).cuda()
 
     def run_steps(layer, steps, warmup, sort_input=None, on_yet=None):
         """steps x (table build, trial kernel, sort + PML/TVaR to the host): wall ms per
